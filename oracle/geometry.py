@@ -1,0 +1,166 @@
+"""Mesh geometry for straight-edged quads (2D) and trilinear hexahedra (3D).
+
+Test infrastructure (see package docstring).  Follows Sec. 3.1 of the paper
+("Solution Domain Discretisation"): cell centroid x_P and volume Omega_P, face
+centre x_f, unit normal n_f (outward from the owner P), area Gamma_f, and
+quadrature points x_{f,q} with weights alpha_q summing to one.
+
+Readings where the paper is silent for these element shapes:
+
+* Cells are handled through their (bi/tri)linear isoparametric map; Omega_P and
+  x_P are integrated exactly with 2 Gauss-Legendre points per direction.
+* A 3D face is the bilinear surface through its four vertices.  Its single
+  normal and area come from the exact vector area S_f = 1/2 (x2-x0) x (x3-x1):
+  Gamma_f = |S_f|, n_f = S_f / Gamma_f.  Quadrature points are the n_g x n_g
+  Gauss-Legendre points of the bilinear map, alpha_q proportional to
+  w_i w_j |x_s x x_t| and normalised to sum 1.
+* 2D faces are edges with n_g Gauss-Legendre points, alpha_q = w_q / 2.
+* The face centre is x_f = sum_q alpha_q x_{f,q}.
+* The body-force volume quadrature uses (p+2)^D Gauss-Legendre points of the
+  cell map with weights w detJ (so that sum_q beta_q Omega_P = sum_q w_q detJ_q).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+# local faces, vertex order giving the outward normal of the cell
+QUAD_FACES = np.array([[3, 0], [1, 2], [0, 1], [2, 3]])
+HEX_FACES = np.array([[0, 4, 7, 3], [1, 2, 6, 5], [0, 1, 5, 4], [3, 7, 6, 2],
+                      [0, 3, 2, 1], [4, 5, 6, 7]])
+QUAD_REF = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float)
+HEX_REF = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
+                    [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]], float)
+
+
+def gauss_01(n: int):
+    """n-point Gauss-Legendre rule mapped to [0, 1] (weights sum to 1)."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def shape_functions(ref: np.ndarray, xi: np.ndarray):
+    """(Bi/tri)linear shape functions N_a(xi) and dN_a/dxi_j at points xi (m, D)."""
+    m, D = xi.shape
+    na = ref.shape[0]
+    N = np.ones((m, na))
+    dN = np.ones((m, na, D))
+    for a in range(na):
+        for d in range(D):
+            f = xi[:, d] if ref[a, d] else 1.0 - xi[:, d]
+            df = 1.0 if ref[a, d] else -1.0
+            N[:, a] *= f
+            for j in range(D):
+                dN[:, a, j] *= df if j == d else f
+    return N, dN
+
+
+def cell_quadrature(X: np.ndarray, n: int):
+    """Tensor Gauss-Legendre quadrature of the cell map.
+
+    X: (n_c, 2^D, D) vertex coordinates.  Returns points (n_c, n^D, D) and
+    weights w * detJ (n_c, n^D), which integrate over the physical cell.
+    """
+    D = X.shape[2]
+    ref = QUAD_REF if D == 2 else HEX_REF
+    t, w = gauss_01(n)
+    grids = np.meshgrid(*([t] * D), indexing="ij")
+    wgrid = np.meshgrid(*([w] * D), indexing="ij")
+    xi = np.stack([g.ravel() for g in grids], axis=1)
+    wq = np.prod(np.stack([g.ravel() for g in wgrid], axis=1), axis=1)
+    N, dN = shape_functions(ref, xi)
+    pts = np.einsum("qa,cad->cqd", N, X)
+    J = np.einsum("qaj,cai->cqij", dN, X)  # dx_i / dxi_j
+    detJ = np.linalg.det(J)
+    return pts, wq[None, :] * detJ
+
+
+def cell_volume_centroid(X: np.ndarray):
+    pts, W = cell_quadrature(X, 2)
+    vol = W.sum(axis=1)
+    cen = np.einsum("cq,cqd->cd", W, pts) / vol[:, None]
+    return vol, cen
+
+
+@dataclass
+class Faces:
+    """All faces of a mesh.  Internal faces have neigh >= 0, boundary faces -1."""
+    owner: np.ndarray   # (n_f,)
+    neigh: np.ndarray   # (n_f,)
+    verts: np.ndarray   # (n_f, 2|4) vertex ids in the owner's outward order
+    owner_slot: np.ndarray  # local face index in the owner cell
+    neigh_slot: np.ndarray  # local face index in the neighbour cell (-1 boundary)
+
+
+def enumerate_faces(cells: np.ndarray, dim: int) -> Faces:
+    """Match local faces of all cells by their (sorted) vertex sets.
+
+    The owner is the lower cell id (its copy appears first), the neighbour the
+    other one; a face seen once is a boundary face.
+    """
+    lf = QUAD_FACES if dim == 2 else HEX_FACES
+    nlf = lf.shape[0]
+    n_c = cells.shape[0]
+    fv = cells[:, lf]                      # (n_c, nlf, nv)
+    flat = fv.reshape(n_c * nlf, -1)
+    keys = np.sort(flat, axis=1)
+    uniq, inv, counts = np.unique(keys, axis=0, return_inverse=True, return_counts=True)
+    inv = inv.ravel()
+    if np.any(counts > 2):
+        raise ValueError("non-manifold mesh: a face is shared by more than two cells")
+    n_f = uniq.shape[0]
+    rows = np.arange(n_c * nlf)
+    first = np.full(n_f, -1, np.int64)
+    second = np.full(n_f, -1, np.int64)
+    for r in rows:  # rows are in increasing cell order
+        f = inv[r]
+        if first[f] < 0:
+            first[f] = r
+        else:
+            second[f] = r
+    owner = first // nlf
+    neigh = np.where(second >= 0, second // nlf, -1)
+    return Faces(owner=owner, neigh=neigh, verts=flat[first],
+                 owner_slot=first % nlf, neigh_slot=np.where(second >= 0, second % nlf, -1))
+
+
+@dataclass
+class FaceGeom:
+    centre: np.ndarray  # (n_f, D)
+    normal: np.ndarray  # (n_f, D) unit, outward from owner
+    area: np.ndarray    # (n_f,)
+    qpts: np.ndarray    # (n_f, Nq, D)
+    qw: np.ndarray      # (n_f, Nq), sums to 1
+
+
+def face_geometry(verts: np.ndarray, fverts: np.ndarray, n_gauss: int) -> FaceGeom:
+    """Geometry and quadrature of faces given their ordered vertex ids."""
+    P = verts[fverts]  # (n_f, nv, D)
+    t, w = gauss_01(n_gauss)
+    if P.shape[1] == 2:
+        a, b = P[:, 0], P[:, 1]
+        e = b - a
+        area = np.sqrt(np.sum(e * e, axis=1))
+        normal = np.stack([e[:, 1], -e[:, 0]], axis=1) / area[:, None]
+        qpts = a[:, None, :] + t[None, :, None] * e[:, None, :]
+        qw = np.broadcast_to(w, (P.shape[0], w.size)).copy()
+    else:
+        x0, x1, x2, x3 = P[:, 0], P[:, 1], P[:, 2], P[:, 3]
+        S = 0.5 * np.cross(x2 - x0, x3 - x1)
+        area = np.sqrt(np.sum(S * S, axis=1))
+        normal = S / area[:, None]
+        s, tt = np.meshgrid(t, t, indexing="ij")
+        ws, wt = np.meshgrid(w, w, indexing="ij")
+        s = s.ravel(); tt = tt.ravel(); wq = (ws * wt).ravel()
+        qpts = ((1 - s)[None, :, None] * (1 - tt)[None, :, None] * x0[:, None]
+                + s[None, :, None] * (1 - tt)[None, :, None] * x1[:, None]
+                + s[None, :, None] * tt[None, :, None] * x2[:, None]
+                + (1 - s)[None, :, None] * tt[None, :, None] * x3[:, None])
+        xs = (1 - tt)[None, :, None] * (x1 - x0)[:, None] + tt[None, :, None] * (x2 - x3)[:, None]
+        xt = (1 - s)[None, :, None] * (x3 - x0)[:, None] + s[None, :, None] * (x2 - x1)[:, None]
+        jac = np.sqrt(np.sum(np.cross(xs, xt) ** 2, axis=2))
+        qw = wq[None, :] * jac
+        qw = qw / qw.sum(axis=1, keepdims=True)
+    centre = np.einsum("fq,fqd->fd", qw, qpts)
+    return FaceGeom(centre, normal, area, qpts, qw)

@@ -1,0 +1,305 @@
+"""The high-order finite-volume residual R(u) (paper Secs. 3.2-3.5, Apps. A-B).
+
+Test infrastructure (see package docstring).
+
+    R_P(u) = sum_{f in int}  Gamma_f n_f . [sum_q alpha_q sigma_{f,q}]          (eq. divStressDiscret)
+           + sum_{b in disp} Gamma_b n_b . [sum_q alpha_q sigma_{b,q}]
+           + sum_{b in trac} Gamma_b sum_q alpha_q T_{b,q}
+           + sum_{f in int u disp} t_{alpha,f} Gamma_f                             (eq. alpha)
+           + sum_q beta_q f_b(x_{Omega,q}) Omega_P                                  (eq. bodyTerm)
+
+with internal-face terms added to the owner and subtracted from the neighbour.
+R(u) = 0 is static equilibrium (Sec. 4.1).
+
+* (grad u)_{f,q} = sum_N c_{x_N} (x) u_N (+ c_b (x) u_{b,q} on displacement faces),
+  eq. faceQuadGrad, stored as G[i][j] = d u_j / d x_i.
+* Linear elasticity: sigma = mu G + mu G^T + lambda tr(G) I (eq. linearElastic).
+* Neo-Hookean (total Lagrangian): F = I + G^T, J = det F, b = F F^T,
+  bbar = J^{-2/3} b, sigma = (mu/J) dev(bbar) + (kappa/2)(J^2-1)/J I (eq. neoHook),
+  P = J sigma F^{-T} (eq. nanson), face term n_o . P^T (eq. momentum_TL);
+  kappa = lambda + 2 mu / 3.  J^{-2/3} is evaluated as exp(-2/3 ln J) so the
+  complex-step derivative goes through.
+* alpha-stabilisation: t = alpha Kbar / |d_PN . n_f| (u*_{f,N} - u*_{f,P}), Kbar = 2 mu + lambda;
+  on displacement faces t = alpha Kbar / |d_Pb . n_b| (u_b(x_b) - u*_{b,P}).  The
+  extrapolations u* use u_P itself plus d . grad u + 1/2 d^2 : grad grad u
+  + 1/6 d^3 ::: grad grad grad u from the cell stencil (eq. alphaJump, App. B).
+* Traction faces: Gamma_b sum_q alpha_q T_{b,q} (the weights alpha_q are taken to
+  apply, as in the other surface terms; the printed equation omits them).
+* Loads (u_b, T, f_b) are multiplied by ``load`` for load increments.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from workloads.fields import DISP, TRAC
+
+from . import geometry as geo
+from .lsq import reconstruction, row_index
+from .stencil import nearest
+
+
+@dataclass
+class Discretisation:
+    dim: int
+    p: int
+    n_cells: int
+    material: int
+    mu: float
+    lam: float
+    alpha: float
+    cen: np.ndarray
+    vol: np.ndarray
+    # internal faces (possibly only those touching active cells)
+    f_own: np.ndarray
+    f_nei: np.ndarray
+    f_n: np.ndarray
+    f_area: np.ndarray
+    f_x: np.ndarray
+    f_qw: np.ndarray
+    f_st: np.ndarray      # (nf, S)
+    f_C: np.ndarray       # (nf, Nq, D, S)
+    # displacement faces
+    d_own: np.ndarray
+    d_n: np.ndarray
+    d_area: np.ndarray
+    d_x: np.ndarray
+    d_qw: np.ndarray
+    d_st: np.ndarray
+    d_C: np.ndarray       # (nd, Nq, D, S)
+    d_Cg: np.ndarray      # (nd, Nq, D) ghost coefficients
+    d_ubq: np.ndarray     # (nd, Nq, D) prescribed u at q-points (load 1)
+    d_ubc: np.ndarray     # (nd, D) prescribed u at face centre (load 1)
+    # cell stencils and derivative coefficients (for cells that need u*)
+    c_st: np.ndarray      # (n_c, S), -1 rows where not built
+    c_D1: np.ndarray      # (n_c, D, S)
+    c_D2: np.ndarray | None  # (n_c, D, D, S)
+    c_D3: np.ndarray | None  # (n_c, D, D, D, S)
+    # constant sources at load 1
+    b_body: np.ndarray    # (n_c, D)
+    b_trac: np.ndarray    # (n_c, D)
+    active: np.ndarray    # (n_c,) bool: cells whose R is complete
+    max_cond: float = 0.0
+
+    @property
+    def kbar(self):
+        return 2.0 * self.mu + self.lam
+
+
+def _face_coefficients(xq, st, cen, p, k, ghost_weight=None):
+    """Gradient rows at every face q-point: (nf, Nq, D, S) and ghost (nf, Nq, D)."""
+    nf, nq, D = xq.shape
+    S = st.shape[1]
+    pts = xq.reshape(nf * nq, D)
+    Xs = np.repeat(cen[st], nq, axis=0)  # (nf*nq, S, D)
+    A, cond = reconstruction(pts, Xs, p, k, ghost_weight)
+    rows = row_index(D, p)
+    grad_rows = [rows[tuple(1 if d == i else 0 for d in range(D))] for i in range(D)]
+    C = A[:, grad_rows, :S].reshape(nf, nq, D, S)
+    Cg = A[:, grad_rows, S].reshape(nf, nq, D) if ghost_weight is not None else None
+    return C, Cg, cond.max(initial=0.0)
+
+
+def _cell_coefficients(cells, st, cen, p, k):
+    """Derivative tensors at cell centroids: D1 (m,D,S), D2 (m,D,D,S), D3 (m,D,D,D,S)."""
+    D = cen.shape[1]
+    A, cond = reconstruction(cen[cells], cen[st], p, k)
+    rows = row_index(D, p)
+
+    def row(*axes):
+        e = [0] * D
+        for a in axes:
+            e[a] += 1
+        return rows[tuple(e)]
+
+    m, S = st.shape
+    D1 = np.stack([A[:, row(i), :] for i in range(D)], axis=1)
+    D2 = D3 = None
+    if p >= 2:
+        D2 = np.empty((m, D, D, S))
+        for i in range(D):
+            for j in range(D):
+                D2[:, i, j] = A[:, row(i, j), :]
+    if p >= 3:
+        D3 = np.empty((m, D, D, D, S))
+        for i in range(D):
+            for j in range(D):
+                for l in range(D):
+                    D3[:, i, j, l] = A[:, row(i, j, l), :]
+    return D1, D2, D3, cond.max(initial=0.0)
+
+
+def build(problem, active=None) -> Discretisation:
+    """Set up geometry, stencils, coefficients and sources for ``problem``.
+
+    ``active`` (optional bool mask or index array) restricts the work to what the
+    residual of those cells needs; R is then only complete on active cells.
+    """
+    mesh = problem.mesh
+    D, p, S = mesh.dim, problem.p, problem.stencil_size
+    n_c = mesh.n_cells
+    X = mesh.verts[mesh.cells]
+    vol, cen = geo.cell_volume_centroid(X)
+    faces = geo.enumerate_faces(mesh.cells, D)
+    fg = geo.face_geometry(mesh.verts, faces.verts, problem.n_gauss)
+    act = np.ones(n_c, bool)
+    if active is not None:
+        act = np.zeros(n_c, bool)
+        act[np.asarray(active)] = True
+    touch = act[faces.owner] | np.where(faces.neigh >= 0, act[np.maximum(faces.neigh, 0)], False)
+    internal = (faces.neigh >= 0) & touch
+    bnd = (faces.neigh < 0) & touch
+    loads = problem.loads
+    btype = loads.bc_type(fg.centre[bnd], fg.normal[bnd]) if bnd.any() else np.zeros(0, np.int32)
+    bidx = np.nonzero(bnd)[0]
+    disp = bidx[btype == DISP]
+    trac = bidx[btype == TRAC]
+    q = problem.stencil_quantum
+    k = problem.k_weight
+
+    fi = np.nonzero(internal)[0]
+    f_st = nearest(fg.centre[fi], cen, S, q)
+    f_C, _, c1 = _face_coefficients(fg.qpts[fi], f_st, cen, p, k)
+    d_st = nearest(fg.centre[disp], cen, S, q)
+    d_C, d_Cg, c2 = _face_coefficients(fg.qpts[disp], d_st, cen, p, k, problem.ghost_weight)
+    if d_Cg is None:
+        d_Cg = np.zeros((0, fg.qpts.shape[1], D))
+
+    # cells whose u* is needed: both sides of internal faces, owners of disp faces
+    need = np.zeros(n_c, bool)
+    need[faces.owner[fi]] = True
+    need[faces.neigh[fi]] = True
+    need[faces.owner[disp]] = True
+    cells = np.nonzero(need)[0]
+    c_st = np.full((n_c, S), -1, np.int64)
+    c_st[cells] = nearest(cen[cells], cen, S, q)
+    D1, D2, D3, c3 = _cell_coefficients(cells, c_st[cells], cen, p, k)
+    c_D1 = np.zeros((n_c, D, S)); c_D1[cells] = D1
+    c_D2 = c_D3 = None
+    if D2 is not None:
+        c_D2 = np.zeros((n_c, D, D, S)); c_D2[cells] = D2
+    if D3 is not None:
+        c_D3 = np.zeros((n_c, D, D, D, S)); c_D3[cells] = D3
+
+    # body force (p+2)^D Gauss points of the cell map
+    b_body = np.zeros((n_c, D))
+    ac = np.nonzero(act)[0]
+    if ac.size:
+        pts, W = geo.cell_quadrature(X[ac], p + 2)
+        fb = loads.body(pts.reshape(-1, D)).reshape(pts.shape)
+        b_body[ac] = np.einsum("cq,cqd->cd", W, fb)
+    # traction faces
+    b_trac = np.zeros((n_c, D))
+    if trac.size:
+        nq = fg.qpts.shape[1]
+        T = loads.traction(fg.qpts[trac].reshape(-1, D), np.repeat(fg.normal[trac], nq, axis=0))
+        T = T.reshape(trac.size, nq, D)
+        contrib = fg.area[trac, None] * np.einsum("fq,fqd->fd", fg.qw[trac], T)
+        np.add.at(b_trac, faces.owner[trac], contrib)
+    # prescribed displacements
+    nq = fg.qpts.shape[1]
+    d_ubq = loads.u_b(fg.qpts[disp].reshape(-1, D)).reshape(disp.size, nq, D)
+    d_ubc = loads.u_b(fg.centre[disp])
+
+    return Discretisation(
+        dim=D, p=p, n_cells=n_c, material=problem.material, mu=problem.mu, lam=problem.lam,
+        alpha=problem.alpha, cen=cen, vol=vol,
+        f_own=faces.owner[fi], f_nei=faces.neigh[fi], f_n=fg.normal[fi], f_area=fg.area[fi],
+        f_x=fg.centre[fi], f_qw=fg.qw[fi], f_st=f_st, f_C=f_C,
+        d_own=faces.owner[disp], d_n=fg.normal[disp], d_area=fg.area[disp], d_x=fg.centre[disp],
+        d_qw=fg.qw[disp], d_st=d_st, d_C=d_C, d_Cg=d_Cg, d_ubq=d_ubq, d_ubc=d_ubc,
+        c_st=c_st, c_D1=c_D1, c_D2=c_D2, c_D3=c_D3, b_body=b_body, b_trac=b_trac, active=act,
+        max_cond=float(max(c1, c2, c3)))
+
+
+# ----------------------------------------------------------------------------- stresses
+
+def stress_linear(G, mu, lam):
+    """eq. linearElastic with G[..., i, j] = d u_j / d x_i."""
+    D = G.shape[-1]
+    tr = np.trace(G, axis1=-2, axis2=-1)
+    return mu * G + mu * np.swapaxes(G, -1, -2) + lam * tr[..., None, None] * np.eye(D)
+
+
+def piola_neo_hookean(G, mu, lam):
+    """First Piola-Kirchhoff stress P = J sigma F^{-T} of eq. neoHook (3D)."""
+    D = G.shape[-1]
+    if D != 3:
+        raise ValueError("the neo-Hookean law is implemented in 3D only")
+    kappa = lam + 2.0 * mu / 3.0
+    I = np.eye(3)
+    F = I + np.swapaxes(G, -1, -2)
+    J = np.linalg.det(F)
+    b = F @ np.swapaxes(F, -1, -2)
+    bbar = np.exp(-2.0 / 3.0 * np.log(J))[..., None, None] * b
+    dev = bbar - (np.trace(bbar, axis1=-2, axis2=-1) / 3.0)[..., None, None] * I
+    sigma = (mu / J)[..., None, None] * dev + (0.5 * kappa * (J * J - 1.0) / J)[..., None, None] * I
+    Finv_T = np.swapaxes(np.linalg.inv(F), -1, -2)
+    return J[..., None, None] * sigma @ Finv_T
+
+
+def face_term(disc, G, normal, area, qw):
+    """Gamma n . [sum_q alpha_q S_q] where S = sigma (LE) or P^T (NH)."""
+    if disc.material == 0:
+        Sq = stress_linear(G, disc.mu, disc.lam)
+    else:
+        Sq = np.swapaxes(piola_neo_hookean(G, disc.mu, disc.lam), -1, -2)
+    Sbar = np.einsum("fq,fqij->fij", qw, Sq)
+    return area[:, None] * np.einsum("fi,fij->fj", normal, Sbar)
+
+
+# ----------------------------------------------------------------------------- u*
+
+def extrapolate(disc, u, cells, d):
+    """u*_{f,X} = u_X + d.grad u_X + 1/2 d^2 : grad grad u_X + 1/6 d^3 ::: grad^3 u_X."""
+    st = disc.c_st[cells]
+    ug = u[st]  # (m, S, D)
+    grad = np.einsum("mis,msj->mij", disc.c_D1[cells], ug)
+    val = u[cells] + np.einsum("mi,mij->mj", d, grad)
+    if disc.p >= 2:
+        H = np.einsum("miks,msj->mikj", disc.c_D2[cells], ug)
+        val = val + 0.5 * np.einsum("mi,mk,mikj->mj", d, d, H)
+    if disc.p >= 3:
+        T = np.einsum("mikls,msj->miklj", disc.c_D3[cells], ug)
+        val = val + (1.0 / 6.0) * np.einsum("mi,mk,ml,miklj->mj", d, d, d, T)
+    return val
+
+
+# ----------------------------------------------------------------------------- residual
+
+def face_fluxes(disc, u, load=1.0):
+    """Internal-face fluxes (owner side) and displacement-face fluxes."""
+    kbar = disc.kbar
+    # internal faces
+    G = np.einsum("fqis,fsj->fqij", disc.f_C, u[disc.f_st])
+    Ff = face_term(disc, G, disc.f_n, disc.f_area, disc.f_qw)
+    dPN = disc.cen[disc.f_nei] - disc.cen[disc.f_own]
+    a = disc.alpha * kbar / np.abs(np.sum(dPN * disc.f_n, axis=1))
+    uP = extrapolate(disc, u, disc.f_own, disc.f_x - disc.cen[disc.f_own])
+    uN = extrapolate(disc, u, disc.f_nei, disc.f_x - disc.cen[disc.f_nei])
+    Ff = Ff + (a[:, None] * (uN - uP)) * disc.f_area[:, None]
+    # displacement faces
+    Fd = np.zeros((disc.d_own.size, disc.dim), dtype=Ff.dtype)
+    if disc.d_own.size:
+        ubq = load * disc.d_ubq
+        G = (np.einsum("fqis,fsj->fqij", disc.d_C, u[disc.d_st])
+             + np.einsum("fqi,fqj->fqij", disc.d_Cg, ubq))
+        Fd = face_term(disc, G, disc.d_n, disc.d_area, disc.d_qw)
+        dPb = disc.d_x - disc.cen[disc.d_own]
+        ab = disc.alpha * kbar / np.abs(np.sum(dPb * disc.d_n, axis=1))
+        uP = extrapolate(disc, u, disc.d_own, dPb)
+        Fd = Fd + (ab[:, None] * (load * disc.d_ubc - uP)) * disc.d_area[:, None]
+    return Ff, Fd
+
+
+def residual(disc, u, load=1.0):
+    """R(u), (n_c, D).  u is (n_c, D) float64 or complex128."""
+    u = np.asarray(u)
+    Ff, Fd = face_fluxes(disc, u, load)
+    R = np.zeros((disc.n_cells, disc.dim), dtype=np.result_type(u.dtype, np.float64))
+    np.add.at(R, disc.f_own, Ff)
+    np.add.at(R, disc.f_nei, -Ff)
+    np.add.at(R, disc.d_own, Fd)
+    R += load * (disc.b_body + disc.b_trac)
+    return R

@@ -1,0 +1,189 @@
+"""Pins of the oracle's J.v, preconditioner, FGMRES and Newton."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as w
+from oracle import jacobian as jc
+from oracle import krylov as kr
+from oracle import newton as nw
+from oracle import precond as pc
+from oracle import residual as rs
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2)])
+def test_jvp_matches_brute_force_linear(dim, p):
+    prob = w.square_mms(5, p, perturb=0.2) if dim == 2 else w.cube_mms(5, p, perturb=0.2)
+    disc = rs.build(prob)
+    J = jc.jacobian_affine(disc)
+    n = disc.n_cells
+    u, v = w.random_state(n, dim, 1), w.random_state(n, dim, 2, scale=1.0)
+    Jv = jc.jvp(disc, u, v)
+    ref = J @ v.ravel()
+    assert np.linalg.norm(Jv.ravel() - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_complex_step_equals_affine_jacobian_for_linear_elasticity():
+    prob = w.square_mms(4, 2, perturb=0.2)
+    disc = rs.build(prob)
+    Ja = jc.jacobian_affine(disc)
+    Jc = jc.jacobian_complex_step(disc, w.random_state(disc.n_cells, 2, 3))
+    assert np.allclose(Ja, Jc, rtol=1e-12, atol=1e-12 * np.abs(Ja).max())
+
+
+def test_jvp_matches_complex_step_neo_hookean():
+    prob = w.cantilever(shape=(6, 3, 3), p=1, n_plus=20)
+    prob.mesh = w.box_mesh((6, 3, 3), lengths=(10.0, 1, 1), perturb=0.1, seed=2)
+    disc = rs.build(prob)
+    n = disc.n_cells
+    u = w.random_state(n, 3, 4, scale=0.05)
+    J = jc.jacobian_complex_step(disc, u)
+    v = w.random_state(n, 3, 5, scale=1.0)
+    Jv = jc.jvp(disc, u, v)
+    ref = J @ v.ravel()
+    assert np.linalg.norm(Jv.ravel() - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_zero_direction_gives_zero_product():
+    disc = rs.build(w.square_mms(4, 1))
+    v = np.zeros((16, 2))
+    assert not np.any(jc.jvp(disc, np.ones((16, 2)), v))
+
+
+def test_compact_preconditioner_is_scaled_laplacian_on_uniform_hex():
+    prob = w.cube_mms(5, 1, perturb=0.0)
+    disc = rs.build(prob)
+    A = pc.assemble(disc)
+    h = 0.2
+    kb = disc.kbar
+    Ad = A.toarray()
+    assert np.allclose(Ad, Ad.T)
+    ijk = w.cell_ijk(prob.mesh)
+    for P in range(disc.n_cells):
+        nb = np.nonzero(np.abs(ijk - ijk[P]).sum(axis=1) == 1)[0]
+        assert np.allclose(Ad[P, nb], kb * h, rtol=1e-13)
+        n_bfaces = 6 - nb.size
+        # displacement faces: Kbar Gamma / |d_Pb . n| = Kbar h^2 / (h/2)
+        assert Ad[P, P] == pytest.approx(-kb * h * nb.size - 2 * kb * h * n_bfaces, rel=1e-13)
+    ev = np.linalg.eigvalsh(Ad)
+    assert ev.max() < 0
+
+
+def test_compact_preconditioner_row_sums_without_dirichlet():
+    prob = w.cantilever(shape=(8, 3, 3), p=1, n_plus=20)
+    disc = rs.build(prob)
+    A = pc.assemble(disc)
+    touches = np.zeros(disc.n_cells, bool)
+    touches[disc.d_own] = True
+    rows = np.asarray(A.sum(axis=1)).ravel()
+    assert np.allclose(rows[~touches], 0.0, atol=1e-12 * np.abs(A.data).max())
+    assert np.all(rows[touches] < 0)
+
+
+def test_greedy_colouring_is_valid_and_red_black_on_grids():
+    for prob in (w.square_mms(6, 1, perturb=0.2), w.cube_mms(4, 1, perturb=0.2)):
+        disc = rs.build(prob)
+        A = pc.assemble(disc)
+        col = pc.greedy_colours(A)
+        Ac = A.tocoo()
+        off = Ac.row != Ac.col
+        assert np.all(col[Ac.row[off]] != col[Ac.col[off]])
+        ijk = w.cell_ijk(prob.mesh)
+        assert np.array_equal(col, ijk.sum(axis=1) % 2)
+
+
+def test_sgs_converges_to_direct_solve_and_fp32_close():
+    prob = w.cube_mms(5, 1, perturb=0.2)
+    disc = rs.build(prob)
+    A = pc.assemble(disc)
+    col = pc.greedy_colours(A)
+    r = w.random_state(disc.n_cells, 3, 9, scale=1.0)
+    z = pc.sgs(A, col, r, 200)
+    ref = np.stack([spla.spsolve(A.tocsc(), r[:, j]) for j in range(3)], axis=1)
+    assert np.allclose(z, ref, rtol=1e-10, atol=1e-12)
+    z64 = pc.sgs(A, col, r, 2)
+    z32 = pc.sgs(A, col, r, 2, dtype=np.float32)
+    assert np.abs(z32 - z64).max() <= 1e-5 * np.abs(z64).max()
+
+
+def test_sgs_block_colour_update_equals_sequential_sweep():
+    prob = w.square_mms(5, 1, perturb=0.2)
+    disc = rs.build(prob)
+    A = pc.assemble(disc).tocsr()
+    col = pc.greedy_colours(A)
+    r = w.random_state(disc.n_cells, 2, 1, scale=1.0)
+    order = [P for c in (0, 1) for P in np.nonzero(col == c)[0]]
+    order = order + order[::-1]
+    z = np.zeros_like(r)
+    for P in order:  # plain Gauss-Seidel in colour order
+        s = r[P].copy()
+        for t in range(A.indptr[P], A.indptr[P + 1]):
+            if A.indices[t] != P:
+                s -= A.data[t] * z[A.indices[t]]
+        z[P] = s / A[P, P]
+    assert np.allclose(pc.sgs(A, col, r, 1), z, rtol=1e-13, atol=1e-15)
+
+
+def test_fgmres_matches_dense_solve():
+    rng = np.random.default_rng(0)
+    for n in (5, 40, 120):
+        A = rng.standard_normal((n, n)) + n * np.eye(n)
+        b = rng.standard_normal(n)
+        x, info = kr.fgmres(lambda v: A @ v, b, m=30, rtol=1e-12, maxit=2000)
+        assert info["converged"]
+        assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-9)
+
+
+def test_fgmres_exact_preconditioner_one_iteration():
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((50, 50)) + 10 * np.eye(50)
+    Ainv = np.linalg.inv(A)
+    b = rng.standard_normal(50)
+    x, info = kr.fgmres(lambda v: A @ v, b, M=lambda v: Ainv @ v, rtol=1e-10)
+    assert info["iters"] == 1 and np.allclose(x, np.linalg.solve(A, b))
+
+
+def test_fgmres_residual_estimate_monotone():
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((80, 80)) + 5 * np.eye(80)
+    b = rng.standard_normal(80)
+    _, info = kr.fgmres(lambda v: A @ v, b, m=30, rtol=1e-10, maxit=29)
+    h = np.asarray(info["hist"])
+    assert np.all(np.diff(h[:30]) <= 1e-14)
+
+
+def test_newton_linear_elastic_converges_in_three_steps():
+    prob = w.square_mms(12, 2, perturb=0.2)
+    disc = rs.build(prob)
+    u, st = nw.newton(disc, np.zeros((disc.n_cells, 2)), tol=1e-10, eta=1e-4)
+    assert st["newton"] <= 3
+    R = rs.residual(disc, u)
+    assert np.linalg.norm(R) <= 1e-10 * np.linalg.norm(rs.residual(disc, 0 * u))
+
+
+def test_cubic_patch_test_p3_is_exact():
+    """p = 3 reproduces a cubic displacement field to machine precision (Sec. 5, case 2)."""
+    mesh = w.box_mesh((8, 8), perturb=0.2, seed=4)
+    prob = w.poly_patch(mesh, 3, 3, seed=6)
+    disc = rs.build(prob)
+    u, _ = nw.newton(disc, np.zeros((disc.n_cells, 2)), tol=1e-13, eta=1e-6, maxit_newton=8)
+    ue = prob.loads.exact.value(disc.cen)
+    assert np.abs(u - ue).max() <= 1e-9 * np.abs(ue).max()
+
+
+@pytest.mark.slow
+def test_mms_orders_2d():
+    """Observed displacement orders on 8^2, 16^2, 32^2 (Sec. 5.1, case 1)."""
+    errs = {p: [] for p in (1, 2, 3)}
+    for n in (8, 16, 32):
+        for p in (1, 2, 3):
+            prob = w.square_mms(n, p)
+            disc = rs.build(prob)
+            u, _ = nw.newton(disc, np.zeros((disc.n_cells, 2)), tol=1e-11, eta=1e-4)
+            ue = prob.loads.exact.value(disc.cen)
+            errs[p].append(np.sqrt(np.mean(np.sum((u - ue) ** 2, axis=1))))
+    order = {p: np.log2(errs[p][1] / errs[p][2]) for p in errs}
+    assert order[1] > 1.8
+    assert order[2] > 1.5
+    assert order[3] > 3.0
+    assert errs[3][2] < errs[2][2] < errs[1][2]

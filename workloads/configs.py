@@ -1,0 +1,114 @@
+"""Named synthetic workloads shaped like the paper's benchmarks (inputs only).
+
+Each builder returns a :class:`Problem`: a seeded mesh, the discretisation
+parameters (order p, stencil surplus n+, Gauss points per face direction, alpha,
+weight shape k, ghost weight), the material, and the loads as point functions.
+
+* ``square_mms``   - 2D plane-strain manufactured solution on the unit square
+                     (32 x 32 quads, p = 2, 2 Gauss points per edge).
+* ``cube_mms``     - 3D linear elastic manufactured trigonometric solution on a
+                     perturbed hex mesh of the unit cube (64^3, p = 3, 2x2 points).
+* ``cantilever``   - 3D neo-Hookean cantilever 200 x 20 x 20 on [0,10]x[0,1]^2,
+                     clamped at x = 0, dead tip traction, 10 load increments.
+* ``poly_patch``   - any mesh with a random polynomial field of degree <= p and
+                     its exact loads (patch tests).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .fields import (Loads, cantilever_loads, lame_from_young, mms_2d_unit, mms_3d_trig,
+                     mms_loads, random_poly_field)
+from .meshes import Mesh, box_mesh
+
+LINEAR_ELASTIC, NEO_HOOKEAN = 0, 1
+
+PAPER_N_PLUS = {2: {1: 10, 2: 10, 3: 10}, 3: {1: 45, 2: 55, 3: 65}}
+
+
+@dataclass
+class Problem:
+    name: str
+    mesh: Mesh
+    p: int
+    n_plus: int
+    n_gauss: int
+    material: int
+    mu: float
+    lam: float
+    loads: Loads
+    alpha: float = 0.1
+    k_weight: float = 6.0
+    ghost_weight: float = 1.0
+    stencil_quantum: float = 0.0
+    n_increments: int = 1
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def dim(self):
+        return self.mesh.dim
+
+    @property
+    def stencil_size(self):
+        d, p = self.dim, self.p
+        nt = (p + 1) * (p + 2) // 2 if d == 2 else (p + 1) * (p + 2) * (p + 3) // 6
+        return nt + self.n_plus
+
+
+def default_gauss(p: int) -> int:
+    return 1 if p == 1 else 2
+
+
+def quantum_for(mesh: Mesh) -> float:
+    """Squared-distance quantum used to break stencil ties (1e-6 h_min^2)."""
+    return 1e-6 * float(np.min(mesh.spacing())) ** 2
+
+
+def square_mms(n: int = 32, p: int = 2, perturb: float = 0.0, seed: int = 0,
+               E: float = 1.0, nu: float = 0.3, n_plus=None, n_gauss=None) -> Problem:
+    mesh = box_mesh((n, n), perturb=perturb, seed=seed)
+    mu, lam = lame_from_young(E, nu)
+    return Problem(f"square_mms_{n}_p{p}", mesh, p, PAPER_N_PLUS[2][p] if n_plus is None else n_plus,
+                   n_gauss or default_gauss(p), LINEAR_ELASTIC, mu, lam,
+                   mms_loads(mms_2d_unit(), mu, lam), stencil_quantum=quantum_for(mesh))
+
+
+def cube_mms(n: int = 64, p: int = 3, perturb: float = 0.2, seed: int = 0,
+             E: float = 1.0, nu: float = 0.3, n_plus=None, n_gauss=None, lengths=None,
+             mode: str = "random") -> Problem:
+    shape = (n, n, n) if np.isscalar(n) else tuple(n)
+    mesh = box_mesh(shape, lengths=lengths, perturb=perturb, seed=seed, mode=mode)
+    mu, lam = lame_from_young(E, nu)
+    return Problem(f"cube_mms_{'x'.join(map(str, shape))}_p{p}", mesh, p,
+                   PAPER_N_PLUS[3][p] if n_plus is None else n_plus,
+                   n_gauss or default_gauss(p), LINEAR_ELASTIC, mu, lam,
+                   mms_loads(mms_3d_trig(), mu, lam), stencil_quantum=quantum_for(mesh))
+
+
+def cantilever(shape=(200, 20, 20), p: int = 2, mu: float = 1.0, lam: float = 10.0,
+               tip_traction: float = 2.18e-3, n_increments: int = 10, perturb: float = 0.0,
+               seed: int = 0, n_plus=None) -> Problem:
+    L = 10.0
+    mesh = box_mesh(shape, lengths=(L, 1.0, 1.0), perturb=perturb, seed=seed)
+    loads = cantilever_loads(L, (0.0, -tip_traction, 0.0))
+    return Problem(f"cantilever_{'x'.join(map(str, shape))}_p{p}", mesh, p,
+                   PAPER_N_PLUS[3][p] if n_plus is None else n_plus, default_gauss(p),
+                   NEO_HOOKEAN, mu, lam, loads, stencil_quantum=quantum_for(mesh),
+                   n_increments=n_increments)
+
+
+def poly_patch(mesh: Mesh, p: int, degree: int, seed: int = 0, E: float = 1.0, nu: float = 0.3,
+               n_plus=None, n_gauss=None, scale: float = 1.0, traction_faces=None) -> Problem:
+    mu, lam = lame_from_young(E, nu)
+    fld = random_poly_field(mesh.dim, degree, seed, scale)
+    return Problem(f"poly{degree}_p{p}", mesh, p,
+                   PAPER_N_PLUS[mesh.dim][p] if n_plus is None else n_plus,
+                   n_gauss or default_gauss(p), LINEAR_ELASTIC, mu, lam,
+                   mms_loads(fld, mu, lam, traction_faces), stencil_quantum=quantum_for(mesh))
+
+
+def random_state(n_cells: int, dim: int, seed: int, scale: float = 1e-3) -> np.ndarray:
+    """Seeded N(0,1)*scale displacement state (n_cells, dim)."""
+    return np.random.default_rng(seed).standard_normal((n_cells, dim)) * scale

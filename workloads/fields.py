@@ -1,0 +1,214 @@
+"""Manufactured displacement fields and the loads that go with them (inputs only).
+
+A field gives u(x) and its exact partial derivatives.  The loads a problem
+needs are evaluated from the exact field:
+
+* body force of linear elasticity, f_b = -div(sigma(u)), with
+  sigma = mu (grad u + grad u^T) + lambda (div u) I;
+* traction on a boundary with outward normal n, t_j = sum_i n_i sigma_ij.
+
+These are the manufactured-solution inputs of a problem, not part of the
+finite-volume method, and are shared by the CPU oracle and the GPU library.
+Derivative multi-indices are tuples (a, b[, c]).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def lame_from_young(E: float, nu: float):
+    """Lame parameters (mu, lambda) from Young's modulus and Poisson's ratio."""
+    mu = E / (2.0 * (1.0 + nu))
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    return mu, lam
+
+
+class Field:
+    dim: int
+
+    def deriv(self, x: np.ndarray, alpha) -> np.ndarray:
+        """d^alpha u at points x (m, dim) -> (m, dim) (component-minor)."""
+        raise NotImplementedError
+
+    def value(self, x):
+        return self.deriv(x, (0,) * self.dim)
+
+    def grad(self, x):
+        """G[m, i, j] = d u_j / d x_i."""
+        out = np.empty((x.shape[0], self.dim, self.dim))
+        for i in range(self.dim):
+            a = [0] * self.dim
+            a[i] = 1
+            out[:, i, :] = self.deriv(x, tuple(a))
+        return out
+
+    def second(self, x, i, j):
+        a = [0] * self.dim
+        a[i] += 1
+        a[j] += 1
+        return self.deriv(x, tuple(a))
+
+
+@dataclass
+class TrigField(Field):
+    """u_j = sum_t coef[t, j] * prod_d sin(k[t, d] x_d + phase[t, d])."""
+    dim: int
+    coef: np.ndarray   # (terms, dim)
+    k: np.ndarray      # (terms, dim)
+    phase: np.ndarray  # (terms, dim)
+
+    def deriv(self, x, alpha):
+        x = np.atleast_2d(np.asarray(x, float))
+        out = np.zeros((x.shape[0], self.dim))
+        for t in range(self.coef.shape[0]):
+            prod = np.ones(x.shape[0])
+            for d in range(self.dim):
+                n = alpha[d]
+                kk = self.k[t, d]
+                prod = prod * (kk ** n) * np.sin(kk * x[:, d] + self.phase[t, d] + n * (math.pi / 2))
+            out += prod[:, None] * self.coef[t][None, :]
+        return out
+
+
+@dataclass
+class PolyField(Field):
+    """u_j = sum_m coef[m, j] * x^e[m, 0] * y^e[m, 1] (* z^e[m, 2])."""
+    dim: int
+    expo: np.ndarray  # (monomials, dim) int
+    coef: np.ndarray  # (monomials, dim)
+
+    def deriv(self, x, alpha):
+        x = np.atleast_2d(np.asarray(x, float))
+        out = np.zeros((x.shape[0], self.dim))
+        for m in range(self.expo.shape[0]):
+            prod = np.ones(x.shape[0])
+            ok = True
+            for d in range(self.dim):
+                e, n = int(self.expo[m, d]), int(alpha[d])
+                if n > e:
+                    ok = False
+                    break
+                c = math.factorial(e) // math.factorial(e - n)
+                prod = prod * c * x[:, d] ** (e - n)
+            if ok:
+                out += prod[:, None] * self.coef[m][None, :]
+        return out
+
+
+def random_poly_field(dim: int, degree: int, seed: int, scale: float = 1.0) -> PolyField:
+    """All monomials of total degree <= degree, seeded N(0,1)*scale coefficients."""
+    expo = [e for e in np.ndindex(*([degree + 1] * dim)) if sum(e) <= degree]
+    rng = np.random.default_rng(seed)
+    coef = rng.standard_normal((len(expo), dim)) * scale
+    return PolyField(dim, np.asarray(expo, int), coef)
+
+
+@dataclass
+class ZeroField(Field):
+    dim: int
+
+    def deriv(self, x, alpha):
+        return np.zeros((np.atleast_2d(x).shape[0], self.dim))
+
+
+def stress_le(G: np.ndarray, mu: float, lam: float) -> np.ndarray:
+    """Small-strain stress from G[m, i, j] = du_j/dx_i (input helper for loads)."""
+    dim = G.shape[-1]
+    tr = np.trace(G, axis1=-2, axis2=-1)
+    return mu * (G + np.swapaxes(G, -1, -2)) + lam * tr[..., None, None] * np.eye(dim)
+
+
+def body_force_le(fld: Field, mu: float, lam: float, x: np.ndarray) -> np.ndarray:
+    """f_b = -(mu lap u + (mu + lambda) grad div u) at x (m, dim)."""
+    dim = fld.dim
+    x = np.atleast_2d(x)
+    f = np.zeros((x.shape[0], dim))
+    for d in range(dim):
+        f -= mu * fld.second(x, d, d)
+    for j in range(dim):
+        s = np.zeros(x.shape[0])
+        for d in range(dim):
+            s += fld.second(x, j, d)[:, d]
+        f[:, j] -= (mu + lam) * s
+    return f
+
+
+def traction_le(fld: Field, mu: float, lam: float, x: np.ndarray, n: np.ndarray) -> np.ndarray:
+    """t_j = sum_i n_i sigma_ij of the exact field."""
+    sig = stress_le(fld.grad(np.atleast_2d(x)), mu, lam)
+    return np.einsum("mi,mij->mj", np.atleast_2d(n), sig)
+
+
+def mms_2d_unit() -> TrigField:
+    """u = (sin(pi x) sin(pi y), cos(pi x) sin(pi y)) on the unit square."""
+    pi = math.pi
+    coef = np.array([[1.0, 0.0], [0.0, 1.0]])
+    k = np.array([[pi, pi], [pi, pi]])
+    phase = np.array([[0.0, 0.0], [pi / 2, 0.0]])
+    return TrigField(2, coef, k, phase)
+
+
+def mms_3d_trig(a=(2e-6, 4e-6, 6e-6)) -> TrigField:
+    """u_i = a_i sin(4 pi x) sin(2 pi y) sin(pi z) (the 3D manufactured field)."""
+    pi = math.pi
+    coef = np.array([list(a)], float)
+    k = np.array([[4 * pi, 2 * pi, pi]])
+    phase = np.zeros((1, 3))
+    return TrigField(3, coef, k, phase)
+
+
+@dataclass
+class Loads:
+    """Everything a problem prescribes, as point functions.
+
+    bc_type(xc, n) -> int array (0 = displacement, 1 = traction) per boundary face.
+    u_b(x) -> prescribed displacement; traction(x, n) -> prescribed traction;
+    body(x) -> body force.  All take/return (m, dim) arrays.
+    """
+    dim: int
+    bc_type: object
+    u_b: object
+    traction: object
+    body: object
+    exact: Field | None = None
+    meta: dict = field(default_factory=dict)
+
+
+DISP, TRAC = 0, 1
+
+
+def mms_loads(fld: Field, mu: float, lam: float, traction_faces=None) -> Loads:
+    """Manufactured problem: displacement BC everywhere except faces selected by
+    ``traction_faces(xc, n) -> bool`` which get the exact traction."""
+    def bc_type(xc, n):
+        t = np.full(xc.shape[0], DISP, np.int32)
+        if traction_faces is not None:
+            t[traction_faces(xc, n)] = TRAC
+        return t
+    return Loads(fld.dim, bc_type, fld.value,
+                 lambda x, n: traction_le(fld, mu, lam, x, n),
+                 lambda x: body_force_le(fld, mu, lam, x), exact=fld)
+
+
+def cantilever_loads(length: float, tip_traction) -> Loads:
+    """Clamped at x = 0 (u = 0), dead-load traction on x = length, free elsewhere."""
+    tip = np.asarray(tip_traction, float)
+    dim = tip.shape[0]
+    tol = 1e-9 * length
+
+    def bc_type(xc, n):
+        t = np.full(xc.shape[0], TRAC, np.int32)
+        t[np.abs(xc[:, 0]) < tol] = DISP
+        return t
+
+    def traction(x, n):
+        out = np.zeros((x.shape[0], dim))
+        out[np.abs(x[:, 0] - length) < tol] = tip
+        return out
+
+    return Loads(dim, bc_type, lambda x: np.zeros((x.shape[0], dim)), traction,
+                 lambda x: np.zeros((x.shape[0], dim)), exact=None,
+                 meta={"tip_traction": tip.tolist()})

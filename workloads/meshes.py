@@ -1,0 +1,111 @@
+"""Seeded structured mesh generators (inputs only, no discretisation arithmetic).
+
+Both the CPU oracle and the GPU library consume the arrays made here.  A mesh
+is a vertex array ``verts`` (n_verts, dim) float64 and a connectivity array
+``cells`` (n_cells, 4 | 8) int64 in VTK order:
+
+* 2D quad:  0 (x0,y0), 1 (x1,y0), 2 (x1,y1), 3 (x0,y1)  -- counter-clockwise.
+* 3D hex:   0..3 as the quad on the bottom z-plane, 4..7 the same on the top.
+
+Cells and vertices are numbered lexicographically with i (x) fastest.
+
+Perturbation (the "randomly perturbed by up to +-20 % of spacing" meshes): every
+interior vertex, every axis, gets an independent uniform offset in
+[-a*h_axis, +a*h_axis] drawn from ``numpy.random.default_rng(seed)`` in vertex
+order (i fastest), axis-minor.  Boundary vertices are not moved, so the domain
+stays an exact box.  ``mode="tensor"`` instead perturbs the 1D grid lines of
+each axis (faces stay planar).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Mesh:
+    dim: int
+    verts: np.ndarray  # (n_verts, dim) float64
+    cells: np.ndarray  # (n_cells, 2**dim) int64, VTK order
+    shape: tuple       # cells per axis
+    lengths: tuple     # box edge lengths
+    origin: tuple
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cells.shape[0])
+
+    @property
+    def n_verts(self) -> int:
+        return int(self.verts.shape[0])
+
+    def spacing(self) -> np.ndarray:
+        return np.asarray(self.lengths, float) / np.asarray(self.shape, float)
+
+
+def _grid_lines(n: int, length: float, origin: float) -> np.ndarray:
+    return origin + length * np.arange(n + 1, dtype=np.float64) / n
+
+
+def box_mesh(shape, lengths=None, origin=None, perturb: float = 0.0,
+             seed: int = 0, mode: str = "random") -> Mesh:
+    """Structured quad (len(shape)==2) or hex (len(shape)==3) mesh of a box.
+
+    ``perturb`` is the maximum vertex offset as a fraction of the local cell
+    spacing along each axis; ``mode`` is "random" (per interior vertex) or
+    "tensor" (per interior grid line, keeps faces planar).
+    """
+    shape = tuple(int(s) for s in shape)
+    dim = len(shape)
+    if dim not in (2, 3):
+        raise ValueError("shape must have 2 or 3 entries")
+    lengths = tuple(float(v) for v in (lengths or (1.0,) * dim))
+    origin = tuple(float(v) for v in (origin or (0.0,) * dim))
+    h = np.asarray(lengths) / np.asarray(shape)
+
+    lines = [_grid_lines(shape[a], lengths[a], origin[a]) for a in range(dim)]
+    if perturb and mode == "tensor":
+        rng = np.random.default_rng(seed)
+        for a in range(dim):
+            off = rng.uniform(-perturb * h[a], perturb * h[a], size=shape[a] + 1)
+            off[0] = off[-1] = 0.0
+            lines[a] = lines[a] + off
+
+    nv = [s + 1 for s in shape]
+    if dim == 2:
+        X, Y = np.meshgrid(lines[0], lines[1], indexing="xy")  # (ny+1, nx+1)
+        verts = np.stack([X.ravel(), Y.ravel()], axis=1)
+    else:
+        Z, Y, X = np.meshgrid(lines[2], lines[1], lines[0], indexing="ij")
+        verts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+
+    if perturb and mode == "random":
+        rng = np.random.default_rng(seed)
+        off = rng.uniform(-1.0, 1.0, size=verts.shape) * (perturb * h)[None, :]
+        idx = np.indices(nv[::-1]).reshape(dim, -1)[::-1].T  # (n_verts, dim): i, j[, k]
+        interior = np.all((idx > 0) & (idx < np.asarray(shape)[None, :]), axis=1)
+        verts[interior] += off[interior]
+    elif perturb and mode != "tensor":
+        raise ValueError("mode must be 'random' or 'tensor'")
+
+    def vid(i, j, k=0):
+        return (k * nv[1] + j) * nv[0] + i
+
+    if dim == 2:
+        j, i = np.meshgrid(np.arange(shape[1]), np.arange(shape[0]), indexing="ij")
+        i = i.ravel(); j = j.ravel()
+        cells = np.stack([vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)], axis=1)
+    else:
+        k, j, i = np.meshgrid(np.arange(shape[2]), np.arange(shape[1]), np.arange(shape[0]), indexing="ij")
+        i = i.ravel(); j = j.ravel(); k = k.ravel()
+        cells = np.stack([vid(i, j, k), vid(i + 1, j, k), vid(i + 1, j + 1, k), vid(i, j + 1, k),
+                          vid(i, j, k + 1), vid(i + 1, j, k + 1), vid(i + 1, j + 1, k + 1), vid(i, j + 1, k + 1)], axis=1)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    return Mesh(dim, verts, cells, shape, lengths, origin)
+
+
+def cell_ijk(mesh: Mesh) -> np.ndarray:
+    """Structured (i, j[, k]) index of every cell, (n_cells, dim)."""
+    return np.indices(mesh.shape[::-1]).reshape(mesh.dim, -1)[::-1].T.copy()
