@@ -1,0 +1,227 @@
+/*
+ * hofv.h - C ABI of the MI355X (gfx950) library for the Jacobian-free
+ * Newton-Krylov solution of high-order cell-centred finite-volume solid
+ * mechanics (Batistic, Castrillo, Cardiff, arXiv 2601.18417).
+ *
+ * Problem statement (paper Sec. 4.1): find the cell-centroid displacements u
+ * with R(u) = 0, where R is the high-order finite-volume residual of Secs. 3.2-3.5
+ * (least-squares face-point gradients, linear-elastic or neo-Hookean
+ * tractions, alpha-stabilisation, face-to-cell sum, body force and boundary
+ * loads), by Newton's method with the finite-difference Jacobian-vector
+ * product J v ~ (R(u + eps v) - R(u)) / eps inside a Krylov solver that is
+ * preconditioned by the compact-stencil approximate Jacobian.
+ *
+ * Conventions for every function:
+ *  - The return value is a hofv_status; 0 is success.  Nothing throws or
+ *    aborts across this interface; hofv_last_error() describes the last
+ *    failure on a context.
+ *  - Host arrays passed in are copied before the call returns; the caller
+ *    keeps ownership.  Host pointers handed out by the library stay valid
+ *    until hofv_destroy().
+ *  - "Device" pointers are HIP device allocations (e.g. from PyTorch tensors)
+ *    on the device that was current at hofv_create().  Field vectors are FP64,
+ *    component-major: v[c * n_cells + P], c < dim, in the caller's cell
+ *    numbering.  They must stay alive until the work queued on `stream`
+ *    completes.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Hot
+ *    calls only queue work on it, except where a call says it synchronises.
+ *  - Call order: create -> set_mesh -> (boundary_faces, volume_qpoints) ->
+ *    set_bc -> set_body_force -> setup -> hot calls.  Out of order: HOFV_ESTATE.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef HOFV_H
+#define HOFV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hofv_ctx hofv_ctx;
+
+typedef enum {
+  HOFV_OK = 0,
+  HOFV_EINVAL = -1,     /* bad argument */
+  HOFV_ENOMEM = -2,     /* host or device allocation failed */
+  HOFV_EHIP = -3,       /* a HIP runtime call failed */
+  HOFV_ESINGULAR = -4,  /* a least-squares stencil is rank deficient */
+  HOFV_ENOCONV = -5,    /* an iterative solve did not reach its tolerance */
+  HOFV_ENAN = -6,       /* NaN/Inf met in a solve */
+  HOFV_EINVERTED = -7,  /* neo-Hookean: det F <= 0 at a quadrature point */
+  HOFV_ESTATE = -8      /* call made out of order */
+} hofv_status;
+
+enum { HOFV_LINEAR_ELASTIC = 0, HOFV_NEO_HOOKEAN = 1 };
+enum { HOFV_BC_DISPLACEMENT = 0, HOFV_BC_TRACTION = 1 };
+
+/* Discretisation parameters (paper Secs. 3.4-3.5). */
+typedef struct {
+  int32_t dim;            /* 2 (plane strain, quads) or 3 (hexahedra) */
+  int32_t order_p;        /* reconstruction order p = 1, 2, 3 (2nd/3rd/4th order) */
+  int32_t n_plus;         /* surplus stencil nodes n+, |S| = N_t + n+ (Sec. 3.5.2) */
+  int32_t n_gauss;        /* Gauss-Legendre points per face direction */
+  int32_t material;       /* HOFV_LINEAR_ELASTIC or HOFV_NEO_HOOKEAN (3D only) */
+  int32_t fold_quadrature;/* 1: linear elasticity sums the face-point coefficients
+                             over the quadrature points at setup (same R, fewer
+                             bytes); 0: per-point gradients.  Ignored for NH. */
+  double mu, lambda;      /* Lame parameters; Kbar = 2 mu + lambda (Sec. 3.4) */
+  double alpha;           /* stabilisation scale, eq. alpha (paper default 0.1) */
+  double k_weight;        /* shape k of eq. weightFunc (paper: 6) */
+  double ghost_weight;    /* weight of displacement ghost nodes (paper: 1) */
+  double stencil_quantum; /* squared distances closer than this tie; ties are
+                             broken by lower caller cell id (> 0 required) */
+  int32_t host_only;      /* 1: no device is used; hofv_setup builds the tables on
+                             the host and keeps them for hofv_host_table (for
+                             inspection on machines without a GPU); hot calls
+                             then fail with HOFV_ESTATE */
+} hofv_params;
+
+/* Creates a context on the current HIP device.  *out is NULL on failure. */
+hofv_status hofv_create(const hofv_params* params, hofv_ctx** out);
+
+/* Frees every host and device buffer of ctx.  NULL is accepted. */
+hofv_status hofv_destroy(hofv_ctx* ctx);
+
+/* Last error message of ctx (or of the last failed hofv_create when ctx is
+ * NULL); valid until the next call on ctx. */
+const char* hofv_last_error(const hofv_ctx* ctx);
+
+/* Mesh (Sec. 3.1): verts [n_verts][dim] FP64; cell_verts [n_cells][4 | 8]
+ * int64 in VTK quad/hexahedron order.  Faces are matched by vertex sets. */
+hofv_status hofv_set_mesh(hofv_ctx* ctx, int64_t n_verts, const double* verts,
+                          int64_t n_cells, const int64_t* cell_verts);
+
+/* Boundary faces in the library's order, so that the caller can evaluate its
+ * boundary conditions there: face centres x_b [n][dim], unit outward normals
+ * [n][dim], quadrature points x_{b,q} [n][n_q][dim] with n_q = n_gauss^(dim-1).
+ * Pointers are owned by ctx. */
+hofv_status hofv_boundary_faces(hofv_ctx* ctx, int64_t* n_bfaces, int32_t* n_q,
+                                const double** centres, const double** normals,
+                                const double** qpoints);
+
+/* Volume quadrature points of the body-force integral (eq. bodyTerm),
+ * [n_cells][n_qv][dim], n_qv = (p+2)^dim Gauss-Legendre points of the cell map. */
+hofv_status hofv_volume_qpoints(hofv_ctx* ctx, int32_t* n_qv, const double** points);
+
+/* Boundary conditions (Sec. 3.5.3), per boundary face in hofv_boundary_faces
+ * order: type[n] (HOFV_BC_*); u_b at the quadrature points [n][n_q][dim] and at
+ * the face centre [n][dim] (read on displacement faces); nominal traction at
+ * the quadrature points [n][n_q][dim] (read on traction faces).  NULL arrays
+ * mean zero. */
+hofv_status hofv_set_bc(hofv_ctx* ctx, const int32_t* type, const double* u_b_q,
+                        const double* u_b_centre, const double* traction_q);
+
+/* Body force f_b at the volume quadrature points [n_cells][n_qv][dim]; NULL = 0. */
+hofv_status hofv_set_body_force(hofv_ctx* ctx, const double* values);
+
+typedef struct {
+  int32_t stencil_size;    /* |S| */
+  int32_t n_colours;       /* colours of the preconditioner sweeps */
+  int64_t n_internal_faces, n_disp_faces, n_trac_faces;
+  double max_cond;         /* largest max|R_ii| / min|R_ii| of the LS QRs */
+  double device_bytes;     /* device memory held by the context */
+  double residual_bytes;   /* algorithmic HBM bytes of one residual */
+  double setup_seconds;
+} hofv_setup_report;
+
+/* Builds stencils (Sec. 3.5.2), least-squares coefficients (Sec. 3.5.1,
+ * Householder QR), sources, the compact preconditioner and its colouring on
+ * the host, then copies everything to the device.  Synchronises.  Fails with
+ * HOFV_ESINGULAR when a stencil is rank deficient (min|R_ii| <= 1e-14 max). */
+hofv_status hofv_setup(hofv_ctx* ctx, hofv_setup_report* report);
+
+/* Load factor s for load increments: u_b, tractions and f_b are scaled by s. */
+hofv_status hofv_set_load_scale(hofv_ctx* ctx, double s);
+
+/* R = R(u) (eq. divStressDiscret with eqs. faceQuadGrad, alpha, alphaJump,
+ * bodyTerm).  d_u, d_R: device [dim][n_cells]; they must not alias. */
+hofv_status hofv_residual(hofv_ctx* ctx, const double* d_u, double* d_R, void* stream);
+
+/* Jv = (R(u + eps v) - R(u)) / eps (Sec. 4.1).  d_Ru must hold R(u).
+ * eps <= 0 selects eps = sqrt((1 + ||u||_2) eps_mach) / ||v||_2 computed on the
+ * device (Jv = 0 when v = 0).  d_Jv must not alias the inputs. */
+hofv_status hofv_jvp(hofv_ctx* ctx, const double* d_u, const double* d_Ru, const double* d_v,
+                     double* d_Jv, double eps, void* stream);
+
+/* z ~ P^{-1} r with P the compact approximate Jacobian (Sec. 4.1): n_sweeps
+ * symmetric multicolour Gauss-Seidel sweeps in FP32 from z = 0.  learned != 0
+ * adds the network correction (hofv_nn_*) when one is loaded.  d_r, d_z must
+ * not alias. */
+hofv_status hofv_precond_apply(hofv_ctx* ctx, const double* d_r, double* d_z, int32_t n_sweeps,
+                               int32_t learned, void* stream);
+
+typedef struct {
+  int32_t restart;       /* m of FGMRES(m), default 30 */
+  int32_t max_iters;     /* total Krylov iterations */
+  double rtol;           /* stop at ||rhs - J x|| <= rtol ||rhs|| */
+  int32_t n_sweeps;      /* preconditioner sweeps per application */
+  int32_t learned;       /* use the learned correction */
+} hofv_krylov_opts;
+
+typedef struct {
+  int32_t iters;
+  int32_t converged;
+  double rel_residual;   /* final ||rhs - J x|| / ||rhs|| (recomputed) */
+  double seconds;
+} hofv_krylov_stats;
+
+/* Solves J(u) x = rhs by right-preconditioned flexible GMRES(m) with J v from
+ * hofv_jvp and z = M(v) from hofv_precond_apply; x holds the initial guess on
+ * entry.  Synchronises once per iteration (Hessenberg column to the host). */
+hofv_status hofv_fgmres_solve(hofv_ctx* ctx, const double* d_u, const double* d_Ru,
+                              const double* d_rhs, double* d_x, const hofv_krylov_opts* opts,
+                              hofv_krylov_stats* stats, void* stream);
+
+typedef struct {
+  double tol;            /* ||R|| <= tol ||R_0|| per load increment */
+  double eta;            /* Krylov rtol per Newton step */
+  int32_t max_newton;    /* per increment */
+  int32_t n_increments;  /* load factors i / n, i = 1..n */
+  int32_t max_line_search; /* backtracking halvings */
+  hofv_krylov_opts krylov;
+} hofv_newton_opts;
+
+typedef struct {
+  int32_t newton_iters;
+  int32_t krylov_iters;
+  int32_t converged;
+  double rel_residual;   /* of the last increment */
+  double seconds;
+} hofv_newton_stats;
+
+/* Newton with backtracking line search on ||R||_2 (accept the first
+ * ||R(u + lam du)|| <= (1 - 1e-4 lam) ||R(u)||, lam = 1, 1/2, ...), J du = -R by
+ * hofv_fgmres_solve, for each load increment.  d_u: initial guess in,
+ * solution out.  Synchronises. */
+hofv_status hofv_newton_solve(hofv_ctx* ctx, double* d_u, const hofv_newton_opts* opts,
+                              hofv_newton_stats* stats, void* stream);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around
+ * every kernel while enabled.  hofv_kernel_time synchronises and returns the
+ * summed milliseconds and launch count of the kernel called `name` since the
+ * last reset (enable = 1 resets). */
+hofv_status hofv_set_timing(hofv_ctx* ctx, int32_t enable);
+hofv_status hofv_kernel_time(hofv_ctx* ctx, const char* name, double* total_ms, int64_t* count);
+
+/* Host copy of a setup table of a host_only context (after hofv_setup):
+ * name is one of "face_stencil" [S][nf] i32, "cell_stencil" [S][nc] i32,
+ * "face_coef" f64 ([S][dim][nf] folded, [S][nq][dim][nf] per point),
+ * "cell_extrap" [S][2 dim][nc] f64, "face_own", "face_nei" [nf] i32,
+ * "face_area_vec" f64, "face_stab" [nf] f64, "cell_faces" [2 dim][nc] i32,
+ * "cell_src" [dim][nc] f64, "pc_perm" [nc] i32, "pc_dinv" [nc] f32,
+ * "pc_a" [2 dim][nc] f32, "pc_nbr" [2 dim][nc] i32, "centroids" [nc][dim] f64,
+ * "face_centre" [nf][dim] f64.
+ * *data stays valid until hofv_destroy; *count is the number of elements and
+ * *elem_bytes their size. */
+hofv_status hofv_host_table(hofv_ctx* ctx, const char* name, int64_t* count, int32_t* elem_bytes,
+                            const void** data);
+
+/* Algorithmic HBM bytes of one launch of kernel `name` (the byte model). */
+hofv_status hofv_kernel_bytes(hofv_ctx* ctx, const char* name, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOFV_H */

@@ -1,0 +1,201 @@
+"""Thin Python binding of libhofv: argument marshalling only.
+
+Device vectors are torch tensors on the HIP device, float64, laid out
+component-major ([dim][n_cells], i.e. shape (dim, n_cells), contiguous).  Every
+computation happens in the library; this module only passes pointers, sizes
+and options, and evaluates the caller's boundary/body-force functions at the
+points the library reports (those functions are problem inputs).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+class HofvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{L.STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 HIP tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+class Context:
+    """One discretisation on one device (hofv_ctx)."""
+
+    def __init__(self, dim, order_p, n_plus, n_gauss, material, mu, lam, alpha=0.1, k_weight=6.0,
+                 ghost_weight=1.0, stencil_quantum=1e-12, fold_quadrature=True, host_only=False):
+        self.lib = L.load()
+        prm = L.Params(dim, order_p, n_plus, n_gauss, material, int(bool(fold_quadrature)), mu, lam, alpha,
+                       k_weight, ghost_weight, stencil_quantum, int(bool(host_only)))
+        h = C.c_void_p()
+        st = self.lib.hofv_create(C.byref(prm), C.byref(h))
+        if st != L.HOFV_OK:
+            raise HofvError(st, self.lib.hofv_last_error(None).decode())
+        self.h = h
+        self.dim = dim
+        self.params = prm
+        self.n_cells = 0
+        self.report = None
+
+    def _check(self, st):
+        if st != L.HOFV_OK:
+            raise HofvError(st, self.lib.hofv_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hofv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------- setup
+    def set_mesh(self, verts, cells):
+        verts = np.ascontiguousarray(verts, np.float64)
+        cells = np.ascontiguousarray(cells, np.int64)
+        self._check(self.lib.hofv_set_mesh(self.h, verts.shape[0], _dptr(verts), cells.shape[0],
+                                           cells.ctypes.data_as(C.POINTER(C.c_int64))))
+        self.n_cells = cells.shape[0]
+
+    def boundary_faces(self):
+        n = C.c_int64()
+        nq = C.c_int32()
+        cen, nor, qp = (C.POINTER(C.c_double)(), C.POINTER(C.c_double)(), C.POINTER(C.c_double)())
+        self._check(self.lib.hofv_boundary_faces(self.h, C.byref(n), C.byref(nq), C.byref(cen), C.byref(nor),
+                                                 C.byref(qp)))
+        D, nb, q = self.dim, n.value, nq.value
+        as_np = lambda p, shape: np.ctypeslib.as_array(p, shape=shape).copy() if nb else np.zeros(shape)
+        return as_np(cen, (nb, D)), as_np(nor, (nb, D)), as_np(qp, (nb, q, D))
+
+    def volume_qpoints(self):
+        nqv = C.c_int32()
+        pts = C.POINTER(C.c_double)()
+        self._check(self.lib.hofv_volume_qpoints(self.h, C.byref(nqv), C.byref(pts)))
+        return np.ctypeslib.as_array(pts, shape=(self.n_cells, nqv.value, self.dim)).copy()
+
+    def set_bc(self, types, u_b_q, u_b_centre, traction_q):
+        types = np.ascontiguousarray(types, np.int32)
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (u_b_q, u_b_centre, traction_q)]
+        self._check(self.lib.hofv_set_bc(self.h, types.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         *[_dptr(a) for a in arrs]))
+
+    def set_body_force(self, values):
+        v = None if values is None else np.ascontiguousarray(values, np.float64)
+        self._check(self.lib.hofv_set_body_force(self.h, _dptr(v)))
+
+    def setup(self):
+        rep = L.SetupReport()
+        self._check(self.lib.hofv_setup(self.h, C.byref(rep)))
+        self.report = {k: getattr(rep, k) for k, _ in L.SetupReport._fields_}
+        return self.report
+
+    def set_load_scale(self, s):
+        self._check(self.lib.hofv_set_load_scale(self.h, float(s)))
+
+    # ------------------------------------------------------------------- hot
+    def residual(self, u, R, stream=None):
+        self._check(self.lib.hofv_residual(self.h, _ptr(u), _ptr(R), _stream(stream)))
+
+    def jvp(self, u, Ru, v, Jv, eps=0.0, stream=None):
+        self._check(self.lib.hofv_jvp(self.h, _ptr(u), _ptr(Ru), _ptr(v), _ptr(Jv), float(eps), _stream(stream)))
+
+    def precond_apply(self, r, z, n_sweeps=2, learned=False, stream=None):
+        self._check(self.lib.hofv_precond_apply(self.h, _ptr(r), _ptr(z), int(n_sweeps), int(bool(learned)),
+                                                _stream(stream)))
+
+    def fgmres_solve(self, u, Ru, rhs, x, restart=30, max_iters=1000, rtol=1e-6, n_sweeps=2, learned=False,
+                     stream=None, check=True):
+        o = L.KrylovOpts(restart, max_iters, rtol, n_sweeps, int(bool(learned)))
+        s = L.KrylovStats()
+        st = self.lib.hofv_fgmres_solve(self.h, _ptr(u), _ptr(Ru), _ptr(rhs), _ptr(x), C.byref(o), C.byref(s),
+                                        _stream(stream))
+        if check or st not in (L.HOFV_OK, -5):
+            self._check(st)
+        return {k: getattr(s, k) for k, _ in L.KrylovStats._fields_}
+
+    def newton_solve(self, u, tol=1e-8, eta=1e-4, max_newton=50, n_increments=1, max_line_search=10,
+                     restart=30, max_krylov=2000, n_sweeps=2, learned=False, stream=None, check=True):
+        o = L.NewtonOpts(tol, eta, max_newton, n_increments, max_line_search,
+                         L.KrylovOpts(restart, max_krylov, eta, n_sweeps, int(bool(learned))))
+        s = L.NewtonStats()
+        st = self.lib.hofv_newton_solve(self.h, _ptr(u), C.byref(o), C.byref(s), _stream(stream))
+        if check or st not in (L.HOFV_OK, -5):
+            self._check(st)
+        return {k: getattr(s, k) for k, _ in L.NewtonStats._fields_}
+
+    def host_table(self, name):
+        """Copy of a setup table of a host_only context (numpy, flat)."""
+        n = C.c_int64()
+        eb = C.c_int32()
+        data = C.c_void_p()
+        self._check(self.lib.hofv_host_table(self.h, name.encode(), C.byref(n), C.byref(eb), C.byref(data)))
+        dtype = {("face_coef", 8): np.float64}.get((name, eb.value))
+        if dtype is None:
+            dtype = {4: np.int32, 8: np.float64}[eb.value]
+            if name in ("pc_dinv", "pc_a"):
+                dtype = np.float32
+        buf = (C.c_char * (n.value * eb.value)).from_address(data.value) if n.value else b""
+        return np.frombuffer(bytes(buf), dtype=dtype).copy()
+
+    # -------------------------------------------------------------- timing
+    def set_timing(self, enable):
+        self._check(self.lib.hofv_set_timing(self.h, int(bool(enable))))
+
+    def kernel_time(self, name):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self.lib.hofv_kernel_time(self.h, name.encode(), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def kernel_bytes(self, name):
+        b = C.c_double()
+        self._check(self.lib.hofv_kernel_bytes(self.h, name.encode(), C.byref(b)))
+        return b.value
+
+
+def context_for(problem, fold_quadrature=True, host_only=False):
+    """Create and set up a Context for a problem description (mesh, orders,
+    material, loads as point functions), evaluating the loads at the library's
+    boundary and volume quadrature points."""
+    ctx = Context(problem.mesh.dim, problem.p, problem.n_plus, problem.n_gauss, problem.material, problem.mu,
+                  problem.lam, problem.alpha, problem.k_weight, problem.ghost_weight, problem.stencil_quantum,
+                  fold_quadrature, host_only)
+    ctx.set_mesh(problem.mesh.verts, problem.mesh.cells)
+    cen, nor, qp = ctx.boundary_faces()
+    D = problem.mesh.dim
+    loads = problem.loads
+    nb, nq = qp.shape[0], qp.shape[1]
+    types = loads.bc_type(cen, nor) if nb else np.zeros(0, np.int32)
+    ubq = loads.u_b(qp.reshape(-1, D)).reshape(nb, nq, D) if nb else None
+    ubc = loads.u_b(cen) if nb else None
+    tq = loads.traction(qp.reshape(-1, D), np.repeat(nor, nq, axis=0)).reshape(nb, nq, D) if nb else None
+    ctx.set_bc(types, ubq, ubc, tq)
+    vq = ctx.volume_qpoints()
+    ctx.set_body_force(loads.body(vq.reshape(-1, D)).reshape(vq.shape))
+    ctx.setup()
+    return ctx

@@ -1,0 +1,303 @@
+// C ABI entry points of libhofv (declared in include/hofv.h).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace hofv {
+
+static std::string g_create_error;
+
+hofv_status fail(hofv_ctx* c, hofv_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return s;
+}
+
+hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const double* rhs, double* x,
+                        const hofv_krylov_opts* o, hofv_krylov_stats* stats, hipStream_t st);
+hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_newton_stats* stats,
+                        hipStream_t st);
+
+hofv_status jvp_impl(hofv_ctx* c, const double* u, const double* Ru, const double* v, double* Jv, double eps,
+                     hipStream_t st) {
+  hofv_status s;
+  if ((s = launch_eps(c, u, v, eps, st))) return s;
+  if ((s = launch_axpy_w(c, u, v, st))) return s;
+  return launch_residual(c, c->dev.w, Jv, Ru, c->dev.eps, st);
+}
+
+hofv_status precond_dispatch(hofv_ctx* c, const double* r, double* z, int sweeps, int learned, hipStream_t st) {
+  (void)learned;
+  return launch_precond(c, r, z, sweeps, st);
+}
+
+static hofv_status need(hofv_ctx* c, int state, const char* what) {
+  if (!c) return fail(nullptr, HOFV_EINVAL, "null context");
+  if (c->state == 5 && state == 4) return fail(c, HOFV_ESTATE, std::string(what) + " on a host_only context");
+  if (c->state < state) return fail(c, HOFV_ESTATE, std::string(what) + " called out of order");
+  return HOFV_OK;
+}
+
+static hofv_status set_device(hofv_ctx* c) {
+  HOFV_HIP(c, hipSetDevice(c->device));
+  return HOFV_OK;
+}
+
+}  // namespace hofv
+
+using namespace hofv;
+
+extern "C" {
+
+hofv_status hofv_create(const hofv_params* prm, hofv_ctx** out) {
+  if (!out) return fail(nullptr, HOFV_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!prm) return fail(nullptr, HOFV_EINVAL, "params is NULL");
+  if (prm->dim != 2 && prm->dim != 3) return fail(nullptr, HOFV_EINVAL, "dim must be 2 or 3");
+  if (prm->order_p < 1 || prm->order_p > 3) return fail(nullptr, HOFV_EINVAL, "order_p must be 1, 2 or 3");
+  if (prm->n_plus < 0) return fail(nullptr, HOFV_EINVAL, "n_plus must be >= 0");
+  if (prm->n_gauss < 1 || prm->n_gauss > 3) return fail(nullptr, HOFV_EINVAL, "n_gauss must be 1..3");
+  if (prm->material != HOFV_LINEAR_ELASTIC && prm->material != HOFV_NEO_HOOKEAN)
+    return fail(nullptr, HOFV_EINVAL, "unknown material");
+  if (prm->material == HOFV_NEO_HOOKEAN && prm->dim != 3)
+    return fail(nullptr, HOFV_EINVAL, "the neo-Hookean law needs dim = 3");
+  if (!(prm->stencil_quantum > 0)) return fail(nullptr, HOFV_EINVAL, "stencil_quantum must be > 0");
+  if (!(prm->mu > 0) || !(prm->k_weight > 0) || prm->alpha < 0 || prm->ghost_weight <= 0)
+    return fail(nullptr, HOFV_EINVAL, "mu, k_weight, ghost_weight must be > 0 and alpha >= 0");
+  hofv_ctx* c = new (std::nothrow) hofv_ctx();
+  if (!c) return fail(nullptr, HOFV_ENOMEM, "out of host memory");
+  c->prm = *prm;
+  c->D = prm->dim;
+  int dev = -1;
+  if (!prm->host_only && hipGetDevice(&dev) != hipSuccess) {
+    delete c;
+    return fail(nullptr, HOFV_EHIP, "no HIP device");
+  }
+  c->device = dev;
+  *out = c;
+  return HOFV_OK;
+}
+
+hofv_status hofv_destroy(hofv_ctx* c) {
+  if (!c) return HOFV_OK;
+  if (c->device >= 0) {
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+  }
+  for (void* p : c->allocations) hipFree(p);
+  for (auto& t : c->timers) {
+    hipEventDestroy(t.start);
+    hipEventDestroy(t.stop);
+  }
+  delete c;
+  return HOFV_OK;
+}
+
+const char* hofv_last_error(const hofv_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+hofv_status hofv_set_mesh(hofv_ctx* c, int64_t n_verts, const double* verts, int64_t n_cells,
+                          const int64_t* cell_verts) {
+  if (!c) return fail(nullptr, HOFV_EINVAL, "null context");
+  if (c->state != 0) return fail(c, HOFV_ESTATE, "set_mesh may be called once");
+  if (n_verts <= 0 || n_cells <= 0 || !verts || !cell_verts) return fail(c, HOFV_EINVAL, "empty mesh");
+  if (n_cells >= INT32_MAX / 8) return fail(c, HOFV_EINVAL, "too many cells for 32-bit indices");
+  const int D = c->D, ncv = D == 2 ? 4 : 8;
+  c->nv = n_verts;
+  c->nc = n_cells;
+  c->verts.assign(verts, verts + n_verts * D);
+  c->cells.assign(cell_verts, cell_verts + n_cells * ncv);
+  for (int64_t v : c->cells)
+    if (v < 0 || v >= n_verts) return fail(c, HOFV_EINVAL, "cell vertex index out of range");
+  hofv_status s;
+  if ((s = build_topology(c))) return s;
+  if ((s = build_geometry(c))) return s;
+  c->state = 1;
+  return HOFV_OK;
+}
+
+hofv_status hofv_boundary_faces(hofv_ctx* c, int64_t* n_bfaces, int32_t* n_q, const double** centres,
+                                const double** normals, const double** qpoints) {
+  hofv_status s = need(c, 1, "boundary_faces");
+  if (s) return s;
+  if (n_bfaces) *n_bfaces = (int64_t)c->bface.size();
+  if (n_q) *n_q = c->nq;
+  if (centres) *centres = c->b_centre.data();
+  if (normals) *normals = c->b_normal.data();
+  if (qpoints) *qpoints = c->b_qp.data();
+  return HOFV_OK;
+}
+
+hofv_status hofv_volume_qpoints(hofv_ctx* c, int32_t* n_qv, const double** points) {
+  hofv_status s = need(c, 1, "volume_qpoints");
+  if (s) return s;
+  if (n_qv) *n_qv = c->nqv;
+  if (points) *points = c->vq_pts.data();
+  return HOFV_OK;
+}
+
+hofv_status hofv_set_bc(hofv_ctx* c, const int32_t* type, const double* u_b_q, const double* u_b_centre,
+                        const double* traction_q) {
+  hofv_status s = need(c, 1, "set_bc");
+  if (s) return s;
+  if (c->state >= 4) return fail(c, HOFV_ESTATE, "set_bc after setup");
+  const size_t nb = c->bface.size();
+  const int D = c->D, nq = c->nq;
+  c->btype.assign(nb, HOFV_BC_DISPLACEMENT);
+  if (type) {
+    for (size_t b = 0; b < nb; ++b) {
+      if (type[b] != HOFV_BC_DISPLACEMENT && type[b] != HOFV_BC_TRACTION)
+        return fail(c, HOFV_EINVAL, "unknown boundary condition type");
+      c->btype[b] = type[b];
+    }
+  }
+  c->ubq.assign(nb * nq * D, 0.0);
+  c->ubc.assign(nb * D, 0.0);
+  c->tq.assign(nb * nq * D, 0.0);
+  if (u_b_q) std::memcpy(c->ubq.data(), u_b_q, c->ubq.size() * sizeof(double));
+  if (u_b_centre) std::memcpy(c->ubc.data(), u_b_centre, c->ubc.size() * sizeof(double));
+  if (traction_q) std::memcpy(c->tq.data(), traction_q, c->tq.size() * sizeof(double));
+  c->state = std::max(c->state, 2);
+  return HOFV_OK;
+}
+
+hofv_status hofv_set_body_force(hofv_ctx* c, const double* values) {
+  hofv_status s = need(c, 1, "set_body_force");
+  if (s) return s;
+  if (c->state >= 4) return fail(c, HOFV_ESTATE, "set_body_force after setup");
+  if (values) c->fb.assign(values, values + (size_t)c->nc * c->nqv * c->D);
+  else c->fb.clear();
+  c->state = std::max(c->state, 3);
+  return HOFV_OK;
+}
+
+hofv_status hofv_setup(hofv_ctx* c, hofv_setup_report* rep) {
+  hofv_status s = need(c, 1, "setup");
+  if (s) return s;
+  if (c->state >= 4) return fail(c, HOFV_ESTATE, "setup may be called once");
+  if (c->btype.empty() && !c->bface.empty()) {
+    if ((s = hofv_set_bc(c, nullptr, nullptr, nullptr, nullptr))) return s;
+  }
+  if (!c->prm.host_only && (s = set_device(c))) return s;
+  if ((s = build_tables(c))) return s;
+  c->state = c->prm.host_only ? 5 : 4;
+  if (rep) *rep = c->report;
+  return HOFV_OK;
+}
+
+hofv_status hofv_set_load_scale(hofv_ctx* c, double sc) {
+  hofv_status s = need(c, 1, "set_load_scale");
+  if (s) return s;
+  if (!std::isfinite(sc)) return fail(c, HOFV_EINVAL, "load scale must be finite");
+  c->load = sc;
+  return HOFV_OK;
+}
+
+hofv_status hofv_residual(hofv_ctx* c, const double* d_u, double* d_R, void* stream) {
+  hofv_status s = need(c, 4, "residual");
+  if (s) return s;
+  if (!d_u || !d_R || (const void*)d_u == (void*)d_R) return fail(c, HOFV_EINVAL, "bad u/R pointers");
+  if ((s = set_device(c))) return s;
+  return launch_residual(c, d_u, d_R, nullptr, nullptr, (hipStream_t)stream);
+}
+
+hofv_status hofv_jvp(hofv_ctx* c, const double* d_u, const double* d_Ru, const double* d_v, double* d_Jv,
+                     double eps, void* stream) {
+  hofv_status s = need(c, 4, "jvp");
+  if (s) return s;
+  if (!d_u || !d_Ru || !d_v || !d_Jv) return fail(c, HOFV_EINVAL, "null pointer");
+  if ((const void*)d_Jv == (const void*)d_u || (const void*)d_Jv == (const void*)d_Ru ||
+      (const void*)d_Jv == (const void*)d_v)
+    return fail(c, HOFV_EINVAL, "Jv must not alias the inputs");
+  if (!std::isfinite(eps)) return fail(c, HOFV_EINVAL, "eps must be finite");
+  if ((s = set_device(c))) return s;
+  return jvp_impl(c, d_u, d_Ru, d_v, d_Jv, eps, (hipStream_t)stream);
+}
+
+hofv_status hofv_precond_apply(hofv_ctx* c, const double* d_r, double* d_z, int32_t n_sweeps, int32_t learned,
+                               void* stream) {
+  hofv_status s = need(c, 4, "precond_apply");
+  if (s) return s;
+  if (!d_r || !d_z || (const void*)d_r == (void*)d_z) return fail(c, HOFV_EINVAL, "bad r/z pointers");
+  if (n_sweeps < 1) return fail(c, HOFV_EINVAL, "n_sweeps must be >= 1");
+  if ((s = set_device(c))) return s;
+  return precond_dispatch(c, d_r, d_z, n_sweeps, learned, (hipStream_t)stream);
+}
+
+hofv_status hofv_fgmres_solve(hofv_ctx* c, const double* d_u, const double* d_Ru, const double* d_rhs,
+                              double* d_x, const hofv_krylov_opts* opts, hofv_krylov_stats* stats, void* stream) {
+  hofv_status s = need(c, 4, "fgmres_solve");
+  if (s) return s;
+  if (!d_u || !d_Ru || !d_rhs || !d_x || !opts) return fail(c, HOFV_EINVAL, "null pointer");
+  if ((s = set_device(c))) return s;
+  hofv_krylov_stats tmp{};
+  s = fgmres_impl(c, d_u, d_Ru, d_rhs, d_x, opts, stats ? stats : &tmp, (hipStream_t)stream);
+  if (s == HOFV_OK && !(stats ? stats : &tmp)->converged)
+    return fail(c, HOFV_ENOCONV, "FGMRES did not reach the tolerance");
+  return s;
+}
+
+hofv_status hofv_newton_solve(hofv_ctx* c, double* d_u, const hofv_newton_opts* opts, hofv_newton_stats* stats,
+                              void* stream) {
+  hofv_status s = need(c, 4, "newton_solve");
+  if (s) return s;
+  if (!d_u || !opts) return fail(c, HOFV_EINVAL, "null pointer");
+  if ((s = set_device(c))) return s;
+  hofv_newton_stats tmp{};
+  return newton_impl(c, d_u, opts, stats ? stats : &tmp, (hipStream_t)stream);
+}
+
+hofv_status hofv_host_table(hofv_ctx* c, const char* name, int64_t* count, int32_t* elem_bytes,
+                            const void** data) {
+  if (!c || !name) return fail(c, HOFV_EINVAL, "null argument");
+  if (c->state != 5) return fail(c, HOFV_ESTATE, "host tables exist after setup of a host_only context");
+  auto it = c->host_tables.find(name);
+  if (it == c->host_tables.end()) return fail(c, HOFV_EINVAL, std::string("unknown table ") + name);
+  if (count) *count = it->second.elem ? (int64_t)(it->second.bytes.size() / it->second.elem) : 0;
+  if (elem_bytes) *elem_bytes = it->second.elem;
+  if (data) *data = it->second.bytes.data();
+  return HOFV_OK;
+}
+
+hofv_status hofv_set_timing(hofv_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, HOFV_EINVAL, "null context");
+  if (c->device >= 0) hipDeviceSynchronize();
+  for (auto& t : c->timers) {
+    hipEventDestroy(t.start);
+    hipEventDestroy(t.stop);
+  }
+  c->timers.clear();
+  c->timing = enable != 0;
+  return HOFV_OK;
+}
+
+hofv_status hofv_kernel_time(hofv_ctx* c, const char* name, double* total_ms, int64_t* count) {
+  if (!c || !name) return fail(c, HOFV_EINVAL, "null argument");
+  double tot = 0;
+  int64_t n = 0;
+  for (auto& t : c->timers) {
+    if (t.name != name) continue;
+    HOFV_HIP(c, hipEventSynchronize(t.stop));
+    float ms = 0;
+    HOFV_HIP(c, hipEventElapsedTime(&ms, t.start, t.stop));
+    tot += ms;
+    ++n;
+  }
+  if (total_ms) *total_ms = tot;
+  if (count) *count = n;
+  return HOFV_OK;
+}
+
+hofv_status hofv_kernel_bytes(hofv_ctx* c, const char* name, double* bytes) {
+  if (!c || !name || !bytes) return fail(c, HOFV_EINVAL, "null argument");
+  auto it = c->kernel_bytes.find(name);
+  if (it == c->kernel_bytes.end()) return fail(c, HOFV_EINVAL, std::string("no byte model for ") + name);
+  *bytes = it->second;
+  return HOFV_OK;
+}
+
+}  // extern "C"

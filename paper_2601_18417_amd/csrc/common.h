@@ -1,0 +1,196 @@
+// Internal declarations shared by the host setup and the HIP kernels of libhofv.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "hofv.h"
+
+namespace hofv {
+
+// cell-face slot code for the face -> cell sum: f >= 0 owner side, ~f (< 0)
+// neighbour side, kNoFace for traction/unused slots
+constexpr int32_t kNoFace = INT32_MIN;
+
+struct TimerRec {
+  std::string name;
+  hipEvent_t start, stop;
+};
+
+// Device-resident tables built by hofv_setup.  Layouts are "k-major, item
+// minor": entry (k, item) of a per-face table lives at k * n_items + item so a
+// wavefront that owns 64 consecutive items reads 64 consecutive words.
+struct DeviceTables {
+  int32_t S = 0;         // stencil size
+  int32_t nq = 0;        // quadrature points per face
+  int64_t nf = 0;        // internal + displacement faces handled by the face kernel
+  int64_t nfi = 0;       // internal faces (first nfi entries)
+  // faces
+  int32_t* f_stencil = nullptr;  // [S][nf]
+  double* f_coef = nullptr;      // folded: [S][D][nf]; per-point: [S][nq][D][nf]
+  int32_t* f_own = nullptr;      // [nf]
+  int32_t* f_nei = nullptr;      // [nf] (-1 on displacement faces)
+  int32_t* f_slots = nullptr;    // [nf] owner slot | neighbour slot << 8
+  double* f_area_vec = nullptr;  // folded: [D][nf] = Gamma n; per-point: [nq][D][nf] = alpha_q Gamma n
+  double* f_stab = nullptr;      // [nf] alpha Kbar Gamma / |d . n|
+  double* f_ghost = nullptr;     // per-point NH: [nq][D][D][nfd] ghost gradient at load 1
+  // cells
+  int32_t* c_stencil = nullptr;  // [S][nc]
+  double* c_extrap = nullptr;    // [S][2D][nc] extrapolation rows (u* - u_P)
+  int32_t* c_faces = nullptr;    // [2D][nc] slot codes
+  double* c_src = nullptr;       // [D][nc] constant sources at load 1
+  // transient
+  double* ustar = nullptr;       // [2D][D][nc]
+  double* flux = nullptr;        // [D][nf]
+  double* w = nullptr;           // [D][nc] u + eps v
+  double* scratch = nullptr;     // reduction partials
+  double* eps = nullptr;         // device scalar(s)
+  int32_t* flag = nullptr;       // device error flags (NH inverted element)
+  // preconditioner (colour-major numbering)
+  int32_t n_colours = 0;
+  std::vector<int64_t> colour_start;  // n_colours + 1
+  int32_t* p_perm = nullptr;     // [nc] position -> cell
+  int32_t* p_nbr = nullptr;      // [2D][nc] neighbour positions (self where none)
+  float* p_a = nullptr;          // [2D][nc] off-diagonal A_PN
+  float* p_dinv = nullptr;       // [nc] 1 / A_PP
+  float* p_r = nullptr;          // [D][nc]
+  float* p_z = nullptr;          // [D][nc]
+};
+
+struct Krylov {
+  int m = 0;
+  double* V = nullptr;   // [(m+1)][n]
+  double* Z = nullptr;   // [m][n]
+  double* h = nullptr;   // device Hessenberg column scratch [2 (m+2)]
+  double* tmp = nullptr; // [n]
+  double* tmp2 = nullptr;
+  double* hbuf = nullptr;  // pinned host copy
+};
+
+}  // namespace hofv
+
+struct hofv_ctx {
+  hofv_params prm{};
+  int device = 0;
+  int state = 0;  // 0 created, 1 mesh, 2 bc set, 3 body set, 4 ready
+  std::string err;
+  double load = 1.0;
+
+  // mesh (host)
+  int D = 0;
+  int64_t nv = 0, nc = 0;
+  std::vector<double> verts;
+  std::vector<int64_t> cells;
+  std::vector<double> cen, vol;  // [nc][D], [nc]
+
+  // all faces: owner/neighbour/slots and ordered vertex ids
+  struct Face {
+    int64_t own, nei;
+    int32_t sown, snei;
+    int64_t v[4];
+  };
+  std::vector<Face> faces;           // internal faces first, then boundary faces
+  int64_t n_internal = 0;
+  std::vector<int64_t> bface;        // indices into faces of boundary faces (caller order)
+  int32_t nq = 0, nqv = 0;
+  // geometry of every face: centre, unit normal, area, q-points, weights
+  std::vector<double> f_centre, f_normal, f_area, f_qp, f_qw;
+  // boundary views handed to the caller
+  std::vector<double> b_centre, b_normal, b_qp;
+  std::vector<double> vq_pts, vq_w;  // [nc][nqv][D], [nc][nqv]
+
+  // boundary data from the caller
+  std::vector<int32_t> btype;
+  std::vector<double> ubq, ubc, tq, fb;
+
+  hofv_setup_report report{};
+  hofv::DeviceTables dev;
+  hofv::Krylov kry;
+  std::vector<void*> allocations;
+  size_t device_bytes = 0;
+
+  // host copies of the setup tables (host_only contexts)
+  struct HostTable {
+    std::vector<char> bytes;
+    int32_t elem = 0;
+  };
+  std::map<std::string, HostTable> host_tables;
+
+  // timing
+  bool timing = false;
+  std::vector<hofv::TimerRec> timers;
+  std::map<std::string, double> kernel_bytes;
+};
+
+namespace hofv {
+
+// error helpers
+hofv_status fail(hofv_ctx* c, hofv_status s, const std::string& msg);
+#define HOFV_HIP(ctx, call)                                                               \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return ::hofv::fail(ctx, HOFV_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+hofv_status dev_alloc(hofv_ctx* c, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return fail(c, HOFV_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->allocations.push_back(q);
+  c->device_bytes += count * sizeof(T);
+  *p = static_cast<T*>(q);
+  return HOFV_OK;
+}
+
+template <class T>
+hofv_status upload(hofv_ctx* c, T** p, const std::vector<T>& host) {
+  hofv_status s = dev_alloc(c, p, host.size());
+  if (s) return s;
+  if (!host.empty()) HOFV_HIP(c, hipMemcpy(*p, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+  return HOFV_OK;
+}
+
+// host setup stages (setup_*.cpp)
+hofv_status build_topology(hofv_ctx* c);
+hofv_status build_geometry(hofv_ctx* c);
+hofv_status build_tables(hofv_ctx* c);
+
+// stencils: cells nearest to each point, ties by (rint(d2/quantum), id)
+void nearest_cells(const std::vector<double>& cen, int D, int64_t nc, const double* pts,
+                   int64_t npts, int S, double quantum, int32_t* out);
+
+// Least-squares fit at xt over the stencil X[S][D] (plus a co-located ghost
+// node when ghost_w > 0).  For each target writes the stencil coefficients
+// out[r][0..m), m = S (+1 ghost), of one linear functional of the fit:
+//  kind kTargetGradient: targets[r] is an axis i, functional = d u / d x_i;
+//  kind kTargetExtrap:   targets[r*D..] is a vector d, functional =
+//                        u~(x + d) - u~(x) of the fitted Taylor polynomial.
+// Returns false when rank deficient (min|R_ii| <= 1e-14 max|R_ii|).
+enum { kTargetGradient = 0, kTargetExtrap = 1 };
+bool ls_functionals(int D, int p, double kshape, const double* xt, const double* X, int S,
+                    double ghost_w, int kind, int n_targets, const double* targets, double* out,
+                    double* cond, double* h_out);
+int n_basis(int D, int p);
+void basis_exponents(int D, int p, int (*e)[3]);
+
+// kernel launchers (kernels.hip)
+hofv_status launch_residual(hofv_ctx* c, const double* u, double* R, const double* Ru,
+                            const double* eps_dev, hipStream_t st);
+hofv_status launch_eps(hofv_ctx* c, const double* u, const double* v, double eps_host,
+                       hipStream_t st);
+hofv_status launch_axpy_w(hofv_ctx* c, const double* u, const double* v, hipStream_t st);
+hofv_status launch_precond(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st);
+
+// timing helpers
+void timer_begin(hofv_ctx* c, const char* name, hipStream_t st, hipEvent_t* ev);
+void timer_end(hofv_ctx* c, const char* name, hipStream_t st, hipEvent_t ev);
+
+}  // namespace hofv

@@ -1,0 +1,512 @@
+// HIP kernels of the residual R(u), the finite-difference J.v and the FP32
+// preconditioner sweeps for gfx950 (wave64).
+//
+// Residual = k_extrap (cells) -> k_face_* (faces) -> k_cell_sum (cells):
+//   k_extrap   u*_{f,P} - u_P = sum_k E[k][slot][P] u(S_P[k]) for every face slot
+//              of P (eq. alphaJump, pre-contracted at setup);
+//   k_face_le  linear elasticity with quadrature-summed gradient coefficients:
+//              G = sum_k c[k] (x) u(S_f[k]), F = Gamma n . sigma(G)
+//              + alpha Kbar Gamma / |d.n| (u*_N - u*_P)     (eqs. faceQuadGrad, alpha);
+//   k_face_q   per-quadrature-point gradients, linear elastic or neo-Hookean
+//              (first Piola stress P = sigma cof(F), traction P n_o);
+//   k_cell_sum R_P = sum of +-F over the cell's faces + load * src_P, or, for
+//              J.v, (that - R(u)_P) / eps.
+// One thread owns one face or one cell; per-item tables are stored
+// k-major/item-minor so the 64 lanes of a wavefront read 64 consecutive words
+// of each coefficient stream, and only the stencil gathers of u are scattered
+// (they hit L2: u is 8 D bytes per cell).
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+
+#include "common.h"
+
+namespace hofv {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned blocks_for(int64_t n, int per = kBlock) { return (unsigned)((n + per - 1) / per); }
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_extrap(int64_t nc, int S, const int32_t* __restrict__ st,
+                                                    const double* __restrict__ E, const double* __restrict__ u,
+                                                    double* __restrict__ ustar) {
+  constexpr int NS = 2 * D;
+  const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (P >= nc) return;
+  double acc[NS][D];
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[s][c] = 0.0;
+#pragma unroll 2
+  for (int k = 0; k < S; ++k) {
+    const int32_t n = __builtin_nontemporal_load(&st[(int64_t)k * nc + P]);
+    double un[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) un[c] = u[(int64_t)c * nc + n];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double e = __builtin_nontemporal_load(&E[((int64_t)k * NS + s) * nc + P]);
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[s][c] += e * un[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double uP = u[(int64_t)c * nc + P];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) ustar[((int64_t)s * D + c) * nc + P] = uP + acc[s][c];
+  }
+}
+
+// stabilisation part alpha Kbar Gamma/|d.n| (u*_N - u*_P); on displacement
+// faces only -u*_P (the u_b part is a constant source)
+template <int D>
+__device__ inline void add_stab(int64_t f, int64_t nfi, int64_t nc, const int32_t* own, const int32_t* nei,
+                                const int32_t* slots, const double* stab, const double* ustar, double* t) {
+  const int32_t P = own[f];
+  const int32_t sl = slots[f];
+  const double a = stab[f];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double jump = -ustar[((int64_t)(sl & 0xff) * D + j) * nc + P];
+    if (f < nfi) jump += ustar[((int64_t)(sl >> 8) * D + j) * nc + nei[f]];
+    t[j] += a * jump;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_face_le(int64_t nf, int64_t nfi, int64_t nc, int S,
+                                                     const int32_t* __restrict__ st, const double* __restrict__ C,
+                                                     const int32_t* __restrict__ own, const int32_t* __restrict__ nei,
+                                                     const int32_t* __restrict__ slots,
+                                                     const double* __restrict__ Sv, const double* __restrict__ stab,
+                                                     double mu, double lam, const double* __restrict__ u,
+                                                     const double* __restrict__ ustar, double* __restrict__ F) {
+  const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (f >= nf) return;
+  double G[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) G[i][j] = 0.0;
+#pragma unroll 2
+  for (int k = 0; k < S; ++k) {
+    const int32_t n = __builtin_nontemporal_load(&st[(int64_t)k * nf + f]);
+    double un[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) un[j] = u[(int64_t)j * nc + n];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double c = __builtin_nontemporal_load(&C[((int64_t)k * D + i) * nf + f]);
+#pragma unroll
+      for (int j = 0; j < D; ++j) G[i][j] += c * un[j];
+    }
+  }
+  double tr = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) tr += G[i][i];
+  double sv[D], t[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) sv[i] = Sv[(int64_t)i * nf + f];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) s += sv[i] * (mu * (G[i][j] + G[j][i]) + (i == j ? lam * tr : 0.0));
+    t[j] = s;
+  }
+  add_stab<D>(f, nfi, nc, own, nei, slots, stab, ustar, t);
+#pragma unroll
+  for (int j = 0; j < D; ++j) F[(int64_t)j * nf + f] = t[j];
+}
+
+// per-quadrature-point face kernel; MAT 0 linear elastic, 1 neo-Hookean (D = 3)
+template <int D, int NQ, int MAT>
+__global__ __launch_bounds__(kBlock) void k_face_q(int64_t nf, int64_t nfi, int64_t nc, int S,
+                                                    const int32_t* __restrict__ st, const double* __restrict__ C,
+                                                    const int32_t* __restrict__ own, const int32_t* __restrict__ nei,
+                                                    const int32_t* __restrict__ slots,
+                                                    const double* __restrict__ Sv, const double* __restrict__ stab,
+                                                    const double* __restrict__ ghost, double load, double mu,
+                                                    double lam, const double* __restrict__ u,
+                                                    const double* __restrict__ ustar, double* __restrict__ F,
+                                                    int32_t* __restrict__ flag) {
+  const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (f >= nf) return;
+  double G[NQ][D][D];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) G[q][i][j] = 0.0;
+  for (int k = 0; k < S; ++k) {
+    const int32_t n = __builtin_nontemporal_load(&st[(int64_t)k * nf + f]);
+    double un[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) un[j] = u[(int64_t)j * nc + n];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const double c = __builtin_nontemporal_load(&C[(((int64_t)k * NQ + q) * D + i) * nf + f]);
+#pragma unroll
+        for (int j = 0; j < D; ++j) G[q][i][j] += c * un[j];
+      }
+  }
+  if (MAT == 1 && f >= nfi) {
+    const int64_t nfd = nf - nfi, fd = f - nfi;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) G[q][i][j] += load * ghost[(((int64_t)q * D + i) * D + j) * nfd + fd];
+  }
+  double t[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) t[j] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double sv[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) sv[i] = Sv[((int64_t)q * D + i) * nf + f];
+    if (MAT == 0) {
+      double tr = 0.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) tr += G[q][i][i];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) s += sv[i] * (mu * (G[q][i][j] + G[q][j][i]) + (i == j ? lam * tr : 0.0));
+        t[j] += s;
+      }
+    } else {
+      // F = I + G^T, J = det F, bbar = J^{-2/3} F F^T,
+      // sigma = mu/J dev(bbar) + kappa/2 (J^2 - 1)/J I, P = J sigma F^{-T} = sigma cof(F)
+      double Fm[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Fm[a][b] = (a == b ? 1.0 : 0.0) + G[q][b][a];
+      double cof[3][3];
+      cof[0][0] = Fm[1][1] * Fm[2][2] - Fm[1][2] * Fm[2][1];
+      cof[0][1] = Fm[1][2] * Fm[2][0] - Fm[1][0] * Fm[2][2];
+      cof[0][2] = Fm[1][0] * Fm[2][1] - Fm[1][1] * Fm[2][0];
+      cof[1][0] = Fm[2][1] * Fm[0][2] - Fm[2][2] * Fm[0][1];
+      cof[1][1] = Fm[2][2] * Fm[0][0] - Fm[2][0] * Fm[0][2];
+      cof[1][2] = Fm[2][0] * Fm[0][1] - Fm[2][1] * Fm[0][0];
+      cof[2][0] = Fm[0][1] * Fm[1][2] - Fm[0][2] * Fm[1][1];
+      cof[2][1] = Fm[0][2] * Fm[1][0] - Fm[0][0] * Fm[1][2];
+      cof[2][2] = Fm[0][0] * Fm[1][1] - Fm[0][1] * Fm[1][0];
+      double J = Fm[0][0] * cof[0][0] + Fm[0][1] * cof[0][1] + Fm[0][2] * cof[0][2];
+      if (!(J > 0.0)) {
+        flag[0] = 1;
+        J = 1.0;
+      }
+      const double kappa = lam + 2.0 * mu / 3.0;
+      const double cb = cbrt(J);
+      const double jm23 = 1.0 / (cb * cb);
+      double b[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b[a][c] = jm23 * (Fm[a][0] * Fm[c][0] + Fm[a][1] * Fm[c][1] + Fm[a][2] * Fm[c][2]);
+      const double trb = (b[0][0] + b[1][1] + b[2][2]) / 3.0;
+      const double invJ = 1.0 / J;
+      const double pr = 0.5 * kappa * (J * J - 1.0) * invJ;
+      double sig[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sig[a][c] = mu * invJ * (b[a][c] - (a == c ? trb : 0.0)) + (a == c ? pr : 0.0);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const double Pji = sig[j][0] * cof[0][i] + sig[j][1] * cof[1][i] + sig[j][2] * cof[2][i];
+          s += sv[i] * Pji;
+        }
+        t[j] += s;
+      }
+    }
+  }
+  add_stab<D>(f, nfi, nc, own, nei, slots, stab, ustar, t);
+#pragma unroll
+  for (int j = 0; j < D; ++j) F[(int64_t)j * nf + f] = t[j];
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, const int32_t* __restrict__ cf,
+                                                      const double* __restrict__ F, const double* __restrict__ src,
+                                                      double load, const double* __restrict__ Ru,
+                                                      const double* __restrict__ eps, double* __restrict__ R) {
+  constexpr int NS = 2 * D;
+  const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (P >= nc) return;
+  int32_t code[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) code[s] = cf[(int64_t)s * nc + P];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    double acc = load * src[(int64_t)c * nc + P];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int32_t k = code[s];
+      if (k == kNoFace) continue;
+      if (k >= 0) acc += F[(int64_t)c * nf + k];
+      else acc -= F[(int64_t)c * nf + ~k];
+    }
+    if (Ru) {
+      const double e = eps[0];
+      acc = e > 0.0 ? (acc - Ru[(int64_t)c * nc + P]) / e : 0.0;
+    }
+    R[(int64_t)c * nc + P] = acc;
+  }
+}
+
+// ---- eps = sqrt((1 + ||u||) eps_mach) / ||v|| on the device -----------------
+
+constexpr int kRedBlocks = 512;
+
+__global__ __launch_bounds__(kBlock) void k_sumsq2(int64_t n, const double* __restrict__ a,
+                                                   const double* __restrict__ b, double* __restrict__ part) {
+  __shared__ double sa[kBlock], sb[kBlock];
+  double xa = 0.0, xb = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const double x = a[i], y = b[i];
+    xa += x * x;
+    xb += y * y;
+  }
+  sa[threadIdx.x] = xa;
+  sb[threadIdx.x] = xb;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sa[threadIdx.x] += sa[threadIdx.x + s];
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sa[0];
+    part[kRedBlocks + blockIdx.x] = sb[0];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_eps_final(const double* __restrict__ part, int nb,
+                                                      double* __restrict__ eps) {
+  __shared__ double sa[kBlock], sb[kBlock];
+  double xa = 0.0, xb = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) {
+    xa += part[i];
+    xb += part[kRedBlocks + i];
+  }
+  sa[threadIdx.x] = xa;
+  sb[threadIdx.x] = xb;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sa[threadIdx.x] += sa[threadIdx.x + s];
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double nu = sqrt(sa[0]), nv = sqrt(sb[0]);
+    eps[0] = nv > 0.0 ? sqrt((1.0 + nu) * DBL_EPSILON) / nv : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_set_scalar(double* p, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpy_eps(int64_t n, const double* __restrict__ u,
+                                                     const double* __restrict__ v, const double* __restrict__ eps,
+                                                     double* __restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) w[i] = u[i] + eps[0] * v[i];
+}
+
+// ---- FP32 multicolour Gauss-Seidel ----------------------------------------
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_pc_in(int64_t nc, const int32_t* __restrict__ perm,
+                                                  const double* __restrict__ r, float* __restrict__ r32,
+                                                  float* __restrict__ z32) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nc) return;
+  const int32_t P = perm[i];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    r32[(int64_t)c * nc + i] = (float)r[(int64_t)c * nc + P];
+    z32[(int64_t)c * nc + i] = 0.0f;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_pc_sweep(int64_t nc, int64_t begin, int64_t end,
+                                                     const int32_t* __restrict__ nbr, const float* __restrict__ a,
+                                                     const float* __restrict__ dinv, const float* __restrict__ r32,
+                                                     float* __restrict__ z32) {
+  constexpr int NS = 2 * D;
+  const int64_t i = begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= end) return;
+  float acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = r32[(int64_t)c * nc + i];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int32_t N = nbr[(int64_t)s * nc + i];
+    const float aa = a[(int64_t)s * nc + i];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] -= aa * z32[(int64_t)c * nc + N];
+  }
+  const float di = dinv[i];
+#pragma unroll
+  for (int c = 0; c < D; ++c) z32[(int64_t)c * nc + i] = acc[c] * di;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_pc_out(int64_t nc, const int32_t* __restrict__ perm,
+                                                   const float* __restrict__ z32, double* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nc) return;
+  const int32_t P = perm[i];
+#pragma unroll
+  for (int c = 0; c < D; ++c) z[(int64_t)c * nc + P] = (double)z32[(int64_t)c * nc + i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+void timer_begin(hofv_ctx* c, const char* name, hipStream_t st, hipEvent_t* ev) {
+  if (!c->timing) return;
+  hipEventCreate(ev);
+  hipEventRecord(*ev, st);
+}
+
+void timer_end(hofv_ctx* c, const char* name, hipStream_t st, hipEvent_t ev) {
+  if (!c->timing) return;
+  hipEvent_t e2;
+  hipEventCreate(&e2);
+  hipEventRecord(e2, st);
+  c->timers.push_back({name, ev, e2});
+}
+
+#define TIMED(name, launch)              \
+  do {                                   \
+    hipEvent_t ev_;                      \
+    timer_begin(c, name, st, &ev_);      \
+    launch;                              \
+    timer_end(c, name, st, ev_);         \
+  } while (0)
+
+template <int D>
+static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const double* Ru, const double* eps,
+                                 hipStream_t st) {
+  DeviceTables& t = c->dev;
+  const int64_t nc = c->nc, nf = t.nf;
+  const bool nh = c->prm.material == HOFV_NEO_HOOKEAN;
+  const bool fold = !nh && c->prm.fold_quadrature;
+  TIMED("k_extrap", (k_extrap<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, t.S, t.c_stencil, t.c_extrap, u, t.ustar)));
+  if (nf > 0) {
+    if (fold) {
+      TIMED("k_face_le", (k_face_le<D><<<blocks_for(nf), kBlock, 0, st>>>(
+                             nf, t.nfi, nc, t.S, t.f_stencil, t.f_coef, t.f_own, t.f_nei, t.f_slots, t.f_area_vec,
+                             t.f_stab, c->prm.mu, c->prm.lambda, u, t.ustar, t.flux)));
+    } else {
+#define FACEQ(NQ, MAT, NAME)                                                                                  \
+  TIMED(NAME, (k_face_q<D, NQ, MAT><<<blocks_for(nf), kBlock, 0, st>>>(                                       \
+                  nf, t.nfi, nc, t.S, t.f_stencil, t.f_coef, t.f_own, t.f_nei, t.f_slots, t.f_area_vec, t.f_stab, \
+                  t.f_ghost, c->load, c->prm.mu, c->prm.lambda, u, t.ustar, t.flux, t.flag)))
+      const int nq = t.nq;
+      if (nh) {
+        if constexpr (D == 3) {
+          if (nq == 1) FACEQ(1, 1, "k_face_nh");
+          else if (nq == 4) FACEQ(4, 1, "k_face_nh");
+          else if (nq == 9) FACEQ(9, 1, "k_face_nh");
+          else return fail(c, HOFV_EINVAL, "unsupported number of face quadrature points");
+        } else {
+          return fail(c, HOFV_EINVAL, "the neo-Hookean law needs dim = 3");
+        }
+      } else {
+        if (nq == 1) FACEQ(1, 0, "k_face_q");
+        else if (nq == 2) FACEQ(2, 0, "k_face_q");
+        else if (nq == 3) FACEQ(3, 0, "k_face_q");
+        else if (nq == 4) FACEQ(4, 0, "k_face_q");
+        else if (nq == 9) FACEQ(9, 0, "k_face_q");
+        else return fail(c, HOFV_EINVAL, "unsupported number of face quadrature points");
+      }
+#undef FACEQ
+    }
+  }
+  TIMED("k_cell_sum", (k_cell_sum<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, nf, t.c_faces, t.flux, t.c_src, c->load,
+                                                                          Ru, eps, R)));
+  HOFV_HIP(c, hipGetLastError());
+  return HOFV_OK;
+}
+
+hofv_status launch_residual(hofv_ctx* c, const double* u, double* R, const double* Ru, const double* eps,
+                            hipStream_t st) {
+  return c->D == 2 ? residual_impl<2>(c, u, R, Ru, eps, st) : residual_impl<3>(c, u, R, Ru, eps, st);
+}
+
+hofv_status launch_eps(hofv_ctx* c, const double* u, const double* v, double eps_host, hipStream_t st) {
+  DeviceTables& t = c->dev;
+  const int64_t n = (int64_t)c->D * c->nc;
+  if (eps_host > 0) {
+    k_set_scalar<<<1, kBlock, 0, st>>>(t.eps, eps_host);
+  } else {
+    const int nb = (int)std::min<int64_t>(kRedBlocks, blocks_for(n));
+    TIMED("k_sumsq2", (k_sumsq2<<<nb, kBlock, 0, st>>>(n, u, v, t.scratch)));
+    k_eps_final<<<1, kBlock, 0, st>>>(t.scratch, nb, t.eps);
+  }
+  HOFV_HIP(c, hipGetLastError());
+  return HOFV_OK;
+}
+
+hofv_status launch_axpy_w(hofv_ctx* c, const double* u, const double* v, hipStream_t st) {
+  const int64_t n = (int64_t)c->D * c->nc;
+  TIMED("k_axpy_eps", (k_axpy_eps<<<blocks_for(n), kBlock, 0, st>>>(n, u, v, c->dev.eps, c->dev.w)));
+  HOFV_HIP(c, hipGetLastError());
+  return HOFV_OK;
+}
+
+template <int D>
+static hofv_status precond_impl(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st) {
+  DeviceTables& t = c->dev;
+  const int64_t nc = c->nc;
+  k_pc_in<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, t.p_perm, r, t.p_r, t.p_z);
+  // symmetric sweeps: colours 0..C-1 then C-1..0; an immediately repeated
+  // colour is skipped (cells of one colour are uncoupled, so it is a no-op)
+  int last = -1;
+  for (int s = 0; s < sweeps; ++s) {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int k = 0; k < t.n_colours; ++k) {
+        const int col = pass == 0 ? k : t.n_colours - 1 - k;
+        if (col == last) continue;
+        last = col;
+        const int64_t b = t.colour_start[col], e = t.colour_start[col + 1];
+        if (e > b)
+          TIMED("k_pc_sweep", (k_pc_sweep<D><<<blocks_for(e - b), kBlock, 0, st>>>(nc, b, e, t.p_nbr, t.p_a, t.p_dinv,
+                                                                                    t.p_r, t.p_z)));
+      }
+  }
+  k_pc_out<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, t.p_perm, t.p_z, z);
+  HOFV_HIP(c, hipGetLastError());
+  return HOFV_OK;
+}
+
+hofv_status launch_precond(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st) {
+  return c->D == 2 ? precond_impl<2>(c, r, z, sweeps, st) : precond_impl<3>(c, r, z, sweeps, st);
+}
+
+}  // namespace hofv

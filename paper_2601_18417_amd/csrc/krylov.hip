@@ -1,0 +1,329 @@
+// Krylov and Newton drivers on one HIP stream.
+//
+// FGMRES(m) with right preconditioning (Saad's flexible variant) and
+// classical Gram-Schmidt applied twice: per iteration z_j = M(v_j),
+// w = J z_j (finite-difference product), h = V^T w and w -= V h twice,
+// v_{j+1} = w / ||w||.  The Hessenberg column (j + 2 numbers) is the only
+// device-to-host transfer of an iteration; Givens rotations run on the host.
+// Dot products are deterministic: fixed block partials reduced in fixed order.
+//
+// Newton (Sec. 4.1 with the Armijo backtracking reading of the line search):
+// per load increment, J du = -R by FGMRES, u += lam du with lam = 1, 1/2, ...
+// accepted at ||R(u + lam du)|| <= (1 - 1e-4 lam) ||R(u)||.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace hofv {
+
+namespace {
+
+constexpr int kB = 256;
+constexpr int kMaxDots = 32;
+constexpr int kDotBlocks = 256;
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
+
+// part[i * kDotBlocks + block] = partial of sum_l V_i[l] w[l], i < nv
+__global__ __launch_bounds__(kB) void k_multidot(int64_t n, int nv, const double* __restrict__ V, int64_t ld,
+                                                 const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[kB];
+  double acc[kMaxDots];
+#pragma unroll
+  for (int i = 0; i < kMaxDots; ++i) acc[i] = 0.0;
+  for (int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x; l < n; l += (int64_t)gridDim.x * kB) {
+    const double x = w[l];
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < nv) acc[i] += V[(int64_t)i * ld + l] * x;
+  }
+  for (int i = 0; i < nv; ++i) {
+    red[threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int s = kB / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[i * kDotBlocks + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[i] (+)= sum_b part[i][b] for i < nv, one block per i
+__global__ __launch_bounds__(kB) void k_reduce_parts(int nv, int nb, const double* __restrict__ part,
+                                                     double* __restrict__ out, int accumulate) {
+  __shared__ double red[kB];
+  const int i = blockIdx.x;
+  if (i >= nv) return;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kB) a += part[i * kDotBlocks + b];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = kB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = accumulate ? out[i] + red[0] : red[0];
+}
+
+// w[l] += sign * sum_i h[i] V_i[l]
+__global__ __launch_bounds__(kB) void k_multiaxpy(int64_t n, int nv, const double* __restrict__ V, int64_t ld,
+                                                  const double* __restrict__ h, double sign, double* __restrict__ w) {
+  const int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (l >= n) return;
+  double s = 0.0;
+  for (int i = 0; i < nv; ++i) s += h[i] * V[(int64_t)i * ld + l];
+  w[l] += sign * s;
+}
+
+// y = x * (1 / d[0]) if d[0] > 0 (d is a squared norm when sq != 0)
+__global__ __launch_bounds__(kB) void k_scale_by(int64_t n, const double* __restrict__ x, const double* __restrict__ d,
+                                                 int sq, double* __restrict__ y) {
+  const int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (l >= n) return;
+  const double nrm = sq ? sqrt(d[0]) : d[0];
+  y[l] = nrm > 0.0 ? x[l] / nrm : 0.0;
+}
+
+__global__ __launch_bounds__(kB) void k_lincomb(int64_t n, double a, const double* __restrict__ x, double b,
+                                                const double* __restrict__ y, double* __restrict__ z) {
+  const int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (l < n) z[l] = a * x[l] + b * y[l];
+}
+
+__global__ __launch_bounds__(kB) void k_fill(int64_t n, double v, double* __restrict__ z) {
+  const int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (l < n) z[l] = v;
+}
+
+__global__ __launch_bounds__(kB) void k_fill_i(int n, int v, int32_t* __restrict__ z) {
+  const int l = blockIdx.x * kB + threadIdx.x;
+  if (l < n) z[l] = v;
+}
+
+}  // namespace
+
+// dots of x against nv rows of V (stride ld); result on device in out[0..nv)
+static hofv_status dots(hofv_ctx* c, int64_t n, int nv, const double* V, int64_t ld, const double* x, double* out,
+                        int accumulate, hipStream_t st) {
+  const int nb = (int)std::min<int64_t>(kDotBlocks, nblk(n));
+  k_multidot<<<nb, kB, 0, st>>>(n, nv, V, ld, x, c->dev.scratch);
+  k_reduce_parts<<<nv, kB, 0, st>>>(nv, nb, c->dev.scratch, out, accumulate);
+  HOFV_HIP(c, hipGetLastError());
+  return HOFV_OK;
+}
+
+static hofv_status host_norm(hofv_ctx* c, int64_t n, const double* x, double* out, hipStream_t st) {
+  hofv_status s = dots(c, n, 1, x, n, x, c->kry.h + 2 * (kMaxDots + 2), 0, st);
+  if (s) return s;
+  double v;
+  HOFV_HIP(c, hipMemcpyAsync(&v, c->kry.h + 2 * (kMaxDots + 2), sizeof(double), hipMemcpyDeviceToHost, st));
+  HOFV_HIP(c, hipStreamSynchronize(st));
+  *out = std::sqrt(v);
+  return HOFV_OK;
+}
+
+static hofv_status ensure_krylov(hofv_ctx* c, int m) {
+  Krylov& k = c->kry;
+  if (k.V && k.m >= m) return HOFV_OK;
+  if (k.V) {  // grow: release the old set
+    for (void* p : {(void*)k.V, (void*)k.Z}) {
+      hipFree(p);
+      c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), p), c->allocations.end());
+    }
+  }
+  const int64_t n = (int64_t)c->D * c->nc;
+  hofv_status s;
+  if ((s = dev_alloc(c, &k.V, (size_t)(m + 1) * n))) return s;
+  if ((s = dev_alloc(c, &k.Z, (size_t)m * n))) return s;
+  if (!k.h) {
+    if ((s = dev_alloc(c, &k.h, 4 * (kMaxDots + 2)))) return s;
+    if ((s = dev_alloc(c, &k.tmp, (size_t)n))) return s;
+    if ((s = dev_alloc(c, &k.tmp2, (size_t)n))) return s;
+  }
+  k.m = m;
+  return HOFV_OK;
+}
+
+hofv_status jvp_impl(hofv_ctx* c, const double* u, const double* Ru, const double* v, double* Jv, double eps,
+                     hipStream_t st);
+hofv_status precond_dispatch(hofv_ctx* c, const double* r, double* z, int sweeps, int learned, hipStream_t st);
+
+hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const double* rhs, double* x,
+                        const hofv_krylov_opts* o, hofv_krylov_stats* stats, hipStream_t st) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int m = std::max(1, std::min(o->restart > 0 ? o->restart : 30, kMaxDots - 1));
+  const int maxit = o->max_iters > 0 ? o->max_iters : 1000;
+  const double rtol = o->rtol > 0 ? o->rtol : 1e-6;
+  const int sweeps = o->n_sweeps > 0 ? o->n_sweeps : 2;
+  hofv_status s = ensure_krylov(c, m);
+  if (s) return s;
+  Krylov& K = c->kry;
+  const int64_t n = (int64_t)c->D * c->nc;
+  double* hd = K.h;  // [0, kMaxDots+2): Hessenberg column; [kMaxDots+2]: squared norm
+  double bnorm, xnorm;
+  if ((s = host_norm(c, n, rhs, &bnorm, st))) return s;
+  if ((s = host_norm(c, n, x, &xnorm, st))) return s;
+  stats->iters = 0;
+  stats->converged = 0;
+  if (!std::isfinite(bnorm) || !std::isfinite(xnorm)) return fail(c, HOFV_ENAN, "NaN/Inf in FGMRES input");
+  if (bnorm == 0.0) {
+    k_fill<<<nblk(n), kB, 0, st>>>(n, 0.0, x);
+    stats->converged = 1;
+    stats->rel_residual = 0.0;
+    HOFV_HIP(c, hipStreamSynchronize(st));
+    return HOFV_OK;
+  }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hcol(m + 2);
+  int it = 0;
+  double beta = 0;
+  for (;;) {
+    // V_0 = rhs - J x
+    if (xnorm > 0) {
+      if ((s = jvp_impl(c, u, Ru, x, K.tmp, 0.0, st))) return s;
+      k_lincomb<<<nblk(n), kB, 0, st>>>(n, 1.0, rhs, -1.0, K.tmp, K.V);
+    } else {
+      k_lincomb<<<nblk(n), kB, 0, st>>>(n, 1.0, rhs, 0.0, rhs, K.V);
+    }
+    if ((s = host_norm(c, n, K.V, &beta, st))) return s;
+    if (!std::isfinite(beta)) return fail(c, HOFV_ENAN, "NaN/Inf in the FGMRES residual");
+    if (beta <= rtol * bnorm || it >= maxit) break;
+    k_fill<<<1, kB, 0, st>>>(1, beta, hd + kMaxDots + 3);
+    k_scale_by<<<nblk(n), kB, 0, st>>>(n, K.V, hd + kMaxDots + 3, 0, K.V);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int kdone = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = K.V + (size_t)j * n;
+      double* zj = K.Z + (size_t)j * n;
+      double* w = K.V + (size_t)(j + 1) * n;
+      if ((s = precond_dispatch(c, vj, zj, sweeps, o->learned, st))) return s;
+      if ((s = jvp_impl(c, u, Ru, zj, w, 0.0, st))) return s;
+      // CGS2
+      if ((s = dots(c, n, j + 1, K.V, n, w, hd, 0, st))) return s;
+      k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd, -1.0, w);
+      if ((s = dots(c, n, j + 1, K.V, n, w, hd + kMaxDots + 4 + 0, 0, st))) return s;
+      k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd + kMaxDots + 4, -1.0, w);
+      if ((s = dots(c, n, 1, w, n, w, hd + j + 1, 0, st))) return s;
+      k_scale_by<<<nblk(n), kB, 0, st>>>(n, w, hd + j + 1, 1, w);
+      HOFV_HIP(c, hipGetLastError());
+      std::vector<double> h2(j + 1);
+      HOFV_HIP(c, hipMemcpyAsync(hcol.data(), hd, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
+      HOFV_HIP(c, hipMemcpyAsync(h2.data(), hd + kMaxDots + 4, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+      HOFV_HIP(c, hipStreamSynchronize(st));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i] + h2[i];
+      H[(size_t)(j + 1) * m + j] = std::sqrt(hcol[j + 1]);
+      if (!std::isfinite(H[(size_t)(j + 1) * m + j])) return fail(c, HOFV_ENAN, "NaN/Inf in Arnoldi");
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+      const double den = std::hypot(a, b);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? b / den : 0.0;
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      kdone = j + 1;
+      if (std::fabs(g[j + 1]) <= rtol * bnorm || it >= maxit || den == 0.0) break;
+    }
+    for (int i = kdone - 1; i >= 0; --i) {
+      double sum = g[i];
+      for (int l = i + 1; l < kdone; ++l) sum -= H[(size_t)i * m + l] * y[l];
+      y[i] = sum / H[(size_t)i * m + i];
+    }
+    HOFV_HIP(c, hipMemcpyAsync(hd, y.data(), kdone * sizeof(double), hipMemcpyHostToDevice, st));
+    k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, kdone, K.Z, n, hd, 1.0, x);
+    HOFV_HIP(c, hipGetLastError());
+    xnorm = 1.0;
+  }
+  stats->iters = it;
+  stats->rel_residual = beta / bnorm;
+  stats->converged = beta <= rtol * bnorm;
+  stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return HOFV_OK;
+}
+
+hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_newton_stats* stats,
+                        hipStream_t st) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = (int64_t)c->D * c->nc;
+  hofv_status s = ensure_krylov(c, std::min(o->krylov.restart > 0 ? o->krylov.restart : 30, kMaxDots - 1));
+  if (s) return s;
+  // workspace: R, du, rhs, ut, Rt
+  static thread_local std::vector<double*> none;
+  double *R, *du, *rhs, *ut, *Rt;
+  if ((s = dev_alloc(c, &R, n)) || (s = dev_alloc(c, &du, n)) || (s = dev_alloc(c, &rhs, n)) ||
+      (s = dev_alloc(c, &ut, n)) || (s = dev_alloc(c, &Rt, n)))
+    return s;
+  auto release = [&]() {
+    for (double* p : {R, du, rhs, ut, Rt}) {
+      hipFree(p);
+      c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), (void*)p), c->allocations.end());
+      c->device_bytes -= n * sizeof(double);
+    }
+  };
+  const int ninc = std::max(1, o->n_increments);
+  const double tol = o->tol > 0 ? o->tol : 1e-8;
+  hofv_krylov_opts ko = o->krylov;
+  ko.rtol = o->eta > 0 ? o->eta : 1e-4;
+  stats->newton_iters = 0;
+  stats->krylov_iters = 0;
+  stats->converged = 1;
+  hofv_status result = HOFV_OK;
+  for (int inc = 1; inc <= ninc && result == HOFV_OK; ++inc) {
+    c->load = (double)inc / ninc;
+    if ((s = launch_residual(c, u, R, nullptr, nullptr, st))) { result = s; break; }
+    double r0, rn;
+    if ((s = host_norm(c, n, R, &r0, st))) { result = s; break; }
+    rn = r0;
+    int itn = 0;
+    while (rn > tol * r0 && itn < (o->max_newton > 0 ? o->max_newton : 50)) {
+      k_lincomb<<<nblk(n), kB, 0, st>>>(n, -1.0, R, 0.0, R, rhs);
+      k_fill<<<nblk(n), kB, 0, st>>>(n, 0.0, du);
+      hofv_krylov_stats ks{};
+      if ((s = fgmres_impl(c, u, R, rhs, du, &ko, &ks, st))) { result = s; break; }
+      stats->krylov_iters += ks.iters;
+      double lam = 1.0, rt = 0.0;
+      bool accepted = false;
+      const int maxls = o->max_line_search > 0 ? o->max_line_search : 10;
+      for (int ls = 0; ls <= maxls; ++ls) {
+        k_lincomb<<<nblk(n), kB, 0, st>>>(n, 1.0, u, lam, du, ut);
+        k_fill_i<<<1, kB, 0, st>>>(1, 0, c->dev.flag);
+        if ((s = launch_residual(c, ut, Rt, nullptr, nullptr, st))) { result = s; break; }
+        int32_t flag = 0;
+        HOFV_HIP(c, hipMemcpyAsync(&flag, c->dev.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        if ((s = host_norm(c, n, Rt, &rt, st))) { result = s; break; }
+        if (!flag && std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * rn) { accepted = true; break; }
+        if (ls == maxls && !flag && std::isfinite(rt)) { accepted = true; break; }  // last trial
+        lam *= 0.5;
+      }
+      if (result) break;
+      if (!accepted) { result = fail(c, HOFV_EINVERTED, "line search found no admissible step"); break; }
+      HOFV_HIP(c, hipMemcpyAsync(u, ut, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      HOFV_HIP(c, hipMemcpyAsync(R, Rt, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      rn = rt;
+      ++itn;
+      ++stats->newton_iters;
+    }
+    stats->rel_residual = r0 > 0 ? rn / r0 : 0.0;
+    if (!(rn <= tol * r0)) stats->converged = 0;
+  }
+  HOFV_HIP(c, hipStreamSynchronize(st));
+  release();
+  stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (result == HOFV_OK && !stats->converged)
+    return fail(c, HOFV_ENOCONV, "Newton did not reach the tolerance");
+  return result;
+}
+
+}  // namespace hofv

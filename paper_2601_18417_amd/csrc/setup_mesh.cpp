@@ -1,0 +1,312 @@
+// Mesh topology and geometry for straight-edged quads and trilinear hexahedra
+// (paper Sec. 3.1): face matching, owner/neighbour, outward unit normals and
+// areas from the exact vector area of each (bi)linear face, face and cell
+// Gauss-Legendre quadrature, cell volumes and centroids.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <numeric>
+
+#include "common.h"
+
+namespace hofv {
+
+namespace {
+
+// library-local face tables: vertex cycles whose right-hand normal points out
+const int kQuadFace[4][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}};
+const int kHexFace[6][4] = {{0, 3, 2, 1}, {4, 5, 6, 7}, {0, 1, 5, 4},
+                            {3, 7, 6, 2}, {0, 4, 7, 3}, {1, 2, 6, 5}};
+
+// Gauss-Legendre nodes/weights on [0,1] by Newton iteration on P_n.
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    double t = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        double pk = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      if (n == 1) { p1 = t; p0 = 1.0; }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        double pk = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      dp = (n == 1) ? 1.0 : n * (t * p1 - p0) / (t * t - 1.0);
+    }
+    x[n - 1 - i] = 0.5 * (t + 1.0);
+    w[n - 1 - i] = 1.0 / ((1.0 - t * t) * dp * dp);  // = (2/((1-t^2)P'^2)) / 2
+  }
+}
+
+inline void cross3(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// trilinear hex map at reference point (r,s,t) in [0,1]^3: position and Jacobian determinant
+void hex_map(const double* X /*8x3*/, double r, double s, double t, double* x, double* detJ) {
+  // vertex reference coordinates in VTK order
+  static const int ref[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0},
+                                {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
+  double J[3][3] = {{0}};
+  x[0] = x[1] = x[2] = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    double fr = ref[a][0] ? r : 1 - r, gr = ref[a][0] ? 1.0 : -1.0;
+    double fs = ref[a][1] ? s : 1 - s, gs = ref[a][1] ? 1.0 : -1.0;
+    double ft = ref[a][2] ? t : 1 - t, gt = ref[a][2] ? 1.0 : -1.0;
+    double N = fr * fs * ft;
+    double dN[3] = {gr * fs * ft, fr * gs * ft, fr * fs * gt};
+    for (int i = 0; i < 3; ++i) {
+      x[i] += N * X[3 * a + i];
+      for (int j = 0; j < 3; ++j) J[i][j] += X[3 * a + i] * dN[j];
+    }
+  }
+  *detJ = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+          J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+void quad_map(const double* X /*4x2*/, double r, double s, double* x, double* detJ) {
+  double N[4] = {(1 - r) * (1 - s), r * (1 - s), r * s, (1 - r) * s};
+  double dr[4] = {-(1 - s), (1 - s), s, -s};
+  double ds[4] = {-(1 - r), -r, r, (1 - r)};
+  double J[2][2] = {{0}};
+  x[0] = x[1] = 0;
+  for (int a = 0; a < 4; ++a) {
+    x[0] += N[a] * X[2 * a];
+    x[1] += N[a] * X[2 * a + 1];
+    J[0][0] += X[2 * a] * dr[a];
+    J[0][1] += X[2 * a] * ds[a];
+    J[1][0] += X[2 * a + 1] * dr[a];
+    J[1][1] += X[2 * a + 1] * ds[a];
+  }
+  *detJ = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+}
+
+}  // namespace
+
+hofv_status build_topology(hofv_ctx* c) {
+  const int D = c->D;
+  const int nlf = D == 2 ? 4 : 6, nfv = D == 2 ? 2 : 4, ncv = D == 2 ? 4 : 8;
+  struct Rec {
+    std::array<int64_t, 4> key;
+    int64_t cell;
+    int32_t slot;
+  };
+  std::vector<Rec> recs((size_t)c->nc * nlf);
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < c->nc; ++e) {
+    const int64_t* cv = &c->cells[(size_t)e * ncv];
+    for (int s = 0; s < nlf; ++s) {
+      Rec& r = recs[(size_t)e * nlf + s];
+      r.key = {-1, -1, -1, -1};
+      for (int k = 0; k < nfv; ++k) r.key[k] = cv[D == 2 ? kQuadFace[s][k] : kHexFace[s][k]];
+      std::sort(r.key.begin(), r.key.begin() + nfv);
+      r.cell = e;
+      r.slot = s;
+    }
+  }
+  std::sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) {
+    if (a.key != b.key) return a.key < b.key;
+    return a.cell < b.cell;
+  });
+  std::vector<hofv_ctx::Face> inner, bnd;
+  inner.reserve(recs.size() / 2);
+  for (size_t i = 0; i < recs.size();) {
+    size_t j = i + 1;
+    while (j < recs.size() && recs[j].key == recs[i].key) ++j;
+    if (j - i > 2) return fail(c, HOFV_EINVAL, "non-manifold mesh: a face is shared by more than two cells");
+    hofv_ctx::Face f{};
+    f.own = recs[i].cell;
+    f.sown = recs[i].slot;
+    const int64_t* cv = &c->cells[(size_t)f.own * ncv];
+    for (int k = 0; k < nfv; ++k) f.v[k] = cv[D == 2 ? kQuadFace[f.sown][k] : kHexFace[f.sown][k]];
+    if (j - i == 2) {
+      f.nei = recs[i + 1].cell;
+      f.snei = recs[i + 1].slot;
+      if (f.nei == f.own) return fail(c, HOFV_EINVAL, "degenerate cell: repeated face");
+      inner.push_back(f);
+    } else {
+      f.nei = -1;
+      f.snei = -1;
+      bnd.push_back(f);
+    }
+    i = j;
+  }
+  auto by_owner = [](const hofv_ctx::Face& a, const hofv_ctx::Face& b) {
+    return a.own != b.own ? a.own < b.own : a.sown < b.sown;
+  };
+  std::sort(inner.begin(), inner.end(), by_owner);
+  std::sort(bnd.begin(), bnd.end(), by_owner);
+  c->n_internal = (int64_t)inner.size();
+  c->faces = std::move(inner);
+  c->faces.insert(c->faces.end(), bnd.begin(), bnd.end());
+  c->bface.resize(bnd.size());
+  std::iota(c->bface.begin(), c->bface.end(), c->n_internal);
+  return HOFV_OK;
+}
+
+hofv_status build_geometry(hofv_ctx* c) {
+  const int D = c->D, p = c->prm.order_p, ng = c->prm.n_gauss;
+  const int64_t nc = c->nc;
+  const int ncv = D == 2 ? 4 : 8;
+  c->cen.assign((size_t)nc * D, 0.0);
+  c->vol.assign(nc, 0.0);
+  std::vector<double> g2x, g2w, gvx, gvw, gfx, gfw;
+  gauss_legendre01(2, g2x, g2w);
+  gauss_legendre01(p + 2, gvx, gvw);
+  gauss_legendre01(ng, gfx, gfw);
+  const int nv1 = p + 2;
+  c->nqv = D == 2 ? nv1 * nv1 : nv1 * nv1 * nv1;
+  c->vq_pts.assign((size_t)nc * c->nqv * D, 0.0);
+  c->vq_w.assign((size_t)nc * c->nqv, 0.0);
+  bool bad = false;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+  for (int64_t e = 0; e < nc; ++e) {
+    double X[24];
+    for (int a = 0; a < ncv; ++a)
+      for (int d = 0; d < D; ++d) X[D * a + d] = c->verts[(size_t)c->cells[(size_t)e * ncv + a] * D + d];
+    if (D == 2) {
+      // polygon (shoelace) area and centroid of the straight-edged quad
+      double A2 = 0, cx = 0, cy = 0;
+      for (int a = 0; a < 4; ++a) {
+        int b = (a + 1) % 4;
+        double cr = X[2 * a] * X[2 * b + 1] - X[2 * b] * X[2 * a + 1];
+        A2 += cr;
+        cx += (X[2 * a] + X[2 * b]) * cr;
+        cy += (X[2 * a + 1] + X[2 * b + 1]) * cr;
+      }
+      c->vol[e] = 0.5 * A2;
+      c->cen[2 * e] = cx / (3.0 * A2);
+      c->cen[2 * e + 1] = cy / (3.0 * A2);
+      int q = 0;
+      for (int i = 0; i < nv1; ++i)
+        for (int j = 0; j < nv1; ++j, ++q) {
+          double x[2], dj;
+          quad_map(X, gvx[i], gvx[j], x, &dj);
+          c->vq_pts[((size_t)e * c->nqv + q) * 2] = x[0];
+          c->vq_pts[((size_t)e * c->nqv + q) * 2 + 1] = x[1];
+          c->vq_w[(size_t)e * c->nqv + q] = gvw[i] * gvw[j] * dj;
+        }
+    } else {
+      double V = 0, m[3] = {0, 0, 0};
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          for (int k = 0; k < 2; ++k) {
+            double x[3], dj;
+            hex_map(X, g2x[i], g2x[j], g2x[k], x, &dj);
+            double wq = g2w[i] * g2w[j] * g2w[k] * dj;
+            V += wq;
+            for (int d = 0; d < 3; ++d) m[d] += wq * x[d];
+          }
+      c->vol[e] = V;
+      for (int d = 0; d < 3; ++d) c->cen[3 * e + d] = m[d] / V;
+      int q = 0;
+      for (int i = 0; i < nv1; ++i)
+        for (int j = 0; j < nv1; ++j)
+          for (int k = 0; k < nv1; ++k, ++q) {
+            double x[3], dj;
+            hex_map(X, gvx[i], gvx[j], gvx[k], x, &dj);
+            for (int d = 0; d < 3; ++d) c->vq_pts[((size_t)e * c->nqv + q) * 3 + d] = x[d];
+            c->vq_w[(size_t)e * c->nqv + q] = gvw[i] * gvw[j] * gvw[k] * dj;
+          }
+    }
+    if (!(c->vol[e] > 0)) bad = true;
+  }
+  if (bad) return fail(c, HOFV_EINVAL, "a cell has non-positive volume (check vertex order)");
+
+  // faces
+  const int64_t nf = (int64_t)c->faces.size();
+  c->nq = D == 2 ? ng : ng * ng;
+  const int nq = c->nq;
+  c->f_centre.assign((size_t)nf * D, 0.0);
+  c->f_normal.assign((size_t)nf * D, 0.0);
+  c->f_area.assign(nf, 0.0);
+  c->f_qp.assign((size_t)nf * nq * D, 0.0);
+  c->f_qw.assign((size_t)nf * nq, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int64_t f = 0; f < nf; ++f) {
+    const hofv_ctx::Face& F = c->faces[f];
+    double* qp = &c->f_qp[(size_t)f * nq * D];
+    double* qw = &c->f_qw[(size_t)f * nq];
+    if (D == 2) {
+      const double* a = &c->verts[(size_t)F.v[0] * 2];
+      const double* b = &c->verts[(size_t)F.v[1] * 2];
+      double ex = b[0] - a[0], ey = b[1] - a[1];
+      double L = std::sqrt(ex * ex + ey * ey);
+      c->f_area[f] = L;
+      c->f_normal[2 * f] = ey / L;
+      c->f_normal[2 * f + 1] = -ex / L;
+      for (int q = 0; q < nq; ++q) {
+        qp[2 * q] = a[0] + gfx[q] * ex;
+        qp[2 * q + 1] = a[1] + gfx[q] * ey;
+        qw[q] = gfw[q];
+      }
+    } else {
+      const double* x0 = &c->verts[(size_t)F.v[0] * 3];
+      const double* x1 = &c->verts[(size_t)F.v[1] * 3];
+      const double* x2 = &c->verts[(size_t)F.v[2] * 3];
+      const double* x3 = &c->verts[(size_t)F.v[3] * 3];
+      double d20[3], d31[3], Sv[3];
+      for (int d = 0; d < 3; ++d) { d20[d] = x2[d] - x0[d]; d31[d] = x3[d] - x1[d]; }
+      cross3(d20, d31, Sv);
+      for (int d = 0; d < 3; ++d) Sv[d] *= 0.5;
+      double A = std::sqrt(Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2]);
+      c->f_area[f] = A;
+      for (int d = 0; d < 3; ++d) c->f_normal[3 * f + d] = Sv[d] / A;
+      double wsum = 0;
+      int q = 0;
+      for (int i = 0; i < ng; ++i)
+        for (int j = 0; j < ng; ++j, ++q) {
+          double s = gfx[i], t = gfx[j];
+          double xs[3], xt[3], nn[3];
+          for (int d = 0; d < 3; ++d) {
+            qp[3 * q + d] = (1 - s) * (1 - t) * x0[d] + s * (1 - t) * x1[d] + s * t * x2[d] + (1 - s) * t * x3[d];
+            xs[d] = (1 - t) * (x1[d] - x0[d]) + t * (x2[d] - x3[d]);
+            xt[d] = (1 - s) * (x3[d] - x0[d]) + s * (x2[d] - x1[d]);
+          }
+          cross3(xs, xt, nn);
+          qw[q] = gfw[i] * gfw[j] * std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+          wsum += qw[q];
+        }
+      for (int k = 0; k < nq; ++k) qw[k] /= wsum;
+    }
+    for (int d = 0; d < D; ++d) {
+      double s = 0;
+      for (int q = 0; q < nq; ++q) s += qw[q] * qp[q * D + d];
+      c->f_centre[(size_t)f * D + d] = s;
+    }
+  }
+  // boundary views in caller order
+  const size_t nb = c->bface.size();
+  c->b_centre.resize(nb * D);
+  c->b_normal.resize(nb * D);
+  c->b_qp.resize(nb * nq * D);
+  for (size_t b = 0; b < nb; ++b) {
+    int64_t f = c->bface[b];
+    for (int d = 0; d < D; ++d) {
+      c->b_centre[b * D + d] = c->f_centre[(size_t)f * D + d];
+      c->b_normal[b * D + d] = c->f_normal[(size_t)f * D + d];
+    }
+    for (int k = 0; k < nq * D; ++k) c->b_qp[b * nq * D + k] = c->f_qp[(size_t)f * nq * D + k];
+  }
+  return HOFV_OK;
+}
+
+}  // namespace hofv

@@ -1,0 +1,346 @@
+// Builds every device table of the residual, J.v and preconditioner kernels
+// on the host and uploads it (hofv_setup).
+//
+//  * face tables (internal faces, then displacement faces): stencil around the
+//    face centre, gradient coefficients at each quadrature point (eq.
+//    faceQuadGrad with the ghost node of Sec. 3.5.3 on displacement faces),
+//    either kept per point or, for linear elasticity, summed with the
+//    quadrature weights (n . sigma is linear in grad u, so the face term only
+//    needs sum_q alpha_q (grad u)_q when every point shares the face normal);
+//  * cell tables: stencil around the centroid and, for every face slot, the
+//    coefficients of u*_{f,P} - u_P (eq. alphaJump);
+//  * sources at load 1: body force (eq. bodyTerm), traction faces, the ghost
+//    part of displacement-face gradients (linear elasticity) and the u_b part
+//    of the displacement-face stabilisation;
+//  * the compact approximate Jacobian in FP32 with a greedy colouring.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "common.h"
+
+namespace hofv {
+
+hofv_status build_tables(hofv_ctx* c) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int D = c->D, p = c->prm.order_p, NS = 2 * D;
+  const int64_t nc = c->nc;
+  const int nq = c->nq;
+  const bool nh = c->prm.material == HOFV_NEO_HOOKEAN;
+  const bool fold = !nh && c->prm.fold_quadrature;
+  const double mu = c->prm.mu, lam = c->prm.lambda, kbar = 2 * mu + lam;
+  const int S = n_basis(D, p) + c->prm.n_plus;
+  if (S > 255) return fail(c, HOFV_EINVAL, "stencil size above 255");
+  if (S > nc) return fail(c, HOFV_EINVAL, "stencil size exceeds the number of cells");
+  const double kshape = c->prm.k_weight, gw = c->prm.ghost_weight, alpha = c->prm.alpha;
+
+  // kernel faces: internal, then displacement
+  std::vector<int64_t> kf;
+  kf.reserve(c->faces.size());
+  for (int64_t f = 0; f < c->n_internal; ++f) kf.push_back(f);
+  std::vector<int64_t> trac;
+  for (size_t b = 0; b < c->bface.size(); ++b) {
+    if (c->btype[b] == HOFV_BC_DISPLACEMENT) kf.push_back(c->bface[b]);
+    else trac.push_back((int64_t)b);
+  }
+  const int64_t nf = (int64_t)kf.size(), nfi = c->n_internal, nfd = nf - nfi;
+  std::vector<int64_t> kf_of_face(c->faces.size(), -1);
+  std::vector<int64_t> bidx_of_face(c->faces.size(), -1);
+  for (int64_t i = 0; i < nf; ++i) kf_of_face[kf[i]] = i;
+  for (size_t b = 0; b < c->bface.size(); ++b) bidx_of_face[c->bface[b]] = (int64_t)b;
+
+  // stencils
+  std::vector<double> pts((size_t)nf * D);
+  for (int64_t i = 0; i < nf; ++i)
+    for (int d = 0; d < D; ++d) pts[i * D + d] = c->f_centre[(size_t)kf[i] * D + d];
+  std::vector<int32_t> fst((size_t)nf * S), cst((size_t)nc * S);
+  nearest_cells(c->cen, D, nc, pts.data(), nf, S, c->prm.stencil_quantum, fst.data());
+  nearest_cells(c->cen, D, nc, c->cen.data(), nc, S, c->prm.stencil_quantum, cst.data());
+
+  // face coefficients
+  const int ncoef = fold ? D : nq * D;
+  std::vector<double> fcoef((size_t)S * ncoef * nf, 0.0);
+  std::vector<double> fsv((size_t)(fold ? D : nq * D) * nf, 0.0);
+  std::vector<double> fstab(nf, 0.0), faj(nf, 0.0);
+  std::vector<double> fghost(nh ? (size_t)nq * D * D * std::max<int64_t>(nfd, 1) : 0, 0.0);
+  std::vector<double> src((size_t)D * nc, 0.0);
+  std::vector<int32_t> fown(nf), fnei(nf), fslots(nf);
+  double max_cond = 0.0;
+  bool singular = false;
+  // per-face constant source contributions, summed into src serially afterwards
+  std::vector<double> fsrc((size_t)nf * D, 0.0);
+#pragma omp parallel for schedule(dynamic, 64) reduction(max : max_cond) reduction(|| : singular)
+  for (int64_t i = 0; i < nf; ++i) {
+    const int64_t f = kf[i];
+    const hofv_ctx::Face& F = c->faces[f];
+    const bool disp = F.nei < 0;
+    const int64_t b = disp ? bidx_of_face[f] : -1;
+    fown[i] = (int32_t)F.own;
+    fnei[i] = (int32_t)F.nei;
+    fslots[i] = F.sown | ((disp ? 0 : F.snei) << 8);
+    const double* n = &c->f_normal[(size_t)f * D];
+    const double A = c->f_area[f];
+    const double* qw = &c->f_qw[(size_t)f * nq];
+    double X[256 * 3];
+    for (int k = 0; k < S; ++k)
+      for (int d = 0; d < D; ++d) X[k * D + d] = c->cen[(size_t)fst[i * S + k] * D + d];
+    double targets[3] = {0, 1, 2};
+    double out[3 * 256];
+    double Gg[3][3] = {{0}};  // sum_q alpha_q ghost gradient (LE) at load 1
+    for (int q = 0; q < nq; ++q) {
+      double cond, h;
+      bool ok = ls_functionals(D, p, kshape, &c->f_qp[((size_t)f * nq + q) * D], X, S, disp ? gw : 0.0,
+                               kTargetGradient, D, targets, out, &cond, &h);
+      if (!ok) singular = true;
+      max_cond = std::max(max_cond, cond);
+      const int m = S + (disp ? 1 : 0);
+      for (int a = 0; a < D; ++a) {
+        for (int k = 0; k < S; ++k) {
+          if (fold) fcoef[((size_t)k * D + a) * nf + i] += qw[q] * out[a * m + k];
+          else fcoef[(((size_t)k * nq + q) * D + a) * nf + i] = out[a * m + k];
+        }
+        if (disp) {
+          const double cg = out[a * m + S];
+          const double* ub = &c->ubq[((size_t)b * nq + q) * D];
+          for (int j = 0; j < D; ++j) {
+            if (nh) fghost[(((size_t)q * D + a) * D + j) * nfd + (i - nfi)] = cg * ub[j];
+            else Gg[a][j] += qw[q] * cg * ub[j];
+          }
+        }
+      }
+      if (!fold)
+        for (int d = 0; d < D; ++d) fsv[((size_t)q * D + d) * nf + i] = qw[q] * A * n[d];
+    }
+    if (fold)
+      for (int d = 0; d < D; ++d) fsv[(size_t)d * nf + i] = A * n[d];
+    // stabilisation coefficient alpha Kbar Gamma / |d . n|
+    const double* xP = &c->cen[(size_t)F.own * D];
+    const double* xo = disp ? &c->f_centre[(size_t)f * D] : &c->cen[(size_t)F.nei * D];
+    double dn = 0;
+    for (int d = 0; d < D; ++d) dn += (xo[d] - xP[d]) * n[d];
+    const double a_f = alpha * kbar * A / std::fabs(dn);
+    fstab[i] = a_f;
+    faj[i] = kbar * A / std::fabs(dn);
+    if (disp) {
+      // constant parts: u_b of the stabilisation and (LE) the ghost term
+      const double* ubc = &c->ubc[(size_t)b * D];
+      for (int j = 0; j < D; ++j) fsrc[i * D + j] += a_f * ubc[j];
+      if (!nh) {
+        double tr = 0;
+        for (int d = 0; d < D; ++d) tr += Gg[d][d];
+        for (int j = 0; j < D; ++j) {
+          double t = 0;
+          for (int a = 0; a < D; ++a) t += A * n[a] * (mu * (Gg[a][j] + Gg[j][a]) + (a == j ? lam * tr : 0.0));
+          fsrc[i * D + j] += t;
+        }
+      }
+    }
+  }
+  if (singular) return fail(c, HOFV_ESINGULAR, "rank-deficient least-squares stencil at a face quadrature point");
+  for (int64_t i = nfi; i < nf; ++i)
+    for (int j = 0; j < D; ++j) src[(size_t)j * nc + fown[i]] += fsrc[i * D + j];
+
+  // cell extrapolation rows and face slot codes
+  std::vector<double> cext((size_t)S * NS * nc, 0.0);
+  std::vector<int32_t> cfaces((size_t)NS * nc, kNoFace);
+  for (int64_t i = 0; i < nf; ++i) {
+    cfaces[(size_t)(fslots[i] & 0xff) * nc + fown[i]] = (int32_t)i;
+    if (i < nfi) cfaces[(size_t)(fslots[i] >> 8) * nc + fnei[i]] = ~(int32_t)i;
+  }
+#pragma omp parallel for schedule(dynamic, 64) reduction(max : max_cond) reduction(|| : singular)
+  for (int64_t P = 0; P < nc; ++P) {
+    double X[256 * 3];
+    for (int k = 0; k < S; ++k)
+      for (int d = 0; d < D; ++d) X[k * D + d] = c->cen[(size_t)cst[P * S + k] * D + d];
+    double dvec[6 * 3];
+    int slots[6], nt = 0;
+    for (int s = 0; s < NS; ++s) {
+      int32_t code = cfaces[(size_t)s * nc + P];
+      if (code == kNoFace) continue;
+      int64_t i = code >= 0 ? code : ~code;
+      int64_t f = kf[i];
+      for (int d = 0; d < D; ++d) dvec[nt * D + d] = c->f_centre[(size_t)f * D + d] - c->cen[(size_t)P * D + d];
+      slots[nt++] = s;
+    }
+    if (nt == 0) continue;
+    double out[6 * 256], cond, h;
+    bool ok = ls_functionals(D, p, kshape, &c->cen[(size_t)P * D], X, S, 0.0, kTargetExtrap, nt, dvec, out,
+                             &cond, &h);
+    if (!ok) singular = true;
+    max_cond = std::max(max_cond, cond);
+    for (int r = 0; r < nt; ++r)
+      for (int k = 0; k < S; ++k) cext[((size_t)k * NS + slots[r]) * nc + P] = out[r * S + k];
+  }
+  if (singular) return fail(c, HOFV_ESINGULAR, "rank-deficient least-squares stencil at a cell centroid");
+
+  // body force and traction sources (load 1)
+  if (!c->fb.empty()) {
+#pragma omp parallel for schedule(static)
+    for (int64_t P = 0; P < nc; ++P)
+      for (int j = 0; j < D; ++j) {
+        double s = 0;
+        for (int q = 0; q < c->nqv; ++q)
+          s += c->vq_w[(size_t)P * c->nqv + q] * c->fb[((size_t)P * c->nqv + q) * D + j];
+        src[(size_t)j * nc + P] += s;
+      }
+  }
+  for (int64_t b : trac) {
+    int64_t f = c->bface[b];
+    const hofv_ctx::Face& F = c->faces[f];
+    for (int j = 0; j < D; ++j) {
+      double s = 0;
+      for (int q = 0; q < nq; ++q) s += c->f_qw[(size_t)f * nq + q] * c->tq[((size_t)b * nq + q) * D + j];
+      src[(size_t)j * nc + F.own] += c->f_area[f] * s;
+    }
+  }
+
+  // compact approximate Jacobian: scalar A on every component
+  std::vector<double> diag(nc, 0.0);
+  std::vector<double> offd((size_t)NS * nc, 0.0);
+  std::vector<int64_t> nbr((size_t)NS * nc, -1);
+  for (int64_t i = 0; i < nf; ++i) {
+    const double a = faj[i];  // Kbar Gamma / |d . n|
+    const int64_t P = fown[i];
+    diag[P] -= a;
+    if (i < nfi) {
+      const int64_t N = fnei[i];
+      diag[N] -= a;
+      offd[(size_t)(fslots[i] & 0xff) * nc + P] = a;
+      nbr[(size_t)(fslots[i] & 0xff) * nc + P] = N;
+      offd[(size_t)(fslots[i] >> 8) * nc + N] = a;
+      nbr[(size_t)(fslots[i] >> 8) * nc + N] = P;
+    }
+  }
+  std::vector<int32_t> colour(nc, -1);
+  int ncol = 0;
+  for (int64_t P = 0; P < nc; ++P) {
+    uint64_t used = 0;
+    for (int s = 0; s < NS; ++s) {
+      int64_t N = nbr[(size_t)s * nc + P];
+      if (N >= 0 && colour[N] >= 0 && colour[N] < 64) used |= 1ull << colour[N];
+    }
+    int col = 0;
+    while (used >> col & 1ull) ++col;
+    colour[P] = col;
+    ncol = std::max(ncol, col + 1);
+  }
+  std::vector<int32_t> perm(nc);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return colour[a] < colour[b]; });
+  std::vector<int32_t> pos(nc);
+  for (int64_t i = 0; i < nc; ++i) pos[perm[i]] = (int32_t)i;
+  c->dev.colour_start.assign(ncol + 1, 0);
+  for (int64_t P = 0; P < nc; ++P) c->dev.colour_start[colour[P] + 1]++;
+  // stencils are searched point-major; the kernels read them k-major
+  std::vector<int32_t> fst_k((size_t)S * nf), cst_k((size_t)S * nc);
+  for (int64_t i = 0; i < nf; ++i)
+    for (int k = 0; k < S; ++k) fst_k[(size_t)k * nf + i] = fst[(size_t)i * S + k];
+  for (int64_t P = 0; P < nc; ++P)
+    for (int k = 0; k < S; ++k) cst_k[(size_t)k * nc + P] = cst[(size_t)P * S + k];
+  for (int k = 0; k < ncol; ++k) c->dev.colour_start[k + 1] += c->dev.colour_start[k];
+  c->dev.n_colours = ncol;
+  std::vector<int32_t> pnbr((size_t)NS * nc);
+  std::vector<float> pa((size_t)NS * nc), pdinv(nc);
+  for (int64_t i = 0; i < nc; ++i) {
+    const int64_t P = perm[i];
+    pdinv[i] = (float)(1.0 / diag[P]);
+    for (int s = 0; s < NS; ++s) {
+      int64_t N = nbr[(size_t)s * nc + P];
+      pnbr[(size_t)s * nc + i] = N >= 0 ? pos[N] : (int32_t)i;
+      pa[(size_t)s * nc + i] = N >= 0 ? (float)offd[(size_t)s * nc + P] : 0.0f;
+    }
+  }
+
+  if (c->prm.host_only) {
+    auto keep = [&](const char* name, const auto& v) {
+      hofv_ctx::HostTable& h = c->host_tables[name];
+      h.elem = (int32_t)sizeof(v[0]);
+      h.bytes.resize(v.size() * sizeof(v[0]));
+      if (!v.empty()) std::memcpy(h.bytes.data(), v.data(), h.bytes.size());
+    };
+    keep("face_stencil", fst_k);
+    keep("cell_stencil", cst_k);
+    keep("face_coef", fcoef);
+    keep("cell_extrap", cext);
+    keep("face_own", fown);
+    keep("face_nei", fnei);
+    keep("face_area_vec", fsv);
+    keep("face_stab", fstab);
+    keep("cell_faces", cfaces);
+    keep("cell_src", src);
+    keep("pc_perm", perm);
+    keep("pc_dinv", pdinv);
+    keep("pc_a", pa);
+    keep("pc_nbr", pnbr);
+    keep("centroids", c->cen);
+    keep("face_centre", pts);
+    c->dev.S = S;
+    c->dev.nq = nq;
+    c->dev.nf = nf;
+    c->dev.nfi = nfi;
+  }
+  // byte model (algorithmic HBM bytes per launch; gathers counted once per cell)
+  const double ub = (double)D * 8 * nc;
+  const double face_b = (double)nf * S * (ncoef * 8.0 + 4.0) + (double)nf * (4 * 3 + 8 + 8.0 * (fold ? D : nq * D)) +
+                        (nh ? (double)nq * D * D * 8 * nfd : 0.0) + ub + 2.0 * D * 8 * nf + (double)D * 8 * nf;
+  const double ext_b = (double)nc * S * (NS * 8.0 + 4.0) + ub + (double)NS * D * 8 * nc;
+  const double sum_b = (double)nc * (NS * 4.0 + 2 * D * 8.0) + 2.0 * D * 8 * nf;
+  c->kernel_bytes[nh ? "k_face_nh" : (fold ? "k_face_le" : "k_face_q")] = face_b;
+  c->kernel_bytes["k_extrap"] = ext_b;
+  c->kernel_bytes["k_cell_sum"] = sum_b;
+  c->report.stencil_size = S;
+  c->report.n_colours = ncol;
+  c->report.n_internal_faces = nfi;
+  c->report.n_disp_faces = nfd;
+  c->report.n_trac_faces = (int64_t)trac.size();
+  c->report.max_cond = max_cond;
+  c->report.residual_bytes = face_b + ext_b + sum_b;
+  if (c->prm.host_only) {
+    c->report.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return HOFV_OK;
+  }
+
+  // upload
+  DeviceTables& t = c->dev;
+  t.S = S;
+  t.nq = nq;
+  t.nf = nf;
+  t.nfi = nfi;
+  hofv_status st;
+#define UP(ptr, vec) \
+  if ((st = upload(c, &ptr, vec))) return st;
+  UP(t.f_stencil, fst_k);
+  UP(t.f_coef, fcoef);
+  UP(t.f_own, fown);
+  UP(t.f_nei, fnei);
+  UP(t.f_slots, fslots);
+  UP(t.f_area_vec, fsv);
+  UP(t.f_stab, fstab);
+  if (nh) UP(t.f_ghost, fghost);
+  UP(t.c_stencil, cst_k);
+  UP(t.c_extrap, cext);
+  UP(t.c_faces, cfaces);
+  UP(t.c_src, src);
+  UP(t.p_perm, perm);
+  UP(t.p_nbr, pnbr);
+  UP(t.p_a, pa);
+  UP(t.p_dinv, pdinv);
+#undef UP
+  if ((st = dev_alloc(c, &t.ustar, (size_t)NS * D * nc))) return st;
+  if ((st = dev_alloc(c, &t.flux, (size_t)D * nf))) return st;
+  if ((st = dev_alloc(c, &t.w, (size_t)D * nc))) return st;
+  if ((st = dev_alloc(c, &t.scratch, 16384))) return st;  // >= 32 dot partials x 256 blocks
+  if ((st = dev_alloc(c, &t.eps, 8))) return st;
+  if ((st = dev_alloc(c, &t.flag, 8))) return st;
+  if ((st = dev_alloc(c, &t.p_r, (size_t)D * nc))) return st;
+  if ((st = dev_alloc(c, &t.p_z, (size_t)D * nc))) return st;
+  HOFV_HIP(c, hipMemset(t.flag, 0, 8 * sizeof(int32_t)));
+
+  c->report.device_bytes = (double)c->device_bytes;
+  c->report.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return HOFV_OK;
+}
+
+}  // namespace hofv

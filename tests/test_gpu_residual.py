@@ -1,0 +1,160 @@
+"""GPU parity of R(u) and J.v against the FP64 oracle, through the C ABI.
+
+Tolerances: R to 1e-10 relative (2-norm) on seeded random states, and a
+per-cell scale-aware bound (|dR_P| <= 1e-10 (sum of |face fluxes| + |sources|))
+near the manufactured solution; J.v with the same eps to 1e-6 relative: both
+sides difference two residuals whose constant parts (boundary sources of order
+one) round at eps_mach and are divided by eps ~ 1e-10..1e-8, so the products
+themselves carry ~1e-8 relative noise.
+"""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import jacobian as ojac
+from oracle import residual as ores
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _api():
+    from paper_2601_18417_amd import api
+    return api
+
+
+def to_dev(a):
+    return torch.tensor(np.ascontiguousarray(a.T), device=DEV, dtype=torch.float64)
+
+
+def to_host(t):
+    return t.cpu().numpy().T
+
+
+def _flux_scale(disc, u):
+    Ff, Fd = ores.face_fluxes(disc, u)
+    s = np.zeros((disc.n_cells, disc.dim))
+    np.add.at(s, disc.f_own, np.abs(Ff))
+    np.add.at(s, disc.f_nei, np.abs(Ff))
+    np.add.at(s, disc.d_own, np.abs(Fd))
+    return s + np.abs(disc.b_body + disc.b_trac)
+
+
+CASES = {
+    "square32_p2": lambda: w.square_mms(32, 2),
+    "square12_p3_pert": lambda: w.square_mms(12, 3, perturb=0.2, seed=4),
+    "square9_p1": lambda: w.square_mms(9, 1, perturb=0.15, seed=2),
+    "cube8_p1_pert": lambda: w.cube_mms(8, 1, perturb=0.2, seed=1),
+    "cube8_p2_pert": lambda: w.cube_mms(8, 2, perturb=0.2, seed=2),
+    "cube9_p3_pert": lambda: w.cube_mms(9, 3, perturb=0.2, seed=3),
+    "box_11x7x6_p3": lambda: w.cube_mms((11, 7, 6), 3, perturb=0.2, seed=5, lengths=(1.0, 0.6, 0.5)),
+    "cube7_p2_traction": lambda: w.poly_patch(w.box_mesh((7, 7, 7), perturb=0.2, seed=8), 2, 3, seed=3,
+                                              traction_faces=lambda xc, n: xc[:, 2] > 1 - 1e-9),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("fold", [True, False])
+def test_residual_parity(name, fold):
+    prob = CASES[name]()
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob, fold_quadrature=fold)
+    n, D = disc.n_cells, disc.dim
+    for seed in (11, 12):
+        u = w.random_state(n, D, seed=seed)
+        R = torch.empty((D, n), device=DEV, dtype=torch.float64)
+        ctx.residual(to_dev(u), R)
+        torch.cuda.synchronize()
+        Ro = ores.residual(disc, u)
+        rel = np.linalg.norm(to_host(R) - Ro) / np.linalg.norm(Ro)
+        assert rel <= 1e-10, (name, seed, rel)
+    # near the manufactured solution
+    if prob.loads.exact is not None:
+        u = prob.loads.exact.value(disc.cen)
+        R = torch.empty((D, n), device=DEV, dtype=torch.float64)
+        ctx.residual(to_dev(u), R)
+        torch.cuda.synchronize()
+        Ro = ores.residual(disc, u)
+        bound = 1e-10 * _flux_scale(disc, u)
+        assert np.all(np.abs(to_host(R) - Ro) <= bound), name
+
+
+@pytest.mark.parametrize("name", ["square32_p2", "cube8_p2_pert", "cube9_p3_pert"])
+def test_jvp_parity(name):
+    prob = CASES[name]()
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n, D = disc.n_cells, disc.dim
+    u = w.random_state(n, D, seed=1)
+    v = w.random_state(n, D, seed=2, scale=1.0)
+    ud, vd = to_dev(u), to_dev(v)
+    Ru = torch.empty_like(ud)
+    ctx.residual(ud, Ru)
+    Ro = ores.residual(disc, u)
+    eps = ojac.default_eps(u, v)
+    Jo = ojac.jvp(disc, u, v, Ro, eps)
+    Jv = torch.empty_like(ud)
+    ctx.jvp(ud, Ru, vd, Jv, eps=eps)
+    torch.cuda.synchronize()
+    assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
+    # device-side default eps
+    ctx.jvp(ud, Ru, vd, Jv, eps=0.0)
+    torch.cuda.synchronize()
+    assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
+    # v = 0 gives exactly 0
+    ctx.jvp(ud, Ru, torch.zeros_like(vd), Jv, eps=0.0)
+    torch.cuda.synchronize()
+    assert not torch.any(Jv)
+
+
+def test_load_scale_scales_sources():
+    prob = CASES["cube7_p2_traction"]()
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    u = w.random_state(n, 3, seed=4)
+    R = torch.empty((3, n), device=DEV, dtype=torch.float64)
+    ctx.set_load_scale(0.3)
+    ctx.residual(to_dev(u), R)
+    torch.cuda.synchronize()
+    Ro = ores.residual(disc, u, load=0.3)
+    assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro)
+
+
+def test_residual_is_deterministic():
+    prob = CASES["cube9_p3_pert"]()
+    ctx = _api().context_for(prob)
+    n = prob.mesh.n_cells
+    ud = to_dev(w.random_state(n, 3, seed=9))
+    R1 = torch.empty_like(ud)
+    R2 = torch.empty_like(ud)
+    ctx.residual(ud, R1)
+    ctx.residual(ud, R2)
+    torch.cuda.synchronize()
+    assert torch.equal(R1, R2)
+
+
+def test_neo_hookean_residual_and_jvp_parity():
+    prob = w.cantilever(shape=(12, 5, 5), p=2, tip_traction=0.05)
+    prob.mesh = w.box_mesh((12, 5, 5), lengths=(10.0, 1, 1), perturb=0.15, seed=3)
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    u = w.random_state(n, 3, seed=5, scale=0.05)
+    for load in (1.0, 0.4):
+        ctx.set_load_scale(load)
+        ud = to_dev(u)
+        R = torch.empty_like(ud)
+        ctx.residual(ud, R)
+        torch.cuda.synchronize()
+        Ro = ores.residual(disc, u, load)
+        assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro)
+    v = w.random_state(n, 3, seed=6, scale=1.0)
+    eps = ojac.default_eps(u, v)
+    Jv = torch.empty_like(ud)
+    ctx.jvp(ud, R, to_dev(v), Jv, eps=eps)
+    torch.cuda.synchronize()
+    Jo = ojac.jvp(disc, u, v, Ro, eps, load=0.4)
+    assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
