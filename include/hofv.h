@@ -100,6 +100,10 @@ hofv_status hofv_boundary_faces(hofv_ctx* ctx, int64_t* n_bfaces, int32_t* n_q,
                                 const double** centres, const double** normals,
                                 const double** qpoints);
 
+/* Cell centroids x_P [n_cells][dim] (caller numbering), the points where the
+ * unknowns live (Sec. 3, point-valued finite volume).  Owned by ctx. */
+hofv_status hofv_cell_centroids(hofv_ctx* ctx, const double** centroids);
+
 /* Volume quadrature points of the body-force integral (eq. bodyTerm),
  * [n_cells][n_qv][dim], n_qv = (p+2)^dim Gauss-Legendre points of the cell map. */
 hofv_status hofv_volume_qpoints(hofv_ctx* ctx, int32_t* n_qv, const double** points);

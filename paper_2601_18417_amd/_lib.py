@@ -64,6 +64,7 @@ SIGNATURES = {
     "hofv_set_mesh": (ST, [P, I64, D, I64, C.POINTER(C.c_int64)]),
     "hofv_boundary_faces": (ST, [P, C.POINTER(I64), C.POINTER(C.c_int32), C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
     "hofv_volume_qpoints": (ST, [P, C.POINTER(C.c_int32), C.POINTER(D)]),
+    "hofv_cell_centroids": (ST, [P, C.POINTER(D)]),
     "hofv_set_bc": (ST, [P, C.POINTER(C.c_int32), D, D, D]),
     "hofv_set_body_force": (ST, [P, D]),
     "hofv_setup": (ST, [P, C.POINTER(SetupReport)]),

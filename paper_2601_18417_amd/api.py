@@ -92,6 +92,11 @@ class Context:
         as_np = lambda p, shape: np.ctypeslib.as_array(p, shape=shape).copy() if nb else np.zeros(shape)
         return as_np(cen, (nb, D)), as_np(nor, (nb, D)), as_np(qp, (nb, q, D))
 
+    def cell_centroids(self):
+        pts = C.POINTER(C.c_double)()
+        self._check(self.lib.hofv_cell_centroids(self.h, C.byref(pts)))
+        return np.ctypeslib.as_array(pts, shape=(self.n_cells, self.dim)).copy()
+
     def volume_qpoints(self):
         nqv = C.c_int32()
         pts = C.POINTER(C.c_double)()

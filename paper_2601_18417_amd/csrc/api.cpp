@@ -132,6 +132,14 @@ hofv_status hofv_boundary_faces(hofv_ctx* c, int64_t* n_bfaces, int32_t* n_q, co
   return HOFV_OK;
 }
 
+hofv_status hofv_cell_centroids(hofv_ctx* c, const double** centroids) {
+  hofv_status s = need(c, 1, "cell_centroids");
+  if (s) return s;
+  if (!centroids) return fail(c, HOFV_EINVAL, "null argument");
+  *centroids = c->cen.data();
+  return HOFV_OK;
+}
+
 hofv_status hofv_volume_qpoints(hofv_ctx* c, int32_t* n_qv, const double** points) {
   hofv_status s = need(c, 1, "volume_qpoints");
   if (s) return s;

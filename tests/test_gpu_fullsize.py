@@ -1,0 +1,69 @@
+"""Parity at the benchmark's full size: 64^3 perturbed hex, p = 3, the same
+launch configuration bench.py times.  The oracle evaluates R and J.v on a
+sample of cells one by one (its setup restricted to what those cells need)."""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import jacobian as ojac
+from oracle import residual as ores
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def big():
+    from paper_2601_18417_amd import api
+    prob = w.cube_mms(64, 3, perturb=0.2, seed=0)
+    ctx = api.context_for(prob)
+    n = prob.mesh.n_cells
+    rng = np.random.default_rng(123)
+    ijk = w.cell_ijk(prob.mesh)
+    corner = np.nonzero(np.all((ijk == 0) | (ijk == 63), axis=1))[0][:4]
+    edge = np.nonzero((ijk[:, 0] == 0) & (ijk[:, 1] == 1))[0][:3]
+    sample = np.unique(np.concatenate([rng.choice(n, 40, replace=False), corner, edge]))
+    disc = ores.build(prob, active=sample)
+    return prob, ctx, disc, sample
+
+
+def test_fullsize_residual_and_jvp_sampled(big):
+    prob, ctx, disc, sample = big
+    n = prob.mesh.n_cells
+    u = w.random_state(n, 3, seed=21)
+    v = np.random.default_rng(1000).standard_normal((n, 3))
+    ud = torch.tensor(u.T.copy(), device=DEV)
+    vd = torch.tensor(v.T.copy(), device=DEV)
+    R = torch.empty_like(ud)
+    Jv = torch.empty_like(ud)
+    ctx.residual(ud, R)
+    eps = ojac.default_eps(u, v)
+    ctx.jvp(ud, R, vd, Jv, eps=eps)
+    torch.cuda.synchronize()
+    Rg, Jg = R.cpu().numpy().T, Jv.cpu().numpy().T
+    Ro = ores.residual(disc, u)
+    # J.v at the sampled cells from the oracle's own two residual evaluations
+    Jo = (ores.residual(disc, u + eps * v) - Ro) / eps
+    s = sample
+    assert np.linalg.norm(Rg[s] - Ro[s]) <= 1e-10 * np.linalg.norm(Ro[s])
+    assert np.linalg.norm(Jg[s] - Jo[s]) <= 1e-6 * np.linalg.norm(Jo[s])
+    assert np.all(np.isfinite(Rg)) and np.all(np.isfinite(Jg))
+
+
+def test_fullsize_manufactured_state(big):
+    prob, ctx, disc, sample = big
+    u = prob.loads.exact.value(ctx.cell_centroids())
+    ud = torch.tensor(u.T.copy(), device=DEV)
+    R = torch.empty_like(ud)
+    ctx.residual(ud, R)
+    torch.cuda.synchronize()
+    Rg = R.cpu().numpy().T
+    Ro = ores.residual(disc, u)
+    Ff, Fd = ores.face_fluxes(disc, u)
+    scale = np.zeros_like(Ro)
+    np.add.at(scale, disc.f_own, np.abs(Ff))
+    np.add.at(scale, disc.f_nei, np.abs(Ff))
+    np.add.at(scale, disc.d_own, np.abs(Fd))
+    scale += np.abs(disc.b_body)
+    assert np.all(np.abs(Rg[sample] - Ro[sample]) <= 1e-10 * scale[sample])
