@@ -105,7 +105,7 @@ def main():
     torch.cuda.synchronize()
     t_jvp = time.perf_counter() - t0
     kernels = {}
-    for name in ("k_face_le", "k_extrap", "k_cell_sum", "k_axpy_eps", "k_sumsq2"):
+    for name in ("k_face_le", "k_extrap", "k_cell_sum", "k_pack", "k_sumsq2"):
         ms, cnt = ctx.kernel_time(name)
         if cnt:
             kernels[name] = {"avg_ms": ms / cnt, "launches": cnt}

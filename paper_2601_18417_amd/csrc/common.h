@@ -46,7 +46,7 @@ struct DeviceTables {
   // transient
   double* ustar = nullptr;       // [2D][D][nc]
   double* flux = nullptr;        // [D][nf]
-  double* w = nullptr;           // [D][nc] u + eps v
+  double* w = nullptr;           // [nc][4 | 2] padded gather copy of u (or u + eps v)
   double* scratch = nullptr;     // reduction partials
   double* eps = nullptr;         // device scalar(s)
   int32_t* flag = nullptr;       // device error flags (NH inverted element)

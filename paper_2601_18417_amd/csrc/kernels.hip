@@ -29,12 +29,31 @@ constexpr int kBlock = 256;
 
 inline unsigned blocks_for(int64_t n, int per = kBlock) { return (unsigned)((n + per - 1) / per); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Remap so that XCD x runs one contiguous range of logical blocks: the
+// stencil gathers of a range stay within one L2.  Bijective for any grid.
+__device__ inline int64_t xcd_block() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t x = b % 8, local = b / 8, base = nb / 8, r = nb % 8;
+  return x * base + (x < r ? x : r) + local;
+}
+
+// displacement of cell n from the padded gather copy (4 doubles per cell in
+// 3D, 2 in 2D): one 16-byte and one 8-byte load from one 32-byte segment
+template <int D>
+__device__ inline void load_u(const double* __restrict__ ug, int64_t n, double* un) {
+  const double2 a = *reinterpret_cast<const double2*>(ug + (D == 3 ? 4 : 2) * n);
+  un[0] = a.x;
+  un[1] = a.y;
+  if constexpr (D == 3) un[2] = ug[4 * n + 2];
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_extrap(int64_t nc, int S, const int32_t* __restrict__ st,
                                                     const double* __restrict__ E, const double* __restrict__ u,
                                                     double* __restrict__ ustar) {
   constexpr int NS = 2 * D;
-  const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t P = xcd_block() * kBlock + threadIdx.x;
   if (P >= nc) return;
   double acc[NS][D];
 #pragma unroll
@@ -45,8 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_extrap(int64_t nc, int S, const int3
   for (int k = 0; k < S; ++k) {
     const int32_t n = __builtin_nontemporal_load(&st[(int64_t)k * nc + P]);
     double un[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) un[c] = u[(int64_t)c * nc + n];
+    load_u<D>(u, n, un);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const double e = __builtin_nontemporal_load(&E[((int64_t)k * NS + s) * nc + P]);
@@ -54,12 +72,12 @@ __global__ __launch_bounds__(kBlock) void k_extrap(int64_t nc, int S, const int3
       for (int c = 0; c < D; ++c) acc[s][c] += e * un[c];
     }
   }
+  double uP[D];
+  load_u<D>(u, P, uP);
 #pragma unroll
-  for (int c = 0; c < D; ++c) {
-    const double uP = u[(int64_t)c * nc + P];
+  for (int c = 0; c < D; ++c)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) ustar[((int64_t)s * D + c) * nc + P] = uP + acc[s][c];
-  }
+    for (int s = 0; s < NS; ++s) ustar[((int64_t)s * D + c) * nc + P] = uP[c] + acc[s][c];
 }
 
 // stabilisation part alpha Kbar Gamma/|d.n| (u*_N - u*_P); on displacement
@@ -86,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_face_le(int64_t nf, int64_t nfi, int
                                                      const double* __restrict__ Sv, const double* __restrict__ stab,
                                                      double mu, double lam, const double* __restrict__ u,
                                                      const double* __restrict__ ustar, double* __restrict__ F) {
-  const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t f = xcd_block() * kBlock + threadIdx.x;
   if (f >= nf) return;
   double G[D][D];
 #pragma unroll
@@ -97,8 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_face_le(int64_t nf, int64_t nfi, int
   for (int k = 0; k < S; ++k) {
     const int32_t n = __builtin_nontemporal_load(&st[(int64_t)k * nf + f]);
     double un[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) un[j] = u[(int64_t)j * nc + n];
+    load_u<D>(u, n, un);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const double c = __builtin_nontemporal_load(&C[((int64_t)k * D + i) * nf + f]);
@@ -135,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_face_q(int64_t nf, int64_t nfi, int6
                                                     double lam, const double* __restrict__ u,
                                                     const double* __restrict__ ustar, double* __restrict__ F,
                                                     int32_t* __restrict__ flag) {
-  const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t f = xcd_block() * kBlock + threadIdx.x;
   if (f >= nf) return;
   double G[NQ][D][D];
 #pragma unroll
@@ -147,8 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_face_q(int64_t nf, int64_t nfi, int6
   for (int k = 0; k < S; ++k) {
     const int32_t n = __builtin_nontemporal_load(&st[(int64_t)k * nf + f]);
     double un[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) un[j] = u[(int64_t)j * nc + n];
+    load_u<D>(u, n, un);
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
@@ -328,11 +344,23 @@ __global__ __launch_bounds__(kBlock) void k_set_scalar(double* p, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_axpy_eps(int64_t n, const double* __restrict__ u,
-                                                     const double* __restrict__ v, const double* __restrict__ eps,
-                                                     double* __restrict__ w) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) w[i] = u[i] + eps[0] * v[i];
+// padded gather copy of u (+ eps v when v != null): ug[P][0..D) = u[.][P] + eps v[.][P]
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_pack(int64_t nc, const double* __restrict__ u,
+                                                 const double* __restrict__ v, const double* __restrict__ eps,
+                                                 double* __restrict__ ug) {
+  constexpr int W = D == 3 ? 4 : 2;
+  const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (P >= nc) return;
+  const double e = v ? eps[0] : 0.0;
+  double x[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) x[c] = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) x[c] = v ? u[(int64_t)c * nc + P] + e * v[(int64_t)c * nc + P] : u[(int64_t)c * nc + P];
+  double2* o = reinterpret_cast<double2*>(ug + (int64_t)W * P);
+  o[0] = make_double2(x[0], x[1]);
+  if constexpr (W == 4) o[1] = make_double2(x[2], x[3]);
 }
 
 // ---- FP32 multicolour Gauss-Seidel ----------------------------------------
@@ -409,6 +437,7 @@ void timer_end(hofv_ctx* c, const char* name, hipStream_t st, hipEvent_t ev) {
     timer_end(c, name, st, ev_);         \
   } while (0)
 
+// R(ug) where ug is the padded gather copy (k_pack)
 template <int D>
 static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const double* Ru, const double* eps,
                                  hipStream_t st) {
@@ -456,7 +485,14 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
 
 hofv_status launch_residual(hofv_ctx* c, const double* u, double* R, const double* Ru, const double* eps,
                             hipStream_t st) {
-  return c->D == 2 ? residual_impl<2>(c, u, R, Ru, eps, st) : residual_impl<3>(c, u, R, Ru, eps, st);
+  // Ru == nullptr: R = R(u).  Otherwise u is the packed copy already made by
+  // launch_axpy_w (u + eps v) and R receives (R(u + eps v) - Ru) / eps.
+  if (!Ru) {
+    if (c->D == 2) k_pack<2><<<blocks_for(c->nc), kBlock, 0, st>>>(c->nc, u, nullptr, nullptr, c->dev.w);
+    else k_pack<3><<<blocks_for(c->nc), kBlock, 0, st>>>(c->nc, u, nullptr, nullptr, c->dev.w);
+  }
+  const double* ug = c->dev.w;
+  return c->D == 2 ? residual_impl<2>(c, ug, R, Ru, eps, st) : residual_impl<3>(c, ug, R, Ru, eps, st);
 }
 
 hofv_status launch_eps(hofv_ctx* c, const double* u, const double* v, double eps_host, hipStream_t st) {
@@ -474,8 +510,9 @@ hofv_status launch_eps(hofv_ctx* c, const double* u, const double* v, double eps
 }
 
 hofv_status launch_axpy_w(hofv_ctx* c, const double* u, const double* v, hipStream_t st) {
-  const int64_t n = (int64_t)c->D * c->nc;
-  TIMED("k_axpy_eps", (k_axpy_eps<<<blocks_for(n), kBlock, 0, st>>>(n, u, v, c->dev.eps, c->dev.w)));
+  const int64_t nc = c->nc;
+  if (c->D == 2) TIMED("k_pack", (k_pack<2><<<blocks_for(nc), kBlock, 0, st>>>(nc, u, v, c->dev.eps, c->dev.w)));
+  else TIMED("k_pack", (k_pack<3><<<blocks_for(nc), kBlock, 0, st>>>(nc, u, v, c->dev.eps, c->dev.w)));
   HOFV_HIP(c, hipGetLastError());
   return HOFV_OK;
 }

@@ -36,7 +36,9 @@ hofv_status build_tables(hofv_ctx* c) {
   if (S > nc) return fail(c, HOFV_EINVAL, "stencil size exceeds the number of cells");
   const double kshape = c->prm.k_weight, gw = c->prm.ghost_weight, alpha = c->prm.alpha;
 
-  // kernel faces: internal, then displacement
+  // kernel faces: internal, then displacement, each ordered by (owner slot,
+  // owner) so that a wavefront holds faces of one orientation at consecutive
+  // owners, whose id-sorted stencils are near-shifted copies of each other
   std::vector<int64_t> kf;
   kf.reserve(c->faces.size());
   for (int64_t f = 0; f < c->n_internal; ++f) kf.push_back(f);
@@ -45,6 +47,12 @@ hofv_status build_tables(hofv_ctx* c) {
     if (c->btype[b] == HOFV_BC_DISPLACEMENT) kf.push_back(c->bface[b]);
     else trac.push_back((int64_t)b);
   }
+  auto by_slot = [&](int64_t a, int64_t b) {
+    const hofv_ctx::Face &A = c->faces[a], &B = c->faces[b];
+    return A.sown != B.sown ? A.sown < B.sown : A.own < B.own;
+  };
+  std::sort(kf.begin(), kf.begin() + c->n_internal, by_slot);
+  std::sort(kf.begin() + c->n_internal, kf.end(), by_slot);
   const int64_t nf = (int64_t)kf.size(), nfi = c->n_internal, nfd = nf - nfi;
   std::vector<int64_t> kf_of_face(c->faces.size(), -1);
   std::vector<int64_t> bidx_of_face(c->faces.size(), -1);
@@ -58,6 +66,12 @@ hofv_status build_tables(hofv_ctx* c) {
   std::vector<int32_t> fst((size_t)nf * S), cst((size_t)nc * S);
   nearest_cells(c->cen, D, nc, pts.data(), nf, S, c->prm.stencil_quantum, fst.data());
   nearest_cells(c->cen, D, nc, c->cen.data(), nc, S, c->prm.stencil_quantum, cst.data());
+  // a stencil is a set: store it in increasing cell id so that the k-th
+  // gathers of neighbouring items fall on neighbouring cells
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < nf; ++i) std::sort(&fst[(size_t)i * S], &fst[(size_t)i * S] + S);
+#pragma omp parallel for schedule(static)
+  for (int64_t P = 0; P < nc; ++P) std::sort(&cst[(size_t)P * S], &cst[(size_t)P * S] + S);
 
   // face coefficients
   const int ncoef = fold ? D : nq * D;
@@ -330,7 +344,7 @@ hofv_status build_tables(hofv_ctx* c) {
 #undef UP
   if ((st = dev_alloc(c, &t.ustar, (size_t)NS * D * nc))) return st;
   if ((st = dev_alloc(c, &t.flux, (size_t)D * nf))) return st;
-  if ((st = dev_alloc(c, &t.w, (size_t)D * nc))) return st;
+  if ((st = dev_alloc(c, &t.w, (size_t)(D == 3 ? 4 : 2) * nc))) return st;  // padded gather copy
   if ((st = dev_alloc(c, &t.scratch, 16384))) return st;  // >= 32 dot partials x 256 blocks
   if ((st = dev_alloc(c, &t.eps, 8))) return st;
   if ((st = dev_alloc(c, &t.flag, 8))) return st;
