@@ -201,6 +201,55 @@ typedef struct {
 hofv_status hofv_newton_solve(hofv_ctx* ctx, double* d_u, const hofv_newton_opts* opts,
                               hofv_newton_stats* stats, void* stream);
 
+/* ---- learned correction of the preconditioner -------------------------------
+ * A message-passing network over face neighbours (not part of the paper):
+ * z = z_AJ + s_z g(x), x_P = [r_P/s_r, z_AJ,P/s_z, displacement-face flag, 1],
+ * s = RMS values, encoder 8->64, 4 layers h += relu([h, A0..A3] W_l + b_l)
+ * with A0 = sum_N omega_PN h_N, Ad = sum_N omega_PN e_PN,d h_N (omega from the
+ * compact Jacobian's face couplings, e the unit centroid-to-centroid vector),
+ * decoder 64->3.  BF16 weights/activations with FP32 accumulation on MFMA;
+ * FP32 master weights and Adam state.  A model lives on the device that was
+ * current at hofv_nn_create and may be attached to any context there. */
+typedef struct hofv_nn hofv_nn;
+
+/* Number of FP32 parameters; flat layout We[8][64], be[64], then per layer
+ * W[320][64], b[64], then Wd[64][3], bd[3]. */
+int64_t hofv_nn_param_count(void);
+
+/* New model: He-initialised hidden layers, zero decoder (so that the
+ * corrected preconditioner starts equal to the plain one), zero Adam state. */
+hofv_status hofv_nn_create(uint64_t seed, hofv_nn** out);
+hofv_status hofv_nn_destroy(hofv_nn* nn);
+
+/* Copy the FP32 parameters from/to host memory (n = hofv_nn_param_count()).
+ * set_params also resets the Adam state.  Synchronises. */
+hofv_status hofv_nn_set_params(hofv_nn* nn, const float* host, int64_t n);
+hofv_status hofv_nn_get_params(hofv_nn* nn, float* host, int64_t n);
+
+/* Attach (nn != NULL) or detach the model used by hofv_precond_apply with
+ * learned != 0 and by the solvers' learned option.  The caller keeps
+ * ownership and must keep it alive while attached. */
+hofv_status hofv_nn_attach(hofv_ctx* ctx, hofv_nn* nn);
+
+/* One optimisation step on n_pairs (residual, correction) pairs of ctx's mesh:
+ * d_r, d_e hold n_pairs device vectors [n_pairs][dim][n_cells] FP64.  For each
+ * pair z_AJ = plain preconditioner(r) with n_sweeps sweeps, loss
+ * ||z - e||^2 / ||e||^2; gradients are averaged over the pairs and Adam
+ * (beta 0.9, 0.999, eps 1e-8, step lr) updates the model.  *loss receives the
+ * mean loss before the step.  Synchronises. */
+hofv_status hofv_nn_train_step(hofv_ctx* ctx, hofv_nn* nn, const double* d_r, const double* d_e,
+                               int32_t n_pairs, int32_t n_sweeps, double lr, double* loss, void* stream);
+
+/* Loss and gradient of one pair with an explicit z_AJ (device [dim][n_cells]);
+ * host_grad receives hofv_nn_param_count() floats.  Does not update the model.
+ * Synchronises. */
+hofv_status hofv_nn_gradient(hofv_ctx* ctx, hofv_nn* nn, const double* d_r, const double* d_zaj,
+                             const double* d_e, float* host_grad, double* loss, void* stream);
+
+/* Corrected preconditioner output for an explicit z_AJ: d_z = z_AJ + s_z g. */
+hofv_status hofv_nn_forward(hofv_ctx* ctx, hofv_nn* nn, const double* d_r, const double* d_zaj, double* d_z,
+                            void* stream);
+
 /* Per-kernel timing with HIP events recorded on the launch stream around
  * every kernel while enabled.  hofv_kernel_time synchronises and returns the
  * summed milliseconds and launch count of the kernel called `name` since the

@@ -17,8 +17,9 @@ compact preconditioner's output).  Definition:
 * loss of a pair (r, e): ||z + s_z g - e||^2 / ||e||^2 (s_z, s_r not differentiated).
 
 ``bf16=True`` rounds to bfloat16 (round to nearest even) where the GPU kernels
-store or feed bfloat16: the inputs x, every weight matrix, h after each layer
-and the aggregates A before the product.
+store or feed bfloat16: the inputs x, every weight matrix, h after each layer,
+the aggregates A before the product, and in the backward pass the relu'd
+gradient dY before its two products.
 """
 from __future__ import annotations
 
@@ -158,9 +159,9 @@ def loss_and_grad(params, r, z, e, g_nbr, g_om, g_dirs, bflag, bf16=False):
     dh = dg @ rnd(params["Wd"]).T
     for l in range(N_LAYERS - 1, -1, -1):
         dY = dh * (a["pre"][l] > 0)
-        grads[f"W{l}"] = a["X"][l].T @ dY
+        grads[f"W{l}"] = a["X"][l].T @ rnd(dY)
         grads[f"b{l}"] = dY.sum(axis=0)
-        dX = dY @ rnd(params[f"W{l}"]).T
+        dX = rnd(dY) @ rnd(params[f"W{l}"]).T
         dA = dX[:, WIDTH:].reshape(n, 4, WIDTH)
         dh = dh + dX[:, :WIDTH] + aggregate_t(dA, g_nbr, g_om, g_dirs)
     dpre0 = dh * (a["pre0"] > 0)

@@ -77,6 +77,15 @@ SIGNATURES = {
     "hofv_set_timing": (ST, [P, C.c_int32]),
     "hofv_kernel_time": (ST, [P, C.c_char_p, D, C.POINTER(C.c_int64)]),
     "hofv_kernel_bytes": (ST, [P, C.c_char_p, D]),
+    "hofv_nn_param_count": (C.c_int64, []),
+    "hofv_nn_create": (ST, [C.c_uint64, C.POINTER(P)]),
+    "hofv_nn_destroy": (ST, [P]),
+    "hofv_nn_set_params": (ST, [P, C.POINTER(C.c_float), C.c_int64]),
+    "hofv_nn_get_params": (ST, [P, C.POINTER(C.c_float), C.c_int64]),
+    "hofv_nn_attach": (ST, [P, P]),
+    "hofv_nn_train_step": (ST, [P, P, P, P, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_double), P]),
+    "hofv_nn_gradient": (ST, [P, P, P, P, P, C.POINTER(C.c_float), C.POINTER(C.c_double), P]),
+    "hofv_nn_forward": (ST, [P, P, P, P, P, P]),
     "hofv_host_table": (ST, [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(P)]),
 }
 

@@ -162,7 +162,7 @@ class Context:
         dtype = {("face_coef", 8): np.float64}.get((name, eb.value))
         if dtype is None:
             dtype = {4: np.int32, 8: np.float64}[eb.value]
-            if name in ("pc_dinv", "pc_a"):
+            if name in ("pc_dinv", "pc_a", "nn_wf", "nn_wb", "nn_bflag"):
                 dtype = np.float32
         buf = (C.c_char * (n.value * eb.value)).from_address(data.value) if n.value else b""
         return np.frombuffer(bytes(buf), dtype=dtype).copy()
@@ -181,6 +181,73 @@ class Context:
         b = C.c_double()
         self._check(self.lib.hofv_kernel_bytes(self.h, name.encode(), C.byref(b)))
         return b.value
+
+
+class Model:
+    """The learned preconditioner correction (hofv_nn) on the current device."""
+
+    def __init__(self, seed=0):
+        self.lib = L.load()
+        h = C.c_void_p()
+        st = self.lib.hofv_nn_create(C.c_uint64(seed), C.byref(h))
+        if st != L.HOFV_OK:
+            raise HofvError(st, self.lib.hofv_last_error(None).decode())
+        self.h = h
+        self.n_params = int(self.lib.hofv_nn_param_count())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hofv_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.empty(self.n_params, np.float32)
+        st = self.lib.hofv_nn_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float)), self.n_params)
+        if st != L.HOFV_OK:
+            raise HofvError(st, self.lib.hofv_last_error(None).decode())
+        return out
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, np.float32)
+        st = self.lib.hofv_nn_set_params(self.h, flat.ctypes.data_as(C.POINTER(C.c_float)), flat.size)
+        if st != L.HOFV_OK:
+            raise HofvError(st, self.lib.hofv_last_error(None).decode())
+
+
+def _ctx_nn_methods():
+    def attach(self, model):
+        self._check(self.lib.hofv_nn_attach(self.h, model.h if model is not None else None))
+        self._model = model
+
+    def nn_train_step(self, model, r, e, n_sweeps=2, lr=1e-3, stream=None):
+        """r, e: device tensors [n_pairs, dim, n_cells] float64."""
+        loss = C.c_double()
+        self._check(self.lib.hofv_nn_train_step(self.h, model.h, _ptr(r), _ptr(e), int(r.shape[0]), int(n_sweeps),
+                                                float(lr), C.byref(loss), _stream(stream)))
+        return loss.value
+
+    def nn_gradient(self, model, r, zaj, e, stream=None):
+        g = np.empty(model.n_params, np.float32)
+        loss = C.c_double()
+        self._check(self.lib.hofv_nn_gradient(self.h, model.h, _ptr(r), _ptr(zaj), _ptr(e),
+                                              g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss),
+                                              _stream(stream)))
+        return loss.value, g
+
+    def nn_forward(self, model, r, zaj, z, stream=None):
+        self._check(self.lib.hofv_nn_forward(self.h, model.h, _ptr(r), _ptr(zaj), _ptr(z), _stream(stream)))
+
+    for f in (attach, nn_train_step, nn_gradient, nn_forward):
+        setattr(Context, f.__name__, f)
+
+
+_ctx_nn_methods()
 
 
 def context_for(problem, fold_quadrature=True, host_only=False):

@@ -3,8 +3,10 @@
 
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "common.h"
 
@@ -32,8 +34,13 @@ hofv_status jvp_impl(hofv_ctx* c, const double* u, const double* Ru, const doubl
 }
 
 hofv_status precond_dispatch(hofv_ctx* c, const double* r, double* z, int sweeps, int learned, hipStream_t st) {
-  (void)learned;
-  return launch_precond(c, r, z, sweeps, st);
+  if (!learned || !c->nn) return launch_precond(c, r, z, sweeps, st);
+  hofv_status s;
+  if (!c->nnw.zaj) {
+    if ((s = dev_alloc(c, &c->nnw.zaj, (size_t)c->D * c->nc))) return s;
+  }
+  if ((s = launch_precond(c, r, c->nnw.zaj, sweeps, st))) return s;
+  return nn_apply(c, c->nn, r, c->nnw.zaj, z, st);
 }
 
 static hofv_status need(hofv_ctx* c, int state, const char* what) {
@@ -269,6 +276,151 @@ hofv_status hofv_host_table(hofv_ctx* c, const char* name, int64_t* count, int32
   if (elem_bytes) *elem_bytes = it->second.elem;
   if (data) *data = it->second.bytes.data();
   return HOFV_OK;
+}
+
+int64_t hofv_nn_param_count(void) { return kNnParams; }
+
+hofv_status hofv_nn_create(uint64_t seed, hofv_nn** out) {
+  if (!out) return fail(nullptr, HOFV_EINVAL, "out is NULL");
+  *out = nullptr;
+  hofv_nn* m = new (std::nothrow) hofv_nn();
+  if (!m) return fail(nullptr, HOFV_ENOMEM, "out of host memory");
+  if (hipGetDevice(&m->device) != hipSuccess) {
+    delete m;
+    return fail(nullptr, HOFV_EHIP, "no HIP device");
+  }
+  if (nn_alloc_model(m) != HOFV_OK) {
+    nn_free_model(m);
+    delete m;
+    return fail(nullptr, HOFV_ENOMEM, "device allocation of the model failed");
+  }
+  // He initialisation (splitmix64 + Box-Muller), zero biases and decoder
+  std::vector<float> p(kNnParams, 0.f);
+  uint64_t st = seed ^ 0x9E3779B97F4A7C15ull;
+  auto next = [&]() {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return (double)((z ^ (z >> 31)) >> 11) * (1.0 / 9007199254740992.0);
+  };
+  auto normal = [&]() {
+    double u1 = next(), u2 = next();
+    if (u1 < 1e-300) u1 = 1e-300;
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+  };
+  for (int64_t i = 0; i < kNnIn * kNnWidth; ++i) p[kNnOffWe + i] = (float)(normal() * std::sqrt(2.0 / kNnIn));
+  for (int l = 0; l < kNnLayers; ++l)
+    for (int64_t i = 0; i < kNnLayerK * kNnWidth; ++i)
+      p[kNnOffW(l) + i] = (float)(normal() * std::sqrt(2.0 / kNnLayerK) * 0.5);
+  hofv_status s = hofv_nn_set_params(m, p.data(), kNnParams);
+  if (s) {
+    nn_free_model(m);
+    delete m;
+    return s;
+  }
+  *out = m;
+  return HOFV_OK;
+}
+
+hofv_status hofv_nn_destroy(hofv_nn* m) {
+  if (!m) return HOFV_OK;
+  hipSetDevice(m->device);
+  hipDeviceSynchronize();
+  nn_free_model(m);
+  delete m;
+  return HOFV_OK;
+}
+
+hofv_status hofv_nn_set_params(hofv_nn* m, const float* host, int64_t n) {
+  if (!m || !host || n != kNnParams) return fail(nullptr, HOFV_EINVAL, "bad model or parameter count");
+  if (hipSetDevice(m->device) != hipSuccess) return fail(nullptr, HOFV_EHIP, "hipSetDevice");
+  if (hipMemcpy(m->p, host, kNnParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(m->m, 0, kNnParams * 4) != hipSuccess || hipMemset(m->v, 0, kNnParams * 4) != hipSuccess ||
+      hipMemset(m->g, 0, kNnParams * 4) != hipSuccess)
+    return fail(nullptr, HOFV_EHIP, "parameter upload failed");
+  m->step = 0;
+  if (nn_refresh(m, nullptr) != HOFV_OK || hipDeviceSynchronize() != hipSuccess)
+    return fail(nullptr, HOFV_EHIP, "parameter refresh failed");
+  return HOFV_OK;
+}
+
+hofv_status hofv_nn_get_params(hofv_nn* m, float* host, int64_t n) {
+  if (!m || !host || n != kNnParams) return fail(nullptr, HOFV_EINVAL, "bad model or parameter count");
+  if (hipSetDevice(m->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(host, m->p, kNnParams * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(nullptr, HOFV_EHIP, "parameter download failed");
+  return HOFV_OK;
+}
+
+hofv_status hofv_nn_attach(hofv_ctx* c, hofv_nn* m) {
+  hofv_status s = need(c, 4, "nn_attach");
+  if (s) return s;
+  if (m && m->device != c->device) return fail(c, HOFV_EINVAL, "model and context are on different devices");
+  c->nn = m;
+  return HOFV_OK;
+}
+
+hofv_status hofv_nn_train_step(hofv_ctx* c, hofv_nn* m, const double* d_r, const double* d_e, int32_t n_pairs,
+                               int32_t n_sweeps, double lr, double* loss, void* stream) {
+  hofv_status s = need(c, 4, "nn_train_step");
+  if (s) return s;
+  if (!m || !d_r || !d_e || n_pairs < 1 || n_sweeps < 1 || !(lr >= 0)) return fail(c, HOFV_EINVAL, "bad argument");
+  if (m->device != c->device) return fail(c, HOFV_EINVAL, "model and context are on different devices");
+  if ((s = set_device(c))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (!c->nnw.zaj) {
+    if ((s = dev_alloc(c, &c->nnw.zaj, (size_t)c->D * c->nc))) return s;
+  }
+  double* loss_dev;
+  if ((s = dev_alloc(c, &loss_dev, 1))) return s;
+  if (nn_zero_grad(m, st) || nn_zero_scalar(loss_dev, st)) return fail(c, HOFV_EHIP, "zeroing failed");
+  const size_t len = (size_t)c->D * c->nc;
+  for (int i = 0; i < n_pairs; ++i) {
+    if ((s = launch_precond(c, d_r + i * len, c->nnw.zaj, n_sweeps, st))) return s;
+    if ((s = nn_grad(c, m, d_r + i * len, c->nnw.zaj, d_e + i * len, 1.0f / n_pairs, loss_dev, st))) return s;
+  }
+  double l = 0;
+  HOFV_HIP(c, hipMemcpyAsync(&l, loss_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+  if (nn_adam(m, lr, st)) return fail(c, HOFV_EHIP, "Adam step failed");
+  HOFV_HIP(c, hipStreamSynchronize(st));
+  hipFree(loss_dev);
+  c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), (void*)loss_dev), c->allocations.end());
+  c->device_bytes -= sizeof(double);
+  if (loss) *loss = l / n_pairs;
+  if (!std::isfinite(l)) return fail(c, HOFV_ENAN, "non-finite training loss");
+  return HOFV_OK;
+}
+
+hofv_status hofv_nn_gradient(hofv_ctx* c, hofv_nn* m, const double* d_r, const double* d_zaj, const double* d_e,
+                             float* host_grad, double* loss, void* stream) {
+  hofv_status s = need(c, 4, "nn_gradient");
+  if (s) return s;
+  if (!m || !d_r || !d_zaj || !d_e || !host_grad) return fail(c, HOFV_EINVAL, "bad argument");
+  if ((s = set_device(c))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  double* loss_dev;
+  if ((s = dev_alloc(c, &loss_dev, 1))) return s;
+  if (nn_zero_grad(m, st) || nn_zero_scalar(loss_dev, st)) return fail(c, HOFV_EHIP, "zeroing failed");
+  if ((s = nn_grad(c, m, d_r, d_zaj, d_e, 1.0f, loss_dev, st))) return s;
+  double l = 0;
+  HOFV_HIP(c, hipMemcpyAsync(&l, loss_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+  HOFV_HIP(c, hipMemcpyAsync(host_grad, m->g, kNnParams * 4, hipMemcpyDeviceToHost, st));
+  HOFV_HIP(c, hipStreamSynchronize(st));
+  hipFree(loss_dev);
+  c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), (void*)loss_dev), c->allocations.end());
+  c->device_bytes -= sizeof(double);
+  if (loss) *loss = l;
+  return HOFV_OK;
+}
+
+hofv_status hofv_nn_forward(hofv_ctx* c, hofv_nn* m, const double* d_r, const double* d_zaj, double* d_z,
+                            void* stream) {
+  hofv_status s = need(c, 4, "nn_forward");
+  if (s) return s;
+  if (!m || !d_r || !d_zaj || !d_z) return fail(c, HOFV_EINVAL, "bad argument");
+  if ((s = set_device(c))) return s;
+  return nn_apply(c, m, d_r, d_zaj, d_z, (hipStream_t)stream);
 }
 
 hofv_status hofv_set_timing(hofv_ctx* c, int32_t enable) {

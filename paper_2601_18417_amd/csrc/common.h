@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "hofv.h"
+#include "mpnn.h"
 
 namespace hofv {
 
@@ -59,6 +60,11 @@ struct DeviceTables {
   float* p_dinv = nullptr;       // [nc] 1 / A_PP
   float* p_r = nullptr;          // [D][nc]
   float* p_z = nullptr;          // [D][nc]
+  // face-neighbour graph of the learned correction
+  int32_t* g_nbr = nullptr;      // [2D][nc] neighbour or -1
+  float* g_wf = nullptr;         // [2D][4][nc] omega_PN (e_PN,d omega_PN for d = 1..3)
+  float* g_wb = nullptr;         // [2D][4][nc] weight of h_P in the aggregate of neighbour s
+  float* g_bflag = nullptr;      // [nc] 1 if the cell has a displacement face
 };
 
 struct Krylov {
@@ -110,6 +116,8 @@ struct hofv_ctx {
   hofv_setup_report report{};
   hofv::DeviceTables dev;
   hofv::Krylov kry;
+  hofv::NnWork nnw;
+  hofv_nn* nn = nullptr;  // attached learned correction (not owned)
   std::vector<void*> allocations;
   size_t device_bytes = 0;
 

@@ -247,6 +247,40 @@ hofv_status build_tables(hofv_ctx* c) {
   for (int64_t i = 0; i < nc; ++i) pos[perm[i]] = (int32_t)i;
   c->dev.colour_start.assign(ncol + 1, 0);
   for (int64_t P = 0; P < nc; ++P) c->dev.colour_start[colour[P] + 1]++;
+  // face-neighbour graph of the learned correction: omega_PN = a_PN / sum a,
+  // e_PN = unit vector from x_P to x_N; wb holds, for the neighbour N in slot
+  // s of P, the weights with which h_P enters N's aggregates
+  std::vector<int32_t> gnbr((size_t)NS * nc, -1);
+  std::vector<float> gwf((size_t)NS * 4 * nc, 0.f), gwb((size_t)NS * 4 * nc, 0.f), gbf(nc, 0.f);
+  for (int64_t i = nfi; i < nf; ++i) gbf[fown[i]] = 1.f;
+  for (int64_t P = 0; P < nc; ++P) {
+    double asum = 0;
+    for (int s = 0; s < NS; ++s)
+      if (nbr[(size_t)s * nc + P] >= 0) asum += offd[(size_t)s * nc + P];
+    for (int s = 0; s < NS; ++s) {
+      const int64_t N = nbr[(size_t)s * nc + P];
+      if (N < 0) continue;
+      gnbr[(size_t)s * nc + P] = (int32_t)N;
+      const double om = offd[(size_t)s * nc + P] / asum;
+      double dv[3] = {0, 0, 0}, len = 0;
+      for (int d = 0; d < D; ++d) {
+        dv[d] = c->cen[(size_t)N * D + d] - c->cen[(size_t)P * D + d];
+        len += dv[d] * dv[d];
+      }
+      len = std::sqrt(len);
+      gwf[((size_t)s * 4 + 0) * nc + P] = (float)om;
+      for (int d = 0; d < 3; ++d) gwf[((size_t)s * 4 + 1 + d) * nc + P] = (float)(om * dv[d] / len);
+    }
+  }
+  for (int64_t P = 0; P < nc; ++P)
+    for (int s = 0; s < NS; ++s) {
+      const int64_t N = nbr[(size_t)s * nc + P];
+      if (N < 0) continue;
+      for (int s2 = 0; s2 < NS; ++s2)
+        if (nbr[(size_t)s2 * nc + N] == P)
+          for (int d = 0; d < 4; ++d) gwb[((size_t)s * 4 + d) * nc + P] = gwf[((size_t)s2 * 4 + d) * nc + N];
+    }
+
   // stencils are searched point-major; the kernels read them k-major
   std::vector<int32_t> fst_k((size_t)S * nf), cst_k((size_t)S * nc);
   for (int64_t i = 0; i < nf; ++i)
@@ -290,6 +324,10 @@ hofv_status build_tables(hofv_ctx* c) {
     keep("pc_nbr", pnbr);
     keep("centroids", c->cen);
     keep("face_centre", pts);
+    keep("nn_nbr", gnbr);
+    keep("nn_wf", gwf);
+    keep("nn_wb", gwb);
+    keep("nn_bflag", gbf);
     c->dev.S = S;
     c->dev.nq = nq;
     c->dev.nf = nf;
@@ -341,6 +379,10 @@ hofv_status build_tables(hofv_ctx* c) {
   UP(t.p_nbr, pnbr);
   UP(t.p_a, pa);
   UP(t.p_dinv, pdinv);
+  UP(t.g_nbr, gnbr);
+  UP(t.g_wf, gwf);
+  UP(t.g_wb, gwb);
+  UP(t.g_bflag, gbf);
 #undef UP
   if ((st = dev_alloc(c, &t.ustar, (size_t)NS * D * nc))) return st;
   if ((st = dev_alloc(c, &t.flux, (size_t)D * nf))) return st;

@@ -147,3 +147,26 @@ def test_library_exports_every_declared_symbol(repo_root):
     assert not missing, missing
     assert {"hofv_residual", "hofv_jvp", "hofv_precond_apply", "hofv_fgmres_solve",
             "hofv_newton_solve", "hofv_setup"} <= names
+
+
+def test_learned_graph_tables_match_oracle():
+    from oracle import mpnn
+    prob = w.cube_mms(5, 1, perturb=0.2, seed=4)
+    disc = ores.build(prob)
+    nbr, om, dirs, bflag = mpnn.graph(disc)
+    ctx = api.context_for(prob, host_only=True)
+    n = disc.n_cells
+    gn = ctx.host_table("nn_nbr").reshape(6, n)
+    wf = ctx.host_table("nn_wf").reshape(6, 4, n)
+    wb = ctx.host_table("nn_wb").reshape(6, 4, n)
+    assert np.array_equal(ctx.host_table("nn_bflag"), bflag.astype(np.float32))
+    for P in range(n):
+        lib = {int(gn[s, P]): (wf[s, :, P], wb[s, :, P]) for s in range(6) if gn[s, P] >= 0}
+        ora = {int(nbr[P, k]): k for k in range(6) if nbr[P, k] >= 0}
+        assert set(lib) == set(ora)
+        for N, k in ora.items():
+            ref = np.concatenate([[om[P, k]], om[P, k] * dirs[P, k]])
+            assert np.allclose(lib[N][0], ref, rtol=1e-6, atol=1e-7)
+            back = [kk for kk in range(6) if nbr[N, kk] == P][0]
+            refb = np.concatenate([[om[N, back]], om[N, back] * dirs[N, back]])
+            assert np.allclose(lib[N][1], refb, rtol=1e-6, atol=1e-7)
