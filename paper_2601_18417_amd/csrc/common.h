@@ -62,8 +62,8 @@ struct DeviceTables {
   float* p_z = nullptr;          // [D][nc]
   // face-neighbour graph of the learned correction
   int32_t* g_nbr = nullptr;      // [2D][nc] neighbour or -1
-  float* g_wf = nullptr;         // [2D][4][nc] omega_PN (e_PN,d omega_PN for d = 1..3)
-  float* g_wb = nullptr;         // [2D][4][nc] weight of h_P in the aggregate of neighbour s
+  float* g_wf = nullptr;         // [2D][nc][4] omega_PN, omega_PN e_PN,d (d = 1..3)
+  float* g_wb = nullptr;         // [2D][nc][4] weights of h_P in the aggregates of neighbour s
   float* g_bflag = nullptr;      // [nc] 1 if the cell has a displacement face
 };
 

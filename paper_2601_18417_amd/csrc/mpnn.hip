@@ -73,96 +73,140 @@ __global__ __launch_bounds__(kB) void k_nn_features(int64_t nc, const double* __
 __global__ __launch_bounds__(kB) void k_nn_encoder(int64_t nc, const unsigned short* __restrict__ x,
                                                    const unsigned short* __restrict__ We /*[8][64] bf16*/,
                                                    const float* __restrict__ be, unsigned short* __restrict__ h) {
-  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (t >= nc * kW) return;
-  const int64_t P = t / kW;
-  const int c = (int)(t % kW);
-  float s = be[c];
+  __shared__ float sWe[8 * kW + kW];
+  for (int i = threadIdx.x; i < 8 * kW; i += kB) sWe[i] = bf2f(We[i]);
+  for (int i = threadIdx.x; i < kW; i += kB) sWe[8 * kW + i] = be[i];
+  __syncthreads();
+  const int64_t P = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (P >= nc) return;
+  const us8 xv = *reinterpret_cast<const us8*>(x + P * 8);
+  float xf[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) s += bf2f(x[P * 8 + j]) * bf2f(We[j * kW + c]);
-  h[t] = f2bf(fmaxf(s, 0.0f));
+  for (int j = 0; j < 8; ++j) xf[j] = bf2f(xv[j]);
+#pragma unroll
+  for (int c8 = 0; c8 < kW / 8; ++c8) {
+    us8 o;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int c = 8 * c8 + q;
+      float s = sWe[8 * kW + c];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s += xf[j] * sWe[j * kW + c];
+      o[q] = f2bf(fmaxf(s, 0.0f));
+    }
+    *reinterpret_cast<us8*>(h + P * kW + 8 * c8) = o;
+  }
 }
 
 // ---- message-passing layer, forward -----------------------------------------
-// One wavefront = 16 cells; lane i: row i%16, k-octet i/16.  The aggregates
-// for the lane's cell are gathered in registers and rounded to BF16 as A
-// operands; W is read from its transposed BF16 copy Wt[64][320].
-__global__ __launch_bounds__(kB) void k_nn_layer(int64_t nc, const unsigned short* __restrict__ h,
-                                                 const int32_t* __restrict__ nbr /*[2D][nc]*/,
-                                                 const float* __restrict__ wf /*[2D][4][nc]*/, int NS,
-                                                 const unsigned short* __restrict__ Wt /*[64][320]*/,
-                                                 const float* __restrict__ b, unsigned short* __restrict__ hout,
-                                                 unsigned short* __restrict__ Yout, unsigned short* __restrict__ Xout) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 16;
-  const int row = lane & 15, oct = lane >> 4;
-  const int64_t P = base + row;
-  const bool live = P < nc;
-  f4 acc[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = (f4){0.f, 0.f, 0.f, 0.f};
-  auto mfma_step = [&](int step, const us8& a) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int n = 16 * t + row;
-      const us8 bw = *reinterpret_cast<const us8*>(Wt + (int64_t)n * kK + 32 * step + 8 * oct);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), as_bf8(bw), acc[t], 0, 0, 0);
-    }
-  };
-  // self part: k in [0, 64)
-#pragma unroll
-  for (int kb = 0; kb < 2; ++kb) {
-    us8 a = (us8){0, 0, 0, 0, 0, 0, 0, 0};
-    if (live) a = *reinterpret_cast<const us8*>(h + P * kW + 32 * kb + 8 * oct);
-    if (Xout && live) *reinterpret_cast<us8*>(Xout + P * kK + 32 * kb + 8 * oct) = a;
-    mfma_step(kb, a);
+// A block stages the layer's transposed BF16 weights Wt[64][320] in LDS once
+// (rows padded to 328 entries against bank conflicts); its 8 wavefronts then
+// run kNnTiles tiles of 16 cells each.  The product is computed transposed,
+// Y^T = W^T X^T: the A operand is a 16-channel slice of Wt (from LDS) and the
+// B operand the 16 cells' X (lane i: cell i%16, k-octet i/16), built from h
+// and from aggregates gathered in registers and rounded to BF16.  The
+// accumulator of lane i then holds channels 16 t + 4 (i/16) + j of cell i%16,
+// so the epilogue moves 4 consecutive channels (8 bytes) per load/store.
+constexpr int kNnTiles = 2;
+constexpr int kWtPad = kK + 8;
+constexpr int kLayerThreads = 512;
+constexpr int kLayerWaves = kLayerThreads / 64;
+constexpr int kLayerCells = kLayerWaves * 16 * kNnTiles;  // cells per block
+
+typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kLayerThreads) void k_nn_layer(
+    int64_t nc, const unsigned short* __restrict__ h, const int32_t* __restrict__ nbr /*[2D][nc]*/,
+    const float4* __restrict__ wf /*[2D][nc]*/, int NS, const unsigned short* __restrict__ Wt /*[64][320]*/,
+    const float* __restrict__ b, unsigned short* __restrict__ hout, unsigned short* __restrict__ Yout,
+    unsigned short* __restrict__ Xout) {
+  __shared__ __align__(16) unsigned short sW[kW * kWtPad];
+  for (int i = threadIdx.x; i < kW * kK / 8; i += kLayerThreads) {
+    const int n = i / (kK / 8), k8 = i % (kK / 8);
+    *reinterpret_cast<us8*>(sW + n * kWtPad + 8 * k8) = *reinterpret_cast<const us8*>(Wt + (int64_t)n * kK + 8 * k8);
   }
-  // aggregates: k in [64 (1 + d), 64 (2 + d))
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, oct = lane >> 4;
+  float4 bc[4];
 #pragma unroll
-  for (int kb = 0; kb < 2; ++kb) {
-    float ag[4][8];
+  for (int t = 0; t < 4; ++t) bc[t] = *reinterpret_cast<const float4*>(b + 16 * t + 4 * oct);
+  for (int tile = 0; tile < kNnTiles; ++tile) {
+    const int64_t base = (int64_t)blockIdx.x * kLayerCells + (tile * kLayerWaves + wave) * 16;
+    if (base >= nc) break;
+    const int64_t P = base + row;
+    const bool live = P < nc;
+    f4 acc[4];
 #pragma unroll
-    for (int d = 0; d < 4; ++d)
+    for (int t = 0; t < 4; ++t) acc[t] = (f4){0.f, 0.f, 0.f, 0.f};
+    auto mfma_step = [&](int step, const us8& xk) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) ag[d][j] = 0.0f;
+      for (int t = 0; t < 4; ++t) {
+        const us8 wk = *reinterpret_cast<const us8*>(sW + (16 * t + row) * kWtPad + 32 * step + 8 * oct);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(wk), as_bf8(xk), acc[t], 0, 0, 0);
+      }
+    };
+    // self part: k in [0, 64)
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      us8 a = (us8){0, 0, 0, 0, 0, 0, 0, 0};
+      if (live) a = *reinterpret_cast<const us8*>(h + P * kW + 32 * kb + 8 * oct);
+      if (Xout && live) *reinterpret_cast<us8*>(Xout + P * kK + 32 * kb + 8 * oct) = a;
+      mfma_step(kb, a);
+    }
+    // aggregates: k in [64 (1 + d), 64 (2 + d))
+    float ag[2][4][8];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ag[kb][d][j] = 0.0f;
     if (live) {
       for (int s = 0; s < NS; ++s) {
         const int32_t N = nbr[(int64_t)s * nc + P];
         if (N < 0) continue;
-        const us8 hv = *reinterpret_cast<const us8*>(h + (int64_t)N * kW + 32 * kb + 8 * oct);
-        float w4[4];
+        const float4 w4 = wf[(int64_t)s * nc + P];
+        const float wv[4] = {w4.x, w4.y, w4.z, w4.w};
 #pragma unroll
-        for (int d = 0; d < 4; ++d) w4[d] = wf[((int64_t)s * 4 + d) * nc + P];
+        for (int kb = 0; kb < 2; ++kb) {
+          const us8 hv = *reinterpret_cast<const us8*>(h + (int64_t)N * kW + 32 * kb + 8 * oct);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const float v = bf2f(hv[j]);
+          for (int j = 0; j < 8; ++j) {
+            const float v = bf2f(hv[j]);
 #pragma unroll
-          for (int d = 0; d < 4; ++d) ag[d][j] += w4[d] * v;
+            for (int d = 0; d < 4; ++d) ag[kb][d][j] += wv[d] * v;
+          }
         }
       }
     }
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      us8 a;
+    for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) a[j] = f2bf(ag[d][j]);
-      if (Xout && live) *reinterpret_cast<us8*>(Xout + P * kK + 64 * (1 + d) + 32 * kb + 8 * oct) = a;
-      mfma_step(2 + 2 * d + kb, a);
-    }
-  }
-  // epilogue: lane holds rows 4 oct + j, column 16 t + row
+      for (int d = 0; d < 4; ++d) {
+        us8 a;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int c = 16 * t + row;
-    const float bc = b[c];
+        for (int j = 0; j < 8; ++j) a[j] = f2bf(ag[kb][d][j]);
+        if (Xout && live) *reinterpret_cast<us8*>(Xout + P * kK + 64 * (1 + d) + 32 * kb + 8 * oct) = a;
+        mfma_step(2 + 2 * d + kb, a);
+      }
+    // epilogue: lane holds channels 16 t + 4 oct + j of cell P
+    if (live) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t Q = base + 4 * oct + j;
-      if (Q >= nc) continue;
-      const float y = fmaxf(acc[t][j] + bc, 0.0f);
-      const float hn = bf2f(h[Q * kW + c]) + y;
-      hout[Q * kW + c] = f2bf(hn);
-      if (Yout) Yout[Q * kW + c] = f2bf(y);
+      for (int t = 0; t < 4; ++t) {
+        const int c0 = 16 * t + 4 * oct;
+        const us4 hv = *reinterpret_cast<const us4*>(h + P * kW + c0);
+        const float bb[4] = {bc[t].x, bc[t].y, bc[t].z, bc[t].w};
+        us4 ho, yo;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float y = fmaxf(acc[t][j] + bb[j], 0.0f);
+          ho[j] = f2bf(bf2f(hv[j]) + y);
+          yo[j] = f2bf(y);
+        }
+        *reinterpret_cast<us4*>(hout + P * kW + c0) = ho;
+        if (Yout) *reinterpret_cast<us4*>(Yout + P * kW + c0) = yo;
+      }
     }
   }
 }
@@ -182,10 +226,16 @@ __global__ __launch_bounds__(kB) void k_nn_decoder(int64_t nc, const unsigned sh
   double l = 0.0;
   if (P < nc) {
     float g[3] = {bd[0], bd[1], bd[2]};
-    for (int c = 0; c < kW; ++c) {
-      const float hv = bf2f(h[P * kW + c]);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) g[j] += hv * bf2f(Wd[c * 3 + j]);
+    for (int c8 = 0; c8 < kW / 8; ++c8) {
+      const us8 hv8 = *reinterpret_cast<const us8*>(h + P * kW + 8 * c8);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float hv = bf2f(hv8[q]);
+        const int c = 8 * c8 + q;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) g[j] += hv * bf2f(Wd[c * 3 + j]);
+      }
     }
     const double sz = sc[3];
     const double ie = e ? 1.0 / sc[4] : 0.0;
@@ -320,7 +370,7 @@ __global__ __launch_bounds__(kB) void k_nn_agg_t(int64_t nc, const int32_t* __re
     const int32_t N = nbr[(int64_t)k * nc + P];
     if (N < 0) continue;
 #pragma unroll
-    for (int d = 0; d < 4; ++d) s += wb[((int64_t)k * 4 + d) * nc + P] * dA[(int64_t)N * (kK - kW) + d * kW + c];
+    for (int d = 0; d < 4; ++d) s += wb[((int64_t)k * nc + P) * 4 + d] * dA[(int64_t)N * (kK - kW) + d * kW + c];
   }
   dh_in[t] += s;
 }
@@ -558,13 +608,14 @@ static hofv_status nn_forward(hofv_ctx* c, hofv_nn* m, const double* r, const do
   k_nn_norms<<<nb, kB, 0, st>>>(n, r, zaj, e, w.dpart);
   k_nn_norms_final<<<1, kB, 0, st>>>(nb, n, w.dpart, w.sc);
   k_nn_features<D><<<nblk(nc), kB, 0, st>>>(nc, r, zaj, t.g_bflag, w.sc, w.x);
-  k_nn_encoder<<<nblk(nc * kW), kB, 0, st>>>(nc, w.x, m->We, m->p + kNnOffbe, w.h);
-  const unsigned lb = (unsigned)((nc + 63) / 64);
+  k_nn_encoder<<<nblk(nc), kB, 0, st>>>(nc, w.x, m->We, m->p + kNnOffbe, w.h);
+  const unsigned lb = (unsigned)((nc + kLayerCells - 1) / kLayerCells);
   for (int l = 0; l < kNnLayers; ++l) {
     const unsigned short* hin = w.h + (size_t)l * nc * kW;
     unsigned short* hout = w.h + (size_t)(l + 1) * nc * kW;
     TIMED_NN(c, "k_nn_layer", st,
-             (k_nn_layer<<<lb, kB, 0, st>>>(nc, hin, t.g_nbr, t.g_wf, 2 * D, m->Wt + (size_t)l * kK * kW,
+             (k_nn_layer<<<lb, kLayerThreads, 0, st>>>(nc, hin, t.g_nbr, reinterpret_cast<const float4*>(t.g_wf), 2 * D,
+                                                       m->Wt + (size_t)l * kK * kW,
                                             m->p + kNnOffb(l), hout, train ? w.Y + (size_t)l * nc * kW : nullptr,
                                             train ? w.X + (size_t)l * nc * kK : nullptr)));
   }

@@ -268,8 +268,8 @@ hofv_status build_tables(hofv_ctx* c) {
         len += dv[d] * dv[d];
       }
       len = std::sqrt(len);
-      gwf[((size_t)s * 4 + 0) * nc + P] = (float)om;
-      for (int d = 0; d < 3; ++d) gwf[((size_t)s * 4 + 1 + d) * nc + P] = (float)(om * dv[d] / len);
+      gwf[((size_t)s * nc + P) * 4 + 0] = (float)om;
+      for (int d = 0; d < 3; ++d) gwf[((size_t)s * nc + P) * 4 + 1 + d] = (float)(om * dv[d] / len);
     }
   }
   for (int64_t P = 0; P < nc; ++P)
@@ -278,7 +278,7 @@ hofv_status build_tables(hofv_ctx* c) {
       if (N < 0) continue;
       for (int s2 = 0; s2 < NS; ++s2)
         if (nbr[(size_t)s2 * nc + N] == P)
-          for (int d = 0; d < 4; ++d) gwb[((size_t)s * 4 + d) * nc + P] = gwf[((size_t)s2 * 4 + d) * nc + N];
+          for (int d = 0; d < 4; ++d) gwb[((size_t)s * nc + P) * 4 + d] = gwf[((size_t)s2 * nc + N) * 4 + d];
     }
 
   // stencils are searched point-major; the kernels read them k-major

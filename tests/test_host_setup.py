@@ -157,8 +157,8 @@ def test_learned_graph_tables_match_oracle():
     ctx = api.context_for(prob, host_only=True)
     n = disc.n_cells
     gn = ctx.host_table("nn_nbr").reshape(6, n)
-    wf = ctx.host_table("nn_wf").reshape(6, 4, n)
-    wb = ctx.host_table("nn_wb").reshape(6, 4, n)
+    wf = ctx.host_table("nn_wf").reshape(6, n, 4).transpose(0, 2, 1)
+    wb = ctx.host_table("nn_wb").reshape(6, n, 4).transpose(0, 2, 1)
     assert np.array_equal(ctx.host_table("nn_bflag"), bflag.astype(np.float32))
     for P in range(n):
         lib = {int(gn[s, P]): (wf[s, :, P], wb[s, :, P]) for s in range(6) if gn[s, P] >= 0}
