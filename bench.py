@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="cube", choices=["cube", "cantilever", "square"],
+                    help="cube: 3D LE manufactured solution on a perturbed n^3 mesh (default); cantilever: "
+                         "3D neo-Hookean 200x20x20 beam, 10 load increments; square: 2D 32x32 LE, p=2")
     ap.add_argument("--n", type=int, default=64, help="cells per axis")
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=1000, help="cells for the CPU oracle (0: skip)")
@@ -88,6 +91,8 @@ def main():
                     help="train the learned correction and time the learned Newton solve")
     ap.add_argument("--learned-size", type=int, default=24, help="cells per axis of the training meshes")
     ap.add_argument("--learned-epochs", type=int, default=60)
+    ap.add_argument("--tol", type=float, default=0.0, help="Newton tolerance (default 1e-8; 1e-10 for square)")
+    ap.add_argument("--max-krylov", type=int, default=4000, help="Krylov iterations per Newton step")
     ap.add_argument("--calib", type=int, default=0,
                     help="run a plain 512 MiB elementwise copy first (counter calibration)")
     args = ap.parse_args()
@@ -109,15 +114,26 @@ def main():
         torch.mul(xa, 1.0, out=ya)
         torch.cuda.synchronize()
         del xa, ya
-    prob = w.cube_mms(args.n, args.p, perturb=0.2, seed=0)
-    nc, D = prob.mesh.n_cells, 3
+    if args.workload == "cube":
+        prob = w.cube_mms(args.n, args.p, perturb=0.2, seed=0)
+    elif args.workload == "cantilever":
+        prob = w.cantilever(p=args.p)
+    else:
+        prob = w.square_mms(32, args.p)
+    nc, D = prob.mesh.n_cells, prob.dim
     t0 = time.perf_counter()
     ctx = api.context_for(prob)
     t_setup = time.perf_counter() - t0
     log(f"setup {t_setup:.1f}s report {ctx.report}")
 
     cen = ctx.cell_centroids()
-    u = torch.tensor(prob.loads.exact.value(cen).T.copy(), device=dev)
+    if prob.loads.exact is not None:
+        u = torch.tensor(prob.loads.exact.value(cen).T.copy(), device=dev)
+    else:  # a bent state of the cantilever: u_y = -0.3 x^2 / L, the throughput state
+        L = prob.mesh.lengths[0]
+        st = np.zeros((nc, 3))
+        st[:, 1] = -0.3 * cen[:, 0] ** 2 / L
+        u = torch.tensor(st.T.copy(), device=dev)
     v = torch.tensor(np.random.default_rng(1000).standard_normal((D, nc)), device=dev)
     Ru = torch.empty_like(u)
     Jv = torch.empty_like(u)
@@ -137,7 +153,7 @@ def main():
     torch.cuda.synchronize()
     t_jvp = time.perf_counter() - t0
     kernels = {}
-    for name in ("k_face_le", "k_extrap", "k_cell_sum", "k_pack", "k_sumsq2"):
+    for name in ("k_face_le", "k_face_q", "k_face_nh", "k_extrap", "k_cell_sum", "k_pack", "k_sumsq2"):
         ms, cnt = ctx.kernel_time(name)
         if cnt:
             kernels[name] = {"avg_ms": ms / cnt, "launches": cnt}
@@ -162,13 +178,16 @@ def main():
         except Exception:
             pass
     log(f"kernels {json.dumps(kernels)}")
-    jvp_bytes = sum(ctx.kernel_bytes(k) for k in ("k_face_le", "k_extrap", "k_cell_sum"))
+    jvp_bytes = sum(ctx.kernel_bytes(k) for k in kernels if k in ("k_face_le", "k_face_q", "k_face_nh", "k_extrap",
+                                                                  "k_cell_sum"))
 
     def newton(learned):
         uu = torch.zeros_like(u)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = ctx.newton_solve(uu, tol=1e-8, eta=1e-4, max_krylov=4000, n_sweeps=2, learned=learned, check=False)
+        st = ctx.newton_solve(uu, tol=args.tol if args.tol > 0 else (1e-10 if args.workload == "square" else 1e-8),
+                              eta=1e-4, max_krylov=args.max_krylov, n_sweeps=2, learned=learned, check=False,
+                              n_increments=prob.n_increments)
         torch.cuda.synchronize()
         return {"seconds": time.perf_counter() - t0, "newton_iters": st["newton_iters"],
                 "krylov_iters": st["krylov_iters"], "rel_residual": st["rel_residual"],
@@ -177,10 +196,10 @@ def main():
     solve = None
     if args.solve:
         newton(False)  # warm-up (allocates the Krylov workspace)
-        solve = {"tol": 1e-8, "plain": newton(False),
+        solve = {"plain": newton(False),
                  "plain_preconditioner": "compact approximate Jacobian, 2 FP32 symmetric Gauss-Seidel sweeps"}
         log(f"plain solve {solve['plain']}")
-        if args.learned:
+        if args.learned and args.workload == "cube":
             from paper_2601_18417_amd import learned as lrn
             t0 = time.perf_counter()
             data = []
@@ -217,7 +236,7 @@ def main():
             log(f"learned solve {solve['learned']} training {solve['learned_training']}")
 
     cpu = None
-    if args.cpu_sample > 0:
+    if args.cpu_sample > 0 and args.workload == "cube":
         cpu = cpu_baseline(prob, args.cpu_sample)
         log(f"cpu {cpu}")
 
@@ -234,8 +253,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"3D linear elastic MMS, unit cube {args.n}^3 hex perturbed +-20% (seed 0), "
-                               f"p={args.p}, |S|={ctx.report['stencil_size']}, 2x2 Gauss/face, alpha=0.1",
+        "config": {"workload": {"cube": f"3D linear elastic MMS, unit cube {args.n}^3 hex perturbed +-20% (seed 0), "
+                                        f"p={args.p}, |S|={ctx.report['stencil_size']}, 2x2 Gauss/face, alpha=0.1",
+                                "cantilever": f"3D neo-Hookean cantilever 200x20x20 hex (mu=1, lambda=10), p={args.p}, "
+                                              f"|S|={ctx.report['stencil_size']}, 10 load increments",
+                                "square": f"2D plane-strain LE MMS, 32x32 quads, p={args.p}, "
+                                          f"|S|={ctx.report['stencil_size']}"}[args.workload],
                    "n_cells": nc, "global_batch": nc, "parallelism": "single GPU"},
         "residual_mcells_s": nc / (ms_res * 1e-3) / 1e6,
         "jvp_algorithmic_GBps": jvp_bytes / (ms_step * 1e-3) / 1e9,

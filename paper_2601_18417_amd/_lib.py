@@ -8,7 +8,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhofv.so")
+# HOFV_LIB may name another build of the same library (e.g. a variant under test)
+LIB_PATH = os.environ.get("HOFV_LIB") or os.path.join(HERE, "libhofv.so")
 
 HOFV_OK = 0
 STATUS = {0: "HOFV_OK", -1: "HOFV_EINVAL", -2: "HOFV_ENOMEM", -3: "HOFV_EHIP", -4: "HOFV_ESINGULAR",
