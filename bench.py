@@ -28,15 +28,23 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per k_face_le launch on this workload from two rocprofv3 --pmc
 # passes (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, factors from a plain 512 MiB
-# elementwise copy), valid for the kernel source with this sha256 prefix only.
-MEASURED_TRAFFIC = {"kernel": "k_face_le", "n": 64, "p": 3, "bytes": 2027418183.6,
-                    "kernels_sha256": "220ad8f70527de0f"}
+# elementwise copy), valid only for the kernel and table-layout sources whose
+# combined sha256 has this prefix.
+MEASURED_TRAFFIC = {"kernel": "k_face_le", "n": 64, "p": 3, "bytes": 1912341390.2,
+                    "kernels_sha256": "7fea70fcbc3bf7da"}
+TRAFFIC_SOURCES = ("kernels.hip", "common.h", "setup_blocks.cpp", "setup_tables.cpp")
+
+
+def sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2601_18417_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel, n, p):
-    import hashlib
-    src = os.path.join(ROOT, "paper_2601_18417_amd", "csrc", "kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = sources_sha()
     t = MEASURED_TRAFFIC
     if t["kernel"] == kernel and t["n"] == n and t["p"] == p and t["kernels_sha256"] == sha:
         return t["bytes"]

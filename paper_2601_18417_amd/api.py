@@ -161,7 +161,7 @@ class Context:
         self._check(self.lib.hofv_host_table(self.h, name.encode(), C.byref(n), C.byref(eb), C.byref(data)))
         dtype = {("face_coef", 8): np.float64}.get((name, eb.value))
         if dtype is None:
-            dtype = {4: np.int32, 8: np.float64}[eb.value]
+            dtype = {2: np.uint16, 4: np.int32, 8: np.float64}[eb.value]
             if name in ("pc_dinv", "pc_a", "nn_wf", "nn_wb", "nn_bflag"):
                 dtype = np.float32
         buf = (C.c_char * (n.value * eb.value)).from_address(data.value) if n.value else b""

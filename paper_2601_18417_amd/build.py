@@ -19,7 +19,8 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["api.cpp", "setup_mesh.cpp", "setup_stencil.cpp", "setup_lsq.cpp", "setup_tables.cpp"]
+HOST_SOURCES = ["api.cpp", "setup_mesh.cpp", "setup_stencil.cpp", "setup_lsq.cpp", "setup_blocks.cpp",
+                "setup_tables.cpp"]
 DEVICE_SOURCES = ["kernels.hip", "krylov.hip", "mpnn.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]

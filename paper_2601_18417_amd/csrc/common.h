@@ -13,6 +13,23 @@
 
 namespace hofv {
 
+// Stencil kernels run one workgroup of kBlockItems threads per item block and
+// stage the block's stencil union in LDS: at most kLdsFaceCells cells for the
+// face kernels, kLdsCellCells for the cell extrapolation (cell stencils of
+// neighbouring cells overlap less than those of neighbouring faces).
+#ifndef HOFV_BLOCK_ITEMS
+#define HOFV_BLOCK_ITEMS 256
+#endif
+constexpr int kBlockItems = HOFV_BLOCK_ITEMS;
+#ifndef HOFV_LDS_FACE
+#define HOFV_LDS_FACE 1024
+#endif
+#ifndef HOFV_LDS_CELL
+#define HOFV_LDS_CELL 1280
+#endif
+constexpr int kLdsFaceCells = HOFV_LDS_FACE;
+constexpr int kLdsCellCells = HOFV_LDS_CELL;
+
 // cell-face slot code for the face -> cell sum: f >= 0 owner side, ~f (< 0)
 // neighbour side, kNoFace for traction/unused slots
 constexpr int32_t kNoFace = INT32_MIN;
@@ -30,22 +47,34 @@ struct DeviceTables {
   int32_t nq = 0;        // quadrature points per face
   int64_t nf = 0;        // internal + displacement faces handled by the face kernel
   int64_t nfi = 0;       // internal faces (first nfi entries)
+  // item blocks of the stencil kernels (faces f_*, cells c_*): block b owns
+  // items [blk_item[b], blk_item[b+1]) and the stencil union
+  // ucell[blk_cell[b] .. blk_cell[b+1]); local[k][i] is the position of
+  // stencil entry k of item i in its block's union
+  int32_t nfb = 0, ncb = 0;
+  int32_t* f_blk_item = nullptr;  // [nfb + 1]
+  int32_t* f_blk_cell = nullptr;  // [nfb + 1]
+  int32_t* f_ucell = nullptr;     // [f_blk_cell[nfb]]
+  uint16_t* f_local = nullptr;    // [S][nf]
+  int32_t* c_blk_item = nullptr;
+  int32_t* c_blk_cell = nullptr;
+  int32_t* c_ucell = nullptr;
+  uint16_t* c_local = nullptr;    // [S][nc]
+  int32_t* c_cell = nullptr;      // [nc] cell of each extrapolation item (Morton order)
   // faces
-  int32_t* f_stencil = nullptr;  // [S][nf]
   double* f_coef = nullptr;      // folded: [S][D][nf]; per-point: [S][nq][D][nf]
-  int32_t* f_own = nullptr;      // [nf]
-  int32_t* f_nei = nullptr;      // [nf] (-1 on displacement faces)
+  int32_t* f_own = nullptr;      // [nf] owner's extrapolation item
+  int32_t* f_nei = nullptr;      // [nf] neighbour's extrapolation item (-1 on displacement faces)
   int32_t* f_slots = nullptr;    // [nf] owner slot | neighbour slot << 8
   double* f_area_vec = nullptr;  // folded: [D][nf] = Gamma n; per-point: [nq][D][nf] = alpha_q Gamma n
   double* f_stab = nullptr;      // [nf] alpha Kbar Gamma / |d . n|
   double* f_ghost = nullptr;     // per-point NH: [nq][D][D][nfd] ghost gradient at load 1
-  // cells
-  int32_t* c_stencil = nullptr;  // [S][nc]
+  // cells (extrapolation tables are indexed by extrapolation item)
   double* c_extrap = nullptr;    // [S][2D][nc] extrapolation rows (u* - u_P)
   int32_t* c_faces = nullptr;    // [2D][nc] slot codes
   double* c_src = nullptr;       // [D][nc] constant sources at load 1
   // transient
-  double* ustar = nullptr;       // [2D][D][nc]
+  double* ustar = nullptr;       // [2D][D][nc] by extrapolation item
   double* flux = nullptr;        // [D][nf]
   double* w = nullptr;           // [nc][4 | 2] padded gather copy of u (or u + eps v)
   double* scratch = nullptr;     // reduction partials
@@ -170,6 +199,17 @@ hofv_status upload(hofv_ctx* c, T** p, const std::vector<T>& host) {
 hofv_status build_topology(hofv_ctx* c);
 hofv_status build_geometry(hofv_ctx* c);
 hofv_status build_tables(hofv_ctx* c);
+
+// item blocks for LDS-staged stencil gathers (setup_blocks.cpp)
+struct StencilBlocks {
+  std::vector<int32_t> item, cell, cells;
+  std::vector<uint16_t> local;  // [S][n]
+  int32_t max_cells = 0;
+};
+// indices of pts[n][D] sorted by Morton code over the bounding box
+std::vector<int64_t> morton_order(const double* pts, int D, int64_t n);
+// st: item-major stencils [n][S] of items already in block order
+StencilBlocks make_blocks(const int32_t* st, int64_t n, int S, int64_t nc, int max_items, int max_cells);
 
 // stencils: cells nearest to each point, ties by (rint(d2/quantum), id)
 void nearest_cells(const std::vector<double>& cen, int D, int64_t nc, const double* pts,

@@ -11,10 +11,13 @@
 //              (first Piola stress P = sigma cof(F), traction P n_o);
 //   k_cell_sum R_P = sum of +-F over the cell's faces + load * src_P, or, for
 //              J.v, (that - R(u)_P) / eps.
-// One thread owns one face or one cell; per-item tables are stored
+// One thread owns one face or one cell, one workgroup one item block (items
+// consecutive along a Morton curve).  Per-item tables are stored
 // k-major/item-minor so the 64 lanes of a wavefront read 64 consecutive words
-// of each coefficient stream, and only the stencil gathers of u are scattered
-// (they hit L2: u is 8 D bytes per cell).
+// of each coefficient stream; the stencil values of u come from an LDS copy
+// of the block's stencil union, staged once per workgroup, so the only
+// scattered global loads are the staging gathers (L2 hits: a cell is in the
+// unions of a few neighbouring blocks).
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -26,12 +29,21 @@ namespace hofv {
 namespace {
 
 constexpr int kBlock = 256;
+// chunk sizes (stencil entries) of the pipelined contractions
+#ifndef HOFV_FACE_CHUNK
+#define HOFV_FACE_CHUNK 2
+#endif
+#ifndef HOFV_EXTRAP_CHUNK
+#define HOFV_EXTRAP_CHUNK 1
+#endif
+constexpr int kFaceChunk = HOFV_FACE_CHUNK, kExtrapChunk = HOFV_EXTRAP_CHUNK, kFaceQChunk = 1;
 
 inline unsigned blocks_for(int64_t n, int per = kBlock) { return (unsigned)((n + per - 1) / per); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2.  Remap so that XCD x runs one contiguous range of logical blocks: the
-// stencil gathers of a range stay within one L2.  Bijective for any grid.
+// L2.  Remap so that XCD x runs one contiguous range of logical blocks:
+// neighbouring item blocks, whose stencil unions overlap, share one L2.
+// Bijective for any grid.
 __device__ inline int64_t xcd_block() {
   const int64_t nb = gridDim.x, b = blockIdx.x;
   const int64_t x = b % 8, local = b / 8, base = nb / 8, r = nb % 8;
@@ -48,36 +60,141 @@ __device__ inline void load_u(const double* __restrict__ ug, int64_t n, double* 
   if constexpr (D == 3) un[2] = ug[4 * n + 2];
 }
 
+// Raw buffer resource over [base, base + bytes): loads through it at byte
+// offsets >= bytes return zero instead of touching memory.
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+constexpr int kNt = 2;  // nontemporal cache policy of a buffer load
+
+// Copies the stencil union of item block b into LDS, one plane per
+// component: lds[j][r] = u_j(ucell[blk_cell[b] + r]).
+template <int D, int CAP>
+__device__ inline void stage_union(int64_t b, const int32_t* __restrict__ blk_cell,
+                                   const int32_t* __restrict__ ucell, const double* __restrict__ ug,
+                                   double (*lds)[CAP]) {
+  const int32_t c0 = blk_cell[b];
+  const int32_t n = min(blk_cell[b + 1] - c0, CAP);
+  for (int r = threadIdx.x; r < n; r += kBlockItems) {
+    double un[D];
+    load_u<D>(ug, ucell[c0 + r], un);
+#pragma unroll
+    for (int j = 0; j < D; ++j) lds[j][r] = un[j];
+  }
+  __syncthreads();
+}
+
+// Stencil contraction acc[i][j] = sum_k C[k][i] u(entry k)[j] over the S
+// entries of one item, u read from the block's LDS copy through the 16-bit
+// local positions loc[k][item]; loc and C are k-major with item stride ld
+// (row i of entry k at C[(k I + i) ld + item]).
+// Software-pipelined in chunks of U entries: while chunk j is accumulated,
+// the coefficients of chunk j+1 and the positions of chunk j+2 are in flight.
+// Two coefficient register sets alternate roles so that no loaded value is
+// copied (a copy would wait for the load); the sched_barriers keep each
+// set's loads ahead of the other set's use.  Buffer loads (not plain loads)
+// keep the compiler from sinking the loop-carried loads back to their uses.
+// Chunk indices past the last full pair are clamped onto the last chunk
+// (cache hits) instead of branching.
+template <int D, int I, int U, int CAP>
+__device__ inline void contract_lds(int S, int64_t ld, int64_t item, const uint16_t* __restrict__ loc,
+                                    const double* __restrict__ C, const double (*lds)[CAP],
+                                    double (&acc)[I][D]) {
+  const int nch = S / (2 * U) * 2;
+  const uint32_t vi = (uint32_t)item * 2u, vc = (uint32_t)item * 8u, ldu = (uint32_t)ld;
+  auto load_idx = [&](int ch, uint32_t(&dst)[U]) {
+    ch = ch < nch ? ch : nch - 1;
+    const __amdgpu_buffer_rsrc_t r = buffer_rsrc(loc + (int64_t)ch * U * ld, (uint32_t)U * ldu * 2u);
+#pragma unroll
+    for (int e = 0; e < U; ++e)
+      dst[e] = __builtin_amdgcn_raw_buffer_load_b16(r, vi, (int)((uint32_t)e * ldu * 2u), kNt);
+  };
+  auto load_c = [&](int ch, double(&dst)[U][I]) {
+    ch = ch < nch ? ch : nch - 1;
+    const __amdgpu_buffer_rsrc_t r = buffer_rsrc(C + (int64_t)ch * U * I * ld, (uint32_t)(U * I) * ldu * 8u);
+#pragma unroll
+    for (int e = 0; e < U; ++e)
+#pragma unroll
+      for (int i = 0; i < I; ++i)
+        dst[e][i] = __builtin_bit_cast(
+            double, __builtin_amdgcn_raw_buffer_load_b64(r, vc, (int)((uint32_t)(e * I + i) * ldu * 8u), kNt));
+  };
+  auto fma = [&](const uint32_t(&l)[U], const double(&c)[U][I]) {
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      double uu[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) uu[j] = lds[j][l[e]];
+#pragma unroll
+      for (int i = 0; i < I; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc[i][j] += c[e][i] * uu[j];
+    }
+  };
+  if (nch > 0) {
+    uint32_t ia[U], ib[U];
+    double ca[U][I], cb[U][I];
+    load_idx(0, ia);
+    load_c(0, ca);
+    load_idx(1, ib);
+    int j = 0;
+    do {
+      __builtin_amdgcn_sched_barrier(0);
+      load_c(j + 1, cb);
+      __builtin_amdgcn_sched_barrier(0);
+      fma(ia, ca);
+      load_idx(j + 2, ia);
+      __builtin_amdgcn_sched_barrier(0);
+      load_c(j + 2, ca);
+      __builtin_amdgcn_sched_barrier(0);
+      fma(ib, cb);
+      load_idx(j + 3, ib);
+      j += 2;
+    } while (j < nch);
+  }
+  for (int k = nch * U; k < S; ++k) {
+    const uint32_t l[1] = {loc[(int64_t)k * ld + item]};
+    double c[1][I];
+#pragma unroll
+    for (int i = 0; i < I; ++i) c[0][i] = __builtin_nontemporal_load(&C[((int64_t)k * I + i) * ld + item]);
+    double uu[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) uu[j] = lds[j][l[0]];
+#pragma unroll
+    for (int i = 0; i < I; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) acc[i][j] += c[0][i] * uu[j];
+  }
+}
+
+// u*_{f,P} - u_P = sum_k E[k][slot][r] u(S_P[k]) for every face slot of the
+// cell P of extrapolation item r; ustar is indexed by item
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_extrap(int64_t nc, int S, const int32_t* __restrict__ st,
-                                                    const double* __restrict__ E, const double* __restrict__ u,
+__global__ __launch_bounds__(kBlockItems) void k_extrap(int64_t nc, int S, const int32_t* __restrict__ blk_item,
+                                                    const int32_t* __restrict__ blk_cell,
+                                                    const int32_t* __restrict__ ucell,
+                                                    const uint16_t* __restrict__ loc, const double* __restrict__ E,
+                                                    const int32_t* __restrict__ cell, const double* __restrict__ ug,
                                                     double* __restrict__ ustar) {
   constexpr int NS = 2 * D;
-  const int64_t P = xcd_block() * kBlock + threadIdx.x;
-  if (P >= nc) return;
+  __shared__ double lds[D][kLdsCellCells];
+  const int64_t b = xcd_block();
+  stage_union<D, kLdsCellCells>(b, blk_cell, ucell, ug, lds);
+  const int64_t r = blk_item[b] + threadIdx.x;
+  if (r >= blk_item[b + 1]) return;
   double acc[NS][D];
 #pragma unroll
   for (int s = 0; s < NS; ++s)
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[s][c] = 0.0;
-#pragma unroll 2
-  for (int k = 0; k < S; ++k) {
-    const int32_t n = __builtin_nontemporal_load(&st[(int64_t)k * nc + P]);
-    double un[D];
-    load_u<D>(u, n, un);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const double e = __builtin_nontemporal_load(&E[((int64_t)k * NS + s) * nc + P]);
-#pragma unroll
-      for (int c = 0; c < D; ++c) acc[s][c] += e * un[c];
-    }
-  }
+  contract_lds<D, NS, kExtrapChunk, kLdsCellCells>(S, nc, r, loc, E, lds, acc);
   double uP[D];
-  load_u<D>(u, P, uP);
+  load_u<D>(ug, cell[r], uP);
 #pragma unroll
   for (int c = 0; c < D; ++c)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) ustar[((int64_t)s * D + c) * nc + P] = uP[c] + acc[s][c];
+    for (int s = 0; s < NS; ++s) ustar[((int64_t)s * D + c) * nc + r] = uP[c] + acc[s][c];
 }
 
 // stabilisation part alpha Kbar Gamma/|d.n| (u*_N - u*_P); on displacement
@@ -97,32 +214,27 @@ __device__ inline void add_stab(int64_t f, int64_t nfi, int64_t nc, const int32_
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_face_le(int64_t nf, int64_t nfi, int64_t nc, int S,
-                                                     const int32_t* __restrict__ st, const double* __restrict__ C,
+__global__ __launch_bounds__(kBlockItems) void k_face_le(int64_t nf, int64_t nfi, int64_t nc, int S,
+                                                     const int32_t* __restrict__ blk_item,
+                                                     const int32_t* __restrict__ blk_cell,
+                                                     const int32_t* __restrict__ ucell,
+                                                     const uint16_t* __restrict__ loc, const double* __restrict__ C,
                                                      const int32_t* __restrict__ own, const int32_t* __restrict__ nei,
                                                      const int32_t* __restrict__ slots,
                                                      const double* __restrict__ Sv, const double* __restrict__ stab,
-                                                     double mu, double lam, const double* __restrict__ u,
+                                                     double mu, double lam, const double* __restrict__ ug,
                                                      const double* __restrict__ ustar, double* __restrict__ F) {
-  const int64_t f = xcd_block() * kBlock + threadIdx.x;
-  if (f >= nf) return;
+  __shared__ double lds[D][kLdsFaceCells];
+  const int64_t b = xcd_block();
+  stage_union<D, kLdsFaceCells>(b, blk_cell, ucell, ug, lds);
+  const int64_t f = blk_item[b] + threadIdx.x;
+  if (f >= blk_item[b + 1]) return;
   double G[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j < D; ++j) G[i][j] = 0.0;
-#pragma unroll 2
-  for (int k = 0; k < S; ++k) {
-    const int32_t n = __builtin_nontemporal_load(&st[(int64_t)k * nf + f]);
-    double un[D];
-    load_u<D>(u, n, un);
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      const double c = __builtin_nontemporal_load(&C[((int64_t)k * D + i) * nf + f]);
-#pragma unroll
-      for (int j = 0; j < D; ++j) G[i][j] += c * un[j];
-    }
-  }
+  contract_lds<D, D, kFaceChunk, kLdsFaceCells>(S, nf, f, loc, C, lds, G);
   double tr = 0.0;
 #pragma unroll
   for (int i = 0; i < D; ++i) tr += G[i][i];
@@ -143,37 +255,29 @@ __global__ __launch_bounds__(kBlock) void k_face_le(int64_t nf, int64_t nfi, int
 
 // per-quadrature-point face kernel; MAT 0 linear elastic, 1 neo-Hookean (D = 3)
 template <int D, int NQ, int MAT>
-__global__ __launch_bounds__(kBlock) void k_face_q(int64_t nf, int64_t nfi, int64_t nc, int S,
-                                                    const int32_t* __restrict__ st, const double* __restrict__ C,
+__global__ __launch_bounds__(kBlockItems) void k_face_q(int64_t nf, int64_t nfi, int64_t nc, int S,
+                                                    const int32_t* __restrict__ blk_item,
+                                                    const int32_t* __restrict__ blk_cell,
+                                                    const int32_t* __restrict__ ucell,
+                                                    const uint16_t* __restrict__ loc, const double* __restrict__ C,
                                                     const int32_t* __restrict__ own, const int32_t* __restrict__ nei,
                                                     const int32_t* __restrict__ slots,
                                                     const double* __restrict__ Sv, const double* __restrict__ stab,
                                                     const double* __restrict__ ghost, double load, double mu,
-                                                    double lam, const double* __restrict__ u,
+                                                    double lam, const double* __restrict__ ug,
                                                     const double* __restrict__ ustar, double* __restrict__ F,
                                                     int32_t* __restrict__ flag) {
-  const int64_t f = xcd_block() * kBlock + threadIdx.x;
-  if (f >= nf) return;
-  double G[NQ][D][D];
+  __shared__ double lds[D][kLdsFaceCells];
+  const int64_t b = xcd_block();
+  stage_union<D, kLdsFaceCells>(b, blk_cell, ucell, ug, lds);
+  const int64_t f = blk_item[b] + threadIdx.x;
+  if (f >= blk_item[b + 1]) return;
+  double G[NQ * D][D];  // row q D + i: d u / d x_i at point q
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
+  for (int r = 0; r < NQ * D; ++r)
 #pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-      for (int j = 0; j < D; ++j) G[q][i][j] = 0.0;
-  for (int k = 0; k < S; ++k) {
-    const int32_t n = __builtin_nontemporal_load(&st[(int64_t)k * nf + f]);
-    double un[D];
-    load_u<D>(u, n, un);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        const double c = __builtin_nontemporal_load(&C[(((int64_t)k * NQ + q) * D + i) * nf + f]);
-#pragma unroll
-        for (int j = 0; j < D; ++j) G[q][i][j] += c * un[j];
-      }
-  }
+    for (int j = 0; j < D; ++j) G[r][j] = 0.0;
+  contract_lds<D, NQ * D, kFaceQChunk, kLdsFaceCells>(S, nf, f, loc, C, lds, G);
   if (MAT == 1 && f >= nfi) {
     const int64_t nfd = nf - nfi, fd = f - nfi;
 #pragma unroll
@@ -181,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_face_q(int64_t nf, int64_t nfi, int6
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int j = 0; j < D; ++j) G[q][i][j] += load * ghost[(((int64_t)q * D + i) * D + j) * nfd + fd];
+        for (int j = 0; j < D; ++j) G[q * D + i][j] += load * ghost[(((int64_t)q * D + i) * D + j) * nfd + fd];
   }
   double t[D];
 #pragma unroll
@@ -194,12 +298,12 @@ __global__ __launch_bounds__(kBlock) void k_face_q(int64_t nf, int64_t nfi, int6
     if (MAT == 0) {
       double tr = 0.0;
 #pragma unroll
-      for (int i = 0; i < D; ++i) tr += G[q][i][i];
+      for (int i = 0; i < D; ++i) tr += G[q * D + i][i];
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < D; ++i) s += sv[i] * (mu * (G[q][i][j] + G[q][j][i]) + (i == j ? lam * tr : 0.0));
+        for (int i = 0; i < D; ++i) s += sv[i] * (mu * (G[q * D + i][j] + G[q * D + j][i]) + (i == j ? lam * tr : 0.0));
         t[j] += s;
       }
     } else {
@@ -209,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_face_q(int64_t nf, int64_t nfi, int6
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) Fm[a][b] = (a == b ? 1.0 : 0.0) + G[q][b][a];
+        for (int c = 0; c < 3; ++c) Fm[a][c] = (a == c ? 1.0 : 0.0) + G[q * D + c][a];
       double cof[3][3];
       cof[0][0] = Fm[1][1] * Fm[2][2] - Fm[1][2] * Fm[2][1];
       cof[0][1] = Fm[1][2] * Fm[2][0] - Fm[1][0] * Fm[2][2];
@@ -445,17 +549,20 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
   const int64_t nc = c->nc, nf = t.nf;
   const bool nh = c->prm.material == HOFV_NEO_HOOKEAN;
   const bool fold = !nh && c->prm.fold_quadrature;
-  TIMED("k_extrap", (k_extrap<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, t.S, t.c_stencil, t.c_extrap, u, t.ustar)));
+  TIMED("k_extrap", (k_extrap<D><<<t.ncb, kBlockItems, 0, st>>>(nc, t.S, t.c_blk_item, t.c_blk_cell, t.c_ucell,
+                                                           t.c_local, t.c_extrap, t.c_cell, u, t.ustar)));
   if (nf > 0) {
     if (fold) {
-      TIMED("k_face_le", (k_face_le<D><<<blocks_for(nf), kBlock, 0, st>>>(
-                             nf, t.nfi, nc, t.S, t.f_stencil, t.f_coef, t.f_own, t.f_nei, t.f_slots, t.f_area_vec,
-                             t.f_stab, c->prm.mu, c->prm.lambda, u, t.ustar, t.flux)));
+      TIMED("k_face_le", (k_face_le<D><<<t.nfb, kBlockItems, 0, st>>>(
+                             nf, t.nfi, nc, t.S, t.f_blk_item, t.f_blk_cell, t.f_ucell, t.f_local, t.f_coef, t.f_own,
+                             t.f_nei, t.f_slots, t.f_area_vec, t.f_stab, c->prm.mu, c->prm.lambda, u, t.ustar,
+                             t.flux)));
     } else {
 #define FACEQ(NQ, MAT, NAME)                                                                                  \
-  TIMED(NAME, (k_face_q<D, NQ, MAT><<<blocks_for(nf), kBlock, 0, st>>>(                                       \
-                  nf, t.nfi, nc, t.S, t.f_stencil, t.f_coef, t.f_own, t.f_nei, t.f_slots, t.f_area_vec, t.f_stab, \
-                  t.f_ghost, c->load, c->prm.mu, c->prm.lambda, u, t.ustar, t.flux, t.flag)))
+  TIMED(NAME, (k_face_q<D, NQ, MAT><<<t.nfb, kBlockItems, 0, st>>>(                                                \
+                  nf, t.nfi, nc, t.S, t.f_blk_item, t.f_blk_cell, t.f_ucell, t.f_local, t.f_coef, t.f_own,     \
+                  t.f_nei, t.f_slots, t.f_area_vec, t.f_stab, t.f_ghost, c->load, c->prm.mu, c->prm.lambda, u, \
+                  t.ustar, t.flux, t.flag)))
       const int nq = t.nq;
       if (nh) {
         if constexpr (D == 3) {

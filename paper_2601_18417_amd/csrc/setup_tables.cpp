@@ -36,9 +36,8 @@ hofv_status build_tables(hofv_ctx* c) {
   if (S > nc) return fail(c, HOFV_EINVAL, "stencil size exceeds the number of cells");
   const double kshape = c->prm.k_weight, gw = c->prm.ghost_weight, alpha = c->prm.alpha;
 
-  // kernel faces: internal, then displacement, each ordered by (owner slot,
-  // owner) so that a wavefront holds faces of one orientation at consecutive
-  // owners, whose id-sorted stencils are near-shifted copies of each other
+  // kernel faces: internal, then displacement, each along a Morton curve of
+  // the face centres (item blocks of the face kernels cover compact patches)
   std::vector<int64_t> kf;
   kf.reserve(c->faces.size());
   for (int64_t f = 0; f < c->n_internal; ++f) kf.push_back(f);
@@ -47,12 +46,24 @@ hofv_status build_tables(hofv_ctx* c) {
     if (c->btype[b] == HOFV_BC_DISPLACEMENT) kf.push_back(c->bface[b]);
     else trac.push_back((int64_t)b);
   }
-  auto by_slot = [&](int64_t a, int64_t b) {
-    const hofv_ctx::Face &A = c->faces[a], &B = c->faces[b];
-    return A.sown != B.sown ? A.sown < B.sown : A.own < B.own;
+  auto curve = [&](int64_t begin, int64_t end) {
+    std::vector<double> x((size_t)(end - begin) * D);
+    for (int64_t i = begin; i < end; ++i)
+      for (int d = 0; d < D; ++d) x[(i - begin) * D + d] = c->f_centre[(size_t)kf[i] * D + d];
+    const std::vector<int64_t> o = morton_order(x.data(), D, end - begin);
+    std::vector<int64_t> part(o.size());
+    for (size_t r = 0; r < o.size(); ++r) part[r] = kf[begin + o[r]];
+    std::copy(part.begin(), part.end(), kf.begin() + begin);
   };
-  std::sort(kf.begin(), kf.begin() + c->n_internal, by_slot);
-  std::sort(kf.begin() + c->n_internal, kf.end(), by_slot);
+  curve(0, c->n_internal);
+  curve(c->n_internal, (int64_t)kf.size());
+  // extrapolation items: cells along a Morton curve of the centroids
+  const std::vector<int64_t> corder = morton_order(c->cen.data(), D, nc);
+  std::vector<int32_t> cpos(nc), ccell(nc);
+  for (int64_t r = 0; r < nc; ++r) {
+    cpos[corder[r]] = (int32_t)r;
+    ccell[r] = (int32_t)corder[r];
+  }
   const int64_t nf = (int64_t)kf.size(), nfi = c->n_internal, nfd = nf - nfi;
   std::vector<int64_t> kf_of_face(c->faces.size(), -1);
   std::vector<int64_t> bidx_of_face(c->faces.size(), -1);
@@ -66,12 +77,18 @@ hofv_status build_tables(hofv_ctx* c) {
   std::vector<int32_t> fst((size_t)nf * S), cst((size_t)nc * S);
   nearest_cells(c->cen, D, nc, pts.data(), nf, S, c->prm.stencil_quantum, fst.data());
   nearest_cells(c->cen, D, nc, c->cen.data(), nc, S, c->prm.stencil_quantum, cst.data());
-  // a stencil is a set: store it in increasing cell id so that the k-th
-  // gathers of neighbouring items fall on neighbouring cells
+  // a stencil is a set: store it in increasing cell id (a canonical order;
+  // the block unions are built from it)
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < nf; ++i) std::sort(&fst[(size_t)i * S], &fst[(size_t)i * S] + S);
 #pragma omp parallel for schedule(static)
   for (int64_t P = 0; P < nc; ++P) std::sort(&cst[(size_t)P * S], &cst[(size_t)P * S] + S);
+  std::vector<int32_t> cst_item((size_t)nc * S);  // by extrapolation item
+  for (int64_t r = 0; r < nc; ++r) std::copy_n(&cst[(size_t)corder[r] * S], S, &cst_item[(size_t)r * S]);
+  const StencilBlocks fblk = make_blocks(fst.data(), nf, S, nc, kBlockItems, kLdsFaceCells);
+  const StencilBlocks cblk = make_blocks(cst_item.data(), nc, S, nc, kBlockItems, kLdsCellCells);
+  if (fblk.max_cells > kLdsFaceCells || cblk.max_cells > kLdsCellCells)
+    return fail(c, HOFV_EINVAL, "stencil union of one item exceeds the LDS staging capacity");
 
   // face coefficients
   const int ncoef = fold ? D : nq * D;
@@ -185,7 +202,7 @@ hofv_status build_tables(hofv_ctx* c) {
     if (!ok) singular = true;
     max_cond = std::max(max_cond, cond);
     for (int r = 0; r < nt; ++r)
-      for (int k = 0; k < S; ++k) cext[((size_t)k * NS + slots[r]) * nc + P] = out[r * S + k];
+      for (int k = 0; k < S; ++k) cext[((size_t)k * NS + slots[r]) * nc + cpos[P]] = out[r * S + k];
   }
   if (singular) return fail(c, HOFV_ESINGULAR, "rank-deficient least-squares stencil at a cell centroid");
 
@@ -281,12 +298,12 @@ hofv_status build_tables(hofv_ctx* c) {
           for (int d = 0; d < 4; ++d) gwb[((size_t)s * nc + P) * 4 + d] = gwf[((size_t)s2 * nc + N) * 4 + d];
     }
 
-  // stencils are searched point-major; the kernels read them k-major
-  std::vector<int32_t> fst_k((size_t)S * nf), cst_k((size_t)S * nc);
-  for (int64_t i = 0; i < nf; ++i)
-    for (int k = 0; k < S; ++k) fst_k[(size_t)k * nf + i] = fst[(size_t)i * S + k];
-  for (int64_t P = 0; P < nc; ++P)
-    for (int k = 0; k < S; ++k) cst_k[(size_t)k * nc + P] = cst[(size_t)P * S + k];
+  // the stabilisation term reads u* by extrapolation item
+  std::vector<int32_t> fown_item(nf), fnei_item(nf);
+  for (int64_t i = 0; i < nf; ++i) {
+    fown_item[i] = cpos[fown[i]];
+    fnei_item[i] = fnei[i] >= 0 ? cpos[fnei[i]] : -1;
+  }
   for (int k = 0; k < ncol; ++k) c->dev.colour_start[k + 1] += c->dev.colour_start[k];
   c->dev.n_colours = ncol;
   std::vector<int32_t> pnbr((size_t)NS * nc);
@@ -308,8 +325,23 @@ hofv_status build_tables(hofv_ctx* c) {
       h.bytes.resize(v.size() * sizeof(v[0]));
       if (!v.empty()) std::memcpy(h.bytes.data(), v.data(), h.bytes.size());
     };
+    // global stencils, k-major, for inspection
+    std::vector<int32_t> fst_k((size_t)S * nf), cst_k((size_t)S * nc);
+    for (int64_t i = 0; i < nf; ++i)
+      for (int k = 0; k < S; ++k) fst_k[(size_t)k * nf + i] = fst[(size_t)i * S + k];
+    for (int64_t r = 0; r < nc; ++r)
+      for (int k = 0; k < S; ++k) cst_k[(size_t)k * nc + r] = cst_item[(size_t)r * S + k];
     keep("face_stencil", fst_k);
     keep("cell_stencil", cst_k);
+    keep("cell_order", ccell);
+    keep("face_blk_item", fblk.item);
+    keep("face_blk_cell", fblk.cell);
+    keep("face_ucell", fblk.cells);
+    keep("face_local", fblk.local);
+    keep("cell_blk_item", cblk.item);
+    keep("cell_blk_cell", cblk.cell);
+    keep("cell_ucell", cblk.cells);
+    keep("cell_local", cblk.local);
     keep("face_coef", fcoef);
     keep("cell_extrap", cext);
     keep("face_own", fown);
@@ -333,11 +365,16 @@ hofv_status build_tables(hofv_ctx* c) {
     c->dev.nf = nf;
     c->dev.nfi = nfi;
   }
-  // byte model (algorithmic HBM bytes per launch; gathers counted once per cell)
+  // byte model (algorithmic HBM bytes per launch): coefficient streams and
+  // 2-byte local indices per stencil entry, per-item data, the block cell
+  // lists, u counted once per cell (the staging gathers of a cell shared by
+  // several blocks hit in L2)
   const double ub = (double)D * 8 * nc;
-  const double face_b = (double)nf * S * (ncoef * 8.0 + 4.0) + (double)nf * (4 * 3 + 8 + 8.0 * (fold ? D : nq * D)) +
-                        (nh ? (double)nq * D * D * 8 * nfd : 0.0) + ub + 2.0 * D * 8 * nf + (double)D * 8 * nf;
-  const double ext_b = (double)nc * S * (NS * 8.0 + 4.0) + ub + (double)NS * D * 8 * nc;
+  const double face_b = (double)nf * S * (ncoef * 8.0 + 2.0) + (double)nf * (4 * 3 + 8 + 8.0 * (fold ? D : nq * D)) +
+                        (nh ? (double)nq * D * D * 8 * nfd : 0.0) + 4.0 * fblk.cells.size() + ub +
+                        2.0 * D * 8 * nf + (double)D * 8 * nf;
+  const double ext_b = (double)nc * S * (NS * 8.0 + 2.0) + 4.0 * cblk.cells.size() + 4.0 * nc + ub +
+                       (double)NS * D * 8 * nc;
   const double sum_b = (double)nc * (NS * 4.0 + 2 * D * 8.0) + 2.0 * D * 8 * nf;
   c->kernel_bytes[nh ? "k_face_nh" : (fold ? "k_face_le" : "k_face_q")] = face_b;
   c->kernel_bytes["k_extrap"] = ext_b;
@@ -363,15 +400,24 @@ hofv_status build_tables(hofv_ctx* c) {
   hofv_status st;
 #define UP(ptr, vec) \
   if ((st = upload(c, &ptr, vec))) return st;
-  UP(t.f_stencil, fst_k);
+  t.nfb = (int32_t)fblk.item.size() - 1;
+  t.ncb = (int32_t)cblk.item.size() - 1;
+  UP(t.f_blk_item, fblk.item);
+  UP(t.f_blk_cell, fblk.cell);
+  UP(t.f_ucell, fblk.cells);
+  UP(t.f_local, fblk.local);
+  UP(t.c_blk_item, cblk.item);
+  UP(t.c_blk_cell, cblk.cell);
+  UP(t.c_ucell, cblk.cells);
+  UP(t.c_local, cblk.local);
+  UP(t.c_cell, ccell);
   UP(t.f_coef, fcoef);
-  UP(t.f_own, fown);
-  UP(t.f_nei, fnei);
+  UP(t.f_own, fown_item);
+  UP(t.f_nei, fnei_item);
   UP(t.f_slots, fslots);
   UP(t.f_area_vec, fsv);
   UP(t.f_stab, fstab);
   if (nh) UP(t.f_ghost, fghost);
-  UP(t.c_stencil, cst_k);
   UP(t.c_extrap, cext);
   UP(t.c_faces, cfaces);
   UP(t.c_src, src);

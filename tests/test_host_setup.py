@@ -52,8 +52,10 @@ def test_stencils_and_face_coefficients_match_oracle(mk):
                          np.einsum("fq,fqis->fis", disc.d_qw, disc.d_C)[jd]])
     oc = np.take_along_axis(oc, order[:, None, :], 2)
     assert np.abs(coef - oc).max() <= 1e-11 * np.abs(oc).max()
+    order = ctx.host_table("cell_order")  # extrapolation item -> cell
+    assert np.array_equal(np.sort(order), np.arange(disc.n_cells))
     cst = ctx.host_table("cell_stencil").reshape(S, disc.n_cells).T
-    assert np.array_equal(cst, np.sort(disc.c_st, axis=1))
+    assert np.array_equal(cst, np.sort(disc.c_st[order], axis=1))
 
 
 @pytest.mark.parametrize("mk", CASES[:3])
@@ -66,18 +68,20 @@ def test_extrapolation_rows_match_oracle(mk):
     S, D, nf, fst = _tables(ctx, prob)
     n = disc.n_cells
     NS = 2 * D
-    ext = ctx.host_table("cell_extrap").reshape(S, NS, n)
+    ext = ctx.host_table("cell_extrap").reshape(S, NS, n)  # by extrapolation item
     cst = ctx.host_table("cell_stencil").reshape(S, n)
+    item = np.argsort(ctx.host_table("cell_order"))  # cell -> extrapolation item
     cf = ctx.host_table("cell_faces").reshape(NS, n)
     fc = ctx.host_table("face_centre").reshape(nf, D)
     u = w.random_state(n, D, seed=1, scale=1.0)
     for P in range(0, n, 7):
+        r = item[P]
         for s in range(NS):
             code = cf[s, P]
             if code == np.iinfo(np.int32).min:
                 continue
             f = code if code >= 0 else ~code
-            lib = np.einsum("k,kj->j", ext[:, s, P], u[cst[:, P]])
+            lib = np.einsum("k,kj->j", ext[:, s, r], u[cst[:, r]])
             d = fc[f] - disc.cen[P]
             ref = ores.extrapolate(disc, u, np.array([P]), d[None])[0] - u[P]
             assert np.allclose(lib, ref, rtol=1e-10, atol=1e-10 * np.abs(u).max()), (P, s)
@@ -170,3 +174,30 @@ def test_learned_graph_tables_match_oracle():
             back = [kk for kk in range(6) if nbr[N, kk] == P][0]
             refb = np.concatenate([[om[N, back]], om[N, back] * dirs[N, back]])
             assert np.allclose(lib[N][1], refb, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("mk", [CASES[0], CASES[2], lambda: w.cube_mms(12, 3, perturb=0.2, seed=5)])
+def test_item_blocks_cover_stencils(mk):
+    """Item blocks of the LDS-staged kernels: consecutive items, at most 256
+    per block, a sorted union within the LDS capacity (1024 cells for face
+    blocks, 1280 for cell blocks), and every local position maps back to the
+    item's stencil entry."""
+    prob = mk()
+    ctx = api.context_for(prob, host_only=True)
+    S = prob.stencil_size
+    for kind, stn, cap in (("face", "face_stencil", 1024), ("cell", "cell_stencil", 1280)):
+        st = ctx.host_table(stn)
+        n = st.size // S
+        st = st.reshape(S, n)
+        bi = ctx.host_table(f"{kind}_blk_item")
+        bc = ctx.host_table(f"{kind}_blk_cell")
+        uc = ctx.host_table(f"{kind}_ucell")
+        loc = ctx.host_table(f"{kind}_local").reshape(S, n).astype(np.int64)
+        assert bi[0] == 0 and bi[-1] == n and np.all(np.diff(bi) > 0) and np.all(np.diff(bi) <= 256)
+        assert bc[0] == 0 and bc[-1] == uc.size and np.all(np.diff(bc) <= cap)
+        for b in range(bi.size - 1):
+            un = uc[bc[b]:bc[b + 1]]
+            assert np.all(np.diff(un) > 0)
+            items = slice(bi[b], bi[b + 1])
+            assert np.array_equal(un[loc[:, items]], st[:, items])
+            assert np.array_equal(un, np.unique(st[:, items]))
