@@ -55,8 +55,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, n_sample: int, seed: int = 0):
-    """The FP64 oracle's J.v on n_sample cells of the same mesh (setup excluded)."""
+def cpu_baseline(prob, n_sample: int, u, v, ctx, torch, label, seed: int = 0):
+    """The FP64 oracle's J.v on n_sample cells of the same mesh at the bench's
+    state (setup excluded), and the error of the GPU's R and J.v against it on
+    those cells (same u, v and eps)."""
     from oracle import jacobian as ojac
     from oracle import residual as ores
     rng = np.random.default_rng(seed)
@@ -67,20 +69,127 @@ def cpu_baseline(prob, n_sample: int, seed: int = 0):
     t0 = time.perf_counter()
     disc = ores.build(prob, active=cells)
     t_setup = time.perf_counter() - t0
-    u = prob.loads.exact.value(disc.cen)
-    v = np.random.default_rng(1000).standard_normal((n, prob.dim))
     Ru = ores.residual(disc, u)
     eps = ojac.default_eps(u, v)
     reps = 0
     t0 = time.perf_counter()
     while reps < 3 or time.perf_counter() - t0 < 5.0:
-        ojac.jvp(disc, u, v, Ru, eps)
+        Jo = ojac.jvp(disc, u, v, Ru, eps)
         reps += 1
     t_jvp = (time.perf_counter() - t0) / reps
+    ud = torch.tensor(u.T.copy(), device="cuda:0")
+    vd = torch.tensor(v.T.copy(), device="cuda:0")
+    Rg = torch.empty_like(ud)
+    Jg = torch.empty_like(ud)
+    ctx.residual(ud, Rg)
+    ctx.jvp(ud, Rg, vd, Jg, eps=eps)
+    Rg = Rg.cpu().numpy().T[cells]
+    Jg = Jg.cpu().numpy().T[cells]
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
     return {"value": n_sample / t_jvp / 1e6, "unit": "Mcells/s", "cores": 1, "kind": "oracle",
-            "sample": f"J.v at {n_sample} contiguous cells of the same 64^3 p=3 mesh, {reps} repetitions "
+            "sample": f"J.v at {n_sample} contiguous cells of the same {label} mesh, {reps} repetitions "
                       f"(numpy fp64, one thread; its setup for those cells, {t_setup:.1f}s, not timed)",
-            "seconds_per_jvp": t_jvp}
+            "seconds_per_jvp": t_jvp,
+            "gpu_error_vs_oracle": {"residual_rel_l2": rel(Rg, Ru[cells]), "jvp_rel_l2": rel(Jg, Jo[cells]),
+                                    "cells": n_sample}}
+
+
+def parse_seeds(s):
+    out = []
+    for part in s.split(","):
+        a, _, b = part.partition("-")
+        out += list(range(int(a), int(b) + 1)) if b else [int(a)]
+    return out
+
+
+def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None):
+    """Newton from u = 0 through the problem's load increments (each one a
+    library Newton solve at its load factor, logged as it ends)."""
+    uu = torch.zeros((prob.dim, nc), device="cuda:0", dtype=torch.float64) if u_out is None else u_out.zero_()
+    ninc = max(1, prob.n_increments)
+    out = {"newton_iters": 0, "krylov_iters": 0, "fallbacks": 0, "converged": True, "rel_residual": 0.0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for inc in range(1, ninc + 1):
+        ctx.set_load_scale(inc / ninc)
+        st = ctx.newton_solve(uu, tol=tol, eta=1e-4, max_krylov=max_krylov, n_sweeps=2, learned=learned,
+                              check=False, n_increments=0)
+        for key in ("newton_iters", "krylov_iters", "fallbacks"):
+            out[key] += st[key]
+        out["rel_residual"] = st["rel_residual"]
+        if ninc > 1:
+            log(f"{'learned' if learned else 'plain'} increment {inc}/{ninc}: {st['newton_iters']} Newton, "
+                f"{st['krylov_iters']} Krylov, rel {st['rel_residual']:.2e}, {time.perf_counter() - t0:.1f}s")
+        if not st["converged"]:
+            out["converged"] = False
+            break
+    torch.cuda.synchronize()
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
+def study(args):
+    """The learned-preconditioner study: 'train' harvests pairs on seeded
+    perturbed cubes and trains a model (saved as a float32 .npy); 'eval' times
+    plain vs learned Newton solves to the tolerance on an unseen mesh."""
+    import torch
+
+    import workloads as w
+    from paper_2601_18417_amd import api
+    from paper_2601_18417_amd import learned as lrn
+    dev = torch.device("cuda:0")
+    if args.study == "train":
+        t0 = time.perf_counter()
+        data = []
+        for seed in parse_seeds(args.train_seeds):
+            tp = w.cube_mms(args.learned_size, args.p, perturb=0.2, seed=seed)
+            tctx = api.context_for(tp)
+            u0 = torch.zeros((3, tp.mesh.n_cells), device=dev, dtype=torch.float64)
+            r1, e1 = lrn.harvest_krylov(tctx, u0, n_starts=args.harvest_starts, length=args.harvest_length, seed=seed)
+            r2, e2 = lrn.harvest_newton(tctx, u0, n_steps=2)
+            data.append((tctx, torch.cat([r1, r2]), torch.cat([e1, e2])))
+            log(f"harvested seed {seed}: {data[-1][1].shape[0]} pairs, {time.perf_counter() - t0:.0f}s")
+        t_harvest = time.perf_counter() - t0
+        model = api.Model(7)
+        hist = lrn.train(model, data, epochs=args.learned_epochs, lr=2e-3, batch=4,
+                         log=lambda ep, l: log(f"epoch {ep} loss {l:.4f}"))
+        np.save(args.model, model.get_params())
+        out = {"study": "train", "pairs": int(sum(d[1].shape[0] for d in data)),
+               "meshes": f"{args.learned_size}^3 p={args.p} perturbed cubes, seeds {args.train_seeds}",
+               "epochs": args.learned_epochs, "harvest_seconds": t_harvest,
+               "train_seconds": time.perf_counter() - t0 - t_harvest, "loss_first_epoch": hist[0],
+               "loss_last_epoch": hist[-1], "model": args.model}
+    else:
+        model = api.Model(0)
+        model.set_params(np.load(args.model))
+        if args.workload == "cantilever":
+            prob = w.cantilever(p=args.p)
+            desc = f"neo-Hookean cantilever 200x20x20, p={args.p}, 10 increments"
+        else:
+            lz = args.lz
+            prob = w.cube_mms(args.n, args.p, perturb=0.2, seed=args.seed, lengths=(1.0, 1.0, lz))
+            desc = (f"LE MMS {args.n}^3 perturbed +-20% (seed {args.seed}) on [0,1]^2 x [0,{lz}] "
+                    f"(cell aspect {1.0 / lz:g}), p={args.p}")
+        nc = prob.mesh.n_cells
+        t0 = time.perf_counter()
+        ctx = api.context_for(prob)
+        t_setup = time.perf_counter() - t0
+        ctx.attach(model)
+        tol = args.tol if args.tol > 0 else 1e-8
+        r = torch.randn((prob.dim, nc), device=dev, dtype=torch.float64)
+        z = torch.empty_like(r)
+        ctx.precond_apply(r, z, learned=True)  # allocates the network's workspace
+        plain = newton_run(torch, ctx, prob, nc, False, tol, args.max_krylov)
+        log(f"plain {plain}")
+        learned = newton_run(torch, ctx, prob, nc, True, tol, args.max_krylov)
+        log(f"learned {learned}")
+        out = {"study": "eval", "workload": desc, "n_cells": nc, "tol": tol, "setup_seconds": t_setup,
+               "plain": plain, "learned": learned, "speedup": plain["seconds"] / learned["seconds"],
+               "krylov_ratio": learned["krylov_iters"] / max(plain["krylov_iters"], 1)}
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -103,11 +212,24 @@ def main():
     ap.add_argument("--max-krylov", type=int, default=4000, help="Krylov iterations per Newton step")
     ap.add_argument("--calib", type=int, default=0,
                     help="run a plain 512 MiB elementwise copy first (counter calibration)")
+    ap.add_argument("--study", choices=["train", "eval"], default=None,
+                    help="learned-preconditioner study instead of the benchmark: train a model on "
+                         "--train-seeds (saved to --model) or evaluate --model on one mesh")
+    ap.add_argument("--train-seeds", default="0-49")
+    ap.add_argument("--harvest-starts", type=int, default=4)
+    ap.add_argument("--harvest-length", type=int, default=9)
+    ap.add_argument("--model", default="gpurun_out/learned_model.npy")
+    ap.add_argument("--seed", type=int, default=50, help="mesh seed of --study eval")
+    ap.add_argument("--lz", type=float, default=1.0, help="z extent of the evaluation cube (cell aspect 1/lz)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.study:
+        study(args)
+        return
 
     import torch
 
@@ -191,19 +313,22 @@ def main():
 
     def newton(learned):
         uu = torch.zeros_like(u)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = ctx.newton_solve(uu, tol=args.tol if args.tol > 0 else (1e-10 if args.workload == "square" else 1e-8),
-                              eta=1e-4, max_krylov=args.max_krylov, n_sweeps=2, learned=learned, check=False,
-                              n_increments=prob.n_increments)
-        torch.cuda.synchronize()
-        return {"seconds": time.perf_counter() - t0, "newton_iters": st["newton_iters"],
-                "krylov_iters": st["krylov_iters"], "rel_residual": st["rel_residual"],
-                "converged": bool(st["converged"])}
+        out = newton_run(torch, ctx, prob, nc, learned,
+                         args.tol if args.tol > 0 else (1e-10 if args.workload == "square" else 1e-8),
+                         args.max_krylov, u_out=uu)
+        ctx.set_load_scale(1.0)
+        if args.workload == "cantilever":
+            # mean transverse displacement of the last layer of cells / length
+            L = prob.mesh.lengths[0]
+            tip = np.nonzero(cen[:, 0] > L - L / prob.mesh.shape[0])[0]
+            uy = uu[1].cpu().numpy()[tip]
+            out["tip_deflection_over_length"] = float(abs(uy.mean()) / L)
+        return out
 
     solve = None
     if args.solve:
-        newton(False)  # warm-up (allocates the Krylov workspace)
+        if prob.n_increments == 1:
+            newton(False)  # warm-up (allocates the Krylov workspace)
         solve = {"plain": newton(False),
                  "plain_preconditioner": "compact approximate Jacobian, 2 FP32 symmetric Gauss-Seidel sweeps"}
         log(f"plain solve {solve['plain']}")
@@ -244,8 +369,11 @@ def main():
             log(f"learned solve {solve['learned']} training {solve['learned_training']}")
 
     cpu = None
-    if args.cpu_sample > 0 and args.workload == "cube":
-        cpu = cpu_baseline(prob, args.cpu_sample)
+    if args.cpu_sample > 0:
+        label = {"cube": f"{args.n}^3 p={args.p}", "cantilever": f"cantilever p={args.p}",
+                 "square": f"32^2 p={args.p}"}[args.workload]
+        cpu = cpu_baseline(prob, min(args.cpu_sample, nc // 2), u.cpu().numpy().T.copy(),
+                           v.cpu().numpy().T.copy(), ctx, torch, label)
         log(f"cpu {cpu}")
 
     out = {

@@ -168,11 +168,16 @@ typedef struct {
   int32_t converged;
   double rel_residual;   /* final ||rhs - J x|| / ||rhs|| (recomputed) */
   double seconds;
+  int32_t fallbacks;     /* iterations redone with the plain preconditioner
+                            because the learned one produced NaN/Inf */
 } hofv_krylov_stats;
 
 /* Solves J(u) x = rhs by right-preconditioned flexible GMRES(m) with J v from
  * hofv_jvp and z = M(v) from hofv_precond_apply; x holds the initial guess on
- * entry.  Synchronises once per iteration (Hessenberg column to the host). */
+ * entry.  Synchronises once per iteration (Hessenberg column to the host).
+ * With opts->learned, an iteration whose Hessenberg column is not finite is
+ * redone with the plain preconditioner, which is then kept for the rest of
+ * the solve (counted in stats->fallbacks). */
 hofv_status hofv_fgmres_solve(hofv_ctx* ctx, const double* d_u, const double* d_Ru,
                               const double* d_rhs, double* d_x, const hofv_krylov_opts* opts,
                               hofv_krylov_stats* stats, void* stream);
@@ -181,7 +186,8 @@ typedef struct {
   double tol;            /* ||R|| <= tol ||R_0|| per load increment */
   double eta;            /* Krylov rtol per Newton step */
   int32_t max_newton;    /* per increment */
-  int32_t n_increments;  /* load factors i / n, i = 1..n */
+  int32_t n_increments;  /* load factors i / n, i = 1..n; <= 0: one solve at the
+                            factor set by hofv_set_load_scale */
   int32_t max_line_search; /* backtracking halvings */
   hofv_krylov_opts krylov;
 } hofv_newton_opts;
@@ -192,12 +198,16 @@ typedef struct {
   int32_t converged;
   double rel_residual;   /* of the last increment */
   double seconds;
+  int32_t fallbacks;     /* FGMRES iterations redone with the plain preconditioner,
+                            plus linear solves repeated with it after the learned
+                            one missed the Krylov tolerance */
 } hofv_newton_stats;
 
 /* Newton with backtracking line search on ||R||_2 (accept the first
  * ||R(u + lam du)|| <= (1 - 1e-4 lam) ||R(u)||, lam = 1, 1/2, ...), J du = -R by
- * hofv_fgmres_solve, for each load increment.  d_u: initial guess in,
- * solution out.  Synchronises. */
+ * hofv_fgmres_solve, for each load increment.  With krylov.learned, a linear
+ * solve that misses its tolerance is repeated with the plain preconditioner.
+ * d_u: initial guess in, solution out.  Synchronises. */
 hofv_status hofv_newton_solve(hofv_ctx* ctx, double* d_u, const hofv_newton_opts* opts,
                               hofv_newton_stats* stats, void* stream);
 

@@ -39,7 +39,7 @@ class KrylovOpts(C.Structure):
 
 class KrylovStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("fallbacks", C.c_int32)]
 
 
 class NewtonOpts(C.Structure):
@@ -49,7 +49,7 @@ class NewtonOpts(C.Structure):
 
 class NewtonStats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("krylov_iters", C.c_int32), ("converged", C.c_int32),
-                ("rel_residual", C.c_double), ("seconds", C.c_double)]
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("fallbacks", C.c_int32)]
 
 
 P = C.c_void_p

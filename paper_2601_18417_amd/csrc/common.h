@@ -201,10 +201,29 @@ hofv_status build_geometry(hofv_ctx* c);
 hofv_status build_tables(hofv_ctx* c);
 
 // item blocks for LDS-staged stencil gathers (setup_blocks.cpp)
+// Per-stencil-entry tables are stored block by block: block b (items
+// [i0, i0 + nb)) owns the contiguous segment [i0 S R, (i0 + nb) S R) of a
+// table with R rows per entry, holding row r of entry k of its items at
+// (k R + r) nb + (i - i0), so one workgroup streams one contiguous segment.
 struct StencilBlocks {
   std::vector<int32_t> item, cell, cells;
-  std::vector<uint16_t> local;  // [S][n]
+  std::vector<int32_t> block_of;  // [n]
+  std::vector<uint16_t> local;    // positions in the block's union, R = 1
   int32_t max_cells = 0;
+  size_t at(int64_t i, int k, int r, int R, int S) const {
+    const int64_t b = block_of[i], i0 = item[b], nb = item[b + 1] - i0;
+    return (size_t)i0 * S * R + ((size_t)k * R + r) * nb + (size_t)(i - i0);
+  }
+  // the same table in the plain k-major layout [(k R + r) n + i]
+  template <class T>
+  std::vector<T> unblocked(const std::vector<T>& v, int R, int S) const {
+    const int64_t n = (int64_t)block_of.size();
+    std::vector<T> out(v.size());
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < S; ++k)
+        for (int r = 0; r < R; ++r) out[((size_t)k * R + r) * n + i] = v[at(i, k, r, R, S)];
+    return out;
+  }
 };
 // indices of pts[n][D] sorted by Morton code over the bounding box
 std::vector<int64_t> morton_order(const double* pts, int D, int64_t n);

@@ -87,8 +87,9 @@ __device__ inline void stage_union(int64_t b, const int32_t* __restrict__ blk_ce
 
 // Stencil contraction acc[i][j] = sum_k C[k][i] u(entry k)[j] over the S
 // entries of one item, u read from the block's LDS copy through the 16-bit
-// local positions loc[k][item]; loc and C are k-major with item stride ld
-// (row i of entry k at C[(k I + i) ld + item]).
+// local positions loc[k][item]; loc and C are the block's segments, k-major
+// with item stride ld = the block's item count (row i of entry k at
+// C[(k I + i) ld + item]).
 // Software-pipelined in chunks of U entries: while chunk j is accumulated,
 // the coefficients of chunk j+1 and the positions of chunk j+2 are in flight.
 // Two coefficient register sets alternate roles so that no loaded value is
@@ -181,14 +182,15 @@ __global__ __launch_bounds__(kBlockItems) void k_extrap(int64_t nc, int S, const
   __shared__ double lds[D][kLdsCellCells];
   const int64_t b = xcd_block();
   stage_union<D, kLdsCellCells>(b, blk_cell, ucell, ug, lds);
-  const int64_t r = blk_item[b] + threadIdx.x;
-  if (r >= blk_item[b + 1]) return;
+  const int64_t i0 = blk_item[b], nb = blk_item[b + 1] - i0, ti = threadIdx.x;
+  if (ti >= nb) return;
+  const int64_t r = i0 + ti;
   double acc[NS][D];
 #pragma unroll
   for (int s = 0; s < NS; ++s)
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[s][c] = 0.0;
-  contract_lds<D, NS, kExtrapChunk, kLdsCellCells>(S, nc, r, loc, E, lds, acc);
+  contract_lds<D, NS, kExtrapChunk, kLdsCellCells>(S, nb, ti, loc + i0 * S, E + i0 * S * NS, lds, acc);
   double uP[D];
   load_u<D>(ug, cell[r], uP);
 #pragma unroll
@@ -227,14 +229,15 @@ __global__ __launch_bounds__(kBlockItems) void k_face_le(int64_t nf, int64_t nfi
   __shared__ double lds[D][kLdsFaceCells];
   const int64_t b = xcd_block();
   stage_union<D, kLdsFaceCells>(b, blk_cell, ucell, ug, lds);
-  const int64_t f = blk_item[b] + threadIdx.x;
-  if (f >= blk_item[b + 1]) return;
+  const int64_t i0 = blk_item[b], nb = blk_item[b + 1] - i0, ti = threadIdx.x;
+  if (ti >= nb) return;
+  const int64_t f = i0 + ti;
   double G[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j < D; ++j) G[i][j] = 0.0;
-  contract_lds<D, D, kFaceChunk, kLdsFaceCells>(S, nf, f, loc, C, lds, G);
+  contract_lds<D, D, kFaceChunk, kLdsFaceCells>(S, nb, ti, loc + i0 * S, C + i0 * S * D, lds, G);
   double tr = 0.0;
 #pragma unroll
   for (int i = 0; i < D; ++i) tr += G[i][i];
@@ -270,14 +273,15 @@ __global__ __launch_bounds__(kBlockItems) void k_face_q(int64_t nf, int64_t nfi,
   __shared__ double lds[D][kLdsFaceCells];
   const int64_t b = xcd_block();
   stage_union<D, kLdsFaceCells>(b, blk_cell, ucell, ug, lds);
-  const int64_t f = blk_item[b] + threadIdx.x;
-  if (f >= blk_item[b + 1]) return;
+  const int64_t i0 = blk_item[b], nb = blk_item[b + 1] - i0, ti = threadIdx.x;
+  if (ti >= nb) return;
+  const int64_t f = i0 + ti;
   double G[NQ * D][D];  // row q D + i: d u / d x_i at point q
 #pragma unroll
   for (int r = 0; r < NQ * D; ++r)
 #pragma unroll
     for (int j = 0; j < D; ++j) G[r][j] = 0.0;
-  contract_lds<D, NQ * D, kFaceQChunk, kLdsFaceCells>(S, nf, f, loc, C, lds, G);
+  contract_lds<D, NQ * D, kFaceQChunk, kLdsFaceCells>(S, nb, ti, loc + i0 * S, C + i0 * S * NQ * D, lds, G);
   if (MAT == 1 && f >= nfi) {
     const int64_t nfd = nf - nfi, fd = f - nfi;
 #pragma unroll

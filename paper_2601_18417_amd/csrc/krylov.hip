@@ -171,6 +171,8 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
   if ((s = host_norm(c, n, x, &xnorm, st))) return s;
   stats->iters = 0;
   stats->converged = 0;
+  stats->fallbacks = 0;
+  int learned = o->learned;
   if (!std::isfinite(bnorm) || !std::isfinite(xnorm)) return fail(c, HOFV_ENAN, "NaN/Inf in FGMRES input");
   if (bnorm == 0.0) {
     k_fill<<<nblk(n), kB, 0, st>>>(n, 0.0, x);
@@ -202,23 +204,36 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
       double* vj = K.V + (size_t)j * n;
       double* zj = K.Z + (size_t)j * n;
       double* w = K.V + (size_t)(j + 1) * n;
-      if ((s = precond_dispatch(c, vj, zj, sweeps, o->learned, st))) return s;
-      if ((s = jvp_impl(c, u, Ru, zj, w, 0.0, st))) return s;
-      // CGS2
-      if ((s = dots(c, n, j + 1, K.V, n, w, hd, 0, st))) return s;
-      k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd, -1.0, w);
-      if ((s = dots(c, n, j + 1, K.V, n, w, hd + kMaxDots + 4 + 0, 0, st))) return s;
-      k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd + kMaxDots + 4, -1.0, w);
-      if ((s = dots(c, n, 1, w, n, w, hd + j + 1, 0, st))) return s;
-      k_scale_by<<<nblk(n), kB, 0, st>>>(n, w, hd + j + 1, 1, w);
-      HOFV_HIP(c, hipGetLastError());
       std::vector<double> h2(j + 1);
-      HOFV_HIP(c, hipMemcpyAsync(hcol.data(), hd, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
-      HOFV_HIP(c, hipMemcpyAsync(h2.data(), hd + kMaxDots + 4, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-      HOFV_HIP(c, hipStreamSynchronize(st));
+      for (;;) {
+        if ((s = precond_dispatch(c, vj, zj, sweeps, learned, st))) return s;
+        // ||z_j||^2 of a learned output (a NaN z_j would only show up later:
+        // its finite-difference product is defined to be zero)
+        if (learned && (s = dots(c, n, 1, zj, n, zj, hd + kMaxDots + 2, 0, st))) return s;
+        if ((s = jvp_impl(c, u, Ru, zj, w, 0.0, st))) return s;
+        // CGS2
+        if ((s = dots(c, n, j + 1, K.V, n, w, hd, 0, st))) return s;
+        k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd, -1.0, w);
+        if ((s = dots(c, n, j + 1, K.V, n, w, hd + kMaxDots + 4 + 0, 0, st))) return s;
+        k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd + kMaxDots + 4, -1.0, w);
+        if ((s = dots(c, n, 1, w, n, w, hd + j + 1, 0, st))) return s;
+        k_scale_by<<<nblk(n), kB, 0, st>>>(n, w, hd + j + 1, 1, w);
+        HOFV_HIP(c, hipGetLastError());
+        HOFV_HIP(c, hipMemcpyAsync(hcol.data(), hd, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
+        HOFV_HIP(c, hipMemcpyAsync(h2.data(), hd + kMaxDots + 4, (j + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                                   st));
+        double zz = 0.0;
+        if (learned) HOFV_HIP(c, hipMemcpyAsync(&zz, hd + kMaxDots + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+        HOFV_HIP(c, hipStreamSynchronize(st));
+        bool finite = std::isfinite(hcol[j + 1]) && std::isfinite(zz);
+        for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(hcol[i] + h2[i]);
+        if (finite) break;
+        if (!learned) return fail(c, HOFV_ENAN, "NaN/Inf in Arnoldi");
+        learned = 0;  // the plain preconditioner takes over for the rest of the solve
+        ++stats->fallbacks;
+      }
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i] + h2[i];
       H[(size_t)(j + 1) * m + j] = std::sqrt(hcol[j + 1]);
-      if (!std::isfinite(H[(size_t)(j + 1) * m + j])) return fail(c, HOFV_ENAN, "NaN/Inf in Arnoldi");
       for (int i = 0; i < j; ++i) {
         const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
         H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
@@ -272,16 +287,19 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
       c->device_bytes -= n * sizeof(double);
     }
   };
+  // n_increments <= 0: one solve at the load factor set by hofv_set_load_scale
   const int ninc = std::max(1, o->n_increments);
+  const double load0 = c->load;
   const double tol = o->tol > 0 ? o->tol : 1e-8;
   hofv_krylov_opts ko = o->krylov;
   ko.rtol = o->eta > 0 ? o->eta : 1e-4;
   stats->newton_iters = 0;
   stats->krylov_iters = 0;
   stats->converged = 1;
+  stats->fallbacks = 0;
   hofv_status result = HOFV_OK;
   for (int inc = 1; inc <= ninc && result == HOFV_OK; ++inc) {
-    c->load = (double)inc / ninc;
+    c->load = o->n_increments > 0 ? (double)inc / ninc : load0;
     if ((s = launch_residual(c, u, R, nullptr, nullptr, st))) { result = s; break; }
     double r0, rn;
     if ((s = host_norm(c, n, R, &r0, st))) { result = s; break; }
@@ -293,6 +311,16 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
       hofv_krylov_stats ks{};
       if ((s = fgmres_impl(c, u, R, rhs, du, &ko, &ks, st))) { result = s; break; }
       stats->krylov_iters += ks.iters;
+      stats->fallbacks += ks.fallbacks;
+      if (ko.learned && !ks.converged) {
+        // the learned correction missed the tolerance: redo the step with the plain one
+        hofv_krylov_opts kp = ko;
+        kp.learned = 0;
+        k_fill<<<nblk(n), kB, 0, st>>>(n, 0.0, du);
+        if ((s = fgmres_impl(c, u, R, rhs, du, &kp, &ks, st))) { result = s; break; }
+        stats->krylov_iters += ks.iters;
+        ++stats->fallbacks;
+      }
       double lam = 1.0, rt = 0.0;
       bool accepted = false;
       const int maxls = o->max_line_search > 0 ? o->max_line_search : 10;

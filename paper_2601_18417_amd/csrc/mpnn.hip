@@ -37,11 +37,8 @@ constexpr int kB = 256;
 
 inline unsigned nblk(int64_t n, int per = kB) { return (unsigned)((n + per - 1) / per); }
 
-__device__ inline unsigned short f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
-  return (unsigned short)(u >> 16);
-}
+// float -> bfloat16, round to nearest even (gfx950 converts natively)
+__device__ inline unsigned short f2bf(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
 __device__ inline float bf2f(unsigned short b) { return __uint_as_float((uint32_t)b << 16); }
 
 __device__ inline bf8 as_bf8(us8 v) { return __builtin_bit_cast(bf8, v); }
@@ -576,7 +573,7 @@ static hofv_status ensure_ws(hofv_ctx* c, bool train) {
   if (!w.h) {
     if ((s = dev_alloc(c, &w.x, (size_t)nc * 8))) return s;
     if ((s = dev_alloc(c, &w.h, (size_t)(kNnLayers + 1) * nc * kW))) return s;
-    if ((s = dev_alloc(c, &w.zaj, (size_t)c->D * nc))) return s;
+    if (!w.zaj && (s = dev_alloc(c, &w.zaj, (size_t)c->D * nc))) return s;
     if ((s = dev_alloc(c, &w.sc, 16))) return s;
     if ((s = dev_alloc(c, &w.dpart, 3 * 512 + 8))) return s;
   }

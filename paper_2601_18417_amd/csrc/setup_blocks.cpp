@@ -95,6 +95,9 @@ StencilBlocks make_blocks(const int32_t* st, int64_t n, int S, int64_t nc, int m
   }
   if (n > 0) B.item.push_back((int32_t)n);
   const int64_t nb = (int64_t)B.item.size() - 1;
+  B.block_of.assign(n, 0);
+  for (int64_t b = 0; b < nb; ++b)
+    for (int64_t i = B.item[b]; i < B.item[b + 1]; ++i) B.block_of[i] = (int32_t)b;
   // per block: sorted union and the position of every stencil entry in it
   B.cell.assign(nb + 1, 0);
   B.local.assign((size_t)S * n, 0);
@@ -113,7 +116,7 @@ StencilBlocks make_blocks(const int32_t* st, int64_t n, int S, int64_t nc, int m
     std::sort(u.begin(), u.end());
     for (size_t r = 0; r < u.size(); ++r) pos[u[r]] = (int32_t)r;
     for (int64_t i = B.item[b]; i < B.item[b + 1]; ++i)
-      for (int k = 0; k < S; ++k) B.local[(size_t)k * n + i] = (uint16_t)pos[st[i * S + k]];
+      for (int k = 0; k < S; ++k) B.local[B.at(i, k, 0, 1, S)] = (uint16_t)pos[st[i * S + k]];
     for (int32_t cell : u) pos[cell] = -1;
     B.cells.insert(B.cells.end(), u.begin(), u.end());
     B.cell[b + 1] = (int32_t)B.cells.size();

@@ -129,8 +129,8 @@ hofv_status build_tables(hofv_ctx* c) {
       const int m = S + (disp ? 1 : 0);
       for (int a = 0; a < D; ++a) {
         for (int k = 0; k < S; ++k) {
-          if (fold) fcoef[((size_t)k * D + a) * nf + i] += qw[q] * out[a * m + k];
-          else fcoef[(((size_t)k * nq + q) * D + a) * nf + i] = out[a * m + k];
+          if (fold) fcoef[fblk.at(i, k, a, D, S)] += qw[q] * out[a * m + k];
+          else fcoef[fblk.at(i, k, q * D + a, nq * D, S)] = out[a * m + k];
         }
         if (disp) {
           const double cg = out[a * m + S];
@@ -202,7 +202,7 @@ hofv_status build_tables(hofv_ctx* c) {
     if (!ok) singular = true;
     max_cond = std::max(max_cond, cond);
     for (int r = 0; r < nt; ++r)
-      for (int k = 0; k < S; ++k) cext[((size_t)k * NS + slots[r]) * nc + cpos[P]] = out[r * S + k];
+      for (int k = 0; k < S; ++k) cext[cblk.at(cpos[P], k, slots[r], NS, S)] = out[r * S + k];
   }
   if (singular) return fail(c, HOFV_ESINGULAR, "rank-deficient least-squares stencil at a cell centroid");
 
@@ -337,13 +337,14 @@ hofv_status build_tables(hofv_ctx* c) {
     keep("face_blk_item", fblk.item);
     keep("face_blk_cell", fblk.cell);
     keep("face_ucell", fblk.cells);
-    keep("face_local", fblk.local);
+    // per-entry tables in the plain k-major layout (the device holds them block by block)
+    keep("face_local", fblk.unblocked(fblk.local, 1, S));
     keep("cell_blk_item", cblk.item);
     keep("cell_blk_cell", cblk.cell);
     keep("cell_ucell", cblk.cells);
-    keep("cell_local", cblk.local);
-    keep("face_coef", fcoef);
-    keep("cell_extrap", cext);
+    keep("cell_local", cblk.unblocked(cblk.local, 1, S));
+    keep("face_coef", fblk.unblocked(fcoef, ncoef, S));
+    keep("cell_extrap", cblk.unblocked(cext, NS, S));
     keep("face_own", fown);
     keep("face_nei", fnei);
     keep("face_area_vec", fsv);

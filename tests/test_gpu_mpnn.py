@@ -127,3 +127,33 @@ def test_training_reduces_loss_and_iterations():
         its[learned_flag] = tot
     print("fgmres iterations plain/learned", its)
     assert its[True] < its[False]
+
+
+def test_plain_preconditioner_takes_over_from_a_nonfinite_network():
+    """A network whose output is NaN (decoder bias set to NaN on the host)
+    must not break the solvers: FGMRES redoes the iteration with the plain
+    preconditioner, reports it, and returns exactly the plain solve's result;
+    Newton converges and counts the fallbacks."""
+    from paper_2601_18417_amd import api
+    prob = w.cube_mms(8, 2, perturb=0.2, seed=21)
+    ctx = api.context_for(prob)
+    model = api.Model(5)
+    p = model.get_params()
+    p[-3:] = np.nan  # b_d, the last three parameters
+    model.set_params(p)
+    ctx.attach(model)
+    n = prob.mesh.n_cells
+    u = torch.zeros((3, n), device=DEV, dtype=torch.float64)
+    Ru = torch.empty_like(u)
+    ctx.residual(u, Ru)
+    b = torch.randn((3, n), generator=torch.Generator().manual_seed(31), dtype=torch.float64).to(DEV)
+    x_plain = torch.zeros_like(u)
+    s_plain = ctx.fgmres_solve(u, Ru, b, x_plain, rtol=1e-8, max_iters=500, learned=False)
+    x_fb = torch.zeros_like(u)
+    s_fb = ctx.fgmres_solve(u, Ru, b, x_fb, rtol=1e-8, max_iters=500, learned=True)
+    assert s_plain["fallbacks"] == 0 and s_fb["fallbacks"] == 1
+    assert s_fb["converged"] and s_fb["iters"] == s_plain["iters"]
+    assert torch.equal(x_fb, x_plain)
+    uu = torch.zeros_like(u)
+    st = ctx.newton_solve(uu, tol=1e-8, eta=1e-4, learned=True)
+    assert st["converged"] and st["fallbacks"] >= st["newton_iters"] >= 1
