@@ -75,6 +75,12 @@ typedef struct {
                              the host and keeps them for hofv_host_table (for
                              inspection on machines without a GPU); hot calls
                              then fail with HOFV_ESTATE */
+  int32_t precond_levels; /* application of the compact approximate Jacobian:
+                             1 (or 0): n_sweeps symmetric multicolour Gauss-Seidel
+                             sweeps; >= 2: a smoothed-aggregation multigrid
+                             V-cycle of at most that many levels whose finest
+                             smoother is those sweeps (n_sweeps damped Jacobi
+                             steps on coarser levels, exact coarsest solve) */
 } hofv_params;
 
 /* Creates a context on the current HIP device.  *out is NULL on failure. */
@@ -156,7 +162,7 @@ hofv_status hofv_precond_apply(hofv_ctx* ctx, const double* d_r, double* d_z, in
                                int32_t learned, void* stream);
 
 typedef struct {
-  int32_t restart;       /* m of FGMRES(m), default 30 */
+  int32_t restart;       /* m of FGMRES(m), default 30, at most 240 */
   int32_t max_iters;     /* total Krylov iterations */
   double rtol;           /* stop at ||rhs - J x|| <= rtol ||rhs|| */
   int32_t n_sweeps;      /* preconditioner sweeps per application */

@@ -23,7 +23,8 @@ class Params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("order_p", C.c_int32), ("n_plus", C.c_int32), ("n_gauss", C.c_int32),
                 ("material", C.c_int32), ("fold_quadrature", C.c_int32), ("mu", C.c_double),
                 ("lambda_", C.c_double), ("alpha", C.c_double), ("k_weight", C.c_double),
-                ("ghost_weight", C.c_double), ("stencil_quantum", C.c_double), ("host_only", C.c_int32)]
+                ("ghost_weight", C.c_double), ("stencil_quantum", C.c_double), ("host_only", C.c_int32),
+                ("precond_levels", C.c_int32)]
 
 
 class SetupReport(C.Structure):

@@ -45,10 +45,10 @@ class Context:
     """One discretisation on one device (hofv_ctx)."""
 
     def __init__(self, dim, order_p, n_plus, n_gauss, material, mu, lam, alpha=0.1, k_weight=6.0,
-                 ghost_weight=1.0, stencil_quantum=1e-12, fold_quadrature=True, host_only=False):
+                 ghost_weight=1.0, stencil_quantum=1e-12, fold_quadrature=True, host_only=False, precond_levels=1):
         self.lib = L.load()
         prm = L.Params(dim, order_p, n_plus, n_gauss, material, int(bool(fold_quadrature)), mu, lam, alpha,
-                       k_weight, ghost_weight, stencil_quantum, int(bool(host_only)))
+                       k_weight, ghost_weight, stencil_quantum, int(bool(host_only)), int(precond_levels))
         h = C.c_void_p()
         st = self.lib.hofv_create(C.byref(prm), C.byref(h))
         if st != L.HOFV_OK:
@@ -250,13 +250,13 @@ def _ctx_nn_methods():
 _ctx_nn_methods()
 
 
-def context_for(problem, fold_quadrature=True, host_only=False):
+def context_for(problem, fold_quadrature=True, host_only=False, precond_levels=1):
     """Create and set up a Context for a problem description (mesh, orders,
     material, loads as point functions), evaluating the loads at the library's
     boundary and volume quadrature points."""
     ctx = Context(problem.mesh.dim, problem.p, problem.n_plus, problem.n_gauss, problem.material, problem.mu,
                   problem.lam, problem.alpha, problem.k_weight, problem.ghost_weight, problem.stencil_quantum,
-                  fold_quadrature, host_only)
+                  fold_quadrature, host_only, precond_levels)
     ctx.set_mesh(problem.mesh.verts, problem.mesh.cells)
     cen, nor, qp = ctx.boundary_faces()
     D = problem.mesh.dim

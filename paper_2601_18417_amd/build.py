@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["api.cpp", "setup_mesh.cpp", "setup_stencil.cpp", "setup_lsq.cpp", "setup_blocks.cpp",
+HOST_SOURCES = ["api.cpp", "setup_mesh.cpp", "setup_stencil.cpp", "setup_lsq.cpp", "setup_blocks.cpp", "setup_amg.cpp",
                 "setup_tables.cpp"]
 DEVICE_SOURCES = ["kernels.hip", "krylov.hip", "mpnn.hip"]
 

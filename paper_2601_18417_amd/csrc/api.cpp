@@ -74,6 +74,8 @@ hofv_status hofv_create(const hofv_params* prm, hofv_ctx** out) {
   if (prm->material == HOFV_NEO_HOOKEAN && prm->dim != 3)
     return fail(nullptr, HOFV_EINVAL, "the neo-Hookean law needs dim = 3");
   if (!(prm->stencil_quantum > 0)) return fail(nullptr, HOFV_EINVAL, "stencil_quantum must be > 0");
+  if (prm->precond_levels < 0 || prm->precond_levels > 16)
+    return fail(nullptr, HOFV_EINVAL, "precond_levels must be 0..16");
   if (!(prm->mu > 0) || !(prm->k_weight > 0) || prm->alpha < 0 || prm->ghost_weight <= 0)
     return fail(nullptr, HOFV_EINVAL, "mu, k_weight, ghost_weight must be > 0 and alpha >= 0");
   hofv_ctx* c = new (std::nothrow) hofv_ctx();

@@ -89,6 +89,20 @@ struct DeviceTables {
   float* p_dinv = nullptr;       // [nc] 1 / A_PP
   float* p_r = nullptr;          // [D][nc]
   float* p_z = nullptr;          // [D][nc]
+  float* p_diag = nullptr;       // [nc] A_PP (multigrid residual)
+  // multigrid levels 1.. of the approximate Jacobian (empty: sweeps only);
+  // transfer operators of level l map level l (level 0 in colour-major
+  // order) to level l + 1
+  struct MgLevel {
+    int64_t n = 0;
+    int32_t *ptr = nullptr, *col = nullptr;  // off-diagonal CSR (levels >= 1)
+    float *val = nullptr, *diag = nullptr, *wdinv = nullptr;  // wdinv = (omega / rho) / a_ii
+    int32_t *p_ptr = nullptr, *p_col = nullptr, *r_ptr = nullptr, *r_col = nullptr;
+    float *p_val = nullptr, *r_val = nullptr;  // P (rows: this level) and P^T
+    float *r = nullptr, *z = nullptr, *t = nullptr;  // [D][n]
+    float* cinv = nullptr;  // coarsest level: dense inverse, column-major
+  };
+  std::vector<MgLevel> mg;  // mg[0] holds level 0's transfer operators and residual
   // face-neighbour graph of the learned correction
   int32_t* g_nbr = nullptr;      // [2D][nc] neighbour or -1
   float* g_wf = nullptr;         // [2D][nc][4] omega_PN, omega_PN e_PN,d (d = 1..3)
@@ -247,6 +261,12 @@ bool ls_functionals(int D, int p, double kshape, const double* xt, const double*
                     double* cond, double* h_out);
 int n_basis(int D, int p);
 void basis_exponents(int D, int p, int (*e)[3]);
+
+// smoothed-aggregation hierarchy of the approximate Jacobian (setup_amg.cpp):
+// a0 is level 0 in CSR (sorted columns, diagonal included) in cell order,
+// perm the colour-major order of level 0's vectors; uploads c->dev.mg
+hofv_status build_multigrid(hofv_ctx* c, const std::vector<int64_t>& ptr, const std::vector<int32_t>& col,
+                            const std::vector<double>& val, const std::vector<int32_t>& pos, int max_levels);
 
 // kernel launchers (kernels.hip)
 hofv_status launch_residual(hofv_ctx* c, const double* u, double* R, const double* Ru,

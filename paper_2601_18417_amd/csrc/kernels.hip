@@ -520,6 +520,109 @@ __global__ __launch_bounds__(kBlock) void k_pc_out(int64_t nc, const int32_t* __
   for (int c = 0; c < D; ++c) z[(int64_t)c * nc + P] = (double)z32[(int64_t)c * nc + i];
 }
 
+// ---- multigrid V-cycle on the approximate Jacobian (FP32, D right-hand sides)
+
+// t = r - A z on level 0 (2D-neighbour rows in colour-major order)
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_mg_res0(int64_t n, const int32_t* __restrict__ nbr,
+                                                    const float* __restrict__ a, const float* __restrict__ diag,
+                                                    const float* __restrict__ r, const float* __restrict__ z,
+                                                    float* __restrict__ t) {
+  constexpr int NS = 2 * D;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float di = diag[i];
+  float acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = r[(int64_t)c * n + i] - di * z[(int64_t)c * n + i];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int32_t N = nbr[(int64_t)s * n + i];
+    const float aa = a[(int64_t)s * n + i];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] -= aa * z[(int64_t)c * n + N];
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) t[(int64_t)c * n + i] = acc[c];
+}
+
+// t = r - A z on a coarse level (off-diagonal CSR + diagonal)
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_mg_res(int64_t n, const int32_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ col, const float* __restrict__ val,
+                                                   const float* __restrict__ diag, const float* __restrict__ r,
+                                                   const float* __restrict__ z, float* __restrict__ t) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float di = diag[i];
+  float acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = r[(int64_t)c * n + i] - di * z[(int64_t)c * n + i];
+  for (int32_t u = ptr[i]; u < ptr[i + 1]; ++u) {
+    const int32_t j = col[u];
+    const float v = val[u];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] -= v * z[(int64_t)c * n + j];
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) t[(int64_t)c * n + i] = acc[c];
+}
+
+// y = M x (add = 0) or y += M x (add = 1), M in CSR with ny rows over nx columns
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_mg_spmv(int64_t ny, const int32_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ col, const float* __restrict__ val,
+                                                    const float* __restrict__ x, int64_t nx, float* __restrict__ y,
+                                                    int add) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= ny) return;
+  float acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = add ? y[(int64_t)c * ny + i] : 0.0f;
+  for (int32_t u = ptr[i]; u < ptr[i + 1]; ++u) {
+    const int32_t j = col[u];
+    const float v = val[u];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] += v * x[(int64_t)c * nx + j];
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) y[(int64_t)c * ny + i] = acc[c];
+}
+
+// damped Jacobi update z += w_i t_i (t = r - A z)
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_mg_jacobi(int64_t n, const float* __restrict__ wdinv,
+                                                      const float* __restrict__ t, float* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float w = wdinv[i];
+#pragma unroll
+  for (int c = 0; c < D; ++c) z[(int64_t)c * n + i] += w * t[(int64_t)c * n + i];
+}
+
+// z = C r with the coarsest level's dense inverse C (column-major)
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_mg_dense(int64_t n, const float* __restrict__ cinv,
+                                                     const float* __restrict__ r, float* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  float acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = 0.0f;
+  for (int64_t k = 0; k < n; ++k) {
+    const float v = cinv[k * n + i];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] += v * r[(int64_t)c * n + k];
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) z[(int64_t)c * n + i] = acc[c];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_f(int64_t n, float v, float* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -628,13 +731,13 @@ hofv_status launch_axpy_w(hofv_ctx* c, const double* u, const double* v, hipStre
   return HOFV_OK;
 }
 
+// s symmetric multicolour Gauss-Seidel sweeps on level 0, continuing from p_z:
+// colours 0..C-1 then C-1..0; an immediately repeated colour is skipped
+// (cells of one colour are uncoupled, so it is a no-op)
 template <int D>
-static hofv_status precond_impl(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st) {
+static void sgs_sweeps(hofv_ctx* c, int sweeps, hipStream_t st) {
   DeviceTables& t = c->dev;
   const int64_t nc = c->nc;
-  k_pc_in<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, t.p_perm, r, t.p_r, t.p_z);
-  // symmetric sweeps: colours 0..C-1 then C-1..0; an immediately repeated
-  // colour is skipped (cells of one colour are uncoupled, so it is a no-op)
   int last = -1;
   for (int s = 0; s < sweeps; ++s) {
     for (int pass = 0; pass < 2; ++pass)
@@ -648,6 +751,56 @@ static hofv_status precond_impl(hofv_ctx* c, const double* r, double* z, int swe
                                                                                     t.p_r, t.p_z)));
       }
   }
+}
+
+// smoothing on level l: level 0 Gauss-Seidel sweeps, coarser levels damped
+// Jacobi steps (t = r - A z; z += w t)
+template <int D>
+static void mg_smooth(hofv_ctx* c, int l, int sweeps, hipStream_t st) {
+  DeviceTables& t = c->dev;
+  DeviceTables::MgLevel& m = t.mg[l];
+  if (l == 0) {
+    sgs_sweeps<D>(c, sweeps, st);
+    return;
+  }
+  for (int s = 0; s < sweeps; ++s) {
+    k_mg_res<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.ptr, m.col, m.val, m.diag, m.r, m.z, m.t);
+    k_mg_jacobi<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.wdinv, m.t, m.z);
+  }
+}
+
+// V-cycle on level l for r_l (level 0: p_r), result in z_l (level 0: p_z, zero on entry)
+template <int D>
+static void mg_vcycle(hofv_ctx* c, int l, int sweeps, hipStream_t st) {
+  DeviceTables& t = c->dev;
+  DeviceTables::MgLevel& m = t.mg[l];
+  const int nl = (int)t.mg.size();
+  float* r = l == 0 ? t.p_r : m.r;
+  float* z = l == 0 ? t.p_z : m.z;
+  if (l == nl - 1) {
+    k_mg_dense<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.cinv, r, z);
+    return;
+  }
+  if (l > 0) k_fill_f<<<blocks_for((int64_t)D * m.n), kBlock, 0, st>>>((int64_t)D * m.n, 0.0f, z);
+  mg_smooth<D>(c, l, sweeps, st);
+  if (l == 0)
+    k_mg_res0<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.p_nbr, t.p_a, t.p_diag, r, z, m.t);
+  else
+    k_mg_res<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.ptr, m.col, m.val, m.diag, r, z, m.t);
+  DeviceTables::MgLevel& q = t.mg[l + 1];
+  k_mg_spmv<D><<<blocks_for(q.n), kBlock, 0, st>>>(q.n, m.r_ptr, m.r_col, m.r_val, m.t, m.n, q.r, 0);
+  mg_vcycle<D>(c, l + 1, sweeps, st);
+  k_mg_spmv<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.p_ptr, m.p_col, m.p_val, q.z, q.n, z, 1);
+  mg_smooth<D>(c, l, sweeps, st);
+}
+
+template <int D>
+static hofv_status precond_impl(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st) {
+  DeviceTables& t = c->dev;
+  const int64_t nc = c->nc;
+  k_pc_in<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, t.p_perm, r, t.p_r, t.p_z);
+  if (t.mg.size() > 1) mg_vcycle<D>(c, 0, sweeps, st);
+  else sgs_sweeps<D>(c, sweeps, st);
   k_pc_out<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, t.p_perm, t.p_z, z);
   HOFV_HIP(c, hipGetLastError());
   return HOFV_OK;

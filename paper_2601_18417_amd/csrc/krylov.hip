@@ -24,8 +24,13 @@ namespace hofv {
 namespace {
 
 constexpr int kB = 256;
-constexpr int kMaxDots = 32;
+constexpr int kDotChunk = 32;     // vectors per multi-dot launch (accumulators in registers)
 constexpr int kDotBlocks = 256;
+constexpr int kMaxRestart = 240;  // longest FGMRES cycle
+// device scalars of the Krylov driver (K.h): Hessenberg column, ||z||^2 of a
+// learned output, the cycle's beta, the second Gram-Schmidt pass, a norm
+constexpr int kHcol = 0, kZz = kMaxRestart + 2, kBeta = kMaxRestart + 3, kH2 = kMaxRestart + 4,
+              kNorm = 2 * kMaxRestart + 6, kHsize = 2 * kMaxRestart + 8;
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
 
@@ -33,13 +38,13 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
 __global__ __launch_bounds__(kB) void k_multidot(int64_t n, int nv, const double* __restrict__ V, int64_t ld,
                                                  const double* __restrict__ w, double* __restrict__ part) {
   __shared__ double red[kB];
-  double acc[kMaxDots];
+  double acc[kDotChunk];
 #pragma unroll
-  for (int i = 0; i < kMaxDots; ++i) acc[i] = 0.0;
+  for (int i = 0; i < kDotChunk; ++i) acc[i] = 0.0;
   for (int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x; l < n; l += (int64_t)gridDim.x * kB) {
     const double x = w[l];
 #pragma unroll
-    for (int i = 0; i < kMaxDots; ++i)
+    for (int i = 0; i < kDotChunk; ++i)
       if (i < nv) acc[i] += V[(int64_t)i * ld + l] * x;
   }
   for (int i = 0; i < nv; ++i) {
@@ -108,21 +113,25 @@ __global__ __launch_bounds__(kB) void k_fill_i(int n, int v, int32_t* __restrict
 
 }  // namespace
 
-// dots of x against nv rows of V (stride ld); result on device in out[0..nv)
+// dots of x against nv rows of V (stride ld), kDotChunk rows per pass; result
+// on device in out[0..nv)
 static hofv_status dots(hofv_ctx* c, int64_t n, int nv, const double* V, int64_t ld, const double* x, double* out,
                         int accumulate, hipStream_t st) {
   const int nb = (int)std::min<int64_t>(kDotBlocks, nblk(n));
-  k_multidot<<<nb, kB, 0, st>>>(n, nv, V, ld, x, c->dev.scratch);
-  k_reduce_parts<<<nv, kB, 0, st>>>(nv, nb, c->dev.scratch, out, accumulate);
+  for (int c0 = 0; c0 < nv; c0 += kDotChunk) {
+    const int nvc = std::min(kDotChunk, nv - c0);
+    k_multidot<<<nb, kB, 0, st>>>(n, nvc, V + (int64_t)c0 * ld, ld, x, c->dev.scratch);
+    k_reduce_parts<<<nvc, kB, 0, st>>>(nvc, nb, c->dev.scratch, out + c0, accumulate);
+  }
   HOFV_HIP(c, hipGetLastError());
   return HOFV_OK;
 }
 
 static hofv_status host_norm(hofv_ctx* c, int64_t n, const double* x, double* out, hipStream_t st) {
-  hofv_status s = dots(c, n, 1, x, n, x, c->kry.h + 2 * (kMaxDots + 2), 0, st);
+  hofv_status s = dots(c, n, 1, x, n, x, c->kry.h + kNorm, 0, st);
   if (s) return s;
   double v;
-  HOFV_HIP(c, hipMemcpyAsync(&v, c->kry.h + 2 * (kMaxDots + 2), sizeof(double), hipMemcpyDeviceToHost, st));
+  HOFV_HIP(c, hipMemcpyAsync(&v, c->kry.h + kNorm, sizeof(double), hipMemcpyDeviceToHost, st));
   HOFV_HIP(c, hipStreamSynchronize(st));
   *out = std::sqrt(v);
   return HOFV_OK;
@@ -142,7 +151,7 @@ static hofv_status ensure_krylov(hofv_ctx* c, int m) {
   if ((s = dev_alloc(c, &k.V, (size_t)(m + 1) * n))) return s;
   if ((s = dev_alloc(c, &k.Z, (size_t)m * n))) return s;
   if (!k.h) {
-    if ((s = dev_alloc(c, &k.h, 4 * (kMaxDots + 2)))) return s;
+    if ((s = dev_alloc(c, &k.h, kHsize))) return s;
     if ((s = dev_alloc(c, &k.tmp, (size_t)n))) return s;
     if ((s = dev_alloc(c, &k.tmp2, (size_t)n))) return s;
   }
@@ -157,7 +166,7 @@ hofv_status precond_dispatch(hofv_ctx* c, const double* r, double* z, int sweeps
 hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const double* rhs, double* x,
                         const hofv_krylov_opts* o, hofv_krylov_stats* stats, hipStream_t st) {
   auto t0 = std::chrono::steady_clock::now();
-  const int m = std::max(1, std::min(o->restart > 0 ? o->restart : 30, kMaxDots - 1));
+  const int m = std::max(1, std::min(o->restart > 0 ? o->restart : 30, kMaxRestart));
   const int maxit = o->max_iters > 0 ? o->max_iters : 1000;
   const double rtol = o->rtol > 0 ? o->rtol : 1e-6;
   const int sweeps = o->n_sweeps > 0 ? o->n_sweeps : 2;
@@ -165,7 +174,7 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
   if (s) return s;
   Krylov& K = c->kry;
   const int64_t n = (int64_t)c->D * c->nc;
-  double* hd = K.h;  // [0, kMaxDots+2): Hessenberg column; [kMaxDots+2]: squared norm
+  double* hd = K.h;
   double bnorm, xnorm;
   if ((s = host_norm(c, n, rhs, &bnorm, st))) return s;
   if ((s = host_norm(c, n, x, &xnorm, st))) return s;
@@ -195,8 +204,8 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
     if ((s = host_norm(c, n, K.V, &beta, st))) return s;
     if (!std::isfinite(beta)) return fail(c, HOFV_ENAN, "NaN/Inf in the FGMRES residual");
     if (beta <= rtol * bnorm || it >= maxit) break;
-    k_fill<<<1, kB, 0, st>>>(1, beta, hd + kMaxDots + 3);
-    k_scale_by<<<nblk(n), kB, 0, st>>>(n, K.V, hd + kMaxDots + 3, 0, K.V);
+    k_fill<<<1, kB, 0, st>>>(1, beta, hd + kBeta);
+    k_scale_by<<<nblk(n), kB, 0, st>>>(n, K.V, hd + kBeta, 0, K.V);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int kdone = 0;
@@ -209,21 +218,20 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
         if ((s = precond_dispatch(c, vj, zj, sweeps, learned, st))) return s;
         // ||z_j||^2 of a learned output (a NaN z_j would only show up later:
         // its finite-difference product is defined to be zero)
-        if (learned && (s = dots(c, n, 1, zj, n, zj, hd + kMaxDots + 2, 0, st))) return s;
+        if (learned && (s = dots(c, n, 1, zj, n, zj, hd + kZz, 0, st))) return s;
         if ((s = jvp_impl(c, u, Ru, zj, w, 0.0, st))) return s;
         // CGS2
         if ((s = dots(c, n, j + 1, K.V, n, w, hd, 0, st))) return s;
         k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd, -1.0, w);
-        if ((s = dots(c, n, j + 1, K.V, n, w, hd + kMaxDots + 4 + 0, 0, st))) return s;
-        k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd + kMaxDots + 4, -1.0, w);
+        if ((s = dots(c, n, j + 1, K.V, n, w, hd + kH2, 0, st))) return s;
+        k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd + kH2, -1.0, w);
         if ((s = dots(c, n, 1, w, n, w, hd + j + 1, 0, st))) return s;
         k_scale_by<<<nblk(n), kB, 0, st>>>(n, w, hd + j + 1, 1, w);
         HOFV_HIP(c, hipGetLastError());
         HOFV_HIP(c, hipMemcpyAsync(hcol.data(), hd, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
-        HOFV_HIP(c, hipMemcpyAsync(h2.data(), hd + kMaxDots + 4, (j + 1) * sizeof(double), hipMemcpyDeviceToHost,
-                                   st));
+        HOFV_HIP(c, hipMemcpyAsync(h2.data(), hd + kH2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
         double zz = 0.0;
-        if (learned) HOFV_HIP(c, hipMemcpyAsync(&zz, hd + kMaxDots + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+        if (learned) HOFV_HIP(c, hipMemcpyAsync(&zz, hd + kZz, sizeof(double), hipMemcpyDeviceToHost, st));
         HOFV_HIP(c, hipStreamSynchronize(st));
         bool finite = std::isfinite(hcol[j + 1]) && std::isfinite(zz);
         for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(hcol[i] + h2[i]);
@@ -272,7 +280,7 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
                         hipStream_t st) {
   auto t0 = std::chrono::steady_clock::now();
   const int64_t n = (int64_t)c->D * c->nc;
-  hofv_status s = ensure_krylov(c, std::min(o->krylov.restart > 0 ? o->krylov.restart : 30, kMaxDots - 1));
+  hofv_status s = ensure_krylov(c, std::min(o->krylov.restart > 0 ? o->krylov.restart : 30, kMaxRestart));
   if (s) return s;
   // workspace: R, du, rhs, ut, Rt
   static thread_local std::vector<double*> none;

@@ -307,15 +307,38 @@ hofv_status build_tables(hofv_ctx* c) {
   for (int k = 0; k < ncol; ++k) c->dev.colour_start[k + 1] += c->dev.colour_start[k];
   c->dev.n_colours = ncol;
   std::vector<int32_t> pnbr((size_t)NS * nc);
-  std::vector<float> pa((size_t)NS * nc), pdinv(nc);
+  std::vector<float> pa((size_t)NS * nc), pdinv(nc), pdiag(nc);
   for (int64_t i = 0; i < nc; ++i) {
     const int64_t P = perm[i];
     pdinv[i] = (float)(1.0 / diag[P]);
+    pdiag[i] = (float)diag[P];
     for (int s = 0; s < NS; ++s) {
       int64_t N = nbr[(size_t)s * nc + P];
       pnbr[(size_t)s * nc + i] = N >= 0 ? pos[N] : (int32_t)i;
       pa[(size_t)s * nc + i] = N >= 0 ? (float)offd[(size_t)s * nc + P] : 0.0f;
     }
+  }
+
+  if (c->prm.precond_levels >= 2) {
+    // level 0 of the multigrid hierarchy: A in CSR, cell order, sorted columns
+    std::vector<int64_t> aptr(nc + 1, 0);
+    std::vector<int32_t> acol;
+    std::vector<double> aval;
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t P = 0; P < nc; ++P) {
+      row.clear();
+      row.emplace_back((int32_t)P, diag[P]);
+      for (int s = 0; s < NS; ++s)
+        if (nbr[(size_t)s * nc + P] >= 0) row.emplace_back((int32_t)nbr[(size_t)s * nc + P], offd[(size_t)s * nc + P]);
+      std::sort(row.begin(), row.end());
+      for (auto& e : row) {
+        acol.push_back(e.first);
+        aval.push_back(e.second);
+      }
+      aptr[P + 1] = (int64_t)acol.size();
+    }
+    hofv_status sm = build_multigrid(c, aptr, acol, aval, pos, c->prm.precond_levels);
+    if (sm) return sm;
   }
 
   if (c->prm.host_only) {
@@ -426,6 +449,7 @@ hofv_status build_tables(hofv_ctx* c) {
   UP(t.p_nbr, pnbr);
   UP(t.p_a, pa);
   UP(t.p_dinv, pdinv);
+  UP(t.p_diag, pdiag);
   UP(t.g_nbr, gnbr);
   UP(t.g_wf, gwf);
   UP(t.g_wb, gwb);

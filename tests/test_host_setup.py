@@ -201,3 +201,17 @@ def test_item_blocks_cover_stencils(mk):
             items = slice(bi[b], bi[b + 1])
             assert np.array_equal(un[loc[:, items]], st[:, items])
             assert np.array_equal(un, np.unique(st[:, items]))
+
+
+@pytest.mark.parametrize("mk", [lambda: w.cube_mms(12, 2, perturb=0.0), lambda: w.cube_mms(14, 2, perturb=0.2),
+                                lambda: w.cube_mms((10, 10, 10), 1, perturb=0.2, lengths=(1.0, 1.0, 0.1)),
+                                lambda: w.cantilever(shape=(60, 6, 6), p=1, n_plus=20)])
+def test_multigrid_aggregates_match_oracle(mk):
+    prob = mk()
+    disc = ores.build(prob)
+    lev = opc.hierarchy(opc.assemble(disc))
+    ctx = api.context_for(prob, host_only=True, precond_levels=8)
+    sizes = ctx.host_table("mg_sizes")
+    assert list(sizes) == [l["A"].shape[0] for l in lev]
+    for l in range(len(lev) - 1):
+        assert np.array_equal(ctx.host_table(f"mg_agg{l}"), lev[l]["agg"]), l

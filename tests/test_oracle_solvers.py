@@ -187,3 +187,76 @@ def test_mms_orders_2d():
     assert order[2] > 1.5
     assert order[3] > 3.0
     assert errs[3][2] < errs[2][2] < errs[1][2]
+
+
+def _mg_problem(kind):
+    if kind == "cube":
+        return w.cube_mms(12, 1, perturb=0.2)
+    if kind == "flat":  # cell aspect 10
+        return w.cube_mms((10, 10, 10), 1, perturb=0.2, lengths=(1.0, 1.0, 0.1))
+    return w.cantilever(shape=(48, 6, 6), p=1, n_plus=20)
+
+
+@pytest.mark.parametrize("kind", ["cube", "flat", "beam"])
+def test_multigrid_hierarchy_invariants(kind):
+    disc = rs.build(_mg_problem(kind))
+    A = pc.assemble(disc)
+    lev = pc.hierarchy(A)
+    assert len(lev) >= 2
+    for l in range(len(lev) - 1):
+        agg, P = lev[l]["agg"], lev[l]["P"]
+        nc = lev[l + 1]["A"].shape[0]
+        assert agg.min() == 0 and agg.max() == nc - 1 and np.all(np.bincount(agg) >= 1)
+        # aggregates are connected through strong couplings of their members
+        strong = pc.strong_neighbours(lev[l]["A"])
+        for J in range(0, nc, max(1, nc // 25)):
+            members = set(np.nonzero(agg == J)[0])
+            seen, todo = set(), [min(members)]
+            while todo:
+                i = todo.pop()
+                if i in seen:
+                    continue
+                seen.add(i)
+                todo += [j for j, _ in strong[i] if j in members]
+            assert seen == members
+        # P reproduces constants where T does (damped Jacobi keeps P 1 = 1 on rows of zero sum)
+        Ad = lev[l]["A"].toarray()
+        rows0 = np.abs(Ad.sum(axis=1)) <= 1e-12 * np.abs(Ad).max()
+        assert np.allclose((P @ np.ones(nc))[rows0], 1.0, atol=1e-12)
+        assert np.allclose(lev[l + 1]["A"].toarray(), P.T.toarray() @ Ad @ P.toarray(), rtol=1e-12,
+                           atol=1e-12 * np.abs(Ad).max())
+
+
+@pytest.mark.parametrize("kind", ["cube", "flat", "beam"])
+def test_multigrid_vcycle_contracts_and_is_symmetric(kind):
+    """As a stationary iteration x += V(r - A x) the V-cycle converges to
+    A^-1 r by a factor well below the Gauss-Seidel sweeps' own, and the
+    V-cycle operator is symmetric negative definite like A."""
+    disc = rs.build(_mg_problem(kind))
+    A = pc.assemble(disc)
+    lev = pc.hierarchy(A)
+    r = w.random_state(disc.n_cells, 3, 5, scale=1.0)
+    ref = np.stack([spla.spsolve(A.tocsc(), r[:, j]) for j in range(3)], axis=1)
+    x = np.zeros_like(r)
+    errs = []
+    for _ in range(6):
+        x = x + pc.vcycle(lev, r - A @ x, 2)
+        errs.append(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+    assert errs[-1] < 1e-3 and errs[-1] / errs[-2] < 0.35, errs
+    n = disc.n_cells
+    idx = np.random.default_rng(0).choice(n, 40, replace=False)
+    E = np.zeros((n, 40))
+    E[idx, np.arange(40)] = 1.0
+    M = pc.vcycle(lev, E, 2)  # columns M e_i (the same matrix acts on every column)
+    S = M[idx]
+    assert np.allclose(S, S.T, rtol=1e-9, atol=1e-12 * np.abs(S).max())
+    assert np.all(np.linalg.eigvalsh(0.5 * (S + S.T)) < 0)
+
+
+def test_multigrid_fp32_close_to_fp64():
+    disc = rs.build(_mg_problem("cube"))
+    lev = pc.hierarchy(pc.assemble(disc))
+    r = w.random_state(disc.n_cells, 3, 6, scale=1.0)
+    z64 = pc.vcycle(lev, r, 2)
+    z32 = pc.vcycle(lev, r, 2, dtype=np.float32)
+    assert np.abs(z32 - z64).max() <= 2e-5 * np.abs(z64).max()
