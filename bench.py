@@ -175,8 +175,14 @@ def study(args):
                     f"(cell aspect {1.0 / lz:g}), p={args.p}")
         nc = prob.mesh.n_cells
         t0 = time.perf_counter()
-        ctx = api.context_for(prob)
+        ctx = api.context_for(prob, precond_levels=args.precond_levels)
         t_setup = time.perf_counter() - t0
+        multigrid = args.precond_levels >= 2
+        if multigrid:
+            try:
+                ctx.set_multigrid(False)
+            except api.HofvError:
+                multigrid = False
         ctx.attach(model)
         tol = args.tol if args.tol > 0 else 1e-8
         r = torch.randn((prob.dim, nc), device=dev, dtype=torch.float64)
@@ -189,6 +195,10 @@ def study(args):
         out = {"study": "eval", "workload": desc, "n_cells": nc, "tol": tol, "setup_seconds": t_setup,
                "plain": plain, "learned": learned, "speedup": plain["seconds"] / learned["seconds"],
                "krylov_ratio": learned["krylov_iters"] / max(plain["krylov_iters"], 1)}
+        if multigrid:
+            ctx.set_multigrid(True)
+            out["multigrid"] = newton_run(torch, ctx, prob, nc, False, tol, args.max_krylov)
+            log(f"multigrid {out['multigrid']}")
     print(json.dumps(out), flush=True)
 
 
@@ -212,6 +222,9 @@ def main():
     ap.add_argument("--max-krylov", type=int, default=4000, help="Krylov iterations per Newton step")
     ap.add_argument("--calib", type=int, default=0,
                     help="run a plain 512 MiB elementwise copy first (counter calibration)")
+    ap.add_argument("--precond-levels", type=int, default=8,
+                    help="multigrid levels built for the approximate Jacobian (1: sweeps only); the plain and "
+                         "learned solves use the sweeps, a third solve the V-cycle")
     ap.add_argument("--study", choices=["train", "eval"], default=None,
                     help="learned-preconditioner study instead of the benchmark: train a model on "
                          "--train-seeds (saved to --model) or evaluate --model on one mesh")
@@ -252,9 +265,15 @@ def main():
         prob = w.square_mms(32, args.p)
     nc, D = prob.mesh.n_cells, prob.dim
     t0 = time.perf_counter()
-    ctx = api.context_for(prob)
+    ctx = api.context_for(prob, precond_levels=args.precond_levels)
     t_setup = time.perf_counter() - t0
     log(f"setup {t_setup:.1f}s report {ctx.report}")
+    multigrid = args.precond_levels >= 2
+    if multigrid:
+        try:
+            ctx.set_multigrid(False)  # the plain preconditioner is the sweeps
+        except api.HofvError:
+            multigrid = False  # too small a mesh for a second level
 
     cen = ctx.cell_centroids()
     if prob.loads.exact is not None:
@@ -332,6 +351,15 @@ def main():
         solve = {"plain": newton(False),
                  "plain_preconditioner": "compact approximate Jacobian, 2 FP32 symmetric Gauss-Seidel sweeps"}
         log(f"plain solve {solve['plain']}")
+        if multigrid:
+            ctx.set_multigrid(True)
+            if prob.n_increments == 1:
+                newton(False)
+            solve["multigrid"] = newton(False)
+            solve["multigrid_preconditioner"] = ("the same matrix by a smoothed-aggregation V-cycle "
+                                                 "(2 sweeps on the cell level, 2 Jacobi steps on coarser ones)")
+            ctx.set_multigrid(False)
+            log(f"multigrid solve {solve['multigrid']}")
         if args.learned and args.workload == "cube":
             from paper_2601_18417_amd import learned as lrn
             t0 = time.perf_counter()

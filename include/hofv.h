@@ -144,6 +144,12 @@ hofv_status hofv_setup(hofv_ctx* ctx, hofv_setup_report* report);
 /* Load factor s for load increments: u_b, tractions and f_b are scaled by s. */
 hofv_status hofv_set_load_scale(hofv_ctx* ctx, double s);
 
+/* Selects how hofv_precond_apply (and the solvers) apply the approximate
+ * Jacobian: enable != 0 uses the multigrid V-cycle built at setup
+ * (precond_levels >= 2; HOFV_EINVAL if none was built), 0 the sweeps alone.
+ * The default follows precond_levels. */
+hofv_status hofv_set_multigrid(hofv_ctx* ctx, int32_t enable);
+
 /* R = R(u) (eq. divStressDiscret with eqs. faceQuadGrad, alpha, alphaJump,
  * bodyTerm).  d_u, d_R: device [dim][n_cells]; they must not alias. */
 hofv_status hofv_residual(hofv_ctx* ctx, const double* d_u, double* d_R, void* stream);

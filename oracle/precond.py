@@ -91,7 +91,9 @@ def sgs(A, colours, r, sweeps, dtype=np.float64):
 # and adds coarse corrections.  Definitions (the library implements the same
 # rules independently):
 #
-# * strong neighbours of i: j != i with |a_ij| >= THETA sqrt(a_ii a_jj);
+# * strong neighbours of i on level l: j != i with |a_ij| >= theta_l sqrt(a_ii a_jj),
+#   theta_l = THETA / 2^l (coarse operators spread their couplings over more
+#   neighbours);
 # * aggregation, nodes visited in index order:
 #   1. i unassigned and all its strong neighbours unassigned -> new aggregate
 #      {i} + strong(i);
@@ -117,7 +119,7 @@ COARSE_SIZE = 256
 MAX_LEVELS = 8
 
 
-def strong_neighbours(A):
+def strong_neighbours(A, theta=THETA):
     A = A.tocsr()
     d = A.diagonal()
     out = []
@@ -125,15 +127,15 @@ def strong_neighbours(A):
         cols = A.indices[A.indptr[i]:A.indptr[i + 1]]
         vals = A.data[A.indptr[i]:A.indptr[i + 1]]
         keep = [(j, abs(v)) for j, v in zip(cols, vals)
-                if j != i and abs(v) >= THETA * np.sqrt(d[i] * d[j])]
+                if j != i and abs(v) >= theta * np.sqrt(d[i] * d[j])]
         out.append(sorted(keep))
     return out
 
 
-def aggregate(A):
+def aggregate(A, theta=THETA):
     """Aggregate index of every node (np.int64 array) and the number of aggregates."""
     n = A.shape[0]
-    strong = strong_neighbours(A)
+    strong = strong_neighbours(A, theta)
     agg = np.full(n, -1, np.int64)
     k = 0
     for i in range(n):  # pass 1
@@ -173,7 +175,7 @@ def hierarchy(A):
         n = A.shape[0]
         if n <= COARSE_SIZE or len(levels) == MAX_LEVELS:
             break
-        agg, nc = aggregate(A)
+        agg, nc = aggregate(A, THETA / 2 ** (len(levels) - 1))
         if nc > 0.8 * n:
             break
         T = sp.csr_matrix((np.ones(n), (np.arange(n), agg)), shape=(n, nc))

@@ -71,6 +71,7 @@ SIGNATURES = {
     "hofv_set_body_force": (ST, [P, D]),
     "hofv_setup": (ST, [P, C.POINTER(SetupReport)]),
     "hofv_set_load_scale": (ST, [P, C.c_double]),
+    "hofv_set_multigrid": (ST, [P, C.c_int32]),
     "hofv_residual": (ST, [P, P, P, P]),
     "hofv_jvp": (ST, [P, P, P, P, P, C.c_double, P]),
     "hofv_precond_apply": (ST, [P, P, P, C.c_int32, C.c_int32, P]),

@@ -122,6 +122,9 @@ class Context:
     def set_load_scale(self, s):
         self._check(self.lib.hofv_set_load_scale(self.h, float(s)))
 
+    def set_multigrid(self, enable):
+        self._check(self.lib.hofv_set_multigrid(self.h, int(bool(enable))))
+
     # ------------------------------------------------------------------- hot
     def residual(self, u, R, stream=None):
         self._check(self.lib.hofv_residual(self.h, _ptr(u), _ptr(R), _stream(stream)))

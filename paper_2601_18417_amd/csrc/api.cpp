@@ -214,6 +214,14 @@ hofv_status hofv_set_load_scale(hofv_ctx* c, double sc) {
   return HOFV_OK;
 }
 
+hofv_status hofv_set_multigrid(hofv_ctx* c, int32_t enable) {
+  hofv_status s = need(c, 4, "set_multigrid");
+  if (s) return s;
+  if (enable && c->dev.mg.size() < 2) return fail(c, HOFV_EINVAL, "no multigrid hierarchy was built at setup");
+  c->use_mg = enable != 0;
+  return HOFV_OK;
+}
+
 hofv_status hofv_residual(hofv_ctx* c, const double* d_u, double* d_R, void* stream) {
   hofv_status s = need(c, 4, "residual");
   if (s) return s;

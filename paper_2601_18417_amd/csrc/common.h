@@ -173,6 +173,7 @@ struct hofv_ctx {
 
   // timing
   bool timing = false;
+  bool use_mg = false;  // apply the approximate Jacobian by the V-cycle
   std::vector<hofv::TimerRec> timers;
   std::map<std::string, double> kernel_bytes;
 };

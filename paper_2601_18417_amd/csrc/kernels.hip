@@ -799,7 +799,7 @@ static hofv_status precond_impl(hofv_ctx* c, const double* r, double* z, int swe
   DeviceTables& t = c->dev;
   const int64_t nc = c->nc;
   k_pc_in<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, t.p_perm, r, t.p_r, t.p_z);
-  if (t.mg.size() > 1) mg_vcycle<D>(c, 0, sweeps, st);
+  if (c->use_mg && t.mg.size() > 1) mg_vcycle<D>(c, 0, sweeps, st);
   else sgs_sweeps<D>(c, sweeps, st);
   k_pc_out<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, t.p_perm, t.p_z, z);
   HOFV_HIP(c, hipGetLastError());

@@ -5,7 +5,9 @@
 // stalls the Krylov solver.  The multilevel application keeps the paper's
 // matrix, uses its FP32 sweeps as the finest smoother and adds coarse-grid
 // corrections.  Rules (levels l = 0, 1, ...; A_0 = the approximate Jacobian):
-//  * j != i is a strong neighbour of i when |a_ij| >= theta sqrt(a_ii a_jj);
+//  * j != i is a strong neighbour of i on level l when |a_ij| >= theta_l
+//    sqrt(a_ii a_jj), theta_l = theta / 2^l (coarse operators spread their
+//    couplings over more neighbours);
 //  * aggregation in index order: (1) an unassigned node whose strong
 //    neighbours are all unassigned opens an aggregate with them; (2) a node
 //    left over joins the pass-1 aggregate of its strongest strong neighbour
@@ -47,13 +49,13 @@ struct Csr {  // sorted columns per row, diagonal included
   }
 };
 
-std::vector<int32_t> aggregate(const Csr& A, int32_t* n_agg) {
+std::vector<int32_t> aggregate(const Csr& A, double theta, int32_t* n_agg) {
   const int64_t n = A.n;
   std::vector<double> d(n);
   for (int64_t i = 0; i < n; ++i) d[i] = A.diag(i);
   auto strong = [&](int64_t i, int64_t t) {
     const int32_t j = A.col[t];
-    return j != i && std::fabs(A.val[t]) >= kTheta * std::sqrt(d[i] * d[j]);
+    return j != i && std::fabs(A.val[t]) >= theta * std::sqrt(d[i] * d[j]);
   };
   std::vector<int32_t> agg(n, -1);
   int32_t k = 0;
@@ -198,7 +200,7 @@ hofv_status build_multigrid(hofv_ctx* c, const std::vector<int64_t>& ptr, const 
   while ((int)levels.size() < max_levels && levels.back().n > kCoarseSize) {
     const Csr& L = levels.back();
     int32_t nagg = 0;
-    const std::vector<int32_t> agg = aggregate(L, &nagg);
+    const std::vector<int32_t> agg = aggregate(L, kTheta / std::ldexp(1.0, (int)levels.size() - 1), &nagg);
     if (nagg > 0.8 * L.n) break;
     double r = 0.0;
     for (int64_t i = 0; i < L.n; ++i) {

@@ -339,6 +339,7 @@ hofv_status build_tables(hofv_ctx* c) {
     }
     hofv_status sm = build_multigrid(c, aptr, acol, aval, pos, c->prm.precond_levels);
     if (sm) return sm;
+    c->use_mg = c->dev.mg.size() > 1;
   }
 
   if (c->prm.host_only) {

@@ -208,7 +208,7 @@ def test_multigrid_hierarchy_invariants(kind):
         nc = lev[l + 1]["A"].shape[0]
         assert agg.min() == 0 and agg.max() == nc - 1 and np.all(np.bincount(agg) >= 1)
         # aggregates are connected through strong couplings of their members
-        strong = pc.strong_neighbours(lev[l]["A"])
+        strong = pc.strong_neighbours(lev[l]["A"], pc.THETA / 2 ** l)
         for J in range(0, nc, max(1, nc // 25)):
             members = set(np.nonzero(agg == J)[0])
             seen, todo = set(), [min(members)]
