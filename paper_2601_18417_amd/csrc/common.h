@@ -101,6 +101,7 @@ struct DeviceTables {
     float *p_val = nullptr, *r_val = nullptr;  // P (rows: this level) and P^T
     float *r = nullptr, *z = nullptr, *t = nullptr;  // [D][n]
     float* cinv = nullptr;  // coarsest level: dense inverse, column-major
+    int g_a = 1, g_p = 1, g_r = 1;  // lanes per CSR row of A, P, P^T
   };
   std::vector<MgLevel> mg;  // mg[0] holds level 0's transfer operators and residual
   // face-neighbour graph of the learned correction

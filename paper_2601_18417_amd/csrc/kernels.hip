@@ -546,47 +546,69 @@ __global__ __launch_bounds__(kBlock) void k_mg_res0(int64_t n, const int32_t* __
   for (int c = 0; c < D; ++c) t[(int64_t)c * n + i] = acc[c];
 }
 
+// CSR row products with G lanes per row (G a power of two <= 64): lane l of a
+// row's group takes entries l, l + G, ...; the partial sums are combined by
+// butterfly shuffles within the wavefront
+template <int G>
+__device__ inline float group_sum(float v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // t = r - A z on a coarse level (off-diagonal CSR + diagonal)
-template <int D>
+template <int D, int G>
 __global__ __launch_bounds__(kBlock) void k_mg_res(int64_t n, const int32_t* __restrict__ ptr,
                                                    const int32_t* __restrict__ col, const float* __restrict__ val,
                                                    const float* __restrict__ diag, const float* __restrict__ r,
                                                    const float* __restrict__ z, float* __restrict__ t) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const float di = diag[i];
+  const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  const bool live = g < n;
+  const int64_t i = live ? g : n - 1;
   float acc[D];
 #pragma unroll
-  for (int c = 0; c < D; ++c) acc[c] = r[(int64_t)c * n + i] - di * z[(int64_t)c * n + i];
-  for (int32_t u = ptr[i]; u < ptr[i + 1]; ++u) {
-    const int32_t j = col[u];
-    const float v = val[u];
+  for (int c = 0; c < D; ++c) acc[c] = 0.0f;
+  if (live)
+    for (int32_t u = ptr[i] + lane; u < ptr[i + 1]; u += G) {
+      const int32_t j = col[u];
+      const float v = val[u];
 #pragma unroll
-    for (int c = 0; c < D; ++c) acc[c] -= v * z[(int64_t)c * n + j];
-  }
+      for (int c = 0; c < D; ++c) acc[c] += v * z[(int64_t)c * n + j];
+    }
 #pragma unroll
-  for (int c = 0; c < D; ++c) t[(int64_t)c * n + i] = acc[c];
+  for (int c = 0; c < D; ++c) acc[c] = group_sum<G>(acc[c]);
+  if (!live || lane != 0) return;
+  const float di = diag[i];
+#pragma unroll
+  for (int c = 0; c < D; ++c) t[(int64_t)c * n + i] = r[(int64_t)c * n + i] - di * z[(int64_t)c * n + i] - acc[c];
 }
 
 // y = M x (add = 0) or y += M x (add = 1), M in CSR with ny rows over nx columns
-template <int D>
+template <int D, int G>
 __global__ __launch_bounds__(kBlock) void k_mg_spmv(int64_t ny, const int32_t* __restrict__ ptr,
                                                     const int32_t* __restrict__ col, const float* __restrict__ val,
                                                     const float* __restrict__ x, int64_t nx, float* __restrict__ y,
                                                     int add) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= ny) return;
+  const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  const bool live = g < ny;
+  const int64_t i = live ? g : ny - 1;
   float acc[D];
 #pragma unroll
-  for (int c = 0; c < D; ++c) acc[c] = add ? y[(int64_t)c * ny + i] : 0.0f;
-  for (int32_t u = ptr[i]; u < ptr[i + 1]; ++u) {
-    const int32_t j = col[u];
-    const float v = val[u];
+  for (int c = 0; c < D; ++c) acc[c] = 0.0f;
+  if (live)
+    for (int32_t u = ptr[i] + lane; u < ptr[i + 1]; u += G) {
+      const int32_t j = col[u];
+      const float v = val[u];
 #pragma unroll
-    for (int c = 0; c < D; ++c) acc[c] += v * x[(int64_t)c * nx + j];
-  }
+      for (int c = 0; c < D; ++c) acc[c] += v * x[(int64_t)c * nx + j];
+    }
 #pragma unroll
-  for (int c = 0; c < D; ++c) y[(int64_t)c * ny + i] = acc[c];
+  for (int c = 0; c < D; ++c) acc[c] = group_sum<G>(acc[c]);
+  if (!live || lane != 0) return;
+#pragma unroll
+  for (int c = 0; c < D; ++c) y[(int64_t)c * ny + i] = (add ? y[(int64_t)c * ny + i] : 0.0f) + acc[c];
 }
 
 // damped Jacobi update z += w_i t_i (t = r - A z)
@@ -753,6 +775,40 @@ static void sgs_sweeps(hofv_ctx* c, int sweeps, hipStream_t st) {
   }
 }
 
+template <int D>
+static void mg_res(int64_t n, const int32_t* ptr, const int32_t* col, const float* val, const float* diag,
+                   const float* r, const float* z, float* t, int g, hipStream_t st) {
+  const unsigned nb = blocks_for(n * g);
+#define RES(G) k_mg_res<D, G><<<nb, kBlock, 0, st>>>(n, ptr, col, val, diag, r, z, t)
+  switch (g) {
+    case 1: RES(1); break;
+    case 2: RES(2); break;
+    case 4: RES(4); break;
+    case 8: RES(8); break;
+    case 16: RES(16); break;
+    case 32: RES(32); break;
+    default: RES(64); break;
+  }
+#undef RES
+}
+
+template <int D>
+static void mg_spmv(int64_t ny, const int32_t* ptr, const int32_t* col, const float* val, const float* x, int64_t nx,
+                    float* y, int add, int g, hipStream_t st) {
+  const unsigned nb = blocks_for(ny * g);
+#define SPMV(G) k_mg_spmv<D, G><<<nb, kBlock, 0, st>>>(ny, ptr, col, val, x, nx, y, add)
+  switch (g) {
+    case 1: SPMV(1); break;
+    case 2: SPMV(2); break;
+    case 4: SPMV(4); break;
+    case 8: SPMV(8); break;
+    case 16: SPMV(16); break;
+    case 32: SPMV(32); break;
+    default: SPMV(64); break;
+  }
+#undef SPMV
+}
+
 // smoothing on level l: level 0 Gauss-Seidel sweeps, coarser levels damped
 // Jacobi steps (t = r - A z; z += w t)
 template <int D>
@@ -764,7 +820,7 @@ static void mg_smooth(hofv_ctx* c, int l, int sweeps, hipStream_t st) {
     return;
   }
   for (int s = 0; s < sweeps; ++s) {
-    k_mg_res<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.ptr, m.col, m.val, m.diag, m.r, m.z, m.t);
+    mg_res<D>(m.n, m.ptr, m.col, m.val, m.diag, m.r, m.z, m.t, m.g_a, st);
     k_mg_jacobi<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.wdinv, m.t, m.z);
   }
 }
@@ -786,11 +842,11 @@ static void mg_vcycle(hofv_ctx* c, int l, int sweeps, hipStream_t st) {
   if (l == 0)
     k_mg_res0<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.p_nbr, t.p_a, t.p_diag, r, z, m.t);
   else
-    k_mg_res<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.ptr, m.col, m.val, m.diag, r, z, m.t);
+    mg_res<D>(m.n, m.ptr, m.col, m.val, m.diag, r, z, m.t, m.g_a, st);
   DeviceTables::MgLevel& q = t.mg[l + 1];
-  k_mg_spmv<D><<<blocks_for(q.n), kBlock, 0, st>>>(q.n, m.r_ptr, m.r_col, m.r_val, m.t, m.n, q.r, 0);
+  mg_spmv<D>(q.n, m.r_ptr, m.r_col, m.r_val, m.t, m.n, q.r, 0, m.g_r, st);
   mg_vcycle<D>(c, l + 1, sweeps, st);
-  k_mg_spmv<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.p_ptr, m.p_col, m.p_val, q.z, q.n, z, 1);
+  mg_spmv<D>(m.n, m.p_ptr, m.p_col, m.p_val, q.z, q.n, z, 1, m.g_p, st);
   mg_smooth<D>(c, l, sweeps, st);
 }
 

@@ -177,6 +177,14 @@ bool invert(std::vector<double>& a, int64_t n) {
   return true;
 }
 
+// lanes per CSR row in the kernels: the power of two nearest above the average row length
+int lanes(size_t nnz, int64_t rows) {
+  const double avg = rows > 0 ? (double)nnz / (double)rows : 1.0;
+  int g = 1;
+  while (g < 64 && g < avg) g <<= 1;
+  return g;
+}
+
 template <class T, class U>
 std::vector<T> cast(const std::vector<U>& v) {
   return std::vector<T>(v.begin(), v.end());
@@ -264,6 +272,7 @@ hofv_status build_multigrid(hofv_ctx* c, const std::vector<int64_t>& ptr, const 
         dg[i] = (float)L.diag(i);
         wd[i] = l < nl - 1 ? (float)((kOmega / rho[l]) / L.diag(i)) : 0.0f;
       }
+      m.g_a = lanes(oc.size(), L.n);
       UPV(m.ptr, op);
       UPV(m.col, oc);
       UPV(m.val, ov);
@@ -291,6 +300,8 @@ hofv_status build_multigrid(hofv_ctx* c, const std::vector<int64_t>& ptr, const 
       std::vector<int32_t> rp(Pt.ptr.size()), rc(Pt.col.size());
       for (size_t k = 0; k < Pt.ptr.size(); ++k) rp[k] = (int32_t)Pt.ptr[k];
       for (size_t k = 0; k < Pt.col.size(); ++k) rc[k] = l == 0 ? pos[Pt.col[k]] : Pt.col[k];
+      m.g_p = lanes(pc.size(), L.n);
+      m.g_r = lanes(rc.size(), levels[l + 1].n);
       UPV(m.p_ptr, pp);
       UPV(m.p_col, pc);
       UPV(m.p_val, pv);
