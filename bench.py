@@ -165,17 +165,20 @@ def study(args):
     else:
         model = api.Model(0)
         model.set_params(np.load(args.model))
+        t0 = time.perf_counter()
         if args.workload == "cantilever":
             prob = w.cantilever(p=args.p)
             desc = f"neo-Hookean cantilever 200x20x20, p={args.p}, 10 increments"
         else:
             lz = args.lz
             prob = w.cube_mms(args.n, args.p, perturb=0.2, seed=args.seed, lengths=(1.0, 1.0, lz))
+        log(f"mesh generated {time.perf_counter() - t0:.0f}s")
             desc = (f"LE MMS {args.n}^3 perturbed +-20% (seed {args.seed}) on [0,1]^2 x [0,{lz}] "
                     f"(cell aspect {1.0 / lz:g}), p={args.p}")
         nc = prob.mesh.n_cells
         t0 = time.perf_counter()
-        ctx = api.context_for(prob, precond_levels=args.precond_levels)
+        ctx = api.context_for(prob, precond_levels=args.precond_levels,
+                              progress=lambda s: log(f"  {s} {time.perf_counter() - t0:.0f}s"))
         t_setup = time.perf_counter() - t0
         multigrid = args.precond_levels >= 2
         if multigrid:

@@ -253,14 +253,17 @@ def _ctx_nn_methods():
 _ctx_nn_methods()
 
 
-def context_for(problem, fold_quadrature=True, host_only=False, precond_levels=1):
+def context_for(problem, fold_quadrature=True, host_only=False, precond_levels=1, progress=None):
     """Create and set up a Context for a problem description (mesh, orders,
     material, loads as point functions), evaluating the loads at the library's
-    boundary and volume quadrature points."""
+    boundary and volume quadrature points.  progress(stage) is called after
+    each stage when given."""
+    note = progress or (lambda stage: None)
     ctx = Context(problem.mesh.dim, problem.p, problem.n_plus, problem.n_gauss, problem.material, problem.mu,
                   problem.lam, problem.alpha, problem.k_weight, problem.ghost_weight, problem.stencil_quantum,
                   fold_quadrature, host_only, precond_levels)
     ctx.set_mesh(problem.mesh.verts, problem.mesh.cells)
+    note("mesh")
     cen, nor, qp = ctx.boundary_faces()
     D = problem.mesh.dim
     loads = problem.loads
@@ -270,7 +273,10 @@ def context_for(problem, fold_quadrature=True, host_only=False, precond_levels=1
     ubc = loads.u_b(cen) if nb else None
     tq = loads.traction(qp.reshape(-1, D), np.repeat(nor, nq, axis=0)).reshape(nb, nq, D) if nb else None
     ctx.set_bc(types, ubq, ubc, tq)
+    note("boundary conditions")
     vq = ctx.volume_qpoints()
     ctx.set_body_force(loads.body(vq.reshape(-1, D)).reshape(vq.shape))
+    note("body force")
     ctx.setup()
+    note("setup")
     return ctx
