@@ -172,9 +172,9 @@ def study(args):
         else:
             lz = args.lz
             prob = w.cube_mms(args.n, args.p, perturb=0.2, seed=args.seed, lengths=(1.0, 1.0, lz))
-        log(f"mesh generated {time.perf_counter() - t0:.0f}s")
             desc = (f"LE MMS {args.n}^3 perturbed +-20% (seed {args.seed}) on [0,1]^2 x [0,{lz}] "
                     f"(cell aspect {1.0 / lz:g}), p={args.p}")
+        log(f"mesh generated {time.perf_counter() - t0:.0f}s")
         nc = prob.mesh.n_cells
         t0 = time.perf_counter()
         ctx = api.context_for(prob, precond_levels=args.precond_levels,

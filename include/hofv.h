@@ -186,7 +186,10 @@ typedef struct {
 
 /* Solves J(u) x = rhs by right-preconditioned flexible GMRES(m) with J v from
  * hofv_jvp and z = M(v) from hofv_precond_apply; x holds the initial guess on
- * entry.  Synchronises once per iteration (Hessenberg column to the host).
+ * entry.  Iterations are queued eight at a time and the host reads their
+ * Hessenberg columns at once (Givens rotations on the host); columns past the
+ * converged iteration are discarded, so up to seven extra iterations of work
+ * may be spent at the end of a solve.
  * With opts->learned, an iteration whose Hessenberg column is not finite is
  * redone with the plain preconditioner, which is then kept for the rest of
  * the solve (counted in stats->fallbacks). */

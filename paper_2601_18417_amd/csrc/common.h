@@ -119,6 +119,8 @@ struct Krylov {
   double* tmp = nullptr; // [n]
   double* tmp2 = nullptr;
   double* hbuf = nullptr;  // pinned host copy
+  double* Hd = nullptr;    // device Hessenberg columns of a cycle, column-major [m][m + 1]
+  double* zz = nullptr;    // squared norms of learned preconditioner outputs [m]
 };
 
 }  // namespace hofv

@@ -3,8 +3,9 @@
 // FGMRES(m) with right preconditioning (Saad's flexible variant) and
 // classical Gram-Schmidt applied twice: per iteration z_j = M(v_j),
 // w = J z_j (finite-difference product), h = V^T w and w -= V h twice,
-// v_{j+1} = w / ||w||.  The Hessenberg column (j + 2 numbers) is the only
-// device-to-host transfer of an iteration; Givens rotations run on the host.
+// v_{j+1} = w / ||w||.  Hessenberg columns stay on the device; the host reads
+// them every kCheck iterations and applies the Givens rotations, so the GPU
+// does not wait for the host between iterations.
 // Dot products are deterministic: fixed block partials reduced in fixed order.
 //
 // Newton (Sec. 4.1 with the Armijo backtracking reading of the line search):
@@ -27,6 +28,7 @@ constexpr int kB = 256;
 constexpr int kDotChunk = 32;     // vectors per multi-dot launch (accumulators in registers)
 constexpr int kDotBlocks = 256;
 constexpr int kMaxRestart = 240;  // longest FGMRES cycle
+constexpr int kCheck = 8;         // FGMRES iterations queued between host reads
 // device scalars of the Krylov driver (K.h): Hessenberg column, ||z||^2 of a
 // learned output, the cycle's beta, the second Gram-Schmidt pass, a norm
 constexpr int kHcol = 0, kZz = kMaxRestart + 2, kBeta = kMaxRestart + 3, kH2 = kMaxRestart + 4,
@@ -111,6 +113,16 @@ __global__ __launch_bounds__(kB) void k_fill_i(int n, int v, int32_t* __restrict
   if (l < n) z[l] = v;
 }
 
+// H[:, j] of the Arnoldi process from the Gram-Schmidt scalars: h_i = first +
+// second pass (i <= j), h_{j+1} = ||w||; zz (a learned output's squared norm) too
+__global__ void k_store_column(int j, const double* __restrict__ hd, int ldh, double* __restrict__ H,
+                               double* __restrict__ zz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= j) H[(int64_t)j * ldh + i] = hd[kHcol + i] + hd[kH2 + i];
+  if (i == j + 1) H[(int64_t)j * ldh + i] = sqrt(hd[kHcol + j + 1]);
+  if (i == 0) zz[j] = hd[kZz];
+}
+
 }  // namespace
 
 // dots of x against nv rows of V (stride ld), kDotChunk rows per pass; result
@@ -150,6 +162,10 @@ static hofv_status ensure_krylov(hofv_ctx* c, int m) {
   hofv_status s;
   if ((s = dev_alloc(c, &k.V, (size_t)(m + 1) * n))) return s;
   if ((s = dev_alloc(c, &k.Z, (size_t)m * n))) return s;
+  if (!k.Hd) {
+    if ((s = dev_alloc(c, &k.Hd, (size_t)(kMaxRestart + 1) * kMaxRestart))) return s;
+    if ((s = dev_alloc(c, &k.zz, (size_t)kMaxRestart))) return s;
+  }
   if (!k.h) {
     if ((s = dev_alloc(c, &k.h, kHsize))) return s;
     if ((s = dev_alloc(c, &k.tmp, (size_t)n))) return s;
@@ -190,7 +206,7 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
     HOFV_HIP(c, hipStreamSynchronize(st));
     return HOFV_OK;
   }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hcol(m + 2);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   int it = 0;
   double beta = 0;
   for (;;) {
@@ -209,55 +225,75 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int kdone = 0;
-    for (int j = 0; j < m; ++j) {
+    // Iterations are queued kCheck at a time; their Hessenberg columns stay on
+    // the device until the host reads them all at once and applies the Givens
+    // rotations.  Columns past the converged one are discarded; a non-finite
+    // column (a learned output gone bad) rolls back to that iteration, which
+    // is redone with the plain preconditioner.
+    int j = 0, jp = 0;  // next iteration to queue / to process on the host
+    bool done = false;
+    std::vector<double> hblk((size_t)(m + 1) * kCheck), zzb(kCheck);
+    while (!done) {
       double* vj = K.V + (size_t)j * n;
       double* zj = K.Z + (size_t)j * n;
       double* w = K.V + (size_t)(j + 1) * n;
-      std::vector<double> h2(j + 1);
-      for (;;) {
-        if ((s = precond_dispatch(c, vj, zj, sweeps, learned, st))) return s;
-        // ||z_j||^2 of a learned output (a NaN z_j would only show up later:
-        // its finite-difference product is defined to be zero)
-        if (learned && (s = dots(c, n, 1, zj, n, zj, hd + kZz, 0, st))) return s;
-        if ((s = jvp_impl(c, u, Ru, zj, w, 0.0, st))) return s;
-        // CGS2
-        if ((s = dots(c, n, j + 1, K.V, n, w, hd, 0, st))) return s;
-        k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd, -1.0, w);
-        if ((s = dots(c, n, j + 1, K.V, n, w, hd + kH2, 0, st))) return s;
-        k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd + kH2, -1.0, w);
-        if ((s = dots(c, n, 1, w, n, w, hd + j + 1, 0, st))) return s;
-        k_scale_by<<<nblk(n), kB, 0, st>>>(n, w, hd + j + 1, 1, w);
-        HOFV_HIP(c, hipGetLastError());
-        HOFV_HIP(c, hipMemcpyAsync(hcol.data(), hd, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
-        HOFV_HIP(c, hipMemcpyAsync(h2.data(), hd + kH2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-        double zz = 0.0;
-        if (learned) HOFV_HIP(c, hipMemcpyAsync(&zz, hd + kZz, sizeof(double), hipMemcpyDeviceToHost, st));
-        HOFV_HIP(c, hipStreamSynchronize(st));
-        bool finite = std::isfinite(hcol[j + 1]) && std::isfinite(zz);
-        for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(hcol[i] + h2[i]);
-        if (finite) break;
-        if (!learned) return fail(c, HOFV_ENAN, "NaN/Inf in Arnoldi");
-        learned = 0;  // the plain preconditioner takes over for the rest of the solve
-        ++stats->fallbacks;
+      if ((s = precond_dispatch(c, vj, zj, sweeps, learned, st))) return s;
+      // ||z_j||^2 of a learned output (a NaN z_j would only show up later:
+      // its finite-difference product is defined to be zero)
+      if (learned && (s = dots(c, n, 1, zj, n, zj, hd + kZz, 0, st))) return s;
+      if ((s = jvp_impl(c, u, Ru, zj, w, 0.0, st))) return s;
+      // CGS2
+      if ((s = dots(c, n, j + 1, K.V, n, w, hd, 0, st))) return s;
+      k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd, -1.0, w);
+      if ((s = dots(c, n, j + 1, K.V, n, w, hd + kH2, 0, st))) return s;
+      k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd + kH2, -1.0, w);
+      if ((s = dots(c, n, 1, w, n, w, hd + j + 1, 0, st))) return s;
+      k_scale_by<<<nblk(n), kB, 0, st>>>(n, w, hd + j + 1, 1, w);
+      k_store_column<<<(unsigned)((j + 2 + kB - 1) / kB), kB, 0, st>>>(j, hd, m + 1, K.Hd, K.zz);
+      HOFV_HIP(c, hipGetLastError());
+      ++j;
+      if (j - jp < kCheck && j < m && it + (j - jp) < maxit) continue;
+      const int nq = j - jp;
+      HOFV_HIP(c, hipMemcpyAsync(hblk.data(), K.Hd + (size_t)jp * (m + 1), (size_t)nq * (m + 1) * sizeof(double),
+                                 hipMemcpyDeviceToHost, st));
+      HOFV_HIP(c, hipMemcpyAsync(zzb.data(), K.zz + jp, nq * sizeof(double), hipMemcpyDeviceToHost, st));
+      HOFV_HIP(c, hipStreamSynchronize(st));
+      int redo = -1;
+      for (int q = 0; q < nq && !done; ++q) {
+        const int jj = jp + q;
+        const double* col = &hblk[(size_t)q * (m + 1)];
+        bool finite = !learned || std::isfinite(zzb[q]);
+        for (int i = 0; i <= jj + 1; ++i) finite = finite && std::isfinite(col[i]);
+        if (!finite) {
+          if (!learned) return fail(c, HOFV_ENAN, "NaN/Inf in Arnoldi");
+          learned = 0;  // the plain preconditioner takes over for the rest of the solve
+          ++stats->fallbacks;
+          redo = jj;
+          break;
+        }
+        for (int i = 0; i <= jj + 1; ++i) H[(size_t)i * m + jj] = col[i];
+        for (int i = 0; i < jj; ++i) {
+          const double a = H[(size_t)i * m + jj], b = H[(size_t)(i + 1) * m + jj];
+          H[(size_t)i * m + jj] = cs[i] * a + sn[i] * b;
+          H[(size_t)(i + 1) * m + jj] = -sn[i] * a + cs[i] * b;
+        }
+        const double a = H[(size_t)jj * m + jj], b = H[(size_t)(jj + 1) * m + jj];
+        const double den = std::hypot(a, b);
+        cs[jj] = den > 0 ? a / den : 1.0;
+        sn[jj] = den > 0 ? b / den : 0.0;
+        H[(size_t)jj * m + jj] = den;
+        H[(size_t)(jj + 1) * m + jj] = 0.0;
+        g[jj + 1] = -sn[jj] * g[jj];
+        g[jj] = cs[jj] * g[jj];
+        ++it;
+        kdone = jj + 1;
+        if (std::fabs(g[jj + 1]) <= rtol * bnorm || it >= maxit || den == 0.0 || kdone == m) done = true;
       }
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i] + h2[i];
-      H[(size_t)(j + 1) * m + j] = std::sqrt(hcol[j + 1]);
-      for (int i = 0; i < j; ++i) {
-        const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
-        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      if (redo >= 0) {
+        j = jp = redo;
+        continue;
       }
-      const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
-      const double den = std::hypot(a, b);
-      cs[j] = den > 0 ? a / den : 1.0;
-      sn[j] = den > 0 ? b / den : 0.0;
-      H[(size_t)j * m + j] = den;
-      H[(size_t)(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++it;
-      kdone = j + 1;
-      if (std::fabs(g[j + 1]) <= rtol * bnorm || it >= maxit || den == 0.0) break;
+      jp = j;
     }
     for (int i = kdone - 1; i >= 0; --i) {
       double sum = g[i];

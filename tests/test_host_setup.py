@@ -215,3 +215,9 @@ def test_multigrid_aggregates_match_oracle(mk):
     assert list(sizes) == [l["A"].shape[0] for l in lev]
     for l in range(len(lev) - 1):
         assert np.array_equal(ctx.host_table(f"mg_agg{l}"), lev[l]["agg"]), l
+
+
+def test_bench_and_entry_points_compile(repo_root):
+    import py_compile
+    for f in ("bench.py", "__graft_entry__.py"):
+        py_compile.compile(os.path.join(repo_root, f), doraise=True)
