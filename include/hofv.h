@@ -192,7 +192,8 @@ typedef struct {
  * may be spent at the end of a solve.
  * With opts->learned, an iteration whose Hessenberg column is not finite is
  * redone with the plain preconditioner, which is then kept for the rest of
- * the solve (counted in stats->fallbacks). */
+ * the solve; so is a restart cycle that reduced the residual by less than a
+ * factor 0.75 (both counted in stats->fallbacks). */
 hofv_status hofv_fgmres_solve(hofv_ctx* ctx, const double* d_u, const double* d_Ru,
                               const double* d_rhs, double* d_x, const hofv_krylov_opts* opts,
                               hofv_krylov_stats* stats, void* stream);

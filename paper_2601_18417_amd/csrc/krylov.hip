@@ -29,6 +29,7 @@ constexpr int kDotChunk = 32;     // vectors per multi-dot launch (accumulators 
 constexpr int kDotBlocks = 256;
 constexpr int kMaxRestart = 240;  // longest FGMRES cycle
 constexpr int kCheck = 8;         // FGMRES iterations queued between host reads
+constexpr double kLearnedCycle = 0.75;  // slowest accepted residual reduction of a learned cycle
 // device scalars of the Krylov driver (K.h): Hessenberg column, ||z||^2 of a
 // learned output, the cycle's beta, the second Gram-Schmidt pass, a norm
 constexpr int kHcol = 0, kZz = kMaxRestart + 2, kBeta = kMaxRestart + 3, kH2 = kMaxRestart + 4,
@@ -208,7 +209,7 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
   }
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   int it = 0;
-  double beta = 0;
+  double beta = 0, beta_cycle = -1.0;
   for (;;) {
     // V_0 = rhs - J x
     if (xnorm > 0) {
@@ -220,6 +221,13 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
     if ((s = host_norm(c, n, K.V, &beta, st))) return s;
     if (!std::isfinite(beta)) return fail(c, HOFV_ENAN, "NaN/Inf in the FGMRES residual");
     if (beta <= rtol * bnorm || it >= maxit) break;
+    // a learned correction whose last full cycle reduced the residual by less
+    // than kLearnedCycle hands the rest of the solve to the plain preconditioner
+    if (learned && beta_cycle > 0.0 && beta > kLearnedCycle * beta_cycle) {
+      learned = 0;
+      ++stats->fallbacks;
+    }
+    beta_cycle = beta;
     k_fill<<<1, kB, 0, st>>>(1, beta, hd + kBeta);
     k_scale_by<<<nblk(n), kB, 0, st>>>(n, K.V, hd + kBeta, 0, K.V);
     std::fill(g.begin(), g.end(), 0.0);
