@@ -105,9 +105,33 @@ def parse_seeds(s):
     return out
 
 
-def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None):
+def newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, max_newton, label):
+    """One library Newton step per call, each logged as it ends (long solves
+    stay visible); stops at ||R|| <= tol ||R_0||."""
+    R = torch.empty_like(uu)
+    ctx.residual(uu, R)
+    r0 = float(torch.linalg.norm(R))
+    tot = {"newton_iters": 0, "krylov_iters": 0, "fallbacks": 0, "converged": False, "rel_residual": 1.0}
+    t0 = time.perf_counter()
+    for step in range(max_newton):
+        st = ctx.newton_solve(uu, tol=1e-300, eta=1e-4, max_newton=1, max_krylov=max_krylov, n_sweeps=2,
+                              learned=learned, check=False, n_increments=0)
+        for key in ("newton_iters", "krylov_iters", "fallbacks"):
+            tot[key] += st[key]
+        ctx.residual(uu, R)
+        tot["rel_residual"] = float(torch.linalg.norm(R)) / r0
+        log(f"{label} step {step}: {st['krylov_iters']} Krylov, rel {tot['rel_residual']:.2e}, "
+            f"{time.perf_counter() - t0:.1f}s")
+        if tot["rel_residual"] <= tol:
+            tot["converged"] = True
+            break
+    return tot
+
+
+def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None, stepwise=0):
     """Newton from u = 0 through the problem's load increments (each one a
-    library Newton solve at its load factor, logged as it ends)."""
+    library Newton solve at its load factor, logged as it ends; with
+    stepwise > 0, one logged call per Newton step, at most that many steps)."""
     uu = torch.zeros((prob.dim, nc), device="cuda:0", dtype=torch.float64) if u_out is None else u_out.zero_()
     ninc = max(1, prob.n_increments)
     out = {"newton_iters": 0, "krylov_iters": 0, "fallbacks": 0, "converged": True, "rel_residual": 0.0}
@@ -115,8 +139,12 @@ def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None):
     t0 = time.perf_counter()
     for inc in range(1, ninc + 1):
         ctx.set_load_scale(inc / ninc)
-        st = ctx.newton_solve(uu, tol=tol, eta=1e-4, max_krylov=max_krylov, n_sweeps=2, learned=learned,
-                              check=False, n_increments=0)
+        if stepwise:
+            st = newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, stepwise,
+                                 f"{'learned' if learned else 'plain'} increment {inc}")
+        else:
+            st = ctx.newton_solve(uu, tol=tol, eta=1e-4, max_krylov=max_krylov, n_sweeps=2, learned=learned,
+                                  check=False, n_increments=0)
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             out[key] += st[key]
         out["rel_residual"] = st["rel_residual"]
@@ -191,16 +219,16 @@ def study(args):
         r = torch.randn((prob.dim, nc), device=dev, dtype=torch.float64)
         z = torch.empty_like(r)
         ctx.precond_apply(r, z, learned=True)  # allocates the network's workspace
-        plain = newton_run(torch, ctx, prob, nc, False, tol, args.max_krylov)
+        plain = newton_run(torch, ctx, prob, nc, False, tol, args.max_krylov, stepwise=args.max_newton)
         log(f"plain {plain}")
-        learned = newton_run(torch, ctx, prob, nc, True, tol, args.max_krylov)
+        learned = newton_run(torch, ctx, prob, nc, True, tol, args.max_krylov, stepwise=args.max_newton)
         log(f"learned {learned}")
         out = {"study": "eval", "workload": desc, "n_cells": nc, "tol": tol, "setup_seconds": t_setup,
                "plain": plain, "learned": learned, "speedup": plain["seconds"] / learned["seconds"],
                "krylov_ratio": learned["krylov_iters"] / max(plain["krylov_iters"], 1)}
         if multigrid:
             ctx.set_multigrid(True)
-            out["multigrid"] = newton_run(torch, ctx, prob, nc, False, tol, args.max_krylov)
+            out["multigrid"] = newton_run(torch, ctx, prob, nc, False, tol, args.max_krylov, stepwise=args.max_newton)
             log(f"multigrid {out['multigrid']}")
     print(json.dumps(out), flush=True)
 
@@ -236,6 +264,7 @@ def main():
     ap.add_argument("--harvest-length", type=int, default=9)
     ap.add_argument("--model", default="gpurun_out/learned_model.npy")
     ap.add_argument("--seed", type=int, default=50, help="mesh seed of --study eval")
+    ap.add_argument("--max-newton", type=int, default=10, help="Newton steps per increment in --study eval")
     ap.add_argument("--lz", type=float, default=1.0, help="z extent of the evaluation cube (cell aspect 1/lz)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -66,7 +66,10 @@ __device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t 
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-constexpr int kNt = 2;  // nontemporal cache policy of a buffer load
+#ifndef HOFV_NT
+#define HOFV_NT 2
+#endif
+constexpr int kNt = HOFV_NT;  // cache policy bits of the coefficient-stream buffer loads (2: nontemporal)
 
 // Copies the stencil union of item block b into LDS, one plane per
 // component: lds[j][r] = u_j(ucell[blk_cell[b] + r]).
