@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # passes (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, factors from a plain 512 MiB
 # elementwise copy), valid only for the kernel and table-layout sources whose
 # combined sha256 has this prefix.
-MEASURED_TRAFFIC = {"kernel": "k_face_le", "n": 64, "p": 3, "bytes": 1912341390.2,
-                    "kernels_sha256": "7fea70fcbc3bf7da"}
+MEASURED_TRAFFIC = {"kernel": "k_face_le", "n": 64, "p": 3, "bytes": 1913467735.9,
+                    "kernels_sha256": "83fff6effb9ccdc1"}
 TRAFFIC_SOURCES = ("kernels.hip", "common.h", "setup_blocks.cpp", "setup_tables.cpp")
 
 
@@ -105,6 +105,9 @@ def parse_seeds(s):
     return out
 
 
+KRYLOV = {"eta": 1e-4, "restart": 30}  # Newton's Krylov tolerance and FGMRES cycle (set from the arguments)
+
+
 def newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, max_newton, label):
     """One library Newton step per call, each logged as it ends (long solves
     stay visible); stops at ||R|| <= tol ||R_0||."""
@@ -114,8 +117,8 @@ def newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, max_newton, label)
     tot = {"newton_iters": 0, "krylov_iters": 0, "fallbacks": 0, "converged": False, "rel_residual": 1.0}
     t0 = time.perf_counter()
     for step in range(max_newton):
-        st = ctx.newton_solve(uu, tol=1e-300, eta=1e-4, max_newton=1, max_krylov=max_krylov, n_sweeps=2,
-                              learned=learned, check=False, n_increments=0)
+        st = ctx.newton_solve(uu, tol=1e-300, eta=KRYLOV["eta"], max_newton=1, max_krylov=max_krylov, n_sweeps=2,
+                              learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"])
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             tot[key] += st[key]
         ctx.residual(uu, R)
@@ -143,8 +146,8 @@ def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None, stepw
             st = newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, stepwise,
                                  f"{'learned' if learned else 'plain'} increment {inc}")
         else:
-            st = ctx.newton_solve(uu, tol=tol, eta=1e-4, max_krylov=max_krylov, n_sweeps=2, learned=learned,
-                                  check=False, n_increments=0)
+            st = ctx.newton_solve(uu, tol=tol, eta=KRYLOV["eta"], max_krylov=max_krylov, n_sweeps=2,
+                                  learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"])
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             out[key] += st[key]
         out["rel_residual"] = st["rel_residual"]
@@ -265,8 +268,14 @@ def main():
     ap.add_argument("--model", default="gpurun_out/learned_model.npy")
     ap.add_argument("--seed", type=int, default=50, help="mesh seed of --study eval")
     ap.add_argument("--max-newton", type=int, default=10, help="Newton steps per increment in --study eval")
+    ap.add_argument("--eta", type=float, default=1e-4, help="Krylov tolerance of each Newton step")
+    ap.add_argument("--restart", type=int, default=30, help="FGMRES cycle length (at most 240)")
+    ap.add_argument("--stepwise", type=int, default=0,
+                    help="time-to-tolerance solves as one logged library Newton step per call, at most this many "
+                         "steps per increment (0: one library call per increment)")
     ap.add_argument("--lz", type=float, default=1.0, help="z extent of the evaluation cube (cell aspect 1/lz)")
     args = ap.parse_args()
+    KRYLOV["eta"], KRYLOV["restart"] = args.eta, args.restart
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built",
               file=sys.stderr)
@@ -366,7 +375,7 @@ def main():
         uu = torch.zeros_like(u)
         out = newton_run(torch, ctx, prob, nc, learned,
                          args.tol if args.tol > 0 else (1e-10 if args.workload == "square" else 1e-8),
-                         args.max_krylov, u_out=uu)
+                         args.max_krylov, u_out=uu, stepwise=args.stepwise)
         ctx.set_load_scale(1.0)
         if args.workload == "cantilever":
             # mean transverse displacement of the last layer of cells / length
