@@ -105,7 +105,7 @@ def parse_seeds(s):
     return out
 
 
-KRYLOV = {"eta": 1e-4, "restart": 30}  # Newton's Krylov tolerance and FGMRES cycle (set from the arguments)
+KRYLOV = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0}  # Newton's Krylov options (set from the arguments)
 
 
 def newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, max_newton, label):
@@ -118,7 +118,8 @@ def newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, max_newton, label)
     t0 = time.perf_counter()
     for step in range(max_newton):
         st = ctx.newton_solve(uu, tol=1e-300, eta=KRYLOV["eta"], max_newton=1, max_krylov=max_krylov, n_sweeps=2,
-                              learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"])
+                              learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"],
+                              max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"])
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             tot[key] += st[key]
         ctx.residual(uu, R)
@@ -147,7 +148,8 @@ def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None, stepw
                                  f"{'learned' if learned else 'plain'} increment {inc}")
         else:
             st = ctx.newton_solve(uu, tol=tol, eta=KRYLOV["eta"], max_krylov=max_krylov, n_sweeps=2,
-                                  learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"])
+                                  learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"],
+                                  max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"])
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             out[key] += st[key]
         out["rel_residual"] = st["rel_residual"]
@@ -269,13 +271,23 @@ def main():
     ap.add_argument("--seed", type=int, default=50, help="mesh seed of --study eval")
     ap.add_argument("--max-newton", type=int, default=10, help="Newton steps per increment in --study eval")
     ap.add_argument("--eta", type=float, default=1e-4, help="Krylov tolerance of each Newton step")
-    ap.add_argument("--restart", type=int, default=30, help="FGMRES cycle length (at most 240)")
+    ap.add_argument("--restart", type=int, default=30, help="FGMRES cycle length (at most 2048)")
+    ap.add_argument("--line-search", type=int, default=10,
+                    help="Newton backtracking halvings; -1: full steps (halved only at an inverted cell)")
+    ap.add_argument("--forcing", type=int, default=0,
+                    help="0: Krylov tolerance --eta on every Newton step; 1: Eisenstat-Walker from --eta")
+    ap.add_argument("--solvers", default="plain,multigrid,learned",
+                    help="time-to-tolerance solves to run: any of plain, multigrid, learned (learned needs plain)")
     ap.add_argument("--stepwise", type=int, default=0,
                     help="time-to-tolerance solves as one logged library Newton step per call, at most this many "
                          "steps per increment (0: one library call per increment)")
     ap.add_argument("--lz", type=float, default=1.0, help="z extent of the evaluation cube (cell aspect 1/lz)")
     args = ap.parse_args()
-    KRYLOV["eta"], KRYLOV["restart"] = args.eta, args.restart
+    KRYLOV.update(eta=args.eta, restart=args.restart, line_search=args.line_search, forcing=args.forcing)
+    solvers = set(args.solvers.split(","))
+    if args.forcing and args.stepwise:
+        sys.exit("--forcing 1 needs whole-increment library calls (--stepwise 0): the forcing term "
+                 "follows the residual across the steps of one call")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built",
               file=sys.stderr)
@@ -387,12 +399,15 @@ def main():
 
     solve = None
     if args.solve:
-        if prob.n_increments == 1:
-            newton(False)  # warm-up (allocates the Krylov workspace)
-        solve = {"plain": newton(False),
-                 "plain_preconditioner": "compact approximate Jacobian, 2 FP32 symmetric Gauss-Seidel sweeps"}
-        log(f"plain solve {solve['plain']}")
-        if multigrid:
+        solve = {"krylov": {"eta": args.eta, "forcing": args.forcing, "restart": args.restart,
+                            "line_search": args.line_search}}
+        if "plain" in solvers:
+            if prob.n_increments == 1:
+                newton(False)  # warm-up (allocates the Krylov workspace)
+            solve["plain"] = newton(False)
+            solve["plain_preconditioner"] = "compact approximate Jacobian, 2 FP32 symmetric Gauss-Seidel sweeps"
+            log(f"plain solve {solve['plain']}")
+        if multigrid and "multigrid" in solvers:
             ctx.set_multigrid(True)
             if prob.n_increments == 1:
                 newton(False)
@@ -416,7 +431,7 @@ def main():
             solve["precond_ms_" + mode] = (time.perf_counter() - t0) / 20 * 1e3
         if multigrid:
             ctx.set_multigrid(False)
-        if args.learned and args.workload == "cube":
+        if args.learned and args.workload == "cube" and {"plain", "learned"} <= solvers:
             from paper_2601_18417_amd import learned as lrn
             t0 = time.perf_counter()
             data = []

@@ -168,7 +168,8 @@ hofv_status hofv_precond_apply(hofv_ctx* ctx, const double* d_r, double* d_z, in
                                int32_t learned, void* stream);
 
 typedef struct {
-  int32_t restart;       /* m of FGMRES(m), default 30, at most 240 */
+  int32_t restart;       /* m of FGMRES(m), default 30 (<= 0), at most 2048
+                            (HOFV_EINVAL above); the basis takes (2m + 1) n doubles */
   int32_t max_iters;     /* total Krylov iterations */
   double rtol;           /* stop at ||rhs - J x|| <= rtol ||rhs|| */
   int32_t n_sweeps;      /* preconditioner sweeps per application */
@@ -204,8 +205,14 @@ typedef struct {
   int32_t max_newton;    /* per increment */
   int32_t n_increments;  /* load factors i / n, i = 1..n; <= 0: one solve at the
                             factor set by hofv_set_load_scale */
-  int32_t max_line_search; /* backtracking halvings */
-  hofv_krylov_opts krylov;
+  int32_t max_line_search; /* backtracking halvings (0: 10); < 0: full steps
+                              (see hofv_newton_solve) */
+  hofv_krylov_opts krylov; /* krylov.rtol is ignored: eta and forcing set it */
+  int32_t forcing;       /* 0: Krylov rtol = eta on every step; 1: Eisenstat-Walker
+                            choice 2, eta_k = 0.9 (||R_k|| / ||R_k-1||)^2, raised to
+                            0.9 eta_k-1^2 when that exceeds 0.1, at most eta (which
+                            is also the first step's), and at least
+                            0.5 tol ||R_0|| / ||R_k|| */
 } hofv_newton_opts;
 
 typedef struct {
@@ -220,8 +227,14 @@ typedef struct {
 } hofv_newton_stats;
 
 /* Newton with backtracking line search on ||R||_2 (accept the first
- * ||R(u + lam du)|| <= (1 - 1e-4 lam) ||R(u)||, lam = 1, 1/2, ...), J du = -R by
- * hofv_fgmres_solve, for each load increment.  With krylov.learned, a linear
+ * ||R(u + lam du)|| <= (1 - 1e-4 lam) ||R(u)||, lam = 1, 1/2, ..., else the
+ * last trial), J du = -R by hofv_fgmres_solve, for each load increment.  With
+ * opts->max_line_search < 0 every step is a full one (lam = 1) unless its
+ * trial state has an inverted cell (J <= 0 at a face point) or a non-finite
+ * residual, in which case lam is halved up to 10 times; a load concentrated on
+ * a few cells (a tip traction) makes ||R|| a poor merit function, since the
+ * first full step of a bending problem spreads a larger geometric residual
+ * over the whole body before the next steps remove it.  With krylov.learned, a linear
  * solve that misses its tolerance is repeated with the plain preconditioner.
  * d_u: initial guess in, solution out.  Synchronises. */
 hofv_status hofv_newton_solve(hofv_ctx* ctx, double* d_u, const hofv_newton_opts* opts,

@@ -7,10 +7,15 @@ For every load increment i = 1..n (load factor i/n):
     differences and the AJ sweeps as right preconditioner;  backtracking line
     search lam = 1, 1/2, 1/4, ... (at most ``ls_max`` halvings) accepting the
     first ||R(u + lam du)|| <= (1 - 1e-4 lam) ||R(u)|| (or the last trial);
-    until ||R|| <= tol ||R0||.
-The paper uses "a line-search procedure" from the authors' earlier work
-without details and a 6-order residual reduction; the Armijo backtracking and
-the tolerances here are readings (tolerance per problem, Krylov rtol ``eta``).
+    until ||R|| <= tol ||R0||.  The Krylov tolerance is ``eta`` (forcing 0) or
+    the Eisenstat-Walker term of ``forcing_term`` starting from ``eta``
+    (forcing 1).  ls_max < 0: full steps, lam halved (at most
+    10 times) only while R(u + lam du) is not finite (an inverted cell makes
+    the neo-Hookean ln J undefined).
+The paper defers its line search to the authors' earlier work without
+details and reduces the residual by six orders; the Armijo backtracking, the
+full-step mode and the tolerances here are readings (tolerance per problem,
+Krylov rtol ``eta``).
 """
 from __future__ import annotations
 
@@ -22,9 +27,21 @@ from .krylov import fgmres
 from .residual import residual
 
 
+def forcing_term(rn, rprev, eta_prev, eta_max, tol, r0):
+    """Eisenstat & Walker (1996), choice 2 with gamma = 0.9, alpha = 2: the
+    Krylov tolerance follows the observed reduction of ||R||, raised to
+    gamma eta_prev^alpha when that exceeds 0.1 (their safeguard), capped at
+    eta_max, and not below 0.5 tol ||R0|| / ||R|| (no more than the
+    increment's tolerance needs)."""
+    e = 0.9 * (rn / rprev) ** 2
+    if 0.9 * eta_prev ** 2 > 0.1:
+        e = max(e, 0.9 * eta_prev ** 2)
+    return max(min(e, eta_max), 0.5 * tol * r0 / rn)
+
+
 def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
            maxit_newton=50, maxit_krylov=2000, n_increments=1, ls_max=10, precond_fn=None,
-           log=None):
+           log=None, forcing=0):
     n, D = disc.n_cells, disc.dim
     if A is None:
         A = precond.assemble(disc)
@@ -44,7 +61,11 @@ def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
         r0 = np.linalg.norm(R)
         rn = r0
         it = 0
+        eta_k, rprev = eta, r0
         while rn > tol * r0 and it < maxit_newton:
+            if forcing == 1 and it > 0:
+                eta_k = forcing_term(rn, rprev, eta_k, eta, tol, r0)
+            rprev = rn
             Ru = R
             uu = u
 
@@ -55,14 +76,17 @@ def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
                     return np.zeros_like(v)
                 return ((residual(disc, uu + eps * vv, load) - Ru) / eps).ravel()
 
-            du, info = fgmres(J, -R.ravel(), M, m=m, rtol=eta, maxit=maxit_krylov)
+            du, info = fgmres(J, -R.ravel(), M, m=m, rtol=eta_k, maxit=maxit_krylov)
             stats["krylov"] += info["iters"]
             du = du.reshape(n, D)
             lam = 1.0
-            for _ in range(ls_max + 1):
+            full = ls_max < 0
+            for _ in range((10 if full else ls_max) + 1):
                 ut = u + lam * du
-                Rt = residual(disc, ut, load)
-                if np.linalg.norm(Rt) <= (1.0 - 1e-4 * lam) * rn:
+                with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+                    Rt = residual(disc, ut, load)
+                finite = bool(np.all(np.isfinite(Rt)))
+                if finite and (full or np.linalg.norm(Rt) <= (1.0 - 1e-4 * lam) * rn):
                     break
                 lam *= 0.5
             u, R = ut, Rt

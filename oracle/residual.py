@@ -18,7 +18,8 @@ R(u) = 0 is static equilibrium (Sec. 4.1).
   bbar = J^{-2/3} b, sigma = (mu/J) dev(bbar) + (kappa/2)(J^2-1)/J I (eq. neoHook),
   P = J sigma F^{-T} (eq. nanson), face term n_o . P^T (eq. momentum_TL);
   kappa = lambda + 2 mu / 3.  J^{-2/3} is evaluated as exp(-2/3 ln J) so the
-  complex-step derivative goes through.
+  complex-step derivative goes through; J, b and dev(bbar) are formed from
+  H = grad u^T without cancelling O(1) terms (see piola_neo_hookean).
 * alpha-stabilisation: t = alpha Kbar / |d_PN . n_f| (u*_{f,N} - u*_{f,P}), Kbar = 2 mu + lambda;
   on displacement faces t = alpha Kbar / |d_Pb . n_b| (u_b(x_b) - u*_{b,P}).  The
   extrapolations u* use u_P itself plus d . grad u + 1/2 d^2 : grad grad u
@@ -223,19 +224,31 @@ def stress_linear(G, mu, lam):
 
 
 def piola_neo_hookean(G, mu, lam):
-    """First Piola-Kirchhoff stress P = J sigma F^{-T} of eq. neoHook (3D)."""
+    """First Piola-Kirchhoff stress P = J sigma F^{-T} of eq. neoHook (3D).
+
+    With H = G^T (so F = I + H) the same quantities are formed from H alone:
+    J - 1 = tr H + ((tr H)^2 - tr(H H)) / 2 + det H (the expansion of
+    det(I + H)), b - I = H + H^T + H H^T, dev(bbar) = J^{-2/3} dev(b - I) (dev I
+    = 0), J^2 - 1 = (J - 1)(J + 1) and ln J = log1p(J - 1).  Forming J, b and
+    dev(bbar) from F instead subtracts numbers of size 1 whose difference is
+    the strain, which at the strains of a finite-difference product (~1e-8)
+    leaves only about half of the digits.
+    """
     D = G.shape[-1]
     if D != 3:
         raise ValueError("the neo-Hookean law is implemented in 3D only")
     kappa = lam + 2.0 * mu / 3.0
     I = np.eye(3)
-    F = I + np.swapaxes(G, -1, -2)
-    J = np.linalg.det(F)
-    b = F @ np.swapaxes(F, -1, -2)
-    bbar = np.exp(-2.0 / 3.0 * np.log(J))[..., None, None] * b
-    dev = bbar - (np.trace(bbar, axis1=-2, axis2=-1) / 3.0)[..., None, None] * I
-    sigma = (mu / J)[..., None, None] * dev + (0.5 * kappa * (J * J - 1.0) / J)[..., None, None] * I
-    Finv_T = np.swapaxes(np.linalg.inv(F), -1, -2)
+    H = np.swapaxes(G, -1, -2)
+    Ht = G
+    trH = np.trace(H, axis1=-2, axis2=-1)
+    Jm1 = trH + 0.5 * (trH * trH - np.trace(H @ H, axis1=-2, axis2=-1)) + np.linalg.det(H)
+    J = 1.0 + Jm1
+    B = H + Ht + H @ Ht
+    devB = B - (np.trace(B, axis1=-2, axis2=-1) / 3.0)[..., None, None] * I
+    jm23 = np.exp(-2.0 / 3.0 * np.log1p(Jm1))
+    sigma = (mu / J * jm23)[..., None, None] * devB + (0.5 * kappa * Jm1 * (J + 1.0) / J)[..., None, None] * I
+    Finv_T = np.swapaxes(np.linalg.inv(I + H), -1, -2)
     return J[..., None, None] * sigma @ Finv_T
 
 

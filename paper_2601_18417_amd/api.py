@@ -147,9 +147,10 @@ class Context:
         return {k: getattr(s, k) for k, _ in L.KrylovStats._fields_}
 
     def newton_solve(self, u, tol=1e-8, eta=1e-4, max_newton=50, n_increments=1, max_line_search=10,
-                     restart=30, max_krylov=2000, n_sweeps=2, learned=False, stream=None, check=True):
+                     restart=30, max_krylov=2000, n_sweeps=2, learned=False, stream=None, check=True,
+                     forcing=0):
         o = L.NewtonOpts(tol, eta, max_newton, n_increments, max_line_search,
-                         L.KrylovOpts(restart, max_krylov, eta, n_sweeps, int(bool(learned))))
+                         L.KrylovOpts(restart, max_krylov, eta, n_sweeps, int(bool(learned))), int(forcing))
         s = L.NewtonStats()
         st = self.lib.hofv_newton_solve(self.h, _ptr(u), C.byref(o), C.byref(s), _stream(stream))
         if check or st not in (L.HOFV_OK, -5):

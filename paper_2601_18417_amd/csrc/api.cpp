@@ -271,6 +271,7 @@ hofv_status hofv_newton_solve(hofv_ctx* c, double* d_u, const hofv_newton_opts* 
   hofv_status s = need(c, 4, "newton_solve");
   if (s) return s;
   if (!d_u || !opts) return fail(c, HOFV_EINVAL, "null pointer");
+  if (opts->forcing != 0 && opts->forcing != 1) return fail(c, HOFV_EINVAL, "forcing must be 0 or 1");
   if ((s = set_device(c))) return s;
   hofv_newton_stats tmp{};
   return newton_impl(c, d_u, opts, stats ? stats : &tmp, (hipStream_t)stream);

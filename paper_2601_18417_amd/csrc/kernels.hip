@@ -314,44 +314,59 @@ __global__ __launch_bounds__(kBlockItems) void k_face_q(int64_t nf, int64_t nfi,
         t[j] += s;
       }
     } else {
-      // F = I + G^T, J = det F, bbar = J^{-2/3} F F^T,
-      // sigma = mu/J dev(bbar) + kappa/2 (J^2 - 1)/J I, P = J sigma F^{-T} = sigma cof(F)
-      double Fm[3][3];
+      // F = I + H with H = G^T, J = det F, bbar = J^{-2/3} F F^T,
+      // sigma = mu/J dev(bbar) + kappa/2 (J^2 - 1)/J I, P = J sigma F^{-T} = sigma cof(F).
+      // Evaluated from H so that no O(1) terms cancel at small strain (a
+      // finite-difference product perturbs H by ~1e-8):
+      // J - 1 = tr H + ((tr H)^2 - tr(H H))/2 + det H, dev(bbar) = J^{-2/3} dev(B)
+      // with B = b - I = H + H^T + H H^T, J^2 - 1 = (J - 1)(J + 1).
+      double H[3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Fm[a][c] = (a == c ? 1.0 : 0.0) + G[q * D + c][a];
-      double cof[3][3];
-      cof[0][0] = Fm[1][1] * Fm[2][2] - Fm[1][2] * Fm[2][1];
-      cof[0][1] = Fm[1][2] * Fm[2][0] - Fm[1][0] * Fm[2][2];
-      cof[0][2] = Fm[1][0] * Fm[2][1] - Fm[1][1] * Fm[2][0];
-      cof[1][0] = Fm[2][1] * Fm[0][2] - Fm[2][2] * Fm[0][1];
-      cof[1][1] = Fm[2][2] * Fm[0][0] - Fm[2][0] * Fm[0][2];
-      cof[1][2] = Fm[2][0] * Fm[0][1] - Fm[2][1] * Fm[0][0];
-      cof[2][0] = Fm[0][1] * Fm[1][2] - Fm[0][2] * Fm[1][1];
-      cof[2][1] = Fm[0][2] * Fm[1][0] - Fm[0][0] * Fm[1][2];
-      cof[2][2] = Fm[0][0] * Fm[1][1] - Fm[0][1] * Fm[1][0];
-      double J = Fm[0][0] * cof[0][0] + Fm[0][1] * cof[0][1] + Fm[0][2] * cof[0][2];
+        for (int c = 0; c < 3; ++c) H[a][c] = G[q * D + c][a];
+      double cof[3][3];  // cofactors of F = I + H
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int a1 = (a + 1) % 3, a2 = (a + 2) % 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+          const double f11 = (a1 == c1 ? 1.0 : 0.0) + H[a1][c1], f22 = (a2 == c2 ? 1.0 : 0.0) + H[a2][c2];
+          const double f12 = (a1 == c2 ? 1.0 : 0.0) + H[a1][c2], f21 = (a2 == c1 ? 1.0 : 0.0) + H[a2][c1];
+          cof[a][c] = f11 * f22 - f12 * f21;
+        }
+      const double trH = H[0][0] + H[1][1] + H[2][2];
+      double trHH = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) trHH += H[a][c] * H[c][a];
+      const double detH = H[0][0] * (H[1][1] * H[2][2] - H[1][2] * H[2][1]) -
+                          H[0][1] * (H[1][0] * H[2][2] - H[1][2] * H[2][0]) +
+                          H[0][2] * (H[1][0] * H[2][1] - H[1][1] * H[2][0]);
+      double Jm1 = trH + 0.5 * (trH * trH - trHH) + detH;
+      double J = 1.0 + Jm1;
       if (!(J > 0.0)) {
         flag[0] = 1;
         J = 1.0;
+        Jm1 = 0.0;
       }
       const double kappa = lam + 2.0 * mu / 3.0;
       const double cb = cbrt(J);
-      const double jm23 = 1.0 / (cb * cb);
-      double b[3][3];
+      const double invJ = 1.0 / J;
+      const double sdev = mu * invJ / (cb * cb);
+      double B[3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) b[a][c] = jm23 * (Fm[a][0] * Fm[c][0] + Fm[a][1] * Fm[c][1] + Fm[a][2] * Fm[c][2]);
-      const double trb = (b[0][0] + b[1][1] + b[2][2]) / 3.0;
-      const double invJ = 1.0 / J;
-      const double pr = 0.5 * kappa * (J * J - 1.0) * invJ;
+        for (int c = 0; c < 3; ++c) B[a][c] = H[a][c] + H[c][a] + (H[a][0] * H[c][0] + H[a][1] * H[c][1] + H[a][2] * H[c][2]);
+      const double trB = (B[0][0] + B[1][1] + B[2][2]) / 3.0;
+      const double pr = 0.5 * kappa * Jm1 * (J + 1.0) * invJ;
       double sig[3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sig[a][c] = mu * invJ * (b[a][c] - (a == c ? trb : 0.0)) + (a == c ? pr : 0.0);
+        for (int c = 0; c < 3; ++c) sig[a][c] = sdev * (B[a][c] - (a == c ? trB : 0.0)) + (a == c ? pr : 0.0);
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         double s = 0.0;

@@ -10,7 +10,8 @@
 //
 // Newton (Sec. 4.1 with the Armijo backtracking reading of the line search):
 // per load increment, J du = -R by FGMRES, u += lam du with lam = 1, 1/2, ...
-// accepted at ||R(u + lam du)|| <= (1 - 1e-4 lam) ||R(u)||.
+// accepted at ||R(u + lam du)|| <= (1 - 1e-4 lam) ||R(u)||; or full steps
+// (lam = 1 unless the trial state is inadmissible).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,7 +28,7 @@ namespace {
 constexpr int kB = 256;
 constexpr int kDotChunk = 32;     // vectors per multi-dot launch (accumulators in registers)
 constexpr int kDotBlocks = 256;
-constexpr int kMaxRestart = 240;  // longest FGMRES cycle
+constexpr int kMaxRestart = 2048;  // longest FGMRES cycle (slender bodies need long Krylov bases)
 constexpr int kCheck = 8;         // FGMRES iterations queued between host reads
 constexpr double kLearnedCycle = 0.75;  // slowest accepted residual reduction of a learned cycle
 // device scalars of the Krylov driver (K.h): Hessenberg column, ||z||^2 of a
@@ -153,20 +154,21 @@ static hofv_status host_norm(hofv_ctx* c, int64_t n, const double* x, double* ou
 static hofv_status ensure_krylov(hofv_ctx* c, int m) {
   Krylov& k = c->kry;
   if (k.V && k.m >= m) return HOFV_OK;
+  const int64_t n = (int64_t)c->D * c->nc;
   if (k.V) {  // grow: release the old set
-    for (void* p : {(void*)k.V, (void*)k.Z}) {
+    for (void* p : {(void*)k.V, (void*)k.Z, (void*)k.Hd, (void*)k.zz}) {
       hipFree(p);
       c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), p), c->allocations.end());
     }
+    c->device_bytes -= ((size_t)(2 * k.m + 1) * n + (size_t)(k.m + 2) * k.m) * sizeof(double);
+    k.V = k.Z = k.Hd = k.zz = nullptr;
+    k.m = 0;
   }
-  const int64_t n = (int64_t)c->D * c->nc;
   hofv_status s;
   if ((s = dev_alloc(c, &k.V, (size_t)(m + 1) * n))) return s;
   if ((s = dev_alloc(c, &k.Z, (size_t)m * n))) return s;
-  if (!k.Hd) {
-    if ((s = dev_alloc(c, &k.Hd, (size_t)(kMaxRestart + 1) * kMaxRestart))) return s;
-    if ((s = dev_alloc(c, &k.zz, (size_t)kMaxRestart))) return s;
-  }
+  if ((s = dev_alloc(c, &k.Hd, (size_t)(m + 1) * m))) return s;
+  if ((s = dev_alloc(c, &k.zz, (size_t)m))) return s;
   if (!k.h) {
     if ((s = dev_alloc(c, &k.h, kHsize))) return s;
     if ((s = dev_alloc(c, &k.tmp, (size_t)n))) return s;
@@ -183,7 +185,8 @@ hofv_status precond_dispatch(hofv_ctx* c, const double* r, double* z, int sweeps
 hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const double* rhs, double* x,
                         const hofv_krylov_opts* o, hofv_krylov_stats* stats, hipStream_t st) {
   auto t0 = std::chrono::steady_clock::now();
-  const int m = std::max(1, std::min(o->restart > 0 ? o->restart : 30, kMaxRestart));
+  if (o->restart > kMaxRestart) return fail(c, HOFV_EINVAL, "FGMRES restart above 2048");
+  const int m = o->restart > 0 ? o->restart : 30;
   const int maxit = o->max_iters > 0 ? o->max_iters : 1000;
   const double rtol = o->rtol > 0 ? o->rtol : 1e-6;
   const int sweeps = o->n_sweeps > 0 ? o->n_sweeps : 2;
@@ -324,10 +327,10 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
                         hipStream_t st) {
   auto t0 = std::chrono::steady_clock::now();
   const int64_t n = (int64_t)c->D * c->nc;
-  hofv_status s = ensure_krylov(c, std::min(o->krylov.restart > 0 ? o->krylov.restart : 30, kMaxRestart));
+  if (o->krylov.restart > kMaxRestart) return fail(c, HOFV_EINVAL, "FGMRES restart above 2048");
+  hofv_status s = ensure_krylov(c, o->krylov.restart > 0 ? o->krylov.restart : 30);
   if (s) return s;
   // workspace: R, du, rhs, ut, Rt
-  static thread_local std::vector<double*> none;
   double *R, *du, *rhs, *ut, *Rt;
   if ((s = dev_alloc(c, &R, n)) || (s = dev_alloc(c, &du, n)) || (s = dev_alloc(c, &rhs, n)) ||
       (s = dev_alloc(c, &ut, n)) || (s = dev_alloc(c, &Rt, n)))
@@ -344,7 +347,7 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
   const double load0 = c->load;
   const double tol = o->tol > 0 ? o->tol : 1e-8;
   hofv_krylov_opts ko = o->krylov;
-  ko.rtol = o->eta > 0 ? o->eta : 1e-4;
+  const double eta0 = o->eta > 0 ? o->eta : 1e-4;
   stats->newton_iters = 0;
   stats->krylov_iters = 0;
   stats->converged = 1;
@@ -357,7 +360,20 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
     if ((s = host_norm(c, n, R, &r0, st))) { result = s; break; }
     rn = r0;
     int itn = 0;
+    double rprev = r0;
+    ko.rtol = eta0;
     while (rn > tol * r0 && itn < (o->max_newton > 0 ? o->max_newton : 50)) {
+      if (o->forcing == 1 && itn > 0) {
+        // Eisenstat-Walker choice 2 (gamma = 0.9, alpha = 2) with their
+        // safeguard, at most eta0, and no tighter than the increment's
+        // tolerance asks of this step
+        const double prev = ko.rtol;
+        double e = 0.9 * (rn / rprev) * (rn / rprev);
+        if (0.9 * prev * prev > 0.1) e = std::max(e, 0.9 * prev * prev);
+        e = std::min(e, eta0);
+        ko.rtol = std::max(e, 0.5 * tol * r0 / rn);
+      }
+      rprev = rn;
       k_lincomb<<<nblk(n), kB, 0, st>>>(n, -1.0, R, 0.0, R, rhs);
       k_fill<<<nblk(n), kB, 0, st>>>(n, 0.0, du);
       hofv_krylov_stats ks{};
@@ -375,6 +391,9 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
       }
       double lam = 1.0, rt = 0.0;
       bool accepted = false;
+      // max_line_search < 0: full steps, halved only while the trial state is
+      // not admissible (an inverted cell or a non-finite residual)
+      const bool full = o->max_line_search < 0;
       const int maxls = o->max_line_search > 0 ? o->max_line_search : 10;
       for (int ls = 0; ls <= maxls; ++ls) {
         k_lincomb<<<nblk(n), kB, 0, st>>>(n, 1.0, u, lam, du, ut);
@@ -383,8 +402,8 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
         int32_t flag = 0;
         HOFV_HIP(c, hipMemcpyAsync(&flag, c->dev.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         if ((s = host_norm(c, n, Rt, &rt, st))) { result = s; break; }
-        if (!flag && std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * rn) { accepted = true; break; }
-        if (ls == maxls && !flag && std::isfinite(rt)) { accepted = true; break; }  // last trial
+        if (!flag && std::isfinite(rt) && (full || rt <= (1.0 - 1e-4 * lam) * rn)) { accepted = true; break; }
+        if (!full && ls == maxls && !flag && std::isfinite(rt)) { accepted = true; break; }  // last trial
         lam *= 0.5;
       }
       if (result) break;

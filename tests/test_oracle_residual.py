@@ -105,6 +105,19 @@ def test_neo_hookean_reduces_to_linear_elasticity():
     assert 0.9 < slope < 1.1 and errs[-1] < 1e-3
 
 
+def test_neo_hookean_small_strain_keeps_its_digits():
+    """P(G) - sigma_LE(G) = O(|G|^2) (the law linearises to eq. linearElastic
+    at G = 0, App. A), so the relative gap to the linear stress shrinks with
+    |G| down to round-off: at |G| ~ 1e-12 it is ~1e-12.  A form that builds
+    J - 1 or dev(bbar) by subtracting O(1) numbers fails here (its error is
+    ~1e-16 / |G|), and that error is what a finite-difference J.v sees."""
+    G = np.random.default_rng(4).standard_normal((200, 3, 3))
+    for s in (1e-6, 1e-9, 1e-12):
+        P = rs.piola_neo_hookean(s * G, 1.0, 10.0)
+        L = np.swapaxes(rs.stress_linear(s * G, 1.0, 10.0), -1, -2)
+        assert np.abs(P - L).max() <= 50.0 * s * np.abs(L).max()
+
+
 def _fd_grad(f, X, h=1e-6):
     g = np.zeros_like(X)
     for idx in np.ndindex(*X.shape):

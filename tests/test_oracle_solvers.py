@@ -44,6 +44,87 @@ def test_jvp_matches_complex_step_neo_hookean():
     assert np.linalg.norm(Jv.ravel() - ref) <= 1e-6 * np.linalg.norm(ref)
 
 
+def test_fgmres_on_a_slender_neo_hookean_beam_keeps_its_true_residual():
+    """For a linear operator the FGMRES least-squares estimate of the residual
+    is the true residual ||b - J x||.  A finite-difference J.v is linear only to
+    its own precision, and on a clamped beam with free sides (P^-1 J has
+    eigenvalues down to ~1e-4 from bending and torsion) the Krylov coefficients
+    grow until a few 1e-8 of product error decide the result.  With the
+    neo-Hookean stress formed without cancellation the two residuals agree and
+    the solve reaches 1e-6 (the exact inverse of the approximate Jacobian as
+    preconditioner, restart 200, load 0.1 from u = 0)."""
+    prob = w.cantilever(shape=(30, 3, 3), p=1, n_plus=20)
+    disc = rs.build(prob)
+    n = disc.n_cells
+    u = np.zeros((n, 3))
+    R = rs.residual(disc, u, 0.1)
+    lu = spla.splu(pc.assemble(disc).tocsc())
+    x, info = kr.fgmres(lambda v: jc.jvp(disc, u, v.reshape(n, 3), Ru=R, load=0.1).ravel(), -R.ravel(),
+                        lambda v: lu.solve(v.reshape(n, 3)).ravel(), m=200, rtol=1e-6, maxit=400)
+    assert info["converged"] and info["rel"] <= 1e-6
+    assert info["rel"] <= 2.0 * info["hist"][-1]
+
+
+def _tip_loaded_beam(traction, n_increments):
+    prob = w.cantilever(shape=(8, 2, 2), p=1, n_plus=20, n_increments=n_increments)
+    prob.mesh = w.box_mesh((8, 2, 2), lengths=(4.0, 1, 1))
+    prob.loads = w.fields.cantilever_loads(4.0, (0.0, -traction, 0.0))
+    return rs.build(prob)
+
+
+def test_newton_full_steps_converge_on_a_tip_loaded_beam():
+    """A tip traction bending a neo-Hookean beam by a quarter of its length:
+    the first full Newton step raises ||R|| (the geometric residual of the
+    linear step is spread over the whole beam while R_0 sits on the tip cells),
+    so backtracking on ||R|| crawls, while full steps converge quadratically."""
+    disc = _tip_loaded_beam(0.02, 2)
+    n = disc.n_cells
+    u, st = nw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-7, m=96, maxit_krylov=200,
+                      n_increments=2, ls_max=-1, maxit_newton=8)
+    assert all(inc["rel"] <= 1e-10 and inc["newton"] <= 7 for inc in st["increments"])
+    assert np.abs(u[:, 1]).max() > 0.5
+    _, st_bt = nw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-7, m=96, maxit_krylov=200,
+                         n_increments=2, ls_max=10, maxit_newton=8)
+    assert st_bt["increments"][0]["rel"] > 0.5
+
+
+def test_eisenstat_walker_forcing_saves_krylov_work_and_keeps_the_solution():
+    """forcing = 1 solves the early Newton systems loosely (eta follows the
+    squared reduction of ||R||) and the last one only as far as the tolerance
+    needs: fewer Krylov iterations, the same equilibrium."""
+    disc = _tip_loaded_beam(0.02, 2)
+    n = disc.n_cells
+    kw = dict(tol=1e-10, m=96, maxit_krylov=200, n_increments=2, ls_max=-1, maxit_newton=12)
+    u0, st0 = nw.newton(disc, np.zeros((n, 3)), eta=1e-7, **kw)
+    u1, st1 = nw.newton(disc, np.zeros((n, 3)), eta=0.5, forcing=1, **kw)
+    assert all(inc["rel"] <= 1e-10 for inc in st1["increments"])
+    assert st1["krylov"] < 0.7 * st0["krylov"]
+    assert np.linalg.norm(u1 - u0) <= 1e-8 * np.linalg.norm(u0)
+
+
+def test_forcing_term_rules():
+    # quadratic-rate reduction 0.1 -> 0.9 * 0.01; safeguard off for a small previous eta
+    assert nw.forcing_term(0.1, 1.0, 0.1, 0.5, 1e-12, 1.0) == pytest.approx(0.009)
+    # the safeguard keeps eta from collapsing after one lucky step: 0.9 * 0.5^2 > 0.1
+    assert nw.forcing_term(0.1, 1.0, 0.5, 0.9, 1e-12, 1.0) == pytest.approx(0.225)
+    # capped at eta_max
+    assert nw.forcing_term(1.0, 1.0, 0.5, 0.3, 1e-12, 1.0) == pytest.approx(0.3)
+    # never tighter than the increment's tolerance asks: tol ||R0|| / ||R|| / 2
+    assert nw.forcing_term(1e-7, 1e-4, 1e-3, 0.5, 1e-8, 1.0) == pytest.approx(0.05)
+
+
+def test_newton_full_steps_and_backtracking_agree_under_a_mild_load():
+    disc = _tip_loaded_beam(0.001, 1)
+    n = disc.n_cells
+    sols = []
+    for ls in (10, -1):
+        u, st = nw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-7, m=96, maxit_krylov=200,
+                          ls_max=ls, maxit_newton=10)
+        assert st["increments"][0]["rel"] <= 1e-10
+        sols.append(u)
+    assert np.linalg.norm(sols[0] - sols[1]) <= 1e-8 * np.linalg.norm(sols[0])
+
+
 def test_zero_direction_gives_zero_product():
     disc = rs.build(w.square_mms(4, 1))
     v = np.zeros((16, 2))
