@@ -183,6 +183,8 @@ typedef struct {
   double seconds;
   int32_t fallbacks;     /* iterations redone with the plain preconditioner
                             because the learned one produced NaN/Inf */
+  int32_t stalled;       /* 1: ended because a full cycle reduced the recomputed
+                            residual by less than 1 % */
 } hofv_krylov_stats;
 
 /* Solves J(u) x = rhs by right-preconditioned flexible GMRES(m) with J v from
@@ -194,7 +196,11 @@ typedef struct {
  * With opts->learned, an iteration whose Hessenberg column is not finite is
  * redone with the plain preconditioner, which is then kept for the rest of
  * the solve; so is a restart cycle that reduced the residual by less than a
- * factor 0.75 (both counted in stats->fallbacks). */
+ * factor 0.75 (both counted in stats->fallbacks).  A plain cycle that reduced
+ * the residual, recomputed at the restart, by less than 1 % ends the solve
+ * (stats->stalled, converged 0, x kept): past the residual that the precision
+ * of the finite-difference product allows, the least-squares estimate goes on
+ * falling while the true residual stays. */
 hofv_status hofv_fgmres_solve(hofv_ctx* ctx, const double* d_u, const double* d_Ru,
                               const double* d_rhs, double* d_x, const hofv_krylov_opts* opts,
                               hofv_krylov_stats* stats, void* stream);

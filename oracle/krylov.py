@@ -13,8 +13,16 @@ from __future__ import annotations
 import numpy as np
 
 
-def fgmres(A, b, M=None, x0=None, m=30, rtol=1e-8, maxit=1000, callback=None):
-    """A, M: callables on flat float64 vectors.  Returns (x, info dict)."""
+STALL = 0.99  # a cycle that keeps more than this fraction of the residual ends the solve
+
+
+def fgmres(A, b, M=None, x0=None, m=30, rtol=1e-8, maxit=1000, callback=None, stall=STALL):
+    """A, M: callables on flat float64 vectors.  Returns (x, info dict).
+
+    The solve also ends (info["stalled"]) when a full cycle reduced the true
+    residual, recomputed at the restart, by less than 1 % (stall = 0.99): a
+    finite-difference product is linear only to its precision, and past the
+    residual that precision allows more cycles change nothing."""
     b = np.asarray(b, float).ravel()
     n = b.size
     x = np.zeros(n) if x0 is None else np.asarray(x0, float).ravel().copy()
@@ -26,10 +34,13 @@ def fgmres(A, b, M=None, x0=None, m=30, rtol=1e-8, maxit=1000, callback=None):
     r = b - A(x)
     beta = np.linalg.norm(r)
     hist = [beta / bnorm]
+    beta_prev = None
     while True:
-        if beta <= rtol * bnorm or its >= maxit:
+        stalled = beta_prev is not None and beta > stall * beta_prev
+        if beta <= rtol * bnorm or its >= maxit or stalled:
             return x, {"iters": its, "converged": beta <= rtol * bnorm, "rel": beta / bnorm,
-                       "hist": hist}
+                       "hist": hist, "stalled": bool(stalled and beta > rtol * bnorm)}
+        beta_prev = beta
         V = np.zeros((m + 1, n))
         Z = np.zeros((m, n))
         H = np.zeros((m + 1, m))

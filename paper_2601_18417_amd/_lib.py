@@ -40,7 +40,7 @@ class KrylovOpts(C.Structure):
 
 class KrylovStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double),
-                ("seconds", C.c_double), ("fallbacks", C.c_int32)]
+                ("seconds", C.c_double), ("fallbacks", C.c_int32), ("stalled", C.c_int32)]
 
 
 class NewtonOpts(C.Structure):

@@ -31,6 +31,7 @@ constexpr int kDotBlocks = 256;
 constexpr int kMaxRestart = 2048;  // longest FGMRES cycle (slender bodies need long Krylov bases)
 constexpr int kCheck = 8;         // FGMRES iterations queued between host reads
 constexpr double kLearnedCycle = 0.75;  // slowest accepted residual reduction of a learned cycle
+constexpr double kStallCycle = 0.99;    // a plain cycle keeping more of the residual ends the solve
 // device scalars of the Krylov driver (K.h): Hessenberg column, ||z||^2 of a
 // learned output, the cycle's beta, the second Gram-Schmidt pass, a norm
 constexpr int kHcol = 0, kZz = kMaxRestart + 2, kBeta = kMaxRestart + 3, kH2 = kMaxRestart + 4,
@@ -201,6 +202,7 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
   stats->iters = 0;
   stats->converged = 0;
   stats->fallbacks = 0;
+  stats->stalled = 0;
   int learned = o->learned;
   if (!std::isfinite(bnorm) || !std::isfinite(xnorm)) return fail(c, HOFV_ENAN, "NaN/Inf in FGMRES input");
   if (bnorm == 0.0) {
@@ -229,6 +231,11 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
     if (learned && beta_cycle > 0.0 && beta > kLearnedCycle * beta_cycle) {
       learned = 0;
       ++stats->fallbacks;
+    } else if (beta_cycle > 0.0 && beta > kStallCycle * beta_cycle) {
+      // the true residual no longer follows the least-squares one (the
+      // finite-difference product is linear only to its precision)
+      stats->stalled = 1;
+      break;
     }
     beta_cycle = beta;
     k_fill<<<1, kB, 0, st>>>(1, beta, hd + kBeta);

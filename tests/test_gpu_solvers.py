@@ -198,6 +198,30 @@ def test_newton_eisenstat_walker_forcing_matches_oracle():
         ctx.newton_solve(u, forcing=2)
 
 
+def test_fgmres_stops_when_its_cycles_stall():
+    """At a bent state (a quarter of the length of tip deflection) the
+    one-sided finite-difference product is linear to ~1e-8; asked for 1e-11,
+    FGMRES ends once a cycle no longer reduces the recomputed residual by 1 %,
+    long before max_iters, keeping the reduction it reached."""
+    prob = w.cantilever(shape=(30, 3, 3), p=1, n_plus=20, n_increments=4)
+    prob.mesh = w.box_mesh((30, 3, 3), lengths=(7.5, 1, 1))
+    prob.loads = w.fields.cantilever_loads(7.5, (0.0, -0.004, 0.0))
+    ctx = _api().context_for(prob, precond_levels=8)
+    ctx.set_multigrid(True)
+    n = prob.mesh.n_cells
+    u = torch.zeros((3, n), device=DEV, dtype=torch.float64)
+    st = ctx.newton_solve(u, tol=1e-10, eta=0.3, forcing=1, n_increments=4, max_line_search=-1, restart=200,
+                          max_krylov=400, max_newton=15)
+    assert st["converged"] and float(u[1].abs().max()) > 1.0
+    ctx.set_load_scale(1.25)
+    R = torch.empty_like(u)
+    ctx.residual(u, R)
+    x = torch.zeros_like(u)
+    ks = ctx.fgmres_solve(u, R, -R, x, restart=200, max_iters=4000, rtol=1e-11, check=False)
+    assert ks["stalled"] == 1 and not ks["converged"] and ks["iters"] < 2000
+    assert ks["rel_residual"] < 1e-2
+
+
 def test_newton_full_steps_on_a_tip_loaded_beam_match_oracle():
     """A tip traction bends a neo-Hookean beam by a quarter of its length; full
     Newton steps (max_line_search < 0) converge in a few steps per increment on

@@ -125,6 +125,23 @@ def test_newton_full_steps_and_backtracking_agree_under_a_mild_load():
     assert np.linalg.norm(sols[0] - sols[1]) <= 1e-8 * np.linalg.norm(sols[0])
 
 
+def test_fgmres_stops_on_a_stagnating_cycle():
+    """GMRES(m) on the cyclic shift S e_i = e_{i+1} with b = e_1 makes no
+    progress at all while m < n (the Krylov space of every cycle misses the
+    solution's support): the solve ends after the second cycle instead of
+    running to maxit; with m = n it solves the system exactly."""
+    n = 12
+    S = np.roll(np.eye(n), 1, axis=0)
+    b = np.zeros(n)
+    b[0] = 1.0
+    x, info = kr.fgmres(lambda v: S @ v, b, m=4, rtol=1e-10, maxit=1000)
+    assert info["stalled"] and not info["converged"] and info["iters"] == 4
+    assert info["rel"] == pytest.approx(1.0)
+    x, info = kr.fgmres(lambda v: S @ v, b, m=n, rtol=1e-10, maxit=1000)
+    assert info["converged"] and not info["stalled"]
+    assert np.allclose(S @ x, b)
+
+
 def test_zero_direction_gives_zero_product():
     disc = rs.build(w.square_mms(4, 1))
     v = np.zeros((16, 2))
