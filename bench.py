@@ -108,6 +108,15 @@ def parse_seeds(s):
 KRYLOV = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0}  # Newton's Krylov options (set from the arguments)
 
 
+def forcing_term(rn, rprev, eta_prev, eta_max, tol, r0):
+    """The library's Eisenstat-Walker rule (forcing = 1), applied here across
+    one-step library calls."""
+    e = 0.9 * (rn / rprev) ** 2
+    if 0.9 * eta_prev ** 2 > 0.1:
+        e = max(e, 0.9 * eta_prev ** 2)
+    return max(min(e, eta_max), 0.5 * tol * r0 / rn)
+
+
 def newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, max_newton, label):
     """One library Newton step per call, each logged as it ends (long solves
     stay visible); stops at ||R|| <= tol ||R_0||."""
@@ -116,15 +125,20 @@ def newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, max_newton, label)
     r0 = float(torch.linalg.norm(R))
     tot = {"newton_iters": 0, "krylov_iters": 0, "fallbacks": 0, "converged": False, "rel_residual": 1.0}
     t0 = time.perf_counter()
+    eta, rn, rprev = KRYLOV["eta"], r0, r0
     for step in range(max_newton):
-        st = ctx.newton_solve(uu, tol=1e-300, eta=KRYLOV["eta"], max_newton=1, max_krylov=max_krylov, n_sweeps=2,
+        if KRYLOV["forcing"] and step > 0:
+            eta = forcing_term(rn, rprev, eta, KRYLOV["eta"], tol, r0)
+        rprev = rn
+        st = ctx.newton_solve(uu, tol=1e-300, eta=eta, max_newton=1, max_krylov=max_krylov, n_sweeps=2,
                               learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"],
-                              max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"])
+                              max_line_search=KRYLOV["line_search"])
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             tot[key] += st[key]
         ctx.residual(uu, R)
-        tot["rel_residual"] = float(torch.linalg.norm(R)) / r0
-        log(f"{label} step {step}: {st['krylov_iters']} Krylov, rel {tot['rel_residual']:.2e}, "
+        rn = float(torch.linalg.norm(R))
+        tot["rel_residual"] = rn / r0
+        log(f"{label} step {step}: {st['krylov_iters']} Krylov (eta {eta:.1e}), rel {tot['rel_residual']:.2e}, "
             f"{time.perf_counter() - t0:.1f}s")
         if tot["rel_residual"] <= tol:
             tot["converged"] = True
@@ -224,14 +238,20 @@ def study(args):
         r = torch.randn((prob.dim, nc), device=dev, dtype=torch.float64)
         z = torch.empty_like(r)
         ctx.precond_apply(r, z, learned=True)  # allocates the network's workspace
-        plain = newton_run(torch, ctx, prob, nc, False, tol, args.max_krylov, stepwise=args.max_newton)
-        log(f"plain {plain}")
-        learned = newton_run(torch, ctx, prob, nc, True, tol, args.max_krylov, stepwise=args.max_newton)
-        log(f"learned {learned}")
+        solvers = set(args.solvers.split(","))
         out = {"study": "eval", "workload": desc, "n_cells": nc, "tol": tol, "setup_seconds": t_setup,
-               "plain": plain, "learned": learned, "speedup": plain["seconds"] / learned["seconds"],
-               "krylov_ratio": learned["krylov_iters"] / max(plain["krylov_iters"], 1)}
-        if multigrid:
+               "krylov": {"eta": args.eta, "forcing": args.forcing, "restart": args.restart,
+                          "line_search": args.line_search}}
+        if "plain" in solvers:
+            out["plain"] = newton_run(torch, ctx, prob, nc, False, tol, args.max_krylov, stepwise=args.max_newton)
+            log(f"plain {out['plain']}")
+        if "learned" in solvers:
+            out["learned"] = newton_run(torch, ctx, prob, nc, True, tol, args.max_krylov, stepwise=args.max_newton)
+            log(f"learned {out['learned']}")
+        if "plain" in out and "learned" in out:
+            out["speedup"] = out["plain"]["seconds"] / out["learned"]["seconds"]
+            out["krylov_ratio"] = out["learned"]["krylov_iters"] / max(out["plain"]["krylov_iters"], 1)
+        if multigrid and "multigrid" in solvers:
             ctx.set_multigrid(True)
             out["multigrid"] = newton_run(torch, ctx, prob, nc, False, tol, args.max_krylov, stepwise=args.max_newton)
             log(f"multigrid {out['multigrid']}")
@@ -285,9 +305,6 @@ def main():
     args = ap.parse_args()
     KRYLOV.update(eta=args.eta, restart=args.restart, line_search=args.line_search, forcing=args.forcing)
     solvers = set(args.solvers.split(","))
-    if args.forcing and args.stepwise:
-        sys.exit("--forcing 1 needs whole-increment library calls (--stepwise 0): the forcing term "
-                 "follows the residual across the steps of one call")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built",
               file=sys.stderr)
