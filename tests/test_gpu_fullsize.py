@@ -1,6 +1,8 @@
-"""Parity at the benchmark's full size: 64^3 perturbed hex, p = 3, the same
-launch configuration bench.py times.  The oracle evaluates R and J.v on a
-sample of cells one by one (its setup restricted to what those cells need)."""
+"""Parity at full size, in the launch configuration bench.py times: the 64^3
+perturbed hex at p = 3 (the benchmark), the 200x20x20 neo-Hookean cantilever
+at p = 2 in a bent state, and the 128^3 perturbed hex at p = 1.  The oracle
+evaluates R and J.v on a sample of cells one by one (its setup restricted to
+what those cells need)."""
 import numpy as np
 import pytest
 
@@ -67,3 +69,62 @@ def test_fullsize_manufactured_state(big):
     np.add.at(scale, disc.d_own, np.abs(Fd))
     scale += np.abs(disc.b_body)
     assert np.all(np.abs(Rg[sample] - Ro[sample]) <= 1e-10 * scale[sample])
+
+
+def _sample(prob, rng, k=40):
+    n = prob.mesh.n_cells
+    ijk = w.cell_ijk(prob.mesh)
+    top = np.array(prob.mesh.shape) - 1
+    corner = np.nonzero(np.all((ijk == 0) | (ijk == top), axis=1))[0][:4]
+    face = np.nonzero(ijk[:, 0] == 0)[0][:3]
+    far = np.nonzero(ijk[:, 0] == top[0])[0][:3]
+    return np.unique(np.concatenate([rng.choice(n, k, replace=False), corner, face, far]))
+
+
+def _check_sampled(prob, ctx, disc, sample, u, v, rtol_r=1e-10, rtol_j=1e-6):
+    ud = torch.tensor(u.T.copy(), device=DEV)
+    vd = torch.tensor(v.T.copy(), device=DEV)
+    R = torch.empty_like(ud)
+    Jv = torch.empty_like(ud)
+    ctx.residual(ud, R)
+    eps = ojac.default_eps(u, v)
+    ctx.jvp(ud, R, vd, Jv, eps=eps)
+    torch.cuda.synchronize()
+    Rg, Jg = R.cpu().numpy().T, Jv.cpu().numpy().T
+    Ro = ores.residual(disc, u)
+    Jo = (ores.residual(disc, u + eps * v) - Ro) / eps
+    s = sample
+    assert np.linalg.norm(Rg[s] - Ro[s]) <= rtol_r * np.linalg.norm(Ro[s])
+    assert np.linalg.norm(Jg[s] - Jo[s]) <= rtol_j * np.linalg.norm(Jo[s])
+    assert np.all(np.isfinite(Rg)) and np.all(np.isfinite(Jg))
+
+
+def test_fullsize_cantilever_bent_state_sampled():
+    """200x20x20 neo-Hookean cantilever, p = 2: a bent state u_y = -0.3 x^2 / L
+    plus noise, at full load; sampled cells include the clamped end and the tip."""
+    from paper_2601_18417_amd import api
+    prob = w.cantilever(p=2)
+    ctx = api.context_for(prob)
+    n = prob.mesh.n_cells
+    sample = _sample(prob, np.random.default_rng(7))
+    disc = ores.build(prob, active=sample)
+    cen = ctx.cell_centroids()
+    L = prob.mesh.lengths[0]
+    u = w.random_state(n, 3, seed=22, scale=1e-3)
+    u[:, 1] += -0.3 * cen[:, 0] ** 2 / L
+    v = np.random.default_rng(1001).standard_normal((n, 3))
+    _check_sampled(prob, ctx, disc, sample, u, v)
+
+
+def test_fullsize_128_cube_p1_sampled():
+    """128^3 perturbed hex (2,097,152 cells), p = 1 (a smaller sample: the
+    oracle's brute-force stencil search scans all 2M centroids per point)."""
+    from paper_2601_18417_amd import api
+    prob = w.cube_mms(128, 1, perturb=0.2, seed=0)
+    ctx = api.context_for(prob)
+    n = prob.mesh.n_cells
+    sample = _sample(prob, np.random.default_rng(8), k=12)
+    disc = ores.build(prob, active=sample)
+    u = w.random_state(n, 3, seed=23)
+    v = np.random.default_rng(1002).standard_normal((n, 3))
+    _check_sampled(prob, ctx, disc, sample, u, v)
