@@ -105,7 +105,7 @@ def parse_seeds(s):
     return out
 
 
-KRYLOV = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0}  # Newton's Krylov options (set from the arguments)
+KRYLOV = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0}  # Newton's Krylov options (set from the arguments)
 
 
 def forcing_term(rn, rprev, eta_prev, eta_max, tol, r0):
@@ -155,6 +155,17 @@ def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None, stepw
     out = {"newton_iters": 0, "krylov_iters": 0, "fallbacks": 0, "converged": True, "rel_residual": 0.0}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    if KRYLOV["predictor"] and ninc > 1:
+        # the predictor spans increments: one library call for all of them
+        st = ctx.newton_solve(uu, tol=tol, eta=KRYLOV["eta"], max_krylov=max_krylov, n_sweeps=2, learned=learned,
+                              check=False, n_increments=ninc, restart=KRYLOV["restart"],
+                              max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"], predictor=1)
+        torch.cuda.synchronize()
+        out.update({key: st[key] for key in ("newton_iters", "krylov_iters", "fallbacks", "rel_residual")})
+        out["converged"] = bool(st["converged"])
+        out["seconds"] = time.perf_counter() - t0
+        log(f"{'learned' if learned else 'plain'} {ninc} increments with the predictor: {out}")
+        return out
     for inc in range(1, ninc + 1):
         ctx.set_load_scale(inc / ninc)
         if stepwise:
@@ -296,6 +307,9 @@ def main():
                     help="Newton backtracking halvings; -1: full steps (halved only at an inverted cell)")
     ap.add_argument("--forcing", type=int, default=0,
                     help="0: Krylov tolerance --eta on every Newton step; 1: Eisenstat-Walker from --eta")
+    ap.add_argument("--predictor", type=int, default=0,
+                    help="1: start each load increment from the secant prediction (one library call for "
+                         "all increments)")
     ap.add_argument("--solvers", default="plain,multigrid,learned",
                     help="time-to-tolerance solves to run: any of plain, multigrid, learned (learned needs plain)")
     ap.add_argument("--stepwise", type=int, default=0,
@@ -303,7 +317,8 @@ def main():
                          "steps per increment (0: one library call per increment)")
     ap.add_argument("--lz", type=float, default=1.0, help="z extent of the evaluation cube (cell aspect 1/lz)")
     args = ap.parse_args()
-    KRYLOV.update(eta=args.eta, restart=args.restart, line_search=args.line_search, forcing=args.forcing)
+    KRYLOV.update(eta=args.eta, restart=args.restart, line_search=args.line_search, forcing=args.forcing,
+                  predictor=args.predictor)
     solvers = set(args.solvers.split(","))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built",
@@ -417,7 +432,7 @@ def main():
     solve = None
     if args.solve:
         solve = {"krylov": {"eta": args.eta, "forcing": args.forcing, "restart": args.restart,
-                            "line_search": args.line_search}}
+                            "line_search": args.line_search, "predictor": args.predictor}}
         if "plain" in solvers:
             if prob.n_increments == 1:
                 newton(False)  # warm-up (allocates the Krylov workspace)

@@ -219,6 +219,11 @@ typedef struct {
                             0.9 eta_k-1^2 when that exceeds 0.1, at most eta (which
                             is also the first step's), and at least
                             0.5 tol ||R_0|| / ||R_k|| */
+  int32_t predictor;     /* 0: each increment starts from the last converged state;
+                            1: from u_i + (u_i - u_{i-1}) (secant in the load
+                            factor), unless that state has an inverted cell or a
+                            non-finite residual; ||R_0|| is still that of u_i at
+                            the new load */
 } hofv_newton_opts;
 
 typedef struct {

@@ -9,7 +9,9 @@ For every load increment i = 1..n (load factor i/n):
     first ||R(u + lam du)|| <= (1 - 1e-4 lam) ||R(u)|| (or the last trial);
     until ||R|| <= tol ||R0||.  The Krylov tolerance is ``eta`` (forcing 0) or
     the Eisenstat-Walker term of ``forcing_term`` starting from ``eta``
-    (forcing 1).  ls_max < 0: full steps, lam halved (at most
+    (forcing 1).  predictor 1 starts increment i+1 from u_i + (u_i - u_{i-1})
+    (a secant in the load factor; not in the paper) when R there is finite,
+    R0 staying that of u_i at the new load.  ls_max < 0: full steps, lam halved (at most
     10 times) only while R(u + lam du) is not finite (an inverted cell makes
     the neo-Hookean ln J undefined).
 The paper defers its line search to the authors' earlier work without
@@ -41,7 +43,7 @@ def forcing_term(rn, rprev, eta_prev, eta_max, tol, r0):
 
 def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
            maxit_newton=50, maxit_krylov=2000, n_increments=1, ls_max=10, precond_fn=None,
-           log=None, forcing=0):
+           log=None, forcing=0, predictor=0):
     n, D = disc.n_cells, disc.dim
     if A is None:
         A = precond.assemble(disc)
@@ -55,11 +57,21 @@ def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
             return precond_fn(v.reshape(n, D)).ravel()
         return precond.sgs(A, colours, v.reshape(n, D), sweeps).ravel()
 
+    u_prev = u.copy()
     for inc in range(1, n_increments + 1):
         load = inc / n_increments
         R = residual(disc, u, load)
         r0 = np.linalg.norm(R)
         rn = r0
+        if predictor == 1 and inc > 1:
+            u_pred = u + (u - u_prev)
+            u_prev = u
+            with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+                R_pred = residual(disc, u_pred, load)
+            if np.all(np.isfinite(R_pred)):
+                u, R, rn = u_pred, R_pred, np.linalg.norm(R_pred)
+        elif predictor == 1:
+            u_prev = u.copy()
         it = 0
         eta_k, rprev = eta, r0
         while rn > tol * r0 and it < maxit_newton:

@@ -46,7 +46,7 @@ class KrylovStats(C.Structure):
 class NewtonOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("eta", C.c_double), ("max_newton", C.c_int32),
                 ("n_increments", C.c_int32), ("max_line_search", C.c_int32), ("krylov", KrylovOpts),
-                ("forcing", C.c_int32)]
+                ("forcing", C.c_int32), ("predictor", C.c_int32)]
 
 
 class NewtonStats(C.Structure):

@@ -148,9 +148,10 @@ class Context:
 
     def newton_solve(self, u, tol=1e-8, eta=1e-4, max_newton=50, n_increments=1, max_line_search=10,
                      restart=30, max_krylov=2000, n_sweeps=2, learned=False, stream=None, check=True,
-                     forcing=0):
+                     forcing=0, predictor=0):
         o = L.NewtonOpts(tol, eta, max_newton, n_increments, max_line_search,
-                         L.KrylovOpts(restart, max_krylov, eta, n_sweeps, int(bool(learned))), int(forcing))
+                         L.KrylovOpts(restart, max_krylov, eta, n_sweeps, int(bool(learned))), int(forcing),
+                         int(predictor))
         s = L.NewtonStats()
         st = self.lib.hofv_newton_solve(self.h, _ptr(u), C.byref(o), C.byref(s), _stream(stream))
         if check or st not in (L.HOFV_OK, -5):

@@ -272,6 +272,7 @@ hofv_status hofv_newton_solve(hofv_ctx* c, double* d_u, const hofv_newton_opts* 
   if (s) return s;
   if (!d_u || !opts) return fail(c, HOFV_EINVAL, "null pointer");
   if (opts->forcing != 0 && opts->forcing != 1) return fail(c, HOFV_EINVAL, "forcing must be 0 or 1");
+  if (opts->predictor != 0 && opts->predictor != 1) return fail(c, HOFV_EINVAL, "predictor must be 0 or 1");
   if ((s = set_device(c))) return s;
   hofv_newton_stats tmp{};
   return newton_impl(c, d_u, opts, stats ? stats : &tmp, (hipStream_t)stream);

@@ -351,6 +351,13 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
   };
   // n_increments <= 0: one solve at the load factor set by hofv_set_load_scale
   const int ninc = std::max(1, o->n_increments);
+  // secant predictor: the previous increment's converged state
+  double* up = nullptr;
+  const bool predict = o->predictor == 1 && ninc > 1;
+  if (predict && (s = dev_alloc(c, &up, n))) {
+    release();
+    return s;
+  }
   const double load0 = c->load;
   const double tol = o->tol > 0 ? o->tol : 1e-8;
   hofv_krylov_opts ko = o->krylov;
@@ -366,6 +373,25 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
     double r0, rn;
     if ((s = host_norm(c, n, R, &r0, st))) { result = s; break; }
     rn = r0;
+    if (predict && inc > 1) {
+      // start from u_i + (u_i - u_{i-1}) unless that state is inadmissible;
+      // r0 stays the residual of u_i at the new load
+      k_lincomb<<<nblk(n), kB, 0, st>>>(n, 2.0, u, -1.0, up, ut);
+      HOFV_HIP(c, hipMemcpyAsync(up, u, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      k_fill_i<<<1, kB, 0, st>>>(1, 0, c->dev.flag);
+      if ((s = launch_residual(c, ut, Rt, nullptr, nullptr, st))) { result = s; break; }
+      int32_t flag = 0;
+      HOFV_HIP(c, hipMemcpyAsync(&flag, c->dev.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      double rt;
+      if ((s = host_norm(c, n, Rt, &rt, st))) { result = s; break; }
+      if (!flag && std::isfinite(rt)) {
+        HOFV_HIP(c, hipMemcpyAsync(u, ut, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HOFV_HIP(c, hipMemcpyAsync(R, Rt, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        rn = rt;
+      }
+    } else if (predict) {
+      HOFV_HIP(c, hipMemcpyAsync(up, u, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
     int itn = 0;
     double rprev = r0;
     ko.rtol = eta0;
@@ -426,6 +452,11 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
   }
   HOFV_HIP(c, hipStreamSynchronize(st));
   release();
+  if (up) {
+    hipFree(up);
+    c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), (void*)up), c->allocations.end());
+    c->device_bytes -= n * sizeof(double);
+  }
   stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (result == HOFV_OK && !stats->converged)
     return fail(c, HOFV_ENOCONV, "Newton did not reach the tolerance");

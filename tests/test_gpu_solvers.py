@@ -198,6 +198,29 @@ def test_newton_eisenstat_walker_forcing_matches_oracle():
         ctx.newton_solve(u, forcing=2)
 
 
+def test_newton_secant_predictor_matches_oracle():
+    """predictor = 1 over four increments of the tip-loaded beam: fewer Newton
+    steps than without it, and the oracle's state."""
+    prob = w.cantilever(shape=(8, 2, 2), p=1, n_plus=20, n_increments=4)
+    prob.mesh = w.box_mesh((8, 2, 2), lengths=(4.0, 1, 1))
+    prob.loads = w.fields.cantilever_loads(4.0, (0.0, -0.02, 0.0))
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    kw = dict(tol=1e-10, eta=1e-7, n_increments=4, max_line_search=-1, restart=96, max_krylov=200, max_newton=12)
+    u = torch.zeros((3, n), device=DEV, dtype=torch.float64)
+    st0 = ctx.newton_solve(u, **kw)
+    u.zero_()
+    st1 = ctx.newton_solve(u, predictor=1, **kw)
+    assert st0["converged"] and st1["converged"]
+    assert st1["newton_iters"] < st0["newton_iters"]
+    uo, _ = onw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-7, m=96, maxit_krylov=200, n_increments=4,
+                       ls_max=-1, maxit_newton=12, predictor=1)
+    assert np.linalg.norm(to_host(u) - uo) <= 1e-7 * np.linalg.norm(uo)
+    with pytest.raises(_api().HofvError):
+        ctx.newton_solve(u, predictor=3)
+
+
 def test_fgmres_stops_when_its_cycles_stall():
     """At a bent state (a quarter of the length of tip deflection) the
     one-sided finite-difference product is linear to ~1e-8; asked for 1e-11,

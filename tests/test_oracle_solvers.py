@@ -102,6 +102,19 @@ def test_eisenstat_walker_forcing_saves_krylov_work_and_keeps_the_solution():
     assert np.linalg.norm(u1 - u0) <= 1e-8 * np.linalg.norm(u0)
 
 
+def test_secant_predictor_saves_newton_steps_and_keeps_the_solution():
+    """Starting each load increment from u_i + (u_i - u_{i-1}) instead of u_i
+    ends at the same equilibrium in fewer Newton steps."""
+    disc = _tip_loaded_beam(0.02, 4)
+    n = disc.n_cells
+    kw = dict(tol=1e-10, eta=1e-7, m=96, maxit_krylov=200, n_increments=4, ls_max=-1, maxit_newton=12)
+    u0, st0 = nw.newton(disc, np.zeros((n, 3)), **kw)
+    u1, st1 = nw.newton(disc, np.zeros((n, 3)), predictor=1, **kw)
+    assert all(inc["rel"] <= 1e-10 for inc in st1["increments"])
+    assert st1["newton"] < st0["newton"]
+    assert np.linalg.norm(u1 - u0) <= 1e-8 * np.linalg.norm(u0)
+
+
 def test_forcing_term_rules():
     # quadratic-rate reduction 0.1 -> 0.9 * 0.01; safeguard off for a small previous eta
     assert nw.forcing_term(0.1, 1.0, 0.1, 0.5, 1e-12, 1.0) == pytest.approx(0.009)
