@@ -301,22 +301,34 @@ def main():
     ap.add_argument("--model", default="gpurun_out/learned_model.npy")
     ap.add_argument("--seed", type=int, default=50, help="mesh seed of --study eval")
     ap.add_argument("--max-newton", type=int, default=10, help="Newton steps per increment in --study eval")
-    ap.add_argument("--eta", type=float, default=1e-4, help="Krylov tolerance of each Newton step")
-    ap.add_argument("--restart", type=int, default=30, help="FGMRES cycle length (at most 2048)")
-    ap.add_argument("--line-search", type=int, default=10,
+    ap.add_argument("--eta", type=float, default=None,
+                    help="Krylov tolerance of each Newton step (default 1e-4; cantilever 0.5 with --forcing 1)")
+    ap.add_argument("--restart", type=int, default=None,
+                    help="FGMRES cycle length, at most 2048 (default 30; cantilever 500)")
+    ap.add_argument("--line-search", type=int, default=None,
                     help="Newton backtracking halvings; -1: full steps (halved only at an inverted cell)")
-    ap.add_argument("--forcing", type=int, default=0,
+    ap.add_argument("--forcing", type=int, default=None,
                     help="0: Krylov tolerance --eta on every Newton step; 1: Eisenstat-Walker from --eta")
-    ap.add_argument("--predictor", type=int, default=0,
+    ap.add_argument("--predictor", type=int, default=None,
                     help="1: start each load increment from the secant prediction (one library call for "
                          "all increments)")
-    ap.add_argument("--solvers", default="plain,multigrid,learned",
+    ap.add_argument("--solvers", default=None,
                     help="time-to-tolerance solves to run: any of plain, multigrid, learned (learned needs plain)")
     ap.add_argument("--stepwise", type=int, default=0,
                     help="time-to-tolerance solves as one logged library Newton step per call, at most this many "
                          "steps per increment (0: one library call per increment)")
     ap.add_argument("--lz", type=float, default=1.0, help="z extent of the evaluation cube (cell aspect 1/lz)")
     args = ap.parse_args()
+    # solver settings per workload, where not given: the slender cantilever needs long
+    # cycles, full Newton steps, the forcing term and the predictor (its sweeps-only
+    # solve does not converge, so it runs the multigrid one)
+    defaults = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0,
+                "solvers": "plain,multigrid,learned"}
+    if args.workload == "cantilever":
+        defaults.update(eta=0.5, restart=500, line_search=-1, forcing=1, predictor=1, solvers="multigrid")
+    for key, val in defaults.items():
+        if getattr(args, key) is None:
+            setattr(args, key, val)
     KRYLOV.update(eta=args.eta, restart=args.restart, line_search=args.line_search, forcing=args.forcing,
                   predictor=args.predictor)
     solvers = set(args.solvers.split(","))
