@@ -203,11 +203,25 @@ def study(args):
         t0 = time.perf_counter()
         data = []
         for seed in parse_seeds(args.train_seeds):
-            tp = w.cube_mms(args.learned_size, args.p, perturb=0.2, seed=seed)
-            tctx = api.context_for(tp)
+            if args.workload == "cantilever":
+                # a short beam with the cantilever's cells (0.05 cubes) and slenderness
+                # (10), perturbed by seed; the same tip traction bends it by the same
+                # fraction of its length.  The network learns to correct the V-cycle.
+                nx = args.learned_size
+                shape, lengths = (nx, nx // 10, nx // 10), (0.05 * nx, 0.005 * nx, 0.005 * nx)
+                tp = w.cantilever(shape=shape, p=args.p)
+                tp.mesh = w.box_mesh(shape, lengths=lengths, perturb=0.1, seed=seed)
+                tp.loads = w.fields.cantilever_loads(lengths[0], (0.0, -2.18e-3, 0.0))
+                tctx = api.context_for(tp, precond_levels=8)
+                tctx.set_multigrid(True)
+                tctx.set_load_scale(0.3)
+            else:
+                tp = w.cube_mms(args.learned_size, args.p, perturb=0.2, seed=seed)
+                tctx = api.context_for(tp)
             u0 = torch.zeros((3, tp.mesh.n_cells), device=dev, dtype=torch.float64)
-            r1, e1 = lrn.harvest_krylov(tctx, u0, n_starts=args.harvest_starts, length=args.harvest_length, seed=seed)
-            r2, e2 = lrn.harvest_newton(tctx, u0, n_steps=2)
+            r1, e1 = lrn.harvest_krylov(tctx, u0, n_starts=args.harvest_starts, length=args.harvest_length, seed=seed,
+                                        restart=args.restart)
+            r2, e2 = lrn.harvest_newton(tctx, u0, n_steps=2, restart=args.restart)
             data.append((tctx, torch.cat([r1, r2]), torch.cat([e1, e2])))
             log(f"harvested seed {seed}: {data[-1][1].shape[0]} pairs, {time.perf_counter() - t0:.0f}s")
         t_harvest = time.perf_counter() - t0
@@ -216,7 +230,9 @@ def study(args):
                          log=lambda ep, l: log(f"epoch {ep} loss {l:.4f}"))
         np.save(args.model, model.get_params())
         out = {"study": "train", "pairs": int(sum(d[1].shape[0] for d in data)),
-               "meshes": f"{args.learned_size}^3 p={args.p} perturbed cubes, seeds {args.train_seeds}",
+               "meshes": (f"{args.learned_size}x{args.learned_size // 10}x{args.learned_size // 10} p={args.p} "
+                          f"perturbed neo-Hookean beams (V-cycle inputs)" if args.workload == "cantilever" else
+                          f"{args.learned_size}^3 p={args.p} perturbed cubes") + f", seeds {args.train_seeds}",
                "epochs": args.learned_epochs, "harvest_seconds": t_harvest,
                "train_seconds": time.perf_counter() - t0 - t_harvest, "loss_first_epoch": hist[0],
                "loss_last_epoch": hist[-1], "model": args.model}
@@ -266,6 +282,13 @@ def study(args):
             ctx.set_multigrid(True)
             out["multigrid"] = newton_run(torch, ctx, prob, nc, False, tol, args.max_krylov, stepwise=args.max_newton)
             log(f"multigrid {out['multigrid']}")
+        if multigrid and "mglearned" in solvers:
+            # the network's correction of the V-cycle's output
+            ctx.set_multigrid(True)
+            out["mglearned"] = newton_run(torch, ctx, prob, nc, True, tol, args.max_krylov, stepwise=args.max_newton)
+            log(f"multigrid + learned {out['mglearned']}")
+            if "multigrid" in out:
+                out["mglearned_speedup"] = out["multigrid"]["seconds"] / out["mglearned"]["seconds"]
     print(json.dumps(out), flush=True)
 
 

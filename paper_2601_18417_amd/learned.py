@@ -9,14 +9,15 @@ Training pairs (r, e) with J e = r are produced by the solver itself:
 * Newton pairs: the residual R(u_k) of a Newton iterate and the converged
   correction of J du = -R(u_k).
 
-Each e is solved to ``rtol`` by FGMRES with the plain preconditioner.
+Each e is solved to ``rtol`` by FGMRES(restart) with the context's plain
+preconditioner (the sweeps, or the V-cycle when the context has it enabled).
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def harvest_krylov(ctx, u, n_starts=4, length=6, seed=0, rtol=1e-8, n_sweeps=2, max_iters=3000):
+def harvest_krylov(ctx, u, n_starts=4, length=6, seed=0, rtol=1e-8, n_sweeps=2, max_iters=3000, restart=30):
     """Returns r, e as device tensors [n_pairs, dim, n_cells]."""
     import torch
     dev = u.device
@@ -31,7 +32,8 @@ def harvest_krylov(ctx, u, n_starts=4, length=6, seed=0, rtol=1e-8, n_sweeps=2, 
         v /= torch.linalg.norm(v)
         for k in range(length):
             e = torch.zeros_like(u)
-            ctx.fgmres_solve(u, Ru, v, e, rtol=rtol, max_iters=max_iters, n_sweeps=n_sweeps, check=False)
+            ctx.fgmres_solve(u, Ru, v, e, rtol=rtol, max_iters=max_iters, n_sweeps=n_sweeps, check=False,
+                             restart=restart)
             rs.append(v.clone())
             es.append(e)
             ctx.precond_apply(v, tmp, n_sweeps=n_sweeps)
@@ -41,7 +43,7 @@ def harvest_krylov(ctx, u, n_starts=4, length=6, seed=0, rtol=1e-8, n_sweeps=2, 
     return torch.stack(rs), torch.stack(es)
 
 
-def harvest_newton(ctx, u0, n_steps=3, rtol=1e-8, n_sweeps=2, max_iters=3000):
+def harvest_newton(ctx, u0, n_steps=3, rtol=1e-8, n_sweeps=2, max_iters=3000, restart=30):
     """Pairs (R(u_k), du_k) along a Newton solve from u0 (J du = -R, so e = -du
     for r = R; stored as (r, e) with J e = r)."""
     import torch
@@ -51,7 +53,8 @@ def harvest_newton(ctx, u0, n_steps=3, rtol=1e-8, n_sweeps=2, max_iters=3000):
     for _ in range(n_steps):
         ctx.residual(u, R)
         e = torch.zeros_like(u)
-        ctx.fgmres_solve(u, R, R, e, rtol=rtol, max_iters=max_iters, n_sweeps=n_sweeps, check=False)
+        ctx.fgmres_solve(u, R, R, e, rtol=rtol, max_iters=max_iters, n_sweeps=n_sweeps, check=False,
+                         restart=restart)
         nr = torch.linalg.norm(R)
         rs.append(R / nr)
         es.append(e / nr)
