@@ -337,27 +337,39 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
   if (o->krylov.restart > kMaxRestart) return fail(c, HOFV_EINVAL, "FGMRES restart above 2048");
   hofv_status s = ensure_krylov(c, o->krylov.restart > 0 ? o->krylov.restart : 30);
   if (s) return s;
-  // workspace: R, du, rhs, ut, Rt
-  double *R, *du, *rhs, *ut, *Rt;
-  if ((s = dev_alloc(c, &R, n)) || (s = dev_alloc(c, &du, n)) || (s = dev_alloc(c, &rhs, n)) ||
-      (s = dev_alloc(c, &ut, n)) || (s = dev_alloc(c, &Rt, n)))
-    return s;
-  auto release = [&]() {
-    for (double* p : {R, du, rhs, ut, Rt}) {
-      hipFree(p);
-      c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), (void*)p), c->allocations.end());
-      c->device_bytes -= n * sizeof(double);
+  // workspace: R, du, rhs, ut, Rt and (secant predictor) the previous
+  // increment's converged state; released on every way out
+  struct Workspace {
+    hofv_ctx* c;
+    hipStream_t st;
+    std::vector<double*> bufs;
+    size_t bytes = 0;
+    ~Workspace() {
+      (void)hipStreamSynchronize(st);  // an early error return may leave work queued
+      for (double* p : bufs) {
+        hipFree(p);
+        c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), (void*)p),
+                             c->allocations.end());
+      }
+      c->device_bytes -= bytes;
     }
-  };
+    hofv_status get(double** p, int64_t count) {
+      hofv_status s = dev_alloc(c, p, (size_t)count);
+      if (s == HOFV_OK) {
+        bufs.push_back(*p);
+        bytes += (size_t)count * sizeof(double);
+      }
+      return s;
+    }
+  } ws{c, st, {}};
+  double *R, *du, *rhs, *ut, *Rt, *up = nullptr;
+  if ((s = ws.get(&R, n)) || (s = ws.get(&du, n)) || (s = ws.get(&rhs, n)) || (s = ws.get(&ut, n)) ||
+      (s = ws.get(&Rt, n)))
+    return s;
   // n_increments <= 0: one solve at the load factor set by hofv_set_load_scale
   const int ninc = std::max(1, o->n_increments);
-  // secant predictor: the previous increment's converged state
-  double* up = nullptr;
   const bool predict = o->predictor == 1 && ninc > 1;
-  if (predict && (s = dev_alloc(c, &up, n))) {
-    release();
-    return s;
-  }
+  if (predict && (s = ws.get(&up, n))) return s;
   const double load0 = c->load;
   const double tol = o->tol > 0 ? o->tol : 1e-8;
   hofv_krylov_opts ko = o->krylov;
@@ -451,12 +463,6 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
     if (!(rn <= tol * r0)) stats->converged = 0;
   }
   HOFV_HIP(c, hipStreamSynchronize(st));
-  release();
-  if (up) {
-    hipFree(up);
-    c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), (void*)up), c->allocations.end());
-    c->device_bytes -= n * sizeof(double);
-  }
   stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (result == HOFV_OK && !stats->converged)
     return fail(c, HOFV_ENOCONV, "Newton did not reach the tolerance");
