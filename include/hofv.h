@@ -251,6 +251,31 @@ typedef struct {
 hofv_status hofv_newton_solve(hofv_ctx* ctx, double* d_u, const hofv_newton_opts* opts,
                               hofv_newton_stats* stats, void* stream);
 
+/* ---- dynamics: BDF2 inertia (App. D, eq. inertiaTerm) -------------------------
+ * One integration point per cell (the centroid, u_P itself).  Velocity and
+ * acceleration are both BDF2 differences, so the inertia rho a Omega_P is
+ * m_P u_P - s_P with m_P = 9 rho Omega_P / (4 dt^2) and s_P built from u and v
+ * at the two previous time levels; R_P gains s_P - m_P u_P and the compact
+ * approximate Jacobian gains -m_P on its diagonal (its sweeps include it).
+ *
+ * hofv_set_dynamics: rho > 0 and dt > 0 switch the term on (rho <= 0 switches it
+ * off and restores the static preconditioner).  The multigrid hierarchy is
+ * built for the static operator: it is switched off here, and
+ * hofv_set_multigrid(1) returns HOFV_EINVAL while dynamics are on.  Allocates
+ * 6 D n_c + 2 n_c doubles on the first call.  Synchronises.
+ * hofv_dyn_reset: the history u^t, u^{t-1}, v^t, v^{t-1} (device [D][n_c], copied;
+ * a start from rest passes u0, u0, 0, 0).  HOFV_ESTATE without dynamics.
+ * hofv_dyn_step: one time step, a Newton solve (opts as hofv_newton_solve, with
+ * n_increments and predictor ignored) at the load factor set by
+ * hofv_set_load_scale, from the guess in d_u; on success the history advances
+ * to the result (v by BDF2).  On any error the history stays where it was.
+ * All three synchronise. */
+hofv_status hofv_set_dynamics(hofv_ctx* ctx, double rho, double dt);
+hofv_status hofv_dyn_reset(hofv_ctx* ctx, const double* d_u_t, const double* d_u_tm1, const double* d_v_t,
+                           const double* d_v_tm1, void* stream);
+hofv_status hofv_dyn_step(hofv_ctx* ctx, double* d_u, const hofv_newton_opts* opts, hofv_newton_stats* stats,
+                          void* stream);
+
 /* ---- learned correction of the preconditioner -------------------------------
  * A message-passing network over face neighbours (not part of the paper):
  * z = z_AJ + s_z g(x), x_P = [r_P/s_r, z_AJ,P/s_z, displacement-face flag, 1],

@@ -9,7 +9,9 @@ For every load increment i = 1..n (load factor i/n):
     first ||R(u + lam du)|| <= (1 - 1e-4 lam) ||R(u)|| (or the last trial);
     until ||R|| <= tol ||R0||.  The Krylov tolerance is ``eta`` (forcing 0) or
     the Eisenstat-Walker term of ``forcing_term`` starting from ``eta``
-    (forcing 1).  predictor 1 starts increment i+1 from u_i + (u_i - u_{i-1})
+    (forcing 1).  ``inertia`` = (m, s) adds a BDF2 time step's inertia to R
+    and -m to the approximate Jacobian's diagonal (oracle.dynamics).
+    predictor 1 starts increment i+1 from u_i + (u_i - u_{i-1})
     (a secant in the load factor; not in the paper) when R there is finite,
     R0 staying that of u_i at the new load.  ls_max < 0: full steps, lam halved (at most
     10 times) only while R(u + lam du) is not finite (an inverted cell makes
@@ -43,10 +45,10 @@ def forcing_term(rn, rprev, eta_prev, eta_max, tol, r0):
 
 def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
            maxit_newton=50, maxit_krylov=2000, n_increments=1, ls_max=10, precond_fn=None,
-           log=None, forcing=0, predictor=0):
+           log=None, forcing=0, predictor=0, inertia=None, load_scale=1.0):
     n, D = disc.n_cells, disc.dim
     if A is None:
-        A = precond.assemble(disc)
+        A = precond.assemble(disc, None if inertia is None else inertia[0])
     if colours is None:
         colours = precond.greedy_colours(A)
     u = np.asarray(u0, float).copy()
@@ -59,15 +61,15 @@ def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
 
     u_prev = u.copy()
     for inc in range(1, n_increments + 1):
-        load = inc / n_increments
-        R = residual(disc, u, load)
+        load = load_scale * inc / n_increments
+        R = residual(disc, u, load, inertia)
         r0 = np.linalg.norm(R)
         rn = r0
         if predictor == 1 and inc > 1:
             u_pred = u + (u - u_prev)
             u_prev = u
             with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
-                R_pred = residual(disc, u_pred, load)
+                R_pred = residual(disc, u_pred, load, inertia)
             if np.all(np.isfinite(R_pred)):
                 u, R, rn = u_pred, R_pred, np.linalg.norm(R_pred)
         elif predictor == 1:
@@ -86,7 +88,7 @@ def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
                 eps = default_eps(uu, vv)
                 if eps == 0.0:
                     return np.zeros_like(v)
-                return ((residual(disc, uu + eps * vv, load) - Ru) / eps).ravel()
+                return ((residual(disc, uu + eps * vv, load, inertia) - Ru) / eps).ravel()
 
             du, info = fgmres(J, -R.ravel(), M, m=m, rtol=eta_k, maxit=maxit_krylov)
             stats["krylov"] += info["iters"]
@@ -96,7 +98,7 @@ def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
             for _ in range((10 if full else ls_max) + 1):
                 ut = u + lam * du
                 with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
-                    Rt = residual(disc, ut, load)
+                    Rt = residual(disc, ut, load, inertia)
                 finite = bool(np.all(np.isfinite(Rt)))
                 if finite and (full or np.linalg.norm(Rt) <= (1.0 - 1e-4 * lam) * rn):
                     break

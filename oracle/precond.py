@@ -29,8 +29,10 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def assemble(disc_full):
-    """Sparse A (n_c x n_c) from a full (all-cells) discretisation."""
+def assemble(disc_full, mass=None):
+    """Sparse A (n_c x n_c) from a full (all-cells) discretisation; with the
+    BDF2 inertia's m (oracle.dynamics) the diagonal gains -m_P, the Jacobian of
+    its -m_P u_P."""
     d = disc_full
     n = d.n_cells
     dPN = d.cen[d.f_nei] - d.cen[d.f_own]
@@ -44,6 +46,8 @@ def assemble(disc_full):
     np.add.at(diag, d.f_own, -a)
     np.add.at(diag, d.f_nei, -a)
     np.add.at(diag, d.d_own, -ab)
+    if mass is not None:
+        diag = diag - mass
     A = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
     A = A + sp.diags(diag)
     return A.tocsr()

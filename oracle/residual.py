@@ -306,8 +306,12 @@ def face_fluxes(disc, u, load=1.0):
     return Ff, Fd
 
 
-def residual(disc, u, load=1.0):
-    """R(u), (n_c, D).  u is (n_c, D) float64 or complex128."""
+def residual(disc, u, load=1.0, inertia=None):
+    """R(u), (n_c, D).  u is (n_c, D) float64 or complex128.
+
+    inertia = (m, s) adds the BDF2 inertia of a time step (App. D, one point
+    per cell at the centroid): R_P += s_P - m_P u_P (oracle.dynamics builds m
+    and s from rho, dt and the history)."""
     u = np.asarray(u)
     Ff, Fd = face_fluxes(disc, u, load)
     R = np.zeros((disc.n_cells, disc.dim), dtype=np.result_type(u.dtype, np.float64))
@@ -315,4 +319,7 @@ def residual(disc, u, load=1.0):
     np.add.at(R, disc.f_nei, -Ff)
     np.add.at(R, disc.d_own, Fd)
     R += load * (disc.b_body + disc.b_trac)
+    if inertia is not None:
+        m, s = inertia
+        R += s - m[:, None] * u
     return R

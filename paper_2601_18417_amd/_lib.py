@@ -78,6 +78,9 @@ SIGNATURES = {
     "hofv_precond_apply": (ST, [P, P, P, C.c_int32, C.c_int32, P]),
     "hofv_fgmres_solve": (ST, [P, P, P, P, P, C.POINTER(KrylovOpts), C.POINTER(KrylovStats), P]),
     "hofv_newton_solve": (ST, [P, P, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), P]),
+    "hofv_set_dynamics": (ST, [P, C.c_double, C.c_double]),
+    "hofv_dyn_reset": (ST, [P, P, P, P, P, P]),
+    "hofv_dyn_step": (ST, [P, P, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), P]),
     "hofv_set_timing": (ST, [P, C.c_int32]),
     "hofv_kernel_time": (ST, [P, C.c_char_p, D, C.POINTER(C.c_int64)]),
     "hofv_kernel_bytes": (ST, [P, C.c_char_p, D]),

@@ -146,14 +146,43 @@ class Context:
             self._check(st)
         return {k: getattr(s, k) for k, _ in L.KrylovStats._fields_}
 
+    @staticmethod
+    def _newton_opts(tol, eta, max_newton, n_increments, max_line_search, restart, max_krylov, n_sweeps, learned,
+                     forcing, predictor):
+        return L.NewtonOpts(tol, eta, max_newton, n_increments, max_line_search,
+                            L.KrylovOpts(restart, max_krylov, eta, n_sweeps, int(bool(learned))), int(forcing),
+                            int(predictor))
+
     def newton_solve(self, u, tol=1e-8, eta=1e-4, max_newton=50, n_increments=1, max_line_search=10,
                      restart=30, max_krylov=2000, n_sweeps=2, learned=False, stream=None, check=True,
                      forcing=0, predictor=0):
-        o = L.NewtonOpts(tol, eta, max_newton, n_increments, max_line_search,
-                         L.KrylovOpts(restart, max_krylov, eta, n_sweeps, int(bool(learned))), int(forcing),
-                         int(predictor))
+        o = self._newton_opts(tol, eta, max_newton, n_increments, max_line_search, restart, max_krylov, n_sweeps,
+                              learned, forcing, predictor)
         s = L.NewtonStats()
         st = self.lib.hofv_newton_solve(self.h, _ptr(u), C.byref(o), C.byref(s), _stream(stream))
+        if check or st not in (L.HOFV_OK, -5):
+            self._check(st)
+        return {k: getattr(s, k) for k, _ in L.NewtonStats._fields_}
+
+    # ------------------------------------------------------------- dynamics
+    def set_dynamics(self, rho, dt):
+        """BDF2 inertia with density rho and time step dt (rho <= 0: static)."""
+        self._check(self.lib.hofv_set_dynamics(self.h, float(rho), float(dt)))
+
+    def dyn_reset(self, u_t, v_t, u_tm1=None, v_tm1=None, stream=None):
+        """History of the next step; u_tm1, v_tm1 default to u_t, v_t."""
+        u_tm1 = u_t if u_tm1 is None else u_tm1
+        v_tm1 = v_t if v_tm1 is None else v_tm1
+        self._check(self.lib.hofv_dyn_reset(self.h, _ptr(u_t), _ptr(u_tm1), _ptr(v_t), _ptr(v_tm1),
+                                            _stream(stream)))
+
+    def dyn_step(self, u, tol=1e-8, eta=1e-4, max_newton=50, max_line_search=10, restart=30, max_krylov=2000,
+                 n_sweeps=2, learned=False, stream=None, check=True, forcing=0):
+        """One time step from the guess in u (updated in place)."""
+        o = self._newton_opts(tol, eta, max_newton, 0, max_line_search, restart, max_krylov, n_sweeps, learned,
+                              forcing, 0)
+        s = L.NewtonStats()
+        st = self.lib.hofv_dyn_step(self.h, _ptr(u), C.byref(o), C.byref(s), _stream(stream))
         if check or st not in (L.HOFV_OK, -5):
             self._check(st)
         return {k: getattr(s, k) for k, _ in L.NewtonStats._fields_}

@@ -21,7 +21,7 @@ ARCH = "gfx950"
 
 HOST_SOURCES = ["api.cpp", "setup_mesh.cpp", "setup_stencil.cpp", "setup_lsq.cpp", "setup_blocks.cpp", "setup_amg.cpp",
                 "setup_tables.cpp"]
-DEVICE_SOURCES = ["kernels.hip", "krylov.hip", "mpnn.hip"]
+DEVICE_SOURCES = ["kernels.hip", "krylov.hip", "mpnn.hip", "dynamics.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

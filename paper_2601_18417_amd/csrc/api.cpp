@@ -218,8 +218,36 @@ hofv_status hofv_set_multigrid(hofv_ctx* c, int32_t enable) {
   hofv_status s = need(c, 4, "set_multigrid");
   if (s) return s;
   if (enable && c->dev.mg.size() < 2) return fail(c, HOFV_EINVAL, "no multigrid hierarchy was built at setup");
+  if (enable && c->dev.dyn_m) return fail(c, HOFV_EINVAL, "the multigrid hierarchy is built for the static operator");
   c->use_mg = enable != 0;
   return HOFV_OK;
+}
+
+hofv_status hofv_set_dynamics(hofv_ctx* c, double rho, double dt) {
+  hofv_status s = need(c, 4, "set_dynamics");
+  if (s) return s;
+  if ((s = set_device(c))) return s;
+  return dyn_set(c, rho, dt);
+}
+
+hofv_status hofv_dyn_reset(hofv_ctx* c, const double* d_u_t, const double* d_u_tm1, const double* d_v_t,
+                           const double* d_v_tm1, void* stream) {
+  hofv_status s = need(c, 4, "dyn_reset");
+  if (s) return s;
+  if (!d_u_t || !d_u_tm1 || !d_v_t || !d_v_tm1) return fail(c, HOFV_EINVAL, "null pointer");
+  if ((s = set_device(c))) return s;
+  return dyn_reset(c, d_u_t, d_u_tm1, d_v_t, d_v_tm1, (hipStream_t)stream);
+}
+
+hofv_status hofv_dyn_step(hofv_ctx* c, double* d_u, const hofv_newton_opts* opts, hofv_newton_stats* stats,
+                          void* stream) {
+  hofv_status s = need(c, 4, "dyn_step");
+  if (s) return s;
+  if (!d_u || !opts) return fail(c, HOFV_EINVAL, "null pointer");
+  if (opts->forcing != 0 && opts->forcing != 1) return fail(c, HOFV_EINVAL, "forcing must be 0 or 1");
+  if ((s = set_device(c))) return s;
+  hofv_newton_stats tmp{};
+  return dyn_step(c, d_u, opts, stats ? stats : &tmp, (hipStream_t)stream);
 }
 
 hofv_status hofv_residual(hofv_ctx* c, const double* d_u, double* d_R, void* stream) {

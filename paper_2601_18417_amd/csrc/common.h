@@ -90,6 +90,12 @@ struct DeviceTables {
   float* p_r = nullptr;          // [D][nc]
   float* p_z = nullptr;          // [D][nc]
   float* p_diag = nullptr;       // [nc] A_PP (multigrid residual)
+  // BDF2 inertia (App. D, one point per cell): R_P += s_P - m_P u_P
+  double* dyn_rv = nullptr;      // [nc] rho * volume
+  double* dyn_m = nullptr;       // [nc] 9 rho vol / (4 dt^2); null: static
+  double* dyn_m_buf = nullptr;   // the buffer dyn_m points to when dynamics are on
+  double* dyn_s = nullptr;       // [D][nc] the step's constant part
+  double *dyn_ut = nullptr, *dyn_utm1 = nullptr, *dyn_vt = nullptr, *dyn_vtm1 = nullptr;  // [D][nc] history
   // multigrid levels 1.. of the approximate Jacobian (empty: sweeps only);
   // transfer operators of level l map level l (level 0 in colour-major
   // order) to level l + 1
@@ -160,6 +166,12 @@ struct hofv_ctx {
   std::vector<double> ubq, ubc, tq, fb;
 
   hofv_setup_report report{};
+  // approximate Jacobian diagonal by sweep position (static) and the position's
+  // cell, for re-deriving the sweeps' diagonal when an inertia term is added
+  std::vector<double> pc_diag;
+  std::vector<int64_t> pc_perm;
+  double dyn_rho = 0.0, dyn_dt = 0.0;
+  bool dyn_ready = false;  // history set by hofv_dyn_reset
   hofv::DeviceTables dev;
   hofv::Krylov kry;
   hofv::NnWork nnw;
@@ -279,6 +291,11 @@ hofv_status launch_eps(hofv_ctx* c, const double* u, const double* v, double eps
                        hipStream_t st);
 hofv_status launch_axpy_w(hofv_ctx* c, const double* u, const double* v, hipStream_t st);
 hofv_status launch_precond(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st);
+// dynamics.hip
+hofv_status dyn_set(hofv_ctx* c, double rho, double dt);
+hofv_status dyn_reset(hofv_ctx* c, const double* u_t, const double* u_tm1, const double* v_t, const double* v_tm1,
+                      hipStream_t st);
+hofv_status dyn_step(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_newton_stats* stats, hipStream_t st);
 
 // timing helpers
 void timer_begin(hofv_ctx* c, const char* name, hipStream_t st, hipEvent_t* ev);

@@ -388,8 +388,11 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, const int32_t* __restrict__ cf,
                                                       const double* __restrict__ F, const double* __restrict__ src,
                                                       double load, const double* __restrict__ Ru,
-                                                      const double* __restrict__ eps, double* __restrict__ R) {
+                                                      const double* __restrict__ eps, const double* __restrict__ ug,
+                                                      const double* __restrict__ dm, const double* __restrict__ ds,
+                                                      double* __restrict__ R) {
   constexpr int NS = 2 * D;
+  constexpr int W = D == 3 ? 4 : 2;
   const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (P >= nc) return;
   int32_t code[NS];
@@ -405,6 +408,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, con
       if (k >= 0) acc += F[(int64_t)c * nf + k];
       else acc -= F[(int64_t)c * nf + ~k];
     }
+    // BDF2 inertia at the centroid: s_P - m_P u_P (u from the gather copy)
+    if (dm) acc += ds[(int64_t)c * nc + P] - dm[P] * ug[(int64_t)W * P + c];
     if (Ru) {
       const double e = eps[0];
       acc = e > 0.0 ? (acc - Ru[(int64_t)c * nc + P]) / e : 0.0;
@@ -732,7 +737,7 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
     }
   }
   TIMED("k_cell_sum", (k_cell_sum<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, nf, t.c_faces, t.flux, t.c_src, c->load,
-                                                                          Ru, eps, R)));
+                                                                          Ru, eps, u, t.dyn_m, t.dyn_s, R)));
   HOFV_HIP(c, hipGetLastError());
   return HOFV_OK;
 }

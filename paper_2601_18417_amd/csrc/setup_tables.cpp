@@ -308,10 +308,14 @@ hofv_status build_tables(hofv_ctx* c) {
   c->dev.n_colours = ncol;
   std::vector<int32_t> pnbr((size_t)NS * nc);
   std::vector<float> pa((size_t)NS * nc), pdinv(nc), pdiag(nc);
+  c->pc_diag.assign(nc, 0.0);
+  c->pc_perm.assign(nc, 0);
   for (int64_t i = 0; i < nc; ++i) {
     const int64_t P = perm[i];
     pdinv[i] = (float)(1.0 / diag[P]);
     pdiag[i] = (float)diag[P];
+    c->pc_diag[i] = diag[P];
+    c->pc_perm[i] = P;
     for (int s = 0; s < NS; ++s) {
       int64_t N = nbr[(size_t)s * nc + P];
       pnbr[(size_t)s * nc + i] = N >= 0 ? pos[N] : (int32_t)i;
