@@ -189,6 +189,42 @@ def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None, stepw
     return out
 
 
+def column_steps(args, torch, ctx, prob, cen):
+    """BDF2 time steps of the vibrating column from rest under the sudden end
+    traction; the transverse displacement of the loaded end is sampled every
+    10 steps."""
+    nc = prob.mesh.n_cells
+    rho, dt = prob.meta["rho"], prob.meta["dt"]
+    ctx.set_dynamics(rho, dt)
+    u = torch.zeros((3, nc), device="cuda:0", dtype=torch.float64)
+    ctx.dyn_reset(u, u.clone())
+    L = prob.mesh.lengths[0]
+    end = np.nonzero(cen[:, 0] > L - L / prob.mesh.shape[0])[0]
+    tol = args.tol if args.tol > 0 else 1e-8
+    out = {"rho": rho, "dt": dt, "steps": args.time_steps, "newton_iters": 0, "krylov_iters": 0,
+           "tol": tol, "end_displacement": []}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, args.time_steps + 1):
+        st = ctx.dyn_step(u, tol=tol, eta=KRYLOV["eta"], restart=KRYLOV["restart"], max_krylov=args.max_krylov,
+                          max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"], check=False)
+        out["newton_iters"] += st["newton_iters"]
+        out["krylov_iters"] += st["krylov_iters"]
+        if not st["converged"]:
+            out["failed_step"] = k
+            break
+        if k % 10 == 0:
+            ue = u[1:, end].mean(dim=1).cpu().numpy()
+            out["end_displacement"].append([k * dt, float(ue[0]), float(ue[1])])
+            log(f"column step {k}: t = {k * dt:.3f} s, end (u_y, u_z) = ({ue[0]:.4f}, {ue[1]:.4f}) m, "
+                f"{out['newton_iters']} Newton, {out['krylov_iters']} Krylov, {time.perf_counter() - t0:.1f}s")
+    torch.cuda.synchronize()
+    out["seconds"] = time.perf_counter() - t0
+    out["ms_per_step"] = 1e3 * out["seconds"] / max(k, 1)
+    ctx.set_dynamics(0.0, 0.0)
+    return out
+
+
 def study(args):
     """The learned-preconditioner study: 'train' harvests pairs on seeded
     perturbed cubes and trains a model (saved as a float32 .npy); 'eval' times
@@ -297,9 +333,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="cube", choices=["cube", "cantilever", "square"],
+    ap.add_argument("--workload", default="cube", choices=["cube", "cantilever", "square", "column"],
                     help="cube: 3D LE manufactured solution on a perturbed n^3 mesh (default); cantilever: "
-                         "3D neo-Hookean 200x20x20 beam, 10 load increments; square: 2D 32x32 LE, p=2")
+                         "3D neo-Hookean 200x20x20 beam, 10 load increments; square: 2D 32x32 LE, p=2; "
+                         "column: the vibrating neo-Hookean column, BDF2 time steps")
+    ap.add_argument("--column-cells", default="50x5x5", help="cells of the column (length x width x depth)")
+    ap.add_argument("--time-steps", type=int, default=100, help="BDF2 steps of the column (dt = 1 ms)")
     ap.add_argument("--n", type=int, default=64, help="cells per axis")
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=1000, help="cells for the CPU oracle (0: skip)")
@@ -312,7 +351,7 @@ def main():
     ap.add_argument("--max-krylov", type=int, default=4000, help="Krylov iterations per Newton step")
     ap.add_argument("--calib", type=int, default=0,
                     help="run a plain 512 MiB elementwise copy first (counter calibration)")
-    ap.add_argument("--precond-levels", type=int, default=8,
+    ap.add_argument("--precond-levels", type=int, default=None,
                     help="multigrid levels built for the approximate Jacobian (1: sweeps only); the plain and "
                          "learned solves use the sweeps, a third solve the V-cycle")
     ap.add_argument("--study", choices=["train", "eval"], default=None,
@@ -346,9 +385,11 @@ def main():
     # cycles, full Newton steps, the forcing term and the predictor (its sweeps-only
     # solve does not converge, so it runs the multigrid one)
     defaults = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0,
-                "solvers": "plain,multigrid,learned"}
+                "solvers": "plain,multigrid,learned", "precond_levels": 8}
     if args.workload == "cantilever":
         defaults.update(eta=0.5, restart=500, line_search=-1, forcing=1, predictor=1, solvers="multigrid")
+    elif args.workload == "column":  # the mass term keeps each step well conditioned
+        defaults.update(eta=0.1, restart=60, line_search=-1, forcing=1, precond_levels=1)
     for key, val in defaults.items():
         if getattr(args, key) is None:
             setattr(args, key, val)
@@ -381,6 +422,8 @@ def main():
         prob = w.cube_mms(args.n, args.p, perturb=0.2, seed=0)
     elif args.workload == "cantilever":
         prob = w.cantilever(p=args.p)
+    elif args.workload == "column":
+        prob = w.vibrating_column(tuple(int(x) for x in args.column_cells.split("x")), p=args.p)
     else:
         prob = w.square_mms(32, args.p)
     nc, D = prob.mesh.n_cells, prob.dim
@@ -398,10 +441,10 @@ def main():
     cen = ctx.cell_centroids()
     if prob.loads.exact is not None:
         u = torch.tensor(prob.loads.exact.value(cen).T.copy(), device=dev)
-    else:  # a bent state of the cantilever: u_y = -0.3 x^2 / L, the throughput state
+    else:  # a bent state of the beam: u_y = -0.3 x^2 / L (0.03 for the column), the throughput state
         L = prob.mesh.lengths[0]
         st = np.zeros((nc, 3))
-        st[:, 1] = -0.3 * cen[:, 0] ** 2 / L
+        st[:, 1] = -(0.03 if args.workload == "column" else 0.3) * cen[:, 0] ** 2 / L
         u = torch.tensor(st.T.copy(), device=dev)
     v = torch.tensor(np.random.default_rng(1000).standard_normal((D, nc)), device=dev)
     Ru = torch.empty_like(u)
@@ -465,7 +508,9 @@ def main():
         return out
 
     solve = None
-    if args.solve:
+    if args.solve and args.workload == "column":
+        solve = {"dynamics": column_steps(args, torch, ctx, prob, cen)}
+    elif args.solve:
         solve = {"krylov": {"eta": args.eta, "forcing": args.forcing, "restart": args.restart,
                             "line_search": args.line_search, "predictor": args.predictor}}
         if "plain" in solvers:
@@ -559,7 +604,10 @@ def main():
                                 "cantilever": f"3D neo-Hookean cantilever 200x20x20 hex (mu=1, lambda=10), p={args.p}, "
                                               f"|S|={ctx.report['stencil_size']}, 10 load increments",
                                 "square": f"2D plane-strain LE MMS, 32x32 quads, p={args.p}, "
-                                          f"|S|={ctx.report['stencil_size']}"}[args.workload],
+                                          f"|S|={ctx.report['stencil_size']}",
+                                "column": f"3D neo-Hookean vibrating column 6 x 0.2 x 0.2 m, {args.column_cells} hex, "
+                                          f"p={args.p}, |S|={ctx.report['stencil_size']}, BDF2 dt = 1 ms"
+                                }[args.workload],
                    "n_cells": nc, "global_batch": nc, "parallelism": "single GPU"},
         "residual_mcells_s": nc / (ms_res * 1e-3) / 1e6,
         "jvp_algorithmic_GBps": jvp_bytes / (ms_step * 1e-3) / 1e9,

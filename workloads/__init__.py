@@ -7,5 +7,5 @@ from .meshes import Mesh, box_mesh, cell_ijk  # noqa: F401
 from .fields import (DISP, TRAC, Loads, PolyField, TrigField, body_force_le,  # noqa: F401
                      lame_from_young, mms_2d_unit, mms_3d_trig, mms_loads, random_poly_field,
                      traction_le)
-from .configs import (LINEAR_ELASTIC, NEO_HOOKEAN, Problem, cantilever, cube_mms,  # noqa: F401
+from .configs import (LINEAR_ELASTIC, NEO_HOOKEAN, Problem, cantilever, cube_mms, vibrating_column,  # noqa: F401
                       poly_patch, random_state, square_mms)

@@ -99,6 +99,20 @@ def cantilever(shape=(200, 20, 20), p: int = 2, mu: float = 1.0, lam: float = 10
                    n_increments=n_increments)
 
 
+def vibrating_column(shape=(50, 5, 5), p: int = 1, E: float = 15.293e6, nu: float = 0.3,
+                     rho: float = 1000.0, dt: float = 1e-3) -> Problem:
+    """The paper's vibrating 3D column (Sec. 5, case 7): 6 m x 0.2 m x 0.2 m,
+    neo-Hookean, clamped at one end, a sudden traction of 50 kPa in each of the
+    two transverse directions on the other end, BDF2 with dt = 1 ms.  Laid along
+    x here (the paper stands it along z); 1250 cells by default as in the paper.
+    rho and dt ride in ``meta``."""
+    mu, lam = lame_from_young(E, nu)
+    mesh = box_mesh(shape, lengths=(6.0, 0.2, 0.2))
+    loads = cantilever_loads(6.0, (0.0, 5e4, 5e4))
+    return Problem(f"column_{'x'.join(map(str, shape))}_p{p}", mesh, p, PAPER_N_PLUS[3][p], default_gauss(p),
+                   NEO_HOOKEAN, mu, lam, loads, stencil_quantum=quantum_for(mesh), meta={"rho": rho, "dt": dt})
+
+
 def poly_patch(mesh: Mesh, p: int, degree: int, seed: int = 0, E: float = 1.0, nu: float = 0.3,
                n_plus=None, n_gauss=None, scale: float = 1.0, traction_faces=None) -> Problem:
     mu, lam = lame_from_young(E, nu)
