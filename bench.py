@@ -105,7 +105,7 @@ def parse_seeds(s):
     return out
 
 
-KRYLOV = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0}  # Newton's Krylov options (set from the arguments)
+KRYLOV = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0, "side": 0}  # Newton's Krylov options (set from the arguments)
 
 
 def forcing_term(rn, rprev, eta_prev, eta_max, tol, r0):
@@ -132,7 +132,7 @@ def newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, max_newton, label)
         rprev = rn
         st = ctx.newton_solve(uu, tol=1e-300, eta=eta, max_newton=1, max_krylov=max_krylov, n_sweeps=2,
                               learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"],
-                              max_line_search=KRYLOV["line_search"])
+                              max_line_search=KRYLOV["line_search"], side=KRYLOV["side"])
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             tot[key] += st[key]
         ctx.residual(uu, R)
@@ -159,7 +159,7 @@ def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None, stepw
         # the predictor spans increments: one library call for all of them
         st = ctx.newton_solve(uu, tol=tol, eta=KRYLOV["eta"], max_krylov=max_krylov, n_sweeps=2, learned=learned,
                               check=False, n_increments=ninc, restart=KRYLOV["restart"],
-                              max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"], predictor=1)
+                              max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"], predictor=1, side=KRYLOV["side"])
         torch.cuda.synchronize()
         out.update({key: st[key] for key in ("newton_iters", "krylov_iters", "fallbacks", "rel_residual")})
         out["converged"] = bool(st["converged"])
@@ -174,7 +174,7 @@ def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None, stepw
         else:
             st = ctx.newton_solve(uu, tol=tol, eta=KRYLOV["eta"], max_krylov=max_krylov, n_sweeps=2,
                                   learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"],
-                                  max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"])
+                                  max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"], side=KRYLOV["side"])
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             out[key] += st[key]
         out["rel_residual"] = st["rel_residual"]
@@ -374,6 +374,9 @@ def main():
     ap.add_argument("--predictor", type=int, default=None,
                     help="1: start each load increment from the secant prediction (one library call for "
                          "all increments)")
+    ap.add_argument("--side", type=int, default=0,
+                    help="0: right-preconditioned FGMRES; 1: left-preconditioned GMRES as eq. jfnk prints it "
+                         "(its tolerance is on the preconditioned residual)")
     ap.add_argument("--solvers", default=None,
                     help="time-to-tolerance solves to run: any of plain, multigrid, learned (learned needs plain)")
     ap.add_argument("--stepwise", type=int, default=0,
@@ -394,7 +397,7 @@ def main():
         if getattr(args, key) is None:
             setattr(args, key, val)
     KRYLOV.update(eta=args.eta, restart=args.restart, line_search=args.line_search, forcing=args.forcing,
-                  predictor=args.predictor)
+                  predictor=args.predictor, side=args.side)
     solvers = set(args.solvers.split(","))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built",
@@ -512,7 +515,7 @@ def main():
         solve = {"dynamics": column_steps(args, torch, ctx, prob, cen)}
     elif args.solve:
         solve = {"krylov": {"eta": args.eta, "forcing": args.forcing, "restart": args.restart,
-                            "line_search": args.line_search, "predictor": args.predictor}}
+                            "line_search": args.line_search, "predictor": args.predictor, "side": args.side}}
         if "plain" in solvers:
             if prob.n_increments == 1:
                 newton(False)  # warm-up (allocates the Krylov workspace)

@@ -174,6 +174,11 @@ typedef struct {
   double rtol;           /* stop at ||rhs - J x|| <= rtol ||rhs|| */
   int32_t n_sweeps;      /* preconditioner sweeps per application */
   int32_t learned;       /* use the learned correction */
+  int32_t side;          /* 0: right-preconditioned flexible GMRES (default);
+                            1: left-preconditioned GMRES on M J x = M rhs as eq. jfnk
+                            prints it: the stopping test and rel_residual are then
+                            those of the preconditioned residual M (rhs - J x)
+                            against M rhs; not with learned (HOFV_EINVAL) */
 } hofv_krylov_opts;
 
 typedef struct {

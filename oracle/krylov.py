@@ -84,3 +84,53 @@ def fgmres(A, b, M=None, x0=None, m=30, rtol=1e-8, maxit=1000, callback=None, st
         x = x + Z[:k].T @ y
         r = b - A(x)
         beta = np.linalg.norm(r)
+
+
+def gmres_left(A, b, M, x0=None, m=30, rtol=1e-8, maxit=1000, stall=STALL):
+    """Left-preconditioned GMRES(m) (eq. jfnk as printed): minimises
+    ||M (b - A x)|| over x0 + K_k(M A, M r0), classical Gram-Schmidt twice; stops
+    when ||M (b - A x)|| <= rtol ||M b|| (recomputed at every restart), after
+    ``maxit`` iterations, or when a cycle keeps more than ``stall`` of that
+    residual.  M must be a fixed linear operator.  Returns (x, info dict)."""
+    b = np.asarray(b, float).ravel()
+    n = b.size
+    x = np.zeros(n) if x0 is None else np.asarray(x0, float).ravel().copy()
+    bnorm = np.linalg.norm(M(b))
+    if bnorm == 0.0:
+        return np.zeros(n), {"iters": 0, "converged": True, "rel": 0.0, "hist": [0.0], "stalled": False}
+    its, beta_prev, hist = 0, None, []
+    while True:
+        r = M(b - A(x))
+        beta = np.linalg.norm(r)
+        hist.append(beta / bnorm)
+        stalled = beta_prev is not None and beta > stall * beta_prev
+        if beta <= rtol * bnorm or its >= maxit or stalled:
+            return x, {"iters": its, "converged": beta <= rtol * bnorm, "rel": beta / bnorm, "hist": hist,
+                       "stalled": bool(stalled and beta > rtol * bnorm)}
+        beta_prev = beta
+        V = np.zeros((m + 1, n))
+        H = np.zeros((m + 1, m))
+        V[0] = r / beta
+        k = 0
+        for j in range(m):
+            w = M(A(V[j]))
+            for _ in range(2):
+                h = V[: j + 1] @ w
+                w = w - V[: j + 1].T @ h
+                H[: j + 1, j] += h
+            H[j + 1, j] = np.linalg.norm(w)
+            its += 1
+            k = j + 1
+            if H[j + 1, j] > 0:
+                V[j + 1] = w / H[j + 1, j]
+            # least-squares residual of this Krylov space
+            e1 = np.zeros(k + 1)
+            e1[0] = beta
+            y, *_ = np.linalg.lstsq(H[: k + 1, :k], e1, rcond=None)
+            res = np.linalg.norm(e1 - H[: k + 1, :k] @ y)
+            if res <= rtol * bnorm or its >= maxit or H[j + 1, j] == 0.0:
+                break
+        e1 = np.zeros(k + 1)
+        e1[0] = beta
+        y, *_ = np.linalg.lstsq(H[: k + 1, :k], e1, rcond=None)
+        x = x + V[:k].T @ y

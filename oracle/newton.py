@@ -10,7 +10,9 @@ For every load increment i = 1..n (load factor i/n):
     until ||R|| <= tol ||R0||.  The Krylov tolerance is ``eta`` (forcing 0) or
     the Eisenstat-Walker term of ``forcing_term`` starting from ``eta``
     (forcing 1).  ``inertia`` = (m, s) adds a BDF2 time step's inertia to R
-    and -m to the approximate Jacobian's diagonal (oracle.dynamics).
+    and -m to the approximate Jacobian's diagonal (oracle.dynamics).  side 1
+    solves each Newton system by left-preconditioned GMRES (eq. jfnk as
+    printed) instead of right-preconditioned FGMRES.
     predictor 1 starts increment i+1 from u_i + (u_i - u_{i-1})
     (a secant in the load factor; not in the paper) when R there is finite,
     R0 staying that of u_i at the new load.  ls_max < 0: full steps, lam halved (at most
@@ -27,7 +29,7 @@ import numpy as np
 
 from . import precond
 from .jacobian import default_eps
-from .krylov import fgmres
+from .krylov import fgmres, gmres_left
 from .residual import residual
 
 
@@ -45,7 +47,7 @@ def forcing_term(rn, rprev, eta_prev, eta_max, tol, r0):
 
 def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
            maxit_newton=50, maxit_krylov=2000, n_increments=1, ls_max=10, precond_fn=None,
-           log=None, forcing=0, predictor=0, inertia=None, load_scale=1.0):
+           log=None, forcing=0, predictor=0, inertia=None, load_scale=1.0, side=0):
     n, D = disc.n_cells, disc.dim
     if A is None:
         A = precond.assemble(disc, None if inertia is None else inertia[0])
@@ -90,7 +92,10 @@ def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
                     return np.zeros_like(v)
                 return ((residual(disc, uu + eps * vv, load, inertia) - Ru) / eps).ravel()
 
-            du, info = fgmres(J, -R.ravel(), M, m=m, rtol=eta_k, maxit=maxit_krylov)
+            if side == 1:
+                du, info = gmres_left(J, -R.ravel(), M, m=m, rtol=eta_k, maxit=maxit_krylov)
+            else:
+                du, info = fgmres(J, -R.ravel(), M, m=m, rtol=eta_k, maxit=maxit_krylov)
             stats["krylov"] += info["iters"]
             du = du.reshape(n, D)
             lam = 1.0

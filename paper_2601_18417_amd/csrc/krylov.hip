@@ -197,8 +197,18 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
   const int64_t n = (int64_t)c->D * c->nc;
   double* hd = K.h;
   double bnorm, xnorm;
-  if ((s = host_norm(c, n, rhs, &bnorm, st))) return s;
+  // left preconditioning (eq. jfnk as printed): GMRES on M J x = M rhs, stopping
+  // on the preconditioned residual; M must then be one fixed operator
+  const bool left = o->side == 1;
+  if (left && o->learned) return fail(c, HOFV_EINVAL, "the learned correction needs right preconditioning");
+  if (o->side != 0 && o->side != 1) return fail(c, HOFV_EINVAL, "side must be 0 (right) or 1 (left)");
   if ((s = host_norm(c, n, x, &xnorm, st))) return s;
+  if (left) {
+    if ((s = precond_dispatch(c, rhs, K.tmp2, sweeps, 0, st))) return s;
+    if ((s = host_norm(c, n, K.tmp2, &bnorm, st))) return s;
+  } else if ((s = host_norm(c, n, rhs, &bnorm, st))) {
+    return s;
+  }
   stats->iters = 0;
   stats->converged = 0;
   stats->fallbacks = 0;
@@ -216,13 +226,15 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
   int it = 0;
   double beta = 0, beta_cycle = -1.0;
   for (;;) {
-    // V_0 = rhs - J x
+    // V_0 = rhs - J x (left: M (rhs - J x))
+    double* r0 = left ? K.tmp2 : K.V;
     if (xnorm > 0) {
       if ((s = jvp_impl(c, u, Ru, x, K.tmp, 0.0, st))) return s;
-      k_lincomb<<<nblk(n), kB, 0, st>>>(n, 1.0, rhs, -1.0, K.tmp, K.V);
+      k_lincomb<<<nblk(n), kB, 0, st>>>(n, 1.0, rhs, -1.0, K.tmp, r0);
     } else {
-      k_lincomb<<<nblk(n), kB, 0, st>>>(n, 1.0, rhs, 0.0, rhs, K.V);
+      k_lincomb<<<nblk(n), kB, 0, st>>>(n, 1.0, rhs, 0.0, rhs, r0);
     }
+    if (left && (s = precond_dispatch(c, r0, K.V, sweeps, 0, st))) return s;
     if ((s = host_norm(c, n, K.V, &beta, st))) return s;
     if (!std::isfinite(beta)) return fail(c, HOFV_ENAN, "NaN/Inf in the FGMRES residual");
     if (beta <= rtol * bnorm || it >= maxit) break;
@@ -255,11 +267,16 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
       double* vj = K.V + (size_t)j * n;
       double* zj = K.Z + (size_t)j * n;
       double* w = K.V + (size_t)(j + 1) * n;
-      if ((s = precond_dispatch(c, vj, zj, sweeps, learned, st))) return s;
-      // ||z_j||^2 of a learned output (a NaN z_j would only show up later:
-      // its finite-difference product is defined to be zero)
-      if (learned && (s = dots(c, n, 1, zj, n, zj, hd + kZz, 0, st))) return s;
-      if ((s = jvp_impl(c, u, Ru, zj, w, 0.0, st))) return s;
+      if (left) {  // w = M J v_j (z_j holds J v_j)
+        if ((s = jvp_impl(c, u, Ru, vj, zj, 0.0, st))) return s;
+        if ((s = precond_dispatch(c, zj, w, sweeps, 0, st))) return s;
+      } else {  // w = J z_j, z_j = M v_j
+        if ((s = precond_dispatch(c, vj, zj, sweeps, learned, st))) return s;
+        // ||z_j||^2 of a learned output (a NaN z_j would only show up later:
+        // its finite-difference product is defined to be zero)
+        if (learned && (s = dots(c, n, 1, zj, n, zj, hd + kZz, 0, st))) return s;
+        if ((s = jvp_impl(c, u, Ru, zj, w, 0.0, st))) return s;
+      }
       // CGS2
       if ((s = dots(c, n, j + 1, K.V, n, w, hd, 0, st))) return s;
       k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd, -1.0, w);
@@ -319,7 +336,7 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
       y[i] = sum / H[(size_t)i * m + i];
     }
     HOFV_HIP(c, hipMemcpyAsync(hd, y.data(), kdone * sizeof(double), hipMemcpyHostToDevice, st));
-    k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, kdone, K.Z, n, hd, 1.0, x);
+    k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, kdone, left ? K.V : K.Z, n, hd, 1.0, x);
     HOFV_HIP(c, hipGetLastError());
     xnorm = 1.0;
   }

@@ -68,6 +68,50 @@ def test_fgmres_parity_linear_system():
     assert np.linalg.norm(to_host(x) - xe) <= 1e-5 * np.linalg.norm(xe)
 
 
+def test_left_gmres_parity_linear_system():
+    """side = 1 (eq. jfnk as printed): GMRES on M J x = M b with the FP32 sweeps
+    as M; the stopping test is on the preconditioned residual, which the oracle's
+    left GMRES with the FP32-emulated sweeps reproduces."""
+    prob = w.cube_mms(8, 2, perturb=0.2)
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    ud = to_dev(np.zeros((n, 3)))
+    Ru = torch.empty_like(ud)
+    ctx.residual(ud, Ru)
+    b = w.random_state(n, 3, seed=7, scale=1.0)
+    x = torch.zeros_like(ud)
+    st = ctx.fgmres_solve(ud, Ru, to_dev(b), x, rtol=1e-7, max_iters=500, n_sweeps=2, side=1)
+    assert st["converged"] and st["rel_residual"] <= 1e-7
+    J = ojac.jacobian_affine(disc)
+    A = opc.assemble(disc)
+    col = opc.greedy_colours(A)
+    M = lambda v: opc.sgs(A, col, v.reshape(n, 3), 2, dtype=np.float32).astype(float).ravel()
+    xo, info = okr.gmres_left(lambda v: J @ v, b.ravel(), M, m=30, rtol=1e-7, maxit=500)
+    assert info["converged"]
+    xe = np.linalg.solve(J, b.ravel()).reshape(n, 3)
+    assert np.linalg.norm(to_host(x) - xe) <= 1e-5 * np.linalg.norm(xe)
+    assert abs(st["iters"] - info["iters"]) <= 2
+    Mr = M((b.ravel() - J @ to_host(x).ravel()))
+    assert np.linalg.norm(Mr) <= 1.01e-7 * np.linalg.norm(M(b.ravel()))
+    with pytest.raises(_api().HofvError):
+        ctx.fgmres_solve(ud, Ru, to_dev(b), x, side=2)
+    with pytest.raises(_api().HofvError):
+        ctx.fgmres_solve(ud, Ru, to_dev(b), x, side=1, learned=True)
+
+
+def test_newton_left_gmres_matches_oracle():
+    prob = w.cube_mms(6, 2, perturb=0.2)
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    u = torch.zeros((3, n), device=DEV, dtype=torch.float64)
+    st = ctx.newton_solve(u, tol=1e-10, eta=1e-7, side=1)
+    assert st["converged"]
+    uo, _ = onw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-7, side=1)
+    assert np.linalg.norm(to_host(u) - uo) <= 1e-7 * np.linalg.norm(uo)
+
+
 def test_fgmres_nonzero_initial_guess_and_zero_rhs():
     prob = w.square_mms(10, 2)
     ctx = _api().context_for(prob)

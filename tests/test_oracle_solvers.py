@@ -155,6 +155,51 @@ def test_fgmres_stops_on_a_stagnating_cycle():
     assert np.allclose(S @ x, b)
 
 
+def _left_system(n=40, seed=0):
+    rng = np.random.default_rng(seed)
+    A = np.eye(n) * 4 + rng.standard_normal((n, n)) * 0.4
+    d = np.abs(rng.standard_normal(n)) * 10 + 0.5  # a badly scaled diagonal preconditioner
+    b = rng.standard_normal(n)
+    return A, d, b
+
+
+def test_left_gmres_solves_and_stops_on_the_preconditioned_residual():
+    A, d, b = _left_system()
+    M = lambda v: v / d
+    x, info = kr.gmres_left(lambda v: A @ v, b, M, m=20, rtol=1e-10, maxit=400)
+    assert info["converged"]
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-8, atol=1e-9)
+    assert info["rel"] == pytest.approx(np.linalg.norm(M(b - A @ x)) / np.linalg.norm(M(b)), rel=1e-6)
+    # M = A^-1: one iteration
+    Ainv = np.linalg.inv(A)
+    x, info = kr.gmres_left(lambda v: A @ v, b, lambda v: Ainv @ v, m=5, rtol=1e-10, maxit=10)
+    assert info["converged"] and info["iters"] == 1
+
+
+def test_left_gmres_minimises_over_its_krylov_space():
+    """After k < m iterations of one cycle from x = 0, ||M(b - A x)|| is the
+    least-squares minimum over span{M b, (MA) M b, ..., (MA)^{k-1} M b}."""
+    A, d, b = _left_system(seed=1)
+    MA = A / d[:, None]
+    Mb = b / d
+    for k in (3, 7):
+        x, info = kr.gmres_left(lambda v: A @ v, b, lambda v: v / d, m=20, rtol=1e-30, maxit=k)
+        K = np.stack([np.linalg.matrix_power(MA, i) @ Mb for i in range(k)], axis=1)
+        c, *_ = np.linalg.lstsq(MA @ K, Mb, rcond=None)
+        best = np.linalg.norm(Mb - MA @ K @ c) / np.linalg.norm(Mb)
+        assert info["rel"] == pytest.approx(best, rel=1e-6)
+
+
+def test_newton_with_left_gmres_reaches_the_right_preconditioned_state():
+    prob = w.cube_mms(5, 2, perturb=0.2)
+    disc = rs.build(prob)
+    n = disc.n_cells
+    u0, _ = nw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-8, m=60)
+    u1, st = nw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-8, m=60, side=1)
+    assert st["increments"][0]["rel"] <= 1e-10
+    assert np.linalg.norm(u1 - u0) <= 1e-8 * np.linalg.norm(u0)
+
+
 def test_zero_direction_gives_zero_product():
     disc = rs.build(w.square_mms(4, 1))
     v = np.zeros((16, 2))
