@@ -36,6 +36,7 @@ struct NnWork {
   float* dA = nullptr;           // [nc][256]
   float* dg = nullptr;           // [nc][3]
   float* part = nullptr;         // block partials of parameter gradients
+  float* part2 = nullptr;        // row-group sums of those partials [kNnRedGroups][count]
   double* lpart = nullptr;       // block partials of the loss
   double* zaj = nullptr;         // [D][nc] plain preconditioner output
   double* sc = nullptr;          // scalars: [2] rms r, [3] rms z, [4] |e|^2, [5] loss

@@ -445,6 +445,25 @@ __global__ __launch_bounds__(kB) void k_nn_reduce(int64_t count, int64_t nb, int
   grad[i] += scale * s;
 }
 
+// part2[g * count + i] = sum over the rows b of group g (b0 <= b < b1, in order)
+// of part[b * stride + i]; a block takes 64 outputs and one group, its four
+// row lanes interleaved and combined in a fixed order (deterministic)
+constexpr int kNnRedGroups = 128;
+__global__ __launch_bounds__(kB) void k_nn_reduce_rows(int64_t count, int64_t nb, int64_t stride, int64_t per_group,
+                                                       const float* __restrict__ part, float* __restrict__ part2) {
+  __shared__ float red[4][64];
+  const int o = threadIdx.x & 63, r4 = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + o;
+  const int64_t g = blockIdx.y;
+  const int64_t b0 = g * per_group, b1 = b0 + per_group < nb ? b0 + per_group : nb;
+  float s = 0.f;
+  if (i < count)
+    for (int64_t b = b0 + r4; b < b1; b += 4) s += part[b * stride + i];
+  red[r4][o] = s;
+  __syncthreads();
+  if (r4 == 0 && i < count) part2[g * count + i] = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
+}
+
 __global__ __launch_bounds__(kB) void k_nn_sum_d(int nb, const double* __restrict__ part, double* __restrict__ out) {
   __shared__ double red[kB];
   double s = 0.0;
@@ -589,6 +608,7 @@ static hofv_status ensure_ws(hofv_ctx* c, bool train) {
     const int64_t nb4 = (nc * kW + kB - 1) / kB;
     const size_t part = std::max<size_t>((size_t)nbw * kK * kW, (size_t)nb4 * 576);
     if ((s = dev_alloc(c, &w.part, part))) return s;
+    if ((s = dev_alloc(c, &w.part2, (size_t)kNnRedGroups * kK * kW))) return s;
     if ((s = dev_alloc(c, &w.lpart, (size_t)nblk(nc) + 8))) return s;
   }
   return HOFV_OK;
@@ -631,6 +651,17 @@ hofv_status nn_apply(hofv_ctx* c, hofv_nn* m, const double* r, const double* zaj
 
 // gradient of the loss of one pair (r, e), accumulated (scaled) into m->g;
 // the pair's loss is added to *loss_dev.
+// grad[i] += scale * sum_b part[b * stride + i], i < count (count <= kK kW), in
+// two fixed-order stages: row groups in parallel, then the group sums
+static void reduce_grad(int64_t count, int64_t nb, int64_t stride, const float* part, float* part2, float scale,
+                        float* grad, hipStream_t st) {
+  const int64_t per = (nb + kNnRedGroups - 1) / kNnRedGroups;
+  const int64_t groups = (nb + per - 1) / per;
+  k_nn_reduce_rows<<<dim3((unsigned)((count + 63) / 64), (unsigned)groups), kB, 0, st>>>(count, nb, stride, per, part,
+                                                                                         part2);
+  k_nn_reduce<<<nblk(count), kB, 0, st>>>(count, groups, count, part2, scale, grad);
+}
+
 template <int D>
 static hofv_status nn_grad_pair(hofv_ctx* c, hofv_nn* m, const double* r, const double* zaj, const double* e,
                                 float scale, double* loss_dev, hipStream_t st) {
@@ -644,18 +675,17 @@ static hofv_status nn_grad_pair(hofv_ctx* c, hofv_nn* m, const double* r, const 
   // decoder
   const int64_t nb4 = (nc * kW + kB - 1) / kB;
   k_nn_decoder_bwd<<<(unsigned)nb4, kB, 0, st>>>(nc, w.h + (size_t)kNnLayers * nc * kW, m->Wd, w.dg, w.dh, w.part);
-  k_nn_reduce<<<1, kB, 0, st>>>(195, nb4, 195, w.part, scale, m->g + kNnOffWd);
+  reduce_grad(195, nb4, 195, w.part, w.part2, scale, m->g + kNnOffWd, st);
   float* dh = w.dh;
   float* dh2 = w.dh2;
   const unsigned lb = (unsigned)((nc + 63) / 64);
   const int64_t nbw = (nc + kDwCells - 1) / kDwCells;
   for (int l = kNnLayers - 1; l >= 0; --l) {
     k_nn_relu_bwd<<<(unsigned)nb4, kB, 0, st>>>(nc, dh, w.Y + (size_t)l * nc * kW, w.dY, w.part);
-    k_nn_reduce<<<1, kB, 0, st>>>(kW, nb4, kW, w.part, scale, m->g + kNnOffb(l));
+    reduce_grad(kW, nb4, kW, w.part, w.part2, scale, m->g + kNnOffb(l), st);
     TIMED_NN(c, "k_nn_dw", st,
              (k_nn_dw<<<(unsigned)nbw, kB, 0, st>>>(nc, w.X + (size_t)l * nc * kK, w.dY, w.part)));
-    k_nn_reduce<<<nblk((int64_t)kK * kW), kB, 0, st>>>((int64_t)kK * kW, nbw, (int64_t)kK * kW, w.part, scale,
-                                                        m->g + kNnOffW(l));
+    reduce_grad((int64_t)kK * kW, nbw, (int64_t)kK * kW, w.part, w.part2, scale, m->g + kNnOffW(l), st);
     TIMED_NN(c, "k_nn_dx", st,
              (k_nn_dx<<<lb, kB, 0, st>>>(nc, w.dY, m->Wr + (size_t)l * kK * kW, dh, dh2, w.dA)));
     k_nn_agg_t<<<(unsigned)nb4, kB, 0, st>>>(nc, t.g_nbr, t.g_wb, 2 * D, w.dA, dh2);
@@ -663,7 +693,7 @@ static hofv_status nn_grad_pair(hofv_ctx* c, hofv_nn* m, const double* r, const 
   }
   k_nn_encoder_bwd<<<(unsigned)nb4, kB, 0, st>>>(nc, w.x, w.h, dh, w.part);
   // part rows: j < 8 -> dWe[j][c], j = 8 -> dbe[c]; kNnOffWe..kNnOffbe are adjacent
-  k_nn_reduce<<<nblk(576), kB, 0, st>>>(576, nb4, 576, w.part, scale, m->g + kNnOffWe);
+  reduce_grad(576, nb4, 576, w.part, w.part2, scale, m->g + kNnOffWe, st);
   if (hipGetLastError() != hipSuccess) return fail(c, HOFV_EHIP, "MPNN backward launch failed");
   return HOFV_OK;
 }
