@@ -434,23 +434,14 @@ __global__ __launch_bounds__(kB) void k_nn_encoder_bwd(int64_t nc, const unsigne
   }
 }
 
-// grad[off + i] += sum_b part[b * stride + i]  (fixed order: deterministic)
-__global__ __launch_bounds__(kB) void k_nn_reduce(int64_t count, int64_t nb, int64_t stride,
-                                                  const float* __restrict__ part, float scale,
-                                                  float* __restrict__ grad) {
-  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (i >= count) return;
-  float s = 0.f;
-  for (int64_t b = 0; b < nb; ++b) s += part[b * stride + i];
-  grad[i] += scale * s;
-}
-
-// part2[g * count + i] = sum over the rows b of group g (b0 <= b < b1, in order)
-// of part[b * stride + i]; a block takes 64 outputs and one group, its four
-// row lanes interleaved and combined in a fixed order (deterministic)
+// s = sum over the rows b of group g (b0 <= b < b1, in order) of part[b * stride + i],
+// stored as part2[g * count + i], or added as grad[i] += scale * s when grad is
+// given; a block takes 64 outputs and one group, its four row lanes
+// interleaved and combined in a fixed order (deterministic)
 constexpr int kNnRedGroups = 128;
 __global__ __launch_bounds__(kB) void k_nn_reduce_rows(int64_t count, int64_t nb, int64_t stride, int64_t per_group,
-                                                       const float* __restrict__ part, float* __restrict__ part2) {
+                                                       const float* __restrict__ part, float* __restrict__ part2,
+                                                       float scale, float* __restrict__ grad) {
   __shared__ float red[4][64];
   const int o = threadIdx.x & 63, r4 = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + o;
@@ -461,7 +452,11 @@ __global__ __launch_bounds__(kB) void k_nn_reduce_rows(int64_t count, int64_t nb
     for (int64_t b = b0 + r4; b < b1; b += 4) s += part[b * stride + i];
   red[r4][o] = s;
   __syncthreads();
-  if (r4 == 0 && i < count) part2[g * count + i] = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
+  if (r4 == 0 && i < count) {
+    const float t = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
+    if (grad) grad[i] += scale * t;
+    else part2[g * count + i] = t;
+  }
 }
 
 __global__ __launch_bounds__(kB) void k_nn_sum_d(int nb, const double* __restrict__ part, double* __restrict__ out) {
@@ -657,9 +652,9 @@ static void reduce_grad(int64_t count, int64_t nb, int64_t stride, const float* 
                         float* grad, hipStream_t st) {
   const int64_t per = (nb + kNnRedGroups - 1) / kNnRedGroups;
   const int64_t groups = (nb + per - 1) / per;
-  k_nn_reduce_rows<<<dim3((unsigned)((count + 63) / 64), (unsigned)groups), kB, 0, st>>>(count, nb, stride, per, part,
-                                                                                         part2);
-  k_nn_reduce<<<nblk(count), kB, 0, st>>>(count, groups, count, part2, scale, grad);
+  const unsigned bx = (unsigned)((count + 63) / 64);
+  k_nn_reduce_rows<<<dim3(bx, (unsigned)groups), kB, 0, st>>>(count, nb, stride, per, part, part2, 0.f, nullptr);
+  k_nn_reduce_rows<<<dim3(bx, 1), kB, 0, st>>>(count, groups, count, groups, part2, nullptr, scale, grad);
 }
 
 template <int D>
