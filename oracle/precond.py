@@ -46,6 +46,13 @@ def assemble(disc_full, mass=None):
     np.add.at(diag, d.f_own, -a)
     np.add.at(diag, d.f_nei, -a)
     np.add.at(diag, d.d_own, -ab)
+    if d.s_own is not None:
+        # symmetry faces: the paper's term a_b (R_b - I) u_P = -2 a_b n n^T u_P acts
+        # on the normal component only; one scalar matrix for every component
+        # takes its isotropic average, -(2/3) a_b on the diagonal
+        dPs = d.s_x - d.cen[d.s_own]
+        a_s = d.kbar * d.s_area / np.abs(np.sum(dPs * d.s_n, axis=1))
+        np.add.at(diag, d.s_own, -(2.0 / 3.0) * a_s)
     if mass is not None:
         diag = diag - mass
     A = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()

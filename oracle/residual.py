@@ -26,6 +26,12 @@ R(u) = 0 is static equilibrium (Sec. 4.1).
   + 1/6 d^3 ::: grad grad grad u from the cell stencil (eq. alphaJump, App. B).
 * Traction faces: Gamma_b sum_q alpha_q T_{b,q} (the weights alpha_q are taken to
   apply, as in the other surface terms; the printed equation omits them).
+* Symmetry faces (Sec. 3.5): the stencil is the ceil(|S|/2) cells nearest to the
+  face centre plus their mirror images through the face plane; the gradient is
+  sum_N c_N (x) u_N + sum_N c'_N (x) (R_b u_N), R_b = I - 2 n n, with c and c'
+  from one reconstruction over both sets of positions; the face term is
+  Gamma n . sum_q alpha_q sigma_q as on displacement faces, with no
+  stabilisation term.
 * Loads (u_b, T, f_b) are multiplied by ``load`` for load increments.
 """
 from __future__ import annotations
@@ -34,7 +40,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from workloads.fields import DISP, TRAC
+from workloads.fields import DISP, SYMM, TRAC
 
 from . import geometry as geo
 from .lsq import reconstruction, row_index
@@ -82,6 +88,16 @@ class Discretisation:
     b_trac: np.ndarray    # (n_c, D)
     active: np.ndarray    # (n_c,) bool: cells whose R is complete
     max_cond: float = 0.0
+    # symmetry faces: half stencil (n_s, ceil(S/2)), coefficients of the cells
+    # and of their mirror images (n_s, Nq, D, ceil(S/2)); None when there are none
+    s_own: np.ndarray | None = None
+    s_n: np.ndarray | None = None
+    s_area: np.ndarray | None = None
+    s_x: np.ndarray | None = None
+    s_qw: np.ndarray | None = None
+    s_st: np.ndarray | None = None
+    s_C: np.ndarray | None = None
+    s_Cg: np.ndarray | None = None
 
     @property
     def kbar(self):
@@ -100,6 +116,22 @@ def _face_coefficients(xq, st, cen, p, k, ghost_weight=None):
     C = A[:, grad_rows, :S].reshape(nf, nq, D, S)
     Cg = A[:, grad_rows, S].reshape(nf, nq, D) if ghost_weight is not None else None
     return C, Cg, cond.max(initial=0.0)
+
+
+def _symmetry_coefficients(xq, st, cen, xf, nrm, p, k):
+    """Gradient rows at symmetry-face q-points over the half stencil (cells) and
+    its mirror images through the face plane: two (nf, Nq, D, S_half) arrays."""
+    nf, nq, D = xq.shape
+    Sh = st.shape[1]
+    Xp = cen[st]
+    dist = np.einsum("fsd,fd->fs", Xp - xf[:, None, :], nrm)
+    Xg = Xp - 2.0 * dist[..., None] * nrm[:, None, :]
+    Xs = np.repeat(np.concatenate([Xp, Xg], axis=1), nq, axis=0)
+    A, cond = reconstruction(xq.reshape(nf * nq, D), Xs, p, k)
+    rows = row_index(D, p)
+    grad_rows = [rows[tuple(1 if d == i else 0 for d in range(D))] for i in range(D)]
+    C = A[:, grad_rows, :].reshape(nf, nq, D, 2 * Sh)
+    return C[..., :Sh], C[..., Sh:], cond.max(initial=0.0)
 
 
 def _cell_coefficients(cells, st, cen, p, k):
@@ -156,6 +188,7 @@ def build(problem, active=None) -> Discretisation:
     bidx = np.nonzero(bnd)[0]
     disp = bidx[btype == DISP]
     trac = bidx[btype == TRAC]
+    sym = bidx[btype == SYMM]
     q = problem.stencil_quantum
     k = problem.k_weight
 
@@ -166,6 +199,12 @@ def build(problem, active=None) -> Discretisation:
     d_C, d_Cg, c2 = _face_coefficients(fg.qpts[disp], d_st, cen, p, k, problem.ghost_weight)
     if d_Cg is None:
         d_Cg = np.zeros((0, fg.qpts.shape[1], D))
+    sym_kw, c4 = {}, 0.0
+    if sym.size:
+        s_st = nearest(fg.centre[sym], cen, (S + 1) // 2, q)
+        s_C, s_Cg, c4 = _symmetry_coefficients(fg.qpts[sym], s_st, cen, fg.centre[sym], fg.normal[sym], p, k)
+        sym_kw = dict(s_own=faces.owner[sym], s_n=fg.normal[sym], s_area=fg.area[sym], s_x=fg.centre[sym],
+                      s_qw=fg.qw[sym], s_st=s_st, s_C=s_C, s_Cg=s_Cg)
 
     # cells whose u* is needed: both sides of internal faces, owners of disp faces
     need = np.zeros(n_c, bool)
@@ -211,7 +250,7 @@ def build(problem, active=None) -> Discretisation:
         d_own=faces.owner[disp], d_n=fg.normal[disp], d_area=fg.area[disp], d_x=fg.centre[disp],
         d_qw=fg.qw[disp], d_st=d_st, d_C=d_C, d_Cg=d_Cg, d_ubq=d_ubq, d_ubc=d_ubc,
         c_st=c_st, c_D1=c_D1, c_D2=c_D2, c_D3=c_D3, b_body=b_body, b_trac=b_trac, active=act,
-        max_cond=float(max(c1, c2, c3)))
+        max_cond=float(max(c1, c2, c3, c4)), **sym_kw)
 
 
 # ----------------------------------------------------------------------------- stresses
@@ -306,6 +345,17 @@ def face_fluxes(disc, u, load=1.0):
     return Ff, Fd
 
 
+def symmetry_fluxes(disc, u):
+    """Face terms of the symmetry faces (owner side), (n_s, D)."""
+    if disc.s_own is None:
+        return np.zeros((0, disc.dim))
+    ug = u[disc.s_st]
+    n = disc.s_n
+    Ru = ug - 2.0 * np.einsum("fsd,fd->fs", ug, n)[..., None] * n[:, None, :]
+    G = np.einsum("fqis,fsj->fqij", disc.s_C, ug) + np.einsum("fqis,fsj->fqij", disc.s_Cg, Ru)
+    return face_term(disc, G, n, disc.s_area, disc.s_qw)
+
+
 def residual(disc, u, load=1.0, inertia=None):
     """R(u), (n_c, D).  u is (n_c, D) float64 or complex128.
 
@@ -318,6 +368,8 @@ def residual(disc, u, load=1.0, inertia=None):
     np.add.at(R, disc.f_own, Ff)
     np.add.at(R, disc.f_nei, -Ff)
     np.add.at(R, disc.d_own, Fd)
+    if disc.s_own is not None:
+        np.add.at(R, disc.s_own, symmetry_fluxes(disc, u))
     R += load * (disc.b_body + disc.b_trac)
     if inertia is not None:
         m, s = inertia

@@ -54,6 +54,33 @@ def test_traction_faces_with_exact_traction(dim, shape):
     assert _rel_zero(disc, prob.loads.exact.value(disc.cen)) < 1e-12
 
 
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_symmetric_polynomial_fields_give_zero_residual_with_symmetry_faces(p):
+    """Faces on x = 0 are symmetry planes (Sec. 3.5: half stencil plus its mirror
+    image, ghosts carrying R_b u).  A polynomial of degree <= p that is
+    symmetric about x = 0 (u_x odd in x, u_y and u_z even) is its own mirror
+    image, so the reconstruction reproduces it and R = 0."""
+    mesh = w.box_mesh((5, 5, 5), perturb=0.2, seed=3, mode="tensor")
+    prob = w.poly_patch(mesh, p, p, seed=p, symmetric=True)
+    disc = rs.build(prob)
+    assert disc.s_own.size == 25 and disc.s_st.shape[1] == (prob.stencil_size + 1) // 2
+    assert _rel_zero(disc, prob.loads.exact.value(disc.cen)) < 1e-12
+
+
+def test_symmetry_faces_see_an_asymmetric_field():
+    """The same faces with a field that is not symmetric about x = 0: the mirror
+    images contradict it and the cells on the plane keep a residual."""
+    mesh = w.box_mesh((5, 5, 5), perturb=0.2, seed=3, mode="tensor")
+    prob = w.poly_patch(mesh, 2, 2, seed=2)
+    fld = prob.loads.exact
+    prob.loads = w.fields.mms_loads(fld, prob.mu, prob.lam, symmetry_faces=lambda xc, n: np.abs(xc[:, 0]) < 1e-9)
+    disc = rs.build(prob)
+    u = fld.value(disc.cen)
+    R = rs.residual(disc, u)
+    on_plane = np.unique(disc.s_own)
+    assert np.abs(R[on_plane]).max() > 1e-3 * np.abs(rs.symmetry_fluxes(disc, u)).max()
+
+
 def _nh_problem(shape=(5, 4, 4), p=2, pert=0.15, loads=None):
     mesh = w.box_mesh(shape, perturb=pert, seed=5, mode="tensor")
     zero = lambda x: np.zeros_like(x)

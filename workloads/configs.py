@@ -19,7 +19,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .fields import (Loads, cantilever_loads, lame_from_young, mms_2d_unit, mms_3d_trig,
+from .fields import (Loads, cantilever_loads, lame_from_young, mms_2d_unit, mms_3d_trig, symmetric_poly_field,
                      mms_loads, random_poly_field)
 from .meshes import Mesh, box_mesh
 
@@ -114,13 +114,23 @@ def vibrating_column(shape=(50, 5, 5), p: int = 1, E: float = 15.293e6, nu: floa
 
 
 def poly_patch(mesh: Mesh, p: int, degree: int, seed: int = 0, E: float = 1.0, nu: float = 0.3,
-               n_plus=None, n_gauss=None, scale: float = 1.0, traction_faces=None) -> Problem:
+               n_plus=None, n_gauss=None, scale: float = 1.0, traction_faces=None,
+               symmetric: bool = False) -> Problem:
+    """Polynomial manufactured problem; symmetric=True takes a field symmetric
+    about x = 0 and makes the mesh's x = 0 faces symmetry planes."""
     mu, lam = lame_from_young(E, nu)
-    fld = random_poly_field(mesh.dim, degree, seed, scale)
+    if symmetric:
+        fld = symmetric_poly_field(mesh.dim, degree, seed, scale)
+        tol = 1e-9 * float(np.max(mesh.lengths))
+        sym = lambda xc, n: np.abs(xc[:, 0] - mesh.origin[0]) < tol
+        assert abs(mesh.origin[0]) < tol, "the symmetry plane is x = 0"
+    else:
+        fld = random_poly_field(mesh.dim, degree, seed, scale)
+        sym = None
     return Problem(f"poly{degree}_p{p}", mesh, p,
                    PAPER_N_PLUS[mesh.dim][p] if n_plus is None else n_plus,
                    n_gauss or default_gauss(p), LINEAR_ELASTIC, mu, lam,
-                   mms_loads(fld, mu, lam, traction_faces), stencil_quantum=quantum_for(mesh))
+                   mms_loads(fld, mu, lam, traction_faces, sym), stencil_quantum=quantum_for(mesh))
 
 
 def random_state(n_cells: int, dim: int, seed: int, scale: float = 1e-3) -> np.ndarray:

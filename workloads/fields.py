@@ -98,6 +98,17 @@ class PolyField(Field):
         return out
 
 
+def symmetric_poly_field(dim: int, degree: int, seed: int, scale: float = 1.0) -> PolyField:
+    """A random polynomial field symmetric about the plane x = 0: u_x odd in x,
+    the other components even in x (its mirror image is itself)."""
+    f = random_poly_field(dim, degree, seed, scale)
+    odd = f.expo[:, 0] % 2 == 1
+    coef = f.coef.copy()
+    coef[~odd, 0] = 0.0
+    coef[odd, 1:] = 0.0
+    return PolyField(dim, f.expo, coef)
+
+
 def random_poly_field(dim: int, degree: int, seed: int, scale: float = 1.0) -> PolyField:
     """All monomials of total degree <= degree, seeded N(0,1)*scale coefficients."""
     expo = [e for e in np.ndindex(*([degree + 1] * dim)) if sum(e) <= degree]
@@ -164,7 +175,8 @@ def mms_3d_trig(a=(2e-6, 4e-6, 6e-6)) -> TrigField:
 class Loads:
     """Everything a problem prescribes, as point functions.
 
-    bc_type(xc, n) -> int array (0 = displacement, 1 = traction) per boundary face.
+    bc_type(xc, n) -> int array (0 = displacement, 1 = traction, 2 = symmetry plane)
+    per boundary face.
     u_b(x) -> prescribed displacement; traction(x, n) -> prescribed traction;
     body(x) -> body force.  All take/return (m, dim) arrays.
     """
@@ -177,16 +189,20 @@ class Loads:
     meta: dict = field(default_factory=dict)
 
 
-DISP, TRAC = 0, 1
+DISP, TRAC, SYMM = 0, 1, 2
 
 
-def mms_loads(fld: Field, mu: float, lam: float, traction_faces=None) -> Loads:
+def mms_loads(fld: Field, mu: float, lam: float, traction_faces=None, symmetry_faces=None) -> Loads:
     """Manufactured problem: displacement BC everywhere except faces selected by
-    ``traction_faces(xc, n) -> bool`` which get the exact traction."""
+    ``traction_faces(xc, n) -> bool`` which get the exact traction, and faces
+    selected by ``symmetry_faces`` (symmetry planes; the field must be symmetric
+    about them)."""
     def bc_type(xc, n):
         t = np.full(xc.shape[0], DISP, np.int32)
         if traction_faces is not None:
             t[traction_faces(xc, n)] = TRAC
+        if symmetry_faces is not None:
+            t[symmetry_faces(xc, n)] = SYMM
         return t
     return Loads(fld.dim, bc_type, fld.value,
                  lambda x, n: traction_le(fld, mu, lam, x, n),
