@@ -333,10 +333,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="cube", choices=["cube", "cantilever", "square", "column"],
+    ap.add_argument("--workload", default="cube", choices=["cube", "cantilever", "square", "column", "symmetric"],
                     help="cube: 3D LE manufactured solution on a perturbed n^3 mesh (default); cantilever: "
                          "3D neo-Hookean 200x20x20 beam, 10 load increments; square: 2D 32x32 LE, p=2; "
-                         "column: the vibrating neo-Hookean column, BDF2 time steps")
+                         "column: the vibrating neo-Hookean column, BDF2 time steps; symmetric: a polynomial "
+                         "field symmetric about x = 0 on a tensor-perturbed n^3 box whose x = 0 faces are "
+                         "symmetry planes")
     ap.add_argument("--column-cells", default="50x5x5", help="cells of the column (length x width x depth)")
     ap.add_argument("--time-steps", type=int, default=100, help="BDF2 steps of the column (dt = 1 ms)")
     ap.add_argument("--n", type=int, default=64, help="cells per axis")
@@ -427,6 +429,9 @@ def main():
         prob = w.cantilever(p=args.p)
     elif args.workload == "column":
         prob = w.vibrating_column(tuple(int(x) for x in args.column_cells.split("x")), p=args.p)
+    elif args.workload == "symmetric":
+        prob = w.poly_patch(w.box_mesh((args.n,) * 3, perturb=0.2, seed=0, mode="tensor"), args.p, args.p, seed=1,
+                            symmetric=True)
     else:
         prob = w.square_mms(32, args.p)
     nc, D = prob.mesh.n_cells, prob.dim
@@ -584,7 +589,7 @@ def main():
     cpu = None
     if args.cpu_sample > 0:
         label = {"cube": f"{args.n}^3 p={args.p}", "cantilever": f"cantilever p={args.p}",
-                 "square": f"32^2 p={args.p}"}[args.workload]
+                 "square": f"32^2 p={args.p}"}.get(args.workload, f"{args.workload} p={args.p}")
         cpu = cpu_baseline(prob, min(args.cpu_sample, nc // 2), u.cpu().numpy().T.copy(),
                            v.cpu().numpy().T.copy(), ctx, torch, label)
         log(f"cpu {cpu}")
@@ -609,7 +614,10 @@ def main():
                                 "square": f"2D plane-strain LE MMS, 32x32 quads, p={args.p}, "
                                           f"|S|={ctx.report['stencil_size']}",
                                 "column": f"3D neo-Hookean vibrating column 6 x 0.2 x 0.2 m, {args.column_cells} hex, "
-                                          f"p={args.p}, |S|={ctx.report['stencil_size']}, BDF2 dt = 1 ms"
+                                          f"p={args.p}, |S|={ctx.report['stencil_size']}, BDF2 dt = 1 ms",
+                                "symmetric": f"3D LE polynomial (degree p) symmetric about x = 0, {args.n}^3 hex "
+                                             f"tensor-perturbed +-20%, symmetry planes on x = 0, p={args.p}, "
+                                             f"|S|={ctx.report['stencil_size']}"
                                 }[args.workload],
                    "n_cells": nc, "global_batch": nc, "parallelism": "single GPU"},
         "residual_mcells_s": nc / (ms_res * 1e-3) / 1e6,

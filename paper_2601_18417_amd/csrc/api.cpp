@@ -167,7 +167,7 @@ hofv_status hofv_set_bc(hofv_ctx* c, const int32_t* type, const double* u_b_q, c
   c->btype.assign(nb, HOFV_BC_DISPLACEMENT);
   if (type) {
     for (size_t b = 0; b < nb; ++b) {
-      if (type[b] != HOFV_BC_DISPLACEMENT && type[b] != HOFV_BC_TRACTION)
+      if (type[b] != HOFV_BC_DISPLACEMENT && type[b] != HOFV_BC_TRACTION && type[b] != HOFV_BC_SYMMETRY)
         return fail(c, HOFV_EINVAL, "unknown boundary condition type");
       c->btype[b] = type[b];
     }

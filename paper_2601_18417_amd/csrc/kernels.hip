@@ -384,12 +384,39 @@ __global__ __launch_bounds__(kBlockItems) void k_face_q(int64_t nf, int64_t nfi,
   for (int j = 0; j < D; ++j) F[(int64_t)j * nf + f] = t[j];
 }
 
+// symmetry faces (linear elastic): F_s[j] = sum_N sum_k T[N][j][k] u_N,k over the
+// face's half stencil, u from the gather copy; one thread per face
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_face_sym(int64_t nfs, int Sh, const int32_t* __restrict__ st,
+                                                     const double* __restrict__ T, const double* __restrict__ ug,
+                                                     double* __restrict__ Fs) {
+  constexpr int W = D == 3 ? 4 : 2;
+  const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (f >= nfs) return;
+  double t[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) t[j] = 0.0;
+  for (int N = 0; N < Sh; ++N) {
+    const int64_t cell = st[(int64_t)N * nfs + f];
+    double u[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) u[k] = ug[W * cell + k];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int k = 0; k < D; ++k) t[j] += T[(((int64_t)N * D + j) * D + k) * nfs + f] * u[k];
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j) Fs[(int64_t)j * nfs + f] = t[j];
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, const int32_t* __restrict__ cf,
                                                       const double* __restrict__ F, const double* __restrict__ src,
                                                       double load, const double* __restrict__ Ru,
                                                       const double* __restrict__ eps, const double* __restrict__ ug,
                                                       const double* __restrict__ dm, const double* __restrict__ ds,
+                                                      const double* __restrict__ Fs, int64_t nfs,
                                                       double* __restrict__ R) {
   constexpr int NS = 2 * D;
   constexpr int W = D == 3 ? 4 : 2;
@@ -405,7 +432,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, con
     for (int s = 0; s < NS; ++s) {
       const int32_t k = code[s];
       if (k == kNoFace) continue;
-      if (k >= 0) acc += F[(int64_t)c * nf + k];
+      if (k >= nf) acc += Fs[(int64_t)c * nfs + (k - nf)];  // symmetry face
+      else if (k >= 0) acc += F[(int64_t)c * nf + k];
       else acc -= F[(int64_t)c * nf + ~k];
     }
     // BDF2 inertia at the centroid: s_P - m_P u_P (u from the gather copy)
@@ -736,8 +764,11 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
 #undef FACEQ
     }
   }
+  if (t.sym_nf > 0)
+    k_face_sym<D><<<blocks_for(t.sym_nf), kBlock, 0, st>>>(t.sym_nf, t.sym_S, t.sym_st, t.sym_T, u, t.sym_flux);
   TIMED("k_cell_sum", (k_cell_sum<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, nf, t.c_faces, t.flux, t.c_src, c->load,
-                                                                          Ru, eps, u, t.dyn_m, t.dyn_s, R)));
+                                                                          Ru, eps, u, t.dyn_m, t.dyn_s, t.sym_flux,
+                                                                          t.sym_nf, R)));
   HOFV_HIP(c, hipGetLastError());
   return HOFV_OK;
 }

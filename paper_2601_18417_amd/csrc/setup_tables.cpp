@@ -41,11 +41,13 @@ hofv_status build_tables(hofv_ctx* c) {
   std::vector<int64_t> kf;
   kf.reserve(c->faces.size());
   for (int64_t f = 0; f < c->n_internal; ++f) kf.push_back(f);
-  std::vector<int64_t> trac;
+  std::vector<int64_t> trac, symb;
   for (size_t b = 0; b < c->bface.size(); ++b) {
     if (c->btype[b] == HOFV_BC_DISPLACEMENT) kf.push_back(c->bface[b]);
+    else if (c->btype[b] == HOFV_BC_SYMMETRY) symb.push_back((int64_t)b);
     else trac.push_back((int64_t)b);
   }
+  if (!symb.empty() && nh) return fail(c, HOFV_EINVAL, "symmetry faces need the linear-elastic law");
   auto curve = [&](int64_t begin, int64_t end) {
     std::vector<double> x((size_t)(end - begin) * D);
     for (int64_t i = begin; i < end; ++i)
@@ -173,6 +175,78 @@ hofv_status build_tables(hofv_ctx* c) {
   for (int64_t i = nfi; i < nf; ++i)
     for (int j = 0; j < D; ++j) src[(size_t)j * nc + fown[i]] += fsrc[i * D + j];
 
+  // symmetry faces (Sec. 3.5): the ceil(S/2) cells nearest the face centre and
+  // their mirror images through the face plane; the images carry R u, R = I - 2 n n.
+  // For the linear law the face term is linear in each u_N: folded over the
+  // quadrature points into T[N][j][k], the traction t_j per unit u_N,k.
+  const int Sh = (S + 1) / 2;
+  const int64_t nfs = (int64_t)symb.size();
+  std::vector<int32_t> sst((size_t)nfs * Sh), sst_t((size_t)Sh * nfs);
+  std::vector<double> sT((size_t)Sh * D * D * nfs, 0.0), saj(nfs, 0.0);
+  std::vector<int32_t> sown(nfs), sslot(nfs);
+  if (nfs) {
+    std::vector<double> spts((size_t)nfs * D);
+    for (int64_t i = 0; i < nfs; ++i)
+      for (int d = 0; d < D; ++d) spts[i * D + d] = c->f_centre[(size_t)c->bface[symb[i]] * D + d];
+    nearest_cells(c->cen, D, nc, spts.data(), nfs, Sh, c->prm.stencil_quantum, sst.data());
+  }
+#pragma omp parallel for schedule(dynamic, 16) reduction(max : max_cond) reduction(|| : singular)
+  for (int64_t i = 0; i < nfs; ++i) {
+    const int64_t f = c->bface[symb[i]];
+    const hofv_ctx::Face& F = c->faces[f];
+    sown[i] = (int32_t)F.own;
+    sslot[i] = F.sown;
+    const double* n = &c->f_normal[(size_t)f * D];
+    const double* xf = &c->f_centre[(size_t)f * D];
+    const double A = c->f_area[f];
+    double X[512 * 3];
+    for (int k = 0; k < Sh; ++k) {
+      const double* x = &c->cen[(size_t)sst[i * Sh + k] * D];
+      double dn = 0;
+      for (int d = 0; d < D; ++d) dn += (x[d] - xf[d]) * n[d];
+      for (int d = 0; d < D; ++d) {
+        X[k * D + d] = x[d];
+        X[(Sh + k) * D + d] = x[d] - 2.0 * dn * n[d];
+      }
+    }
+    double R[3][3];
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b) R[a][b] = (a == b ? 1.0 : 0.0) - 2.0 * n[a] * n[b];
+    const double targets[3] = {0, 1, 2};
+    double out[3 * 512];
+    for (int q = 0; q < nq; ++q) {
+      double cond, h;
+      const bool ok = ls_functionals(D, p, kshape, &c->f_qp[((size_t)f * nq + q) * D], X, 2 * Sh, 0.0,
+                                     kTargetGradient, D, targets, out, &cond, &h);
+      if (!ok) singular = true;
+      max_cond = std::max(max_cond, cond);
+      const double wq = c->f_qw[(size_t)f * nq + q] * A;
+      const int m = 2 * Sh;
+      for (int N = 0; N < Sh; ++N)
+        for (int kc = 0; kc < D; ++kc) {
+          // gradient G[a][j] produced by a unit u_N,kc: its own coefficient and its image's
+          double G[3][3];
+          for (int a = 0; a < D; ++a)
+            for (int j = 0; j < D; ++j)
+              G[a][j] = out[a * m + N] * (j == kc ? 1.0 : 0.0) + out[a * m + Sh + N] * R[j][kc];
+          double tr = 0;
+          for (int d = 0; d < D; ++d) tr += G[d][d];
+          for (int j = 0; j < D; ++j) {
+            double t = 0;
+            for (int a = 0; a < D; ++a) t += n[a] * (mu * (G[a][j] + G[j][a]) + (a == j ? lam * tr : 0.0));
+            sT[(((size_t)N * D + j) * D + kc) * nfs + i] += wq * t;
+          }
+        }
+    }
+    const double* xP = &c->cen[(size_t)F.own * D];
+    double dn = 0;
+    for (int d = 0; d < D; ++d) dn += (xf[d] - xP[d]) * n[d];
+    saj[i] = kbar * A / std::fabs(dn);
+  }
+  if (singular) return fail(c, HOFV_ESINGULAR, "rank-deficient least-squares stencil at a symmetry face");
+  for (int64_t i = 0; i < nfs; ++i)
+    for (int N = 0; N < Sh; ++N) sst_t[(size_t)N * nfs + i] = sst[i * Sh + N];
+
   // cell extrapolation rows and face slot codes
   std::vector<double> cext((size_t)S * NS * nc, 0.0);
   std::vector<int32_t> cfaces((size_t)NS * nc, kNoFace);
@@ -180,6 +254,7 @@ hofv_status build_tables(hofv_ctx* c) {
     cfaces[(size_t)(fslots[i] & 0xff) * nc + fown[i]] = (int32_t)i;
     if (i < nfi) cfaces[(size_t)(fslots[i] >> 8) * nc + fnei[i]] = ~(int32_t)i;
   }
+  for (int64_t i = 0; i < nfs; ++i) cfaces[(size_t)sslot[i] * nc + sown[i]] = (int32_t)(nf + i);
 #pragma omp parallel for schedule(dynamic, 64) reduction(max : max_cond) reduction(|| : singular)
   for (int64_t P = 0; P < nc; ++P) {
     double X[256 * 3];
@@ -189,7 +264,7 @@ hofv_status build_tables(hofv_ctx* c) {
     int slots[6], nt = 0;
     for (int s = 0; s < NS; ++s) {
       int32_t code = cfaces[(size_t)s * nc + P];
-      if (code == kNoFace) continue;
+      if (code == kNoFace || code >= nf) continue;  // traction and symmetry faces need no u*
       int64_t i = code >= 0 ? code : ~code;
       int64_t f = kf[i];
       for (int d = 0; d < D; ++d) dvec[nt * D + d] = c->f_centre[(size_t)f * D + d] - c->cen[(size_t)P * D + d];
@@ -244,6 +319,10 @@ hofv_status build_tables(hofv_ctx* c) {
       nbr[(size_t)(fslots[i] >> 8) * nc + N] = P;
     }
   }
+  // symmetry faces: the term a_b (R_b - I) u_P = -2 a_b n n^T u_P acts on the
+  // normal component only; one scalar matrix for every component takes its
+  // isotropic average, -(2/3) a_b on the diagonal
+  for (int64_t i = 0; i < nfs; ++i) diag[sown[i]] -= (2.0 / 3.0) * saj[i];
   std::vector<int32_t> colour(nc, -1);
   int ncol = 0;
   for (int64_t P = 0; P < nc; ++P) {
@@ -459,6 +538,13 @@ hofv_status build_tables(hofv_ctx* c) {
   UP(t.g_wf, gwf);
   UP(t.g_wb, gwb);
   UP(t.g_bflag, gbf);
+  t.sym_nf = nfs;
+  t.sym_S = Sh;
+  if (nfs) {
+    UP(t.sym_st, sst_t);
+    UP(t.sym_T, sT);
+    if ((st = dev_alloc(c, &t.sym_flux, (size_t)D * nfs))) return st;
+  }
 #undef UP
   if ((st = dev_alloc(c, &t.ustar, (size_t)NS * D * nc))) return st;
   if ((st = dev_alloc(c, &t.flux, (size_t)D * nf))) return st;

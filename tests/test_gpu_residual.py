@@ -52,6 +52,15 @@ CASES = {
     "box_11x7x6_p3": lambda: w.cube_mms((11, 7, 6), 3, perturb=0.2, seed=5, lengths=(1.0, 0.6, 0.5)),
     "cube7_p2_traction": lambda: w.poly_patch(w.box_mesh((7, 7, 7), perturb=0.2, seed=8), 2, 3, seed=3,
                                               traction_faces=lambda xc, n: xc[:, 2] > 1 - 1e-9),
+    # symmetry planes on x = 0 with fields symmetric about them
+    "square8_p2_symmetry": lambda: w.poly_patch(w.box_mesh((8, 7), perturb=0.15, seed=4, mode="tensor"), 2, 2,
+                                                seed=6, symmetric=True),
+    "box_p1_symmetry": lambda: w.poly_patch(w.box_mesh((6, 5, 5), perturb=0.2, seed=4, mode="tensor"), 1, 1,
+                                            seed=5, symmetric=True),
+    "box_p2_symmetry": lambda: w.poly_patch(w.box_mesh((6, 5, 5), perturb=0.2, seed=4, mode="tensor"), 2, 2,
+                                            seed=6, symmetric=True),
+    "box_p3_symmetry": lambda: w.poly_patch(w.box_mesh((7, 6, 6), perturb=0.2, seed=4, mode="tensor"), 3, 3,
+                                            seed=7, symmetric=True),
 }
 
 
@@ -81,7 +90,7 @@ def test_residual_parity(name, fold):
         assert np.all(np.abs(to_host(R) - Ro) <= bound), name
 
 
-@pytest.mark.parametrize("name", ["square32_p2", "cube8_p2_pert", "cube9_p3_pert"])
+@pytest.mark.parametrize("name", ["square32_p2", "cube8_p2_pert", "cube9_p3_pert", "box_p3_symmetry"])
 def test_jvp_parity(name):
     prob = CASES[name]()
     disc = ores.build(prob)
@@ -158,3 +167,10 @@ def test_neo_hookean_residual_and_jvp_parity():
     torch.cuda.synchronize()
     Jo = ojac.jvp(disc, u, v, Ro, eps, load=0.4)
     assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
+
+
+def test_symmetry_faces_need_the_linear_law():
+    prob = w.poly_patch(w.box_mesh((4, 4, 4), mode="tensor"), 1, 1, seed=1, symmetric=True)
+    prob.material = w.NEO_HOOKEAN
+    with pytest.raises(_api().HofvError):
+        _api().context_for(prob)

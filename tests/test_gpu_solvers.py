@@ -29,7 +29,9 @@ def to_host(t):
 
 @pytest.mark.parametrize("prob_fn", [lambda: w.square_mms(16, 2, perturb=0.2),
                                      lambda: w.cube_mms(9, 2, perturb=0.2),
-                                     lambda: w.cantilever(shape=(16, 4, 4), p=1, n_plus=20)])
+                                     lambda: w.cantilever(shape=(16, 4, 4), p=1, n_plus=20),
+                                     lambda: w.poly_patch(w.box_mesh((8, 6, 6), perturb=0.2, seed=4, mode="tensor"),
+                                                          2, 2, seed=6, symmetric=True)])
 @pytest.mark.parametrize("sweeps", [1, 3])
 def test_precond_parity(prob_fn, sweeps):
     prob = prob_fn()
@@ -110,6 +112,23 @@ def test_newton_left_gmres_matches_oracle():
     assert st["converged"]
     uo, _ = onw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-7, side=1)
     assert np.linalg.norm(to_host(u) - uo) <= 1e-7 * np.linalg.norm(uo)
+
+
+def test_newton_with_symmetry_faces_matches_oracle():
+    """A symmetric quadratic field on a box whose x = 0 faces are symmetry planes
+    (p = 2, exact for it): Newton on the GPU and in the oracle reach the same
+    state, which is the field itself."""
+    prob = w.poly_patch(w.box_mesh((6, 5, 5), perturb=0.2, seed=4, mode="tensor"), 2, 2, seed=6, symmetric=True)
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    u = torch.zeros((3, n), device=DEV, dtype=torch.float64)
+    st = ctx.newton_solve(u, tol=1e-10, eta=1e-8, restart=60)
+    assert st["converged"]
+    uo, _ = onw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-8, m=60)
+    ue = prob.loads.exact.value(disc.cen)
+    assert np.linalg.norm(to_host(u) - uo) <= 1e-7 * np.linalg.norm(uo)
+    assert np.linalg.norm(to_host(u) - ue) <= 1e-7 * np.linalg.norm(ue)
 
 
 def test_fgmres_nonzero_initial_guess_and_zero_rhs():

@@ -221,3 +221,18 @@ def test_bench_and_entry_points_compile(repo_root):
     import py_compile
     for f in ("bench.py", "__graft_entry__.py"):
         py_compile.compile(os.path.join(repo_root, f), doraise=True)
+
+
+def test_symmetry_faces_get_their_own_flux_codes():
+    """Cells on a symmetry plane point one face slot at the symmetry fluxes
+    (codes >= the number of internal and displacement faces)."""
+    prob = w.poly_patch(w.box_mesh((5, 4, 4), perturb=0.2, seed=4, mode="tensor"), 2, 2, seed=6, symmetric=True)
+    disc = ores.build(prob)
+    ctx = api.context_for(prob, host_only=True)
+    n = disc.n_cells
+    cf = ctx.host_table("cell_faces").reshape(6, n)
+    nf = len(disc.f_own) + len(disc.d_own)
+    sym_codes = cf[(cf >= nf) & (cf != np.iinfo(np.int32).min)]
+    assert sorted(sym_codes - nf) == list(range(disc.s_own.size))
+    owners = np.nonzero((cf >= nf).any(axis=0))[0]
+    assert sorted(owners) == sorted(disc.s_own)
