@@ -54,9 +54,9 @@ typedef enum {
 
 enum { HOFV_LINEAR_ELASTIC = 0, HOFV_NEO_HOOKEAN = 1 };
 /* Symmetry planes (Sec. 3.5): the face's stencil is the ceil(|S|/2) nearest cells and
- * their mirror images, the images carrying R_b u (R_b = I - 2 n n); the linear-elastic
- * law only (HOFV_EINVAL at setup with the neo-Hookean one); u_b and traction values
- * given for such faces are ignored. */
+ * their mirror images, the images carrying R_b u (R_b = I - 2 n n); both laws; no
+ * stabilisation term on such faces; u_b and traction values given for them are
+ * ignored. */
 enum { HOFV_BC_DISPLACEMENT = 0, HOFV_BC_TRACTION = 1, HOFV_BC_SYMMETRY = 2 };
 
 /* Discretisation parameters (paper Secs. 3.4-3.5). */

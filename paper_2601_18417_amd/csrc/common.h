@@ -90,12 +90,16 @@ struct DeviceTables {
   float* p_r = nullptr;          // [D][nc]
   float* p_z = nullptr;          // [D][nc]
   float* p_diag = nullptr;       // [nc] A_PP (multigrid residual)
-  // symmetry faces (linear elastic): half stencils and per-entry traction
-  // matrices; their fluxes live in sym_flux, cell codes >= nf point there
+  // symmetry faces: half stencils and per-entry traction matrices (linear
+  // elastic) or per-point coefficients (neo-Hookean); their fluxes live in
+  // sym_flux, cell codes >= nf point there
   int64_t sym_nf = 0;
   int32_t sym_S = 0;
   int32_t* sym_st = nullptr;     // [S_half][nfs] stencil cells
-  double* sym_T = nullptr;       // [S_half][D][D][nfs] traction per unit u_N,k
+  double* sym_T = nullptr;       // [S_half][D][D][nfs] traction per unit u_N,k (linear elastic)
+  double* sym_C = nullptr;       // [S_half][nq][2][D][nfs] point coefficients of cell and image (NH)
+  double* sym_sv = nullptr;      // [nq][D][nfs] weighted area vectors (NH)
+  double* sym_n = nullptr;       // [D][nfs] unit normals (NH)
   double* sym_flux = nullptr;    // [D][nfs]
   // BDF2 inertia (App. D, one point per cell): R_P += s_P - m_P u_P
   double* dyn_rv = nullptr;      // [nc] rho * volume

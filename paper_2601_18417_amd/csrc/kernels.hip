@@ -259,6 +259,76 @@ __global__ __launch_bounds__(kBlockItems) void k_face_le(int64_t nf, int64_t nfi
   for (int j = 0; j < D; ++j) F[(int64_t)j * nf + f] = t[j];
 }
 
+// neo-Hookean face traction at one quadrature point: t_j += sum_i sv_i P_ji with
+// P the first Piola-Kirchhoff stress of the gradient G (G[i][j] = d u_j / d x_i)
+// and sv the point's weighted area vector; flag[0] = 1 at an inverted point
+__device__ inline void nh_traction(const double (*G)[3], const double* sv, double mu, double lam, double* t,
+                                   int32_t* __restrict__ flag) {
+  // F = I + H with H = G^T, J = det F, bbar = J^{-2/3} F F^T,
+  // sigma = mu/J dev(bbar) + kappa/2 (J^2 - 1)/J I, P = J sigma F^{-T} = sigma cof(F).
+  // Evaluated from H so that no O(1) terms cancel at small strain (a
+  // finite-difference product perturbs H by ~1e-8):
+  // J - 1 = tr H + ((tr H)^2 - tr(H H))/2 + det H, dev(bbar) = J^{-2/3} dev(B)
+  // with B = b - I = H + H^T + H H^T, J^2 - 1 = (J - 1)(J + 1).
+  double H[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) H[a][c] = G[c][a];
+  double cof[3][3];  // cofactors of F = I + H
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int a1 = (a + 1) % 3, a2 = (a + 2) % 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+      const double f11 = (a1 == c1 ? 1.0 : 0.0) + H[a1][c1], f22 = (a2 == c2 ? 1.0 : 0.0) + H[a2][c2];
+      const double f12 = (a1 == c2 ? 1.0 : 0.0) + H[a1][c2], f21 = (a2 == c1 ? 1.0 : 0.0) + H[a2][c1];
+      cof[a][c] = f11 * f22 - f12 * f21;
+    }
+  const double trH = H[0][0] + H[1][1] + H[2][2];
+  double trHH = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) trHH += H[a][c] * H[c][a];
+  const double detH = H[0][0] * (H[1][1] * H[2][2] - H[1][2] * H[2][1]) -
+                      H[0][1] * (H[1][0] * H[2][2] - H[1][2] * H[2][0]) +
+                      H[0][2] * (H[1][0] * H[2][1] - H[1][1] * H[2][0]);
+  double Jm1 = trH + 0.5 * (trH * trH - trHH) + detH;
+  double J = 1.0 + Jm1;
+  if (!(J > 0.0)) {
+    flag[0] = 1;
+    J = 1.0;
+    Jm1 = 0.0;
+  }
+  const double kappa = lam + 2.0 * mu / 3.0;
+  const double cb = cbrt(J);
+  const double invJ = 1.0 / J;
+  const double sdev = mu * invJ / (cb * cb);
+  double B[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) B[a][c] = H[a][c] + H[c][a] + (H[a][0] * H[c][0] + H[a][1] * H[c][1] + H[a][2] * H[c][2]);
+  const double trB = (B[0][0] + B[1][1] + B[2][2]) / 3.0;
+  const double pr = 0.5 * kappa * Jm1 * (J + 1.0) * invJ;
+  double sig[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sig[a][c] = sdev * (B[a][c] - (a == c ? trB : 0.0)) + (a == c ? pr : 0.0);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double Pji = sig[j][0] * cof[0][i] + sig[j][1] * cof[1][i] + sig[j][2] * cof[2][i];
+      s += sv[i] * Pji;
+    }
+    t[j] += s;
+  }
+}
+
 // per-quadrature-point face kernel; MAT 0 linear elastic, 1 neo-Hookean (D = 3)
 template <int D, int NQ, int MAT>
 __global__ __launch_bounds__(kBlockItems) void k_face_q(int64_t nf, int64_t nfi, int64_t nc, int S,
@@ -302,7 +372,7 @@ __global__ __launch_bounds__(kBlockItems) void k_face_q(int64_t nf, int64_t nfi,
     double sv[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) sv[i] = Sv[((int64_t)q * D + i) * nf + f];
-    if (MAT == 0) {
+    if constexpr (MAT == 0) {
       double tr = 0.0;
 #pragma unroll
       for (int i = 0; i < D; ++i) tr += G[q * D + i][i];
@@ -314,69 +384,7 @@ __global__ __launch_bounds__(kBlockItems) void k_face_q(int64_t nf, int64_t nfi,
         t[j] += s;
       }
     } else {
-      // F = I + H with H = G^T, J = det F, bbar = J^{-2/3} F F^T,
-      // sigma = mu/J dev(bbar) + kappa/2 (J^2 - 1)/J I, P = J sigma F^{-T} = sigma cof(F).
-      // Evaluated from H so that no O(1) terms cancel at small strain (a
-      // finite-difference product perturbs H by ~1e-8):
-      // J - 1 = tr H + ((tr H)^2 - tr(H H))/2 + det H, dev(bbar) = J^{-2/3} dev(B)
-      // with B = b - I = H + H^T + H H^T, J^2 - 1 = (J - 1)(J + 1).
-      double H[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) H[a][c] = G[q * D + c][a];
-      double cof[3][3];  // cofactors of F = I + H
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int a1 = (a + 1) % 3, a2 = (a + 2) % 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-          const double f11 = (a1 == c1 ? 1.0 : 0.0) + H[a1][c1], f22 = (a2 == c2 ? 1.0 : 0.0) + H[a2][c2];
-          const double f12 = (a1 == c2 ? 1.0 : 0.0) + H[a1][c2], f21 = (a2 == c1 ? 1.0 : 0.0) + H[a2][c1];
-          cof[a][c] = f11 * f22 - f12 * f21;
-        }
-      const double trH = H[0][0] + H[1][1] + H[2][2];
-      double trHH = 0.0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) trHH += H[a][c] * H[c][a];
-      const double detH = H[0][0] * (H[1][1] * H[2][2] - H[1][2] * H[2][1]) -
-                          H[0][1] * (H[1][0] * H[2][2] - H[1][2] * H[2][0]) +
-                          H[0][2] * (H[1][0] * H[2][1] - H[1][1] * H[2][0]);
-      double Jm1 = trH + 0.5 * (trH * trH - trHH) + detH;
-      double J = 1.0 + Jm1;
-      if (!(J > 0.0)) {
-        flag[0] = 1;
-        J = 1.0;
-        Jm1 = 0.0;
-      }
-      const double kappa = lam + 2.0 * mu / 3.0;
-      const double cb = cbrt(J);
-      const double invJ = 1.0 / J;
-      const double sdev = mu * invJ / (cb * cb);
-      double B[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) B[a][c] = H[a][c] + H[c][a] + (H[a][0] * H[c][0] + H[a][1] * H[c][1] + H[a][2] * H[c][2]);
-      const double trB = (B[0][0] + B[1][1] + B[2][2]) / 3.0;
-      const double pr = 0.5 * kappa * Jm1 * (J + 1.0) * invJ;
-      double sig[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) sig[a][c] = sdev * (B[a][c] - (a == c ? trB : 0.0)) + (a == c ? pr : 0.0);
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const double Pji = sig[j][0] * cof[0][i] + sig[j][1] * cof[1][i] + sig[j][2] * cof[2][i];
-          s += sv[i] * Pji;
-        }
-        t[j] += s;
-      }
+      nh_traction(&G[q * D], sv, mu, lam, t, flag);
     }
   }
   add_stab<D>(f, nfi, nc, own, nei, slots, stab, ustar, t);
@@ -408,6 +416,48 @@ __global__ __launch_bounds__(kBlock) void k_face_sym(int64_t nfs, int Sh, const 
   }
 #pragma unroll
   for (int j = 0; j < D; ++j) Fs[(int64_t)j * nfs + f] = t[j];
+}
+
+// symmetry faces, neo-Hookean: the gradient at each point from the cells and
+// their images (which carry R u, R = I - 2 n n), then the point traction
+template <int NQ>
+__global__ __launch_bounds__(kBlock) void k_face_sym_nh(int64_t nfs, int Sh, const int32_t* __restrict__ st,
+                                                        const double* __restrict__ C, const double* __restrict__ sv,
+                                                        const double* __restrict__ nrm, double mu, double lam,
+                                                        const double* __restrict__ ug, double* __restrict__ Fs,
+                                                        int32_t* __restrict__ flag) {
+  const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (f >= nfs) return;
+  const double n[3] = {nrm[f], nrm[nfs + f], nrm[2 * nfs + f]};
+  double G[NQ * 3][3];
+#pragma unroll
+  for (int r = 0; r < NQ * 3; ++r)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) G[r][j] = 0.0;
+  for (int N = 0; N < Sh; ++N) {
+    const int64_t cell = st[(int64_t)N * nfs + f];
+    const double u[3] = {ug[4 * cell], ug[4 * cell + 1], ug[4 * cell + 2]};
+    const double un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+    const double ru[3] = {u[0] - 2.0 * un * n[0], u[1] - 2.0 * un * n[1], u[2] - 2.0 * un * n[2]};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double c0 = C[((((int64_t)N * NQ + q) * 2 + 0) * 3 + a) * nfs + f];
+        const double c1 = C[((((int64_t)N * NQ + q) * 2 + 1) * 3 + a) * nfs + f];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) G[q * 3 + a][j] += c0 * u[j] + c1 * ru[j];
+      }
+  }
+  double t[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double s[3] = {sv[((int64_t)q * 3) * nfs + f], sv[((int64_t)q * 3 + 1) * nfs + f],
+                         sv[((int64_t)q * 3 + 2) * nfs + f]};
+    nh_traction(&G[q * 3], s, mu, lam, t, flag);
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Fs[(int64_t)j * nfs + f] = t[j];
 }
 
 template <int D>
@@ -764,8 +814,21 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
 #undef FACEQ
     }
   }
-  if (t.sym_nf > 0)
-    k_face_sym<D><<<blocks_for(t.sym_nf), kBlock, 0, st>>>(t.sym_nf, t.sym_S, t.sym_st, t.sym_T, u, t.sym_flux);
+  if (t.sym_nf > 0) {
+    if (!nh) {
+      k_face_sym<D><<<blocks_for(t.sym_nf), kBlock, 0, st>>>(t.sym_nf, t.sym_S, t.sym_st, t.sym_T, u, t.sym_flux);
+    } else if constexpr (D == 3) {
+      const unsigned g = blocks_for(t.sym_nf);
+#define SYMNH(Q)                                                                                                    \
+  k_face_sym_nh<Q><<<g, kBlock, 0, st>>>(t.sym_nf, t.sym_S, t.sym_st, t.sym_C, t.sym_sv, t.sym_n, c->prm.mu,        \
+                                         c->prm.lambda, u, t.sym_flux, t.flag)
+      if (t.nq == 1) SYMNH(1);
+      else if (t.nq == 4) SYMNH(4);
+      else if (t.nq == 9) SYMNH(9);
+      else return fail(c, HOFV_EINVAL, "unsupported number of face quadrature points");
+#undef SYMNH
+    }
+  }
   TIMED("k_cell_sum", (k_cell_sum<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, nf, t.c_faces, t.flux, t.c_src, c->load,
                                                                           Ru, eps, u, t.dyn_m, t.dyn_s, t.sym_flux,
                                                                           t.sym_nf, R)));

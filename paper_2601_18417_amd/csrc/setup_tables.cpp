@@ -47,7 +47,6 @@ hofv_status build_tables(hofv_ctx* c) {
     else if (c->btype[b] == HOFV_BC_SYMMETRY) symb.push_back((int64_t)b);
     else trac.push_back((int64_t)b);
   }
-  if (!symb.empty() && nh) return fail(c, HOFV_EINVAL, "symmetry faces need the linear-elastic law");
   auto curve = [&](int64_t begin, int64_t end) {
     std::vector<double> x((size_t)(end - begin) * D);
     for (int64_t i = begin; i < end; ++i)
@@ -182,7 +181,11 @@ hofv_status build_tables(hofv_ctx* c) {
   const int Sh = (S + 1) / 2;
   const int64_t nfs = (int64_t)symb.size();
   std::vector<int32_t> sst((size_t)nfs * Sh), sst_t((size_t)Sh * nfs);
-  std::vector<double> sT((size_t)Sh * D * D * nfs, 0.0), saj(nfs, 0.0);
+  std::vector<double> sT(nh ? 0 : (size_t)Sh * D * D * nfs, 0.0), saj(nfs, 0.0);
+  // neo-Hookean: per-point coefficients of each cell and of its image
+  // [Sh][nq][2][D][nfs], weighted area vectors [nq][D][nfs], normals [D][nfs]
+  std::vector<double> sC(nh ? (size_t)Sh * nq * 2 * D * nfs : 0, 0.0), ssv(nh ? (size_t)nq * D * nfs : 0, 0.0),
+      sn(nh ? (size_t)D * nfs : 0, 0.0);
   std::vector<int32_t> sown(nfs), sslot(nfs);
   if (nfs) {
     std::vector<double> spts((size_t)nfs * D);
@@ -222,6 +225,14 @@ hofv_status build_tables(hofv_ctx* c) {
       max_cond = std::max(max_cond, cond);
       const double wq = c->f_qw[(size_t)f * nq + q] * A;
       const int m = 2 * Sh;
+      if (nh) {
+        for (int N = 0; N < Sh; ++N)
+          for (int side = 0; side < 2; ++side)
+            for (int a = 0; a < D; ++a)
+              sC[((((size_t)N * nq + q) * 2 + side) * D + a) * nfs + i] = out[a * m + side * Sh + N];
+        for (int d = 0; d < D; ++d) ssv[((size_t)q * D + d) * nfs + i] = wq * n[d];
+        continue;
+      }
       for (int N = 0; N < Sh; ++N)
         for (int kc = 0; kc < D; ++kc) {
           // gradient G[a][j] produced by a unit u_N,kc: its own coefficient and its image's
@@ -238,6 +249,8 @@ hofv_status build_tables(hofv_ctx* c) {
           }
         }
     }
+    if (nh)
+      for (int d = 0; d < D; ++d) sn[(size_t)d * nfs + i] = n[d];
     const double* xP = &c->cen[(size_t)F.own * D];
     double dn = 0;
     for (int d = 0; d < D; ++d) dn += (xf[d] - xP[d]) * n[d];
@@ -542,7 +555,13 @@ hofv_status build_tables(hofv_ctx* c) {
   t.sym_S = Sh;
   if (nfs) {
     UP(t.sym_st, sst_t);
-    UP(t.sym_T, sT);
+    if (nh) {
+      UP(t.sym_C, sC);
+      UP(t.sym_sv, ssv);
+      UP(t.sym_n, sn);
+    } else {
+      UP(t.sym_T, sT);
+    }
     if ((st = dev_alloc(c, &t.sym_flux, (size_t)D * nfs))) return st;
   }
 #undef UP
