@@ -416,3 +416,22 @@ def test_multigrid_fp32_close_to_fp64():
     z64 = pc.vcycle(lev, r, 2)
     z32 = pc.vcycle(lev, r, 2, dtype=np.float32)
     assert np.abs(z32 - z64).max() <= 2e-5 * np.abs(z64).max()
+
+
+def test_bench_forcing_rule_is_the_oracles():
+    """bench.py applies the forcing rule itself across one-step library calls;
+    it must be the same rule (the library's, written in the oracle)."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "bench_mod", os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        r0 = 1.0
+        rprev = 10 ** rng.uniform(-9, 0)
+        rn = rprev * 10 ** rng.uniform(-4, 0.3)
+        eta_prev, eta_max, tol = 10 ** rng.uniform(-6, 0), 10 ** rng.uniform(-3, 0), 10 ** rng.uniform(-12, -6)
+        assert bench.forcing_term(rn, rprev, eta_prev, eta_max, tol, r0) == \
+            nw.forcing_term(rn, rprev, eta_prev, eta_max, tol, r0)
