@@ -19,7 +19,6 @@ R = 0 becomes R = rho a Omega (the face and body terms drive the acceleration).
 """
 from __future__ import annotations
 
-
 from .newton import newton
 
 
