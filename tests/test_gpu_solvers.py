@@ -236,6 +236,11 @@ def test_long_cycle_fgmres_solves_a_slender_neo_hookean_beam():
     print("beam FGMRES(600) relative residual / iterations (sweeps, multigrid):", rel, its)
     assert rel[8] <= 1e-6 and its[8] < 600
     assert rel[1] > 100 * rel[8]
+    # cycles are capped at 2048 vectors: a longer one is an argument error
+    with pytest.raises(_api().HofvError):
+        ctx.fgmres_solve(u, R, -R, x, restart=4096, max_iters=10)
+    with pytest.raises(_api().HofvError):
+        ctx.newton_solve(u, restart=2049, max_newton=1)
 
 
 def test_newton_eisenstat_walker_forcing_matches_oracle():
