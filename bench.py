@@ -368,7 +368,7 @@ def main():
     ap.add_argument("--eta", type=float, default=None,
                     help="Krylov tolerance of each Newton step (default 1e-4; cantilever 0.5 with --forcing 1)")
     ap.add_argument("--restart", type=int, default=None,
-                    help="FGMRES cycle length, at most 2048 (default 30; cantilever 500)")
+                    help="FGMRES cycle length, at most 2048 (default 30; cantilever 250)")
     ap.add_argument("--line-search", type=int, default=None,
                     help="Newton backtracking halvings; -1: full steps (halved only at an inverted cell)")
     ap.add_argument("--forcing", type=int, default=None,
@@ -392,7 +392,7 @@ def main():
     defaults = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0,
                 "solvers": "plain,multigrid,learned", "precond_levels": 8}
     if args.workload == "cantilever":
-        defaults.update(eta=0.5, restart=500, line_search=-1, forcing=1, predictor=1, solvers="multigrid")
+        defaults.update(eta=0.5, restart=250, line_search=-1, forcing=1, predictor=1, solvers="multigrid")
     elif args.workload == "column":  # the mass term keeps each step well conditioned
         defaults.update(eta=0.1, restart=60, line_search=-1, forcing=1, precond_levels=1)
     for key, val in defaults.items():
