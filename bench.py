@@ -348,6 +348,8 @@ def main():
     ap.add_argument("--learned", type=int, default=1,
                     help="train the learned correction and time the learned Newton solve")
     ap.add_argument("--learned-size", type=int, default=24, help="cells per axis of the training meshes")
+    ap.add_argument("--nej-inner", type=int, default=4,
+                    help="inner GMRES iterations per application of the near-exact Jacobian (solver nej)")
     ap.add_argument("--learned-epochs", type=int, default=60)
     ap.add_argument("--tol", type=float, default=0.0, help="Newton tolerance (default 1e-8; 1e-10 for square)")
     ap.add_argument("--max-krylov", type=int, default=4000, help="Krylov iterations per Newton step")
@@ -380,7 +382,8 @@ def main():
                     help="0: right-preconditioned FGMRES; 1: left-preconditioned GMRES as eq. jfnk prints it "
                          "(its tolerance is on the preconditioned residual)")
     ap.add_argument("--solvers", default=None,
-                    help="time-to-tolerance solves to run: any of plain, multigrid, learned (learned needs plain)")
+                    help="time-to-tolerance solves to run: any of plain, multigrid, learned (learned needs plain), "
+                         "nej / nejmg (the near-exact Jacobian of App. C over the sweeps / the V-cycle, linear elastic law)")
     ap.add_argument("--stepwise", type=int, default=0,
                     help="time-to-tolerance solves as one logged library Newton step per call, at most this many "
                          "steps per increment (0: one library call per increment)")
@@ -536,6 +539,20 @@ def main():
                                                  "(2 sweeps on the cell level, 2 Jacobi steps on coarser ones)")
             ctx.set_multigrid(False)
             log(f"multigrid solve {solve['multigrid']}")
+        for name, inner_mg in (("nej", False), ("nejmg", True)):
+            if name not in solvers or prob.material != w.LINEAR_ELASTIC or (inner_mg and not multigrid):
+                continue
+            ctx.set_multigrid(inner_mg)
+            ctx.set_nej(args.nej_inner)
+            if prob.n_increments == 1:
+                newton(False)
+            solve[name] = newton(False)
+            solve[name + "_preconditioner"] = (f"near-exact Jacobian (App. C): {args.nej_inner} GMRES iterations on "
+                                               "the stabilisation-free operator, right-preconditioned by the "
+                                               + ("V-cycle" if inner_mg else "sweeps"))
+            ctx.set_nej(0)
+            ctx.set_multigrid(False)
+            log(f"{name} solve {solve[name]}")
         # one application of each preconditioner, host-timed over 20 calls
         rr = torch.randn((D, nc), device=dev, dtype=torch.float64, generator=torch.Generator(device=dev).manual_seed(5))
         zz = torch.empty_like(rr)

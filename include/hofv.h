@@ -154,6 +154,28 @@ hofv_status hofv_set_load_scale(hofv_ctx* ctx, double s);
  * The default follows precond_levels. */
 hofv_status hofv_set_multigrid(hofv_ctx* ctx, int32_t enable);
 
+/* Near-exact Jacobian (App. C, linear elastic law only): the derivative of the
+ * discrete momentum equations without the alpha-stabilisation term of
+ * Sec. 3.4, with the full face stencils.  The residual is affine in u, so
+ * d_out = A d_v is evaluated matrix-free as the residual of d_v with the
+ * stabilisation, every load (u_b, tractions, f_b) and the inertia source set
+ * to zero; with dynamics on, A includes the -m_P u_P mass term of the step.
+ * Device arrays [dim][n_cells], no aliasing; ordered on `stream`, does not
+ * synchronise.  HOFV_EINVAL for the neo-Hookean law or bad pointers. */
+hofv_status hofv_nej_apply(hofv_ctx* ctx, const double* d_v, double* d_out, void* stream);
+
+/* Uses the near-exact Jacobian as the preconditioner of hofv_precond_apply and
+ * the solvers: z ~ A^{-1} r by inner_iters (1..64) iterations of GMRES from
+ * zero on A, right-preconditioned by the approximate Jacobian (the sweeps or
+ * the V-cycle, as selected), so each application costs inner_iters residual
+ * evaluations and inner_iters + 1 approximate-Jacobian applications.  The
+ * result depends on r nonlinearly, so the outer solve must be the flexible
+ * right-preconditioned FGMRES (side 0) without the learned correction
+ * (HOFV_EINVAL otherwise).  inner_iters = 0 switches it off.  Allocates the
+ * inner basis ((inner_iters + 1) [dim][n_cells] vectors) on first use or
+ * growth; HOFV_EINVAL for the neo-Hookean law or inner_iters outside 0..64. */
+hofv_status hofv_set_nej(hofv_ctx* ctx, int32_t inner_iters);
+
 /* R = R(u) (eq. divStressDiscret with eqs. faceQuadGrad, alpha, alphaJump,
  * bodyTerm).  d_u, d_R: device [dim][n_cells]; they must not alias. */
 hofv_status hofv_residual(hofv_ctx* ctx, const double* d_u, double* d_R, void* stream);

@@ -73,6 +73,8 @@ SIGNATURES = {
     "hofv_setup": (ST, [P, C.POINTER(SetupReport)]),
     "hofv_set_load_scale": (ST, [P, C.c_double]),
     "hofv_set_multigrid": (ST, [P, C.c_int32]),
+    "hofv_set_nej": (ST, [P, C.c_int32]),
+    "hofv_nej_apply": (ST, [P, P, P, P]),
     "hofv_residual": (ST, [P, P, P, P]),
     "hofv_jvp": (ST, [P, P, P, P, P, C.c_double, P]),
     "hofv_precond_apply": (ST, [P, P, P, C.c_int32, C.c_int32, P]),

@@ -125,12 +125,21 @@ class Context:
     def set_multigrid(self, enable):
         self._check(self.lib.hofv_set_multigrid(self.h, int(bool(enable))))
 
+    def set_nej(self, inner_iters):
+        """Near-exact Jacobian preconditioner (App. C) with inner_iters inner
+        GMRES iterations per application; 0 switches it off."""
+        self._check(self.lib.hofv_set_nej(self.h, int(inner_iters)))
+
     # ------------------------------------------------------------------- hot
     def residual(self, u, R, stream=None):
         self._check(self.lib.hofv_residual(self.h, _ptr(u), _ptr(R), _stream(stream)))
 
     def jvp(self, u, Ru, v, Jv, eps=0.0, stream=None):
         self._check(self.lib.hofv_jvp(self.h, _ptr(u), _ptr(Ru), _ptr(v), _ptr(Jv), float(eps), _stream(stream)))
+
+    def nej_apply(self, v, out, stream=None):
+        """out = A v for the near-exact Jacobian A (linear elastic law)."""
+        self._check(self.lib.hofv_nej_apply(self.h, _ptr(v), _ptr(out), _stream(stream)))
 
     def precond_apply(self, r, z, n_sweeps=2, learned=False, stream=None):
         self._check(self.lib.hofv_precond_apply(self.h, _ptr(r), _ptr(z), int(n_sweeps), int(bool(learned)),

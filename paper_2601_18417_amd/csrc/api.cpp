@@ -34,6 +34,10 @@ hofv_status jvp_impl(hofv_ctx* c, const double* u, const double* Ru, const doubl
 }
 
 hofv_status precond_dispatch(hofv_ctx* c, const double* r, double* z, int sweeps, int learned, hipStream_t st) {
+  if (c->nej.k > 0) {
+    if (learned) return fail(c, HOFV_EINVAL, "the learned correction is trained on the approximate Jacobian");
+    return nej_solve(c, r, z, sweeps, st);
+  }
   if (!learned || !c->nn) return launch_precond(c, r, z, sweeps, st);
   hofv_status s;
   if (!c->nnw.zaj) {
@@ -221,6 +225,24 @@ hofv_status hofv_set_multigrid(hofv_ctx* c, int32_t enable) {
   if (enable && c->dev.dyn_m) return fail(c, HOFV_EINVAL, "the multigrid hierarchy is built for the static operator");
   c->use_mg = enable != 0;
   return HOFV_OK;
+}
+
+hofv_status hofv_set_nej(hofv_ctx* c, int32_t inner_iters) {
+  hofv_status s = need(c, 4, "set_nej");
+  if (s) return s;
+  if ((s = set_device(c))) return s;
+  return nej_set(c, inner_iters);
+}
+
+hofv_status hofv_nej_apply(hofv_ctx* c, const double* d_v, double* d_out, void* stream) {
+  hofv_status s = need(c, 4, "nej_apply");
+  if (s) return s;
+  if (!d_v || !d_out || (const void*)d_v == (void*)d_out) return fail(c, HOFV_EINVAL, "bad v/out pointers");
+  if (c->prm.material != HOFV_LINEAR_ELASTIC)
+    return fail(c, HOFV_EINVAL, "the near-exact Jacobian is defined for the linear elastic law");
+  if ((s = set_device(c))) return s;
+  if ((s = nej_zero(c))) return s;
+  return launch_nej(c, d_v, d_out, (hipStream_t)stream);
 }
 
 hofv_status hofv_set_dynamics(hofv_ctx* c, double rho, double dt) {

@@ -140,6 +140,21 @@ struct Krylov {
   double* zz = nullptr;    // squared norms of learned preconditioner outputs [m]
 };
 
+// near-exact Jacobian preconditioner (App. C): k right-preconditioned GMRES
+// iterations on the stabilisation-free linear operator per application
+struct Nej {
+  int k = 0;               // inner iterations (0: off)
+  int cap = 0;             // allocated basis size
+  double* zero = nullptr;  // [max(nf, D nc)] zeros in place of the stabilisation and inertia sources
+  double* V = nullptr;     // [(cap+1)][n]
+  double* t = nullptr;     // [n]
+  double* h = nullptr;     // device scalars in the Krylov driver's layout
+  double* Hd = nullptr;    // [cap][cap + 1]
+  double* zz = nullptr;    // [cap]
+  double* y = nullptr;     // [cap]
+  std::vector<double> hbuf, ybuf;
+};
+
 }  // namespace hofv
 
 struct hofv_ctx {
@@ -185,6 +200,7 @@ struct hofv_ctx {
   bool dyn_ready = false;  // history set by hofv_dyn_reset
   hofv::DeviceTables dev;
   hofv::Krylov kry;
+  hofv::Nej nej;
   hofv::NnWork nnw;
   hofv_nn* nn = nullptr;  // attached learned correction (not owned)
   std::vector<void*> allocations;
@@ -302,6 +318,11 @@ hofv_status launch_eps(hofv_ctx* c, const double* u, const double* v, double eps
                        hipStream_t st);
 hofv_status launch_axpy_w(hofv_ctx* c, const double* u, const double* v, hipStream_t st);
 hofv_status launch_precond(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st);
+hofv_status launch_nej(hofv_ctx* c, const double* v, double* out, hipStream_t st);
+// krylov.hip: the near-exact Jacobian preconditioner
+hofv_status nej_zero(hofv_ctx* c);
+hofv_status nej_set(hofv_ctx* c, int k);
+hofv_status nej_solve(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st);
 // dynamics.hip
 hofv_status dyn_set(hofv_ctx* c, double rho, double dt);
 hofv_status dyn_reset(hofv_ctx* c, const double* u_t, const double* u_tm1, const double* v_t, const double* v_tm1,

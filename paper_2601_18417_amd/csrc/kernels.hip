@@ -848,6 +848,27 @@ hofv_status launch_residual(hofv_ctx* c, const double* u, double* R, const doubl
   return c->D == 2 ? residual_impl<2>(c, ug, R, Ru, eps, st) : residual_impl<3>(c, ug, R, Ru, eps, st);
 }
 
+// The near-exact Jacobian of App. C: the derivative of the discrete linear
+// elastic equations without the alpha-stabilisation.  The residual is affine
+// in u, so with the stabilisation coefficients, the loads and the inertia
+// source set to zero it is that linear operator itself (for dynamics, minus
+// the mass term m_P, which belongs to the step's Jacobian).
+hofv_status launch_nej(hofv_ctx* c, const double* v, double* out, hipStream_t st) {
+  DeviceTables& t = c->dev;
+  const double load = c->load;
+  double* stab = t.f_stab;
+  double* ds = t.dyn_s;
+  c->load = 0.0;
+  t.f_stab = c->nej.zero;
+  if (t.dyn_m) t.dyn_s = c->nej.zero;
+  // the launches take the values at enqueue time; restore them at once
+  const hofv_status s = launch_residual(c, v, out, nullptr, nullptr, st);
+  c->load = load;
+  t.f_stab = stab;
+  t.dyn_s = ds;
+  return s;
+}
+
 hofv_status launch_eps(hofv_ctx* c, const double* u, const double* v, double eps_host, hipStream_t st) {
   DeviceTables& t = c->dev;
   const int64_t n = (int64_t)c->D * c->nc;

@@ -201,6 +201,8 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
   // on the preconditioned residual; M must then be one fixed operator
   const bool left = o->side == 1;
   if (left && o->learned) return fail(c, HOFV_EINVAL, "the learned correction needs right preconditioning");
+  if (c->nej.k > 0 && (left || o->learned))
+    return fail(c, HOFV_EINVAL, "the near-exact Jacobian preconditioner needs right preconditioning, unlearned");
   if (o->side != 0 && o->side != 1) return fail(c, HOFV_EINVAL, "side must be 0 (right) or 1 (left)");
   if ((s = host_norm(c, n, x, &xnorm, st))) return s;
   if (left) {
@@ -344,6 +346,129 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
   stats->rel_residual = beta / bnorm;
   stats->converged = beta <= rtol * bnorm;
   stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return HOFV_OK;
+}
+
+// ---------------------------------------------------------------- near-exact Jacobian
+
+constexpr int kMaxNej = 64;  // longest inner GMRES of the near-exact Jacobian
+
+hofv_status nej_zero(hofv_ctx* c) {
+  if (c->nej.zero) return HOFV_OK;
+  const size_t nz = std::max<size_t>(c->faces.size(), (size_t)c->D * c->nc);
+  hofv_status s = dev_alloc(c, &c->nej.zero, nz);
+  if (s) return s;
+  HOFV_HIP(c, hipMemset(c->nej.zero, 0, nz * sizeof(double)));
+  return HOFV_OK;
+}
+
+hofv_status nej_set(hofv_ctx* c, int k) {
+  if (k < 0 || k > kMaxNej) return fail(c, HOFV_EINVAL, "near-exact Jacobian inner iterations must be 0..64");
+  if (k > 0 && c->prm.material != HOFV_LINEAR_ELASTIC)
+    return fail(c, HOFV_EINVAL, "the near-exact Jacobian is defined for the linear elastic law");
+  Nej& N = c->nej;
+  const int64_t n = (int64_t)c->D * c->nc;
+  hofv_status s;
+  if (k > N.cap) {
+    if (N.V) {  // grow: release the old basis
+      for (void* p : {(void*)N.V, (void*)N.Hd, (void*)N.zz, (void*)N.y}) {
+        hipFree(p);
+        c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), p), c->allocations.end());
+      }
+      c->device_bytes -= ((size_t)(N.cap + 1) * n + (size_t)(N.cap + 1) * N.cap + 2 * (size_t)N.cap) * sizeof(double);
+      N.V = N.Hd = N.zz = N.y = nullptr;
+      N.cap = 0;
+    }
+    if ((s = dev_alloc(c, &N.V, (size_t)(k + 1) * n)) || (s = dev_alloc(c, &N.Hd, (size_t)(k + 1) * k)) ||
+        (s = dev_alloc(c, &N.zz, (size_t)k)) || (s = dev_alloc(c, &N.y, (size_t)k)))
+      return s;
+    N.cap = k;
+  }
+  if (k > 0 && (s = nej_zero(c))) return s;
+  if (k > 0 && !N.t) {
+    if ((s = dev_alloc(c, &N.t, (size_t)n)) || (s = dev_alloc(c, &N.h, kHsize))) return s;
+  }
+  N.k = k;
+  return HOFV_OK;
+}
+
+// z ~ A^{-1} r for the near-exact Jacobian A: k iterations of GMRES from zero,
+// right-preconditioned by the approximate Jacobian M (sweeps or V-cycle), so
+// z = M (V_k y) with y minimising ||beta e_1 - H y||.  The Arnoldi vectors use
+// the same CGS2 as the outer solver; the host reads the Hessenberg matrix once.
+hofv_status nej_solve(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st) {
+  Nej& N = c->nej;
+  const int k = N.k;
+  const int64_t n = (int64_t)c->D * c->nc;
+  double* hd = N.h;
+  hofv_status s;
+  if ((s = dots(c, n, 1, r, n, r, hd + kBeta, 0, st))) return s;
+  k_scale_by<<<nblk(n), kB, 0, st>>>(n, r, hd + kBeta, 1, N.V);
+  for (int j = 0; j < k; ++j) {
+    double* vj = N.V + (size_t)j * n;
+    double* w = N.V + (size_t)(j + 1) * n;
+    if ((s = launch_precond(c, vj, N.t, sweeps, st))) return s;
+    if ((s = launch_nej(c, N.t, w, st))) return s;
+    if ((s = dots(c, n, j + 1, N.V, n, w, hd, 0, st))) return s;
+    k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, N.V, n, hd, -1.0, w);
+    if ((s = dots(c, n, j + 1, N.V, n, w, hd + kH2, 0, st))) return s;
+    k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, N.V, n, hd + kH2, -1.0, w);
+    if ((s = dots(c, n, 1, w, n, w, hd + j + 1, 0, st))) return s;
+    k_scale_by<<<nblk(n), kB, 0, st>>>(n, w, hd + j + 1, 1, w);
+    k_store_column<<<(unsigned)((j + 2 + kB - 1) / kB), kB, 0, st>>>(j, hd, k + 1, N.Hd, N.zz);
+  }
+  HOFV_HIP(c, hipGetLastError());
+  N.hbuf.resize((size_t)(k + 1) * k + 1);
+  HOFV_HIP(c, hipMemcpyAsync(N.hbuf.data(), N.Hd, (size_t)(k + 1) * k * sizeof(double), hipMemcpyDeviceToHost, st));
+  HOFV_HIP(c, hipMemcpyAsync(N.hbuf.data() + (size_t)(k + 1) * k, hd + kBeta, sizeof(double), hipMemcpyDeviceToHost,
+                             st));
+  HOFV_HIP(c, hipStreamSynchronize(st));
+  const double beta = std::sqrt(N.hbuf[(size_t)(k + 1) * k]);
+  for (size_t i = 0; i < N.hbuf.size(); ++i)
+    if (!std::isfinite(N.hbuf[i])) return fail(c, HOFV_ENAN, "NaN/Inf in the near-exact Jacobian solve");
+  if (beta == 0.0) {
+    k_fill<<<nblk(n), kB, 0, st>>>(n, 0.0, z);
+    HOFV_HIP(c, hipGetLastError());
+    return HOFV_OK;
+  }
+  // least squares by Givens rotations; a zero subdiagonal ends the Krylov
+  // space there (the solve is exact within it)
+  std::vector<double> H((size_t)(k + 1) * k), cs(k), sn(k), g(k + 1, 0.0);
+  int kk = 0;
+  g[0] = beta;
+  for (int j = 0; j < k; ++j) {
+    const double* col = &N.hbuf[(size_t)j * (k + 1)];
+    for (int i = 0; i <= j + 1; ++i) H[(size_t)i * k + j] = col[i];
+    for (int i = 0; i < j; ++i) {
+      const double a = H[(size_t)i * k + j], b = H[(size_t)(i + 1) * k + j];
+      H[(size_t)i * k + j] = cs[i] * a + sn[i] * b;
+      H[(size_t)(i + 1) * k + j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = H[(size_t)j * k + j], b = H[(size_t)(j + 1) * k + j];
+    const double den = std::hypot(a, b);
+    if (den == 0.0) break;
+    cs[j] = a / den;
+    sn[j] = b / den;
+    H[(size_t)j * k + j] = den;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    kk = j + 1;
+    if (b == 0.0) break;
+  }
+  N.ybuf.assign(k, 0.0);
+  for (int i = kk - 1; i >= 0; --i) {
+    double a = g[i];
+    for (int l = i + 1; l < kk; ++l) a -= H[(size_t)i * k + l] * N.ybuf[l];
+    N.ybuf[i] = a / H[(size_t)i * k + i];
+  }
+  HOFV_HIP(c, hipMemcpyAsync(N.y, N.ybuf.data(), (size_t)k * sizeof(double), hipMemcpyHostToDevice, st));
+  k_fill<<<nblk(n), kB, 0, st>>>(n, 0.0, N.t);
+  k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, kk, N.V, n, N.y, 1.0, N.t);
+  HOFV_HIP(c, hipGetLastError());
+  s = launch_precond(c, N.t, z, sweeps, st);
+  if (s) return s;
+  // the host vector y is reused by the next call only after this one has run
+  HOFV_HIP(c, hipStreamSynchronize(st));
   return HOFV_OK;
 }
 
