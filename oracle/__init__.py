@@ -23,4 +23,5 @@ triangular solves) as steps:
 * ``krylov``    - right-preconditioned flexible GMRES(m).
 * ``newton``    - Newton with backtracking line search and load increments.
 * ``mpnn``      - the learned preconditioner correction (FP64 reference).
+* ``nej``       - the near-exact Jacobian of App. C and its inner GMRES.
 """
