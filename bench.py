@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # passes (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, factors from a plain 512 MiB
 # elementwise copy), valid only for the kernel and table-layout sources whose
 # combined sha256 has this prefix.
-MEASURED_TRAFFIC = {"kernel": "k_face_le", "n": 64, "p": 3, "bytes": 1913819226.3,
-                    "kernels_sha256": "7ad8e381c511e423"}
+MEASURED_TRAFFIC = {"kernel": "k_face_le", "n": 64, "p": 3, "bytes": 1913328645.5,
+                    "kernels_sha256": "380c2a8dcb4100c1"}
 TRAFFIC_SOURCES = ("kernels.hip", "common.h", "setup_blocks.cpp", "setup_tables.cpp")
 
 

@@ -24,4 +24,5 @@ triangular solves) as steps:
 * ``newton``    - Newton with backtracking line search and load increments.
 * ``mpnn``      - the learned preconditioner correction (FP64 reference).
 * ``nej``       - the near-exact Jacobian of App. C and its inner GMRES.
+* ``dynamics``  - BDF2 time stepping of the momentum equation (App. D).
 """
