@@ -333,7 +333,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="cube", choices=["cube", "cantilever", "square", "column", "symmetric"],
+    ap.add_argument("--workload", default="cube",
+                    choices=["cube", "cantilever", "square", "column", "symmetric", "tets"],
                     help="cube: 3D LE manufactured solution on a perturbed n^3 mesh (default); cantilever: "
                          "3D neo-Hookean 200x20x20 beam, 10 load increments; square: 2D 32x32 LE, p=2; "
                          "column: the vibrating neo-Hookean column, BDF2 time steps; symmetric: a polynomial "
@@ -432,6 +433,8 @@ def main():
         prob = w.cantilever(p=args.p)
     elif args.workload == "column":
         prob = w.vibrating_column(tuple(int(x) for x in args.column_cells.split("x")), p=args.p)
+    elif args.workload == "tets":
+        prob = w.tet_mms(args.n, args.p, perturb=0.2, seed=0)
     elif args.workload == "symmetric":
         prob = w.poly_patch(w.box_mesh((args.n,) * 3, perturb=0.2, seed=0, mode="tensor"), args.p, args.p, seed=1,
                             symmetric=True)
@@ -632,6 +635,8 @@ def main():
                                           f"|S|={ctx.report['stencil_size']}",
                                 "column": f"3D neo-Hookean vibrating column 6 x 0.2 x 0.2 m, {args.column_cells} hex, "
                                           f"p={args.p}, |S|={ctx.report['stencil_size']}, BDF2 dt = 1 ms",
+                                "tets": f"3D linear elastic MMS, unit cube, {args.n}^3 hex perturbed +-20% (seed 0) "
+                                        f"each split into 6 tetrahedra, p={args.p}, |S|={ctx.report['stencil_size']}",
                                 "symmetric": f"3D LE polynomial (degree p) symmetric about x = 0, {args.n}^3 hex "
                                              f"tensor-perturbed +-20%, symmetry planes on x = 0, p={args.p}, "
                                              f"|S|={ctx.report['stencil_size']}"
@@ -640,7 +645,7 @@ def main():
         "residual_mcells_s": nc / (ms_res * 1e-3) / 1e6,
         "jvp_algorithmic_GBps": jvp_bytes / (ms_step * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.n, args.p),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.n, args.p) if args.workload == "cube" else None,
                      "bytes_per_launch": byts, "avg_ms": kernels[dom]["avg_ms"]},
         "kernels": kernels,
         "time_to_tol": solve,

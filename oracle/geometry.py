@@ -1,4 +1,5 @@
-"""Mesh geometry for straight-edged quads (2D) and trilinear hexahedra (3D).
+"""Mesh geometry for straight-edged quads (2D), trilinear hexahedra and
+tetrahedra (3D).
 
 Test infrastructure (see package docstring).  Follows Sec. 3.1 of the paper
 ("Solution Domain Discretisation"): cell centroid x_P and volume Omega_P, face
@@ -18,18 +19,32 @@ Readings where the paper is silent for these element shapes:
 * The face centre is x_f = sum_q alpha_q x_{f,q}.
 * The body-force volume quadrature uses (p+2)^D Gauss-Legendre points of the
   cell map with weights w detJ (so that sum_q beta_q Omega_P = sum_q w_q detJ_q).
+* Tetrahedra (the paper's tetrahedral meshes; its symmetric Dunavant and
+  Shunn-Ham rules are not reproduced): a tetrahedron is flat-faced, Omega_P is
+  its determinant / 6 and x_P the mean of its vertices.  A triangle face with
+  vertices x0, x1, x2 is integrated through the collapsed map
+  x0 + a (x1 - x0 + b (x2 - x1)), whose area element is 2 Gamma a: n_g
+  Gauss-Jacobi points of weight a times n_g Gauss-Legendre points in b.  The
+  cell map x0 + a (x1 - x0 + b (x2 - x1 + c (x3 - x2))) has detJ = 6 Omega a^2 b:
+  Gauss-Jacobi points of weights a^2 and b, Gauss-Legendre in c, p + 2 each.
+  With n points per direction these conical products are exact for total
+  degree 2n - 1.
 """
 from __future__ import annotations
 
 from dataclasses import dataclass
 
 import numpy as np
+from scipy.special import roots_jacobi
 
 # local faces, vertex order giving the outward normal of the cell
 QUAD_FACES = np.array([[3, 0], [1, 2], [0, 1], [2, 3]])
 HEX_FACES = np.array([[0, 4, 7, 3], [1, 2, 6, 5], [0, 1, 5, 4], [3, 7, 6, 2],
                       [0, 3, 2, 1], [4, 5, 6, 7]])
 QUAD_REF = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float)
+# the face opposite each vertex, ordered for the outward normal of a tetrahedron
+# with (x1 - x0) x (x2 - x0) . (x3 - x0) > 0
+TET_FACES = np.array([[1, 2, 3], [0, 3, 2], [0, 1, 3], [0, 2, 1]])
 HEX_REF = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
                     [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]], float)
 
@@ -38,6 +53,32 @@ def gauss_01(n: int):
     """n-point Gauss-Legendre rule mapped to [0, 1] (weights sum to 1)."""
     x, w = np.polynomial.legendre.leggauss(n)
     return 0.5 * (x + 1.0), 0.5 * w
+
+
+def jacobi_01(n: int, beta: int):
+    """n-point Gauss rule for the weight u^beta on [0, 1] (weights sum to
+    1 / (beta + 1)), from scipy's Gauss-Jacobi rule on [-1, 1], u = (1 + x) / 2."""
+    x, w = roots_jacobi(n, 0.0, float(beta))
+    return 0.5 * (x + 1.0), w / 2.0 ** (beta + 1)
+
+
+def is_tet(X: np.ndarray) -> bool:
+    return X.shape[-1] == 3 and X.shape[-2] == 4
+
+
+def tet_quadrature(X: np.ndarray, n: int):
+    """Conical-product rule on tetrahedra X (n_c, 4, 3): points (n_c, n^3, 3),
+    weights (n_c, n^3) integrating over the physical cell."""
+    a, wa = jacobi_01(n, 2)
+    b, wb = jacobi_01(n, 1)
+    c, wc = gauss_01(n)
+    A, B, Cc = (g.ravel() for g in np.meshgrid(a, b, c, indexing="ij"))
+    W = np.einsum("i,j,k->ijk", wa, wb, wc).ravel()
+    x0, x1, x2, x3 = X[:, 0], X[:, 1], X[:, 2], X[:, 3]
+    pts = x0[:, None] + A[None, :, None] * ((x1 - x0)[:, None] + B[None, :, None]
+                                            * ((x2 - x1)[:, None] + Cc[None, :, None] * (x3 - x2)[:, None]))
+    det = np.einsum("cd,cd->c", np.cross(x1 - x0, x2 - x0), x3 - x0)
+    return pts, W[None, :] * det[:, None]
 
 
 def shape_functions(ref: np.ndarray, xi: np.ndarray):
@@ -62,6 +103,8 @@ def cell_quadrature(X: np.ndarray, n: int):
     X: (n_c, 2^D, D) vertex coordinates.  Returns points (n_c, n^D, D) and
     weights w * detJ (n_c, n^D), which integrate over the physical cell.
     """
+    if is_tet(X):
+        return tet_quadrature(X, n)
     D = X.shape[2]
     ref = QUAD_REF if D == 2 else HEX_REF
     t, w = gauss_01(n)
@@ -77,6 +120,9 @@ def cell_quadrature(X: np.ndarray, n: int):
 
 
 def cell_volume_centroid(X: np.ndarray):
+    if is_tet(X):
+        det = np.einsum("cd,cd->c", np.cross(X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]), X[:, 3] - X[:, 0])
+        return det / 6.0, X.mean(axis=1)
     pts, W = cell_quadrature(X, 2)
     vol = W.sum(axis=1)
     cen = np.einsum("cq,cqd->cd", W, pts) / vol[:, None]
@@ -99,7 +145,7 @@ def enumerate_faces(cells: np.ndarray, dim: int) -> Faces:
     The owner is the lower cell id (its copy appears first), the neighbour the
     other one; a face seen once is a boundary face.
     """
-    lf = QUAD_FACES if dim == 2 else HEX_FACES
+    lf = QUAD_FACES if dim == 2 else (TET_FACES if cells.shape[1] == 4 else HEX_FACES)
     nlf = lf.shape[0]
     n_c = cells.shape[0]
     fv = cells[:, lf]                      # (n_c, nlf, nv)
@@ -145,6 +191,15 @@ def face_geometry(verts: np.ndarray, fverts: np.ndarray, n_gauss: int) -> FaceGe
         normal = np.stack([e[:, 1], -e[:, 0]], axis=1) / area[:, None]
         qpts = a[:, None, :] + t[None, :, None] * e[:, None, :]
         qw = np.broadcast_to(w, (P.shape[0], w.size)).copy()
+    elif P.shape[1] == 3:
+        x0, x1, x2 = P[:, 0], P[:, 1], P[:, 2]
+        S = 0.5 * np.cross(x1 - x0, x2 - x0)
+        area = np.sqrt(np.sum(S * S, axis=1))
+        normal = S / area[:, None]
+        a, wa = jacobi_01(n_gauss, 1)
+        A, B = (g.ravel() for g in np.meshgrid(a, t, indexing="ij"))
+        qpts = x0[:, None] + A[None, :, None] * ((x1 - x0)[:, None] + B[None, :, None] * (x2 - x1)[:, None])
+        qw = np.broadcast_to(2.0 * np.outer(wa, w).ravel(), (P.shape[0], A.size)).copy()
     else:
         x0, x1, x2, x3 = P[:, 0], P[:, 1], P[:, 2], P[:, 3]
         S = 0.5 * np.cross(x2 - x0, x3 - x1)

@@ -1,7 +1,11 @@
-// Mesh topology and geometry for straight-edged quads and trilinear hexahedra
-// (paper Sec. 3.1): face matching, owner/neighbour, outward unit normals and
-// areas from the exact vector area of each (bi)linear face, face and cell
-// Gauss-Legendre quadrature, cell volumes and centroids.
+// Mesh topology and geometry for straight-edged quads, trilinear hexahedra and
+// tetrahedra (paper Sec. 3.1): face matching, owner/neighbour, outward unit
+// normals and areas from the exact vector area of each (bi)linear or flat
+// face, face and cell quadrature, cell volumes and centroids.  Triangles and
+// tetrahedra take conical-product rules (Gauss-Jacobi nodes along the
+// collapsed directions, Gauss-Legendre along the last), generated here in
+// place of the paper's tabulated symmetric rules; with n points per direction
+// they are exact for polynomials of total degree 2n - 1.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -17,6 +21,53 @@ namespace {
 const int kQuadFace[4][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}};
 const int kHexFace[6][4] = {{0, 3, 2, 1}, {4, 5, 6, 7}, {0, 1, 5, 4},
                             {3, 7, 6, 2}, {0, 4, 7, 3}, {1, 2, 6, 5}};
+// tetrahedron with (x1 - x0) x (x2 - x0) . (x3 - x0) > 0
+const int kTetFace[4][3] = {{0, 2, 1}, {0, 1, 3}, {1, 2, 3}, {0, 3, 2}};
+
+// Gauss-Jacobi rule for the weight u^beta on [0,1] (weights sum to
+// 1 / (beta + 1)): the nodes are the eigenvalues of the Jacobi matrix of the
+// monic orthogonal polynomials (the alpha = 0 Jacobi recurrence mapped from
+// [-1,1]), found by Sturm-sequence bisection; the weights are the Christoffel
+// numbers 1 / sum_k phat_k(x)^2 of the orthonormal polynomials.
+void gauss_jacobi01(int n, int beta, std::vector<double>& x, std::vector<double>& w) {
+  std::vector<double> a(n), b(n, 0.0);  // b[k]: off-diagonal squared between k-1 and k
+  for (int k = 0; k < n; ++k) {
+    const double t = 2.0 * k + beta;
+    a[k] = 0.5 * ((double)beta * beta / (t * (t + 2.0)) + 1.0);
+    if (k > 0) b[k] = 0.25 * 4.0 * k * k * (k + beta) * (k + beta) / (t * t * (t + 1.0) * (t - 1.0));
+  }
+  auto below = [&](double y) {  // eigenvalues < y
+    int cnt = 0;
+    double q = a[0] - y;
+    if (q < 0) ++cnt;
+    for (int k = 1; k < n; ++k) {
+      if (q == 0.0) q = 1e-300;
+      q = (a[k] - y) - b[k] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const double mu0 = 1.0 / (beta + 1.0);
+  for (int i = 0; i < n; ++i) {
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 200 && hi - lo > 1e-17; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (below(mid) > i) hi = mid;
+      else lo = mid;
+    }
+    x[i] = 0.5 * (lo + hi);
+    double p0 = 1.0 / std::sqrt(mu0), pm = 0.0, s = p0 * p0;
+    for (int k = 0; k + 1 < n; ++k) {
+      const double pk = ((x[i] - a[k]) * p0 - (k > 0 ? std::sqrt(b[k]) * pm : 0.0)) / std::sqrt(b[k + 1]);
+      pm = p0;
+      p0 = pk;
+      s += p0 * p0;
+    }
+    w[i] = 1.0 / s;
+  }
+}
 
 // Gauss-Legendre nodes/weights on [0,1] by Newton iteration on P_n.
 void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
@@ -103,7 +154,9 @@ void quad_map(const double* X /*4x2*/, double r, double s, double* x, double* de
 
 hofv_status build_topology(hofv_ctx* c) {
   const int D = c->D;
-  const int nlf = D == 2 ? 4 : 6, nfv = D == 2 ? 2 : 4, ncv = D == 2 ? 4 : 8;
+  const bool tet = D == 3 && c->cells.size() == (size_t)c->nc * 4;
+  const int nlf = D == 2 ? 4 : (tet ? 4 : 6), nfv = D == 2 ? 2 : (tet ? 3 : 4), ncv = D == 2 ? 4 : (tet ? 4 : 8);
+  auto lface = [&](int sl, int k) { return D == 2 ? kQuadFace[sl][k] : (tet ? kTetFace[sl][k] : kHexFace[sl][k]); };
   struct Rec {
     std::array<int64_t, 4> key;
     int64_t cell;
@@ -116,7 +169,7 @@ hofv_status build_topology(hofv_ctx* c) {
     for (int s = 0; s < nlf; ++s) {
       Rec& r = recs[(size_t)e * nlf + s];
       r.key = {-1, -1, -1, -1};
-      for (int k = 0; k < nfv; ++k) r.key[k] = cv[D == 2 ? kQuadFace[s][k] : kHexFace[s][k]];
+      for (int k = 0; k < nfv; ++k) r.key[k] = cv[lface(s, k)];
       std::sort(r.key.begin(), r.key.begin() + nfv);
       r.cell = e;
       r.slot = s;
@@ -136,7 +189,7 @@ hofv_status build_topology(hofv_ctx* c) {
     f.own = recs[i].cell;
     f.sown = recs[i].slot;
     const int64_t* cv = &c->cells[(size_t)f.own * ncv];
-    for (int k = 0; k < nfv; ++k) f.v[k] = cv[D == 2 ? kQuadFace[f.sown][k] : kHexFace[f.sown][k]];
+    for (int k = 0; k < 4; ++k) f.v[k] = k < nfv ? cv[lface(f.sown, k)] : -1;
     if (j - i == 2) {
       f.nei = recs[i + 1].cell;
       f.snei = recs[i + 1].slot;
@@ -165,13 +218,18 @@ hofv_status build_topology(hofv_ctx* c) {
 hofv_status build_geometry(hofv_ctx* c) {
   const int D = c->D, p = c->prm.order_p, ng = c->prm.n_gauss;
   const int64_t nc = c->nc;
-  const int ncv = D == 2 ? 4 : 8;
+  const bool tet = D == 3 && c->cells.size() == (size_t)nc * 4;
+  const int ncv = D == 2 ? 4 : (tet ? 4 : 8);
   c->cen.assign((size_t)nc * D, 0.0);
   c->vol.assign(nc, 0.0);
   std::vector<double> g2x, g2w, gvx, gvw, gfx, gfw;
   gauss_legendre01(2, g2x, g2w);
   gauss_legendre01(p + 2, gvx, gvw);
   gauss_legendre01(ng, gfx, gfw);
+  std::vector<double> j1x, j1w, j2x, j2w, t1x, t1w;  // Gauss-Jacobi u^2, u (cells); u (faces)
+  gauss_jacobi01(p + 2, 2, j2x, j2w);
+  gauss_jacobi01(p + 2, 1, j1x, j1w);
+  gauss_jacobi01(ng, 1, t1x, t1w);
   const int nv1 = p + 2;
   c->nqv = D == 2 ? nv1 * nv1 : nv1 * nv1 * nv1;
   c->vq_pts.assign((size_t)nc * c->nqv * D, 0.0);
@@ -204,6 +262,31 @@ hofv_status build_geometry(hofv_ctx* c) {
           c->vq_pts[((size_t)e * c->nqv + q) * 2 + 1] = x[1];
           c->vq_w[(size_t)e * c->nqv + q] = gvw[i] * gvw[j] * dj;
         }
+    } else if (tet) {
+      // flat tetrahedron: Omega = det / 6, centroid = vertex mean; the volume
+      // rule maps (a, b, c) in [0,1]^3 to x0 + a (e1 + b (e2 + c e3)),
+      // e1 = x1 - x0, e2 = x2 - x1, e3 = x3 - x2, with det = 6 Omega a^2 b
+      double e1[3], e2[3], e3[3], f2[3], f3[3], cr[3];
+      for (int d = 0; d < 3; ++d) {
+        e1[d] = X[3 + d] - X[d];
+        e2[d] = X[6 + d] - X[3 + d];
+        e3[d] = X[9 + d] - X[6 + d];
+        f2[d] = X[6 + d] - X[d];
+        f3[d] = X[9 + d] - X[d];
+      }
+      cross3(e1, f2, cr);
+      const double det = cr[0] * f3[0] + cr[1] * f3[1] + cr[2] * f3[2];
+      c->vol[e] = det / 6.0;
+      for (int d = 0; d < 3; ++d) c->cen[3 * e + d] = 0.25 * (X[d] + X[3 + d] + X[6 + d] + X[9 + d]);
+      int q = 0;
+      for (int i = 0; i < nv1; ++i)
+        for (int j = 0; j < nv1; ++j)
+          for (int k = 0; k < nv1; ++k, ++q) {
+            const double a = j2x[i], b = j1x[j], cc = gvx[k];
+            for (int d = 0; d < 3; ++d)
+              c->vq_pts[((size_t)e * c->nqv + q) * 3 + d] = X[d] + a * (e1[d] + b * (e2[d] + cc * e3[d]));
+            c->vq_w[(size_t)e * c->nqv + q] = j2w[i] * j1w[j] * gvw[k] * det;
+          }
     } else {
       double V = 0, m[3] = {0, 0, 0};
       for (int i = 0; i < 2; ++i)
@@ -258,6 +341,29 @@ hofv_status build_geometry(hofv_ctx* c) {
         qp[2 * q + 1] = a[1] + gfx[q] * ey;
         qw[q] = gfw[q];
       }
+    } else if (F.v[3] < 0) {
+      // flat triangle: x0 + a (x1 - x0 + b (x2 - x1)), area element 2 A a
+      const double* x0 = &c->verts[(size_t)F.v[0] * 3];
+      const double* x1 = &c->verts[(size_t)F.v[1] * 3];
+      const double* x2 = &c->verts[(size_t)F.v[2] * 3];
+      double d10[3], d20[3], d21[3], Sv[3];
+      for (int d = 0; d < 3; ++d) {
+        d10[d] = x1[d] - x0[d];
+        d20[d] = x2[d] - x0[d];
+        d21[d] = x2[d] - x1[d];
+      }
+      cross3(d10, d20, Sv);
+      for (int d = 0; d < 3; ++d) Sv[d] *= 0.5;
+      const double A = std::sqrt(Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2]);
+      c->f_area[f] = A;
+      for (int d = 0; d < 3; ++d) c->f_normal[3 * f + d] = Sv[d] / A;
+      int q = 0;
+      for (int i = 0; i < ng; ++i)
+        for (int j = 0; j < ng; ++j, ++q) {
+          const double a = t1x[i], b = gfx[j];
+          for (int d = 0; d < 3; ++d) qp[3 * q + d] = x0[d] + a * (d10[d] + b * d21[d]);
+          qw[q] = 2.0 * t1w[i] * gfw[j];  // the weights of u on [0,1] sum to 1/2
+        }
     } else {
       const double* x0 = &c->verts[(size_t)F.v[0] * 3];
       const double* x1 = &c->verts[(size_t)F.v[1] * 3];

@@ -1,0 +1,129 @@
+"""GPU parity on tetrahedral meshes (hexes of a perturbed box, each split into
+six tetrahedra): residual, J.v, the neo-Hookean law, Newton against the
+oracle, and convergence under the manufactured solution."""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import jacobian as ojac
+from oracle import newton as onw
+from oracle import residual as ores
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _api():
+    from paper_2601_18417_amd import api
+    return api
+
+
+def to_dev(a):
+    return torch.tensor(np.ascontiguousarray(a.T), device=DEV, dtype=torch.float64)
+
+
+def to_host(t):
+    return t.cpu().numpy().T
+
+
+def _nh_beam():
+    prob = w.cantilever(shape=(6, 2, 2), p=1, n_plus=20)
+    m = prob.mesh
+    prob.mesh = w.tet_mesh(m.shape, lengths=m.lengths, origin=m.origin, perturb=0.1, seed=2)
+    return prob
+
+
+CASES = {
+    "tet3_p1": lambda: w.tet_mms(3, 1, perturb=0.2),
+    "tet3_p2": lambda: w.tet_mms(3, 2, perturb=0.2),
+    "tet4_p3": lambda: w.tet_mms(4, 3, perturb=0.2, seed=1),
+    "tet4_poly2": lambda: w.poly_patch(w.tet_mesh((4, 4, 4), perturb=0.2, seed=3), 2, 2, seed=5),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("fold", [True, False])
+def test_residual_parity_on_tets(name, fold):
+    prob = CASES[name]()
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob, fold_quadrature=fold)
+    n = disc.n_cells
+    for seed in (11, 12):
+        u = w.random_state(n, 3, seed=seed)
+        R = torch.empty((3, n), device=DEV, dtype=torch.float64)
+        ctx.residual(to_dev(u), R)
+        torch.cuda.synchronize()
+        Ro = ores.residual(disc, u)
+        assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro), (name, seed)
+    u = prob.loads.exact.value(disc.cen)
+    R = torch.empty((3, n), device=DEV, dtype=torch.float64)
+    ctx.residual(to_dev(u), R)
+    torch.cuda.synchronize()
+    Ff, Fd = ores.face_fluxes(disc, u)
+    scale = max(np.abs(Ff).max(), np.abs(Fd).max())
+    Ro = ores.residual(disc, u)
+    assert np.abs(to_host(R) - Ro).max() <= 1e-10 * scale
+    if name == "tet4_poly2":  # exact field of degree p: zero residual
+        assert np.abs(to_host(R)).max() <= 1e-11 * scale
+
+
+def test_jvp_parity_on_tets():
+    prob = w.tet_mms(4, 2, perturb=0.2)
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    u = w.random_state(n, 3, seed=1)
+    v = w.random_state(n, 3, seed=2, scale=1.0)
+    ud, vd = to_dev(u), to_dev(v)
+    R = torch.empty_like(ud)
+    Jv = torch.empty_like(ud)
+    ctx.residual(ud, R)
+    eps = ojac.default_eps(u, v)
+    ctx.jvp(ud, R, vd, Jv, eps=eps)
+    torch.cuda.synchronize()
+    Jo = ojac.jvp(disc, u, v, eps=eps)
+    assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
+
+
+def test_neo_hookean_residual_parity_on_tets():
+    prob = _nh_beam()
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    u = w.random_state(n, 3, seed=13, scale=1e-2)
+    R = torch.empty((3, n), device=DEV, dtype=torch.float64)
+    ctx.residual(to_dev(u), R)
+    torch.cuda.synchronize()
+    Ro = ores.residual(disc, u)
+    assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro)
+
+
+def test_newton_on_tets_matches_oracle():
+    prob = w.tet_mms(3, 2, perturb=0.2)
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    u = torch.zeros((3, n), device=DEV, dtype=torch.float64)
+    st = ctx.newton_solve(u, tol=1e-10, eta=1e-8, restart=60)
+    assert st["converged"]
+    uo, _ = onw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-8, m=60)
+    assert np.linalg.norm(to_host(u) - uo) <= 1e-7 * np.linalg.norm(uo)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_mms_error_falls_on_refined_tets(p):
+    """Regular tetrahedra (Kuhn split of a uniform grid): the centroid RMS
+    error falls at least linearly from 4^3 to 8^3 hexes' worth of tetrahedra."""
+    errs = []
+    for n in (4, 8):
+        prob = w.tet_mms(n, p, perturb=0.0)
+        ctx = _api().context_for(prob)
+        u = torch.zeros((3, prob.mesh.n_cells), device=DEV, dtype=torch.float64)
+        st = ctx.newton_solve(u, tol=1e-10, eta=1e-6, max_krylov=4000)
+        assert st["converged"]
+        ue = prob.loads.exact.value(ctx.cell_centroids())
+        errs.append(np.sqrt(np.mean(np.sum((to_host(u) - ue) ** 2, axis=1))))
+    slope = np.log(errs[0] / errs[1]) / np.log(2.0)
+    print(f"tets p={p} errors {errs} slope {slope:.2f}")
+    assert slope >= 1.0

@@ -25,7 +25,8 @@ def _tables(ctx, prob):
 CASES = [lambda: w.square_mms(8, 2, perturb=0.2), lambda: w.square_mms(7, 3),
          lambda: w.cube_mms(6, 3, perturb=0.2), lambda: w.cube_mms(6, 2),
          lambda: w.poly_patch(w.box_mesh((5, 6, 5), perturb=0.2, seed=2), 1, 1,
-                              traction_faces=lambda xc, n: xc[:, 1] > 1 - 1e-9)]
+                              traction_faces=lambda xc, n: xc[:, 1] > 1 - 1e-9),
+         lambda: w.tet_mms(3, 2, perturb=0.2), lambda: w.tet_mms(4, 3, perturb=0.2, seed=1)]
 
 
 @pytest.mark.parametrize("mk", CASES)
@@ -58,7 +59,7 @@ def test_stencils_and_face_coefficients_match_oracle(mk):
     assert np.array_equal(cst, np.sort(disc.c_st[order], axis=1))
 
 
-@pytest.mark.parametrize("mk", CASES[:3])
+@pytest.mark.parametrize("mk", CASES[:3] + CASES[-2:])
 def test_extrapolation_rows_match_oracle(mk):
     """u*_{f,P} - u_P from the library's pre-contracted rows equals the
     oracle's derivative tensors contracted with d (eq. alphaJump)."""
@@ -87,12 +88,13 @@ def test_extrapolation_rows_match_oracle(mk):
             assert np.allclose(lib, ref, rtol=1e-10, atol=1e-10 * np.abs(u).max()), (P, s)
 
 
-def test_sources_match_oracle_plus_boundary_constants():
+@pytest.mark.parametrize("mesh", [lambda: w.box_mesh((6, 5, 5), perturb=0.2, seed=3),
+                                  lambda: w.tet_mesh((4, 4, 4), perturb=0.2, seed=3)])
+def test_sources_match_oracle_plus_boundary_constants(mesh):
     """Cell sources = body force + traction faces + the u_b-dependent constants
     of displacement faces (ghost gradient term and u_b of the stabilisation),
     which the oracle carries inside its face fluxes: R_oracle(0) equals them."""
-    prob = w.poly_patch(w.box_mesh((6, 5, 5), perturb=0.2, seed=3), 2, 2, seed=2,
-                        traction_faces=lambda xc, n: xc[:, 0] > 1 - 1e-9)
+    prob = w.poly_patch(mesh(), 2, 2, seed=2, traction_faces=lambda xc, n: xc[:, 0] > 1 - 1e-9)
     disc = ores.build(prob)
     ctx = api.context_for(prob, host_only=True)
     n = disc.n_cells
@@ -101,8 +103,9 @@ def test_sources_match_oracle_plus_boundary_constants():
     assert np.abs(src - R0).max() <= 1e-11 * np.abs(R0).max()
 
 
-def test_preconditioner_tables_match_oracle():
-    prob = w.cube_mms(5, 1, perturb=0.2)
+@pytest.mark.parametrize("mk", [lambda: w.cube_mms(5, 1, perturb=0.2), lambda: w.tet_mms(3, 1, perturb=0.2)])
+def test_preconditioner_tables_match_oracle(mk):
+    prob = mk()
     disc = ores.build(prob)
     A = opc.assemble(disc).toarray()
     col = opc.greedy_colours(opc.assemble(disc))

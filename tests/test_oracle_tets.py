@@ -1,0 +1,105 @@
+"""Pins of the oracle on tetrahedral meshes (Sec. 3.1 geometry and quadrature
+on simplices; the paper's tetrahedral cases of Sec. 5)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import geometry as geo
+from oracle import residual as rs
+
+
+def _simplex_moment(e):
+    """Integral of prod x_i^e_i over the unit simplex: prod e_i! / (sum e + D)!."""
+    return math.prod(math.factorial(k) for k in e) / math.factorial(sum(e) + len(e))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_triangle_rule_degree(n):
+    """The n x n conical product on the triangle (0,0,0), (1,0,0), (0,1,0) is
+    exact for every monomial x^a y^b of degree <= 2n - 1 and not for all of
+    degree 2n."""
+    tri = np.array([[[0.0, 0, 0], [1.0, 0, 0], [0.0, 1, 0]]])
+    g = geo.face_geometry(tri[0], np.array([[0, 1, 2]]), n)
+    assert g.area[0] == pytest.approx(0.5)
+    assert np.allclose(g.normal[0], [0, 0, 1])
+    x, y = g.qpts[0, :, 0], g.qpts[0, :, 1]
+    for deg in range(2 * n + 1):
+        errs = []
+        for a in range(deg + 1):
+            q = g.area[0] * np.sum(g.qw[0] * x ** a * y ** (deg - a))
+            errs.append(abs(q - _simplex_moment((a, deg - a))))
+        if deg <= 2 * n - 1:
+            assert max(errs) <= 1e-15
+        else:
+            assert max(errs) > 1e-8
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_tet_rule_degree(n):
+    """The cell rule on the unit tetrahedron is exact to degree 2n - 1 and not
+    beyond; on a sheared tetrahedron it integrates 1 and x to volume and
+    volume times centroid."""
+    X = np.array([[[0.0, 0, 0], [1.0, 0, 0], [0.0, 1, 0], [0.0, 0, 1]]])
+    pts, W = geo.cell_quadrature(X, n)
+    for deg in range(2 * n + 1):
+        errs = []
+        for a in range(deg + 1):
+            for b in range(deg + 1 - a):
+                c = deg - a - b
+                q = np.sum(W[0] * pts[0, :, 0] ** a * pts[0, :, 1] ** b * pts[0, :, 2] ** c)
+                errs.append(abs(q - _simplex_moment((a, b, c))))
+        if deg <= 2 * n - 1:
+            assert max(errs) <= 1e-15
+        else:
+            assert max(errs) > 1e-9
+    Y = np.array([[[0.3, 0.1, 0], [2.0, 0.4, 0.2], [0.5, 1.7, 0.1], [0.2, 0.6, 1.4]]])
+    vol, cen = geo.cell_volume_centroid(Y)
+    pts, W = geo.cell_quadrature(Y, n)
+    det = np.linalg.det(np.stack([Y[0, 1] - Y[0, 0], Y[0, 2] - Y[0, 0], Y[0, 3] - Y[0, 0]]))
+    assert vol[0] == pytest.approx(det / 6.0, rel=1e-14)
+    assert W.sum() == pytest.approx(vol[0], rel=1e-14)
+    assert np.allclose(np.einsum("q,qd->d", W[0], pts[0]) / W.sum(), cen[0], rtol=1e-14)
+
+
+def test_tet_mesh_invariants():
+    """Kuhn split of a perturbed box: positive volumes summing to the box, each
+    cell's outward vector areas summing to zero, every interior triangle shared
+    by exactly two tetrahedra and the boundary made of 2 triangles per square."""
+    mesh = w.tet_mesh((4, 3, 5), lengths=(2.0, 1.0, 1.5), perturb=0.2, seed=7)
+    X = mesh.verts[mesh.cells]
+    vol, _ = geo.cell_volume_centroid(X)
+    assert vol.min() > 0 and vol.sum() == pytest.approx(3.0, rel=1e-13)
+    faces = geo.enumerate_faces(mesh.cells, 3)
+    g = geo.face_geometry(mesh.verts, faces.verts, 1)
+    S = g.normal * g.area[:, None]
+    net = np.zeros((mesh.n_cells, 3))
+    np.add.at(net, faces.owner, S)
+    inner = faces.neigh >= 0
+    np.add.at(net, faces.neigh[inner], -S[inner])
+    assert np.abs(net).max() <= 1e-14
+    assert np.count_nonzero(~inner) == 2 * 2 * (4 * 3 + 3 * 5 + 4 * 5)
+    assert mesh.n_cells == 6 * 60
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("perturb", [0.0, 0.2])
+def test_polynomial_fields_give_zero_residual_on_tets(p, perturb):
+    """Flat faces: the reconstruction reproduces degree-p fields and the face
+    and volume rules integrate their stress and body force exactly, so the
+    residual of the exact field vanishes on regular and irregular tetrahedra."""
+    prob = w.poly_patch(w.tet_mesh((4, 4, 4), perturb=perturb, seed=3), p, p, seed=5)
+    disc = rs.build(prob)
+    R = rs.residual(disc, prob.loads.exact.value(disc.cen))
+    Ff, Fd = rs.face_fluxes(disc, prob.loads.exact.value(disc.cen))
+    scale = max(np.abs(Ff).max(), np.abs(Fd).max())
+    assert np.abs(R).max() <= 1e-12 * scale
+
+
+def test_degree_above_p_leaves_a_residual_on_tets():
+    prob = w.poly_patch(w.tet_mesh((4, 4, 4), perturb=0.2, seed=3), 1, 2, seed=5)
+    disc = rs.build(prob)
+    R = rs.residual(disc, prob.loads.exact.value(disc.cen))
+    Ff, _ = rs.face_fluxes(disc, prob.loads.exact.value(disc.cen))
+    assert np.abs(R).max() > 1e-4 * np.abs(Ff).max()

@@ -21,7 +21,7 @@ import numpy as np
 
 from .fields import (Loads, cantilever_loads, lame_from_young, mms_2d_unit, mms_3d_trig, symmetric_poly_field,
                      mms_loads, random_poly_field)
-from .meshes import Mesh, box_mesh
+from .meshes import Mesh, box_mesh, tet_mesh
 
 LINEAR_ELASTIC, NEO_HOOKEAN = 0, 1
 
@@ -82,6 +82,19 @@ def cube_mms(n: int = 64, p: int = 3, perturb: float = 0.2, seed: int = 0,
     mesh = box_mesh(shape, lengths=lengths, perturb=perturb, seed=seed, mode=mode)
     mu, lam = lame_from_young(E, nu)
     return Problem(f"cube_mms_{'x'.join(map(str, shape))}_p{p}", mesh, p,
+                   PAPER_N_PLUS[3][p] if n_plus is None else n_plus,
+                   n_gauss or default_gauss(p), LINEAR_ELASTIC, mu, lam,
+                   mms_loads(mms_3d_trig(), mu, lam), stencil_quantum=quantum_for(mesh))
+
+
+def tet_mms(n: int = 16, p: int = 2, perturb: float = 0.2, seed: int = 0,
+            E: float = 1.0, nu: float = 0.3, n_plus=None, n_gauss=None, mode: str = "random") -> Problem:
+    """The 3D manufactured problem on a tetrahedral mesh: n^3 hexes of the unit
+    cube (perturbed as in cube_mms), each split into six tetrahedra."""
+    shape = (n, n, n) if np.isscalar(n) else tuple(n)
+    mesh = tet_mesh(shape, perturb=perturb, seed=seed, mode=mode)
+    mu, lam = lame_from_young(E, nu)
+    return Problem(f"tet_mms_{'x'.join(map(str, shape))}_p{p}", mesh, p,
                    PAPER_N_PLUS[3][p] if n_plus is None else n_plus,
                    n_gauss or default_gauss(p), LINEAR_ELASTIC, mu, lam,
                    mms_loads(mms_3d_trig(), mu, lam), stencil_quantum=quantum_for(mesh))

@@ -6,6 +6,7 @@ is a vertex array ``verts`` (n_verts, dim) float64 and a connectivity array
 
 * 2D quad:  0 (x0,y0), 1 (x1,y0), 2 (x1,y1), 3 (x0,y1)  -- counter-clockwise.
 * 3D hex:   0..3 as the quad on the bottom z-plane, 4..7 the same on the top.
+* 3D tet:   (n_cells, 4), positively oriented ((x1-x0) x (x2-x0) . (x3-x0) > 0).
 
 Cells and vertices are numbered lexicographically with i (x) fastest.
 
@@ -104,6 +105,29 @@ def box_mesh(shape, lengths=None, origin=None, perturb: float = 0.0,
                           vid(i, j, k + 1), vid(i + 1, j, k + 1), vid(i + 1, j + 1, k + 1), vid(i, j + 1, k + 1)], axis=1)
     cells = np.ascontiguousarray(cells, dtype=np.int64)
     return Mesh(dim, verts, cells, shape, lengths, origin)
+
+
+# Kuhn split of a hex (VTK numbering) into six tetrahedra along its 0-6
+# diagonal: one per ordering of the axes, the path 0 -> ... -> 6 stepping one
+# axis at a time.  Every hex of a structured grid splits the same way, so the
+# triangles of neighbouring hexes match.
+_KUHN = np.array([[0, 1, 2, 6], [0, 1, 5, 6], [0, 3, 2, 6], [0, 3, 7, 6], [0, 4, 5, 6], [0, 4, 7, 6]])
+
+
+def tet_mesh(shape, lengths=None, origin=None, perturb: float = 0.0, seed: int = 0,
+             mode: str = "random") -> Mesh:
+    """Tetrahedral mesh of a box: the structured hex mesh of ``box_mesh`` (same
+    vertices and perturbation) with every hex split into six tetrahedra, each
+    ordered for positive volume.  ``shape`` stays the hex grid's."""
+    hx = box_mesh(shape, lengths, origin, perturb, seed, mode)
+    if hx.dim != 3:
+        raise ValueError("tetrahedral meshes are 3D")
+    cells = hx.cells[:, _KUHN].reshape(-1, 4)
+    X = hx.verts[cells]
+    det = np.einsum("cd,cd->c", np.cross(X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]), X[:, 3] - X[:, 0])
+    neg = det < 0
+    cells[neg] = cells[neg][:, [0, 2, 1, 3]]
+    return Mesh(3, hx.verts, np.ascontiguousarray(cells, np.int64), hx.shape, hx.lengths, hx.origin)
 
 
 def cell_ijk(mesh: Mesh) -> np.ndarray:
