@@ -102,17 +102,18 @@ const char* hofv_last_error(const hofv_ctx* ctx);
 hofv_status hofv_set_mesh(hofv_ctx* ctx, int64_t n_verts, const double* verts,
                           int64_t n_cells, const int64_t* cell_verts);
 
-/* Tetrahedral mesh (Sec. 3.1; the paper's tetrahedral cases of Sec. 5), dim = 3
- * only: cell_verts [n_cells][4] int64 with positive orientation,
- * (x1 - x0) x (x2 - x0) . (x3 - x0) > 0 (HOFV_EINVAL from setup of the
- * geometry otherwise).  Faces are flat triangles matched by vertex sets; face
- * and volume quadrature are conical-product Gauss-Jacobi/Gauss-Legendre rules
- * with n_gauss^2 points per face and (order_p + 2)^3 per cell, exact for
- * polynomials of total degree 2 n_gauss - 1 and 2 order_p + 3.  Everything
- * after the mesh (stencils, tables, kernels, solvers) is the same as for
- * hexahedra.  Called instead of hofv_set_mesh, once. */
-hofv_status hofv_set_mesh_tets(hofv_ctx* ctx, int64_t n_verts, const double* verts, int64_t n_cells,
-                               const int64_t* cell_verts);
+/* Simplex mesh (Sec. 3.1; the paper's triangular and tetrahedral cases of
+ * Sec. 5): cell_verts [n_cells][dim + 1] int64, triangles counter-clockwise,
+ * tetrahedra with (x1 - x0) x (x2 - x0) . (x3 - x0) > 0 (HOFV_EINVAL from the
+ * geometry stage otherwise).  Faces (edges in 2D, flat triangles in 3D) are
+ * matched by vertex sets; a triangle face has n_gauss^2 quadrature points, an
+ * edge n_gauss, a cell (order_p + 2)^dim, from conical-product
+ * Gauss-Jacobi/Gauss-Legendre rules exact for total degree 2 n - 1 with n
+ * points per direction.  Everything after the mesh (stencils, tables,
+ * kernels, solvers) is the same as for quads and hexahedra.  Called instead
+ * of hofv_set_mesh, once. */
+hofv_status hofv_set_mesh_simplices(hofv_ctx* ctx, int64_t n_verts, const double* verts, int64_t n_cells,
+                                    const int64_t* cell_verts);
 
 /* Boundary faces in the library's order, so that the caller can evaluate its
  * boundary conditions there: face centres x_b [n][dim], unit outward normals

@@ -1,5 +1,5 @@
-"""Mesh geometry for straight-edged quads (2D), trilinear hexahedra and
-tetrahedra (3D).
+"""Mesh geometry for straight-edged quads and triangles (2D), trilinear
+hexahedra and tetrahedra (3D).
 
 Test infrastructure (see package docstring).  Follows Sec. 3.1 of the paper
 ("Solution Domain Discretisation"): cell centroid x_P and volume Omega_P, face
@@ -29,6 +29,9 @@ Readings where the paper is silent for these element shapes:
   Gauss-Jacobi points of weights a^2 and b, Gauss-Legendre in c, p + 2 each.
   With n points per direction these conical products are exact for total
   degree 2n - 1.
+* Triangles (2D): Omega_P = det / 2, x_P the vertex mean, and the cell rule
+  through x0 + a (x1 - x0 + b (x2 - x1)) (detJ = 2 Omega a): Gauss-Jacobi in a,
+  Gauss-Legendre in b.
 """
 from __future__ import annotations
 
@@ -45,6 +48,8 @@ QUAD_REF = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float)
 # the face opposite each vertex, ordered for the outward normal of a tetrahedron
 # with (x1 - x0) x (x2 - x0) . (x3 - x0) > 0
 TET_FACES = np.array([[1, 2, 3], [0, 3, 2], [0, 1, 3], [0, 2, 1]])
+# edges of a counter-clockwise triangle, opposite vertices 2, 0, 1
+TRI_FACES = np.array([[0, 1], [1, 2], [2, 0]])
 HEX_REF = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
                     [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]], float)
 
@@ -64,6 +69,24 @@ def jacobi_01(n: int, beta: int):
 
 def is_tet(X: np.ndarray) -> bool:
     return X.shape[-1] == 3 and X.shape[-2] == 4
+
+
+def is_tri(X: np.ndarray) -> bool:
+    return X.shape[-1] == 2 and X.shape[-2] == 3
+
+
+def tri_quadrature(X: np.ndarray, n: int):
+    """Conical-product rule on triangles X (n_c, 3, 2): points (n_c, n^2, 2),
+    weights (n_c, n^2) integrating over the physical cell."""
+    a, wa = jacobi_01(n, 1)
+    b, wb = gauss_01(n)
+    A, B = (g.ravel() for g in np.meshgrid(a, b, indexing="ij"))
+    W = np.outer(wa, wb).ravel()
+    x0, x1, x2 = X[:, 0], X[:, 1], X[:, 2]
+    pts = x0[:, None] + A[None, :, None] * ((x1 - x0)[:, None] + B[None, :, None] * (x2 - x1)[:, None])
+    e1, e2 = x1 - x0, x2 - x0
+    det = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]
+    return pts, W[None, :] * det[:, None]
 
 
 def tet_quadrature(X: np.ndarray, n: int):
@@ -105,6 +128,8 @@ def cell_quadrature(X: np.ndarray, n: int):
     """
     if is_tet(X):
         return tet_quadrature(X, n)
+    if is_tri(X):
+        return tri_quadrature(X, n)
     D = X.shape[2]
     ref = QUAD_REF if D == 2 else HEX_REF
     t, w = gauss_01(n)
@@ -123,6 +148,9 @@ def cell_volume_centroid(X: np.ndarray):
     if is_tet(X):
         det = np.einsum("cd,cd->c", np.cross(X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]), X[:, 3] - X[:, 0])
         return det / 6.0, X.mean(axis=1)
+    if is_tri(X):
+        e1, e2 = X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]
+        return 0.5 * (e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]), X.mean(axis=1)
     pts, W = cell_quadrature(X, 2)
     vol = W.sum(axis=1)
     cen = np.einsum("cq,cqd->cd", W, pts) / vol[:, None]
@@ -145,7 +173,10 @@ def enumerate_faces(cells: np.ndarray, dim: int) -> Faces:
     The owner is the lower cell id (its copy appears first), the neighbour the
     other one; a face seen once is a boundary face.
     """
-    lf = QUAD_FACES if dim == 2 else (TET_FACES if cells.shape[1] == 4 else HEX_FACES)
+    if cells.shape[1] == dim + 1:
+        lf = TRI_FACES if dim == 2 else TET_FACES
+    else:
+        lf = QUAD_FACES if dim == 2 else HEX_FACES
     nlf = lf.shape[0]
     n_c = cells.shape[0]
     fv = cells[:, lf]                      # (n_c, nlf, nv)

@@ -78,8 +78,8 @@ class Context:
     def set_mesh(self, verts, cells):
         verts = np.ascontiguousarray(verts, np.float64)
         cells = np.ascontiguousarray(cells, np.int64)
-        # a 3D mesh of 4-vertex cells is tetrahedral
-        fn = self.lib.hofv_set_mesh_tets if verts.shape[1] == 3 and cells.shape[1] == 4 else self.lib.hofv_set_mesh
+        # cells of dim + 1 vertices are triangles or tetrahedra
+        fn = self.lib.hofv_set_mesh_simplices if cells.shape[1] == verts.shape[1] + 1 else self.lib.hofv_set_mesh
         self._check(fn(self.h, verts.shape[0], _dptr(verts), cells.shape[0],
                        cells.ctypes.data_as(C.POINTER(C.c_int64))))
         self.n_cells = cells.shape[0]

@@ -133,17 +133,17 @@ hofv_status hofv_set_mesh(hofv_ctx* c, int64_t n_verts, const double* verts, int
   return HOFV_OK;
 }
 
-hofv_status hofv_set_mesh_tets(hofv_ctx* c, int64_t n_verts, const double* verts, int64_t n_cells,
-                               const int64_t* cell_verts) {
+hofv_status hofv_set_mesh_simplices(hofv_ctx* c, int64_t n_verts, const double* verts, int64_t n_cells,
+                                    const int64_t* cell_verts) {
   if (!c) return fail(nullptr, HOFV_EINVAL, "null context");
   if (c->state != 0) return fail(c, HOFV_ESTATE, "set_mesh may be called once");
-  if (c->D != 3) return fail(c, HOFV_EINVAL, "tetrahedral meshes need dim = 3");
   if (n_verts <= 0 || n_cells <= 0 || !verts || !cell_verts) return fail(c, HOFV_EINVAL, "empty mesh");
   if (n_cells >= INT32_MAX / 8) return fail(c, HOFV_EINVAL, "too many cells for 32-bit indices");
+  const int D = c->D;
   c->nv = n_verts;
   c->nc = n_cells;
-  c->verts.assign(verts, verts + n_verts * 3);
-  c->cells.assign(cell_verts, cell_verts + n_cells * 4);
+  c->verts.assign(verts, verts + n_verts * D);
+  c->cells.assign(cell_verts, cell_verts + n_cells * (D + 1));
   for (int64_t v : c->cells)
     if (v < 0 || v >= n_verts) return fail(c, HOFV_EINVAL, "cell vertex index out of range");
   hofv_status s;

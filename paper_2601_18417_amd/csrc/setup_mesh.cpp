@@ -1,5 +1,5 @@
-// Mesh topology and geometry for straight-edged quads, trilinear hexahedra and
-// tetrahedra (paper Sec. 3.1): face matching, owner/neighbour, outward unit
+// Mesh topology and geometry for straight-edged quads and triangles, trilinear
+// hexahedra and tetrahedra (paper Sec. 3.1): face matching, owner/neighbour, outward unit
 // normals and areas from the exact vector area of each (bi)linear or flat
 // face, face and cell quadrature, cell volumes and centroids.  Triangles and
 // tetrahedra take conical-product rules (Gauss-Jacobi nodes along the
@@ -19,6 +19,7 @@ namespace {
 
 // library-local face tables: vertex cycles whose right-hand normal points out
 const int kQuadFace[4][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}};
+const int kTriFace[3][2] = {{0, 1}, {1, 2}, {2, 0}};  // counter-clockwise triangle
 const int kHexFace[6][4] = {{0, 3, 2, 1}, {4, 5, 6, 7}, {0, 1, 5, 4},
                             {3, 7, 6, 2}, {0, 4, 7, 3}, {1, 2, 6, 5}};
 // tetrahedron with (x1 - x0) x (x2 - x0) . (x3 - x0) > 0
@@ -154,9 +155,12 @@ void quad_map(const double* X /*4x2*/, double r, double s, double* x, double* de
 
 hofv_status build_topology(hofv_ctx* c) {
   const int D = c->D;
-  const bool tet = D == 3 && c->cells.size() == (size_t)c->nc * 4;
-  const int nlf = D == 2 ? 4 : (tet ? 4 : 6), nfv = D == 2 ? 2 : (tet ? 3 : 4), ncv = D == 2 ? 4 : (tet ? 4 : 8);
-  auto lface = [&](int sl, int k) { return D == 2 ? kQuadFace[sl][k] : (tet ? kTetFace[sl][k] : kHexFace[sl][k]); };
+  const bool simplex = c->cells.size() == (size_t)c->nc * (D + 1);
+  const int ncv = simplex ? D + 1 : (D == 2 ? 4 : 8), nlf = simplex ? D + 1 : 2 * D, nfv = D == 2 ? 2 : (simplex ? 3 : 4);
+  auto lface = [&](int sl, int k) {
+    if (D == 2) return simplex ? kTriFace[sl][k] : kQuadFace[sl][k];
+    return simplex ? kTetFace[sl][k] : kHexFace[sl][k];
+  };
   struct Rec {
     std::array<int64_t, 4> key;
     int64_t cell;
@@ -218,8 +222,8 @@ hofv_status build_topology(hofv_ctx* c) {
 hofv_status build_geometry(hofv_ctx* c) {
   const int D = c->D, p = c->prm.order_p, ng = c->prm.n_gauss;
   const int64_t nc = c->nc;
-  const bool tet = D == 3 && c->cells.size() == (size_t)nc * 4;
-  const int ncv = D == 2 ? 4 : (tet ? 4 : 8);
+  const bool simplex = c->cells.size() == (size_t)nc * (D + 1), tet = simplex && D == 3;
+  const int ncv = simplex ? D + 1 : (D == 2 ? 4 : 8);
   c->cen.assign((size_t)nc * D, 0.0);
   c->vol.assign(nc, 0.0);
   std::vector<double> g2x, g2w, gvx, gvw, gfx, gfw;
@@ -241,10 +245,10 @@ hofv_status build_geometry(hofv_ctx* c) {
     for (int a = 0; a < ncv; ++a)
       for (int d = 0; d < D; ++d) X[D * a + d] = c->verts[(size_t)c->cells[(size_t)e * ncv + a] * D + d];
     if (D == 2) {
-      // polygon (shoelace) area and centroid of the straight-edged quad
+      // polygon (shoelace) area and centroid of the straight-edged quad or triangle
       double A2 = 0, cx = 0, cy = 0;
-      for (int a = 0; a < 4; ++a) {
-        int b = (a + 1) % 4;
+      for (int a = 0; a < ncv; ++a) {
+        int b = (a + 1) % ncv;
         double cr = X[2 * a] * X[2 * b + 1] - X[2 * b] * X[2 * a + 1];
         A2 += cr;
         cx += (X[2 * a] + X[2 * b]) * cr;
@@ -256,11 +260,16 @@ hofv_status build_geometry(hofv_ctx* c) {
       int q = 0;
       for (int i = 0; i < nv1; ++i)
         for (int j = 0; j < nv1; ++j, ++q) {
-          double x[2], dj;
-          quad_map(X, gvx[i], gvx[j], x, &dj);
-          c->vq_pts[((size_t)e * c->nqv + q) * 2] = x[0];
-          c->vq_pts[((size_t)e * c->nqv + q) * 2 + 1] = x[1];
-          c->vq_w[(size_t)e * c->nqv + q] = gvw[i] * gvw[j] * dj;
+          double* xq = &c->vq_pts[((size_t)e * c->nqv + q) * 2];
+          if (simplex) {  // x0 + a (x1 - x0 + b (x2 - x1)), detJ = 2 Omega a
+            const double a = j1x[i], b = gvx[j];
+            for (int d = 0; d < 2; ++d) xq[d] = X[d] + a * (X[2 + d] - X[d] + b * (X[4 + d] - X[2 + d]));
+            c->vq_w[(size_t)e * c->nqv + q] = j1w[i] * gvw[j] * A2;
+          } else {
+            double dj;
+            quad_map(X, gvx[i], gvx[j], xq, &dj);
+            c->vq_w[(size_t)e * c->nqv + q] = gvw[i] * gvw[j] * dj;
+          }
         }
     } else if (tet) {
       // flat tetrahedron: Omega = det / 6, centroid = vertex mean; the volume

@@ -1,6 +1,7 @@
-"""GPU parity on tetrahedral meshes (hexes of a perturbed box, each split into
-six tetrahedra): residual, J.v, the neo-Hookean law, Newton against the
-oracle, and convergence under the manufactured solution."""
+"""GPU parity on simplex meshes (quads of a perturbed rectangle split into two
+triangles, hexes of a perturbed box into six tetrahedra): residual, J.v, the
+neo-Hookean law, Newton against the oracle, and convergence under the
+manufactured solution."""
 import numpy as np
 import pytest
 
@@ -39,32 +40,35 @@ CASES = {
     "tet3_p2": lambda: w.tet_mms(3, 2, perturb=0.2),
     "tet4_p3": lambda: w.tet_mms(4, 3, perturb=0.2, seed=1),
     "tet4_poly2": lambda: w.poly_patch(w.tet_mesh((4, 4, 4), perturb=0.2, seed=3), 2, 2, seed=5),
+    "tri6_p1": lambda: w.tri_mms(6, 1, perturb=0.2),
+    "tri8_p3": lambda: w.tri_mms(8, 3, perturb=0.2),
+    "tri8_poly2": lambda: w.poly_patch(w.tri_mesh((8, 8), perturb=0.2, seed=3), 2, 2, seed=5),
 }
 
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("fold", [True, False])
-def test_residual_parity_on_tets(name, fold):
+def test_residual_parity_on_simplices(name, fold):
     prob = CASES[name]()
     disc = ores.build(prob)
     ctx = _api().context_for(prob, fold_quadrature=fold)
-    n = disc.n_cells
+    n, D = disc.n_cells, disc.dim
     for seed in (11, 12):
-        u = w.random_state(n, 3, seed=seed)
-        R = torch.empty((3, n), device=DEV, dtype=torch.float64)
+        u = w.random_state(n, D, seed=seed)
+        R = torch.empty((D, n), device=DEV, dtype=torch.float64)
         ctx.residual(to_dev(u), R)
         torch.cuda.synchronize()
         Ro = ores.residual(disc, u)
         assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro), (name, seed)
     u = prob.loads.exact.value(disc.cen)
-    R = torch.empty((3, n), device=DEV, dtype=torch.float64)
+    R = torch.empty((D, n), device=DEV, dtype=torch.float64)
     ctx.residual(to_dev(u), R)
     torch.cuda.synchronize()
     Ff, Fd = ores.face_fluxes(disc, u)
     scale = max(np.abs(Ff).max(), np.abs(Fd).max())
     Ro = ores.residual(disc, u)
     assert np.abs(to_host(R) - Ro).max() <= 1e-10 * scale
-    if name == "tet4_poly2":  # exact field of degree p: zero residual
+    if "poly" in name:  # exact field of degree p: zero residual
         assert np.abs(to_host(R)).max() <= 1e-11 * scale
 
 
@@ -99,31 +103,33 @@ def test_neo_hookean_residual_parity_on_tets():
     assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro)
 
 
-def test_newton_on_tets_matches_oracle():
-    prob = w.tet_mms(3, 2, perturb=0.2)
+@pytest.mark.parametrize("mk", [lambda: w.tet_mms(3, 2, perturb=0.2), lambda: w.tri_mms(8, 2, perturb=0.2)])
+def test_newton_on_simplices_matches_oracle(mk):
+    prob = mk()
     disc = ores.build(prob)
     ctx = _api().context_for(prob)
-    n = disc.n_cells
-    u = torch.zeros((3, n), device=DEV, dtype=torch.float64)
+    n, D = disc.n_cells, disc.dim
+    u = torch.zeros((D, n), device=DEV, dtype=torch.float64)
     st = ctx.newton_solve(u, tol=1e-10, eta=1e-8, restart=60)
     assert st["converged"]
-    uo, _ = onw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-8, m=60)
+    uo, _ = onw.newton(disc, np.zeros((n, D)), tol=1e-10, eta=1e-8, m=60)
     assert np.linalg.norm(to_host(u) - uo) <= 1e-7 * np.linalg.norm(uo)
 
 
-@pytest.mark.parametrize("p", [1, 2])
-def test_mms_error_falls_on_refined_tets(p):
-    """Regular tetrahedra (Kuhn split of a uniform grid): the centroid RMS
-    error falls at least linearly from 4^3 to 8^3 hexes' worth of tetrahedra."""
+@pytest.mark.parametrize("kind,p,sizes", [("tet", 1, (4, 8)), ("tet", 2, (4, 8)), ("tri", 1, (8, 16)),
+                                          ("tri", 2, (8, 16)), ("tri", 3, (8, 16))])
+def test_mms_error_falls_on_refined_simplices(kind, p, sizes):
+    """Regular simplices (the split of a uniform grid): the centroid RMS error
+    falls at least linearly when the grid is refined twice over."""
     errs = []
-    for n in (4, 8):
-        prob = w.tet_mms(n, p, perturb=0.0)
+    for n in sizes:
+        prob = (w.tet_mms if kind == "tet" else w.tri_mms)(n, p, perturb=0.0)
         ctx = _api().context_for(prob)
-        u = torch.zeros((3, prob.mesh.n_cells), device=DEV, dtype=torch.float64)
+        u = torch.zeros((prob.dim, prob.mesh.n_cells), device=DEV, dtype=torch.float64)
         st = ctx.newton_solve(u, tol=1e-10, eta=1e-6, max_krylov=4000)
         assert st["converged"]
         ue = prob.loads.exact.value(ctx.cell_centroids())
         errs.append(np.sqrt(np.mean(np.sum((to_host(u) - ue) ** 2, axis=1))))
     slope = np.log(errs[0] / errs[1]) / np.log(2.0)
-    print(f"tets p={p} errors {errs} slope {slope:.2f}")
+    print(f"{kind} p={p} errors {errs} slope {slope:.2f}")
     assert slope >= 1.0

@@ -26,6 +26,7 @@ CASES = [lambda: w.square_mms(8, 2, perturb=0.2), lambda: w.square_mms(7, 3),
          lambda: w.cube_mms(6, 3, perturb=0.2), lambda: w.cube_mms(6, 2),
          lambda: w.poly_patch(w.box_mesh((5, 6, 5), perturb=0.2, seed=2), 1, 1,
                               traction_faces=lambda xc, n: xc[:, 1] > 1 - 1e-9),
+         lambda: w.tri_mms(6, 3, perturb=0.2),
          lambda: w.tet_mms(3, 2, perturb=0.2), lambda: w.tet_mms(4, 3, perturb=0.2, seed=1)]
 
 
@@ -59,7 +60,7 @@ def test_stencils_and_face_coefficients_match_oracle(mk):
     assert np.array_equal(cst, np.sort(disc.c_st[order], axis=1))
 
 
-@pytest.mark.parametrize("mk", CASES[:3] + CASES[-2:])
+@pytest.mark.parametrize("mk", CASES[:3] + CASES[-3:])
 def test_extrapolation_rows_match_oracle(mk):
     """u*_{f,P} - u_P from the library's pre-contracted rows equals the
     oracle's derivative tensors contracted with d (eq. alphaJump)."""

@@ -1,5 +1,6 @@
-"""Pins of the oracle on tetrahedral meshes (Sec. 3.1 geometry and quadrature
-on simplices; the paper's tetrahedral cases of Sec. 5)."""
+"""Pins of the oracle on triangular and tetrahedral meshes (Sec. 3.1 geometry
+and quadrature on simplices; the paper's triangular and tetrahedral cases of
+Sec. 5)."""
 import math
 
 import numpy as np
@@ -34,6 +35,28 @@ def test_triangle_rule_degree(n):
             assert max(errs) <= 1e-15
         else:
             assert max(errs) > 1e-8
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_triangle_cell_rule_degree(n):
+    """The 2D cell rule on the unit triangle is exact to degree 2n - 1 and not
+    beyond; a sheared triangle gets its determinant area and vertex-mean
+    centroid."""
+    X = np.array([[[0.0, 0], [1.0, 0], [0.0, 1]]])
+    pts, W = geo.cell_quadrature(X, n)
+    for deg in range(2 * n + 1):
+        errs = [abs(np.sum(W[0] * pts[0, :, 0] ** a * pts[0, :, 1] ** (deg - a)) - _simplex_moment((a, deg - a)))
+                for a in range(deg + 1)]
+        if deg <= 2 * n - 1:
+            assert max(errs) <= 1e-15
+        else:
+            assert max(errs) > 1e-9
+    Y = np.array([[[0.3, 0.1], [2.0, 0.4], [0.5, 1.7]]])
+    vol, cen = geo.cell_volume_centroid(Y)
+    pts, W = geo.cell_quadrature(Y, n)
+    assert vol[0] == pytest.approx(0.5 * np.linalg.det(np.stack([Y[0, 1] - Y[0, 0], Y[0, 2] - Y[0, 0]])), rel=1e-14)
+    assert W.sum() == pytest.approx(vol[0], rel=1e-14)
+    assert np.allclose(np.einsum("q,qd->d", W[0], pts[0]) / W.sum(), cen[0], rtol=1e-14)
 
 
 @pytest.mark.parametrize("n", [2, 3, 4])
@@ -81,6 +104,33 @@ def test_tet_mesh_invariants():
     assert np.abs(net).max() <= 1e-14
     assert np.count_nonzero(~inner) == 2 * 2 * (4 * 3 + 3 * 5 + 4 * 5)
     assert mesh.n_cells == 6 * 60
+
+
+def test_tri_mesh_invariants():
+    mesh = w.tri_mesh((5, 4), lengths=(2.0, 1.0), perturb=0.2, seed=7)
+    X = mesh.verts[mesh.cells]
+    vol, _ = geo.cell_volume_centroid(X)
+    assert vol.min() > 0 and vol.sum() == pytest.approx(2.0, rel=1e-13)
+    faces = geo.enumerate_faces(mesh.cells, 2)
+    g = geo.face_geometry(mesh.verts, faces.verts, 1)
+    S = g.normal * g.area[:, None]
+    net = np.zeros((mesh.n_cells, 2))
+    np.add.at(net, faces.owner, S)
+    inner = faces.neigh >= 0
+    np.add.at(net, faces.neigh[inner], -S[inner])
+    assert np.abs(net).max() <= 1e-14
+    assert np.count_nonzero(~inner) == 2 * (5 + 4)
+    assert mesh.n_cells == 2 * 20
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("perturb", [0.0, 0.2])
+def test_polynomial_fields_give_zero_residual_on_triangles(p, perturb):
+    prob = w.poly_patch(w.tri_mesh((8, 8), perturb=perturb, seed=3), p, p, seed=5)
+    disc = rs.build(prob)
+    R = rs.residual(disc, prob.loads.exact.value(disc.cen))
+    Ff, Fd = rs.face_fluxes(disc, prob.loads.exact.value(disc.cen))
+    assert np.abs(R).max() <= 1e-12 * max(np.abs(Ff).max(), np.abs(Fd).max())
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])

@@ -21,7 +21,7 @@ import numpy as np
 
 from .fields import (Loads, cantilever_loads, lame_from_young, mms_2d_unit, mms_3d_trig, symmetric_poly_field,
                      mms_loads, random_poly_field)
-from .meshes import Mesh, box_mesh, tet_mesh
+from .meshes import Mesh, box_mesh, tet_mesh, tri_mesh
 
 LINEAR_ELASTIC, NEO_HOOKEAN = 0, 1
 
@@ -85,6 +85,17 @@ def cube_mms(n: int = 64, p: int = 3, perturb: float = 0.2, seed: int = 0,
                    PAPER_N_PLUS[3][p] if n_plus is None else n_plus,
                    n_gauss or default_gauss(p), LINEAR_ELASTIC, mu, lam,
                    mms_loads(mms_3d_trig(), mu, lam), stencil_quantum=quantum_for(mesh))
+
+
+def tri_mms(n: int = 16, p: int = 2, perturb: float = 0.2, seed: int = 0,
+            E: float = 1.0, nu: float = 0.3, n_plus=None, n_gauss=None) -> Problem:
+    """The 2D manufactured problem of square_mms on n x n quads of the unit
+    square (perturbed as there), each split into two triangles."""
+    mesh = tri_mesh((n, n), perturb=perturb, seed=seed)
+    mu, lam = lame_from_young(E, nu)
+    return Problem(f"tri_mms_{n}_p{p}", mesh, p, PAPER_N_PLUS[2][p] if n_plus is None else n_plus,
+                   n_gauss or default_gauss(p), LINEAR_ELASTIC, mu, lam,
+                   mms_loads(mms_2d_unit(), mu, lam), stencil_quantum=quantum_for(mesh))
 
 
 def tet_mms(n: int = 16, p: int = 2, perturb: float = 0.2, seed: int = 0,

@@ -7,6 +7,7 @@ is a vertex array ``verts`` (n_verts, dim) float64 and a connectivity array
 * 2D quad:  0 (x0,y0), 1 (x1,y0), 2 (x1,y1), 3 (x0,y1)  -- counter-clockwise.
 * 3D hex:   0..3 as the quad on the bottom z-plane, 4..7 the same on the top.
 * 3D tet:   (n_cells, 4), positively oriented ((x1-x0) x (x2-x0) . (x3-x0) > 0).
+* 2D tri:   (n_cells, 3), counter-clockwise.
 
 Cells and vertices are numbered lexicographically with i (x) fastest.
 
@@ -128,6 +129,22 @@ def tet_mesh(shape, lengths=None, origin=None, perturb: float = 0.0, seed: int =
     neg = det < 0
     cells[neg] = cells[neg][:, [0, 2, 1, 3]]
     return Mesh(3, hx.verts, np.ascontiguousarray(cells, np.int64), hx.shape, hx.lengths, hx.origin)
+
+
+def tri_mesh(shape, lengths=None, origin=None, perturb: float = 0.0, seed: int = 0,
+             mode: str = "random") -> Mesh:
+    """Triangular mesh of a rectangle: the structured quad mesh of ``box_mesh``
+    (same vertices and perturbation) with every quad split along its 0-2
+    diagonal, each triangle ordered counter-clockwise."""
+    q = box_mesh(shape, lengths, origin, perturb, seed, mode)
+    if q.dim != 2:
+        raise ValueError("triangular meshes are 2D")
+    cells = q.cells[:, [[0, 1, 2], [0, 2, 3]]].reshape(-1, 3)
+    X = q.verts[cells]
+    e1, e2 = X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]
+    neg = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0] < 0
+    cells[neg] = cells[neg][:, [0, 2, 1]]
+    return Mesh(2, q.verts, np.ascontiguousarray(cells, np.int64), q.shape, q.lengths, q.origin)
 
 
 def cell_ijk(mesh: Mesh) -> np.ndarray:
