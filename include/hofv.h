@@ -61,7 +61,7 @@ enum { HOFV_BC_DISPLACEMENT = 0, HOFV_BC_TRACTION = 1, HOFV_BC_SYMMETRY = 2 };
 
 /* Discretisation parameters (paper Secs. 3.4-3.5). */
 typedef struct {
-  int32_t dim;            /* 2 (plane strain, quads) or 3 (hexahedra) */
+  int32_t dim;            /* 2 (plane strain: quads, triangles) or 3 (hexahedra, tetrahedra) */
   int32_t order_p;        /* reconstruction order p = 1, 2, 3 (2nd/3rd/4th order) */
   int32_t n_plus;         /* surplus stencil nodes n+, |S| = N_t + n+ (Sec. 3.5.2) */
   int32_t n_gauss;        /* Gauss-Legendre points per face direction */
@@ -85,6 +85,16 @@ typedef struct {
                              V-cycle of at most that many levels whose finest
                              smoother is those sweeps (n_sweeps damped Jacobi
                              steps on coarser levels, exact coarsest solve) */
+  int32_t face_rule;      /* quadrature of hexahedral (quadrilateral) faces,
+                             Sec. 3.1: 0: n_gauss x n_gauss Gauss-Legendre points
+                             of the bilinear face; 1: fan triangulation from the
+                             face's lowest-numbered vertex into two triangles with the
+                             simplex rule on each (2 n_gauss^2 points), each
+                             triangle's weights scaled by its area over the sum of
+                             the two areas.  Area and normal come from the face's
+                             vector area either way.  1 needs the linear elastic
+                             law with fold_quadrature = 1 (HOFV_EINVAL otherwise);
+                             triangle faces and 2D edges ignore it. */
 } hofv_params;
 
 /* Creates a context on the current HIP device.  *out is NULL on failure. */

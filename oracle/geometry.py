@@ -29,6 +29,12 @@ Readings where the paper is silent for these element shapes:
   Gauss-Jacobi points of weights a^2 and b, Gauss-Legendre in c, p + 2 each.
   With n points per direction these conical products are exact for total
   degree 2n - 1.
+* Fan rule for quadrilateral faces (Sec. 3.1 subdivides polygonal faces by
+  fan triangulation): the fan starts at the face's lowest-numbered vertex y0,
+  keeping the cyclic order, giving triangles (y0, y1, y2) and (y0, y2, y3);
+  each gets the triangle rule above, its weights scaled by its area over the
+  sum of both areas (the paper's consistent face area).  The face's area and
+  normal still come from its vector area.
 * Triangles (2D): Omega_P = det / 2, x_P the vertex mean, and the cell rule
   through x0 + a (x1 - x0 + b (x2 - x1)) (detJ = 2 Omega a): Gauss-Jacobi in a,
   Gauss-Legendre in b.
@@ -211,7 +217,16 @@ class FaceGeom:
     qw: np.ndarray      # (n_f, Nq), sums to 1
 
 
-def face_geometry(verts: np.ndarray, fverts: np.ndarray, n_gauss: int) -> FaceGeom:
+def _triangle_points(x0, x1, x2, n):
+    """Conical-product points (n_f, n^2, 3) and weights summing to 1."""
+    a, wa = jacobi_01(n, 1)
+    t, w = gauss_01(n)
+    A, B = (g.ravel() for g in np.meshgrid(a, t, indexing="ij"))
+    pts = x0[:, None] + A[None, :, None] * ((x1 - x0)[:, None] + B[None, :, None] * (x2 - x1)[:, None])
+    return pts, 2.0 * np.outer(wa, w).ravel()
+
+
+def face_geometry(verts: np.ndarray, fverts: np.ndarray, n_gauss: int, fan: bool = False) -> FaceGeom:
     """Geometry and quadrature of faces given their ordered vertex ids."""
     P = verts[fverts]  # (n_f, nv, D)
     t, w = gauss_01(n_gauss)
@@ -227,10 +242,24 @@ def face_geometry(verts: np.ndarray, fverts: np.ndarray, n_gauss: int) -> FaceGe
         S = 0.5 * np.cross(x1 - x0, x2 - x0)
         area = np.sqrt(np.sum(S * S, axis=1))
         normal = S / area[:, None]
-        a, wa = jacobi_01(n_gauss, 1)
-        A, B = (g.ravel() for g in np.meshgrid(a, t, indexing="ij"))
-        qpts = x0[:, None] + A[None, :, None] * ((x1 - x0)[:, None] + B[None, :, None] * (x2 - x1)[:, None])
-        qw = np.broadcast_to(2.0 * np.outer(wa, w).ravel(), (P.shape[0], A.size)).copy()
+        qpts, wt = _triangle_points(x0, x1, x2, n_gauss)
+        qw = np.broadcast_to(wt, (P.shape[0], wt.size)).copy()
+    elif fan:
+        x0, x1, x2, x3 = P[:, 0], P[:, 1], P[:, 2], P[:, 3]
+        S = 0.5 * np.cross(x2 - x0, x3 - x1)
+        area = np.sqrt(np.sum(S * S, axis=1))
+        normal = S / area[:, None]
+        m = np.argmin(fverts, axis=1)
+        Y = np.stack([P[np.arange(P.shape[0]), (m + k) % 4] for k in range(4)], axis=1)
+        parts, wts = [], []
+        tri_area = [0.5 * np.linalg.norm(np.cross(Y[:, b] - Y[:, 0], Y[:, c] - Y[:, 0]), axis=1)
+                    for b, c in ((1, 2), (2, 3))]
+        for (b, c), At in zip(((1, 2), (2, 3)), tri_area):
+            pts, wt = _triangle_points(Y[:, 0], Y[:, b], Y[:, c], n_gauss)
+            parts.append(pts)
+            wts.append(wt[None, :] * (At / (tri_area[0] + tri_area[1]))[:, None])
+        qpts = np.concatenate(parts, axis=1)
+        qw = np.concatenate(wts, axis=1)
     else:
         x0, x1, x2, x3 = P[:, 0], P[:, 1], P[:, 2], P[:, 3]
         S = 0.5 * np.cross(x2 - x0, x3 - x1)

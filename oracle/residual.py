@@ -175,7 +175,7 @@ def build(problem, active=None) -> Discretisation:
     X = mesh.verts[mesh.cells]
     vol, cen = geo.cell_volume_centroid(X)
     faces = geo.enumerate_faces(mesh.cells, D)
-    fg = geo.face_geometry(mesh.verts, faces.verts, problem.n_gauss)
+    fg = geo.face_geometry(mesh.verts, faces.verts, problem.n_gauss, fan=problem.face_rule == 1)
     act = np.ones(n_c, bool)
     if active is not None:
         act = np.zeros(n_c, bool)

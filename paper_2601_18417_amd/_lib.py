@@ -24,7 +24,7 @@ class Params(C.Structure):
                 ("material", C.c_int32), ("fold_quadrature", C.c_int32), ("mu", C.c_double),
                 ("lambda_", C.c_double), ("alpha", C.c_double), ("k_weight", C.c_double),
                 ("ghost_weight", C.c_double), ("stencil_quantum", C.c_double), ("host_only", C.c_int32),
-                ("precond_levels", C.c_int32)]
+                ("precond_levels", C.c_int32), ("face_rule", C.c_int32)]
 
 
 class SetupReport(C.Structure):

@@ -45,10 +45,12 @@ class Context:
     """One discretisation on one device (hofv_ctx)."""
 
     def __init__(self, dim, order_p, n_plus, n_gauss, material, mu, lam, alpha=0.1, k_weight=6.0,
-                 ghost_weight=1.0, stencil_quantum=1e-12, fold_quadrature=True, host_only=False, precond_levels=1):
+                 ghost_weight=1.0, stencil_quantum=1e-12, fold_quadrature=True, host_only=False, precond_levels=1,
+                 face_rule=0):
         self.lib = L.load()
         prm = L.Params(dim, order_p, n_plus, n_gauss, material, int(bool(fold_quadrature)), mu, lam, alpha,
-                       k_weight, ghost_weight, stencil_quantum, int(bool(host_only)), int(precond_levels))
+                       k_weight, ghost_weight, stencil_quantum, int(bool(host_only)), int(precond_levels),
+                       int(face_rule))
         h = C.c_void_p()
         st = self.lib.hofv_create(C.byref(prm), C.byref(h))
         if st != L.HOFV_OK:
@@ -303,7 +305,7 @@ def context_for(problem, fold_quadrature=True, host_only=False, precond_levels=1
     note = progress or (lambda stage: None)
     ctx = Context(problem.mesh.dim, problem.p, problem.n_plus, problem.n_gauss, problem.material, problem.mu,
                   problem.lam, problem.alpha, problem.k_weight, problem.ghost_weight, problem.stencil_quantum,
-                  fold_quadrature, host_only, precond_levels)
+                  fold_quadrature, host_only, precond_levels, problem.face_rule)
     ctx.set_mesh(problem.mesh.verts, problem.mesh.cells)
     note("mesh")
     cen, nor, qp = ctx.boundary_faces()

@@ -325,7 +325,8 @@ hofv_status build_geometry(hofv_ctx* c) {
 
   // faces
   const int64_t nf = (int64_t)c->faces.size();
-  c->nq = D == 2 ? ng : ng * ng;
+  const bool fan = D == 3 && !simplex && c->prm.face_rule == 1;
+  c->nq = D == 2 ? ng : (fan ? 2 * ng * ng : ng * ng);
   const int nq = c->nq;
   c->f_centre.assign((size_t)nf * D, 0.0);
   c->f_normal.assign((size_t)nf * D, 0.0);
@@ -385,22 +386,54 @@ hofv_status build_geometry(hofv_ctx* c) {
       double A = std::sqrt(Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2]);
       c->f_area[f] = A;
       for (int d = 0; d < 3; ++d) c->f_normal[3 * f + d] = Sv[d] / A;
-      double wsum = 0;
-      int q = 0;
-      for (int i = 0; i < ng; ++i)
-        for (int j = 0; j < ng; ++j, ++q) {
-          double s = gfx[i], t = gfx[j];
-          double xs[3], xt[3], nn[3];
+      if (fan) {
+        // the fan starts at the face's lowest-numbered vertex y0 (cyclic order
+        // kept): triangles (y0, y1, y2) and (y0, y2, y3); a point of triangle
+        // (a, b, c) is a + s (b - a + t (c - b)), weight 2 w_s w_t of the
+        // triangle's share A_k / (A_0 + A_1) of the face
+        int m = 0;
+        for (int k = 1; k < 4; ++k)
+          if (F.v[k] < F.v[m]) m = k;
+        const double* y[4];
+        for (int k = 0; k < 4; ++k) y[k] = &c->verts[(size_t)F.v[(m + k) % 4] * 3];
+        const double* tri[2][3] = {{y[0], y[1], y[2]}, {y[0], y[2], y[3]}};
+        double At[2];
+        for (int k = 0; k < 2; ++k) {
+          double u1[3], u2[3], cr[3];
           for (int d = 0; d < 3; ++d) {
-            qp[3 * q + d] = (1 - s) * (1 - t) * x0[d] + s * (1 - t) * x1[d] + s * t * x2[d] + (1 - s) * t * x3[d];
-            xs[d] = (1 - t) * (x1[d] - x0[d]) + t * (x2[d] - x3[d]);
-            xt[d] = (1 - s) * (x3[d] - x0[d]) + s * (x2[d] - x1[d]);
+            u1[d] = tri[k][1][d] - tri[k][0][d];
+            u2[d] = tri[k][2][d] - tri[k][0][d];
           }
-          cross3(xs, xt, nn);
-          qw[q] = gfw[i] * gfw[j] * std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
-          wsum += qw[q];
+          cross3(u1, u2, cr);
+          At[k] = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
         }
-      for (int k = 0; k < nq; ++k) qw[k] /= wsum;
+        int q = 0;
+        for (int k = 0; k < 2; ++k)
+          for (int i = 0; i < ng; ++i)
+            for (int j = 0; j < ng; ++j, ++q) {
+              const double s = t1x[i], t = gfx[j];
+              for (int d = 0; d < 3; ++d)
+                qp[3 * q + d] = tri[k][0][d] + s * (tri[k][1][d] - tri[k][0][d] + t * (tri[k][2][d] - tri[k][1][d]));
+              qw[q] = 2.0 * t1w[i] * gfw[j] * At[k] / (At[0] + At[1]);
+            }
+      } else {
+        double wsum = 0;
+        int q = 0;
+        for (int i = 0; i < ng; ++i)
+          for (int j = 0; j < ng; ++j, ++q) {
+            double s = gfx[i], t = gfx[j];
+            double xs[3], xt[3], nn[3];
+            for (int d = 0; d < 3; ++d) {
+              qp[3 * q + d] = (1 - s) * (1 - t) * x0[d] + s * (1 - t) * x1[d] + s * t * x2[d] + (1 - s) * t * x3[d];
+              xs[d] = (1 - t) * (x1[d] - x0[d]) + t * (x2[d] - x3[d]);
+              xt[d] = (1 - s) * (x3[d] - x0[d]) + s * (x2[d] - x1[d]);
+            }
+            cross3(xs, xt, nn);
+            qw[q] = gfw[i] * gfw[j] * std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+            wsum += qw[q];
+          }
+        for (int k = 0; k < nq; ++k) qw[k] /= wsum;
+      }
     }
     for (int d = 0; d < D; ++d) {
       double s = 0;

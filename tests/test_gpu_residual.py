@@ -196,3 +196,28 @@ def test_neo_hookean_symmetry_faces_parity(p):
     assert disc.s_own.size > 0
     assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro)
     assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_residual_and_jvp_parity_with_the_fan_face_rule(p):
+    """Quadrilateral faces integrated by fan triangulation (two triangles from
+    the lowest-numbered vertex, area-scaled weights) on a randomly perturbed
+    cube, whose faces are not planar."""
+    prob = w.cube_mms(6 if p == 2 else 7, p, perturb=0.2)
+    prob.face_rule = 1
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    u = w.random_state(n, 3, seed=21)
+    v = w.random_state(n, 3, seed=22, scale=1.0)
+    ud, vd = to_dev(u), to_dev(v)
+    R = torch.empty_like(ud)
+    Jv = torch.empty_like(ud)
+    ctx.residual(ud, R)
+    eps = ojac.default_eps(u, v)
+    ctx.jvp(ud, R, vd, Jv, eps=eps)
+    torch.cuda.synchronize()
+    Ro = ores.residual(disc, u)
+    assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro)
+    Jo = ojac.jvp(disc, u, v, eps=eps)
+    assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)

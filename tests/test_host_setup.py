@@ -22,10 +22,16 @@ def _tables(ctx, prob):
     return S, D, nf, fst.reshape(S, nf).T
 
 
+def _fan(prob):
+    prob.face_rule = 1
+    return prob
+
+
 CASES = [lambda: w.square_mms(8, 2, perturb=0.2), lambda: w.square_mms(7, 3),
          lambda: w.cube_mms(6, 3, perturb=0.2), lambda: w.cube_mms(6, 2),
          lambda: w.poly_patch(w.box_mesh((5, 6, 5), perturb=0.2, seed=2), 1, 1,
                               traction_faces=lambda xc, n: xc[:, 1] > 1 - 1e-9),
+         lambda: _fan(w.cube_mms(6, 3, perturb=0.2)),
          lambda: w.tri_mms(6, 3, perturb=0.2),
          lambda: w.tet_mms(3, 2, perturb=0.2), lambda: w.tet_mms(4, 3, perturb=0.2, seed=1)]
 
@@ -139,6 +145,10 @@ def test_setup_rejects_bad_parameters():
         api.Context(4, 2, 10, 2, 0, 1.0, 1.0, stencil_quantum=1e-9, host_only=True)
     with pytest.raises(api.HofvError):
         api.Context(2, 2, 10, 2, 1, 1.0, 1.0, stencil_quantum=1e-9, host_only=True)  # NH in 2D
+    for nh, fold, rule in ((1, True, 1), (0, False, 1), (0, True, 2)):  # the fan rule's limits
+        with pytest.raises(api.HofvError):
+            api.Context(3, 2, 55, 2, nh, 1.0, 1.0, stencil_quantum=1e-9, fold_quadrature=fold, host_only=True,
+                        face_rule=rule)
     ctx = api.Context(2, 3, 10, 2, 0, 1.0, 1.0, stencil_quantum=1e-9, host_only=True)
     mesh = w.box_mesh((2, 2))
     ctx.set_mesh(mesh.verts, mesh.cells)

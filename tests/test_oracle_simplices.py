@@ -153,3 +153,37 @@ def test_degree_above_p_leaves_a_residual_on_tets():
     R = rs.residual(disc, prob.loads.exact.value(disc.cen))
     Ff, _ = rs.face_fluxes(disc, prob.loads.exact.value(disc.cen))
     assert np.abs(R).max() > 1e-4 * np.abs(Ff).max()
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_fan_rule_on_a_planar_quadrilateral(n):
+    """Fan rule (the paper's face subdivision): on a planar trapezoid it
+    integrates every monomial of degree <= 2n - 1 exactly, whichever vertex
+    carries the lowest id, and the points do not depend on where the cyclic
+    vertex list starts."""
+    verts = np.array([[0.0, 0, 0], [2.0, 0, 0], [1.5, 1, 0], [0.5, 1, 0]])
+    exact = lambda a, b: sum(((2.0 - 0.5 * y) ** (a + 1) - (0.5 * y) ** (a + 1)) / (a + 1) * y ** b * wy
+                             for y, wy in zip(*geo.gauss_01(8)))
+    for ids in ([0, 1, 2, 3], [2, 3, 0, 1]):
+        g = geo.face_geometry(verts, np.array([ids]), n, fan=True)
+        assert g.area[0] == pytest.approx(1.5)
+        x, y = g.qpts[0, :, 0], g.qpts[0, :, 1]
+        for deg in range(2 * n):
+            for a in range(deg + 1):
+                q = g.area[0] * np.sum(g.qw[0] * x ** a * y ** (deg - a))
+                assert q == pytest.approx(exact(a, deg - a), rel=1e-13, abs=1e-14)
+    g0 = geo.face_geometry(verts, np.array([[0, 1, 2, 3]]), 2, fan=True)
+    g1 = geo.face_geometry(verts, np.array([[1, 2, 3, 0]]), 2, fan=True)
+    assert np.allclose(g0.qpts, g1.qpts) and np.allclose(g0.qw, g1.qw)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_polynomial_fields_give_zero_residual_with_the_fan_rule(p):
+    prob = w.poly_patch(w.box_mesh((5, 5, 5), perturb=0.2, seed=3, mode="tensor"), p, p, seed=5)
+    prob.face_rule = 1
+    disc = rs.build(prob)
+    assert disc.f_qw.shape[1] == 2 * prob.n_gauss ** 2
+    u = prob.loads.exact.value(disc.cen)
+    R = rs.residual(disc, u)
+    Ff, Fd = rs.face_fluxes(disc, u)
+    assert np.abs(R).max() <= 1e-12 * max(np.abs(Ff).max(), np.abs(Fd).max())

@@ -44,6 +44,7 @@ class Problem:
     ghost_weight: float = 1.0
     stencil_quantum: float = 0.0
     n_increments: int = 1
+    face_rule: int = 0  # quad faces: 0 tensor Gauss-Legendre, 1 fan triangulation
     meta: dict = field(default_factory=dict)
 
     @property
