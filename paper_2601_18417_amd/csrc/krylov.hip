@@ -424,8 +424,11 @@ hofv_status nej_solve(hofv_ctx* c, const double* r, double* z, int sweeps, hipSt
                              st));
   HOFV_HIP(c, hipStreamSynchronize(st));
   const double beta = std::sqrt(N.hbuf[(size_t)(k + 1) * k]);
-  for (size_t i = 0; i < N.hbuf.size(); ++i)
-    if (!std::isfinite(N.hbuf[i])) return fail(c, HOFV_ENAN, "NaN/Inf in the near-exact Jacobian solve");
+  // column j holds rows 0..j+1; the rows below were never written
+  bool finite = std::isfinite(beta);
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i <= j + 1; ++i) finite = finite && std::isfinite(N.hbuf[(size_t)j * (k + 1) + i]);
+  if (!finite) return fail(c, HOFV_ENAN, "NaN/Inf in the near-exact Jacobian solve");
   if (beta == 0.0) {
     k_fill<<<nblk(n), kB, 0, st>>>(n, 0.0, z);
     HOFV_HIP(c, hipGetLastError());
