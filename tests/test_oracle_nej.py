@@ -154,3 +154,22 @@ def test_nej_preconditioner_loses_on_irregular_tetrahedra():
     _, i_aj = kr.fgmres(Jm, b, lambda v: pc.sgs(AJ, col, v.reshape(n, 3), 2).ravel(), rtol=1e-8, maxit=600)
     assert i_nej["converged"] and i_aj["converged"]
     assert i_nej["iters"] > 2 * i_aj["iters"]
+
+
+def test_nej_on_symmetry_plane_cells_is_the_divergence_of_the_stress():
+    """App. C's symmetry-face part: the mirrored half stencil reproduces a
+    quadratic field symmetric about the plane, so cells whose faces are all
+    internal or on the plane also get Omega_P div sigma."""
+    mesh = w.box_mesh((6, 5, 5), perturb=0.2, seed=4, mode="tensor")
+    prob = w.poly_patch(mesh, 2, 2, seed=6, symmetric=True)
+    disc = rs.build(prob)
+    assert disc.s_own is not None and disc.s_own.size > 0
+    A = nej.operator(disc)
+    fld = w.fields.symmetric_poly_field(3, 2, seed=13)
+    u = fld.value(disc.cen)
+    Au = (A @ u.ravel()).reshape(disc.n_cells, 3)
+    ref = disc.vol[:, None] * _div_stress(fld, disc.mu, disc.lam, disc.cen)
+    cnt = np.bincount(np.concatenate([disc.f_own, disc.f_nei, disc.s_own]), minlength=disc.n_cells)
+    cells = np.intersect1d(np.nonzero(cnt == 6)[0], disc.s_own)
+    assert cells.size >= 4
+    assert np.abs(Au[cells] - ref[cells]).max() <= 1e-9 * np.abs(ref[cells]).max()

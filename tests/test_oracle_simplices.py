@@ -8,6 +8,7 @@ import pytest
 
 import workloads as w
 from oracle import geometry as geo
+from oracle import jacobian as jc
 from oracle import residual as rs
 
 
@@ -187,3 +188,21 @@ def test_polynomial_fields_give_zero_residual_with_the_fan_rule(p):
     R = rs.residual(disc, u)
     Ff, Fd = rs.face_fluxes(disc, u)
     assert np.abs(R).max() <= 1e-12 * max(np.abs(Ff).max(), np.abs(Fd).max())
+
+
+@pytest.mark.parametrize("p,min_slope", [(1, 1.9), (2, 1.5), (3, 3.5)])
+def test_oracle_converges_on_regular_triangles(p, min_slope):
+    """The 2D manufactured problem on 8^2 and 16^2 quads split into triangles,
+    solved exactly (the linear law's residual is affine): the centroid RMS
+    error against the manufactured field falls at the scheme's rate (observed
+    2.11, 1.66 and 4.08 at p = 1, 2, 3)."""
+    errs = []
+    for n in (8, 16):
+        prob = w.tri_mms(n, p, perturb=0.0)
+        disc = rs.build(prob)
+        J = jc.jacobian_affine(disc)
+        R0 = rs.residual(disc, np.zeros((disc.n_cells, 2)))
+        u = -np.linalg.solve(J, R0.ravel()).reshape(-1, 2)
+        ue = prob.loads.exact.value(disc.cen)
+        errs.append(np.sqrt(np.mean(np.sum((u - ue) ** 2, axis=1))))
+    assert np.log(errs[0] / errs[1]) / np.log(2.0) >= min_slope
