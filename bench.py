@@ -365,7 +365,7 @@ def main():
     ap.add_argument("--train-seeds", default="0-49")
     ap.add_argument("--harvest-starts", type=int, default=4)
     ap.add_argument("--harvest-length", type=int, default=9)
-    ap.add_argument("--model", default="gpurun_out/learned_model.npy")
+    ap.add_argument("--model", default="learned_model.npy", help="weights file written by --study train, read by eval")
     ap.add_argument("--seed", type=int, default=50, help="mesh seed of --study eval")
     ap.add_argument("--max-newton", type=int, default=10, help="Newton steps per increment in --study eval")
     ap.add_argument("--eta", type=float, default=None,
