@@ -96,7 +96,8 @@ def test_extrapolation_rows_match_oracle(mk):
 
 
 @pytest.mark.parametrize("mesh", [lambda: w.box_mesh((6, 5, 5), perturb=0.2, seed=3),
-                                  lambda: w.tet_mesh((4, 4, 4), perturb=0.2, seed=3)])
+                                  lambda: w.tet_mesh((4, 4, 4), perturb=0.2, seed=3),
+                                  lambda: w.tri_mesh((8, 7), perturb=0.2, seed=3)])
 def test_sources_match_oracle_plus_boundary_constants(mesh):
     """Cell sources = body force + traction faces + the u_b-dependent constants
     of displacement faces (ghost gradient term and u_b of the stabilisation),
@@ -104,9 +105,9 @@ def test_sources_match_oracle_plus_boundary_constants(mesh):
     prob = w.poly_patch(mesh(), 2, 2, seed=2, traction_faces=lambda xc, n: xc[:, 0] > 1 - 1e-9)
     disc = ores.build(prob)
     ctx = api.context_for(prob, host_only=True)
-    n = disc.n_cells
-    src = ctx.host_table("cell_src").reshape(3, n).T
-    R0 = ores.residual(disc, np.zeros((n, 3)))
+    n, D = disc.n_cells, disc.dim
+    src = ctx.host_table("cell_src").reshape(D, n).T
+    R0 = ores.residual(disc, np.zeros((n, D)))
     assert np.abs(src - R0).max() <= 1e-11 * np.abs(R0).max()
 
 
