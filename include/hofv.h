@@ -210,9 +210,11 @@ hofv_status hofv_jvp(hofv_ctx* ctx, const double* d_u, const double* d_Ru, const
                      double* d_Jv, double eps, void* stream);
 
 /* z ~ P^{-1} r with P the compact approximate Jacobian (Sec. 4.1): n_sweeps
- * symmetric multicolour Gauss-Seidel sweeps in FP32 from z = 0.  learned != 0
- * adds the network correction (hofv_nn_*) when one is loaded.  d_r, d_z must
- * not alias. */
+ * symmetric multicolour Gauss-Seidel sweeps in FP32 from z = 0, or the
+ * V-cycle (hofv_set_multigrid).  learned != 0 adds the network correction
+ * (hofv_nn_*) when one is loaded.  With hofv_set_nej on, z ~ A^{-1} r for the
+ * near-exact Jacobian A instead (learned != 0 is then HOFV_EINVAL).  d_r, d_z
+ * must not alias. */
 hofv_status hofv_precond_apply(hofv_ctx* ctx, const double* d_r, double* d_z, int32_t n_sweeps,
                                int32_t learned, void* stream);
 
