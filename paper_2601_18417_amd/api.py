@@ -80,6 +80,10 @@ class Context:
     def set_mesh(self, verts, cells):
         verts = np.ascontiguousarray(verts, np.float64)
         cells = np.ascontiguousarray(cells, np.int64)
+        if verts.ndim != 2 or verts.shape[1] != self.dim:
+            raise ValueError(f"verts must be (n_verts, {self.dim})")
+        if cells.ndim != 2 or cells.shape[1] not in (2 ** self.dim, self.dim + 1):
+            raise ValueError(f"cells must be (n_cells, {2 ** self.dim}) or (n_cells, {self.dim + 1})")
         # cells of dim + 1 vertices are triangles or tetrahedra
         fn = self.lib.hofv_set_mesh_simplices if cells.shape[1] == verts.shape[1] + 1 else self.lib.hofv_set_mesh
         self._check(fn(self.h, verts.shape[0], _dptr(verts), cells.shape[0],

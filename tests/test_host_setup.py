@@ -251,3 +251,21 @@ def test_symmetry_faces_get_their_own_flux_codes():
     assert sorted(sym_codes - nf) == list(range(disc.s_own.size))
     owners = np.nonzero((cf >= nf).any(axis=0))[0]
     assert sorted(owners) == sorted(disc.s_own)
+
+
+def test_mesh_shapes_and_orientation_are_checked():
+    """The binding refuses cell arrays of the wrong width (the library would
+    read past them); the library refuses a negatively oriented tetrahedron."""
+    mesh = w.tet_mesh((2, 2, 2))
+    ctx = api.Context(3, 1, 20, 1, 0, 1.0, 1.0, stencil_quantum=1e-9, host_only=True)
+    with pytest.raises(ValueError):
+        ctx.set_mesh(mesh.verts, mesh.cells[:, :3])
+    with pytest.raises(ValueError):
+        ctx.set_mesh(mesh.verts[:, :2], mesh.cells)
+    bad = mesh.cells.copy()
+    bad[5] = bad[5][[0, 2, 1, 3]]
+    with pytest.raises(api.HofvError):
+        ctx.set_mesh(mesh.verts, bad)
+    ok = api.Context(3, 1, 20, 1, 0, 1.0, 1.0, stencil_quantum=1e-9, host_only=True)
+    ok.set_mesh(mesh.verts, mesh.cells)
+    assert ok.n_cells == 48
