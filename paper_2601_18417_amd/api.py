@@ -114,11 +114,25 @@ class Context:
     def set_bc(self, types, u_b_q, u_b_centre, traction_q):
         types = np.ascontiguousarray(types, np.int32)
         arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (u_b_q, u_b_centre, traction_q)]
+        # the library reads these sizes from the pointers: check them here
+        n, nq = C.c_int64(), C.c_int32()
+        self._check(self.lib.hofv_boundary_faces(self.h, C.byref(n), C.byref(nq), None, None, None))
+        nb, q, D = n.value, nq.value, self.dim
+        if types.shape != (nb,):
+            raise ValueError(f"types must be ({nb},)")
+        for a, shape in zip(arrs, ((nb, q, D), (nb, D), (nb, q, D))):
+            if a is not None and a.size != nb * int(np.prod(shape[1:])):
+                raise ValueError(f"boundary arrays must be {shape}")
         self._check(self.lib.hofv_set_bc(self.h, types.ctypes.data_as(C.POINTER(C.c_int32)),
                                          *[_dptr(a) for a in arrs]))
 
     def set_body_force(self, values):
         v = None if values is None else np.ascontiguousarray(values, np.float64)
+        if v is not None:
+            nqv = C.c_int32()
+            self._check(self.lib.hofv_volume_qpoints(self.h, C.byref(nqv), None))
+            if v.size != self.n_cells * nqv.value * self.dim:
+                raise ValueError(f"body force must be ({self.n_cells}, {nqv.value}, {self.dim})")
         self._check(self.lib.hofv_set_body_force(self.h, _dptr(v)))
 
     def setup(self):

@@ -269,3 +269,13 @@ def test_mesh_shapes_and_orientation_are_checked():
     ok = api.Context(3, 1, 20, 1, 0, 1.0, 1.0, stencil_quantum=1e-9, host_only=True)
     ok.set_mesh(mesh.verts, mesh.cells)
     assert ok.n_cells == 48
+    cen, _, qp = ok.boundary_faces()
+    nb = cen.shape[0]
+    with pytest.raises(ValueError):  # boundary arrays sized for another mesh
+        ok.set_bc(np.zeros(nb - 1, np.int32), None, None, None)
+    with pytest.raises(ValueError):
+        ok.set_bc(np.zeros(nb, np.int32), np.zeros((nb, 1, 3)), np.zeros((nb - 1, 3)), None)
+    ok.set_bc(np.zeros(nb, np.int32), np.zeros(qp.shape), np.zeros((nb, 3)), None)
+    with pytest.raises(ValueError):
+        ok.set_body_force(np.zeros((48, 1, 3)))
+    ok.set_body_force(np.zeros(ok.volume_qpoints().shape))
