@@ -30,10 +30,12 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def _ptr(t):
+def _ptr(t, numel=None):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError("expected a contiguous float64 HIP tensor")
+    if numel is not None and t.numel() != numel:  # the kernels index by the mesh's size
+        raise ValueError(f"expected a tensor of {numel} elements, got {t.numel()}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -64,6 +66,10 @@ class Context:
     def _check(self, st):
         if st != L.HOFV_OK:
             raise HofvError(st, self.lib.hofv_last_error(self.h).decode())
+
+    def _v(self, t):
+        """Pointer of a device vector [dim][n_cells] of this mesh."""
+        return _ptr(t, self.dim * self.n_cells)
 
     def close(self):
         if getattr(self, "h", None):
@@ -154,25 +160,26 @@ class Context:
 
     # ------------------------------------------------------------------- hot
     def residual(self, u, R, stream=None):
-        self._check(self.lib.hofv_residual(self.h, _ptr(u), _ptr(R), _stream(stream)))
+        self._check(self.lib.hofv_residual(self.h, self._v(u), self._v(R), _stream(stream)))
 
     def jvp(self, u, Ru, v, Jv, eps=0.0, stream=None):
-        self._check(self.lib.hofv_jvp(self.h, _ptr(u), _ptr(Ru), _ptr(v), _ptr(Jv), float(eps), _stream(stream)))
+        self._check(self.lib.hofv_jvp(self.h, self._v(u), self._v(Ru), self._v(v), self._v(Jv), float(eps),
+                                      _stream(stream)))
 
     def nej_apply(self, v, out, stream=None):
         """out = A v for the near-exact Jacobian A (linear elastic law)."""
-        self._check(self.lib.hofv_nej_apply(self.h, _ptr(v), _ptr(out), _stream(stream)))
+        self._check(self.lib.hofv_nej_apply(self.h, self._v(v), self._v(out), _stream(stream)))
 
     def precond_apply(self, r, z, n_sweeps=2, learned=False, stream=None):
-        self._check(self.lib.hofv_precond_apply(self.h, _ptr(r), _ptr(z), int(n_sweeps), int(bool(learned)),
+        self._check(self.lib.hofv_precond_apply(self.h, self._v(r), self._v(z), int(n_sweeps), int(bool(learned)),
                                                 _stream(stream)))
 
     def fgmres_solve(self, u, Ru, rhs, x, restart=30, max_iters=1000, rtol=1e-6, n_sweeps=2, learned=False,
                      stream=None, check=True, side=0):
         o = L.KrylovOpts(restart, max_iters, rtol, n_sweeps, int(bool(learned)), int(side))
         s = L.KrylovStats()
-        st = self.lib.hofv_fgmres_solve(self.h, _ptr(u), _ptr(Ru), _ptr(rhs), _ptr(x), C.byref(o), C.byref(s),
-                                        _stream(stream))
+        st = self.lib.hofv_fgmres_solve(self.h, self._v(u), self._v(Ru), self._v(rhs), self._v(x), C.byref(o),
+                                        C.byref(s), _stream(stream))
         if check or st not in (L.HOFV_OK, -5):
             self._check(st)
         return {k: getattr(s, k) for k, _ in L.KrylovStats._fields_}
@@ -190,7 +197,7 @@ class Context:
         o = self._newton_opts(tol, eta, max_newton, n_increments, max_line_search, restart, max_krylov, n_sweeps,
                               learned, forcing, predictor, side)
         s = L.NewtonStats()
-        st = self.lib.hofv_newton_solve(self.h, _ptr(u), C.byref(o), C.byref(s), _stream(stream))
+        st = self.lib.hofv_newton_solve(self.h, self._v(u), C.byref(o), C.byref(s), _stream(stream))
         if check or st not in (L.HOFV_OK, -5):
             self._check(st)
         return {k: getattr(s, k) for k, _ in L.NewtonStats._fields_}
@@ -204,7 +211,7 @@ class Context:
         """History of the next step; u_tm1, v_tm1 default to u_t, v_t."""
         u_tm1 = u_t if u_tm1 is None else u_tm1
         v_tm1 = v_t if v_tm1 is None else v_tm1
-        self._check(self.lib.hofv_dyn_reset(self.h, _ptr(u_t), _ptr(u_tm1), _ptr(v_t), _ptr(v_tm1),
+        self._check(self.lib.hofv_dyn_reset(self.h, self._v(u_t), self._v(u_tm1), self._v(v_t), self._v(v_tm1),
                                             _stream(stream)))
 
     def dyn_step(self, u, tol=1e-8, eta=1e-4, max_newton=50, max_line_search=10, restart=30, max_krylov=2000,
@@ -213,7 +220,7 @@ class Context:
         o = self._newton_opts(tol, eta, max_newton, 0, max_line_search, restart, max_krylov, n_sweeps, learned,
                               forcing, 0)
         s = L.NewtonStats()
-        st = self.lib.hofv_dyn_step(self.h, _ptr(u), C.byref(o), C.byref(s), _stream(stream))
+        st = self.lib.hofv_dyn_step(self.h, self._v(u), C.byref(o), C.byref(s), _stream(stream))
         if check or st not in (L.HOFV_OK, -5):
             self._check(st)
         return {k: getattr(s, k) for k, _ in L.NewtonStats._fields_}
@@ -293,20 +300,21 @@ def _ctx_nn_methods():
     def nn_train_step(self, model, r, e, n_sweeps=2, lr=1e-3, stream=None):
         """r, e: device tensors [n_pairs, dim, n_cells] float64."""
         loss = C.c_double()
-        self._check(self.lib.hofv_nn_train_step(self.h, model.h, _ptr(r), _ptr(e), int(r.shape[0]), int(n_sweeps),
-                                                float(lr), C.byref(loss), _stream(stream)))
+        n = int(r.shape[0]) * self.dim * self.n_cells
+        self._check(self.lib.hofv_nn_train_step(self.h, model.h, _ptr(r, n), _ptr(e, n), int(r.shape[0]),
+                                                int(n_sweeps), float(lr), C.byref(loss), _stream(stream)))
         return loss.value
 
     def nn_gradient(self, model, r, zaj, e, stream=None):
         g = np.empty(model.n_params, np.float32)
         loss = C.c_double()
-        self._check(self.lib.hofv_nn_gradient(self.h, model.h, _ptr(r), _ptr(zaj), _ptr(e),
+        self._check(self.lib.hofv_nn_gradient(self.h, model.h, self._v(r), self._v(zaj), self._v(e),
                                               g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss),
                                               _stream(stream)))
         return loss.value, g
 
     def nn_forward(self, model, r, zaj, z, stream=None):
-        self._check(self.lib.hofv_nn_forward(self.h, model.h, _ptr(r), _ptr(zaj), _ptr(z), _stream(stream)))
+        self._check(self.lib.hofv_nn_forward(self.h, model.h, self._v(r), self._v(zaj), self._v(z), _stream(stream)))
 
     for f in (attach, nn_train_step, nn_gradient, nn_forward):
         setattr(Context, f.__name__, f)
