@@ -173,3 +173,24 @@ def test_nej_on_symmetry_plane_cells_is_the_divergence_of_the_stress():
     cells = np.intersect1d(np.nonzero(cnt == 6)[0], disc.s_own)
     assert cells.size >= 4
     assert np.abs(Au[cells] - ref[cells]).max() <= 1e-9 * np.abs(ref[cells]).max()
+
+
+@pytest.mark.parametrize("mk", [lambda: w.cube_mms(5, 2, perturb=0.0), lambda: w.tet_mms(3, 2, perturb=0.2)])
+def test_nej_weakest_mode_is_a_checkerboard(mk):
+    """Without the alpha-term the weakest mode of the operator alternates in
+    sign across most faces and is much weaker than the full Jacobian's, whose
+    weakest mode is smooth: the stabilisation exists to damp such modes."""
+    disc = rs.build(mk())
+    J = jc.jacobian_affine(disc)
+    A = nej.operator(disc)
+
+    def weakest(M):
+        _, s, vt = np.linalg.svd(M)
+        v = vt[-1].reshape(-1, 3)
+        x = v[:, np.argmax(np.abs(v).sum(axis=0))]
+        return s[-1] / s[0], np.mean(np.sign(x[disc.f_own]) != np.sign(x[disc.f_nei]))
+
+    rel_a, flips_a = weakest(A)
+    rel_j, flips_j = weakest(J)
+    assert rel_a < 0.2 * rel_j
+    assert flips_a > 0.8 and flips_j < 0.3
