@@ -91,8 +91,10 @@ typedef struct {
                              face's lowest-numbered vertex into two triangles with the
                              simplex rule on each (2 n_gauss^2 points), each
                              triangle's weights scaled by its area over the sum of
-                             the two areas.  Area and normal come from the face's
-                             vector area either way.  1 needs the linear elastic
+                             the two areas, and the face area Gamma_f that sum (on
+                             a warped face larger than the vector area's length).
+                             The normal is the vector area's direction either way;
+                             rule 0 takes Gamma_f as that vector's length.  1 needs the linear elastic
                              law with fold_quadrature = 1 (HOFV_EINVAL otherwise);
                              triangle faces and 2D edges ignore it. */
 } hofv_params;

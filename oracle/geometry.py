@@ -260,6 +260,9 @@ def face_geometry(verts: np.ndarray, fverts: np.ndarray, n_gauss: int, fan: bool
             wts.append(wt[None, :] * (At / (tri_area[0] + tri_area[1]))[:, None])
         qpts = np.concatenate(parts, axis=1)
         qw = np.concatenate(wts, axis=1)
+        # Sec. 3.1: the face area is the sum of the sub-triangle areas (the
+        # normal stays the vector area's direction, one per face)
+        area = tri_area[0] + tri_area[1]
     else:
         x0, x1, x2, x3 = P[:, 0], P[:, 1], P[:, 2], P[:, 3]
         S = 0.5 * np.cross(x2 - x0, x3 - x1)

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "common.h"
+#include "givens.h"
 
 namespace hofv {
 
@@ -224,7 +225,8 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
     HOFV_HIP(c, hipStreamSynchronize(st));
     return HOFV_OK;
   }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  GivensLsq lsq;
+  std::vector<double> y(m);
   int it = 0;
   double beta = 0, beta_cycle = -1.0;
   for (;;) {
@@ -254,8 +256,7 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
     beta_cycle = beta;
     k_fill<<<1, kB, 0, st>>>(1, beta, hd + kBeta);
     k_scale_by<<<nblk(n), kB, 0, st>>>(n, K.V, hd + kBeta, 0, K.V);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
+    lsq.reset(m, beta);
     int kdone = 0;
     // Iterations are queued kCheck at a time; their Hessenberg columns stay on
     // the device until the host reads them all at once and applies the Givens
@@ -308,23 +309,23 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
           redo = jj;
           break;
         }
-        for (int i = 0; i <= jj + 1; ++i) H[(size_t)i * m + jj] = col[i];
-        for (int i = 0; i < jj; ++i) {
-          const double a = H[(size_t)i * m + jj], b = H[(size_t)(i + 1) * m + jj];
-          H[(size_t)i * m + jj] = cs[i] * a + sn[i] * b;
-          H[(size_t)(i + 1) * m + jj] = -sn[i] * a + cs[i] * b;
+        if (!lsq.add(col)) {
+          // the rotated column is zero: z_j adds no direction.  A learned
+          // output redoes the iteration with the plain preconditioner; a plain
+          // one ends the cycle with the columns accepted so far
+          if (learned) {
+            learned = 0;
+            ++stats->fallbacks;
+            redo = jj;
+            break;
+          }
+          ++it;
+          done = true;
+          break;
         }
-        const double a = H[(size_t)jj * m + jj], b = H[(size_t)(jj + 1) * m + jj];
-        const double den = std::hypot(a, b);
-        cs[jj] = den > 0 ? a / den : 1.0;
-        sn[jj] = den > 0 ? b / den : 0.0;
-        H[(size_t)jj * m + jj] = den;
-        H[(size_t)(jj + 1) * m + jj] = 0.0;
-        g[jj + 1] = -sn[jj] * g[jj];
-        g[jj] = cs[jj] * g[jj];
         ++it;
-        kdone = jj + 1;
-        if (std::fabs(g[jj + 1]) <= rtol * bnorm || it >= maxit || den == 0.0 || kdone == m) done = true;
+        kdone = lsq.k;
+        if (lsq.residual() <= rtol * bnorm || it >= maxit || kdone == m) done = true;
       }
       if (redo >= 0) {
         j = jp = redo;
@@ -332,11 +333,7 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
       }
       jp = j;
     }
-    for (int i = kdone - 1; i >= 0; --i) {
-      double sum = g[i];
-      for (int l = i + 1; l < kdone; ++l) sum -= H[(size_t)i * m + l] * y[l];
-      y[i] = sum / H[(size_t)i * m + i];
-    }
+    lsq.solve(y.data());
     HOFV_HIP(c, hipMemcpyAsync(hd, y.data(), kdone * sizeof(double), hipMemcpyHostToDevice, st));
     k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, kdone, left ? K.V : K.Z, n, hd, 1.0, x);
     HOFV_HIP(c, hipGetLastError());
@@ -435,35 +432,16 @@ hofv_status nej_solve(hofv_ctx* c, const double* r, double* z, int sweeps, hipSt
     return HOFV_OK;
   }
   // least squares by Givens rotations; a zero subdiagonal ends the Krylov
-  // space there (the solve is exact within it)
-  std::vector<double> H((size_t)(k + 1) * k), cs(k), sn(k), g(k + 1, 0.0);
-  int kk = 0;
-  g[0] = beta;
+  // space there (the solve is exact within it), a zero rotated column is dropped
+  GivensLsq lsq;
+  lsq.reset(k, beta);
   for (int j = 0; j < k; ++j) {
     const double* col = &N.hbuf[(size_t)j * (k + 1)];
-    for (int i = 0; i <= j + 1; ++i) H[(size_t)i * k + j] = col[i];
-    for (int i = 0; i < j; ++i) {
-      const double a = H[(size_t)i * k + j], b = H[(size_t)(i + 1) * k + j];
-      H[(size_t)i * k + j] = cs[i] * a + sn[i] * b;
-      H[(size_t)(i + 1) * k + j] = -sn[i] * a + cs[i] * b;
-    }
-    const double a = H[(size_t)j * k + j], b = H[(size_t)(j + 1) * k + j];
-    const double den = std::hypot(a, b);
-    if (den == 0.0) break;
-    cs[j] = a / den;
-    sn[j] = b / den;
-    H[(size_t)j * k + j] = den;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    kk = j + 1;
-    if (b == 0.0) break;
+    if (!lsq.add(col) || col[j + 1] == 0.0) break;
   }
+  const int kk = lsq.k;
   N.ybuf.assign(k, 0.0);
-  for (int i = kk - 1; i >= 0; --i) {
-    double a = g[i];
-    for (int l = i + 1; l < kk; ++l) a -= H[(size_t)i * k + l] * N.ybuf[l];
-    N.ybuf[i] = a / H[(size_t)i * k + i];
-  }
+  lsq.solve(N.ybuf.data());
   HOFV_HIP(c, hipMemcpyAsync(N.y, N.ybuf.data(), (size_t)k * sizeof(double), hipMemcpyHostToDevice, st));
   k_fill<<<nblk(n), kB, 0, st>>>(n, 0.0, N.t);
   k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, kk, N.V, n, N.y, 1.0, N.t);

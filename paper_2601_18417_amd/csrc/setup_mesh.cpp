@@ -407,6 +407,9 @@ hofv_status build_geometry(hofv_ctx* c) {
           cross3(u1, u2, cr);
           At[k] = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
         }
+        // the face area is the sum of the triangle areas (Sec. 3.1); on a
+        // warped face it exceeds |S_f|, whose direction stays the normal
+        c->f_area[f] = At[0] + At[1];
         int q = 0;
         for (int k = 0; k < 2; ++k)
           for (int i = 0; i < ng; ++i)

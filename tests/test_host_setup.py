@@ -279,3 +279,38 @@ def test_mesh_shapes_and_orientation_are_checked():
     with pytest.raises(ValueError):
         ok.set_body_force(np.zeros((48, 1, 3)))
     ok.set_body_force(np.zeros(ok.volume_qpoints().shape))
+
+
+def test_library_skewness_coefficients_on_sheared_grid():
+    """The library's own stabilisation coefficients alpha Kbar Gamma / |d . n|
+    (eq. alpha) and approximate-Jacobian couplings Kbar Gamma / |d . n| (Sec. 4.1)
+    on the grid sheared by x += s y, against the closed forms (not the oracle):
+    slanted faces (1 + s^2), flat faces 1, displacement faces 2 and 2 (1 + s^2)."""
+    from test_oracle_residual import SHEAR, sheared_square
+    n = 7
+    prob = sheared_square(n)
+    ctx = api.context_for(prob, host_only=True)
+    kb, al, s2 = 2 * prob.mu + prob.lam, prob.alpha, SHEAR ** 2
+    ijk = w.cell_ijk(prob.mesh)
+    own = ctx.host_table("face_own")  # caller cell ids
+    nei = ctx.host_table("face_nei")
+    stab = ctx.host_table("face_stab")
+    fc = ctx.host_table("face_centre").reshape(-1, 2)
+    cen = ctx.host_table("centroids").reshape(-1, 2)
+    for f in range(stab.size):
+        P = own[f]
+        if nei[f] >= 0:
+            slanted = ijk[nei[f]][1] == ijk[P][1]
+        else:  # a flat boundary face lies straight below or above the centroid's row
+            slanted = abs(fc[f, 1] - cen[P, 1]) < 1e-12
+        expect = al * kb * (1 + s2 if slanted else 1.0) * (1.0 if nei[f] >= 0 else 2.0)
+        assert stab[f] == pytest.approx(expect, rel=1e-12)
+    perm = ctx.host_table("pc_perm")
+    a = ctx.host_table("pc_a").reshape(4, -1)
+    nbr = ctx.host_table("pc_nbr").reshape(4, -1)
+    for i in range(perm.size):
+        for s in range(4):
+            if a[s, i] != 0:
+                di, dj = ijk[perm[nbr[s, i]]] - ijk[perm[i]]
+                assert abs(di) + abs(dj) == 1
+                assert a[s, i] == pytest.approx(kb * (1 + s2) if dj == 0 else kb, rel=1e-6)

@@ -243,3 +243,84 @@ def test_active_subset_matches_full_residual():
     part = rs.build(prob, active=sub)
     u = w.random_state(full.n_cells, 3, 8)
     assert np.allclose(rs.residual(part, u)[sub], rs.residual(full, u)[sub], rtol=1e-14, atol=1e-17)
+
+
+# --- eq. alpha's skewness measure |d_PN . n_f| on a sheared grid --------------
+#
+# A uniform grid sheared by x += s y has parallelogram cells.  On the slanted
+# faces (between cells i and i+1) d_PN = (h, 0), n_f = (1, -s)/sqrt(1+s^2) and
+# Gamma_f = h sqrt(1+s^2), so Gamma_f / |d_PN . n_f| = 1 + s^2 while
+# Gamma_f / |d_PN| = sqrt(1+s^2); on the horizontal faces d_PN = (s h, h),
+# n_f = (0, 1), Gamma_f = h: the two ratios are 1 and 1/sqrt(1+s^2).  The
+# shear s = 0.6 keeps every squared lattice distance within the 13-cell p = 1
+# stencil distinct except for the pairs +-delta, so interior stencils are
+# point-symmetric.
+
+SHEAR = 0.6
+
+
+def sheared_square(n, p=1, s=SHEAR, zero_loads=False):
+    prob = w.square_mms(n, p)
+    v = prob.mesh.verts.copy()
+    v[:, 0] += s * v[:, 1]
+    prob.mesh.verts = v
+    if zero_loads:
+        zero = lambda x: np.zeros((x.shape[0], 2))
+        prob.loads = w.fields.Loads(2, lambda xc, nrm: np.full(xc.shape[0], w.fields.DISP, np.int32), zero,
+                                    lambda x, nrm: zero(x), zero)
+    return prob
+
+
+def _symmetric_stencil(disc, ijk, n, P):
+    """Whether P's cell stencil is invariant under the point reflection about P."""
+    st = {tuple(ijk[c]) for c in disc.c_st[P]}
+    return all((2 * ijk[P][0] - a, 2 * ijk[P][1] - b) in st for a, b in st)
+
+
+def test_stabilisation_skewness_checkerboard_on_sheared_grid():
+    """p = 1, checkerboard u: on cells whose stencil (and whose face neighbours'
+    stencils) are point-symmetric the reconstructed gradient is zero, u* = u_P,
+    and each face adds alpha Kbar Gamma_f / |d_PN . n_f| (u_N - u_P) with
+    u_N = -u_P: the stabilisation part of R_P is -4 alpha Kbar (2 + s^2) u_P.
+    With |d_PN| in place of |d_PN . n_f| it would be
+    -4 alpha Kbar (sqrt(1+s^2) + 1/sqrt(1+s^2)) u_P."""
+    n = 12
+    prob = sheared_square(n)
+    disc = rs.build(prob)
+    d0 = rs.build(prob)
+    d0.alpha = 0.0
+    ijk = w.cell_ijk(prob.mesh)
+    sgn = (-1.0) ** (ijk[:, 0] + ijk[:, 1])
+    u = np.stack([sgn, -0.7 * sgn], axis=1)
+    Rs = rs.residual(disc, u) - rs.residual(d0, u)
+    sym = np.array([_symmetric_stencil(disc, ijk, n, P) for P in range(disc.n_cells)])
+    good = np.array([sym[P] and all(sym[Q] for Q in range(disc.n_cells)
+                                    if np.abs(ijk[Q] - ijk[P]).sum() == 1) for P in range(disc.n_cells)])
+    assert good.sum() >= 25
+    s2 = SHEAR ** 2
+    expect = -4.0 * prob.alpha * disc.kbar * (2.0 + s2) * u[good]
+    assert np.allclose(Rs[good], expect, rtol=1e-12, atol=0)
+    wrong = -4.0 * prob.alpha * disc.kbar * (np.sqrt(1 + s2) + 1 / np.sqrt(1 + s2)) * u[good]
+    assert np.abs(Rs[good] - wrong).max() > 0.05 * np.abs(wrong).max()
+
+
+def test_stabilisation_skewness_on_sheared_displacement_faces():
+    """A constant field c with u_b = 0: the reconstruction of a constant is
+    exact on any stencil, so u* = c and internal faces add nothing; each
+    displacement face adds alpha Kbar Gamma_b / |d_Pb . n_b| (0 - c).  Bottom and
+    top faces: Gamma_b / |d_Pb . n_b| = h / (h/2) = 2; left and right (slanted)
+    faces: h sqrt(1+s^2) / (h / (2 sqrt(1+s^2))) = 2 (1 + s^2)."""
+    n = 8
+    prob = sheared_square(n, zero_loads=True)
+    disc = rs.build(prob)
+    d0 = rs.build(prob)
+    d0.alpha = 0.0
+    c = np.array([0.3, -1.1])
+    u = np.tile(c, (disc.n_cells, 1))
+    Rs = rs.residual(disc, u) - rs.residual(d0, u)
+    ijk = w.cell_ijk(prob.mesh)
+    n_flat = (ijk[:, 1] == 0).astype(float) + (ijk[:, 1] == n - 1)
+    n_slant = (ijk[:, 0] == 0).astype(float) + (ijk[:, 0] == n - 1)
+    coef = 2.0 * n_flat + 2.0 * (1 + SHEAR ** 2) * n_slant
+    expect = -prob.alpha * disc.kbar * coef[:, None] * c[None, :]
+    assert np.allclose(Rs, expect, rtol=1e-12, atol=1e-14)

@@ -178,6 +178,22 @@ def test_fan_rule_on_a_planar_quadrilateral(n):
     assert np.allclose(g0.qpts, g1.qpts) and np.allclose(g0.qw, g1.qw)
 
 
+@pytest.mark.parametrize("order", [[0, 1, 2, 3], [1, 2, 3, 0], [3, 2, 1, 0]])
+def test_fan_rule_area_of_a_warped_quadrilateral(order):
+    """Sec. 3.1 takes the face area as the sum of its sub-triangle areas.  The
+    face (0,0,0), (1,0,0), (1,1,z), (0,1,0) is cut from vertex 0 into two
+    triangles of area sqrt(1+z^2)/2 each, so Gamma = sqrt(1+z^2), while its
+    vector area (-z, -z, 2)/2 has length sqrt(1+z^2/2); the normal stays
+    that vector's direction."""
+    z = 0.5
+    verts = np.array([[0.0, 0, 0], [1.0, 0, 0], [1.0, 1, z], [0.0, 1, 0]])
+    g = geo.face_geometry(verts, np.array([order]), 2, fan=True)
+    assert g.area[0] == pytest.approx(np.sqrt(1 + z * z), rel=1e-14)
+    sgn = 1.0 if order[1] == (order[0] + 1) % 4 else -1.0
+    assert np.allclose(g.normal[0], sgn * np.array([-z, -z, 2.0]) / np.sqrt(2 * z * z + 4), rtol=1e-14)
+    assert g.qw[0].sum() == pytest.approx(1.0, rel=1e-14)
+
+
 @pytest.mark.parametrize("p", [1, 2, 3])
 def test_polynomial_fields_give_zero_residual_with_the_fan_rule(p):
     prob = w.poly_patch(w.box_mesh((5, 5, 5), perturb=0.2, seed=3, mode="tensor"), p, p, seed=5)

@@ -435,3 +435,32 @@ def test_bench_forcing_rule_is_the_oracles():
         eta_prev, eta_max, tol = 10 ** rng.uniform(-6, 0), 10 ** rng.uniform(-3, 0), 10 ** rng.uniform(-12, -6)
         assert bench.forcing_term(rn, rprev, eta_prev, eta_max, tol, r0) == \
             nw.forcing_term(rn, rprev, eta_prev, eta_max, tol, r0)
+
+
+def test_compact_preconditioner_skewness_on_sheared_grid():
+    """Sec. 4.1's off-diagonal K Gamma_f / |d_PN . n_f| on a grid sheared by
+    x += s y (h = 1/n): K (1 + s^2) between cells i and i+1 (slanted faces),
+    K between cells j and j+1; displacement faces add 2 K (flat) and
+    2 K (1 + s^2) (slanted) to the diagonal's magnitude.  With |d_PN| the
+    slanted entries would be K sqrt(1 + s^2) and the flat ones K / sqrt(1 + s^2)."""
+    from test_oracle_residual import SHEAR, sheared_square
+    n = 7
+    prob = sheared_square(n)
+    disc = rs.build(prob)
+    A = pc.assemble(disc).toarray()
+    kb = disc.kbar
+    s2 = SHEAR ** 2
+    ijk = w.cell_ijk(prob.mesh)
+    for P in range(disc.n_cells):
+        diag = 0.0
+        for Q in range(disc.n_cells):
+            di, dj = ijk[Q] - ijk[P]
+            if abs(di) + abs(dj) != 1:
+                assert Q == P or A[P, Q] == 0.0
+                continue
+            expect = kb * (1 + s2) if dj == 0 else kb
+            assert A[P, Q] == pytest.approx(expect, rel=1e-13)
+            diag -= expect
+        i, j = ijk[P]
+        diag -= 2 * kb * ((i == 0) + (i == n - 1)) * (1 + s2) + 2 * kb * ((j == 0) + (j == n - 1))
+        assert A[P, P] == pytest.approx(diag, rel=1e-13)
