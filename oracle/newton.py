@@ -114,5 +114,5 @@ def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
             stats["newton"] += 1
             if log:
                 log(inc, it, rn / r0, info["iters"], lam)
-        stats["increments"].append({"load": load, "newton": it, "rel": rn / r0 if r0 else 0.0})
+        stats["increments"].append({"load": load, "newton": it, "rel": rn / r0 if r0 else 0.0, "r0": r0})
     return u, stats

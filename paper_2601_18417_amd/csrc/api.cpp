@@ -28,8 +28,7 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
 hofv_status jvp_impl(hofv_ctx* c, const double* u, const double* Ru, const double* v, double* Jv, double eps,
                      hipStream_t st) {
   hofv_status s;
-  if ((s = launch_eps(c, u, v, eps, st))) return s;
-  if ((s = launch_axpy_w(c, u, v, st))) return s;
+  if ((s = launch_jvp_pack(c, u, v, eps, st))) return s;
   return launch_residual(c, c->dev.w, Jv, Ru, c->dev.eps, st);
 }
 
@@ -106,10 +105,7 @@ hofv_status hofv_destroy(hofv_ctx* c) {
     hipDeviceSynchronize();
   }
   for (void* p : c->allocations) hipFree(p);
-  for (auto& t : c->timers) {
-    hipEventDestroy(t.start);
-    hipEventDestroy(t.stop);
-  }
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   delete c;
   return HOFV_OK;
 }
@@ -511,11 +507,8 @@ hofv_status hofv_nn_forward(hofv_ctx* c, hofv_nn* m, const double* d_r, const do
 hofv_status hofv_set_timing(hofv_ctx* c, int32_t enable) {
   if (!c) return fail(nullptr, HOFV_EINVAL, "null context");
   if (c->device >= 0) hipDeviceSynchronize();
-  for (auto& t : c->timers) {
-    hipEventDestroy(t.start);
-    hipEventDestroy(t.stop);
-  }
   c->timers.clear();
+  c->ev_used = 0;
   c->timing = enable != 0;
   return HOFV_OK;
 }

@@ -30,6 +30,11 @@ constexpr int kBlockItems = HOFV_BLOCK_ITEMS;
 constexpr int kLdsFaceCells = HOFV_LDS_FACE;
 constexpr int kLdsCellCells = HOFV_LDS_CELL;
 
+// grid-wide sums: at most kRedParts block partials per value; fused
+// Gram-Schmidt passes handle up to kGsChunk basis vectors
+constexpr int kRedParts = 512;
+constexpr int kGsChunk = 32;
+
 // cell-face slot code for the face -> cell sum: f >= 0 owner side, ~f (< 0)
 // neighbour side, kNoFace for traction/unused slots
 constexpr int32_t kNoFace = INT32_MIN;
@@ -78,6 +83,7 @@ struct DeviceTables {
   double* flux = nullptr;        // [D][nf]
   double* w = nullptr;           // [nc][4 | 2] padded gather copy of u (or u + eps v)
   double* scratch = nullptr;     // reduction partials
+  double* part = nullptr;        // [3][kGsChunk][kRedParts] partials of the Krylov sums
   double* eps = nullptr;         // device scalar(s)
   int32_t* flag = nullptr;       // device error flags (NH inverted element)
   // preconditioner (colour-major numbering)
@@ -217,6 +223,8 @@ struct hofv_ctx {
   bool timing = false;
   bool use_mg = false;  // apply the approximate Jacobian by the V-cycle
   std::vector<hofv::TimerRec> timers;
+  std::vector<hipEvent_t> ev_pool;  // events of the timers, reused
+  size_t ev_used = 0;
   std::map<std::string, double> kernel_bytes;
 };
 
@@ -314,9 +322,7 @@ hofv_status build_multigrid(hofv_ctx* c, const std::vector<int64_t>& ptr, const 
 // kernel launchers (kernels.hip)
 hofv_status launch_residual(hofv_ctx* c, const double* u, double* R, const double* Ru,
                             const double* eps_dev, hipStream_t st);
-hofv_status launch_eps(hofv_ctx* c, const double* u, const double* v, double eps_host,
-                       hipStream_t st);
-hofv_status launch_axpy_w(hofv_ctx* c, const double* u, const double* v, hipStream_t st);
+hofv_status launch_jvp_pack(hofv_ctx* c, const double* u, const double* v, double eps_host, hipStream_t st);
 hofv_status launch_precond(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st);
 hofv_status launch_nej(hofv_ctx* c, const double* v, double* out, hipStream_t st);
 // krylov.hip: the near-exact Jacobian preconditioner

@@ -23,6 +23,7 @@
 #include <cfloat>
 
 #include "common.h"
+#include "reduce.h"
 
 namespace hofv {
 
@@ -498,70 +499,48 @@ __global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, con
 
 // ---- eps = sqrt((1 + ||u||) eps_mach) / ||v|| on the device -----------------
 
-constexpr int kRedBlocks = 512;
-
+// partials of ||u||^2 and ||v||^2: part[block], part[kRedParts + block]
 __global__ __launch_bounds__(kBlock) void k_sumsq2(int64_t n, const double* __restrict__ a,
                                                    const double* __restrict__ b, double* __restrict__ part) {
-  __shared__ double sa[kBlock], sb[kBlock];
-  double xa = 0.0, xb = 0.0;
+  __shared__ double sred[(kBlock / 64) * 2], sout[2];
+  double acc[2] = {0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
     const double x = a[i], y = b[i];
-    xa += x * x;
-    xb += y * y;
+    acc[0] += x * x;
+    acc[1] += y * y;
   }
-  sa[threadIdx.x] = xa;
-  sb[threadIdx.x] = xb;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sa[threadIdx.x] += sa[threadIdx.x + s];
-      sb[threadIdx.x] += sb[threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = sa[0];
-    part[kRedBlocks + blockIdx.x] = sb[0];
-  }
+  block_reduce<2, kBlock>(acc, sred, sout);
+  if (threadIdx.x < 2) part[threadIdx.x * kRedParts + blockIdx.x] = sout[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kBlock) void k_eps_final(const double* __restrict__ part, int nb,
-                                                      double* __restrict__ eps) {
-  __shared__ double sa[kBlock], sb[kBlock];
-  double xa = 0.0, xb = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kBlock) {
-    xa += part[i];
-    xb += part[kRedBlocks + i];
-  }
-  sa[threadIdx.x] = xa;
-  sb[threadIdx.x] = xb;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sa[threadIdx.x] += sa[threadIdx.x + s];
-      sb[threadIdx.x] += sb[threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const double nu = sqrt(sa[0]), nv = sqrt(sb[0]);
-    eps[0] = nv > 0.0 ? sqrt((1.0 + nu) * DBL_EPSILON) / nv : 0.0;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_set_scalar(double* p, double v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
-}
-
-// padded gather copy of u (+ eps v when v != null): ug[P][0..D) = u[.][P] + eps v[.][P]
+// Padded gather copy of u (+ eps v when v != null): ug[P][0..D) = u[.][P] + eps v[.][P].
+// eps is eps_host when nb == 0, else sqrt((1 + ||u||) eps_mach) / ||v|| (0 when
+// v = 0) from the nb block partials of k_sumsq2, added up by every block in
+// the same fixed order; block 0 stores it at eps_out for the cell sum.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_pack(int64_t nc, const double* __restrict__ u,
-                                                 const double* __restrict__ v, const double* __restrict__ eps,
+                                                 const double* __restrict__ v, double eps_host, int nb,
+                                                 const double* __restrict__ part, double* __restrict__ eps_out,
                                                  double* __restrict__ ug) {
   constexpr int W = D == 3 ? 4 : 2;
+  double e = eps_host;
+  if (v && nb > 0) {
+    __shared__ double sred[(kBlock / 64) * 2], sn[2];
+    double a[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int t = threadIdx.x;
+      double s = t < nb ? part[q * kRedParts + t] : 0.0;
+      if (t + kBlock < nb) s += part[q * kRedParts + t + kBlock];
+      a[q] = s;
+    }
+    block_reduce<2, kBlock>(a, sred, sn);
+    const double nu = sqrt(sn[0]), nv = sqrt(sn[1]);
+    e = nv > 0.0 ? sqrt((1.0 + nu) * DBL_EPSILON) / nv : 0.0;
+  }
+  if (v && blockIdx.x == 0 && threadIdx.x == 0) eps_out[0] = e;
   const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (P >= nc) return;
-  const double e = v ? eps[0] : 0.0;
   double x[W];
 #pragma unroll
   for (int c = 0; c < W; ++c) x[c] = 0.0;
@@ -749,16 +728,26 @@ __global__ __launch_bounds__(kBlock) void k_fill_f(int64_t n, float v, float* __
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// events come from a pool kept by the context (created once, reused after
+// every hofv_set_timing), so a timed launch costs two event records only
+static hipEvent_t pooled_event(hofv_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    hipEventCreate(&e);
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
 void timer_begin(hofv_ctx* c, const char* name, hipStream_t st, hipEvent_t* ev) {
   if (!c->timing) return;
-  hipEventCreate(ev);
+  *ev = pooled_event(c);
   hipEventRecord(*ev, st);
 }
 
 void timer_end(hofv_ctx* c, const char* name, hipStream_t st, hipEvent_t ev) {
   if (!c->timing) return;
-  hipEvent_t e2;
-  hipEventCreate(&e2);
+  hipEvent_t e2 = pooled_event(c);
   hipEventRecord(e2, st);
   c->timers.push_back({name, ev, e2});
 }
@@ -839,10 +828,10 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
 hofv_status launch_residual(hofv_ctx* c, const double* u, double* R, const double* Ru, const double* eps,
                             hipStream_t st) {
   // Ru == nullptr: R = R(u).  Otherwise u is the packed copy already made by
-  // launch_axpy_w (u + eps v) and R receives (R(u + eps v) - Ru) / eps.
+  // launch_jvp_pack (u + eps v) and R receives (R(u + eps v) - Ru) / eps.
   if (!Ru) {
-    if (c->D == 2) k_pack<2><<<blocks_for(c->nc), kBlock, 0, st>>>(c->nc, u, nullptr, nullptr, c->dev.w);
-    else k_pack<3><<<blocks_for(c->nc), kBlock, 0, st>>>(c->nc, u, nullptr, nullptr, c->dev.w);
+    if (c->D == 2) k_pack<2><<<blocks_for(c->nc), kBlock, 0, st>>>(c->nc, u, nullptr, 0.0, 0, nullptr, nullptr, c->dev.w);
+    else k_pack<3><<<blocks_for(c->nc), kBlock, 0, st>>>(c->nc, u, nullptr, 0.0, 0, nullptr, nullptr, c->dev.w);
   }
   const double* ug = c->dev.w;
   return c->D == 2 ? residual_impl<2>(c, ug, R, Ru, eps, st) : residual_impl<3>(c, ug, R, Ru, eps, st);
@@ -869,24 +858,21 @@ hofv_status launch_nej(hofv_ctx* c, const double* v, double* out, hipStream_t st
   return s;
 }
 
-hofv_status launch_eps(hofv_ctx* c, const double* u, const double* v, double eps_host, hipStream_t st) {
+// u + eps v into the gather copy, eps = eps_host if > 0, else from device norms
+// (k_sumsq2's partials, added up inside k_pack); eps lands in dev.eps
+hofv_status launch_jvp_pack(hofv_ctx* c, const double* u, const double* v, double eps_host, hipStream_t st) {
   DeviceTables& t = c->dev;
-  const int64_t n = (int64_t)c->D * c->nc;
-  if (eps_host > 0) {
-    k_set_scalar<<<1, kBlock, 0, st>>>(t.eps, eps_host);
-  } else {
-    const int nb = (int)std::min<int64_t>(kRedBlocks, blocks_for(n));
+  const int64_t nc = c->nc, n = (int64_t)c->D * nc;
+  int nb = 0;
+  if (!(eps_host > 0)) {
+    nb = (int)std::min<int64_t>(kRedParts, blocks_for(n));
     TIMED("k_sumsq2", (k_sumsq2<<<nb, kBlock, 0, st>>>(n, u, v, t.scratch)));
-    k_eps_final<<<1, kBlock, 0, st>>>(t.scratch, nb, t.eps);
   }
-  HOFV_HIP(c, hipGetLastError());
-  return HOFV_OK;
-}
-
-hofv_status launch_axpy_w(hofv_ctx* c, const double* u, const double* v, hipStream_t st) {
-  const int64_t nc = c->nc;
-  if (c->D == 2) TIMED("k_pack", (k_pack<2><<<blocks_for(nc), kBlock, 0, st>>>(nc, u, v, c->dev.eps, c->dev.w)));
-  else TIMED("k_pack", (k_pack<3><<<blocks_for(nc), kBlock, 0, st>>>(nc, u, v, c->dev.eps, c->dev.w)));
+  const double e = eps_host > 0 ? eps_host : 0.0;
+  if (c->D == 2)
+    TIMED("k_pack", (k_pack<2><<<blocks_for(nc), kBlock, 0, st>>>(nc, u, v, e, nb, t.scratch, t.eps, t.w)));
+  else
+    TIMED("k_pack", (k_pack<3><<<blocks_for(nc), kBlock, 0, st>>>(nc, u, v, e, nb, t.scratch, t.eps, t.w)));
   HOFV_HIP(c, hipGetLastError());
   return HOFV_OK;
 }

@@ -21,14 +21,14 @@
 
 #include "common.h"
 #include "givens.h"
+#include "reduce.h"
 
 namespace hofv {
 
 namespace {
 
 constexpr int kB = 256;
-constexpr int kDotChunk = 32;     // vectors per multi-dot launch (accumulators in registers)
-constexpr int kDotBlocks = 256;
+constexpr int kDotChunk = kGsChunk;  // vectors per multi-dot launch (accumulators in registers)
 constexpr int kMaxRestart = 2048;  // longest FGMRES cycle (slender bodies need long Krylov bases)
 constexpr int kCheck = 8;         // FGMRES iterations queued between host reads
 constexpr double kLearnedCycle = 0.75;  // slowest accepted residual reduction of a learned cycle
@@ -40,46 +40,112 @@ constexpr int kHcol = 0, kZz = kMaxRestart + 2, kBeta = kMaxRestart + 3, kH2 = k
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
 
-// part[i * kDotBlocks + block] = partial of sum_l V_i[l] w[l], i < nv
-__global__ __launch_bounds__(kB) void k_multidot(int64_t n, int nv, const double* __restrict__ V, int64_t ld,
-                                                 const double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double red[kB];
-  double acc[kDotChunk];
+// ---- grid-wide sums ----------------------------------------------------------
+// A grid-wide sum is done in two fixed-order stages: each of nb <= kRedParts
+// blocks reduces its elements (wavefront butterflies, then its wavefronts in
+// order; reduce.h) to one partial per value, part[i * kRedParts + block]; the
+// consumer of the sum (the next kernel) adds the partials of every block in
+// the same fixed order, so all its blocks agree on the total bit for bit.
+
+// partials of sum_l V_i[l] w[l], i < nv <= NV
+template <int NV>
+__global__ __launch_bounds__(kB) void k_dot(int64_t n, int nv, const double* __restrict__ V, int64_t ld,
+                                            const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sred[(kB / 64) * NV], sout[NV];
+  double acc[NV];
 #pragma unroll
-  for (int i = 0; i < kDotChunk; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   for (int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x; l < n; l += (int64_t)gridDim.x * kB) {
     const double x = w[l];
 #pragma unroll
-    for (int i = 0; i < kDotChunk; ++i)
+    for (int i = 0; i < NV; ++i)
       if (i < nv) acc[i] += V[(int64_t)i * ld + l] * x;
   }
-  for (int i = 0; i < nv; ++i) {
-    red[threadIdx.x] = acc[i];
-    __syncthreads();
-    for (int s = kB / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[i * kDotBlocks + blockIdx.x] = red[0];
-    __syncthreads();
-  }
+  block_reduce<NV, kB>(acc, sred, sout);
+  if ((int)threadIdx.x < nv) part[(int64_t)threadIdx.x * kRedParts + blockIdx.x] = sout[threadIdx.x];
 }
 
-// out[i] (+)= sum_b part[i][b] for i < nv, one block per i
-__global__ __launch_bounds__(kB) void k_reduce_parts(int nv, int nb, const double* __restrict__ part,
-                                                     double* __restrict__ out, int accumulate) {
-  __shared__ double red[kB];
-  const int i = blockIdx.x;
-  if (i >= nv) return;
-  double a = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kB) a += part[i * kDotBlocks + b];
-  red[threadIdx.x] = a;
-  __syncthreads();
-  for (int s = kB / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
+// out[i] = sum over the nb (<= 2 kB) partials of value i, for every thread of the block
+template <int NV>
+__device__ __attribute__((always_inline)) inline void reduce_parts(int nb, int nv, const double* __restrict__ part, double* sred, double* out) {
+  double a[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
+    if (i < nv) {
+      const int t = threadIdx.x;
+      if (t < nb) s = part[(int64_t)i * kRedParts + t];
+      if (t + kB < nb) s += part[(int64_t)i * kRedParts + t + kB];
+    }
+    a[i] = s;
   }
-  if (threadIdx.x == 0) out[i] = accumulate ? out[i] + red[0] : red[0];
+  block_reduce<NV, kB>(a, sred, out);
+}
+
+// out[i] (+)= the total of value i, i < nv (one block)
+template <int NV>
+__global__ __launch_bounds__(kB) void k_dot_final(int nb, int nv, const double* __restrict__ part,
+                                                  double* __restrict__ out, int accumulate) {
+  __shared__ double sred[(kB / 64) * NV], sout[NV];
+  reduce_parts<NV>(nb, nv, part, sred, sout);
+  if ((int)threadIdx.x < nv) out[threadIdx.x] = accumulate ? out[threadIdx.x] + sout[threadIdx.x] : sout[threadIdx.x];
+}
+
+// One fused classical Gram-Schmidt pass: h = the totals of part_in (the
+// previous pass's V^T w), w -= V h, and the partials of the new V^T w
+// (NORM = 0) or of w.w (NORM = 1) into part_out.  Block 0 stores h at hout.
+// Each V_i[l] is read once for both products.
+template <int NV, int NORM>
+__global__ __launch_bounds__(kB) void k_gs_pass(int64_t n, int nv, const double* __restrict__ V, int64_t ld, int nb_in,
+                                                const double* __restrict__ part_in, double* __restrict__ hout,
+                                                double* __restrict__ w, double* __restrict__ part_out) {
+  constexpr int NO = NORM ? 1 : NV;
+  __shared__ double sred[(kB / 64) * NV], h[NV], sout[NO];
+  reduce_parts<NV>(nb_in, nv, part_in, sred, h);
+  if (blockIdx.x == 0 && (int)threadIdx.x < nv) hout[threadIdx.x] = h[threadIdx.x];
+  double acc[NO];
+#pragma unroll
+  for (int i = 0; i < NO; ++i) acc[i] = 0.0;
+  for (int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x; l < n; l += (int64_t)gridDim.x * kB) {
+    double vv[NV];
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      vv[i] = i < nv ? V[(int64_t)i * ld + l] : 0.0;
+      s += h[i] * vv[i];
+    }
+    const double x = w[l] - s;
+    w[l] = x;
+    if constexpr (NORM) {
+      acc[0] += x * x;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += vv[i] * x;
+    }
+  }
+  block_reduce<NO, kB>(acc, sred, sout);
+  if ((int)threadIdx.x < (NORM ? 1 : nv)) part_out[(int64_t)threadIdx.x * kRedParts + blockIdx.x] = sout[threadIdx.x];
+}
+
+// Normalisation closing an Arnoldi step: ||w||^2 = the total of part_norm,
+// w /= ||w|| (0 if ||w|| = 0); block 0 writes Hessenberg column j: h_i =
+// first + second pass (i <= j), h_{j+1} = ||w||, and zz (a learned output's
+// squared norm).
+__global__ __launch_bounds__(kB) void k_gs_scale(int64_t n, int j, int nb, const double* __restrict__ part_norm,
+                                                 double* __restrict__ w, double* __restrict__ hd, int ldh,
+                                                 double* __restrict__ H, double* __restrict__ zz) {
+  __shared__ double sred[kB / 64], sn[1];
+  reduce_parts<1>(nb, 1, part_norm, sred, sn);
+  const double nrm = sqrt(sn[0]);
+  for (int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x; l < n; l += (int64_t)gridDim.x * kB)
+    w[l] = nrm > 0.0 ? w[l] / nrm : 0.0;
+  if (blockIdx.x != 0) return;
+  for (int i = threadIdx.x; i <= j; i += kB) H[(int64_t)j * ldh + i] = hd[kHcol + i] + hd[kH2 + i];
+  if (threadIdx.x == 0) {
+    hd[kHcol + j + 1] = sn[0];
+    H[(int64_t)j * ldh + j + 1] = nrm;
+    zz[j] = hd[kZz];
+  }
 }
 
 // w[l] += sign * sum_i h[i] V_i[l]
@@ -117,28 +183,61 @@ __global__ __launch_bounds__(kB) void k_fill_i(int n, int v, int32_t* __restrict
   if (l < n) z[l] = v;
 }
 
-// H[:, j] of the Arnoldi process from the Gram-Schmidt scalars: h_i = first +
-// second pass (i <= j), h_{j+1} = ||w||; zz (a learned output's squared norm) too
-__global__ void k_store_column(int j, const double* __restrict__ hd, int ldh, double* __restrict__ H,
-                               double* __restrict__ zz) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i <= j) H[(int64_t)j * ldh + i] = hd[kHcol + i] + hd[kH2 + i];
-  if (i == j + 1) H[(int64_t)j * ldh + i] = sqrt(hd[kHcol + j + 1]);
-  if (i == 0) zz[j] = hd[kZz];
-}
-
 }  // namespace
+
+// template argument for nv values: the smallest power of two >= nv (<= kGsChunk)
+#define HOFV_NV_DISPATCH(nv, CALL) \
+  do {                             \
+    if ((nv) <= 1) { constexpr int NVT = 1; CALL; }        \
+    else if ((nv) <= 2) { constexpr int NVT = 2; CALL; }   \
+    else if ((nv) <= 4) { constexpr int NVT = 4; CALL; }   \
+    else if ((nv) <= 8) { constexpr int NVT = 8; CALL; }   \
+    else if ((nv) <= 16) { constexpr int NVT = 16; CALL; } \
+    else { constexpr int NVT = 32; CALL; }                 \
+  } while (0)
+
+static int red_blocks(int64_t n) { return (int)std::min<int64_t>(kRedParts, nblk(n)); }
 
 // dots of x against nv rows of V (stride ld), kDotChunk rows per pass; result
 // on device in out[0..nv)
 static hofv_status dots(hofv_ctx* c, int64_t n, int nv, const double* V, int64_t ld, const double* x, double* out,
                         int accumulate, hipStream_t st) {
-  const int nb = (int)std::min<int64_t>(kDotBlocks, nblk(n));
+  const int nb = red_blocks(n);
+  double* part = c->dev.part;
   for (int c0 = 0; c0 < nv; c0 += kDotChunk) {
     const int nvc = std::min(kDotChunk, nv - c0);
-    k_multidot<<<nb, kB, 0, st>>>(n, nvc, V + (int64_t)c0 * ld, ld, x, c->dev.scratch);
-    k_reduce_parts<<<nvc, kB, 0, st>>>(nvc, nb, c->dev.scratch, out + c0, accumulate);
+    HOFV_NV_DISPATCH(nvc, (k_dot<NVT><<<nb, kB, 0, st>>>(n, nvc, V + (int64_t)c0 * ld, ld, x, part),
+                           k_dot_final<NVT><<<1, kB, 0, st>>>(nb, nvc, part, out + c0, accumulate)));
   }
+  HOFV_HIP(c, hipGetLastError());
+  return HOFV_OK;
+}
+
+// Arnoldi step j: w (= J z_j) is orthogonalised against V_0..V_j by classical
+// Gram-Schmidt applied twice and normalised; Hessenberg column j goes to
+// H[j ldh ..] (h_i = first + second pass), the Gram-Schmidt scalars to hd.
+// Up to kGsChunk basis vectors the passes are fused (dot; axpy + dot;
+// axpy + norm; scale: four launches, the basis read three times); longer
+// bases take chunked dots and separate axpys.
+static hofv_status cgs2(hofv_ctx* c, int64_t n, int j, const double* V, double* w, double* hd, double* H, int ldh,
+                        double* zz, hipStream_t st) {
+  const int nv = j + 1, nb = red_blocks(n);
+  double* pA = c->dev.part;
+  double* pB = pA + (size_t)kGsChunk * kRedParts;
+  double* pC = pB + (size_t)kGsChunk * kRedParts;
+  if (nv <= kGsChunk) {
+    HOFV_NV_DISPATCH(nv, (k_dot<NVT><<<nb, kB, 0, st>>>(n, nv, V, n, w, pA),
+                          k_gs_pass<NVT, 0><<<nb, kB, 0, st>>>(n, nv, V, n, nb, pA, hd + kHcol, w, pB),
+                          k_gs_pass<NVT, 1><<<nb, kB, 0, st>>>(n, nv, V, n, nb, pB, hd + kH2, w, pC)));
+  } else {
+    hofv_status s;
+    if ((s = dots(c, n, nv, V, n, w, hd + kHcol, 0, st))) return s;
+    k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, nv, V, n, hd + kHcol, -1.0, w);
+    if ((s = dots(c, n, nv, V, n, w, hd + kH2, 0, st))) return s;
+    k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, nv, V, n, hd + kH2, -1.0, w);
+    k_dot<1><<<nb, kB, 0, st>>>(n, 1, w, n, w, pC);
+  }
+  k_gs_scale<<<nb, kB, 0, st>>>(n, j, nb, pC, w, hd, ldh, H, zz);
   HOFV_HIP(c, hipGetLastError());
   return HOFV_OK;
 }
@@ -280,15 +379,7 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
         if (learned && (s = dots(c, n, 1, zj, n, zj, hd + kZz, 0, st))) return s;
         if ((s = jvp_impl(c, u, Ru, zj, w, 0.0, st))) return s;
       }
-      // CGS2
-      if ((s = dots(c, n, j + 1, K.V, n, w, hd, 0, st))) return s;
-      k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd, -1.0, w);
-      if ((s = dots(c, n, j + 1, K.V, n, w, hd + kH2, 0, st))) return s;
-      k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, K.V, n, hd + kH2, -1.0, w);
-      if ((s = dots(c, n, 1, w, n, w, hd + j + 1, 0, st))) return s;
-      k_scale_by<<<nblk(n), kB, 0, st>>>(n, w, hd + j + 1, 1, w);
-      k_store_column<<<(unsigned)((j + 2 + kB - 1) / kB), kB, 0, st>>>(j, hd, m + 1, K.Hd, K.zz);
-      HOFV_HIP(c, hipGetLastError());
+      if ((s = cgs2(c, n, j, K.V, w, hd, K.Hd, m + 1, K.zz, st))) return s;
       ++j;
       if (j - jp < kCheck && j < m && it + (j - jp) < maxit) continue;
       const int nq = j - jp;
@@ -406,13 +497,7 @@ hofv_status nej_solve(hofv_ctx* c, const double* r, double* z, int sweeps, hipSt
     double* w = N.V + (size_t)(j + 1) * n;
     if ((s = launch_precond(c, vj, N.t, sweeps, st))) return s;
     if ((s = launch_nej(c, N.t, w, st))) return s;
-    if ((s = dots(c, n, j + 1, N.V, n, w, hd, 0, st))) return s;
-    k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, N.V, n, hd, -1.0, w);
-    if ((s = dots(c, n, j + 1, N.V, n, w, hd + kH2, 0, st))) return s;
-    k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, j + 1, N.V, n, hd + kH2, -1.0, w);
-    if ((s = dots(c, n, 1, w, n, w, hd + j + 1, 0, st))) return s;
-    k_scale_by<<<nblk(n), kB, 0, st>>>(n, w, hd + j + 1, 1, w);
-    k_store_column<<<(unsigned)((j + 2 + kB - 1) / kB), kB, 0, st>>>(j, hd, k + 1, N.Hd, N.zz);
+    if ((s = cgs2(c, n, j, N.V, w, hd, N.Hd, k + 1, N.zz, st))) return s;
   }
   HOFV_HIP(c, hipGetLastError());
   N.hbuf.resize((size_t)(k + 1) * k + 1);

@@ -568,7 +568,8 @@ hofv_status build_tables(hofv_ctx* c) {
   if ((st = dev_alloc(c, &t.ustar, (size_t)NS * D * nc))) return st;
   if ((st = dev_alloc(c, &t.flux, (size_t)D * nf))) return st;
   if ((st = dev_alloc(c, &t.w, (size_t)(D == 3 ? 4 : 2) * nc))) return st;  // padded gather copy
-  if ((st = dev_alloc(c, &t.scratch, 16384))) return st;  // >= 32 dot partials x 256 blocks
+  if ((st = dev_alloc(c, &t.scratch, 16384))) return st;  // >= 2 x 512 partials of the J.v norms
+  if ((st = dev_alloc(c, &t.part, (size_t)3 * kGsChunk * kRedParts))) return st;
   if ((st = dev_alloc(c, &t.eps, 8))) return st;
   if ((st = dev_alloc(c, &t.flag, 8))) return st;
   if ((st = dev_alloc(c, &t.p_r, (size_t)D * nc))) return st;

@@ -39,6 +39,8 @@ def _flux_scale(disc, u):
     np.add.at(s, disc.f_own, np.abs(Ff))
     np.add.at(s, disc.f_nei, np.abs(Ff))
     np.add.at(s, disc.d_own, np.abs(Fd))
+    if disc.s_own is not None:
+        np.add.at(s, disc.s_own, np.abs(ores.symmetry_fluxes(disc, u)))
     return s + np.abs(disc.b_body + disc.b_trac)
 
 
@@ -77,8 +79,11 @@ def test_residual_parity(name, fold):
         ctx.residual(to_dev(u), R)
         torch.cuda.synchronize()
         Ro = ores.residual(disc, u)
-        rel = np.linalg.norm(to_host(R) - Ro) / np.linalg.norm(Ro)
+        Rg = to_host(R)
+        rel = np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)
         assert rel <= 1e-10, (name, seed, rel)
+        # and cell by cell, against the size of what the cell sums
+        assert np.all(np.abs(Rg - Ro) <= 1e-10 * _flux_scale(disc, u)), (name, seed)
     # near the manufactured solution
     if prob.loads.exact is not None:
         u = prob.loads.exact.value(disc.cen)
@@ -143,6 +148,26 @@ def test_residual_is_deterministic():
     ctx.residual(ud, R2)
     torch.cuda.synchronize()
     assert torch.equal(R1, R2)
+
+
+def test_fgmres_is_deterministic():
+    """The Krylov sums are fixed-order reductions: two solves of the same
+    system give identical bits."""
+    prob = CASES["cube8_p2_pert"]()
+    ctx = _api().context_for(prob)
+    n = prob.mesh.n_cells
+    ud = to_dev(w.random_state(n, 3, seed=9))
+    Ru = torch.empty_like(ud)
+    ctx.residual(ud, Ru)
+    b = to_dev(w.random_state(n, 3, seed=10, scale=1.0))
+    xs = []
+    for _ in range(2):
+        x = torch.zeros_like(b)
+        st = ctx.fgmres_solve(ud, Ru, b, x, rtol=1e-8, max_iters=400, restart=40)
+        assert st["converged"]
+        xs.append(x)
+    torch.cuda.synchronize()
+    assert torch.equal(xs[0], xs[1])
 
 
 def test_neo_hookean_residual_and_jvp_parity():

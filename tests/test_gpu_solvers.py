@@ -161,10 +161,11 @@ def test_newton_square_mms_matches_oracle():
     st = ctx.newton_solve(u, tol=1e-10, eta=1e-4)
     assert st["converged"] and st["newton_iters"] <= 4
     ug = to_host(u)
+    tol = 1e-10
     R0 = np.linalg.norm(ores.residual(disc, np.zeros((n, 2))))
-    assert np.linalg.norm(ores.residual(disc, ug)) <= 1.01e-10 * R0 * 1.5
-    uo, _ = onw.newton(disc, np.zeros((n, 2)), tol=1e-10, eta=1e-4)
-    assert np.linalg.norm(ug - uo) <= 1e-8 * np.linalg.norm(uo)
+    assert np.linalg.norm(ores.residual(disc, ug)) <= 1.01 * tol * R0
+    uo, _ = onw.newton(disc, np.zeros((n, 2)), tol=tol, eta=1e-4)
+    assert np.linalg.norm(ug - uo) <= 100 * tol * np.linalg.norm(uo)
     ue = prob.loads.exact.value(disc.cen)
     assert np.sqrt(np.mean(np.sum((ug - ue) ** 2, 1))) < 2e-3
 
@@ -184,10 +185,13 @@ def test_newton_neo_hookean_block_matches_oracle(ls_max):
     st = ctx.newton_solve(u, tol=1e-8, eta=1e-4, n_increments=3, max_line_search=ls_max)
     assert st["converged"]
     ug = to_host(u)
-    uo, _ = onw.newton(disc, np.zeros((n, 3)), tol=1e-8, eta=1e-4, n_increments=3, ls_max=ls_max)
-    assert np.linalg.norm(ug - uo) <= 1e-5 * np.linalg.norm(uo)
-    R0 = np.linalg.norm(ores.residual(disc, np.zeros((n, 3))))
-    assert np.linalg.norm(ores.residual(disc, ug)) <= 1e-7 * R0
+    tol = 1e-8
+    uo, ost = onw.newton(disc, np.zeros((n, 3)), tol=tol, eta=1e-4, n_increments=3, ls_max=ls_max)
+    assert np.linalg.norm(ug - uo) <= 100 * tol * np.linalg.norm(uo)
+    # the last increment's reference: ||R|| of the previous increment's state at
+    # full load (the oracle's; the GPU's agrees to the solve tolerance)
+    r0_last = ost["increments"][-1]["r0"]
+    assert np.linalg.norm(ores.residual(disc, ug)) <= 1.01 * tol * r0_last
 
 
 MG_CASES = [lambda: w.cube_mms(12, 2, perturb=0.2),
