@@ -211,6 +211,20 @@ hofv_status hofv_residual(hofv_ctx* ctx, const double* d_u, double* d_R, void* s
 hofv_status hofv_jvp(hofv_ctx* ctx, const double* d_u, const double* d_Ru, const double* d_v,
                      double* d_Jv, double eps, void* stream);
 
+/* hofv_jvp for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same product and arguments, with the block partial sums of the device eps
+ * (eps <= 0) and eps itself kept in a library-wide static device array of
+ * 2048 doubles (16 KiB) per GPU instead of the context's buffers; one call
+ * needs 2 min(512, ceil(dim n_cells / 256)) + 1 of them, at most 1025, so every
+ * mesh fits (HOFV_EINVAL otherwise).  The call makes no hipMalloc/hipFree and
+ * records no timing events.  All calls on one GPU share the array and
+ * overwrite it (nothing in it has to start at zero): calls that overlap on one
+ * GPU, from concurrent streams or threads, race.  Needs hofv_setup, which
+ * looks up the array's address on the context's device (HOFV_ESTATE before). */
+hofv_status hofv_jvp_noalloc(hofv_ctx* ctx, const double* d_u, const double* d_Ru, const double* d_v,
+                             double* d_Jv, double eps, void* stream);
+
 /* z ~ P^{-1} r with P the compact approximate Jacobian (Sec. 4.1): n_sweeps
  * symmetric multicolour Gauss-Seidel sweeps in FP32 from z = 0, or the
  * V-cycle (hofv_set_multigrid).  learned != 0 adds the network correction

@@ -78,6 +78,7 @@ SIGNATURES = {
     "hofv_nej_apply": (ST, [P, P, P, P]),
     "hofv_residual": (ST, [P, P, P, P]),
     "hofv_jvp": (ST, [P, P, P, P, P, C.c_double, P]),
+    "hofv_jvp_noalloc": (ST, [P, P, P, P, P, C.c_double, P]),
     "hofv_precond_apply": (ST, [P, P, P, C.c_int32, C.c_int32, P]),
     "hofv_fgmres_solve": (ST, [P, P, P, P, P, C.POINTER(KrylovOpts), C.POINTER(KrylovStats), P]),
     "hofv_newton_solve": (ST, [P, P, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), P]),

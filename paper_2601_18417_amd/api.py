@@ -166,6 +166,12 @@ class Context:
         self._check(self.lib.hofv_jvp(self.h, self._v(u), self._v(Ru), self._v(v), self._v(Jv), float(eps),
                                       _stream(stream)))
 
+    def jvp_noalloc(self, u, Ru, v, Jv, eps=0.0, stream=None):
+        """jvp with its reduction scratch in the library's static device array
+        (no device allocation in the call)."""
+        self._check(self.lib.hofv_jvp_noalloc(self.h, self._v(u), self._v(Ru), self._v(v), self._v(Jv),
+                                              float(eps), _stream(stream)))
+
     def nej_apply(self, v, out, stream=None):
         """out = A v for the near-exact Jacobian A (linear elastic law)."""
         self._check(self.lib.hofv_nej_apply(self.h, self._v(v), self._v(out), _stream(stream)))

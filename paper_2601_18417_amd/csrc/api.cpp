@@ -224,6 +224,7 @@ hofv_status hofv_setup(hofv_ctx* c, hofv_setup_report* rep) {
   }
   if (!c->prm.host_only && (s = set_device(c))) return s;
   if ((s = build_tables(c))) return s;
+  if (!c->prm.host_only && (s = noalloc_init(c))) return s;
   c->state = c->prm.host_only ? 5 : 4;
   if (rep) *rep = c->report;
   return HOFV_OK;
@@ -310,6 +311,19 @@ hofv_status hofv_jvp(hofv_ctx* c, const double* d_u, const double* d_Ru, const d
   if (!std::isfinite(eps)) return fail(c, HOFV_EINVAL, "eps must be finite");
   if ((s = set_device(c))) return s;
   return jvp_impl(c, d_u, d_Ru, d_v, d_Jv, eps, (hipStream_t)stream);
+}
+
+hofv_status hofv_jvp_noalloc(hofv_ctx* c, const double* d_u, const double* d_Ru, const double* d_v, double* d_Jv,
+                             double eps, void* stream) {
+  hofv_status s = need(c, 4, "jvp_noalloc");
+  if (s) return s;
+  if (!d_u || !d_Ru || !d_v || !d_Jv) return fail(c, HOFV_EINVAL, "null pointer");
+  if ((const void*)d_Jv == (const void*)d_u || (const void*)d_Jv == (const void*)d_Ru ||
+      (const void*)d_Jv == (const void*)d_v)
+    return fail(c, HOFV_EINVAL, "Jv must not alias the inputs");
+  if (!std::isfinite(eps)) return fail(c, HOFV_EINVAL, "eps must be finite");
+  if ((s = set_device(c))) return s;
+  return jvp_noalloc_impl(c, d_u, d_Ru, d_v, d_Jv, eps, (hipStream_t)stream);
 }
 
 hofv_status hofv_precond_apply(hofv_ctx* c, const double* d_r, double* d_z, int32_t n_sweeps, int32_t learned,

@@ -323,6 +323,10 @@ hofv_status build_multigrid(hofv_ctx* c, const std::vector<int64_t>& ptr, const 
 hofv_status launch_residual(hofv_ctx* c, const double* u, double* R, const double* Ru,
                             const double* eps_dev, hipStream_t st);
 hofv_status launch_jvp_pack(hofv_ctx* c, const double* u, const double* v, double eps_host, hipStream_t st);
+// J.v whose eps reduction lives in a static device array (no allocation)
+hofv_status noalloc_init(hofv_ctx* c);
+hofv_status jvp_noalloc_impl(hofv_ctx* c, const double* u, const double* Ru, const double* v, double* Jv,
+                             double eps_host, hipStream_t st);
 hofv_status launch_precond(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st);
 hofv_status launch_nej(hofv_ctx* c, const double* v, double* out, hipStream_t st);
 // krylov.hip: the near-exact Jacobian preconditioner

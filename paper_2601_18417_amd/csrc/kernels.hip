@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <map>
+#include <mutex>
 
 #include "common.h"
 #include "reduce.h"
@@ -875,6 +877,65 @@ hofv_status launch_jvp_pack(hofv_ctx* c, const double* u, const double* v, doubl
     TIMED("k_pack", (k_pack<3><<<blocks_for(nc), kBlock, 0, st>>>(nc, u, v, e, nb, t.scratch, t.eps, t.w)));
   HOFV_HIP(c, hipGetLastError());
   return HOFV_OK;
+}
+
+// ---- J.v without library allocations ---------------------------------------
+// hofv_jvp_noalloc keeps the partial sums of its device eps and eps itself in
+// this file-scope array instead of the context's buffers.  Each GPU holds one
+// copy until the process ends, and every call on that GPU shares it.  In host
+// code `scratch` names a host-side stand-in: kernels get the device address
+// that noalloc_init looked up, never the name itself.
+constexpr int64_t kNoAllocDoubles = 2048;  // 16 KiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+std::mutex g_noalloc_mu;
+std::map<int, double*> g_noalloc_ptr;  // device -> address of `scratch` on it
+}  // namespace
+
+// Looks up the device address of `scratch` on the context's device (current
+// here), once per device.  Called by hofv_setup.
+hofv_status noalloc_init(hofv_ctx* c) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr.count(c->device)) return HOFV_OK;
+  double* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(c, HOFV_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_noalloc_ptr[c->device] = p;
+  return HOFV_OK;
+}
+
+// The J.v of jvp_impl with the eps partials (2 x nb) and eps in `scratch`;
+// no allocation and no timing events.
+hofv_status jvp_noalloc_impl(hofv_ctx* c, const double* u, const double* Ru, const double* v, double* Jv,
+                             double eps_host, hipStream_t st) {
+  double* buf = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc_ptr.find(c->device);
+    if (it != g_noalloc_ptr.end()) buf = it->second;
+  }
+  if (!buf) return fail(c, HOFV_ESTATE, "the static scratch of this device was not looked up (hofv_setup)");
+  const int64_t nc = c->nc, n = (int64_t)c->D * nc;
+  const int nb = eps_host > 0 ? 0 : (int)std::min<int64_t>(kRedParts, blocks_for(n));
+  // partials [2][kRedParts] then eps
+  const int64_t need = 2 * (int64_t)kRedParts + 1;
+  if (need > kNoAllocDoubles)
+    return fail(c, HOFV_EINVAL, "the J.v reduction needs more than the 2048-double static scratch");
+  double* part = buf;
+  double* eps_dev = buf + 2 * kRedParts;
+  DeviceTables& t = c->dev;
+  if (nb > 0) k_sumsq2<<<nb, kBlock, 0, st>>>(n, u, v, part);
+  const double e = eps_host > 0 ? eps_host : 0.0;
+  if (c->D == 2) k_pack<2><<<blocks_for(nc), kBlock, 0, st>>>(nc, u, v, e, nb, part, eps_dev, t.w);
+  else k_pack<3><<<blocks_for(nc), kBlock, 0, st>>>(nc, u, v, e, nb, part, eps_dev, t.w);
+  HOFV_HIP(c, hipGetLastError());
+  const bool timing = c->timing;  // timing events could be created on first use
+  c->timing = false;
+  const hofv_status s = launch_residual(c, t.w, Jv, Ru, eps_dev, st);
+  c->timing = timing;
+  return s;
 }
 
 // s symmetric multicolour Gauss-Seidel sweeps on level 0, continuing from p_z:
