@@ -255,17 +255,16 @@ def study(args):
                 tp = w.cube_mms(args.learned_size, args.p, perturb=0.2, seed=seed)
                 tctx = api.context_for(tp)
             u0 = torch.zeros((3, tp.mesh.n_cells), device=dev, dtype=torch.float64)
-            r1, e1 = lrn.harvest_krylov(tctx, u0, n_starts=args.harvest_starts, length=args.harvest_length, seed=seed,
-                                        restart=args.restart)
-            r2, e2 = lrn.harvest_newton(tctx, u0, n_steps=2, restart=args.restart)
-            data.append((tctx, torch.cat([r1, r2]), torch.cat([e1, e2])))
-            log(f"harvested seed {seed}: {data[-1][1].shape[0]} pairs, {time.perf_counter() - t0:.0f}s")
+            data.append(lrn.harvest(tctx, u0, n_starts=args.harvest_starts, length=args.harvest_length,
+                                    newton_steps=2, seed=seed, restart=args.restart))
+            log(f"harvested seed {seed}: {len(data[-1])} pairs, {time.perf_counter() - t0:.0f}s")
         t_harvest = time.perf_counter() - t0
         model = api.Model(7)
-        hist = lrn.train(model, data, epochs=args.learned_epochs, lr=2e-3, batch=4,
-                         log=lambda ep, l: log(f"epoch {ep} loss {l:.4f}"))
-        np.save(args.model, model.get_params())
-        out = {"study": "train", "pairs": int(sum(d[1].shape[0] for d in data)),
+        hist = lrn.train(model, data, epochs=args.learned_epochs, lr=2e-3, batch=4)
+        for ep, l in enumerate(hist):
+            log(f"epoch {ep} loss {l:.4f}")
+        model.save(args.model)
+        out = {"study": "train", "pairs": int(sum(len(d) for d in data)),
                "meshes": (f"{args.learned_size}x{args.learned_size // 10}x{args.learned_size // 10} p={args.p} "
                           f"perturbed neo-Hookean beams (V-cycle inputs)" if args.workload == "cantilever" else
                           f"{args.learned_size}^3 p={args.p} perturbed cubes") + f", seeds {args.train_seeds}",
@@ -274,7 +273,7 @@ def study(args):
                "loss_last_epoch": hist[-1], "model": args.model}
     else:
         model = api.Model(0)
-        model.set_params(np.load(args.model))
+        model.load(args.model)
         t0 = time.perf_counter()
         if args.workload == "cantilever":
             prob = w.cantilever(p=args.p)
@@ -365,7 +364,8 @@ def main():
     ap.add_argument("--train-seeds", default="0-49")
     ap.add_argument("--harvest-starts", type=int, default=4)
     ap.add_argument("--harvest-length", type=int, default=9)
-    ap.add_argument("--model", default="learned_model.npy", help="weights file written by --study train, read by eval")
+    ap.add_argument("--model", default="learned_model.hofvnn",
+                    help="weights file (hofv_nn_save format) written by --study train, read by eval")
     ap.add_argument("--seed", type=int, default=50, help="mesh seed of --study eval")
     ap.add_argument("--max-newton", type=int, default=10, help="Newton steps per increment in --study eval")
     ap.add_argument("--eta", type=float, default=None,
@@ -579,9 +579,7 @@ def main():
                 tp = w.cube_mms(args.learned_size, args.p, perturb=0.2, seed=seed)
                 tctx = api.context_for(tp)
                 u0 = torch.zeros((3, tp.mesh.n_cells), device=dev, dtype=torch.float64)
-                r1, e1 = lrn.harvest_krylov(tctx, u0, n_starts=4, length=6, seed=seed)
-                r2, e2 = lrn.harvest_newton(tctx, u0, n_steps=2)
-                data.append((tctx, torch.cat([r1, r2]), torch.cat([e1, e2])))
+                data.append(lrn.harvest(tctx, u0, n_starts=4, length=6, newton_steps=2, seed=seed))
             t_harvest = time.perf_counter() - t0
             model = api.Model(7)
             hist = lrn.train(model, data, epochs=args.learned_epochs, lr=2e-3, batch=4)
@@ -590,7 +588,7 @@ def main():
             newton(True)
             solve["learned"] = newton(True)
             solve["learned_training"] = {
-                "pairs": int(sum(d[1].shape[0] for d in data)), "meshes": f"3 x {args.learned_size}^3 p={args.p} "
+                "pairs": int(sum(len(d) for d in data)), "meshes": f"3 x {args.learned_size}^3 p={args.p} "
                 "perturbed cubes, seeds 1-3", "epochs": args.learned_epochs, "harvest_seconds": t_harvest,
                 "train_seconds": t_train, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
             solve["learned_speedup"] = solve["plain"]["seconds"] / solve["learned"]["seconds"]

@@ -397,6 +397,83 @@ hofv_status hofv_nn_gradient(hofv_ctx* ctx, hofv_nn* nn, const double* d_r, cons
 hofv_status hofv_nn_forward(hofv_ctx* ctx, hofv_nn* nn, const double* d_r, const double* d_zaj, double* d_z,
                             void* stream);
 
+/* Writes the FP32 parameters to a file: the 8 bytes "HOFVNN01", the int64
+ * parameter count, then that many float32 values (host byte order).
+ * Synchronises.  HOFV_EINVAL if the file cannot be written. */
+hofv_status hofv_nn_save(hofv_nn* nn, const char* path);
+
+/* Reads a file written by hofv_nn_save into the model (its count must equal
+ * hofv_nn_param_count(); HOFV_EINVAL otherwise) and resets the Adam state. */
+hofv_status hofv_nn_load(hofv_nn* nn, const char* path);
+
+/* ---- training pairs and the training loop --------------------------------
+ * The network is trained on pairs (r, e) with J(u) e = r that the solver
+ * produces itself (the learned correction is not part of the paper).  A pair
+ * set holds up to `capacity` pairs on one context's mesh: device vectors
+ * [capacity][dim][n_cells] FP64 for r and for e, owned by the set, which must
+ * be destroyed before its context. */
+typedef struct hofv_pairset hofv_pairset;
+hofv_status hofv_pairset_create(hofv_ctx* ctx, int32_t capacity, hofv_pairset** out);
+hofv_status hofv_pairset_destroy(hofv_pairset* set);
+/* Pairs held and device pointers to r and e ([n_pairs][dim][n_cells], valid
+ * until the set is destroyed). */
+hofv_status hofv_pairset_data(const hofv_pairset* set, int32_t* n_pairs, const double** d_r, const double** d_e);
+/* Copies pairs first .. first + count - 1 into caller device buffers
+ * [count][dim][n_cells] (either may be NULL); ordered on `stream`.
+ * HOFV_EINVAL outside 0 .. n_pairs. */
+hofv_status hofv_pairset_copy(const hofv_pairset* set, int32_t first, int32_t count, double* d_r, double* d_e,
+                              void* stream);
+
+typedef struct {
+  int32_t n_starts;      /* Krylov-type sequences */
+  int32_t length;        /* pairs per sequence */
+  int32_t newton_steps;  /* Newton pairs */
+  uint64_t seed;         /* start vectors drawn when d_starts is NULL */
+  double rtol;           /* each e solved by FGMRES to ||r - J e|| <= rtol ||r|| */
+  int32_t restart, max_iters, n_sweeps;  /* of those FGMRES solves (plain preconditioner) */
+} hofv_harvest_opts;
+
+/* Appends training pairs at the state d_u (device [dim][n_cells]) to `set`,
+ * each e solved with the context's plain preconditioner (the sweeps, or the
+ * V-cycle when selected):
+ *  - Krylov-type: for each start s, v_0 = b_s / ||b_s|| and
+ *    v_{k+1} = J M v_k / ||J M v_k||, k < length (the vectors FGMRES feeds the
+ *    preconditioner), pairs (v_k, e_k) with J e_k = v_k; b_s is
+ *    d_starts + s dim n_cells when d_starts is given, else standard normal
+ *    values by Box-Muller from consecutive outputs k = 1, 2, ... of the
+ *    splitmix64 generator (Steele, Lea and Flood) seeded with seed + s 2^40,
+ *    two values per pair of outputs;
+ *  - Newton: from u_0 = d_u, e_k with J(u_k) e_k = R(u_k) and the pair
+ *    (R(u_k), e_k) / ||R(u_k)||, u_{k+1} = u_k - e_k, k < newton_steps.
+ * FGMRES solves that miss rtol are kept (their e is the best iterate).
+ * HOFV_EINVAL if the pairs do not fit the set's capacity (nothing is added).
+ * Synchronises. */
+hofv_status hofv_harvest_pairs(hofv_ctx* ctx, const double* d_u, const double* d_starts,
+                               const hofv_harvest_opts* opts, hofv_pairset* set, void* stream);
+
+typedef struct {
+  int32_t epochs;
+  int32_t batch;         /* pairs per optimisation step, all from one set */
+  double lr;             /* Adam step */
+  int32_t n_sweeps;      /* plain preconditioner sweeps inside the loss */
+  uint64_t seed;         /* order of the pairs and of the minibatches */
+  double* epoch_loss;    /* optional host array [epochs]: mean loss per epoch */
+} hofv_train_opts;
+
+typedef struct {
+  int32_t steps;         /* optimisation steps taken */
+  double loss_first, loss_last;  /* mean loss of the first and last epoch */
+  double seconds;
+} hofv_train_stats;
+
+/* Trains nn over n_sets pair sets (each on its own context; the contexts may
+ * differ in mesh and dimension): every epoch cuts each set, in a seeded
+ * random order, into minibatches of `batch` pairs and takes one
+ * hofv_nn_train_step on each minibatch, the minibatches of all sets in a
+ * seeded random order (splitmix64, Fisher-Yates).  Synchronises. */
+hofv_status hofv_nn_train(hofv_nn* nn, int32_t n_sets, hofv_pairset* const* sets, const hofv_train_opts* opts,
+                          hofv_train_stats* stats, void* stream);
+
 /* Per-kernel timing with HIP events recorded on the launch stream around
  * every kernel while enabled.  hofv_kernel_time synchronises and returns the
  * summed milliseconds and launch count of the kernel called `name` since the

@@ -49,6 +49,22 @@ class NewtonOpts(C.Structure):
                 ("forcing", C.c_int32), ("predictor", C.c_int32)]
 
 
+class HarvestOpts(C.Structure):
+    _fields_ = [("n_starts", C.c_int32), ("length", C.c_int32), ("newton_steps", C.c_int32),
+                ("seed", C.c_uint64), ("rtol", C.c_double), ("restart", C.c_int32), ("max_iters", C.c_int32),
+                ("n_sweeps", C.c_int32)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("n_sweeps", C.c_int32),
+                ("seed", C.c_uint64), ("epoch_loss", C.POINTER(C.c_double))]
+
+
+class TrainStats(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("loss_first", C.c_double), ("loss_last", C.c_double),
+                ("seconds", C.c_double)]
+
+
 class NewtonStats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("krylov_iters", C.c_int32), ("converged", C.c_int32),
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("fallbacks", C.c_int32)]
@@ -97,6 +113,14 @@ SIGNATURES = {
     "hofv_nn_train_step": (ST, [P, P, P, P, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_double), P]),
     "hofv_nn_gradient": (ST, [P, P, P, P, P, C.POINTER(C.c_float), C.POINTER(C.c_double), P]),
     "hofv_nn_forward": (ST, [P, P, P, P, P, P]),
+    "hofv_nn_save": (ST, [P, C.c_char_p]),
+    "hofv_nn_load": (ST, [P, C.c_char_p]),
+    "hofv_pairset_create": (ST, [P, C.c_int32, C.POINTER(P)]),
+    "hofv_pairset_destroy": (ST, [P]),
+    "hofv_pairset_data": (ST, [P, C.POINTER(C.c_int32), C.POINTER(P), C.POINTER(P)]),
+    "hofv_pairset_copy": (ST, [P, C.c_int32, C.c_int32, P, P, P]),
+    "hofv_harvest_pairs": (ST, [P, P, P, C.POINTER(HarvestOpts), P, P]),
+    "hofv_nn_train": (ST, [P, C.c_int32, C.POINTER(P), C.POINTER(TrainOpts), C.POINTER(TrainStats), P]),
     "hofv_host_table": (ST, [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(P)]),
 }
 

@@ -297,6 +297,54 @@ class Model:
         if st != L.HOFV_OK:
             raise HofvError(st, self.lib.hofv_last_error(None).decode())
 
+    def save(self, path):
+        st = self.lib.hofv_nn_save(self.h, str(path).encode())
+        if st != L.HOFV_OK:
+            raise HofvError(st, self.lib.hofv_last_error(None).decode())
+
+    def load(self, path):
+        st = self.lib.hofv_nn_load(self.h, str(path).encode())
+        if st != L.HOFV_OK:
+            raise HofvError(st, self.lib.hofv_last_error(None).decode())
+
+
+class PairSet:
+    """Training pairs (r, e), J e = r, on one context's mesh (hofv_pairset)."""
+
+    def __init__(self, ctx, capacity):
+        self.lib = ctx.lib
+        self.ctx = ctx  # the set must not outlive its context
+        h = C.c_void_p()
+        ctx._check(self.lib.hofv_pairset_create(ctx.h, int(capacity), C.byref(h)))
+        self.h = h
+        self.capacity = int(capacity)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hofv_pairset_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        n = C.c_int32()
+        self.lib.hofv_pairset_data(self.h, C.byref(n), None, None)
+        return n.value
+
+    def tensors(self, stream=None):
+        """Copies of (r, e) as torch tensors [n_pairs, dim, n_cells]."""
+        import torch
+        n = len(self)
+        r = torch.empty((n, self.ctx.dim, self.ctx.n_cells), dtype=torch.float64, device="cuda")
+        e = torch.empty_like(r)
+        if n:
+            self.ctx._check(self.lib.hofv_pairset_copy(self.h, 0, n, _ptr(r), _ptr(e), _stream(stream)))
+        return r, e
+
 
 def _ctx_nn_methods():
     def attach(self, model):
@@ -322,8 +370,32 @@ def _ctx_nn_methods():
     def nn_forward(self, model, r, zaj, z, stream=None):
         self._check(self.lib.hofv_nn_forward(self.h, model.h, self._v(r), self._v(zaj), self._v(z), _stream(stream)))
 
-    for f in (attach, nn_train_step, nn_gradient, nn_forward):
+    def harvest_pairs(self, pairs, u, n_starts=0, length=0, newton_steps=0, seed=0, starts=None, rtol=1e-8,
+                      restart=30, max_iters=3000, n_sweeps=2, stream=None):
+        """Appends Krylov-type and Newton pairs at state u to the PairSet `pairs`;
+        starts (optional) [n_starts, dim, n_cells] device tensor of start vectors."""
+        o = L.HarvestOpts(int(n_starts), int(length), int(newton_steps), C.c_uint64(int(seed)), float(rtol),
+                          int(restart), int(max_iters), int(n_sweeps))
+        sp = None if starts is None else _ptr(starts, int(n_starts) * self.dim * self.n_cells)
+        self._check(self.lib.hofv_harvest_pairs(self.h, self._v(u), sp, C.byref(o), pairs.h, _stream(stream)))
+
+    for f in (attach, nn_train_step, nn_gradient, nn_forward, harvest_pairs):
         setattr(Context, f.__name__, f)
+
+
+def nn_train(model, pair_sets, epochs=20, lr=1e-3, batch=4, n_sweeps=2, seed=0, stream=None):
+    """hofv_nn_train over the PairSets; returns (stats dict, mean loss per epoch)."""
+    lib = model.lib
+    sets = (C.c_void_p * len(pair_sets))(*[p.h.value for p in pair_sets])
+    hist = (C.c_double * int(epochs))()
+    o = L.TrainOpts(int(epochs), int(batch), float(lr), int(n_sweeps), C.c_uint64(int(seed)),
+                    C.cast(hist, C.POINTER(C.c_double)))
+    s = L.TrainStats()
+    st = lib.hofv_nn_train(model.h, len(pair_sets), sets, C.byref(o), C.byref(s), _stream(stream))
+    if st != L.HOFV_OK:
+        msg = lib.hofv_last_error(pair_sets[0].ctx.h).decode() or lib.hofv_last_error(None).decode()
+        raise HofvError(st, msg)
+    return {k: getattr(s, k) for k, _ in L.TrainStats._fields_}, list(hist)
 
 
 _ctx_nn_methods()

@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -24,6 +25,9 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
                         const hofv_krylov_opts* o, hofv_krylov_stats* stats, hipStream_t st);
 hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_newton_stats* stats,
                         hipStream_t st);
+
+hofv_status harvest_impl(hofv_ctx* c, const double* u, const double* starts, const hofv_harvest_opts* o,
+                         double* r_out, double* e_out, hipStream_t st);
 
 hofv_status jvp_impl(hofv_ctx* c, const double* u, const double* Ru, const double* v, double* Jv, double eps,
                      hipStream_t st) {
@@ -456,6 +460,57 @@ hofv_status hofv_nn_attach(hofv_ctx* c, hofv_nn* m) {
   return HOFV_OK;
 }
 
+}  // extern "C"
+
+namespace hofv {
+// One optimisation step over the pairs r[i], e[i] (device pointers) of ctx's
+// mesh: z_AJ = plain preconditioner(r), gradients of ||z - e||^2 / ||e||^2
+// averaged over the pairs, then Adam.  *loss: the mean loss before the step.
+static hofv_status train_step(hofv_ctx* c, hofv_nn* m, const double* const* r, const double* const* e, int n,
+                              int sweeps, double lr, double* loss, hipStream_t st) {
+  hofv_status s;
+  if (!c->nnw.zaj) {
+    if ((s = dev_alloc(c, &c->nnw.zaj, (size_t)c->D * c->nc))) return s;
+  }
+  if (nn_zero_grad(m, st) || nn_zero_scalar(m->loss, st)) return fail(c, HOFV_EHIP, "zeroing failed");
+  for (int i = 0; i < n; ++i) {
+    if ((s = launch_precond(c, r[i], c->nnw.zaj, sweeps, st))) return s;
+    if ((s = nn_grad(c, m, r[i], c->nnw.zaj, e[i], 1.0f / n, m->loss, st))) return s;
+  }
+  double l = 0;
+  HOFV_HIP(c, hipMemcpyAsync(&l, m->loss, sizeof(double), hipMemcpyDeviceToHost, st));
+  if (nn_adam(m, lr, st)) return fail(c, HOFV_EHIP, "Adam step failed");
+  HOFV_HIP(c, hipStreamSynchronize(st));
+  if (loss) *loss = l / n;
+  if (!std::isfinite(l)) return fail(c, HOFV_ENAN, "non-finite training loss");
+  return HOFV_OK;
+}
+
+// splitmix64 (Steele, Lea and Flood 2014): the order of the training pairs
+struct SplitMix {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  // uniform in [0, k) by rejection of the biased top range
+  uint64_t below(uint64_t k) {
+    const uint64_t lim = UINT64_MAX - UINT64_MAX % k;
+    uint64_t x;
+    do x = next(); while (x >= lim);
+    return x % k;
+  }
+  template <class T>
+  void shuffle(std::vector<T>& v) {  // Fisher-Yates
+    for (size_t i = v.size(); i > 1; --i) std::swap(v[i - 1], v[below(i)]);
+  }
+};
+}  // namespace hofv
+
+extern "C" {
+
 hofv_status hofv_nn_train_step(hofv_ctx* c, hofv_nn* m, const double* d_r, const double* d_e, int32_t n_pairs,
                                int32_t n_sweeps, double lr, double* loss, void* stream) {
   hofv_status s = need(c, 4, "nn_train_step");
@@ -463,28 +518,172 @@ hofv_status hofv_nn_train_step(hofv_ctx* c, hofv_nn* m, const double* d_r, const
   if (!m || !d_r || !d_e || n_pairs < 1 || n_sweeps < 1 || !(lr >= 0)) return fail(c, HOFV_EINVAL, "bad argument");
   if (m->device != c->device) return fail(c, HOFV_EINVAL, "model and context are on different devices");
   if ((s = set_device(c))) return s;
-  hipStream_t st = (hipStream_t)stream;
-  if (!c->nnw.zaj) {
-    if ((s = dev_alloc(c, &c->nnw.zaj, (size_t)c->D * c->nc))) return s;
-  }
-  double* loss_dev;
-  if ((s = dev_alloc(c, &loss_dev, 1))) return s;
-  if (nn_zero_grad(m, st) || nn_zero_scalar(loss_dev, st)) return fail(c, HOFV_EHIP, "zeroing failed");
   const size_t len = (size_t)c->D * c->nc;
+  std::vector<const double*> r(n_pairs), e(n_pairs);
   for (int i = 0; i < n_pairs; ++i) {
-    if ((s = launch_precond(c, d_r + i * len, c->nnw.zaj, n_sweeps, st))) return s;
-    if ((s = nn_grad(c, m, d_r + i * len, c->nnw.zaj, d_e + i * len, 1.0f / n_pairs, loss_dev, st))) return s;
+    r[i] = d_r + i * len;
+    e[i] = d_e + i * len;
   }
-  double l = 0;
-  HOFV_HIP(c, hipMemcpyAsync(&l, loss_dev, sizeof(double), hipMemcpyDeviceToHost, st));
-  if (nn_adam(m, lr, st)) return fail(c, HOFV_EHIP, "Adam step failed");
-  HOFV_HIP(c, hipStreamSynchronize(st));
-  hipFree(loss_dev);
-  c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), (void*)loss_dev), c->allocations.end());
-  c->device_bytes -= sizeof(double);
-  if (loss) *loss = l / n_pairs;
-  if (!std::isfinite(l)) return fail(c, HOFV_ENAN, "non-finite training loss");
+  return train_step(c, m, r.data(), e.data(), n_pairs, n_sweeps, lr, loss, (hipStream_t)stream);
+}
+
+hofv_status hofv_pairset_create(hofv_ctx* c, int32_t capacity, hofv_pairset** out) {
+  if (!out) return fail(c, HOFV_EINVAL, "out is NULL");
+  *out = nullptr;
+  hofv_status s = need(c, 4, "pairset_create");
+  if (s) return s;
+  if (capacity < 1) return fail(c, HOFV_EINVAL, "capacity must be >= 1");
+  if ((s = set_device(c))) return s;
+  hofv_pairset* p = new (std::nothrow) hofv_pairset();
+  if (!p) return fail(c, HOFV_ENOMEM, "out of host memory");
+  p->ctx = c;
+  p->cap = capacity;
+  const size_t bytes = (size_t)capacity * c->D * c->nc * sizeof(double);
+  if (hipMalloc((void**)&p->r, bytes) != hipSuccess || hipMalloc((void**)&p->e, bytes) != hipSuccess) {
+    if (p->r) hipFree(p->r);
+    delete p;
+    return fail(c, HOFV_ENOMEM, "device allocation of the pair set failed");
+  }
+  *out = p;
   return HOFV_OK;
+}
+
+hofv_status hofv_pairset_destroy(hofv_pairset* p) {
+  if (!p) return HOFV_OK;
+  hipSetDevice(p->ctx->device);
+  hipDeviceSynchronize();
+  hipFree(p->r);
+  hipFree(p->e);
+  delete p;
+  return HOFV_OK;
+}
+
+hofv_status hofv_pairset_data(const hofv_pairset* p, int32_t* n_pairs, const double** d_r, const double** d_e) {
+  if (!p) return fail(nullptr, HOFV_EINVAL, "null pair set");
+  if (n_pairs) *n_pairs = p->n;
+  if (d_r) *d_r = p->r;
+  if (d_e) *d_e = p->e;
+  return HOFV_OK;
+}
+
+hofv_status hofv_pairset_copy(const hofv_pairset* p, int32_t first, int32_t count, double* d_r, double* d_e,
+                              void* stream) {
+  if (!p) return fail(nullptr, HOFV_EINVAL, "null pair set");
+  hofv_ctx* c = p->ctx;
+  if (first < 0 || count < 0 || first + count > p->n) return fail(c, HOFV_EINVAL, "pairs outside the set");
+  hofv_status s = set_device(c);
+  if (s) return s;
+  const size_t len = (size_t)c->D * c->nc, bytes = (size_t)count * len * sizeof(double);
+  hipStream_t st = (hipStream_t)stream;
+  if (d_r && bytes) HOFV_HIP(c, hipMemcpyAsync(d_r, p->r + (size_t)first * len, bytes, hipMemcpyDeviceToDevice, st));
+  if (d_e && bytes) HOFV_HIP(c, hipMemcpyAsync(d_e, p->e + (size_t)first * len, bytes, hipMemcpyDeviceToDevice, st));
+  return HOFV_OK;
+}
+
+hofv_status hofv_harvest_pairs(hofv_ctx* c, const double* d_u, const double* d_starts, const hofv_harvest_opts* o,
+                               hofv_pairset* set, void* stream) {
+  hofv_status s = need(c, 4, "harvest_pairs");
+  if (s) return s;
+  if (!d_u || !o || !set) return fail(c, HOFV_EINVAL, "null pointer");
+  if (set->ctx != c) return fail(c, HOFV_EINVAL, "the pair set belongs to another context");
+  if (o->n_starts < 0 || o->length < 0 || o->newton_steps < 0) return fail(c, HOFV_EINVAL, "negative pair counts");
+  if (c->nej.k > 0) return fail(c, HOFV_EINVAL, "pairs are harvested with the approximate Jacobian, not the NEJ");
+  const int64_t add = (int64_t)o->n_starts * o->length + o->newton_steps;
+  if (set->n + add > set->cap) return fail(c, HOFV_EINVAL, "the pairs do not fit the pair set");
+  if ((s = set_device(c))) return s;
+  const size_t len = (size_t)c->D * c->nc;
+  s = harvest_impl(c, d_u, d_starts, o, set->r + (size_t)set->n * len, set->e + (size_t)set->n * len,
+                   (hipStream_t)stream);
+  if (s == HOFV_OK) set->n += (int32_t)add;
+  return s;
+}
+
+hofv_status hofv_nn_train(hofv_nn* m, int32_t n_sets, hofv_pairset* const* sets, const hofv_train_opts* o,
+                          hofv_train_stats* stats, void* stream) {
+  if (!m || !sets || !o || n_sets < 1) return fail(nullptr, HOFV_EINVAL, "bad argument");
+  if (o->epochs < 1 || o->batch < 1 || o->n_sweeps < 1 || !(o->lr >= 0))
+    return fail(nullptr, HOFV_EINVAL, "epochs, batch and n_sweeps must be >= 1 and lr >= 0");
+  for (int i = 0; i < n_sets; ++i) {
+    if (!sets[i] || sets[i]->n < 1) return fail(nullptr, HOFV_EINVAL, "empty or null pair set");
+    hofv_status s = need(sets[i]->ctx, 4, "nn_train");
+    if (s) return s;
+    if (sets[i]->ctx->device != m->device) return fail(sets[i]->ctx, HOFV_EINVAL, "model and pair set devices differ");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = (hipStream_t)stream;
+  SplitMix rng{o->seed};
+  hofv_train_stats out{};
+  for (int ep = 0; ep < o->epochs; ++ep) {
+    // minibatches: each set's pairs in a random order, cut into batches
+    struct Job {
+      int set;
+      std::vector<int> idx;
+    };
+    std::vector<Job> jobs;
+    for (int i = 0; i < n_sets; ++i) {
+      std::vector<int> perm(sets[i]->n);
+      for (int k = 0; k < sets[i]->n; ++k) perm[k] = k;
+      rng.shuffle(perm);
+      for (size_t b = 0; b < perm.size(); b += (size_t)o->batch)
+        jobs.push_back({i, std::vector<int>(perm.begin() + b, perm.begin() + std::min(perm.size(), b + o->batch))});
+    }
+    rng.shuffle(jobs);
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (const Job& j : jobs) {
+      hofv_pairset* p = sets[j.set];
+      hofv_ctx* c = p->ctx;
+      if (hipSetDevice(c->device) != hipSuccess) return fail(c, HOFV_EHIP, "hipSetDevice");
+      const size_t len = (size_t)c->D * c->nc;
+      std::vector<const double*> r, e;
+      for (int k : j.idx) {
+        r.push_back(p->r + (size_t)k * len);
+        e.push_back(p->e + (size_t)k * len);
+      }
+      double l = 0.0;
+      hofv_status s = train_step(c, m, r.data(), e.data(), (int)r.size(), o->n_sweeps, o->lr, &l, st);
+      if (s) return s;
+      tot += l * (double)r.size();
+      cnt += (int64_t)r.size();
+      ++out.steps;
+    }
+    const double mean = tot / (double)std::max<int64_t>(cnt, 1);
+    if (ep == 0) out.loss_first = mean;
+    out.loss_last = mean;
+    if (o->epoch_loss) o->epoch_loss[ep] = mean;
+  }
+  out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = out;
+  return HOFV_OK;
+}
+
+hofv_status hofv_nn_save(hofv_nn* m, const char* path) {
+  if (!m || !path) return fail(nullptr, HOFV_EINVAL, "null argument");
+  std::vector<float> p(kNnParams);
+  hofv_status s = hofv_nn_get_params(m, p.data(), kNnParams);
+  if (s) return s;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(nullptr, HOFV_EINVAL, std::string("cannot write ") + path);
+  const int64_t cnt = kNnParams;
+  const bool ok = std::fwrite("HOFVNN01", 1, 8, f) == 8 && std::fwrite(&cnt, sizeof cnt, 1, f) == 1 &&
+                  std::fwrite(p.data(), sizeof(float), p.size(), f) == p.size();
+  if (std::fclose(f) != 0 || !ok) return fail(nullptr, HOFV_EINVAL, std::string("cannot write ") + path);
+  return HOFV_OK;
+}
+
+hofv_status hofv_nn_load(hofv_nn* m, const char* path) {
+  if (!m || !path) return fail(nullptr, HOFV_EINVAL, "null argument");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(nullptr, HOFV_EINVAL, std::string("cannot read ") + path);
+  char tag[8];
+  int64_t cnt = 0;
+  std::vector<float> p(kNnParams);
+  bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, "HOFVNN01", 8) == 0 &&
+            std::fread(&cnt, sizeof cnt, 1, f) == 1 && cnt == kNnParams &&
+            std::fread(p.data(), sizeof(float), p.size(), f) == p.size();
+  std::fclose(f);
+  if (!ok) return fail(nullptr, HOFV_EINVAL, std::string(path) + " is not a model of this network");
+  return hofv_nn_set_params(m, p.data(), kNnParams);
 }
 
 hofv_status hofv_nn_gradient(hofv_ctx* c, hofv_nn* m, const double* d_r, const double* d_zaj, const double* d_e,
@@ -494,17 +693,12 @@ hofv_status hofv_nn_gradient(hofv_ctx* c, hofv_nn* m, const double* d_r, const d
   if (!m || !d_r || !d_zaj || !d_e || !host_grad) return fail(c, HOFV_EINVAL, "bad argument");
   if ((s = set_device(c))) return s;
   hipStream_t st = (hipStream_t)stream;
-  double* loss_dev;
-  if ((s = dev_alloc(c, &loss_dev, 1))) return s;
-  if (nn_zero_grad(m, st) || nn_zero_scalar(loss_dev, st)) return fail(c, HOFV_EHIP, "zeroing failed");
-  if ((s = nn_grad(c, m, d_r, d_zaj, d_e, 1.0f, loss_dev, st))) return s;
+  if (nn_zero_grad(m, st) || nn_zero_scalar(m->loss, st)) return fail(c, HOFV_EHIP, "zeroing failed");
+  if ((s = nn_grad(c, m, d_r, d_zaj, d_e, 1.0f, m->loss, st))) return s;
   double l = 0;
-  HOFV_HIP(c, hipMemcpyAsync(&l, loss_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+  HOFV_HIP(c, hipMemcpyAsync(&l, m->loss, sizeof(double), hipMemcpyDeviceToHost, st));
   HOFV_HIP(c, hipMemcpyAsync(host_grad, m->g, kNnParams * 4, hipMemcpyDeviceToHost, st));
   HOFV_HIP(c, hipStreamSynchronize(st));
-  hipFree(loss_dev);
-  c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), (void*)loss_dev), c->allocations.end());
-  c->device_bytes -= sizeof(double);
   if (loss) *loss = l;
   return HOFV_OK;
 }

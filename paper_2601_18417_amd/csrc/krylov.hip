@@ -678,3 +678,90 @@ hofv_status newton_impl(hofv_ctx* c, double* u, const hofv_newton_opts* o, hofv_
 }
 
 }  // namespace hofv
+
+namespace hofv {
+
+// ---------------------------------------------------------------- training pairs
+// Pairs (r, e) with J e = r for the learned correction, written consecutively
+// at r_out / e_out (declared with hofv_harvest_pairs in hofv.h).
+hofv_status harvest_impl(hofv_ctx* c, const double* u, const double* starts, const hofv_harvest_opts* o,
+                         double* r_out, double* e_out, hipStream_t st) {
+  const int64_t n = (int64_t)c->D * c->nc;
+  hofv_krylov_opts ko{};
+  ko.restart = o->restart > 0 ? o->restart : 30;
+  ko.max_iters = o->max_iters > 0 ? o->max_iters : 3000;
+  ko.rtol = o->rtol > 0 ? o->rtol : 1e-8;
+  ko.n_sweeps = o->n_sweeps > 0 ? o->n_sweeps : 2;
+  ko.learned = 0;
+  ko.side = 0;
+  hofv_status s = ensure_krylov(c, ko.restart);
+  if (s) return s;
+  // workspace: R(u), the current v, M v and the Newton state, released on return
+  struct Ws {
+    hofv_ctx* c;
+    hipStream_t st;
+    std::vector<double*> b;
+    size_t bytes = 0;
+    ~Ws() {
+      (void)hipStreamSynchronize(st);
+      for (double* p : b) {
+        hipFree(p);
+        c->allocations.erase(std::remove(c->allocations.begin(), c->allocations.end(), (void*)p),
+                             c->allocations.end());
+      }
+      c->device_bytes -= bytes;
+    }
+  } ws{c, st, {}};
+  double *Ru, *v, *t, *uk;
+  for (double** p : {&Ru, &v, &t, &uk}) {
+    if ((s = dev_alloc(c, p, (size_t)n))) return s;
+    ws.b.push_back(*p);
+    ws.bytes += (size_t)n * sizeof(double);
+  }
+  double* nrm = c->kry.h + kNorm;
+  int64_t k = 0;  // pairs written
+  hofv_krylov_stats ks{};
+  if (o->n_starts > 0 && o->length > 0) {
+    if ((s = launch_residual(c, u, Ru, nullptr, nullptr, st))) return s;
+    for (int sidx = 0; sidx < o->n_starts; ++sidx) {
+      if (starts) {
+        HOFV_HIP(c, hipMemcpyAsync(v, starts + (size_t)sidx * n, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      } else if ((s = fill_normal(n, o->seed + ((uint64_t)sidx << 40), v, st))) {
+        return fail(c, s, "normal generator launch failed");
+      }
+      if ((s = dots(c, n, 1, v, n, v, nrm, 0, st))) return s;
+      k_scale_by<<<nblk(n), kB, 0, st>>>(n, v, nrm, 1, v);
+      for (int l = 0; l < o->length; ++l, ++k) {
+        double* rk = r_out + (size_t)k * n;
+        double* ek = e_out + (size_t)k * n;
+        HOFV_HIP(c, hipMemcpyAsync(rk, v, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        k_fill<<<nblk(n), kB, 0, st>>>(n, 0.0, ek);
+        if ((s = fgmres_impl(c, u, Ru, rk, ek, &ko, &ks, st))) return s;
+        if ((s = precond_dispatch(c, v, t, ko.n_sweeps, 0, st))) return s;
+        if ((s = jvp_impl(c, u, Ru, t, v, 0.0, st))) return s;
+        if ((s = dots(c, n, 1, v, n, v, nrm, 0, st))) return s;
+        k_scale_by<<<nblk(n), kB, 0, st>>>(n, v, nrm, 1, v);
+      }
+    }
+  }
+  if (o->newton_steps > 0) {
+    HOFV_HIP(c, hipMemcpyAsync(uk, u, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    for (int it = 0; it < o->newton_steps; ++it, ++k) {
+      double* rk = r_out + (size_t)k * n;
+      double* ek = e_out + (size_t)k * n;
+      if ((s = launch_residual(c, uk, Ru, nullptr, nullptr, st))) return s;
+      k_fill<<<nblk(n), kB, 0, st>>>(n, 0.0, ek);
+      if ((s = fgmres_impl(c, uk, Ru, Ru, ek, &ko, &ks, st))) return s;
+      // u_{k+1} = u_k - e_k, then (R, e) / ||R||
+      k_lincomb<<<nblk(n), kB, 0, st>>>(n, 1.0, uk, -1.0, ek, uk);
+      if ((s = dots(c, n, 1, Ru, n, Ru, nrm, 0, st))) return s;
+      k_scale_by<<<nblk(n), kB, 0, st>>>(n, Ru, nrm, 1, rk);
+      k_scale_by<<<nblk(n), kB, 0, st>>>(n, ek, nrm, 1, ek);
+    }
+  }
+  HOFV_HIP(c, hipGetLastError());
+  HOFV_HIP(c, hipStreamSynchronize(st));
+  return HOFV_OK;
+}
+
+}  // namespace hofv

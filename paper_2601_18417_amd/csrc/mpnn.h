@@ -45,9 +45,18 @@ struct NnWork {
 
 }  // namespace hofv
 
+// training pairs (r, e), J e = r, on one context's mesh
+struct hofv_pairset {
+  hofv_ctx* ctx = nullptr;
+  int32_t cap = 0, n = 0;
+  double* r = nullptr;  // [cap][dim][n_cells]
+  double* e = nullptr;
+};
+
 struct hofv_nn {
   int device = 0;
   int64_t step = 0;
+  double* loss = nullptr;         // device accumulator of a training step's loss
   float* p = nullptr;             // FP32 master parameters
   float* m = nullptr;             // Adam first moments
   float* v = nullptr;             // Adam second moments
@@ -68,6 +77,8 @@ hofv_status nn_grad(hofv_ctx* c, hofv_nn* m, const double* r, const double* zaj,
 hofv_status nn_zero_grad(hofv_nn* m, hipStream_t st);
 hofv_status nn_zero_scalar(double* p, hipStream_t st);
 hofv_status nn_adam(hofv_nn* m, double lr, hipStream_t st);
+// standard normal values of splitmix64 seeded with `seed` (Box-Muller on output pairs)
+hofv_status fill_normal(int64_t n, uint64_t seed, double* out, hipStream_t st);
 }  // namespace hofv
 
 #define TIMED_NN(ctx, name, st, launch)        \

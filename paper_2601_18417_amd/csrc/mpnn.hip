@@ -546,6 +546,25 @@ __global__ __launch_bounds__(kB) void k_nn_refresh(const float* __restrict__ p, 
   }
 }
 
+// out[i] standard normal: Box-Muller on outputs 2 (i / 2) + 1 and + 2 of splitmix64
+// seeded with `seed` (the k-th output mixes seed + k * 0x9E3779B97F4A7C15)
+__device__ inline double splitmix_unit(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)((z >> 11) + 1) * (1.0 / 9007199254740992.0);  // (0, 1]
+}
+
+__global__ __launch_bounds__(kB) void k_normal(int64_t n, uint64_t seed, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t pr = (uint64_t)(i / 2);
+  const double u1 = splitmix_unit(seed, 2 * pr + 1), u2 = splitmix_unit(seed, 2 * pr + 2);
+  const double rad = sqrt(-2.0 * log(u1)), th = 6.283185307179586 * u2;
+  out[i] = (i & 1) ? rad * sin(th) : rad * cos(th);
+}
+
 __global__ __launch_bounds__(kB) void k_nn_zero_f(int64_t n, float* __restrict__ a) {
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (i < n) a[i] = 0.f;
@@ -562,6 +581,7 @@ __global__ __launch_bounds__(kB) void k_nn_zero_d(int64_t n, double* __restrict_
 hofv_status nn_alloc_model(hofv_nn* m) {
   auto al = [&](void** p, size_t bytes) -> bool { return hipMalloc(p, bytes) == hipSuccess; };
   const size_t np = kNnParams;
+  if (!al((void**)&m->loss, sizeof(double))) return HOFV_ENOMEM;
   if (!al((void**)&m->p, np * 4) || !al((void**)&m->m, np * 4) || !al((void**)&m->v, np * 4) ||
       !al((void**)&m->g, np * 4) || !al((void**)&m->We, 8 * kW * 2) || !al((void**)&m->Wd, 3 * kW * 2) ||
       !al((void**)&m->Wt, (size_t)kNnLayers * kK * kW * 2) || !al((void**)&m->Wr, (size_t)kNnLayers * kK * kW * 2))
@@ -571,7 +591,7 @@ hofv_status nn_alloc_model(hofv_nn* m) {
 
 void nn_free_model(hofv_nn* m) {
   for (void* p : {(void*)m->p, (void*)m->m, (void*)m->v, (void*)m->g, (void*)m->We, (void*)m->Wd, (void*)m->Wt,
-                  (void*)m->Wr})
+                  (void*)m->Wr, (void*)m->loss})
     if (p) hipFree(p);
 }
 
@@ -699,6 +719,11 @@ hofv_status nn_grad(hofv_ctx* c, hofv_nn* m, const double* r, const double* zaj,
   if (s) return s;
   return c->D == 2 ? nn_grad_pair<2>(c, m, r, zaj, e, scale, loss_dev, st)
                    : nn_grad_pair<3>(c, m, r, zaj, e, scale, loss_dev, st);
+}
+
+hofv_status fill_normal(int64_t n, uint64_t seed, double* out, hipStream_t st) {
+  k_normal<<<nblk(n), kB, 0, st>>>(n, seed, out);
+  return hipGetLastError() == hipSuccess ? HOFV_OK : HOFV_EHIP;
 }
 
 hofv_status nn_zero_grad(hofv_nn* m, hipStream_t st) {

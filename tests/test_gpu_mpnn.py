@@ -97,14 +97,11 @@ def test_training_reduces_loss_and_iterations():
     """Train on two seeded meshes, evaluate FGMRES iterations on a third."""
     from paper_2601_18417_amd import api, learned
     data = []
-    ctxs = []
     for seed in (11, 12):
         prob = w.cube_mms(8, 2, perturb=0.2, seed=seed)
         ctx = api.context_for(prob)
         u = torch.zeros((3, prob.mesh.n_cells), device=DEV, dtype=torch.float64)
-        r, e = learned.harvest_krylov(ctx, u, n_starts=3, length=6, seed=seed)
-        data.append((ctx, r, e))
-        ctxs.append(ctx)
+        data.append(learned.harvest(ctx, u, n_starts=3, length=6, newton_steps=0, seed=seed))
     model = api.Model(3)
     hist = learned.train(model, data, epochs=25, lr=2e-3, batch=4)
     assert hist[-1] < 0.5 * hist[0], hist
@@ -157,3 +154,101 @@ def test_plain_preconditioner_takes_over_from_a_nonfinite_network():
     uu = torch.zeros_like(u)
     st = ctx.newton_solve(uu, tol=1e-8, eta=1e-4, learned=True)
     assert st["converged"] and st["fallbacks"] >= st["newton_iters"] >= 1
+
+
+# ---- the C ABI's harvesting and training loop --------------------------------
+
+def _reference_harvest(ctx, u, starts, length, newton_steps, rtol=1e-8, n_sweeps=2, restart=30):
+    """The pair recipe written out as a composition of the library's solver
+    calls with the normalisations in torch (how pairs were harvested before
+    hofv_harvest_pairs): Krylov-type sequences from the given starts, then
+    Newton pairs from u."""
+    Ru = torch.empty_like(u)
+    ctx.residual(u, Ru)
+    rs, es = [], []
+    tmp = torch.empty_like(u)
+    for b in starts:
+        v = b / torch.linalg.norm(b)
+        for _ in range(length):
+            e = torch.zeros_like(u)
+            ctx.fgmres_solve(u, Ru, v, e, rtol=rtol, max_iters=3000, n_sweeps=n_sweeps, check=False, restart=restart)
+            rs.append(v.clone())
+            es.append(e)
+            ctx.precond_apply(v, tmp, n_sweeps=n_sweeps)
+            wv = torch.empty_like(u)
+            ctx.jvp(u, Ru, tmp, wv)
+            v = wv / torch.linalg.norm(wv)
+    uk = u.clone()
+    R = torch.empty_like(u)
+    for _ in range(newton_steps):
+        ctx.residual(uk, R)
+        e = torch.zeros_like(u)
+        ctx.fgmres_solve(uk, R, R, e, rtol=rtol, max_iters=3000, n_sweeps=n_sweeps, check=False, restart=restart)
+        nr = torch.linalg.norm(R)
+        rs.append(R / nr)
+        es.append(e / nr)
+        uk = uk - e
+    return torch.stack(rs), torch.stack(es)
+
+
+def test_harvest_pairs_matches_the_reference_recipe():
+    """hofv_harvest_pairs against the same recipe composed from the library's
+    public calls, from the same start vectors: the pairs agree to the
+    FGMRES tolerance (the two sides normalise by norms summed in different
+    orders, so the solves see right-hand sides that differ in the last bits
+    and may take a different number of iterations; bit-for-bit equality is not
+    defined across reduction orders)."""
+    from paper_2601_18417_amd import api, learned
+    prob = w.cube_mms(8, 2, perturb=0.2, seed=13)
+    ctx = api.context_for(prob)
+    n = prob.mesh.n_cells
+    u = to_dev(w.random_state(n, 3, seed=4, scale=1e-4))
+    starts = torch.randn((2, 3, n), generator=torch.Generator().manual_seed(17), dtype=torch.float64).to(DEV)
+    pairs = learned.harvest(ctx, u, n_starts=2, length=3, newton_steps=2, starts=starts)
+    assert len(pairs) == 8
+    r, e = pairs.tensors()
+    rr, er = _reference_harvest(ctx, u, starts, 3, 2)
+    torch.cuda.synchronize()
+    for k in range(8):
+        dr = float(torch.linalg.norm(r[k] - rr[k]) / torch.linalg.norm(rr[k]))
+        de = float(torch.linalg.norm(e[k] - er[k]) / torch.linalg.norm(er[k]))
+        assert dr <= 1e-12 and de <= 1e-5, (k, dr, de)
+    # every pair satisfies J e = r to the solve tolerance
+    Ru = torch.empty_like(u)
+    ctx.residual(u, Ru)
+    Je = torch.empty_like(u)
+    for k in range(6):
+        ctx.jvp(u, Ru, e[k], Je)
+        torch.cuda.synchronize()
+        assert float(torch.linalg.norm(Je - r[k])) <= 2e-8 * float(torch.linalg.norm(r[k]))
+    # seeded starts are reproducible; a full set refuses more pairs
+    p1 = learned.harvest(ctx, u, n_starts=1, length=2, newton_steps=0, seed=99)
+    p2 = learned.harvest(ctx, u, n_starts=1, length=2, newton_steps=0, seed=99)
+    assert torch.equal(p1.tensors()[0], p2.tensors()[0]) and torch.equal(p1.tensors()[1], p2.tensors()[1])
+    with pytest.raises(api.HofvError):
+        ctx.harvest_pairs(p1, u, n_starts=1, length=1)
+
+
+def test_train_loop_save_and_load(tmp_path):
+    """hofv_nn_train is seeded (two runs give the same parameters), lowers the
+    loss, and a saved model loads back bit for bit."""
+    from paper_2601_18417_amd import api, learned
+    prob = w.cube_mms(8, 2, perturb=0.2, seed=14)
+    ctx = api.context_for(prob)
+    u = torch.zeros((3, prob.mesh.n_cells), device=DEV, dtype=torch.float64)
+    pairs = learned.harvest(ctx, u, n_starts=2, length=4, newton_steps=1, seed=5)
+    params = []
+    for _ in range(2):
+        model = api.Model(3)
+        stats, hist = api.nn_train(model, [pairs], epochs=8, lr=2e-3, batch=3, seed=11)
+        assert stats["steps"] == 8 * 3 and hist[-1] < hist[0]
+        params.append(model.get_params())
+    assert np.array_equal(params[0], params[1])
+    path = tmp_path / "m.hofvnn"
+    model.save(path)
+    other = api.Model(4)
+    other.load(path)
+    assert np.array_equal(other.get_params(), params[1])
+    (tmp_path / "bad").write_bytes(b"not a model")
+    with pytest.raises(api.HofvError):
+        other.load(tmp_path / "bad")
