@@ -9,7 +9,13 @@ norms, at u = the manufactured field and v = standard normal (seed 1000).
 Reported: J.v Mcells/s (the headline value), residual Mcells/s, the roofline
 of the dominant kernel from per-kernel HIP events recorded on the launch
 stream over the timed region, the time of a Newton solve to 1e-8 with the plain
-compact preconditioner, and the CPU oracle timed on a bounded sample.
+compact preconditioner (sweeps), its V-cycle application and the learned
+correction, and the CPU oracle timed on a bounded sample (one thread and all
+cores) with its time to tolerance on the 2D 32x32 problem.  A second leg runs
+the 128^3 p = 3 cube on an unseen seed: J.v throughput and kernel HBM fractions,
+the GPU's error against the oracle on sampled cells, and Newton to 1e-8 with
+the plain sweeps and with the learned correction of the committed model
+(trained on 2D squares and neo-Hookean beams).
 """
 from __future__ import annotations
 
@@ -55,12 +61,41 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, n_sample: int, u, v, ctx, torch, label, seed: int = 0):
-    """The FP64 oracle's J.v on n_sample cells of the same mesh at the bench's
-    state (setup excluded), and the error of the GPU's R and J.v against it on
-    those cells (same u, v and eps)."""
-    from oracle import jacobian as ojac
+_WORKER = {}
+
+
+def _oracle_worker_setup(args):
+    """Worker process: build the oracle's discretisation for its block of cells."""
+    prob_spec, cells, u, v = args
+    import workloads as w
     from oracle import residual as ores
+    from oracle import jacobian as ojac
+    name, n, p = prob_spec
+    prob = w.cube_mms(n, p, perturb=0.2, seed=0)
+    disc = ores.build(prob, active=cells)
+    Ru = ores.residual(disc, u)
+    _WORKER.update(disc=disc, u=u, v=v, Ru=Ru, eps=ojac.default_eps(u, v))
+    return len(cells)
+
+
+def _oracle_worker_jvp(reps):
+    from oracle import jacobian as ojac
+    d = _WORKER
+    for _ in range(reps):
+        ojac.jvp(d["disc"], d["u"], d["v"], d["Ru"], d["eps"])
+    return reps
+
+
+def cpu_baseline(prob, n_sample: int, u, v, ctx, torch, label, seed: int = 0, cube=None):
+    """The FP64 oracle's J.v on n_sample cells of the same mesh at the bench's
+    state (setup excluded), on one thread and on all host cores (one worker
+    process per core, each on its own contiguous block of cells); the error of
+    the GPU's R and J.v against it on those cells (same u, v and eps); and the
+    oracle's time to 1e-10 on the 2D 32x32 p = 2 manufactured problem."""
+    from oracle import jacobian as ojac
+    from oracle import newton as onw
+    from oracle import residual as ores
+    import workloads as w
     rng = np.random.default_rng(seed)
     n = prob.mesh.n_cells
     # a contiguous block of cells (lexicographic), which is what a CPU would sweep
@@ -89,12 +124,162 @@ def cpu_baseline(prob, n_sample: int, u, v, ctx, torch, label, seed: int = 0):
     def rel(a, b):
         return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
-    return {"value": n_sample / t_jvp / 1e6, "unit": "Mcells/s", "cores": 1, "kind": "oracle",
-            "sample": f"J.v at {n_sample} contiguous cells of the same {label} mesh, {reps} repetitions "
-                      f"(numpy fp64, one thread; its setup for those cells, {t_setup:.1f}s, not timed)",
-            "seconds_per_jvp": t_jvp,
-            "gpu_error_vs_oracle": {"residual_rel_l2": rel(Rg, Ru[cells]), "jvp_rel_l2": rel(Jg, Jo[cells]),
-                                    "cells": n_sample}}
+    out = {"value": n_sample / t_jvp / 1e6, "unit": "Mcells/s", "cores": 1, "kind": "oracle",
+           "sample": f"J.v at {n_sample} contiguous cells of the same {label} mesh, {reps} repetitions "
+                     f"(numpy fp64, one thread; its setup for those cells, {t_setup:.1f}s, not timed)",
+           "seconds_per_jvp": t_jvp,
+           "gpu_error_vs_oracle": {"residual_rel_l2": rel(Rg, Ru[cells]), "jvp_rel_l2": rel(Jg, Jo[cells]),
+                                   "cells": n_sample}}
+    try:
+        import platform
+        model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")),
+                     platform.processor())
+    except OSError:
+        model = "unknown"
+    out["cpu_model"] = model
+    out["host_cores"] = os.cpu_count()
+    if cube is not None:
+        # all cores: one spawned process per core (none touches the GPU), each
+        # with its own block of n_sample cells; the J.v phase is timed after
+        # every worker has set up
+        import multiprocessing as mp
+        nw = min(16, os.cpu_count() or 1)
+        blocks = [np.arange(b0, b0 + n_sample) for b0 in
+                  np.linspace(0, n - n_sample, nw).astype(np.int64)]
+        with mp.get_context("spawn").Pool(nw) as pool:
+            pool.map(_oracle_worker_setup, [(cube, blk, u, v) for blk in blocks], chunksize=1)
+            t0 = time.perf_counter()
+            pool.map(_oracle_worker_jvp, [reps] * nw, chunksize=1)
+            t_all = time.perf_counter() - t0
+        out["all_cores"] = {"value": nw * n_sample * reps / t_all / 1e6, "unit": "Mcells/s", "cores": nw,
+                            "sample": f"J.v, {nw} processes x {n_sample} contiguous cells x {reps} repetitions"}
+    # time to tolerance of the whole oracle solve on the 2D 32x32 p = 2 problem
+    sq = w.square_mms(32, 2)
+    t0 = time.perf_counter()
+    dsq = ores.build(sq)
+    t_sq_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, st = onw.newton(dsq, np.zeros((dsq.n_cells, 2)), tol=1e-10, eta=1e-4)
+    out["time_to_tol_square32_p2"] = {"seconds": time.perf_counter() - t0, "tol": 1e-10, "cores": 1,
+                                      "newton_iters": st["newton"], "krylov_iters": st["krylov"],
+                                      "setup_seconds": t_sq_setup}
+    return out
+
+
+C4_MODEL = os.path.join(ROOT, "paper_2601_18417_amd", "weights", "c4_sweeps.hofvnn")
+C4_TRAIN_CMD = ("python bench.py --study train --train-set c4 --mg-base 0 --train-seeds 0-49 --harvest-starts 2 "
+                "--harvest-length 9 --restart 300 --learned-epochs 30 --model paper_2601_18417_amd/weights/"
+                "c4_sweeps.hofvnn")
+
+
+def big_leg(args, torch, api, w, dev):
+    """The 128^3 perturbed cube at p = 3 on an unseen seed: J.v and residual
+    throughput with the face and extrapolation kernels' HBM fractions, the
+    GPU's R and J.v against the oracle on sampled cells, and Newton to 1e-8
+    with the plain sweeps and with the learned correction of the committed
+    model (trained on 2D squares and neo-Hookean beams), each solution's
+    oracle residual on the sampled cells."""
+    from oracle import jacobian as ojac
+    from oracle import residual as ores
+    t0 = time.perf_counter()
+    prob = w.cube_mms(args.big_n, 3, perturb=0.2, seed=args.big_seed)
+    ctx = api.context_for(prob)
+    t_setup = time.perf_counter() - t0
+    log(f"128^3 setup {t_setup:.1f}s")
+    nc = prob.mesh.n_cells
+    cen = ctx.cell_centroids()
+    u = torch.tensor(prob.loads.exact.value(cen).T.copy(), device=dev)
+    v = torch.tensor(np.random.default_rng(1000).standard_normal((3, nc)), device=dev)
+    Ru = torch.empty_like(u)
+    Jv = torch.empty_like(u)
+    ctx.residual(u, Ru)
+    for _ in range(3):
+        ctx.jvp(u, Ru, v, Jv)
+    steps = 10
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.jvp(u, Ru, v, Jv)
+    torch.cuda.synchronize()
+    ms_jvp = (time.perf_counter() - t0) / steps * 1e3
+    kern = {}
+    for name in ("k_face_le", "k_extrap", "k_cell_sum", "k_pack", "k_sumsq2"):
+        ms, cnt = ctx.kernel_time(name)
+        if cnt:
+            kern[name] = {"avg_ms": ms / cnt}
+            if name in ("k_face_le", "k_extrap", "k_cell_sum"):  # the kernels with a byte model
+                kern[name]["GBps"] = ctx.kernel_bytes(name) / (ms / cnt * 1e-3) / 1e9
+                kern[name]["frac_of_hbm_peak"] = kern[name]["GBps"] / HBM_PEAK_GBS
+    ctx.set_timing(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.residual(u, Ru)
+    torch.cuda.synchronize()
+    ms_res = (time.perf_counter() - t0) / steps * 1e3
+    # the oracle on sampled cells: corners, boundary-face cells and random ones
+    ijk = w.cell_ijk(prob.mesh)
+    top = np.array(prob.mesh.shape) - 1
+    rng = np.random.default_rng(77)
+    sample = np.unique(np.concatenate([rng.choice(nc, 12, replace=False),
+                                       np.nonzero(np.all((ijk == 0) | (ijk == top), axis=1))[0][:4],
+                                       np.nonzero(ijk[:, 0] == 0)[0][:3], np.nonzero(ijk[:, 2] == top[2])[0][:3]]))
+    t0 = time.perf_counter()
+    disc = ores.build(prob, active=sample)
+    uh = u.cpu().numpy().T
+    vh = v.cpu().numpy().T
+    eps = ojac.default_eps(uh, vh)
+    ctx.residual(u, Ru)
+    ctx.jvp(u, Ru, v, Jv, eps=eps)
+    Rg, Jg = Ru.cpu().numpy().T[sample], Jv.cpu().numpy().T[sample]
+    Ro = ores.residual(disc, uh)
+    Jo = (ores.residual(disc, uh + eps * vh) - Ro) / eps
+    Ff, Fd = ores.face_fluxes(disc, uh)
+    scale = np.zeros_like(Ro)
+    np.add.at(scale, disc.f_own, np.abs(Ff))
+    np.add.at(scale, disc.f_nei, np.abs(Ff))
+    np.add.at(scale, disc.d_own, np.abs(Fd))
+    scale += np.abs(disc.b_body)
+    err = {"cells": int(sample.size),
+           "residual_max_over_flux_scale": float(np.max(np.abs(Rg - Ro[sample]) / scale[sample])),
+           "jvp_rel_l2": float(np.linalg.norm(Jg - Jo[sample]) / np.linalg.norm(Jo[sample])),
+           "oracle_seconds": time.perf_counter() - t0}
+    R0o = ores.residual(disc, np.zeros_like(uh))[sample]
+    out = {"workload": f"3D linear elastic MMS, unit cube {args.big_n}^3 hex perturbed +-20% (seed {args.big_seed}), "
+                       f"p=3, |S|={ctx.report['stencil_size']}, 2x2 Gauss/face, alpha=0.1",
+           "n_cells": nc, "setup_seconds": t_setup, "jvp_ms": ms_jvp, "jvp_mcells_s": nc / (ms_jvp * 1e-3) / 1e6,
+           "residual_mcells_s": nc / (ms_res * 1e-3) / 1e6, "kernels": kern, "gpu_error_vs_oracle": err}
+    log(f"128^3 J.v {out['jvp_mcells_s']:.0f} Mcells/s, kernels {kern}, oracle {err}")
+    if not args.big_solve:
+        ctx.close()
+        return out
+    # time to 1e-8 from u = 0: plain sweeps, then the learned correction
+    res = {}
+    model = api.Model(0)
+    model.load(args.c4_model)
+    ctx.attach(model)
+    z = torch.empty_like(u)
+    ctx.precond_apply(v, z, learned=True)  # the network's workspace
+    for name, learned in (("plain", False), ("learned", True)):
+        uu = torch.zeros_like(u)
+        st = newton_run(torch, ctx, prob, nc, learned, 1e-8, args.max_krylov, u_out=uu)
+        ug = uu.cpu().numpy().T
+        st["oracle_rel_residual_sampled"] = float(np.linalg.norm(ores.residual(disc, ug)[sample]) /
+                                                  np.linalg.norm(R0o))
+        ue = prob.loads.exact.value(cen)
+        st["rms_error_vs_manufactured"] = float(np.sqrt(np.mean(np.sum((ug - ue) ** 2, axis=1))))
+        res[name] = st
+        log(f"128^3 {name} solve {st}")
+    res["speedup"] = res["plain"]["seconds"] / res["learned"]["seconds"]
+    res["krylov_ratio"] = res["learned"]["krylov_iters"] / max(res["plain"]["krylov_iters"], 1)
+    res["model"] = os.path.relpath(args.c4_model, ROOT)
+    res["training_command"] = C4_TRAIN_CMD
+    res["training"] = ("2,000 pairs: 2D 32x32 p=2 squares and 60x6x6 p=2 neo-Hookean beams, perturbation seeds 0-49; "
+                       "evaluated on an unseen seed")
+    ctx.attach(None)
+    ctx.close()
+    return out, res
 
 
 def parse_seeds(s):
@@ -227,47 +412,90 @@ def column_steps(args, torch, ctx, prob, cen):
 
 def study(args):
     """The learned-preconditioner study: 'train' harvests pairs on seeded
-    perturbed cubes and trains a model (saved as a float32 .npy); 'eval' times
-    plain vs learned Newton solves to the tolerance on an unseen mesh."""
+    meshes (--train-set) and trains a model (saved with hofv_nn_save); 'eval'
+    times plain vs learned Newton solves to the tolerance on an unseen mesh;
+    'nn' times the learned application alone."""
     import torch
 
     import workloads as w
     from paper_2601_18417_amd import api
     from paper_2601_18417_amd import learned as lrn
     dev = torch.device("cuda:0")
+    if args.study == "nn":
+        # the learned preconditioner's application alone (a seeded untrained
+        # model runs every kernel of the forward pass), for kernel traces
+        prob = w.cube_mms(args.n, args.p, perturb=0.2, seed=0)
+        ctx = api.context_for(prob)
+        model = api.Model(7)
+        ctx.attach(model)
+        nc = prob.mesh.n_cells
+        r = torch.randn((3, nc), device=dev, dtype=torch.float64, generator=torch.Generator(device=dev).manual_seed(5))
+        z = torch.empty_like(r)
+        for _ in range(args.warmup):
+            ctx.precond_apply(r, z, learned=True)
+        ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.precond_apply(r, z, learned=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        lay_ms, lay_n = ctx.kernel_time("k_nn_layer")
+        ctx.set_timing(False)
+        print(json.dumps({"study": "nn", "n_cells": nc, "learned_apply_ms": ms,
+                          "k_nn_layer_avg_ms": lay_ms / max(lay_n, 1), "k_nn_layer_launches": lay_n}), flush=True)
+        return
     if args.study == "train":
         t0 = time.perf_counter()
-        data = []
+        data, keep = [], []
+        kinds = {"c4": ["square", "beam"], "cube": ["cube"], "cantilever": ["beam"]}[args.train_set]
         for seed in parse_seeds(args.train_seeds):
-            if args.workload == "cantilever":
-                # a short beam with the cantilever's cells (0.05 cubes) and slenderness
-                # (10), perturbed by seed; the same tip traction bends it by the same
-                # fraction of its length.  The network learns to correct the V-cycle.
-                nx = args.learned_size
-                shape, lengths = (nx, nx // 10, nx // 10), (0.05 * nx, 0.005 * nx, 0.005 * nx)
-                tp = w.cantilever(shape=shape, p=args.p)
-                tp.mesh = w.box_mesh(shape, lengths=lengths, perturb=0.1, seed=seed)
-                tp.loads = w.fields.cantilever_loads(lengths[0], (0.0, -2.18e-3, 0.0))
-                tctx = api.context_for(tp, precond_levels=8)
-                tctx.set_multigrid(True)
-                tctx.set_load_scale(0.3)
-            else:
-                tp = w.cube_mms(args.learned_size, args.p, perturb=0.2, seed=seed)
-                tctx = api.context_for(tp)
-            u0 = torch.zeros((3, tp.mesh.n_cells), device=dev, dtype=torch.float64)
-            data.append(lrn.harvest(tctx, u0, n_starts=args.harvest_starts, length=args.harvest_length,
-                                    newton_steps=2, seed=seed, restart=args.restart))
-            log(f"harvested seed {seed}: {len(data[-1])} pairs, {time.perf_counter() - t0:.0f}s")
+            for kind in kinds:
+                if kind == "beam":
+                    # a short beam with the cantilever's cells (0.05 cubes) and slenderness
+                    # (10), perturbed by seed; the same tip traction bends it by the same
+                    # fraction of its length (the sweeps alone do not solve it: V-cycle)
+                    nx = args.learned_size if args.train_set == "cantilever" else 60
+                    shape, lengths = (nx, nx // 10, nx // 10), (0.05 * nx, 0.005 * nx, 0.005 * nx)
+                    tp = w.cantilever(shape=shape, p=2 if args.train_set == "c4" else args.p)
+                    tp.mesh = w.box_mesh(shape, lengths=lengths, perturb=0.1, seed=seed)
+                    tp.loads = w.fields.cantilever_loads(lengths[0], (0.0, -2.18e-3, 0.0))
+                    mg = True
+                elif kind == "square":  # the 2D 32x32 p = 2 manufactured problem, perturbed by seed
+                    tp = w.square_mms(32, 2, perturb=0.2, seed=seed)
+                    mg = args.mg_base
+                else:
+                    tp = w.cube_mms(args.learned_size, args.p, perturb=0.2, seed=seed)
+                    mg = args.mg_base
+                tctx = api.context_for(tp, precond_levels=8 if mg else 1)
+                if mg:
+                    tctx.set_multigrid(True)
+                if kind == "beam":
+                    tctx.set_load_scale(0.3)
+                u0 = torch.zeros((tp.dim, tp.mesh.n_cells), device=dev, dtype=torch.float64)
+                data.append(lrn.harvest(tctx, u0, n_starts=args.harvest_starts, length=args.harvest_length,
+                                        newton_steps=2, seed=seed, restart=args.restart))
+                if mg and not args.mg_base:
+                    # e came from V-cycle-preconditioned solves; the network learns to
+                    # correct the sweeps' output
+                    tctx.set_multigrid(False)
+                keep.append(tctx)
+                log(f"harvested {kind} seed {seed}: {len(data[-1])} pairs, {time.perf_counter() - t0:.0f}s")
         t_harvest = time.perf_counter() - t0
         model = api.Model(7)
-        hist = lrn.train(model, data, epochs=args.learned_epochs, lr=2e-3, batch=4)
+        hist = lrn.train(model, data, epochs=args.learned_epochs, lr=2e-3, batch=4, seed=args.train_order_seed)
         for ep, l in enumerate(hist):
             log(f"epoch {ep} loss {l:.4f}")
         model.save(args.model)
+        meshes = {"c4": "2D 32x32 p=2 perturbed squares and 60x6x6 p=2 perturbed neo-Hookean beams (the beams' "
+                        "e solved with the V-cycle), network inputs from the "
+                        + ("V-cycle" if args.mg_base else "sweeps"),
+                  "cube": f"{args.learned_size}^3 p={args.p} perturbed cubes" + (" (V-cycle inputs)" if args.mg_base
+                                                                                    else ""),
+                  "cantilever": f"{args.learned_size}x{args.learned_size // 10}x{args.learned_size // 10} "
+                                f"p={args.p} perturbed neo-Hookean beams (V-cycle inputs)"}[args.train_set]
         out = {"study": "train", "pairs": int(sum(len(d) for d in data)),
-               "meshes": (f"{args.learned_size}x{args.learned_size // 10}x{args.learned_size // 10} p={args.p} "
-                          f"perturbed neo-Hookean beams (V-cycle inputs)" if args.workload == "cantilever" else
-                          f"{args.learned_size}^3 p={args.p} perturbed cubes") + f", seeds {args.train_seeds}",
+               "meshes": meshes + f", seeds {args.train_seeds}",
                "epochs": args.learned_epochs, "harvest_seconds": t_harvest,
                "train_seconds": time.perf_counter() - t0 - t_harvest, "loss_first_epoch": hist[0],
                "loss_last_epoch": hist[-1], "model": args.model}
@@ -358,10 +586,18 @@ def main():
     ap.add_argument("--precond-levels", type=int, default=None,
                     help="multigrid levels built for the approximate Jacobian (1: sweeps only); the plain and "
                          "learned solves use the sweeps, a third solve the V-cycle")
-    ap.add_argument("--study", choices=["train", "eval"], default=None,
+    ap.add_argument("--study", choices=["train", "eval", "nn"], default=None,
                     help="learned-preconditioner study instead of the benchmark: train a model on "
-                         "--train-seeds (saved to --model) or evaluate --model on one mesh")
+                         "--train-seeds (saved to --model), evaluate --model on one mesh, or time the "
+                         "learned application alone (nn)")
     ap.add_argument("--train-seeds", default="0-49")
+    ap.add_argument("--train-set", choices=["c4", "cube", "cantilever"], default="cube",
+                    help="training meshes of --study train: c4 = 2D squares and neo-Hookean beams (the learned-"
+                         "preconditioner configuration), cube = perturbed cubes of --learned-size, cantilever = beams")
+    ap.add_argument("--mg-base", type=int, default=0,
+                    help="1: the network corrects the V-cycle's output (training and evaluation contexts build the "
+                         "multigrid hierarchy); 0: the sweeps'")
+    ap.add_argument("--train-order-seed", type=int, default=0, help="seed of the training loop's pair order")
     ap.add_argument("--harvest-starts", type=int, default=4)
     ap.add_argument("--harvest-length", type=int, default=9)
     ap.add_argument("--model", default="learned_model.hofvnn",
@@ -389,6 +625,13 @@ def main():
                     help="time-to-tolerance solves as one logged library Newton step per call, at most this many "
                          "steps per increment (0: one library call per increment)")
     ap.add_argument("--lz", type=float, default=1.0, help="z extent of the evaluation cube (cell aspect 1/lz)")
+    ap.add_argument("--big", type=int, default=1,
+                    help="1: also the 128^3 p = 3 leg (J.v throughput, sampled oracle error, plain and learned "
+                         "Newton with the committed model) after the cube workload")
+    ap.add_argument("--big-n", type=int, default=128)
+    ap.add_argument("--big-seed", type=int, default=50, help="mesh seed of the 128^3 leg (unseen in training)")
+    ap.add_argument("--big-solve", type=int, default=1, help="time-to-tolerance solves in the 128^3 leg")
+    ap.add_argument("--c4-model", default=C4_MODEL, help="weights of the learned correction for the 128^3 leg")
     args = ap.parse_args()
     # solver settings per workload, where not given: the slender cantilever needs long
     # cycles, full Newton steps, the forcing term and the predictor (its sweeps-only
@@ -609,8 +852,14 @@ def main():
         label = {"cube": f"{args.n}^3 p={args.p}", "cantilever": f"cantilever p={args.p}",
                  "square": f"32^2 p={args.p}"}.get(args.workload, f"{args.workload} p={args.p}")
         cpu = cpu_baseline(prob, min(args.cpu_sample, nc // 2), u.cpu().numpy().T.copy(),
-                           v.cpu().numpy().T.copy(), ctx, torch, label)
+                           v.cpu().numpy().T.copy(), ctx, torch, label,
+                           cube=("cube", args.n, args.p) if args.workload == "cube" else None)
         log(f"cpu {cpu}")
+
+    big, c4 = None, None
+    if args.big and args.workload == "cube":
+        r = big_leg(args, torch, api, w, dev)
+        big, c4 = r if isinstance(r, tuple) else (r, None)
 
     out = {
         "metric": "J.v Mcells/s (FP64) & time-to-1e-8 residual, learned vs plain precond",
@@ -649,6 +898,8 @@ def main():
         "time_to_tol": solve,
         "cpu_baseline": cpu,
         "setup_seconds": t_setup,
+        "precision_study_128": big,
+        "learned_128": c4,
     }
     print(json.dumps(out), flush=True)
 

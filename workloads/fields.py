@@ -14,6 +14,7 @@ Derivative multi-indices are tuples (a, b[, c]).
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -71,6 +72,39 @@ class TrigField(Field):
                 prod = prod * (kk ** n) * np.sin(kk * x[:, d] + self.phase[t, d] + n * (math.pi / 2))
             out += prod[:, None] * self.coef[t][None, :]
         return out
+
+
+    def lap_and_graddiv(self, x):
+        """(lap u, grad div u) at x (m, dim), from each term's sin S_d and cos C_d
+        of each coordinate: with P = prod_d S_d, d^2 P / dx_d^2 = -k_d^2 P and, for
+        i != d, d^2 P / dx_i dx_d = k_i k_d C_i C_d prod_{e != i, d} S_e."""
+        x = np.atleast_2d(np.asarray(x, float))
+        D = self.dim
+        lap = np.zeros((x.shape[0], D))
+        gd = np.zeros((x.shape[0], D))
+        for t in range(self.coef.shape[0]):
+            k, a = self.k[t], self.coef[t]
+            S, C = [], []
+            for d in range(D):
+                arg = k[d] * x[:, d] + self.phase[t, d]
+                S.append(np.sin(arg))
+                C.append(np.cos(arg))
+            P = S[0]
+            for d in range(1, D):
+                P = P * S[d]
+            lap -= float(np.sum(k * k)) * P[:, None] * a[None, :]
+            for j in range(D):
+                g = -(k[j] ** 2) * a[j] * P
+                for d in range(D):
+                    if d == j:
+                        continue
+                    term = (k[j] * k[d] * a[d]) * C[j] * C[d]
+                    for e in range(D):
+                        if e != j and e != d:
+                            term = term * S[e]
+                    g = g + term
+                gd[:, j] += g
+        return lap, gd
 
 
 @dataclass
@@ -136,6 +170,23 @@ def body_force_le(fld: Field, mu: float, lam: float, x: np.ndarray) -> np.ndarra
     """f_b = -(mu lap u + (mu + lambda) grad div u) at x (m, dim)."""
     dim = fld.dim
     x = np.atleast_2d(x)
+    if isinstance(fld, TrigField):  # the two contractions directly, chunks of points on threads
+        f = np.empty((x.shape[0], dim))
+        step = 1 << 20
+
+        def chunk(a):
+            lap, graddiv = fld.lap_and_graddiv(x[a:a + step])
+            f[a:a + step] = -(mu * lap + (mu + lam) * graddiv)
+
+        starts = range(0, x.shape[0], step)
+        if len(starts) > 1:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+                list(ex.map(chunk, starts))
+        else:
+            for a in starts:
+                chunk(a)
+        return f
     f = np.zeros((x.shape[0], dim))
     for d in range(dim):
         f -= mu * fld.second(x, d, d)
