@@ -282,3 +282,123 @@ def face_geometry(verts: np.ndarray, fverts: np.ndarray, n_gauss: int, fan: bool
         qw = qw / qw.sum(axis=1, keepdims=True)
     centre = np.einsum("fq,fqd->fd", qw, qpts)
     return FaceGeom(centre, normal, area, qpts, qw)
+
+
+# ---- face-list (polygonal / polyhedral) meshes (Sec. 3.1) --------------------
+#
+# Readings: a polygonal face of m vertices is cut into m - 2 triangles by a fan
+# from its lowest-numbered vertex (cyclic order kept), each with the triangle
+# rule above and weights scaled by its area over the sum of the areas; Gamma_f
+# is that sum and n_f the direction of the face's vector area
+# 1/2 sum_k x_k x x_{k+1}.  Faces with fewer points than the mesh's largest
+# count are padded with zero-weight points at their centre.  A cell is cut
+# into tetrahedra (triangles in 2D) joining the mean of its vertices to the
+# fan triangles (edges) of its faces, oriented outward; Omega_P and x_P are
+# their summed volumes and volume-weighted centroids, and the body force is
+# integrated by the conical-product rule with p + 2 points per direction on
+# each of them.
+
+
+def poly_faces(mesh):
+    """Owner (lower cell id) and neighbour of every face of a face-list mesh,
+    and its vertex loop oriented outward from the owner."""
+    fc = np.asarray(mesh.face_cells)
+    c0, c1 = fc[:, 0], fc[:, 1]
+    flip = (c1 >= 0) & (c1 < c0)
+    owner = np.where(flip, c1, c0)
+    neigh = np.where(flip, c0, c1)
+    ptr = np.asarray(mesh.face_ptr)
+    loops = []
+    for f in range(fc.shape[0]):
+        L = np.asarray(mesh.face_verts[ptr[f]:ptr[f + 1]], np.int64)
+        loops.append(L[::-1].copy() if flip[f] else L)
+    return owner, neigh, loops
+
+
+def _fan(L):
+    """Fan triangles (vertex ids) of the loop L from its lowest vertex."""
+    m = len(L)
+    s = int(np.argmin(L))
+    Y = [L[(s + k) % m] for k in range(m)]
+    return [(Y[0], Y[k], Y[k + 1]) for k in range(1, m - 1)]
+
+
+def polygon_face_geometry(verts, loops, n_gauss):
+    """FaceGeom of the faces given by vertex loops (2D: edges)."""
+    D = verts.shape[1]
+    if D == 2:
+        return face_geometry(verts, np.asarray(loops, np.int64), n_gauss)
+    nf = len(loops)
+    nq = max(len(L) - 2 for L in loops) * n_gauss * n_gauss
+    centre = np.zeros((nf, 3))
+    normal = np.zeros((nf, 3))
+    area = np.zeros(nf)
+    qpts = np.zeros((nf, nq, 3))
+    qw = np.zeros((nf, nq))
+    for f, L in enumerate(loops):
+        P = verts[L]
+        S = 0.5 * np.sum(np.cross(P, np.roll(P, -1, axis=0)), axis=0)
+        normal[f] = S / np.linalg.norm(S)
+        tris = _fan(L)
+        At = np.array([0.5 * np.linalg.norm(np.cross(verts[b] - verts[a], verts[c] - verts[a])) for a, b, c in tris])
+        pts, wts = [], []
+        for (a, b, c), A in zip(tris, At):
+            x, wt = _triangle_points(verts[a][None], verts[b][None], verts[c][None], n_gauss)
+            pts.append(x[0])
+            wts.append(wt * A / At.sum())
+        x = np.concatenate(pts)
+        wq = np.concatenate(wts)
+        area[f] = At.sum()
+        centre[f] = wq @ x
+        qpts[f, :x.shape[0]] = x
+        qpts[f, x.shape[0]:] = centre[f]
+        qw[f, :x.shape[0]] = wq
+    return FaceGeom(centre, normal, area, qpts, qw)
+
+
+def poly_cells(mesh, owner, neigh, loops, n_vol):
+    """Volumes, centroids and body-force quadrature (points, weights, cell of
+    each point) of the cells of a face-list mesh; n_vol points per direction
+    on each sub-simplex."""
+    D = mesh.dim
+    n_c = mesh.n_cells
+    vsum = np.zeros((n_c, D))
+    vcnt = np.zeros(n_c)
+    cell_verts = [set() for _ in range(n_c)]
+    for f, L in enumerate(loops):
+        for c in (owner[f], neigh[f]):
+            if c >= 0:
+                cell_verts[c].update(int(v) for v in L)
+    for c in range(n_c):
+        ids = np.array(sorted(cell_verts[c]))
+        vsum[c] = mesh.verts[ids].sum(axis=0)
+        vcnt[c] = ids.size
+    apex = vsum / vcnt[:, None]
+    simp, cell_of = [], []
+    for f, L in enumerate(loops):
+        for c, Lc in ((owner[f], L), (neigh[f], L[::-1])):
+            if c < 0:
+                continue
+            if D == 2:
+                simp.append(np.stack([apex[c], mesh.verts[Lc[0]], mesh.verts[Lc[1]]]))
+                cell_of.append(c)
+            else:
+                for a, b, cc in _fan(np.asarray(Lc)):
+                    simp.append(np.stack([apex[c], mesh.verts[a], mesh.verts[b], mesh.verts[cc]]))
+                    cell_of.append(c)
+    X = np.array(simp)
+    cell_of = np.array(cell_of, np.int64)
+    if D == 2:
+        e1, e2 = X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]
+        vs = 0.5 * (e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
+        pts, W = tri_quadrature(X, n_vol)
+    else:
+        vs = np.einsum("cd,cd->c", np.cross(X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]), X[:, 3] - X[:, 0]) / 6.0
+        pts, W = tet_quadrature(X, n_vol)
+    vol = np.zeros(n_c)
+    np.add.at(vol, cell_of, vs)
+    mom = np.zeros((n_c, D))
+    np.add.at(mom, cell_of, vs[:, None] * X.mean(axis=1))
+    cen = mom / vol[:, None]
+    nq = pts.shape[1]
+    return vol, cen, pts.reshape(-1, D), W.reshape(-1), np.repeat(cell_of, nq)

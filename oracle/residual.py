@@ -172,10 +172,17 @@ def build(problem, active=None) -> Discretisation:
     mesh = problem.mesh
     D, p, S = mesh.dim, problem.p, problem.stencil_size
     n_c = mesh.n_cells
-    X = mesh.verts[mesh.cells]
-    vol, cen = geo.cell_volume_centroid(X)
-    faces = geo.enumerate_faces(mesh.cells, D)
-    fg = geo.face_geometry(mesh.verts, faces.verts, problem.n_gauss, fan=problem.face_rule == 1)
+    poly = hasattr(mesh, "face_cells")  # a face-list (polygonal / polyhedral) mesh
+    if poly:
+        own, nei, loops = geo.poly_faces(mesh)
+        faces = geo.Faces(owner=own, neigh=nei, verts=None, owner_slot=None, neigh_slot=None)
+        fg = geo.polygon_face_geometry(mesh.verts, loops, problem.n_gauss)
+        vol, cen, vq_pts, vq_w, vq_cell = geo.poly_cells(mesh, own, nei, loops, p + 2)
+    else:
+        X = mesh.verts[mesh.cells]
+        vol, cen = geo.cell_volume_centroid(X)
+        faces = geo.enumerate_faces(mesh.cells, D)
+        fg = geo.face_geometry(mesh.verts, faces.verts, problem.n_gauss, fan=problem.face_rule == 1)
     act = np.ones(n_c, bool)
     if active is not None:
         act = np.zeros(n_c, bool)
@@ -222,10 +229,16 @@ def build(problem, active=None) -> Discretisation:
     if D3 is not None:
         c_D3 = np.zeros((n_c, D, D, D, S)); c_D3[cells] = D3
 
-    # body force (p+2)^D Gauss points of the cell map
+    # body force: (p+2)^D Gauss points of the cell map (of each sub-simplex of a
+    # polyhedral cell)
     b_body = np.zeros((n_c, D))
     ac = np.nonzero(act)[0]
-    if ac.size:
+    if poly:
+        sel = act[vq_cell]
+        if sel.any():
+            fb = loads.body(vq_pts[sel])
+            np.add.at(b_body, vq_cell[sel], vq_w[sel, None] * fb)
+    elif ac.size:
         pts, W = geo.cell_quadrature(X[ac], p + 2)
         fb = loads.body(pts.reshape(-1, D)).reshape(pts.shape)
         b_body[ac] = np.einsum("cq,cqd->cd", W, fb)

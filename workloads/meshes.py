@@ -150,3 +150,102 @@ def tri_mesh(shape, lengths=None, origin=None, perturb: float = 0.0, seed: int =
 def cell_ijk(mesh: Mesh) -> np.ndarray:
     """Structured (i, j[, k]) index of every cell, (n_cells, dim)."""
     return np.indices(mesh.shape[::-1]).reshape(mesh.dim, -1)[::-1].T.copy()
+
+
+# ---- face-list (polygonal / polyhedral) meshes --------------------------------
+
+@dataclass
+class PolyMesh:
+    """A mesh given by its faces: face f has the vertex loop
+    face_verts[face_ptr[f]:face_ptr[f + 1]] (2 vertices in 2D) whose right-hand
+    normal points out of cell face_cells[f, 0] and into face_cells[f, 1]
+    (-1 on the boundary).  Cells are the regions the faces enclose."""
+    dim: int
+    verts: np.ndarray       # (n_verts, dim)
+    face_ptr: np.ndarray    # (n_faces + 1,) int64
+    face_verts: np.ndarray  # int64
+    face_cells: np.ndarray  # (n_faces, 2) int64
+    n_cells_: int
+    shape: tuple            # cells per axis of the fine grid it was made from
+    lengths: tuple
+    origin: tuple
+    fine_cell_of: np.ndarray  # (n_fine_cells,) the polyhedral cell holding each fine cell
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.n_cells_)
+
+    @property
+    def n_verts(self) -> int:
+        return int(self.verts.shape[0])
+
+    @property
+    def n_faces(self) -> int:
+        return int(self.face_cells.shape[0])
+
+    def spacing(self) -> np.ndarray:
+        return np.asarray(self.lengths, float) / np.asarray(self.shape, float)
+
+
+# outward vertex loops of the faces of a VTK quad / hexahedron
+_QUAD_EDGES = np.array([[3, 0], [1, 2], [0, 1], [2, 3]])
+_HEX_LOOPS = np.array([[0, 4, 7, 3], [1, 2, 6, 5], [0, 1, 5, 4], [3, 7, 6, 2], [0, 3, 2, 1], [4, 5, 6, 7]])
+
+
+def split_block_mesh(coarse_shape, lengths=None, origin=None, perturb: float = 0.0, seed: int = 0,
+                     mode: str = "random") -> PolyMesh:
+    """A polygonal (2D) or polyhedral (3D) mesh with hanging vertices: the
+    structured mesh of ``box_mesh`` with twice as many cells per axis (same
+    perturbation rules) in which the 2^dim fine cells of every coarse block
+    (I, J[, K]) with I + J (+ K) even are merged into one cell.  A merged cell
+    keeps the fine faces on its block's boundary, so it has 8 edges (2D) or 24
+    quadrilateral faces (3D), each shared with one fine neighbour; the other
+    cells are the fine quads or hexahedra.  Cells are numbered in the order
+    their first fine cell appears (lexicographic, i fastest)."""
+    cs = tuple(int(s) for s in coarse_shape)
+    dim = len(cs)
+    fine = box_mesh(tuple(2 * s for s in cs), lengths, origin, perturb, seed, mode)
+    ijk = cell_ijk(fine)
+    blk = ijk // 2
+    merged = blk.sum(axis=1) % 2 == 0
+    bid = np.ravel_multi_index(tuple(blk[:, a] for a in range(dim)[::-1]), cs[::-1])
+    cell_of = np.full(fine.n_cells, -1, np.int64)
+    block_cell = {}
+    nxt = 0
+    for f in range(fine.n_cells):
+        if merged[f]:
+            b = int(bid[f])
+            if b not in block_cell:
+                block_cell[b] = nxt
+                nxt += 1
+            cell_of[f] = block_cell[b]
+        else:
+            cell_of[f] = nxt
+            nxt += 1
+    loops = _QUAD_EDGES if dim == 2 else _HEX_LOOPS
+    nl = loops.shape[0]
+    fv = fine.cells[:, loops]                       # (n_fine, nl, nvf)
+    flat = fv.reshape(fine.n_cells * nl, -1)
+    keys = np.sort(flat, axis=1)
+    _, inv, counts = np.unique(keys, axis=0, return_inverse=True, return_counts=True)
+    inv = inv.ravel()
+    first = np.full(counts.size, -1, np.int64)
+    second = np.full(counts.size, -1, np.int64)
+    for r in range(flat.shape[0]):
+        u = inv[r]
+        if first[u] < 0:
+            first[u] = r
+        else:
+            second[u] = r
+    c0 = cell_of[first // nl]
+    c1 = np.where(second >= 0, cell_of[np.maximum(second, 0) // nl], -1)
+    keep = c0 != c1  # faces inside a merged block disappear
+    first, c0, c1 = first[keep], c0[keep], c1[keep]
+    order = np.lexsort((c1, c0))
+    first, c0, c1 = first[order], c0[order], c1[order]
+    nvf = flat.shape[1]
+    face_verts = flat[first].reshape(-1)
+    face_ptr = np.arange(first.size + 1, dtype=np.int64) * nvf
+    return PolyMesh(dim, fine.verts, face_ptr, np.ascontiguousarray(face_verts, np.int64),
+                    np.ascontiguousarray(np.stack([c0, c1], axis=1), np.int64), nxt, fine.shape,
+                    fine.lengths, fine.origin, cell_of)
