@@ -127,6 +127,28 @@ hofv_status hofv_set_mesh(hofv_ctx* ctx, int64_t n_verts, const double* verts,
 hofv_status hofv_set_mesh_simplices(hofv_ctx* ctx, int64_t n_verts, const double* verts, int64_t n_cells,
                                     const int64_t* cell_verts);
 
+/* Polygonal (2D) or polyhedral (3D) mesh given by its faces (Sec. 3.1: the
+ * paper's arbitrary convex polyhedra): face f has the vertex loop
+ * face_verts[face_ptr[f] .. face_ptr[f + 1]) (2 vertices in 2D, at least 3 in
+ * 3D, face_ptr[0] = 0) whose right-hand normal points out of cell
+ * face_cells[2 f] and into face_cells[2 f + 1] (-1: boundary face).  A 3D face
+ * is cut into triangles by a fan from its lowest-numbered vertex; its area is
+ * the sum of the triangle areas, its normal the direction of its vector area
+ * 1/2 sum x_k x x_{k+1}, and its quadrature points are n_gauss^2 per triangle
+ * (faces with fewer triangles than the mesh's largest are padded with
+ * zero-weight points at their centre, so n_q = (most vertices - 2) n_gauss^2;
+ * face_rule is ignored).  A cell is cut into triangles (2D) or tetrahedra
+ * (3D) joining the mean of its distinct vertices to its faces' edges or fan
+ * triangles: its volume and centroid are theirs summed, and its body-force
+ * points are (order_p + 2)^dim per simplex (see hofv_volume_qpoints_csr).
+ * Cells with more than 2 dim faces give each face its own extrapolation item.
+ * HOFV_EINVAL for malformed input (bad indices, a face cell equal on both
+ * sides, a cell with fewer than dim + 1 faces or more than 255, non-positive
+ * volume).  Called instead of hofv_set_mesh, once. */
+hofv_status hofv_set_mesh_polyhedra(hofv_ctx* ctx, int64_t n_verts, const double* verts, int64_t n_cells,
+                                    int64_t n_faces, const int64_t* face_ptr, const int64_t* face_verts,
+                                    const int64_t* face_cells);
+
 /* Boundary faces in the library's order, so that the caller can evaluate its
  * boundary conditions there: face centres x_b [n][dim], unit outward normals
  * [n][dim], quadrature points x_{b,q} [n][n_q][dim] with n_q = n_gauss^(dim-1).
@@ -140,8 +162,15 @@ hofv_status hofv_boundary_faces(hofv_ctx* ctx, int64_t* n_bfaces, int32_t* n_q,
 hofv_status hofv_cell_centroids(hofv_ctx* ctx, const double** centroids);
 
 /* Volume quadrature points of the body-force integral (eq. bodyTerm),
- * [n_cells][n_qv][dim], n_qv = (p+2)^dim Gauss-Legendre points of the cell map. */
+ * [n_cells][n_qv][dim], n_qv = (p+2)^dim Gauss-Legendre points of the cell map.
+ * HOFV_EINVAL when cells have different point counts (polyhedral meshes). */
 hofv_status hofv_volume_qpoints(hofv_ctx* ctx, int32_t* n_qv, const double** points);
+
+/* The same points for any mesh: cell P's are points[cell_ptr[P] ..
+ * cell_ptr[P + 1]) ([n_points][dim]); cell_ptr has n_cells + 1 entries.
+ * Pointers are owned by ctx. */
+hofv_status hofv_volume_qpoints_csr(hofv_ctx* ctx, int64_t* n_points, const int64_t** cell_ptr,
+                                    const double** points);
 
 /* Boundary conditions (Sec. 3.5.3), per boundary face in hofv_boundary_faces
  * order: type[n] (HOFV_BC_*); u_b at the quadrature points [n][n_q][dim] and at
@@ -151,7 +180,9 @@ hofv_status hofv_volume_qpoints(hofv_ctx* ctx, int32_t* n_qv, const double** poi
 hofv_status hofv_set_bc(hofv_ctx* ctx, const int32_t* type, const double* u_b_q,
                         const double* u_b_centre, const double* traction_q);
 
-/* Body force f_b at the volume quadrature points [n_cells][n_qv][dim]; NULL = 0. */
+/* Body force f_b at the volume quadrature points, in their order ([n_points][dim]
+ * of hofv_volume_qpoints_csr, i.e. [n_cells][n_qv][dim] when the counts are
+ * equal); NULL = 0. */
 hofv_status hofv_set_body_force(hofv_ctx* ctx, const double* values);
 
 typedef struct {

@@ -82,6 +82,9 @@ SIGNATURES = {
     "hofv_last_error": (C.c_char_p, [P]),
     "hofv_set_mesh": (ST, [P, I64, D, I64, C.POINTER(C.c_int64)]),
     "hofv_set_mesh_simplices": (ST, [P, I64, D, I64, C.POINTER(C.c_int64)]),
+    "hofv_set_mesh_polyhedra": (ST, [P, I64, D, I64, I64, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64)]),
+    "hofv_volume_qpoints_csr": (ST, [P, C.POINTER(I64), C.POINTER(C.POINTER(C.c_int64)), C.POINTER(D)]),
     "hofv_boundary_faces": (ST, [P, C.POINTER(I64), C.POINTER(C.c_int32), C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
     "hofv_volume_qpoints": (ST, [P, C.POINTER(C.c_int32), C.POINTER(D)]),
     "hofv_cell_centroids": (ST, [P, C.POINTER(D)]),

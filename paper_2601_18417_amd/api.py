@@ -96,6 +96,25 @@ class Context:
                        cells.ctypes.data_as(C.POINTER(C.c_int64))))
         self.n_cells = cells.shape[0]
 
+    def set_mesh_poly(self, verts, face_ptr, face_verts, face_cells, n_cells):
+        """Face-list (polygonal / polyhedral) mesh: face f's vertex loop is
+        face_verts[face_ptr[f]:face_ptr[f + 1]], its right-hand normal pointing
+        out of face_cells[f, 0] into face_cells[f, 1] (-1: boundary)."""
+        verts = np.ascontiguousarray(verts, np.float64)
+        fp = np.ascontiguousarray(face_ptr, np.int64)
+        fv = np.ascontiguousarray(face_verts, np.int64)
+        fc = np.ascontiguousarray(face_cells, np.int64)
+        if verts.ndim != 2 or verts.shape[1] != self.dim:
+            raise ValueError(f"verts must be (n_verts, {self.dim})")
+        nf = fc.shape[0]
+        if fc.shape != (nf, 2) or fp.shape != (nf + 1,) or fv.size != fp[-1]:
+            raise ValueError("face_cells must be (n_faces, 2), face_ptr (n_faces + 1,) ending at len(face_verts)")
+        P64 = C.POINTER(C.c_int64)
+        self._check(self.lib.hofv_set_mesh_polyhedra(self.h, verts.shape[0], _dptr(verts), int(n_cells), nf,
+                                                     fp.ctypes.data_as(P64), fv.ctypes.data_as(P64),
+                                                     fc.ctypes.data_as(P64)))
+        self.n_cells = int(n_cells)
+
     def boundary_faces(self):
         n = C.c_int64()
         nq = C.c_int32()
@@ -117,6 +136,16 @@ class Context:
         self._check(self.lib.hofv_volume_qpoints(self.h, C.byref(nqv), C.byref(pts)))
         return np.ctypeslib.as_array(pts, shape=(self.n_cells, nqv.value, self.dim)).copy()
 
+    def volume_qpoints_csr(self):
+        """(points (n_points, dim), cell_ptr (n_cells + 1,)): cell P's points
+        are points[cell_ptr[P]:cell_ptr[P + 1]]."""
+        n = C.c_int64()
+        ptr = C.POINTER(C.c_int64)()
+        pts = C.POINTER(C.c_double)()
+        self._check(self.lib.hofv_volume_qpoints_csr(self.h, C.byref(n), C.byref(ptr), C.byref(pts)))
+        cp = np.ctypeslib.as_array(ptr, shape=(self.n_cells + 1,)).copy()
+        return np.ctypeslib.as_array(pts, shape=(n.value, self.dim)).copy(), cp
+
     def set_bc(self, types, u_b_q, u_b_centre, traction_q):
         types = np.ascontiguousarray(types, np.int32)
         arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (u_b_q, u_b_centre, traction_q)]
@@ -133,12 +162,13 @@ class Context:
                                          *[_dptr(a) for a in arrs]))
 
     def set_body_force(self, values):
+        """f_b at every volume quadrature point, in the order of volume_qpoints_csr."""
         v = None if values is None else np.ascontiguousarray(values, np.float64)
         if v is not None:
-            nqv = C.c_int32()
-            self._check(self.lib.hofv_volume_qpoints(self.h, C.byref(nqv), None))
-            if v.size != self.n_cells * nqv.value * self.dim:
-                raise ValueError(f"body force must be ({self.n_cells}, {nqv.value}, {self.dim})")
+            n = C.c_int64()
+            self._check(self.lib.hofv_volume_qpoints_csr(self.h, C.byref(n), None, None))
+            if v.size != n.value * self.dim:
+                raise ValueError(f"body force must have {n.value} x {self.dim} values")
         self._check(self.lib.hofv_set_body_force(self.h, _dptr(v)))
 
     def setup(self):
@@ -410,7 +440,11 @@ def context_for(problem, fold_quadrature=True, host_only=False, precond_levels=1
     ctx = Context(problem.mesh.dim, problem.p, problem.n_plus, problem.n_gauss, problem.material, problem.mu,
                   problem.lam, problem.alpha, problem.k_weight, problem.ghost_weight, problem.stencil_quantum,
                   fold_quadrature, host_only, precond_levels, problem.face_rule)
-    ctx.set_mesh(problem.mesh.verts, problem.mesh.cells)
+    m = problem.mesh
+    if hasattr(m, "face_cells"):
+        ctx.set_mesh_poly(m.verts, m.face_ptr, m.face_verts, m.face_cells, m.n_cells)
+    else:
+        ctx.set_mesh(m.verts, m.cells)
     note("mesh")
     cen, nor, qp = ctx.boundary_faces()
     D = problem.mesh.dim
@@ -422,8 +456,8 @@ def context_for(problem, fold_quadrature=True, host_only=False, precond_levels=1
     tq = loads.traction(qp.reshape(-1, D), np.repeat(nor, nq, axis=0)).reshape(nb, nq, D) if nb else None
     ctx.set_bc(types, ubq, ubc, tq)
     note("boundary conditions")
-    vq = ctx.volume_qpoints()
-    ctx.set_body_force(loads.body(vq.reshape(-1, D)).reshape(vq.shape))
+    vq, _ = ctx.volume_qpoints_csr()
+    ctx.set_body_force(loads.body(vq))
     note("body force")
     ctx.setup()
     note("setup")

@@ -156,6 +156,25 @@ hofv_status hofv_set_mesh_simplices(hofv_ctx* c, int64_t n_verts, const double* 
   return HOFV_OK;
 }
 
+hofv_status hofv_set_mesh_polyhedra(hofv_ctx* c, int64_t n_verts, const double* verts, int64_t n_cells,
+                                   int64_t n_faces, const int64_t* face_ptr, const int64_t* face_verts,
+                                   const int64_t* face_cells) {
+  if (!c) return fail(nullptr, HOFV_EINVAL, "null context");
+  if (c->state != 0) return fail(c, HOFV_ESTATE, "set_mesh may be called once");
+  if (n_verts <= 0 || n_cells <= 0 || n_faces <= 0 || !verts || !face_ptr || !face_verts || !face_cells)
+    return fail(c, HOFV_EINVAL, "empty mesh");
+  if (n_cells >= INT32_MAX / 8 || n_faces >= INT32_MAX / 2) return fail(c, HOFV_EINVAL, "too many cells for 32-bit indices");
+  c->nv = n_verts;
+  c->nc = n_cells;
+  c->verts.assign(verts, verts + n_verts * c->D);
+  c->cells.clear();
+  hofv_status s;
+  if ((s = build_topology_poly(c, n_faces, face_ptr, face_verts, face_cells))) return s;
+  if ((s = build_geometry(c))) return s;
+  c->state = 1;
+  return HOFV_OK;
+}
+
 hofv_status hofv_boundary_faces(hofv_ctx* c, int64_t* n_bfaces, int32_t* n_q, const double** centres,
                                 const double** normals, const double** qpoints) {
   hofv_status s = need(c, 1, "boundary_faces");
@@ -179,7 +198,20 @@ hofv_status hofv_cell_centroids(hofv_ctx* c, const double** centroids) {
 hofv_status hofv_volume_qpoints(hofv_ctx* c, int32_t* n_qv, const double** points) {
   hofv_status s = need(c, 1, "volume_qpoints");
   if (s) return s;
+  for (int64_t P = 0; P < c->nc; ++P)
+    if (c->vq_ptr[P + 1] - c->vq_ptr[P] != c->nqv)
+      return fail(c, HOFV_EINVAL, "cells have different numbers of volume points: use hofv_volume_qpoints_csr");
   if (n_qv) *n_qv = c->nqv;
+  if (points) *points = c->vq_pts.data();
+  return HOFV_OK;
+}
+
+hofv_status hofv_volume_qpoints_csr(hofv_ctx* c, int64_t* n_points, const int64_t** cell_ptr,
+                                    const double** points) {
+  hofv_status s = need(c, 1, "volume_qpoints_csr");
+  if (s) return s;
+  if (n_points) *n_points = c->vq_ptr[c->nc];
+  if (cell_ptr) *cell_ptr = c->vq_ptr.data();
   if (points) *points = c->vq_pts.data();
   return HOFV_OK;
 }
@@ -213,7 +245,7 @@ hofv_status hofv_set_body_force(hofv_ctx* c, const double* values) {
   hofv_status s = need(c, 1, "set_body_force");
   if (s) return s;
   if (c->state >= 4) return fail(c, HOFV_ESTATE, "set_body_force after setup");
-  if (values) c->fb.assign(values, values + (size_t)c->nc * c->nqv * c->D);
+  if (values) c->fb.assign(values, values + (size_t)c->vq_ptr[c->nc] * c->D);
   else c->fb.clear();
   c->state = std::max(c->state, 3);
   return HOFV_OK;

@@ -65,7 +65,10 @@ struct DeviceTables {
   int32_t* c_blk_cell = nullptr;
   int32_t* c_ucell = nullptr;
   uint16_t* c_local = nullptr;    // [S][nc]
-  int32_t* c_cell = nullptr;      // [nc] cell of each extrapolation item (Morton order)
+  int32_t* c_cell = nullptr;      // [n_items] cell of each extrapolation item (Morton order)
+  int32_t ns = 0;                 // face slots per cell
+  int32_t nsi = 0;                // face slots per extrapolation item: ns, or 1 (one item per cell face)
+  int64_t n_items = 0;            // extrapolation items
   // faces
   double* f_coef = nullptr;      // folded: [S][D][nf]; per-point: [S][nq][D][nf]
   int32_t* f_own = nullptr;      // [nf] owner's extrapolation item
@@ -184,6 +187,12 @@ struct hofv_ctx {
     int64_t v[4];
   };
   std::vector<Face> faces;           // internal faces first, then boundary faces
+  // face-list (polygonal / polyhedral) meshes: each face's vertex loop,
+  // outward from its owner, in the order of `faces`
+  bool poly = false;
+  std::vector<int64_t> fv_ptr, fv;
+  int NS = 0;                        // face slots per cell (most faces of one cell)
+  std::vector<int64_t> vq_ptr;       // [nc + 1] volume quadrature points of each cell
   int64_t n_internal = 0;
   std::vector<int64_t> bface;        // indices into faces of boundary faces (caller order)
   int32_t nq = 0, nqv = 0;
@@ -191,7 +200,7 @@ struct hofv_ctx {
   std::vector<double> f_centre, f_normal, f_area, f_qp, f_qw;
   // boundary views handed to the caller
   std::vector<double> b_centre, b_normal, b_qp;
-  std::vector<double> vq_pts, vq_w;  // [nc][nqv][D], [nc][nqv]
+  std::vector<double> vq_pts, vq_w;  // [n_points][D], [n_points], cell P's from vq_ptr[P]
 
   // boundary data from the caller
   std::vector<int32_t> btype;
@@ -262,6 +271,8 @@ hofv_status upload(hofv_ctx* c, T** p, const std::vector<T>& host) {
 
 // host setup stages (setup_*.cpp)
 hofv_status build_topology(hofv_ctx* c);
+hofv_status build_topology_poly(hofv_ctx* c, int64_t n_faces, const int64_t* face_ptr, const int64_t* face_verts,
+                                const int64_t* face_cells);
 hofv_status build_geometry(hofv_ctx* c);
 hofv_status build_tables(hofv_ctx* c);
 

@@ -175,16 +175,16 @@ __device__ inline void contract_lds(int S, int64_t ld, int64_t item, const uint1
   }
 }
 
-// u*_{f,P} - u_P = sum_k E[k][slot][r] u(S_P[k]) for every face slot of the
-// cell P of extrapolation item r; ustar is indexed by item
-template <int D>
+// u*_{f,P} - u_P = sum_k E[k][slot][r] u(S_P[k]) for every face slot of
+// extrapolation item r (NS slots: a cell's faces, or one face of it); its
+// cell P = cell[r]; ustar is indexed by item (nc: the number of items)
+template <int D, int NS>
 __global__ __launch_bounds__(kBlockItems) void k_extrap(int64_t nc, int S, const int32_t* __restrict__ blk_item,
                                                     const int32_t* __restrict__ blk_cell,
                                                     const int32_t* __restrict__ ucell,
                                                     const uint16_t* __restrict__ loc, const double* __restrict__ E,
                                                     const int32_t* __restrict__ cell, const double* __restrict__ ug,
                                                     double* __restrict__ ustar) {
-  constexpr int NS = 2 * D;
   __shared__ double lds[D][kLdsCellCells];
   const int64_t b = xcd_block();
   stage_union<D, kLdsCellCells>(b, blk_cell, ucell, ug, lds);
@@ -463,39 +463,43 @@ __global__ __launch_bounds__(kBlock) void k_face_sym_nh(int64_t nfs, int Sh, con
   for (int j = 0; j < 3; ++j) Fs[(int64_t)j * nfs + f] = t[j];
 }
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, const int32_t* __restrict__ cf,
+// NST > 0: NST face slots per cell known at compile time; 0: ns at run time
+template <int D, int NST>
+__global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, int ns, const int32_t* __restrict__ cf,
                                                       const double* __restrict__ F, const double* __restrict__ src,
                                                       double load, const double* __restrict__ Ru,
                                                       const double* __restrict__ eps, const double* __restrict__ ug,
                                                       const double* __restrict__ dm, const double* __restrict__ ds,
                                                       const double* __restrict__ Fs, int64_t nfs,
                                                       double* __restrict__ R) {
-  constexpr int NS = 2 * D;
   constexpr int W = D == 3 ? 4 : 2;
+  const int NS = NST > 0 ? NST : ns;
   const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (P >= nc) return;
-  int32_t code[NS];
+  double acc[D];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) code[s] = cf[(int64_t)s * nc + P];
+  for (int c = 0; c < D; ++c) acc[c] = load * src[(int64_t)c * nc + P];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int32_t k = cf[(int64_t)s * nc + P];
+    if (k == kNoFace) continue;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      if (k >= nf) acc[c] += Fs[(int64_t)c * nfs + (k - nf)];  // symmetry face
+      else if (k >= 0) acc[c] += F[(int64_t)c * nf + k];
+      else acc[c] -= F[(int64_t)c * nf + ~k];
+    }
+  }
 #pragma unroll
   for (int c = 0; c < D; ++c) {
-    double acc = load * src[(int64_t)c * nc + P];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const int32_t k = code[s];
-      if (k == kNoFace) continue;
-      if (k >= nf) acc += Fs[(int64_t)c * nfs + (k - nf)];  // symmetry face
-      else if (k >= 0) acc += F[(int64_t)c * nf + k];
-      else acc -= F[(int64_t)c * nf + ~k];
-    }
+    double a = acc[c];
     // BDF2 inertia at the centroid: s_P - m_P u_P (u from the gather copy)
-    if (dm) acc += ds[(int64_t)c * nc + P] - dm[P] * ug[(int64_t)W * P + c];
+    if (dm) a += ds[(int64_t)c * nc + P] - dm[P] * ug[(int64_t)W * P + c];
     if (Ru) {
       const double e = eps[0];
-      acc = e > 0.0 ? (acc - Ru[(int64_t)c * nc + P]) / e : 0.0;
+      a = e > 0.0 ? (a - Ru[(int64_t)c * nc + P]) / e : 0.0;
     }
-    R[(int64_t)c * nc + P] = acc;
+    R[(int64_t)c * nc + P] = a;
   }
 }
 
@@ -569,12 +573,12 @@ __global__ __launch_bounds__(kBlock) void k_pc_in(int64_t nc, const int32_t* __r
   }
 }
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_pc_sweep(int64_t nc, int64_t begin, int64_t end,
+template <int D, int NST>
+__global__ __launch_bounds__(kBlock) void k_pc_sweep(int64_t nc, int64_t begin, int64_t end, int ns,
                                                      const int32_t* __restrict__ nbr, const float* __restrict__ a,
                                                      const float* __restrict__ dinv, const float* __restrict__ r32,
                                                      float* __restrict__ z32) {
-  constexpr int NS = 2 * D;
+  const int NS = NST > 0 ? NST : ns;
   const int64_t i = begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= end) return;
   float acc[D];
@@ -605,12 +609,12 @@ __global__ __launch_bounds__(kBlock) void k_pc_out(int64_t nc, const int32_t* __
 // ---- multigrid V-cycle on the approximate Jacobian (FP32, D right-hand sides)
 
 // t = r - A z on level 0 (2D-neighbour rows in colour-major order)
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_mg_res0(int64_t n, const int32_t* __restrict__ nbr,
+template <int D, int NST>
+__global__ __launch_bounds__(kBlock) void k_mg_res0(int64_t n, int ns, const int32_t* __restrict__ nbr,
                                                     const float* __restrict__ a, const float* __restrict__ diag,
                                                     const float* __restrict__ r, const float* __restrict__ z,
                                                     float* __restrict__ t) {
-  constexpr int NS = 2 * D;
+  const int NS = NST > 0 ? NST : ns;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const float di = diag[i];
@@ -770,25 +774,33 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
   const int64_t nc = c->nc, nf = t.nf;
   const bool nh = c->prm.material == HOFV_NEO_HOOKEAN;
   const bool fold = !nh && c->prm.fold_quadrature;
-  TIMED("k_extrap", (k_extrap<D><<<t.ncb, kBlockItems, 0, st>>>(nc, t.S, t.c_blk_item, t.c_blk_cell, t.c_ucell,
-                                                           t.c_local, t.c_extrap, t.c_cell, u, t.ustar)));
+  const int64_t ni = t.n_items;  // u* is indexed by extrapolation item
+  if (t.nsi == 1)
+    TIMED("k_extrap", (k_extrap<D, 1><<<t.ncb, kBlockItems, 0, st>>>(ni, t.S, t.c_blk_item, t.c_blk_cell, t.c_ucell,
+                                                                     t.c_local, t.c_extrap, t.c_cell, u, t.ustar)));
+  else
+    TIMED("k_extrap", (k_extrap<D, 2 * D><<<t.ncb, kBlockItems, 0, st>>>(ni, t.S, t.c_blk_item, t.c_blk_cell,
+                                                                         t.c_ucell, t.c_local, t.c_extrap, t.c_cell, u,
+                                                                         t.ustar)));
   if (nf > 0) {
     if (fold) {
       TIMED("k_face_le", (k_face_le<D><<<t.nfb, kBlockItems, 0, st>>>(
-                             nf, t.nfi, nc, t.S, t.f_blk_item, t.f_blk_cell, t.f_ucell, t.f_local, t.f_coef, t.f_own,
+                             nf, t.nfi, ni, t.S, t.f_blk_item, t.f_blk_cell, t.f_ucell, t.f_local, t.f_coef, t.f_own,
                              t.f_nei, t.f_slots, t.f_area_vec, t.f_stab, c->prm.mu, c->prm.lambda, u, t.ustar,
                              t.flux)));
     } else {
 #define FACEQ(NQ, MAT, NAME)                                                                                  \
   TIMED(NAME, (k_face_q<D, NQ, MAT><<<t.nfb, kBlockItems, 0, st>>>(                                                \
-                  nf, t.nfi, nc, t.S, t.f_blk_item, t.f_blk_cell, t.f_ucell, t.f_local, t.f_coef, t.f_own,     \
+                  nf, t.nfi, ni, t.S, t.f_blk_item, t.f_blk_cell, t.f_ucell, t.f_local, t.f_coef, t.f_own,     \
                   t.f_nei, t.f_slots, t.f_area_vec, t.f_stab, t.f_ghost, c->load, c->prm.mu, c->prm.lambda, u, \
                   t.ustar, t.flux, t.flag)))
       const int nq = t.nq;
       if (nh) {
         if constexpr (D == 3) {
           if (nq == 1) FACEQ(1, 1, "k_face_nh");
+          else if (nq == 2) FACEQ(2, 1, "k_face_nh");
           else if (nq == 4) FACEQ(4, 1, "k_face_nh");
+          else if (nq == 8) FACEQ(8, 1, "k_face_nh");
           else if (nq == 9) FACEQ(9, 1, "k_face_nh");
           else return fail(c, HOFV_EINVAL, "unsupported number of face quadrature points");
         } else {
@@ -799,6 +811,7 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
         else if (nq == 2) FACEQ(2, 0, "k_face_q");
         else if (nq == 3) FACEQ(3, 0, "k_face_q");
         else if (nq == 4) FACEQ(4, 0, "k_face_q");
+        else if (nq == 8) FACEQ(8, 0, "k_face_q");
         else if (nq == 9) FACEQ(9, 0, "k_face_q");
         else return fail(c, HOFV_EINVAL, "unsupported number of face quadrature points");
       }
@@ -814,15 +827,22 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
   k_face_sym_nh<Q><<<g, kBlock, 0, st>>>(t.sym_nf, t.sym_S, t.sym_st, t.sym_C, t.sym_sv, t.sym_n, c->prm.mu,        \
                                          c->prm.lambda, u, t.sym_flux, t.flag)
       if (t.nq == 1) SYMNH(1);
+      else if (t.nq == 2) SYMNH(2);
       else if (t.nq == 4) SYMNH(4);
+      else if (t.nq == 8) SYMNH(8);
       else if (t.nq == 9) SYMNH(9);
       else return fail(c, HOFV_EINVAL, "unsupported number of face quadrature points");
 #undef SYMNH
     }
   }
-  TIMED("k_cell_sum", (k_cell_sum<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, nf, t.c_faces, t.flux, t.c_src, c->load,
-                                                                          Ru, eps, u, t.dyn_m, t.dyn_s, t.sym_flux,
-                                                                          t.sym_nf, R)));
+  if (t.ns == 2 * D)
+    TIMED("k_cell_sum", (k_cell_sum<D, 2 * D><<<blocks_for(nc), kBlock, 0, st>>>(
+                            nc, nf, t.ns, t.c_faces, t.flux, t.c_src, c->load, Ru, eps, u, t.dyn_m, t.dyn_s,
+                            t.sym_flux, t.sym_nf, R)));
+  else
+    TIMED("k_cell_sum", (k_cell_sum<D, 0><<<blocks_for(nc), kBlock, 0, st>>>(
+                            nc, nf, t.ns, t.c_faces, t.flux, t.c_src, c->load, Ru, eps, u, t.dyn_m, t.dyn_s,
+                            t.sym_flux, t.sym_nf, R)));
   HOFV_HIP(c, hipGetLastError());
   return HOFV_OK;
 }
@@ -953,9 +973,12 @@ static void sgs_sweeps(hofv_ctx* c, int sweeps, hipStream_t st) {
         if (col == last) continue;
         last = col;
         const int64_t b = t.colour_start[col], e = t.colour_start[col + 1];
-        if (e > b)
-          TIMED("k_pc_sweep", (k_pc_sweep<D><<<blocks_for(e - b), kBlock, 0, st>>>(nc, b, e, t.p_nbr, t.p_a, t.p_dinv,
-                                                                                    t.p_r, t.p_z)));
+        if (e > b && t.ns == 2 * D)
+          TIMED("k_pc_sweep", (k_pc_sweep<D, 2 * D><<<blocks_for(e - b), kBlock, 0, st>>>(
+                                  nc, b, e, t.ns, t.p_nbr, t.p_a, t.p_dinv, t.p_r, t.p_z)));
+        else if (e > b)
+          TIMED("k_pc_sweep", (k_pc_sweep<D, 0><<<blocks_for(e - b), kBlock, 0, st>>>(nc, b, e, t.ns, t.p_nbr, t.p_a,
+                                                                                       t.p_dinv, t.p_r, t.p_z)));
       }
   }
 }
@@ -1024,8 +1047,10 @@ static void mg_vcycle(hofv_ctx* c, int l, int sweeps, hipStream_t st) {
   }
   if (l > 0) k_fill_f<<<blocks_for((int64_t)D * m.n), kBlock, 0, st>>>((int64_t)D * m.n, 0.0f, z);
   mg_smooth<D>(c, l, sweeps, st);
-  if (l == 0)
-    k_mg_res0<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.p_nbr, t.p_a, t.p_diag, r, z, m.t);
+  if (l == 0 && t.ns == 2 * D)
+    k_mg_res0<D, 2 * D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.ns, t.p_nbr, t.p_a, t.p_diag, r, z, m.t);
+  else if (l == 0)
+    k_mg_res0<D, 0><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.ns, t.p_nbr, t.p_a, t.p_diag, r, z, m.t);
   else
     mg_res<D>(m.n, m.ptr, m.col, m.val, m.diag, r, z, m.t, m.g_a, st);
   DeviceTables::MgLevel& q = t.mg[l + 1];

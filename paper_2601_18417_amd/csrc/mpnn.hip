@@ -646,7 +646,7 @@ static hofv_status nn_forward(hofv_ctx* c, hofv_nn* m, const double* r, const do
     const unsigned short* hin = w.h + (size_t)l * nc * kW;
     unsigned short* hout = w.h + (size_t)(l + 1) * nc * kW;
     TIMED_NN(c, "k_nn_layer", st,
-             (k_nn_layer<<<lb, kLayerThreads, 0, st>>>(nc, hin, t.g_nbr, reinterpret_cast<const float4*>(t.g_wf), 2 * D,
+             (k_nn_layer<<<lb, kLayerThreads, 0, st>>>(nc, hin, t.g_nbr, reinterpret_cast<const float4*>(t.g_wf), t.ns,
                                                        m->Wt + (size_t)l * kK * kW,
                                             m->p + kNnOffb(l), hout, train ? w.Y + (size_t)l * nc * kW : nullptr,
                                             train ? w.X + (size_t)l * nc * kK : nullptr)));
@@ -703,7 +703,7 @@ static hofv_status nn_grad_pair(hofv_ctx* c, hofv_nn* m, const double* r, const 
     reduce_grad((int64_t)kK * kW, nbw, (int64_t)kK * kW, w.part, w.part2, scale, m->g + kNnOffW(l), st);
     TIMED_NN(c, "k_nn_dx", st,
              (k_nn_dx<<<lb, kB, 0, st>>>(nc, w.dY, m->Wr + (size_t)l * kK * kW, dh, dh2, w.dA)));
-    k_nn_agg_t<<<(unsigned)nb4, kB, 0, st>>>(nc, t.g_nbr, t.g_wb, 2 * D, w.dA, dh2);
+    k_nn_agg_t<<<(unsigned)nb4, kB, 0, st>>>(nc, t.g_nbr, t.g_wb, t.ns, w.dA, dh2);
     std::swap(dh, dh2);
   }
   k_nn_encoder_bwd<<<(unsigned)nb4, kB, 0, st>>>(nc, w.x, w.h, dh, w.part);

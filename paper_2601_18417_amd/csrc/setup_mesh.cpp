@@ -216,6 +216,75 @@ hofv_status build_topology(hofv_ctx* c) {
   c->faces.insert(c->faces.end(), bnd.begin(), bnd.end());
   c->bface.resize(bnd.size());
   std::iota(c->bface.begin(), c->bface.end(), c->n_internal);
+  c->NS = 2 * D;  // simplices fill D + 1 of them
+  return HOFV_OK;
+}
+
+// Face-list mesh: face f has the vertex loop face_verts[face_ptr[f] ..
+// face_ptr[f + 1]) whose right-hand normal points out of face_cells[2 f] and
+// into face_cells[2 f + 1] (-1: boundary).  The owner becomes the lower cell
+// id (its loop reversed when that swaps the sides); slots number each cell's
+// faces in input order.
+hofv_status build_topology_poly(hofv_ctx* c, int64_t n_faces, const int64_t* face_ptr, const int64_t* face_verts,
+                                const int64_t* face_cells) {
+  const int D = c->D;
+  const int64_t nc = c->nc;
+  if (face_ptr[0] != 0) return fail(c, HOFV_EINVAL, "face_ptr[0] must be 0");
+  std::vector<int32_t> nslot(nc, 0);
+  struct Rec {
+    hofv_ctx::Face f;
+    int64_t src;  // input face
+    bool flip;
+  };
+  std::vector<Rec> inner, bnd;
+  for (int64_t f = 0; f < n_faces; ++f) {
+    const int64_t m = face_ptr[f + 1] - face_ptr[f];
+    if (D == 2 ? m != 2 : m < 3) return fail(c, HOFV_EINVAL, "a face needs 2 vertices in 2D, at least 3 in 3D");
+    for (int64_t k = face_ptr[f]; k < face_ptr[f + 1]; ++k)
+      if (face_verts[k] < 0 || face_verts[k] >= c->nv) return fail(c, HOFV_EINVAL, "face vertex index out of range");
+    int64_t a = face_cells[2 * f], b = face_cells[2 * f + 1];
+    if (a < 0 || a >= nc || b < -1 || b >= nc || a == b) return fail(c, HOFV_EINVAL, "bad face cells");
+    Rec r{};
+    r.src = f;
+    r.flip = b >= 0 && b < a;
+    r.f.own = r.flip ? b : a;
+    r.f.nei = r.flip ? a : b;
+    r.f.sown = nslot[r.f.own]++;
+    r.f.snei = r.f.nei >= 0 ? nslot[r.f.nei]++ : -1;
+    for (int k = 0; k < 4; ++k) r.f.v[k] = -1;
+    (b >= 0 ? inner : bnd).push_back(r);
+  }
+  int ns = 0;
+  for (int64_t P = 0; P < nc; ++P) {
+    if (nslot[P] < D + 1) return fail(c, HOFV_EINVAL, "a cell has fewer than dim + 1 faces");
+    ns = std::max(ns, nslot[P]);
+  }
+  if (ns > 255) return fail(c, HOFV_EINVAL, "a cell has more than 255 faces");
+  auto by_owner = [](const Rec& x, const Rec& y) {
+    return x.f.own != y.f.own ? x.f.own < y.f.own : x.f.sown < y.f.sown;
+  };
+  std::sort(inner.begin(), inner.end(), by_owner);
+  std::sort(bnd.begin(), bnd.end(), by_owner);
+  c->poly = true;
+  c->NS = ns;
+  c->n_internal = (int64_t)inner.size();
+  c->faces.clear();
+  c->fv_ptr.assign(1, 0);
+  c->fv.clear();
+  for (const std::vector<Rec>* part : {&inner, &bnd})
+    for (const Rec& r : *part) {
+      hofv_ctx::Face F = r.f;
+      const int64_t b0 = face_ptr[r.src], e0 = face_ptr[r.src + 1];
+      for (int64_t k = 0; k < e0 - b0; ++k) c->fv.push_back(face_verts[r.flip ? e0 - 1 - k : b0 + k]);
+      c->fv_ptr.push_back((int64_t)c->fv.size());
+      if (D == 2) {  // edges keep using the 2D face path
+        F.v[0] = c->fv[c->fv.size() - 2];
+        F.v[1] = c->fv[c->fv.size() - 1];
+      }
+      c->faces.push_back(F);
+    }
+  c->bface.resize(bnd.size());
+  std::iota(c->bface.begin(), c->bface.end(), c->n_internal);
   return HOFV_OK;
 }
 
@@ -235,10 +304,108 @@ hofv_status build_geometry(hofv_ctx* c) {
   gauss_jacobi01(p + 2, 1, j1x, j1w);
   gauss_jacobi01(ng, 1, t1x, t1w);
   const int nv1 = p + 2;
+  bool bad = false;
+  if (c->poly) {
+    // Cells cut into triangles (2D) or tetrahedra (3D) joining the mean x_a of
+    // the cell's distinct vertices to each face's edge or fan triangles,
+    // oriented outward (the neighbour side takes the reversed loop); volume and
+    // centroid are their sums, the body force takes the simplex rule with
+    // p + 2 points per direction on each.
+    const int npts = D == 2 ? nv1 * nv1 : nv1 * nv1 * nv1;
+    std::vector<std::vector<std::pair<int64_t, int>>> side(nc);  // (face, 0 owner | 1 neighbour)
+    std::vector<int64_t> nsimp(nc, 0);
+    for (int64_t f = 0; f < (int64_t)c->faces.size(); ++f) {
+      const hofv_ctx::Face& F = c->faces[f];
+      const int64_t t = D == 2 ? 1 : c->fv_ptr[f + 1] - c->fv_ptr[f] - 2;
+      side[F.own].push_back({f, 0});
+      nsimp[F.own] += t;
+      if (F.nei >= 0) {
+        side[F.nei].push_back({f, 1});
+        nsimp[F.nei] += t;
+      }
+    }
+    c->vq_ptr.assign(nc + 1, 0);
+    for (int64_t e = 0; e < nc; ++e) c->vq_ptr[e + 1] = c->vq_ptr[e] + nsimp[e] * npts;
+    c->nqv = 0;
+    for (int64_t e = 0; e < nc; ++e) c->nqv = std::max<int64_t>(c->nqv, nsimp[e] * npts);
+    c->vq_pts.assign((size_t)c->vq_ptr[nc] * D, 0.0);
+    c->vq_w.assign((size_t)c->vq_ptr[nc], 0.0);
+#pragma omp parallel for schedule(dynamic, 64) reduction(|| : bad)
+    for (int64_t e = 0; e < nc; ++e) {
+      std::vector<int64_t> vs;
+      for (auto& [f, sd] : side[e])
+        for (int64_t k = c->fv_ptr[f]; k < c->fv_ptr[f + 1]; ++k) vs.push_back(c->fv[k]);
+      std::sort(vs.begin(), vs.end());
+      vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+      double apex[3] = {0, 0, 0};
+      for (int64_t v : vs)
+        for (int d = 0; d < D; ++d) apex[d] += c->verts[(size_t)v * D + d];
+      for (int d = 0; d < D; ++d) apex[d] /= (double)vs.size();
+      double V = 0, mom[3] = {0, 0, 0};
+      int64_t q = c->vq_ptr[e];
+      auto add_simplex = [&](const double* const* X) {  // X[0] = apex, then the oriented face part
+        if (D == 2) {
+          const double e1[2] = {X[1][0] - X[0][0], X[1][1] - X[0][1]}, e2[2] = {X[2][0] - X[0][0], X[2][1] - X[0][1]};
+          const double det = e1[0] * e2[1] - e1[1] * e2[0];
+          V += 0.5 * det;
+          for (int d = 0; d < 2; ++d) mom[d] += 0.5 * det * (X[0][d] + X[1][d] + X[2][d]) / 3.0;
+          for (int i = 0; i < nv1; ++i)
+            for (int j = 0; j < nv1; ++j, ++q) {
+              const double a = j1x[i], b = gvx[j];
+              for (int d = 0; d < 2; ++d)
+                c->vq_pts[(size_t)q * 2 + d] = X[0][d] + a * (X[1][d] - X[0][d] + b * (X[2][d] - X[1][d]));
+              c->vq_w[q] = j1w[i] * gvw[j] * det;
+            }
+          return;
+        }
+        double e1[3], e2[3], e3[3], f2[3], f3[3], cr[3];
+        for (int d = 0; d < 3; ++d) {
+          e1[d] = X[1][d] - X[0][d];
+          e2[d] = X[2][d] - X[1][d];
+          e3[d] = X[3][d] - X[2][d];
+          f2[d] = X[2][d] - X[0][d];
+          f3[d] = X[3][d] - X[0][d];
+        }
+        cross3(e1, f2, cr);
+        const double det = cr[0] * f3[0] + cr[1] * f3[1] + cr[2] * f3[2];
+        V += det / 6.0;
+        for (int d = 0; d < 3; ++d) mom[d] += det / 6.0 * 0.25 * (X[0][d] + X[1][d] + X[2][d] + X[3][d]);
+        for (int i = 0; i < nv1; ++i)
+          for (int j = 0; j < nv1; ++j)
+            for (int k = 0; k < nv1; ++k, ++q) {
+              const double a = j2x[i], b = j1x[j], cc = gvx[k];
+              for (int d = 0; d < 3; ++d) c->vq_pts[(size_t)q * 3 + d] = X[0][d] + a * (e1[d] + b * (e2[d] + cc * e3[d]));
+              c->vq_w[q] = j2w[i] * j1w[j] * gvw[k] * det;
+            }
+      };
+      for (auto& [f, sd] : side[e]) {
+        const int64_t b0 = c->fv_ptr[f], m = c->fv_ptr[f + 1] - b0;
+        std::vector<int64_t> L(m);
+        for (int64_t k = 0; k < m; ++k) L[k] = c->fv[sd ? b0 + m - 1 - k : b0 + k];
+        if (D == 2) {
+          const double* X[3] = {apex, &c->verts[(size_t)L[0] * 2], &c->verts[(size_t)L[1] * 2]};
+          add_simplex(X);
+          continue;
+        }
+        int64_t s0 = 0;
+        for (int64_t k = 1; k < m; ++k)
+          if (L[k] < L[s0]) s0 = k;
+        for (int64_t k = 1; k + 1 < m; ++k) {  // fan triangles (y0, yk, yk+1) from the lowest vertex
+          const double* X[4] = {apex, &c->verts[(size_t)L[s0] * 3], &c->verts[(size_t)L[(s0 + k) % m] * 3],
+                                &c->verts[(size_t)L[(s0 + k + 1) % m] * 3]};
+          add_simplex(X);
+        }
+      }
+      c->vol[e] = V;
+      for (int d = 0; d < D; ++d) c->cen[(size_t)e * D + d] = mom[d] / V;
+      if (!(V > 0)) bad = true;
+    }
+  } else {
   c->nqv = D == 2 ? nv1 * nv1 : nv1 * nv1 * nv1;
+  c->vq_ptr.resize(nc + 1);
+  for (int64_t e = 0; e <= nc; ++e) c->vq_ptr[e] = e * c->nqv;
   c->vq_pts.assign((size_t)nc * c->nqv * D, 0.0);
   c->vq_w.assign((size_t)nc * c->nqv, 0.0);
-  bool bad = false;
 #pragma omp parallel for schedule(static) reduction(|| : bad)
   for (int64_t e = 0; e < nc; ++e) {
     double X[24];
@@ -321,12 +488,18 @@ hofv_status build_geometry(hofv_ctx* c) {
     }
     if (!(c->vol[e] > 0)) bad = true;
   }
+  }
   if (bad) return fail(c, HOFV_EINVAL, "a cell has non-positive volume (check vertex order)");
 
   // faces
   const int64_t nf = (int64_t)c->faces.size();
   const bool fan = D == 3 && !simplex && c->prm.face_rule == 1;
   c->nq = D == 2 ? ng : (fan ? 2 * ng * ng : ng * ng);
+  if (c->poly && D == 3) {  // polygons: the fan's triangles, padded to the largest count
+    int64_t mmax = 3;
+    for (int64_t f = 0; f < nf; ++f) mmax = std::max<int64_t>(mmax, c->fv_ptr[f + 1] - c->fv_ptr[f]);
+    c->nq = (int)((mmax - 2) * ng * ng);
+  }
   const int nq = c->nq;
   c->f_centre.assign((size_t)nf * D, 0.0);
   c->f_normal.assign((size_t)nf * D, 0.0);
@@ -338,7 +511,55 @@ hofv_status build_geometry(hofv_ctx* c) {
     const hofv_ctx::Face& F = c->faces[f];
     double* qp = &c->f_qp[(size_t)f * nq * D];
     double* qw = &c->f_qw[(size_t)f * nq];
-    if (D == 2) {
+    if (c->poly && D == 3) {
+      // polygon of m vertices: vector area 1/2 sum x_k x x_{k+1} gives the
+      // normal; a fan from the lowest vertex gives m - 2 triangles, each with
+      // the triangle rule and its share A_t / sum A of the weight; Gamma_f is
+      // the sum of the triangle areas; unused points sit at the centre with
+      // zero weight
+      const int64_t b0 = c->fv_ptr[f], m = c->fv_ptr[f + 1] - b0;
+      double Sv[3] = {0, 0, 0};
+      for (int64_t k = 0; k < m; ++k) {
+        double cr[3];
+        cross3(&c->verts[(size_t)c->fv[b0 + k] * 3], &c->verts[(size_t)c->fv[b0 + (k + 1) % m] * 3], cr);
+        for (int d = 0; d < 3; ++d) Sv[d] += 0.5 * cr[d];
+      }
+      const double Sn = std::sqrt(Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2]);
+      for (int d = 0; d < 3; ++d) c->f_normal[3 * f + d] = Sv[d] / Sn;
+      int64_t s0 = 0;
+      for (int64_t k = 1; k < m; ++k)
+        if (c->fv[b0 + k] < c->fv[b0 + s0]) s0 = k;
+      auto vx = [&](int64_t k) { return &c->verts[(size_t)c->fv[b0 + (s0 + k) % m] * 3]; };
+      std::vector<double> At(m - 2);
+      double Asum = 0;
+      for (int64_t t = 0; t + 2 < m; ++t) {
+        double u1[3], u2[3], cr[3];
+        for (int d = 0; d < 3; ++d) {
+          u1[d] = vx(t + 1)[d] - vx(0)[d];
+          u2[d] = vx(t + 2)[d] - vx(0)[d];
+        }
+        cross3(u1, u2, cr);
+        At[t] = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        Asum += At[t];
+      }
+      c->f_area[f] = Asum;
+      int q = 0;
+      for (int64_t t = 0; t + 2 < m; ++t)
+        for (int i = 0; i < ng; ++i)
+          for (int j = 0; j < ng; ++j, ++q) {
+            const double a = t1x[i], b = gfx[j];
+            const double *x0 = vx(0), *x1 = vx(t + 1), *x2 = vx(t + 2);
+            for (int d = 0; d < 3; ++d) qp[3 * q + d] = x0[d] + a * (x1[d] - x0[d] + b * (x2[d] - x1[d]));
+            qw[q] = 2.0 * t1w[i] * gfw[j] * At[t] / Asum;
+          }
+      double xc[3] = {0, 0, 0};
+      for (int k = 0; k < q; ++k)
+        for (int d = 0; d < 3; ++d) xc[d] += qw[k] * qp[3 * k + d];
+      for (; q < nq; ++q) {
+        for (int d = 0; d < 3; ++d) qp[3 * q + d] = xc[d];
+        qw[q] = 0.0;
+      }
+    } else if (D == 2) {
       const double* a = &c->verts[(size_t)F.v[0] * 2];
       const double* b = &c->verts[(size_t)F.v[1] * 2];
       double ex = b[0] - a[0], ey = b[1] - a[1];

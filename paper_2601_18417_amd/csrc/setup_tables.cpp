@@ -25,7 +25,11 @@ namespace hofv {
 
 hofv_status build_tables(hofv_ctx* c) {
   auto t0 = std::chrono::steady_clock::now();
-  const int D = c->D, p = c->prm.order_p, NS = 2 * D;
+  const int D = c->D, p = c->prm.order_p, NS = c->NS;
+  // u* extrapolation items: cells (NSI = NS face slots each), or, when a cell
+  // has more faces than a hexahedron, one item per cell face that needs u*
+  const bool hf = NS > 2 * D;
+  const int NSI = hf ? 1 : NS;
   const int64_t nc = c->nc;
   const int nq = c->nq;
   const bool nh = c->prm.material == HOFV_NEO_HOOKEAN;
@@ -58,13 +62,8 @@ hofv_status build_tables(hofv_ctx* c) {
   };
   curve(0, c->n_internal);
   curve(c->n_internal, (int64_t)kf.size());
-  // extrapolation items: cells along a Morton curve of the centroids
+  // cells along a Morton curve of the centroids: the order of the extrapolation items
   const std::vector<int64_t> corder = morton_order(c->cen.data(), D, nc);
-  std::vector<int32_t> cpos(nc), ccell(nc);
-  for (int64_t r = 0; r < nc; ++r) {
-    cpos[corder[r]] = (int32_t)r;
-    ccell[r] = (int32_t)corder[r];
-  }
   const int64_t nf = (int64_t)kf.size(), nfi = c->n_internal, nfd = nf - nfi;
   std::vector<int64_t> kf_of_face(c->faces.size(), -1);
   std::vector<int64_t> bidx_of_face(c->faces.size(), -1);
@@ -84,11 +83,8 @@ hofv_status build_tables(hofv_ctx* c) {
   for (int64_t i = 0; i < nf; ++i) std::sort(&fst[(size_t)i * S], &fst[(size_t)i * S] + S);
 #pragma omp parallel for schedule(static)
   for (int64_t P = 0; P < nc; ++P) std::sort(&cst[(size_t)P * S], &cst[(size_t)P * S] + S);
-  std::vector<int32_t> cst_item((size_t)nc * S);  // by extrapolation item
-  for (int64_t r = 0; r < nc; ++r) std::copy_n(&cst[(size_t)corder[r] * S], S, &cst_item[(size_t)r * S]);
   const StencilBlocks fblk = make_blocks(fst.data(), nf, S, nc, kBlockItems, kLdsFaceCells);
-  const StencilBlocks cblk = make_blocks(cst_item.data(), nc, S, nc, kBlockItems, kLdsCellCells);
-  if (fblk.max_cells > kLdsFaceCells || cblk.max_cells > kLdsCellCells)
+  if (fblk.max_cells > kLdsFaceCells)
     return fail(c, HOFV_EINVAL, "stencil union of one item exceeds the LDS staging capacity");
 
   // face coefficients
@@ -122,6 +118,7 @@ hofv_status build_tables(hofv_ctx* c) {
     double out[3 * 256];
     double Gg[3][3] = {{0}};  // sum_q alpha_q ghost gradient (LE) at load 1
     for (int q = 0; q < nq; ++q) {
+      if (qw[q] == 0.0) continue;  // a padding point of a face with fewer points
       double cond, h;
       bool ok = ls_functionals(D, p, kshape, &c->f_qp[((size_t)f * nq + q) * D], X, S, disp ? gw : 0.0,
                                kTargetGradient, D, targets, out, &cond, &h);
@@ -218,6 +215,7 @@ hofv_status build_tables(hofv_ctx* c) {
     const double targets[3] = {0, 1, 2};
     double out[3 * 512];
     for (int q = 0; q < nq; ++q) {
+      if (c->f_qw[(size_t)f * nq + q] == 0.0) continue;  // padding point
       double cond, h;
       const bool ok = ls_functionals(D, p, kshape, &c->f_qp[((size_t)f * nq + q) * D], X, 2 * Sh, 0.0,
                                      kTargetGradient, D, targets, out, &cond, &h);
@@ -260,21 +258,45 @@ hofv_status build_tables(hofv_ctx* c) {
   for (int64_t i = 0; i < nfs; ++i)
     for (int N = 0; N < Sh; ++N) sst_t[(size_t)N * nfs + i] = sst[i * Sh + N];
 
-  // cell extrapolation rows and face slot codes
-  std::vector<double> cext((size_t)S * NS * nc, 0.0);
+  // face slot codes, extrapolation items and their rows
   std::vector<int32_t> cfaces((size_t)NS * nc, kNoFace);
   for (int64_t i = 0; i < nf; ++i) {
     cfaces[(size_t)(fslots[i] & 0xff) * nc + fown[i]] = (int32_t)i;
     if (i < nfi) cfaces[(size_t)(fslots[i] >> 8) * nc + fnei[i]] = ~(int32_t)i;
   }
   for (int64_t i = 0; i < nfs; ++i) cfaces[(size_t)sslot[i] * nc + sown[i]] = (int32_t)(nf + i);
+  // items: cells in Morton order, or (hf) the slots with internal or
+  // displacement faces of the cells in that order
+  std::vector<int32_t> ccell, cpos(nc, -1), item_of((size_t)NS * nc, -1);
+  for (int64_t r = 0; r < nc; ++r) {
+    const int64_t P = corder[r];
+    cpos[P] = (int32_t)ccell.size();
+    if (!hf) {
+      ccell.push_back((int32_t)P);
+      continue;
+    }
+    for (int s = 0; s < NS; ++s) {
+      const int32_t code = cfaces[(size_t)s * nc + P];
+      if (code == kNoFace || code >= nf) continue;
+      item_of[(size_t)s * nc + P] = (int32_t)ccell.size();
+      ccell.push_back((int32_t)P);
+    }
+  }
+  const int64_t ni = (int64_t)ccell.size();
+  std::vector<int32_t> cst_item((size_t)ni * S);  // stencils by extrapolation item
+  for (int64_t r = 0; r < ni; ++r) std::copy_n(&cst[(size_t)ccell[r] * S], S, &cst_item[(size_t)r * S]);
+  const StencilBlocks cblk = make_blocks(cst_item.data(), ni, S, nc, kBlockItems, kLdsCellCells);
+  if (cblk.max_cells > kLdsCellCells)
+    return fail(c, HOFV_EINVAL, "stencil union of one item exceeds the LDS staging capacity");
+  std::vector<double> cext((size_t)S * NSI * ni, 0.0);
 #pragma omp parallel for schedule(dynamic, 64) reduction(max : max_cond) reduction(|| : singular)
   for (int64_t P = 0; P < nc; ++P) {
     double X[256 * 3];
     for (int k = 0; k < S; ++k)
       for (int d = 0; d < D; ++d) X[k * D + d] = c->cen[(size_t)cst[P * S + k] * D + d];
-    double dvec[6 * 3];
-    int slots[6], nt = 0;
+    std::vector<double> dvec((size_t)NS * 3);
+    std::vector<int> slots(NS);
+    int nt = 0;
     for (int s = 0; s < NS; ++s) {
       int32_t code = cfaces[(size_t)s * nc + P];
       if (code == kNoFace || code >= nf) continue;  // traction and symmetry faces need no u*
@@ -284,13 +306,17 @@ hofv_status build_tables(hofv_ctx* c) {
       slots[nt++] = s;
     }
     if (nt == 0) continue;
-    double out[6 * 256], cond, h;
-    bool ok = ls_functionals(D, p, kshape, &c->cen[(size_t)P * D], X, S, 0.0, kTargetExtrap, nt, dvec, out,
-                             &cond, &h);
+    std::vector<double> out((size_t)nt * S);
+    double cond, h;
+    bool ok = ls_functionals(D, p, kshape, &c->cen[(size_t)P * D], X, S, 0.0, kTargetExtrap, nt, dvec.data(),
+                             out.data(), &cond, &h);
     if (!ok) singular = true;
     max_cond = std::max(max_cond, cond);
     for (int r = 0; r < nt; ++r)
-      for (int k = 0; k < S; ++k) cext[cblk.at(cpos[P], k, slots[r], NS, S)] = out[r * S + k];
+      for (int k = 0; k < S; ++k) {
+        if (hf) cext[cblk.at(item_of[(size_t)slots[r] * nc + P], k, 0, 1, S)] = out[r * S + k];
+        else cext[cblk.at(cpos[P], k, slots[r], NS, S)] = out[r * S + k];
+      }
   }
   if (singular) return fail(c, HOFV_ESINGULAR, "rank-deficient least-squares stencil at a cell centroid");
 
@@ -300,8 +326,7 @@ hofv_status build_tables(hofv_ctx* c) {
     for (int64_t P = 0; P < nc; ++P)
       for (int j = 0; j < D; ++j) {
         double s = 0;
-        for (int q = 0; q < c->nqv; ++q)
-          s += c->vq_w[(size_t)P * c->nqv + q] * c->fb[((size_t)P * c->nqv + q) * D + j];
+        for (int64_t q = c->vq_ptr[P]; q < c->vq_ptr[P + 1]; ++q) s += c->vq_w[q] * c->fb[(size_t)q * D + j];
         src[(size_t)j * nc + P] += s;
       }
   }
@@ -390,11 +415,17 @@ hofv_status build_tables(hofv_ctx* c) {
           for (int d = 0; d < 4; ++d) gwb[((size_t)s * nc + P) * 4 + d] = gwf[((size_t)s2 * nc + N) * 4 + d];
     }
 
-  // the stabilisation term reads u* by extrapolation item
-  std::vector<int32_t> fown_item(nf), fnei_item(nf);
+  // the stabilisation term reads u* by extrapolation item (and slot within it)
+  std::vector<int32_t> fown_item(nf), fnei_item(nf), fslots_item(fslots);
   for (int64_t i = 0; i < nf; ++i) {
-    fown_item[i] = cpos[fown[i]];
-    fnei_item[i] = fnei[i] >= 0 ? cpos[fnei[i]] : -1;
+    if (hf) {
+      fown_item[i] = item_of[(size_t)(fslots[i] & 0xff) * nc + fown[i]];
+      fnei_item[i] = fnei[i] >= 0 ? item_of[(size_t)(fslots[i] >> 8) * nc + fnei[i]] : -1;
+      fslots_item[i] = 0;
+    } else {
+      fown_item[i] = cpos[fown[i]];
+      fnei_item[i] = fnei[i] >= 0 ? cpos[fnei[i]] : -1;
+    }
   }
   for (int k = 0; k < ncol; ++k) c->dev.colour_start[k + 1] += c->dev.colour_start[k];
   c->dev.n_colours = ncol;
@@ -446,11 +477,11 @@ hofv_status build_tables(hofv_ctx* c) {
       if (!v.empty()) std::memcpy(h.bytes.data(), v.data(), h.bytes.size());
     };
     // global stencils, k-major, for inspection
-    std::vector<int32_t> fst_k((size_t)S * nf), cst_k((size_t)S * nc);
+    std::vector<int32_t> fst_k((size_t)S * nf), cst_k((size_t)S * ni);
     for (int64_t i = 0; i < nf; ++i)
       for (int k = 0; k < S; ++k) fst_k[(size_t)k * nf + i] = fst[(size_t)i * S + k];
-    for (int64_t r = 0; r < nc; ++r)
-      for (int k = 0; k < S; ++k) cst_k[(size_t)k * nc + r] = cst_item[(size_t)r * S + k];
+    for (int64_t r = 0; r < ni; ++r)
+      for (int k = 0; k < S; ++k) cst_k[(size_t)k * ni + r] = cst_item[(size_t)r * S + k];
     keep("face_stencil", fst_k);
     keep("cell_stencil", cst_k);
     keep("cell_order", ccell);
@@ -464,7 +495,7 @@ hofv_status build_tables(hofv_ctx* c) {
     keep("cell_ucell", cblk.cells);
     keep("cell_local", cblk.unblocked(cblk.local, 1, S));
     keep("face_coef", fblk.unblocked(fcoef, ncoef, S));
-    keep("cell_extrap", cblk.unblocked(cext, NS, S));
+    keep("cell_extrap", cblk.unblocked(cext, NSI, S));
     keep("face_own", fown);
     keep("face_nei", fnei);
     keep("face_area_vec", fsv);
@@ -494,8 +525,8 @@ hofv_status build_tables(hofv_ctx* c) {
   const double face_b = (double)nf * S * (ncoef * 8.0 + 2.0) + (double)nf * (4 * 3 + 8 + 8.0 * (fold ? D : nq * D)) +
                         (nh ? (double)nq * D * D * 8 * nfd : 0.0) + 4.0 * fblk.cells.size() + ub +
                         2.0 * D * 8 * nf + (double)D * 8 * nf;
-  const double ext_b = (double)nc * S * (NS * 8.0 + 2.0) + 4.0 * cblk.cells.size() + 4.0 * nc + ub +
-                       (double)NS * D * 8 * nc;
+  const double ext_b = (double)ni * S * (NSI * 8.0 + 2.0) + 4.0 * cblk.cells.size() + 4.0 * ni + ub +
+                       (double)NSI * D * 8 * ni;
   const double sum_b = (double)nc * (NS * 4.0 + 2 * D * 8.0) + 2.0 * D * 8 * nf;
   c->kernel_bytes[nh ? "k_face_nh" : (fold ? "k_face_le" : "k_face_q")] = face_b;
   c->kernel_bytes["k_extrap"] = ext_b;
@@ -535,7 +566,7 @@ hofv_status build_tables(hofv_ctx* c) {
   UP(t.f_coef, fcoef);
   UP(t.f_own, fown_item);
   UP(t.f_nei, fnei_item);
-  UP(t.f_slots, fslots);
+  UP(t.f_slots, fslots_item);
   UP(t.f_area_vec, fsv);
   UP(t.f_stab, fstab);
   if (nh) UP(t.f_ghost, fghost);
@@ -565,7 +596,10 @@ hofv_status build_tables(hofv_ctx* c) {
     if ((st = dev_alloc(c, &t.sym_flux, (size_t)D * nfs))) return st;
   }
 #undef UP
-  if ((st = dev_alloc(c, &t.ustar, (size_t)NS * D * nc))) return st;
+  t.nsi = NSI;
+  t.ns = NS;
+  t.n_items = ni;
+  if ((st = dev_alloc(c, &t.ustar, (size_t)NSI * D * ni))) return st;
   if ((st = dev_alloc(c, &t.flux, (size_t)D * nf))) return st;
   if ((st = dev_alloc(c, &t.w, (size_t)(D == 3 ? 4 : 2) * nc))) return st;  // padded gather copy
   if ((st = dev_alloc(c, &t.scratch, 16384))) return st;  // >= 2 x 512 partials of the J.v norms

@@ -1,0 +1,222 @@
+"""GPU parity on polygonal and polyhedral face-list meshes (Sec. 3.1's
+arbitrary cells): the doubled structured grid with every other 2^dim block
+merged into one 8-edge (2D) or 24-face (3D) cell with hanging vertices.  Such
+cells have more than 2 dim faces, so every face gets its own extrapolation
+item; 3D faces are fan-triangulated and their quadrature is padded to the
+largest face.  Residual and J.v against the oracle at p = 1-3 (folded and
+per-point quadrature), the zero residual of degree-p fields, the neo-Hookean
+law (2 and 8 points per face), the compact preconditioner and V-cycle, Newton,
+and convergence under refinement."""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import jacobian as ojac
+from oracle import newton as onw
+from oracle import precond as opc
+from oracle import residual as ores
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _api():
+    from paper_2601_18417_amd import api
+    return api
+
+
+def to_dev(a):
+    return torch.tensor(np.ascontiguousarray(a.T), device=DEV, dtype=torch.float64)
+
+
+def to_host(t):
+    return t.cpu().numpy().T
+
+
+def _m2(seed=2):
+    return w.split_block_mesh((6, 5), perturb=0.2, seed=seed)
+
+
+def _m3(mode="tensor"):
+    return w.split_block_mesh((4, 4, 4), perturb=0.15, seed=4, mode=mode)
+
+
+CASES = {
+    "split2d_p1": lambda: w.poly_patch(_m2(), 1, 1, seed=4),
+    "split2d_p2": lambda: w.poly_patch(_m2(), 2, 2, seed=4),
+    "split2d_p3": lambda: w.poly_patch(_m2(), 3, 3, seed=4),
+    "split2d_p2_traction": lambda: w.poly_patch(_m2(3), 2, 2, seed=5,
+                                                traction_faces=lambda xc, n: xc[:, 1] > 1 - 1e-9),
+    "split3d_p1": lambda: w.poly_patch(_m3(), 1, 1, seed=4),
+    "split3d_p2": lambda: w.poly_patch(_m3(), 2, 2, seed=4),
+    "split3d_p3": lambda: w.poly_patch(_m3(), 3, 3, seed=4),
+    # randomly perturbed vertices: warped quadrilateral faces
+    "split3d_warped_p2": lambda: w.poly_patch(_m3("random"), 2, 2, seed=4),
+}
+# planar faces: a degree-p field is reproduced exactly, so R vanishes
+EXACT = {"split2d_p1", "split2d_p2", "split2d_p3", "split2d_p2_traction", "split3d_p1", "split3d_p2", "split3d_p3"}
+
+
+def _flux_scale(disc, u):
+    Ff, Fd = ores.face_fluxes(disc, u)
+    s = np.zeros((disc.n_cells, disc.dim))
+    np.add.at(s, disc.f_own, np.abs(Ff))
+    np.add.at(s, disc.f_nei, np.abs(Ff))
+    np.add.at(s, disc.d_own, np.abs(Fd))
+    return s + np.abs(disc.b_body + disc.b_trac)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("fold", [True, False])
+def test_residual_parity_on_split_meshes(name, fold):
+    prob = CASES[name]()
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob, fold_quadrature=fold)
+    n, D = disc.n_cells, disc.dim
+    fc = prob.mesh.face_cells
+    assert np.bincount(fc[fc >= 0], minlength=n).max() > 2 * D  # merged cells present
+    for seed in (11, 12):
+        u = w.random_state(n, D, seed=seed)
+        R = torch.empty((D, n), device=DEV, dtype=torch.float64)
+        ctx.residual(to_dev(u), R)
+        torch.cuda.synchronize()
+        Ro = ores.residual(disc, u)
+        assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro), (name, seed)
+    u = prob.loads.exact.value(disc.cen)
+    R = torch.empty((D, n), device=DEV, dtype=torch.float64)
+    ctx.residual(to_dev(u), R)
+    torch.cuda.synchronize()
+    scale = _flux_scale(disc, u)
+    Rg = to_host(R)
+    assert np.all(np.abs(Rg - ores.residual(disc, u)) <= 1e-10 * scale)
+    if name in EXACT:
+        assert np.all(np.abs(Rg) <= 1e-10 * scale)
+
+
+JV_CASES = {
+    "split2d_mms_p3": lambda: w.split_mms((6, 5), 3, perturb=0.2, seed=2),
+    "split3d_mms_p1": lambda: w.split_mms((4, 4, 4), 1, perturb=0.15, seed=4, mode="tensor"),
+    "split3d_mms_p2": lambda: w.split_mms((4, 4, 4), 2, perturb=0.15, seed=4, mode="tensor"),
+    "split3d_mms_p3": lambda: w.split_mms((4, 4, 4), 3, perturb=0.15, seed=4, mode="tensor"),
+    "split3d_mms_warped_p2": lambda: w.split_mms((4, 4, 4), 2, perturb=0.15, seed=4, mode="random"),
+    # degree-3 field of unit size: boundary constants make |R| ~ 30
+    "split3d_p3": CASES["split3d_p3"],
+}
+
+
+@pytest.mark.parametrize("name", list(JV_CASES))
+def test_jvp_parity_on_split_meshes(name):
+    """J.v to 1e-6 relative, plus the rounding floor of any FP64 difference
+    quotient: each side's two residuals are exact to a few ulps of the flux
+    sums S_P they add up, and the difference is divided by eps (8 ulps of |S|
+    over eps: 1e-8 of |J.v| on the manufactured trig problems, 6e-6 with the
+    unit-size degree-3 field)."""
+    prob = JV_CASES[name]()
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n, D = disc.n_cells, disc.dim
+    u = w.random_state(n, D, seed=1)
+    v = w.random_state(n, D, seed=2, scale=1.0)
+    ud, vd = to_dev(u), to_dev(v)
+    R = torch.empty_like(ud)
+    Jv = torch.empty_like(ud)
+    ctx.residual(ud, R)
+    eps = ojac.default_eps(u, v)
+    ctx.jvp(ud, R, vd, Jv, eps=eps)
+    torch.cuda.synchronize()
+    Jo = ojac.jvp(disc, u, v, eps=eps)
+    floor = 8 * 2.0 ** -52 * np.linalg.norm(_flux_scale(disc, u)) / eps
+    err = np.linalg.norm(to_host(Jv) - Jo)
+    print(f"{name}: |dJv|/|Jv| {err / np.linalg.norm(Jo):.2e}, floor {floor / np.linalg.norm(Jo):.2e}")
+    assert err <= 1e-6 * np.linalg.norm(Jo) + floor
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_neo_hookean_parity_on_a_split_beam(p):
+    """A clamped neo-Hookean beam on the split mesh of a 10 x 1 x 1 bar, in a
+    strained state: per-point gradients at 2 (p = 1) and 8 (p = 2) points per
+    quadrilateral face, R at two load scales and J.v."""
+    prob = w.cantilever(shape=(16, 4, 4), p=p, n_plus=20, tip_traction=0.05)
+    prob.mesh = w.split_block_mesh((8, 2, 2), lengths=(10.0, 1.0, 1.0), perturb=0.1, seed=2)
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    u = w.random_state(n, 3, seed=5, scale=0.05)
+    ud = to_dev(u)
+    R = torch.empty_like(ud)
+    for load in (1.0, 0.4):
+        ctx.set_load_scale(load)
+        ctx.residual(ud, R)
+        torch.cuda.synchronize()
+        Ro = ores.residual(disc, u, load)
+        assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro), load
+    v = w.random_state(n, 3, seed=6, scale=1.0)
+    eps = ojac.default_eps(u, v)
+    Jv = torch.empty_like(ud)
+    ctx.jvp(ud, R, to_dev(v), Jv, eps=eps)
+    torch.cuda.synchronize()
+    Jo = ojac.jvp(disc, u, v, Ro, eps, load=0.4)
+    assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
+
+
+@pytest.mark.parametrize("mk", [lambda: w.poly_patch(w.split_block_mesh((12, 12), perturb=0.2, seed=2), 2, 2, seed=4),
+                                lambda: w.poly_patch(_m3(), 2, 2, seed=4)])
+def test_preconditioners_on_split_meshes(mk):
+    """Compact-Jacobian sweeps (up to 24 neighbours per merged cell) and the
+    two-level V-cycle against the oracle's, FP64 and FP32."""
+    prob = mk()
+    disc = ores.build(prob)
+    A = opc.assemble(disc)
+    col = opc.greedy_colours(A)
+    r = w.random_state(disc.n_cells, disc.dim, seed=3, scale=1.0)
+    ctx = _api().context_for(prob, precond_levels=8)
+    z = torch.empty((disc.dim, disc.n_cells), device=DEV, dtype=torch.float64)
+    for mg in (False, True):
+        ctx.set_multigrid(mg)
+        ctx.precond_apply(to_dev(r), z, n_sweeps=2)
+        torch.cuda.synchronize()
+        if mg:
+            lev = opc.hierarchy(A)
+            z64, z32 = opc.vcycle(lev, r, 2), opc.vcycle(lev, r, 2, dtype=np.float32)
+            tol = 1e-4
+        else:
+            z64, z32 = opc.sgs(A, col, r, 2), opc.sgs(A, col, r, 2, dtype=np.float32)
+            tol = 1e-5
+        zg = to_host(z)
+        assert np.abs(zg - z64).max() <= tol * np.abs(z64).max(), mg
+        assert np.abs(zg - z32).max() <= tol * np.abs(z64).max(), mg
+    assert ctx.report["n_colours"] == col.max() + 1
+
+
+@pytest.mark.parametrize("mk", [lambda: w.split_mms((6, 5), 2, perturb=0.2, seed=2),
+                                lambda: w.split_mms((3, 3, 3), 1, perturb=0.15, seed=4, mode="tensor")])
+def test_newton_on_split_meshes_matches_oracle(mk):
+    prob = mk()
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n, D = disc.n_cells, disc.dim
+    u = torch.zeros((D, n), device=DEV, dtype=torch.float64)
+    st = ctx.newton_solve(u, tol=1e-10, eta=1e-8, restart=60)
+    assert st["converged"]
+    uo, _ = onw.newton(disc, np.zeros((n, D)), tol=1e-10, eta=1e-8, m=60)
+    assert np.linalg.norm(to_host(u) - uo) <= 1e-7 * np.linalg.norm(uo)
+
+
+@pytest.mark.parametrize("p,min_slope", [(1, 2.0), (2, 1.5), (3, 3.5)])
+def test_mms_error_falls_on_refined_split_meshes(p, min_slope):
+    """Unperturbed split grids of 4^2 and 8^2 blocks: the centroid RMS error of
+    the converged solution falls at the rate the oracle's solutions show
+    (2.26, 1.71 and 4.00 at p = 1, 2, 3)."""
+    errs = []
+    for cs in ((4, 4), (8, 8)):
+        prob = w.split_mms(cs, p, perturb=0.0, mode="tensor")
+        ctx = _api().context_for(prob)
+        u = torch.zeros((2, prob.mesh.n_cells), device=DEV, dtype=torch.float64)
+        st = ctx.newton_solve(u, tol=1e-10, eta=1e-8, restart=60)
+        assert st["converged"]
+        ue = prob.loads.exact.value(ctx.cell_centroids())
+        errs.append(np.sqrt(np.mean(np.sum((to_host(u) - ue) ** 2, axis=1))))
+    slope = np.log2(errs[0] / errs[1])
+    print(f"split p={p} errors {errs} slope {slope:.2f}")
+    assert slope >= min_slope

@@ -33,7 +33,35 @@ CASES = [lambda: w.square_mms(8, 2, perturb=0.2), lambda: w.square_mms(7, 3),
                               traction_faces=lambda xc, n: xc[:, 1] > 1 - 1e-9),
          lambda: _fan(w.cube_mms(6, 3, perturb=0.2)),
          lambda: w.tri_mms(6, 3, perturb=0.2),
-         lambda: w.tet_mms(3, 2, perturb=0.2), lambda: w.tet_mms(4, 3, perturb=0.2, seed=1)]
+         lambda: w.tet_mms(3, 2, perturb=0.2), lambda: w.tet_mms(4, 3, perturb=0.2, seed=1),
+         # face-list meshes with 8-edge / 24-face merged cells (one extrapolation item per face)
+         lambda: w.poly_patch(w.split_block_mesh((4, 5), perturb=0.2, seed=2), 3, 3, seed=1,
+                              traction_faces=lambda xc, n: xc[:, 1] > 1 - 1e-9),
+         lambda: w.poly_patch(w.split_block_mesh((3, 3, 3), perturb=0.15, seed=4, mode="tensor"), 2, 2, seed=3)]
+
+
+def _items(ctx, n):
+    """Extrapolation items of the library's u* tables: (NS, NSI, item of
+    (cell, slot)).  Items are cells with NS slots each, or, when a cell has
+    more than 2 dim faces, one item per slot with an internal or displacement
+    face (a cell's items consecutive, in slot order)."""
+    order = ctx.host_table("cell_order")
+    cf = ctx.host_table("cell_faces")
+    NS = cf.size // n
+    cf = cf.reshape(NS, n)
+    nf = ctx.host_table("face_own").size
+    if order.size == n:
+        item = np.argsort(order)
+        return NS, NS, lambda P, s: (item[P], s)
+    first = {}
+    for r in range(order.size - 1, -1, -1):
+        first[order[r]] = r
+    where = {}
+    for P, r0 in first.items():
+        used = [s for s in range(NS) if cf[s, P] != np.iinfo(np.int32).min and cf[s, P] < nf]
+        for k, s in enumerate(used):
+            where[(P, s)] = (r0 + k, 0)
+    return NS, 1, lambda P, s: where[(P, s)]
 
 
 @pytest.mark.parametrize("mk", CASES)
@@ -61,8 +89,9 @@ def test_stencils_and_face_coefficients_match_oracle(mk):
     oc = np.take_along_axis(oc, order[:, None, :], 2)
     assert np.abs(coef - oc).max() <= 1e-11 * np.abs(oc).max()
     order = ctx.host_table("cell_order")  # extrapolation item -> cell
-    assert np.array_equal(np.sort(order), np.arange(disc.n_cells))
-    cst = ctx.host_table("cell_stencil").reshape(S, disc.n_cells).T
+    assert np.array_equal(np.unique(order), np.arange(disc.n_cells))
+    assert order.size == disc.n_cells or ctx.host_table("cell_faces").size > 2 * D * disc.n_cells
+    cst = ctx.host_table("cell_stencil").reshape(S, order.size).T
     assert np.array_equal(cst, np.sort(disc.c_st[order], axis=1))
 
 
@@ -75,21 +104,21 @@ def test_extrapolation_rows_match_oracle(mk):
     ctx = api.context_for(prob, host_only=True)
     S, D, nf, fst = _tables(ctx, prob)
     n = disc.n_cells
-    NS = 2 * D
-    ext = ctx.host_table("cell_extrap").reshape(S, NS, n)  # by extrapolation item
-    cst = ctx.host_table("cell_stencil").reshape(S, n)
-    item = np.argsort(ctx.host_table("cell_order"))  # cell -> extrapolation item
+    NS, NSI, where = _items(ctx, n)
+    ni = ctx.host_table("cell_order").size
+    ext = ctx.host_table("cell_extrap").reshape(S, NSI, ni)  # by extrapolation item
+    cst = ctx.host_table("cell_stencil").reshape(S, ni)
     cf = ctx.host_table("cell_faces").reshape(NS, n)
     fc = ctx.host_table("face_centre").reshape(nf, D)
     u = w.random_state(n, D, seed=1, scale=1.0)
-    for P in range(0, n, 7):
-        r = item[P]
+    for P in range(0, n, 7 if n > 40 else 1):
         for s in range(NS):
             code = cf[s, P]
-            if code == np.iinfo(np.int32).min:
+            if code == np.iinfo(np.int32).min or code >= nf:
                 continue
             f = code if code >= 0 else ~code
-            lib = np.einsum("k,kj->j", ext[:, s, r], u[cst[:, r]])
+            r, si = where(P, s)
+            lib = np.einsum("k,kj->j", ext[:, si, r], u[cst[:, r]])
             d = fc[f] - disc.cen[P]
             ref = ores.extrapolate(disc, u, np.array([P]), d[None])[0] - u[P]
             assert np.allclose(lib, ref, rtol=1e-10, atol=1e-10 * np.abs(u).max()), (P, s)
@@ -97,7 +126,9 @@ def test_extrapolation_rows_match_oracle(mk):
 
 @pytest.mark.parametrize("mesh", [lambda: w.box_mesh((6, 5, 5), perturb=0.2, seed=3),
                                   lambda: w.tet_mesh((4, 4, 4), perturb=0.2, seed=3),
-                                  lambda: w.tri_mesh((8, 7), perturb=0.2, seed=3)])
+                                  lambda: w.tri_mesh((8, 7), perturb=0.2, seed=3),
+                                  lambda: w.split_block_mesh((4, 4), perturb=0.2, seed=3),
+                                  lambda: w.split_block_mesh((3, 2, 3), perturb=0.15, seed=3)])
 def test_sources_match_oracle_plus_boundary_constants(mesh):
     """Cell sources = body force + traction faces + the u_b-dependent constants
     of displacement faces (ghost gradient term and u_b of the stabilisation),
@@ -191,7 +222,7 @@ def test_learned_graph_tables_match_oracle():
             assert np.allclose(lib[N][1], refb, rtol=1e-6, atol=1e-7)
 
 
-@pytest.mark.parametrize("mk", [CASES[0], CASES[2], lambda: w.cube_mms(12, 3, perturb=0.2, seed=5)])
+@pytest.mark.parametrize("mk", [CASES[0], CASES[2], CASES[-1], lambda: w.cube_mms(12, 3, perturb=0.2, seed=5)])
 def test_item_blocks_cover_stencils(mk):
     """Item blocks of the LDS-staged kernels: consecutive items, at most 256
     per block, a sorted union within the LDS capacity (1024 cells for face

@@ -21,7 +21,7 @@ import numpy as np
 
 from .fields import (Loads, cantilever_loads, lame_from_young, mms_2d_unit, mms_3d_trig, symmetric_poly_field,
                      mms_loads, random_poly_field)
-from .meshes import Mesh, box_mesh, tet_mesh, tri_mesh
+from .meshes import Mesh, box_mesh, split_block_mesh, tet_mesh, tri_mesh
 
 LINEAR_ELASTIC, NEO_HOOKEAN = 0, 1
 
@@ -110,6 +110,22 @@ def tet_mms(n: int = 16, p: int = 2, perturb: float = 0.2, seed: int = 0,
                    PAPER_N_PLUS[3][p] if n_plus is None else n_plus,
                    n_gauss or default_gauss(p), LINEAR_ELASTIC, mu, lam,
                    mms_loads(mms_3d_trig(), mu, lam), stencil_quantum=quantum_for(mesh))
+
+
+def split_mms(coarse, p: int = 2, perturb: float = 0.2, seed: int = 0, E: float = 1.0, nu: float = 0.3,
+              n_plus=None, n_gauss=None, mode: str = "random") -> Problem:
+    """The manufactured problem of square_mms (2D) or cube_mms (3D) on the
+    polygonal / polyhedral mesh of split_block_mesh(coarse): every other 2^dim
+    block of the doubled grid merged into one 8-edge or 24-face cell."""
+    shape = tuple(coarse)
+    mesh = split_block_mesh(shape, perturb=perturb, seed=seed, mode=mode)
+    D = len(shape)
+    mu, lam = lame_from_young(E, nu)
+    field = mms_2d_unit() if D == 2 else mms_3d_trig()
+    return Problem(f"split_mms_{'x'.join(map(str, shape))}_p{p}", mesh, p,
+                   PAPER_N_PLUS[D][p] if n_plus is None else n_plus,
+                   n_gauss or default_gauss(p), LINEAR_ELASTIC, mu, lam,
+                   mms_loads(field, mu, lam), stencil_quantum=quantum_for(mesh))
 
 
 def cantilever(shape=(200, 20, 20), p: int = 2, mu: float = 1.0, lam: float = 10.0,
