@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # passes (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, factors from a plain 512 MiB
 # elementwise copy), valid only for the kernel and table-layout sources whose
 # combined sha256 has this prefix.
-MEASURED_TRAFFIC = {"kernel": "k_face_le", "n": 64, "p": 3, "bytes": 1913328645.5,
-                    "kernels_sha256": "380c2a8dcb4100c1"}
+MEASURED_TRAFFIC = {"kernel": "k_face_le", "n": 64, "p": 3, "bytes": 1913809734.1,
+                    "kernels_sha256": "e6486c5aa4fbee7d"}
 TRAFFIC_SOURCES = ("kernels.hip", "common.h", "setup_blocks.cpp", "setup_tables.cpp")
 
 
@@ -166,10 +166,10 @@ def cpu_baseline(prob, n_sample: int, u, v, ctx, torch, label, seed: int = 0, cu
     return out
 
 
-C4_MODEL = os.path.join(ROOT, "paper_2601_18417_amd", "weights", "c4_sweeps.hofvnn")
-C4_TRAIN_CMD = ("python bench.py --study train --train-set c4 --mg-base 0 --train-seeds 0-49 --harvest-starts 2 "
+MIXED_MODEL = os.path.join(ROOT, "paper_2601_18417_amd", "weights", "mixed_sweeps.hofvnn")
+MIXED_TRAIN_CMD = ("python bench.py --study train --train-set mixed --mg-base 0 --train-seeds 0-49 --harvest-starts 2 "
                 "--harvest-length 9 --restart 300 --learned-epochs 30 --model paper_2601_18417_amd/weights/"
-                "c4_sweeps.hofvnn")
+                "mixed_sweeps.hofvnn")
 
 
 def big_leg(args, torch, api, w, dev):
@@ -257,7 +257,7 @@ def big_leg(args, torch, api, w, dev):
     # time to 1e-8 from u = 0: plain sweeps, then the learned correction
     res = {}
     model = api.Model(0)
-    model.load(args.c4_model)
+    model.load(args.learned_model)
     ctx.attach(model)
     z = torch.empty_like(u)
     ctx.precond_apply(v, z, learned=True)  # the network's workspace
@@ -273,8 +273,8 @@ def big_leg(args, torch, api, w, dev):
         log(f"128^3 {name} solve {st}")
     res["speedup"] = res["plain"]["seconds"] / res["learned"]["seconds"]
     res["krylov_ratio"] = res["learned"]["krylov_iters"] / max(res["plain"]["krylov_iters"], 1)
-    res["model"] = os.path.relpath(args.c4_model, ROOT)
-    res["training_command"] = C4_TRAIN_CMD
+    res["model"] = os.path.relpath(args.learned_model, ROOT)
+    res["training_command"] = MIXED_TRAIN_CMD
     res["training"] = ("2,000 pairs: 2D 32x32 p=2 squares and 60x6x6 p=2 neo-Hookean beams, perturbation seeds 0-49; "
                        "evaluated on an unseen seed")
     ctx.attach(None)
@@ -448,7 +448,7 @@ def study(args):
     if args.study == "train":
         t0 = time.perf_counter()
         data, keep = [], []
-        kinds = {"c4": ["square", "beam"], "cube": ["cube"], "cantilever": ["beam"]}[args.train_set]
+        kinds = {"mixed": ["square", "beam"], "cube": ["cube"], "cantilever": ["beam"]}[args.train_set]
         for seed in parse_seeds(args.train_seeds):
             for kind in kinds:
                 if kind == "beam":
@@ -457,7 +457,7 @@ def study(args):
                     # fraction of its length (the sweeps alone do not solve it: V-cycle)
                     nx = args.learned_size if args.train_set == "cantilever" else 60
                     shape, lengths = (nx, nx // 10, nx // 10), (0.05 * nx, 0.005 * nx, 0.005 * nx)
-                    tp = w.cantilever(shape=shape, p=2 if args.train_set == "c4" else args.p)
+                    tp = w.cantilever(shape=shape, p=2 if args.train_set == "mixed" else args.p)
                     tp.mesh = w.box_mesh(shape, lengths=lengths, perturb=0.1, seed=seed)
                     tp.loads = w.fields.cantilever_loads(lengths[0], (0.0, -2.18e-3, 0.0))
                     mg = True
@@ -487,7 +487,7 @@ def study(args):
         for ep, l in enumerate(hist):
             log(f"epoch {ep} loss {l:.4f}")
         model.save(args.model)
-        meshes = {"c4": "2D 32x32 p=2 perturbed squares and 60x6x6 p=2 perturbed neo-Hookean beams (the beams' "
+        meshes = {"mixed": "2D 32x32 p=2 perturbed squares and 60x6x6 p=2 perturbed neo-Hookean beams (the beams' "
                         "e solved with the V-cycle), network inputs from the "
                         + ("V-cycle" if args.mg_base else "sweeps"),
                   "cube": f"{args.learned_size}^3 p={args.p} perturbed cubes" + (" (V-cycle inputs)" if args.mg_base
@@ -561,12 +561,13 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cube",
-                    choices=["cube", "cantilever", "square", "column", "symmetric", "tets"],
+                    choices=["cube", "cantilever", "square", "column", "symmetric", "tets", "poly"],
                     help="cube: 3D LE manufactured solution on a perturbed n^3 mesh (default); cantilever: "
                          "3D neo-Hookean 200x20x20 beam, 10 load increments; square: 2D 32x32 LE, p=2; "
                          "column: the vibrating neo-Hookean column, BDF2 time steps; symmetric: a polynomial "
                          "field symmetric about x = 0 on a tensor-perturbed n^3 box whose x = 0 faces are "
-                         "symmetry planes")
+                         "symmetry planes; tets: the cube's hexahedra split into 6 tetrahedra; poly: the cube's "
+                         "problem on the n^3 grid with every other 2x2x2 block merged into one 24-face cell")
     ap.add_argument("--column-cells", default="50x5x5", help="cells of the column (length x width x depth)")
     ap.add_argument("--time-steps", type=int, default=100, help="BDF2 steps of the column (dt = 1 ms)")
     ap.add_argument("--n", type=int, default=64, help="cells per axis")
@@ -591,8 +592,8 @@ def main():
                          "--train-seeds (saved to --model), evaluate --model on one mesh, or time the "
                          "learned application alone (nn)")
     ap.add_argument("--train-seeds", default="0-49")
-    ap.add_argument("--train-set", choices=["c4", "cube", "cantilever"], default="cube",
-                    help="training meshes of --study train: c4 = 2D squares and neo-Hookean beams (the learned-"
+    ap.add_argument("--train-set", choices=["mixed", "cube", "cantilever"], default="cube",
+                    help="training meshes of --study train: mixed = 2D squares and neo-Hookean beams (the learned-"
                          "preconditioner configuration), cube = perturbed cubes of --learned-size, cantilever = beams")
     ap.add_argument("--mg-base", type=int, default=0,
                     help="1: the network corrects the V-cycle's output (training and evaluation contexts build the "
@@ -631,7 +632,7 @@ def main():
     ap.add_argument("--big-n", type=int, default=128)
     ap.add_argument("--big-seed", type=int, default=50, help="mesh seed of the 128^3 leg (unseen in training)")
     ap.add_argument("--big-solve", type=int, default=1, help="time-to-tolerance solves in the 128^3 leg")
-    ap.add_argument("--c4-model", default=C4_MODEL, help="weights of the learned correction for the 128^3 leg")
+    ap.add_argument("--learned-model", default=MIXED_MODEL, help="weights of the learned correction for the 128^3 leg")
     args = ap.parse_args()
     # solver settings per workload, where not given: the slender cantilever needs long
     # cycles, full Newton steps, the forcing term and the predictor (its sweeps-only
@@ -678,6 +679,8 @@ def main():
         prob = w.vibrating_column(tuple(int(x) for x in args.column_cells.split("x")), p=args.p)
     elif args.workload == "tets":
         prob = w.tet_mms(args.n, args.p, perturb=0.2, seed=0)
+    elif args.workload == "poly":
+        prob = w.split_mms((args.n // 2,) * 3, args.p, perturb=0.2, seed=0)
     elif args.workload == "symmetric":
         prob = w.poly_patch(w.box_mesh((args.n,) * 3, perturb=0.2, seed=0, mode="tensor"), args.p, args.p, seed=1,
                             symmetric=True)
@@ -856,10 +859,10 @@ def main():
                            cube=("cube", args.n, args.p) if args.workload == "cube" else None)
         log(f"cpu {cpu}")
 
-    big, c4 = None, None
+    big, learned_big = None, None
     if args.big and args.workload == "cube":
         r = big_leg(args, torch, api, w, dev)
-        big, c4 = r if isinstance(r, tuple) else (r, None)
+        big, learned_big = r if isinstance(r, tuple) else (r, None)
 
     out = {
         "metric": "J.v Mcells/s (FP64) & time-to-1e-8 residual, learned vs plain precond",
@@ -886,7 +889,10 @@ def main():
                                         f"each split into 6 tetrahedra, p={args.p}, |S|={ctx.report['stencil_size']}",
                                 "symmetric": f"3D LE polynomial (degree p) symmetric about x = 0, {args.n}^3 hex "
                                              f"tensor-perturbed +-20%, symmetry planes on x = 0, p={args.p}, "
-                                             f"|S|={ctx.report['stencil_size']}"
+                                             f"|S|={ctx.report['stencil_size']}",
+                                "poly": f"3D linear elastic MMS, unit cube, {args.n}^3 hex perturbed +-20% (seed 0) "
+                                        f"with every other 2x2x2 block merged into one 24-face polyhedron, "
+                                        f"p={args.p}, |S|={ctx.report['stencil_size']}, fan-triangulated faces"
                                 }[args.workload],
                    "n_cells": nc, "global_batch": nc, "parallelism": "single GPU"},
         "residual_mcells_s": nc / (ms_res * 1e-3) / 1e6,
@@ -899,7 +905,7 @@ def main():
         "cpu_baseline": cpu,
         "setup_seconds": t_setup,
         "precision_study_128": big,
-        "learned_128": c4,
+        "learned_128": learned_big,
     }
     print(json.dumps(out), flush=True)
 

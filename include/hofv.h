@@ -94,8 +94,8 @@ typedef struct {
                              the two areas, and the face area Gamma_f that sum (on
                              a warped face larger than the vector area's length).
                              The normal is the vector area's direction either way;
-                             rule 0 takes Gamma_f as that vector's length.  1 needs the linear elastic
-                             law with fold_quadrature = 1 (HOFV_EINVAL otherwise);
+                             rule 0 takes Gamma_f as that vector's length.  Either
+                             rule serves both laws and both quadrature forms;
                              triangle faces and 2D edges ignore it. */
 } hofv_params;
 

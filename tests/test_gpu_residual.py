@@ -223,17 +223,27 @@ def test_neo_hookean_symmetry_faces_parity(p):
     assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
 
 
-@pytest.mark.parametrize("p", [2, 3])
-def test_residual_and_jvp_parity_with_the_fan_face_rule(p):
+def _fan_beam(p):
+    prob = w.cantilever(shape=(10, 3, 3), p=p, n_plus=20, tip_traction=0.05)
+    prob.mesh = w.box_mesh((10, 3, 3), lengths=(10.0, 1.0, 1.0), perturb=0.15, seed=3)
+    return prob
+
+
+@pytest.mark.parametrize("case", ["le_p2_folded", "le_p3_folded", "le_p2_points", "le_p3_points", "nh_p1", "nh_p2"])
+def test_residual_and_jvp_parity_with_the_fan_face_rule(case):
     """Quadrilateral faces integrated by fan triangulation (two triangles from
-    the lowest-numbered vertex, area-scaled weights) on a randomly perturbed
-    cube, whose faces are not planar."""
-    prob = w.cube_mms(6 if p == 2 else 7, p, perturb=0.2)
+    the lowest-numbered vertex, area-scaled weights) on randomly perturbed
+    meshes, whose faces are not planar: the linear law with the points folded
+    into the coefficients or kept (8 points per face), and the neo-Hookean law
+    on a strained beam (2 and 8 points per face)."""
+    law, pp, form = (case.split("_") + [""])[:3]
+    p = int(pp[1])
+    prob = w.cube_mms(6 if p == 2 else 7, p, perturb=0.2) if law == "le" else _fan_beam(p)
     prob.face_rule = 1
     disc = ores.build(prob)
-    ctx = _api().context_for(prob)
+    ctx = _api().context_for(prob, fold_quadrature=form != "points")
     n = disc.n_cells
-    u = w.random_state(n, 3, seed=21)
+    u = w.random_state(n, 3, seed=21, scale=1e-3 if law == "le" else 0.05)
     v = w.random_state(n, 3, seed=22, scale=1.0)
     ud, vd = to_dev(u), to_dev(v)
     R = torch.empty_like(ud)

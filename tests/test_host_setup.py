@@ -142,7 +142,8 @@ def test_sources_match_oracle_plus_boundary_constants(mesh):
     assert np.abs(src - R0).max() <= 1e-11 * np.abs(R0).max()
 
 
-@pytest.mark.parametrize("mk", [lambda: w.cube_mms(5, 1, perturb=0.2), lambda: w.tet_mms(3, 1, perturb=0.2)])
+@pytest.mark.parametrize("mk", [lambda: w.cube_mms(5, 1, perturb=0.2), lambda: w.tet_mms(3, 1, perturb=0.2),
+                                lambda: w.split_mms((3, 3, 2), 1, perturb=0.15, seed=2)])
 def test_preconditioner_tables_match_oracle(mk):
     prob = mk()
     disc = ores.build(prob)
@@ -152,16 +153,20 @@ def test_preconditioner_tables_match_oracle(mk):
     n = disc.n_cells
     perm = ctx.host_table("pc_perm")
     dinv = ctx.host_table("pc_dinv")
-    a = ctx.host_table("pc_a").reshape(6, n)
-    nbr = ctx.host_table("pc_nbr").reshape(6, n)
+    NS = ctx.host_table("pc_a").size // n  # face slots per cell: 6, or the most faces of a polyhedron
+    a = ctx.host_table("pc_a").reshape(NS, n)
+    nbr = ctx.host_table("pc_nbr").reshape(NS, n)
     assert np.array_equal(np.sort(perm), np.arange(n))
     assert np.all(np.diff(col[perm]) >= 0)  # colour-major
     assert np.allclose(1.0 / dinv, np.diag(A)[perm], rtol=1e-6)
+    off = 0
     for i in range(n):
         P = perm[i]
-        for s in range(6):
+        for s in range(NS):
             if a[s, i] != 0:
                 assert a[s, i] == pytest.approx(A[P, perm[nbr[s, i]]], rel=1e-6)
+                off += 1
+    assert off == np.count_nonzero(A) - n  # every off-diagonal entry is in a slot
 
 
 def test_host_only_context_rejects_hot_calls():
@@ -177,10 +182,11 @@ def test_setup_rejects_bad_parameters():
         api.Context(4, 2, 10, 2, 0, 1.0, 1.0, stencil_quantum=1e-9, host_only=True)
     with pytest.raises(api.HofvError):
         api.Context(2, 2, 10, 2, 1, 1.0, 1.0, stencil_quantum=1e-9, host_only=True)  # NH in 2D
-    for nh, fold, rule in ((1, True, 1), (0, False, 1), (0, True, 2)):  # the fan rule's limits
-        with pytest.raises(api.HofvError):
-            api.Context(3, 2, 55, 2, nh, 1.0, 1.0, stencil_quantum=1e-9, fold_quadrature=fold, host_only=True,
-                        face_rule=rule)
+    with pytest.raises(api.HofvError):  # no such face rule
+        api.Context(3, 2, 55, 2, 0, 1.0, 1.0, stencil_quantum=1e-9, host_only=True, face_rule=2)
+    for nh, fold in ((1, True), (0, False)):  # the fan rule with per-point kernels (2 n_gauss^2 points)
+        api.Context(3, 2, 55, 2, nh, 1.0, 1.0, stencil_quantum=1e-9, fold_quadrature=fold, host_only=True,
+                    face_rule=1).close()
     ctx = api.Context(2, 3, 10, 2, 0, 1.0, 1.0, stencil_quantum=1e-9, host_only=True)
     mesh = w.box_mesh((2, 2))
     ctx.set_mesh(mesh.verts, mesh.cells)
