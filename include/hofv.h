@@ -510,6 +510,10 @@ hofv_status hofv_nn_train(hofv_nn* nn, int32_t n_sets, hofv_pairset* const* sets
  * summed milliseconds and launch count of the kernel called `name` since the
  * last reset (enable = 1 resets). */
 hofv_status hofv_set_timing(hofv_ctx* ctx, int32_t enable);
+/* As hofv_set_timing(ctx, 1), but events are recorded only around launches
+ * of the kernel called `name` (NULL: every kernel), so that timing one kernel
+ * does not put event records between all the others. */
+hofv_status hofv_set_timing_only(hofv_ctx* ctx, const char* name);
 hofv_status hofv_kernel_time(hofv_ctx* ctx, const char* name, double* total_ms, int64_t* count);
 
 /* Host copy of a setup table of a host_only context (after hofv_setup):

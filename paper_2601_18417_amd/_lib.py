@@ -105,6 +105,7 @@ SIGNATURES = {
     "hofv_dyn_reset": (ST, [P, P, P, P, P, P]),
     "hofv_dyn_step": (ST, [P, P, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), P]),
     "hofv_set_timing": (ST, [P, C.c_int32]),
+    "hofv_set_timing_only": (ST, [P, C.c_char_p]),
     "hofv_kernel_time": (ST, [P, C.c_char_p, D, C.POINTER(C.c_int64)]),
     "hofv_kernel_bytes": (ST, [P, C.c_char_p, D]),
     "hofv_nn_param_count": (C.c_int64, []),

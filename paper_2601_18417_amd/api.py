@@ -276,8 +276,13 @@ class Context:
         return np.frombuffer(bytes(buf), dtype=dtype).copy()
 
     # -------------------------------------------------------------- timing
-    def set_timing(self, enable):
-        self._check(self.lib.hofv_set_timing(self.h, int(bool(enable))))
+    def set_timing(self, enable, only=None):
+        """Per-kernel HIP events on (resets the record) or off; only = a kernel
+        name times that kernel's launches alone."""
+        if enable and only:
+            self._check(self.lib.hofv_set_timing_only(self.h, only.encode()))
+        else:
+            self._check(self.lib.hofv_set_timing(self.h, int(bool(enable))))
 
     def kernel_time(self, name):
         ms = C.c_double()

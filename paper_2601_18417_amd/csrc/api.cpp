@@ -748,6 +748,14 @@ hofv_status hofv_set_timing(hofv_ctx* c, int32_t enable) {
   c->timers.clear();
   c->ev_used = 0;
   c->timing = enable != 0;
+  c->timing_only.clear();
+  return HOFV_OK;
+}
+
+hofv_status hofv_set_timing_only(hofv_ctx* c, const char* name) {
+  hofv_status s = hofv_set_timing(c, 1);
+  if (s) return s;
+  if (name) c->timing_only = name;
   return HOFV_OK;
 }
 

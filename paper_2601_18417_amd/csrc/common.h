@@ -230,6 +230,7 @@ struct hofv_ctx {
 
   // timing
   bool timing = false;
+  std::string timing_only;  // non-empty: only launches of this kernel are timed
   bool use_mg = false;  // apply the approximate Jacobian by the V-cycle
   std::vector<hofv::TimerRec> timers;
   std::vector<hipEvent_t> ev_pool;  // events of the timers, reused

@@ -746,13 +746,14 @@ static hipEvent_t pooled_event(hofv_ctx* c) {
 }
 
 void timer_begin(hofv_ctx* c, const char* name, hipStream_t st, hipEvent_t* ev) {
-  if (!c->timing) return;
+  *ev = nullptr;
+  if (!c->timing || (!c->timing_only.empty() && c->timing_only != name)) return;
   *ev = pooled_event(c);
   hipEventRecord(*ev, st);
 }
 
 void timer_end(hofv_ctx* c, const char* name, hipStream_t st, hipEvent_t ev) {
-  if (!c->timing) return;
+  if (!c->timing || !ev) return;
   hipEvent_t e2 = pooled_event(c);
   hipEventRecord(e2, st);
   c->timers.push_back({name, ev, e2});
