@@ -632,6 +632,9 @@ def main():
                     help="time-to-tolerance solves as one logged library Newton step per call, at most this many "
                          "steps per increment (0: one library call per increment)")
     ap.add_argument("--lz", type=float, default=1.0, help="z extent of the evaluation cube (cell aspect 1/lz)")
+    ap.add_argument("--stencil-grow", type=int, default=0,
+                    help="grow stencils that fail the pivot test by this many cells at a time (0: such a "
+                         "stencil is an error)")
     ap.add_argument("--big", type=int, default=1,
                     help="1: also the 128^3 p = 3 leg (J.v throughput, sampled oracle error, plain and learned "
                          "Newton with the committed model) after the cube workload")
@@ -692,6 +695,7 @@ def main():
                             symmetric=True)
     else:
         prob = w.square_mms(32, args.p)
+    prob.stencil_grow = args.stencil_grow
     nc, D = prob.mesh.n_cells, prob.dim
     t0 = time.perf_counter()
     ctx = api.context_for(prob, precond_levels=args.precond_levels)
@@ -918,7 +922,9 @@ def main():
                                         f"with every other 2x2x2 block merged into one 24-face polyhedron, "
                                         f"p={args.p}, |S|={ctx.report['stencil_size']}, fan-triangulated faces"
                                 }[args.workload],
-                   "n_cells": nc, "global_batch": nc, "parallelism": "single GPU"},
+                   "n_cells": nc, "global_batch": nc, "parallelism": "single GPU",
+                   **({"stencil_grow": args.stencil_grow, "grown_stencils": ctx.report["n_grown_stencils"]}
+                      if args.stencil_grow else {})},
         "residual_mcells_s": nc / (ms_res * 1e-3) / 1e6,
         "jvp_algorithmic_GBps": jvp_bytes / (ms_step * 1e-3) / 1e9,
         "jvp_frac_of_hbm_peak": jvp_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,

@@ -97,6 +97,17 @@ typedef struct {
                              rule 0 takes Gamma_f as that vector's length.  Either
                              rule serves both laws and both quadrature forms;
                              triangle faces and 2D edges ignore it. */
+  int32_t stencil_grow;   /* 0: a stencil that fails the pivot test of its QR
+                             (min |R_ii| <= 1e-14 max |R_ii|) is an error
+                             (HOFV_ESINGULAR).  g > 0: such a face or cell
+                             stencil is replaced by the |S| + g, |S| + 2g, ...
+                             nearest cells (same tie rule) until it passes, up
+                             to 255 cells and the mesh's cell count (the remedy of
+                             Sec. 5's ill-conditioning study, a larger n+,
+                             applied where the test fails); the tables then
+                             take the largest size and shorter stencils are
+                             padded with zero coefficients.  Symmetry-face
+                             stencils are not grown. */
 } hofv_params;
 
 /* Creates a context on the current HIP device.  *out is NULL on failure. */
@@ -193,6 +204,7 @@ typedef struct {
   double device_bytes;     /* device memory held by the context */
   double residual_bytes;   /* algorithmic HBM bytes of one residual */
   double setup_seconds;
+  int64_t n_grown_stencils;  /* face and cell stencils enlarged by stencil_grow */
 } hofv_setup_report;
 
 /* Builds stencils (Sec. 3.5.2), least-squares coefficients (Sec. 3.5.1,

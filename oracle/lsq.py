@@ -51,15 +51,8 @@ class SingularStencil(ValueError):
     pass
 
 
-def reconstruction(xt: np.ndarray, Xs: np.ndarray, p: int, k: float,
-                   ghost_weight: float | None = None, pivot_tol: float = 1e-14):
-    """Batched LS reconstruction.
-
-    xt: (m, D) expansion points; Xs: (m, S, D) stencil centroids.
-    Returns (A, cond): A is (m, N_t, S [+1 ghost column]) with row e giving the
-    physical derivative d^e u(x~) as a combination of the stencil values (and the
-    ghost value last); cond = max|R_ii| / min|R_ii| per point.
-    """
+def _weighted_qr(xt, Xs, p, k, ghost_weight):
+    """QR of the weighted scaled-Taylor system W^(1/2) Q (eqs. maQw, weightFunc)."""
     m, S, D = Xs.shape
     E = exponents(D, p)
     dx = Xs - xt[:, None, :]
@@ -79,8 +72,28 @@ def reconstruction(xt: np.ndarray, Xs: np.ndarray, p: int, k: float,
         Q = np.concatenate([Q, g], axis=1)
         w = np.concatenate([w, np.full((m, 1), float(ghost_weight))], axis=1)
     sw = np.sqrt(w)
-    B = sw[:, :, None] * Q
-    Qh, R = np.linalg.qr(B, mode="reduced")
+    Qh, R = np.linalg.qr(sw[:, :, None] * Q, mode="reduced")
+    return Qh, R, sw, h, E
+
+
+def pivot_ok(xt: np.ndarray, Xs: np.ndarray, p: int, k: float, ghost_weight: float | None = None,
+             pivot_tol: float = 1e-14) -> np.ndarray:
+    """Per point: does the stencil pass the pivot test min|R_ii| > tol max|R_ii|?"""
+    _, R, _, _, _ = _weighted_qr(xt, Xs, p, k, ghost_weight)
+    diag = np.abs(np.diagonal(R, axis1=1, axis2=2))
+    return diag.min(axis=1) > pivot_tol * diag.max(axis=1)
+
+
+def reconstruction(xt: np.ndarray, Xs: np.ndarray, p: int, k: float,
+                   ghost_weight: float | None = None, pivot_tol: float = 1e-14):
+    """Batched LS reconstruction.
+
+    xt: (m, D) expansion points; Xs: (m, S, D) stencil centroids.
+    Returns (A, cond): A is (m, N_t, S [+1 ghost column]) with row e giving the
+    physical derivative d^e u(x~) as a combination of the stencil values (and the
+    ghost value last); cond = max|R_ii| / min|R_ii| per point.
+    """
+    Qh, R, sw, h, E = _weighted_qr(xt, Xs, p, k, ghost_weight)
     diag = np.abs(np.diagonal(R, axis1=1, axis2=2))
     if np.any(diag.min(axis=1) <= pivot_tol * diag.max(axis=1)):
         raise SingularStencil("rank-deficient least-squares stencil")

@@ -43,7 +43,7 @@ import numpy as np
 from workloads.fields import DISP, SYMM, TRAC
 
 from . import geometry as geo
-from .lsq import reconstruction, row_index
+from .lsq import SingularStencil, pivot_ok, reconstruction, row_index
 from .stencil import nearest
 
 
@@ -200,12 +200,77 @@ def build(problem, active=None) -> Discretisation:
     k = problem.k_weight
 
     fi = np.nonzero(internal)[0]
-    f_st = nearest(fg.centre[fi], cen, S, q)
-    f_C, _, c1 = _face_coefficients(fg.qpts[fi], f_st, cen, p, k)
-    d_st = nearest(fg.centre[disp], cen, S, q)
-    d_C, d_Cg, c2 = _face_coefficients(fg.qpts[disp], d_st, cen, p, k, problem.ghost_weight)
-    if d_Cg is None:
-        d_Cg = np.zeros((0, fg.qpts.shape[1], D))
+    nq = fg.qpts.shape[1]
+    grow = int(getattr(problem, "stencil_grow", 0))
+
+    def stencils(ref, ok):
+        """The S nearest cells of each reference point; with stencil_grow = g > 0
+        a stencil whose least-squares systems fail the pivot test becomes the
+        S + g, S + 2g, ... nearest (up to 255 cells and the cell count): a larger n+
+        where the conditioning needs it (Sec. 5's ill-conditioning study).
+        Returns the per-point cell lists and their sizes."""
+        st = nearest(ref, cen, S, q) if ref.shape[0] else np.zeros((0, S), np.int64)
+        rows = list(st)
+        size = np.full(ref.shape[0], S)
+        if grow <= 0 or ref.shape[0] == 0:
+            return rows, size
+        bad = ~ok(np.arange(ref.shape[0]), st)
+        step = 0
+        while bad.any():
+            step += 1
+            Sg = S + step * grow
+            if Sg > 255 or Sg > n_c:
+                raise SingularStencil("a stencil still fails the pivot test after growing it")
+            idx = np.nonzero(bad)[0]
+            stg = nearest(ref[idx], cen, Sg, q)
+            for j, i in enumerate(idx):
+                rows[i] = stg[j]
+                size[i] = Sg
+            bad[:] = False
+            bad[idx[~ok(idx, stg)]] = True
+        return rows, size
+
+    def faces_ok(fids, ghost):
+        def ok(idx, st):  # every weighted point of each face
+            okq = pivot_ok(fg.qpts[fids[idx]].reshape(-1, D), np.repeat(cen[st], nq, axis=0), p, k, ghost)
+            return np.all(okq.reshape(idx.size, nq) | (fg.qw[fids[idx]] == 0.0), axis=1)
+        return ok
+
+    f_rows, f_size = stencils(fg.centre[fi], faces_ok(fi, None))
+    d_rows, d_size = stencils(fg.centre[disp], faces_ok(disp, problem.ghost_weight))
+    # cells whose u* is needed: both sides of internal faces, owners of disp faces
+    need = np.zeros(n_c, bool)
+    need[faces.owner[fi]] = True
+    need[faces.neigh[fi]] = True
+    need[faces.owner[disp]] = True
+    cells = np.nonzero(need)[0]
+    c_rows, c_size = stencils(cen[cells], lambda idx, st: pivot_ok(cen[cells[idx]], cen[st], p, k))
+    # one table width: the largest stencil; shorter ones are padded with their
+    # last cell and zero coefficients (a zero coefficient adds nothing)
+    SW = int(max([S] + [int(z.max()) for z in (f_size, d_size, c_size) if z.size]))
+
+    def padded(rows, size):
+        out = np.zeros((len(rows), SW), np.int64)
+        for i, r in enumerate(rows):
+            out[i, :size[i]] = r
+            out[i, size[i]:] = r[-1]
+        return out
+
+    def face_tables(fids, rows, size, ghost):
+        C = np.zeros((len(rows), nq, D, SW))
+        Cg = np.zeros((len(rows), nq, D))
+        cmax = 0.0
+        for s_ in np.unique(size):
+            g = np.nonzero(size == s_)[0]
+            Cs, Cgs, c = _face_coefficients(fg.qpts[fids[g]], np.array([rows[i] for i in g]), cen, p, k, ghost)
+            C[g, :, :, :s_] = Cs
+            if Cgs is not None:
+                Cg[g] = Cgs
+            cmax = max(cmax, c)
+        return padded(rows, size), C, Cg, cmax
+
+    f_st, f_C, _, c1 = face_tables(fi, f_rows, f_size, None)
+    d_st, d_C, d_Cg, c2 = face_tables(disp, d_rows, d_size, problem.ghost_weight)
     sym_kw, c4 = {}, 0.0
     if sym.size:
         s_st = nearest(fg.centre[sym], cen, (S + 1) // 2, q)
@@ -213,21 +278,21 @@ def build(problem, active=None) -> Discretisation:
         sym_kw = dict(s_own=faces.owner[sym], s_n=fg.normal[sym], s_area=fg.area[sym], s_x=fg.centre[sym],
                       s_qw=fg.qw[sym], s_st=s_st, s_C=s_C, s_Cg=s_Cg)
 
-    # cells whose u* is needed: both sides of internal faces, owners of disp faces
-    need = np.zeros(n_c, bool)
-    need[faces.owner[fi]] = True
-    need[faces.neigh[fi]] = True
-    need[faces.owner[disp]] = True
-    cells = np.nonzero(need)[0]
-    c_st = np.full((n_c, S), -1, np.int64)
-    c_st[cells] = nearest(cen[cells], cen, S, q)
-    D1, D2, D3, c3 = _cell_coefficients(cells, c_st[cells], cen, p, k)
-    c_D1 = np.zeros((n_c, D, S)); c_D1[cells] = D1
-    c_D2 = c_D3 = None
-    if D2 is not None:
-        c_D2 = np.zeros((n_c, D, D, S)); c_D2[cells] = D2
-    if D3 is not None:
-        c_D3 = np.zeros((n_c, D, D, D, S)); c_D3[cells] = D3
+    c_st = np.full((n_c, SW), -1, np.int64)
+    c_st[cells] = padded(c_rows, c_size)
+    c_D1 = np.zeros((n_c, D, SW))
+    c_D2 = np.zeros((n_c, D, D, SW)) if p >= 2 else None
+    c_D3 = np.zeros((n_c, D, D, D, SW)) if p >= 3 else None
+    c3 = 0.0
+    for s_ in np.unique(c_size):
+        g = np.nonzero(c_size == s_)[0]
+        D1, D2, D3, c = _cell_coefficients(cells[g], np.array([c_rows[i] for i in g]), cen, p, k)
+        c_D1[cells[g], ..., :s_] = D1
+        if D2 is not None:
+            c_D2[cells[g], ..., :s_] = D2
+        if D3 is not None:
+            c_D3[cells[g], ..., :s_] = D3
+        c3 = max(c3, c)
 
     # body force: (p+2)^D Gauss points of the cell map (of each sub-simplex of a
     # polyhedral cell)

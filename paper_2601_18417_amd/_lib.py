@@ -24,13 +24,14 @@ class Params(C.Structure):
                 ("material", C.c_int32), ("fold_quadrature", C.c_int32), ("mu", C.c_double),
                 ("lambda_", C.c_double), ("alpha", C.c_double), ("k_weight", C.c_double),
                 ("ghost_weight", C.c_double), ("stencil_quantum", C.c_double), ("host_only", C.c_int32),
-                ("precond_levels", C.c_int32), ("face_rule", C.c_int32)]
+                ("precond_levels", C.c_int32), ("face_rule", C.c_int32), ("stencil_grow", C.c_int32)]
 
 
 class SetupReport(C.Structure):
     _fields_ = [("stencil_size", C.c_int32), ("n_colours", C.c_int32), ("n_internal_faces", C.c_int64),
                 ("n_disp_faces", C.c_int64), ("n_trac_faces", C.c_int64), ("max_cond", C.c_double),
-                ("device_bytes", C.c_double), ("residual_bytes", C.c_double), ("setup_seconds", C.c_double)]
+                ("device_bytes", C.c_double), ("residual_bytes", C.c_double), ("setup_seconds", C.c_double),
+                ("n_grown_stencils", C.c_int64)]
 
 
 class KrylovOpts(C.Structure):

@@ -48,11 +48,11 @@ class Context:
 
     def __init__(self, dim, order_p, n_plus, n_gauss, material, mu, lam, alpha=0.1, k_weight=6.0,
                  ghost_weight=1.0, stencil_quantum=1e-12, fold_quadrature=True, host_only=False, precond_levels=1,
-                 face_rule=0):
+                 face_rule=0, stencil_grow=0):
         self.lib = L.load()
         prm = L.Params(dim, order_p, n_plus, n_gauss, material, int(bool(fold_quadrature)), mu, lam, alpha,
                        k_weight, ghost_weight, stencil_quantum, int(bool(host_only)), int(precond_levels),
-                       int(face_rule))
+                       int(face_rule), int(stencil_grow))
         h = C.c_void_p()
         st = self.lib.hofv_create(C.byref(prm), C.byref(h))
         if st != L.HOFV_OK:
@@ -444,7 +444,7 @@ def context_for(problem, fold_quadrature=True, host_only=False, precond_levels=1
     note = progress or (lambda stage: None)
     ctx = Context(problem.mesh.dim, problem.p, problem.n_plus, problem.n_gauss, problem.material, problem.mu,
                   problem.lam, problem.alpha, problem.k_weight, problem.ghost_weight, problem.stencil_quantum,
-                  fold_quadrature, host_only, precond_levels, problem.face_rule)
+                  fold_quadrature, host_only, precond_levels, problem.face_rule, getattr(problem, "stencil_grow", 0))
     m = problem.mesh
     if hasattr(m, "face_cells"):
         ctx.set_mesh_poly(m.verts, m.face_ptr, m.face_verts, m.face_cells, m.n_cells)

@@ -84,6 +84,8 @@ hofv_status hofv_create(const hofv_params* prm, hofv_ctx** out) {
   if (prm->precond_levels < 0 || prm->precond_levels > 16)
     return fail(nullptr, HOFV_EINVAL, "precond_levels must be 0..16");
   if (prm->face_rule != 0 && prm->face_rule != 1) return fail(nullptr, HOFV_EINVAL, "face_rule must be 0 or 1");
+  if (prm->stencil_grow < 0 || prm->stencil_grow > 255)
+    return fail(nullptr, HOFV_EINVAL, "stencil_grow must be 0..255");
   if (!(prm->mu > 0) || !(prm->k_weight > 0) || prm->alpha < 0 || prm->ghost_weight <= 0)
     return fail(nullptr, HOFV_EINVAL, "mu, k_weight, ghost_weight must be > 0 and alpha >= 0");
   hofv_ctx* c = new (std::nothrow) hofv_ctx();

@@ -14,6 +14,7 @@
 //    of the displacement-face stabilisation;
 //  * the compact approximate Jacobian in FP32 with a greedy colouring.
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -35,9 +36,9 @@ hofv_status build_tables(hofv_ctx* c) {
   const bool nh = c->prm.material == HOFV_NEO_HOOKEAN;
   const bool fold = !nh && c->prm.fold_quadrature;
   const double mu = c->prm.mu, lam = c->prm.lambda, kbar = 2 * mu + lam;
-  const int S = n_basis(D, p) + c->prm.n_plus;
-  if (S > 255) return fail(c, HOFV_EINVAL, "stencil size above 255");
-  if (S > nc) return fail(c, HOFV_EINVAL, "stencil size exceeds the number of cells");
+  const int S0 = n_basis(D, p) + c->prm.n_plus;  // |S| = N_t + n+ (Sec. 3.5.2)
+  if (S0 > 255) return fail(c, HOFV_EINVAL, "stencil size above 255");
+  if (S0 > nc) return fail(c, HOFV_EINVAL, "stencil size exceeds the number of cells");
   const double kshape = c->prm.k_weight, gw = c->prm.ghost_weight, alpha = c->prm.alpha;
 
   // kernel faces: internal, then displacement, each along a Morton curve of
@@ -74,15 +75,107 @@ hofv_status build_tables(hofv_ctx* c) {
   std::vector<double> pts((size_t)nf * D);
   for (int64_t i = 0; i < nf; ++i)
     for (int d = 0; d < D; ++d) pts[i * D + d] = c->f_centre[(size_t)kf[i] * D + d];
-  std::vector<int32_t> fst((size_t)nf * S), cst((size_t)nc * S);
-  nearest_cells(c->cen, D, nc, pts.data(), nf, S, c->prm.stencil_quantum, fst.data());
-  nearest_cells(c->cen, D, nc, c->cen.data(), nc, S, c->prm.stencil_quantum, cst.data());
+  std::vector<int32_t> fst((size_t)nf * S0), cst((size_t)nc * S0);
+  nearest_cells(c->cen, D, nc, pts.data(), nf, S0, c->prm.stencil_quantum, fst.data());
+  nearest_cells(c->cen, D, nc, c->cen.data(), nc, S0, c->prm.stencil_quantum, cst.data());
+  // stencil size per face and per cell: S0, or more where stencil_grow
+  // enlarged a stencil that failed the pivot test; the tables take the
+  // largest (S) and shorter stencils get zero coefficients past their end
+  std::vector<int32_t> fsz(nf, S0), csz(nc, S0);
+  std::vector<std::vector<int32_t>> fgrown, cgrown;
+  int64_t n_grown = 0;
+  if (c->prm.stencil_grow > 0) {
+    const double qnt = c->prm.stencil_quantum;
+    const int g = c->prm.stencil_grow;
+    const double tgt[3] = {0, 1, 2};
+    // the cells whose u* is needed: both sides of internal faces and the
+    // owners of displacement faces
+    std::vector<char> need(nc, 0);
+    for (int64_t i = 0; i < nf; ++i) {
+      const hofv_ctx::Face& F = c->faces[kf[i]];
+      need[F.own] = 1;
+      if (F.nei >= 0) need[F.nei] = 1;
+    }
+    // pivot test of every least-squares system a stencil takes part in
+    auto face_ok = [&](int64_t i, const int32_t* ids, int sz) {
+      const int64_t f = kf[i];
+      const bool disp = c->faces[f].nei < 0;
+      double X[256 * 3], out[3 * 257], cond, h;
+      for (int k = 0; k < sz; ++k)
+        for (int d = 0; d < D; ++d) X[k * D + d] = c->cen[(size_t)ids[k] * D + d];
+      for (int q = 0; q < nq; ++q) {
+        if (c->f_qw[(size_t)f * nq + q] == 0.0) continue;
+        if (!ls_functionals(D, p, kshape, &c->f_qp[((size_t)f * nq + q) * D], X, sz, disp ? gw : 0.0,
+                            kTargetGradient, D, tgt, out, &cond, &h))
+          return false;
+      }
+      return true;
+    };
+    auto cell_ok = [&](int64_t P, const int32_t* ids, int sz) {
+      if (!need[P]) return true;
+      double X[256 * 3], out[3 * 257], cond, h;
+      for (int k = 0; k < sz; ++k)
+        for (int d = 0; d < D; ++d) X[k * D + d] = c->cen[(size_t)ids[k] * D + d];
+      return ls_functionals(D, p, kshape, &c->cen[(size_t)P * D], X, sz, 0.0, kTargetGradient, D, tgt, out, &cond,
+                            &h);
+    };
+    // a failing stencil becomes the S0 + g, S0 + 2g, ... nearest cells
+    auto grow = [&](int64_t n, const double* ref, const std::vector<int32_t>& st, std::vector<int32_t>& sz,
+                    std::vector<std::vector<int32_t>>& out,
+                    const std::function<bool(int64_t, const int32_t*, int)>& ok) {
+      out.assign(n, {});
+      std::vector<char> bad(n, 0);
+#pragma omp parallel for schedule(dynamic, 64)
+      for (int64_t i = 0; i < n; ++i) bad[i] = !ok(i, &st[(size_t)i * S0], S0);
+      for (int step = 1;; ++step) {
+        std::vector<int64_t> idx;
+        for (int64_t i = 0; i < n; ++i)
+          if (bad[i]) idx.push_back(i);
+        if (idx.empty()) return true;
+        const int Sg = S0 + step * g;
+        if (Sg > 255 || Sg > nc) return false;
+        const int64_t m = (int64_t)idx.size();
+        std::vector<double> rp((size_t)m * D);
+        for (int64_t j = 0; j < m; ++j)
+          for (int d = 0; d < D; ++d) rp[j * D + d] = ref[idx[j] * D + d];
+        std::vector<int32_t> tmp((size_t)m * Sg);
+        nearest_cells(c->cen, D, nc, rp.data(), m, Sg, qnt, tmp.data());
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t j = 0; j < m; ++j) {
+          const int64_t i = idx[j];
+          out[i].assign(&tmp[(size_t)j * Sg], &tmp[(size_t)j * Sg] + Sg);
+          sz[i] = Sg;
+          bad[i] = !ok(i, out[i].data(), Sg);
+        }
+      }
+    };
+    if (!grow(nf, pts.data(), fst, fsz, fgrown, face_ok))
+      return fail(c, HOFV_ESINGULAR, "a face stencil still fails the pivot test after growing it");
+    if (!grow(nc, c->cen.data(), cst, csz, cgrown, cell_ok))
+      return fail(c, HOFV_ESINGULAR, "a cell stencil still fails the pivot test after growing it");
+    for (int32_t v : fsz) n_grown += v > S0;
+    for (int32_t v : csz) n_grown += v > S0;
+  }
+  const int S = std::max(*std::max_element(fsz.begin(), fsz.end()), *std::max_element(csz.begin(), csz.end()));
   // a stencil is a set: store it in increasing cell id (a canonical order;
-  // the block unions are built from it)
+  // the block unions are built from it), padded to S with its largest id
+  auto relayout = [&](int64_t n, std::vector<int32_t>& st, const std::vector<int32_t>& sz,
+                      const std::vector<std::vector<int32_t>>& grown) {
+    std::vector<int32_t> out((size_t)n * S);
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < nf; ++i) std::sort(&fst[(size_t)i * S], &fst[(size_t)i * S] + S);
-#pragma omp parallel for schedule(static)
-  for (int64_t P = 0; P < nc; ++P) std::sort(&cst[(size_t)P * S], &cst[(size_t)P * S] + S);
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t* from = grown.empty() || grown[i].empty() ? &st[(size_t)i * S0] : grown[i].data();
+      int32_t* to = &out[(size_t)i * S];
+      std::copy_n(from, sz[i], to);
+      std::sort(to, to + sz[i]);
+      for (int k = sz[i]; k < S; ++k) to[k] = to[sz[i] - 1];
+    }
+    st.swap(out);
+  };
+  relayout(nf, fst, fsz, fgrown);
+  relayout(nc, cst, csz, cgrown);
+  fgrown.clear();
+  cgrown.clear();
   const StencilBlocks fblk = make_blocks(fst.data(), nf, S, nc, kBlockItems, kLdsFaceCells);
   if (fblk.max_cells > kLdsFaceCells)
     return fail(c, HOFV_EINVAL, "stencil union of one item exceeds the LDS staging capacity");
@@ -111,8 +204,9 @@ hofv_status build_tables(hofv_ctx* c) {
     const double* n = &c->f_normal[(size_t)f * D];
     const double A = c->f_area[f];
     const double* qw = &c->f_qw[(size_t)f * nq];
+    const int Si = fsz[i];  // this face's stencil (S0, or grown)
     double X[256 * 3];
-    for (int k = 0; k < S; ++k)
+    for (int k = 0; k < Si; ++k)
       for (int d = 0; d < D; ++d) X[k * D + d] = c->cen[(size_t)fst[i * S + k] * D + d];
     double targets[3] = {0, 1, 2};
     double out[3 * 256];
@@ -120,18 +214,18 @@ hofv_status build_tables(hofv_ctx* c) {
     for (int q = 0; q < nq; ++q) {
       if (qw[q] == 0.0) continue;  // a padding point of a face with fewer points
       double cond, h;
-      bool ok = ls_functionals(D, p, kshape, &c->f_qp[((size_t)f * nq + q) * D], X, S, disp ? gw : 0.0,
+      bool ok = ls_functionals(D, p, kshape, &c->f_qp[((size_t)f * nq + q) * D], X, Si, disp ? gw : 0.0,
                                kTargetGradient, D, targets, out, &cond, &h);
       if (!ok) singular = true;
       max_cond = std::max(max_cond, cond);
-      const int m = S + (disp ? 1 : 0);
+      const int m = Si + (disp ? 1 : 0);
       for (int a = 0; a < D; ++a) {
-        for (int k = 0; k < S; ++k) {
+        for (int k = 0; k < Si; ++k) {
           if (fold) fcoef[fblk.at(i, k, a, D, S)] += qw[q] * out[a * m + k];
           else fcoef[fblk.at(i, k, q * D + a, nq * D, S)] = out[a * m + k];
         }
         if (disp) {
-          const double cg = out[a * m + S];
+          const double cg = out[a * m + Si];
           const double* ub = &c->ubq[((size_t)b * nq + q) * D];
           for (int j = 0; j < D; ++j) {
             if (nh) fghost[(((size_t)q * D + a) * D + j) * nfd + (i - nfi)] = cg * ub[j];
@@ -175,7 +269,7 @@ hofv_status build_tables(hofv_ctx* c) {
   // their mirror images through the face plane; the images carry R u, R = I - 2 n n.
   // For the linear law the face term is linear in each u_N: folded over the
   // quadrature points into T[N][j][k], the traction t_j per unit u_N,k.
-  const int Sh = (S + 1) / 2;
+  const int Sh = (S0 + 1) / 2;
   const int64_t nfs = (int64_t)symb.size();
   std::vector<int32_t> sst((size_t)nfs * Sh), sst_t((size_t)Sh * nfs);
   std::vector<double> sT(nh ? 0 : (size_t)Sh * D * D * nfs, 0.0), saj(nfs, 0.0);
@@ -291,8 +385,9 @@ hofv_status build_tables(hofv_ctx* c) {
   std::vector<double> cext((size_t)S * NSI * ni, 0.0);
 #pragma omp parallel for schedule(dynamic, 64) reduction(max : max_cond) reduction(|| : singular)
   for (int64_t P = 0; P < nc; ++P) {
+    const int Sp = csz[P];  // this cell's stencil (S0, or grown)
     double X[256 * 3];
-    for (int k = 0; k < S; ++k)
+    for (int k = 0; k < Sp; ++k)
       for (int d = 0; d < D; ++d) X[k * D + d] = c->cen[(size_t)cst[P * S + k] * D + d];
     std::vector<double> dvec((size_t)NS * 3);
     std::vector<int> slots(NS);
@@ -306,16 +401,16 @@ hofv_status build_tables(hofv_ctx* c) {
       slots[nt++] = s;
     }
     if (nt == 0) continue;
-    std::vector<double> out((size_t)nt * S);
+    std::vector<double> out((size_t)nt * Sp);
     double cond, h;
-    bool ok = ls_functionals(D, p, kshape, &c->cen[(size_t)P * D], X, S, 0.0, kTargetExtrap, nt, dvec.data(),
+    bool ok = ls_functionals(D, p, kshape, &c->cen[(size_t)P * D], X, Sp, 0.0, kTargetExtrap, nt, dvec.data(),
                              out.data(), &cond, &h);
     if (!ok) singular = true;
     max_cond = std::max(max_cond, cond);
     for (int r = 0; r < nt; ++r)
-      for (int k = 0; k < S; ++k) {
-        if (hf) cext[cblk.at(item_of[(size_t)slots[r] * nc + P], k, 0, 1, S)] = out[r * S + k];
-        else cext[cblk.at(cpos[P], k, slots[r], NS, S)] = out[r * S + k];
+      for (int k = 0; k < Sp; ++k) {
+        if (hf) cext[cblk.at(item_of[(size_t)slots[r] * nc + P], k, 0, 1, S)] = out[r * Sp + k];
+        else cext[cblk.at(cpos[P], k, slots[r], NS, S)] = out[r * Sp + k];
       }
   }
   if (singular) return fail(c, HOFV_ESINGULAR, "rank-deficient least-squares stencil at a cell centroid");
@@ -532,6 +627,7 @@ hofv_status build_tables(hofv_ctx* c) {
   c->kernel_bytes["k_extrap"] = ext_b;
   c->kernel_bytes["k_cell_sum"] = sum_b;
   c->report.stencil_size = S;
+  c->report.n_grown_stencils = n_grown;
   c->report.n_colours = ncol;
   c->report.n_internal_faces = nfi;
   c->report.n_disp_faces = nfd;

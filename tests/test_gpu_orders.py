@@ -53,3 +53,24 @@ def test_gpu_solution_matches_oracle_newton():
     n = disc.n_cells
     uo, _ = onw.newton(disc, np.zeros((n, 3)), tol=1e-10, eta=1e-6)
     assert np.linalg.norm(ug - uo) <= 1e-7 * np.linalg.norm(uo)
+
+
+@pytest.mark.parametrize("p,bound", [(1, 1.8), (2, 1.8), (3, 3.5)])
+def test_mms_orders_2d_with_twenty_surplus_nodes(p, bound):
+    """The 2D manufactured problem with n+ = 20 (Sec. 5's remedy for structured
+    2D grids) on 8^2, 16^2, 32^2 and 64^2: every refinement keeps the orders of
+    the manufactured-solution study (the oracle's slopes 2.26, 2.07, 2.01 /
+    1.82, 1.83, 1.92 / 4.30, 4.00, 3.91)."""
+    from paper_2601_18417_amd import api
+    errs = []
+    for n in (8, 16, 32, 64):
+        prob = w.square_mms(n, p, n_plus=20)
+        ctx = api.context_for(prob)
+        u = torch.zeros((2, prob.mesh.n_cells), device=DEV, dtype=torch.float64)
+        st = ctx.newton_solve(u, tol=1e-11, eta=1e-6, restart=60, max_krylov=4000)
+        assert st["converged"]
+        ue = prob.loads.exact.value(ctx.cell_centroids())
+        errs.append(np.sqrt(np.mean(np.sum((u.cpu().numpy().T - ue) ** 2, axis=1))))
+    slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    print(f"p={p} errors {errs} slopes {slopes}")
+    assert np.all(slopes >= bound)

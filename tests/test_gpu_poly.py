@@ -196,11 +196,16 @@ def test_newton_on_split_meshes_matches_oracle(mk):
     disc = ores.build(prob)
     ctx = _api().context_for(prob)
     n, D = disc.n_cells, disc.dim
+    tol = 1e-10
     u = torch.zeros((D, n), device=DEV, dtype=torch.float64)
-    st = ctx.newton_solve(u, tol=1e-10, eta=1e-8, restart=60)
+    st = ctx.newton_solve(u, tol=tol, eta=1e-8, restart=60)
     assert st["converged"]
-    uo, _ = onw.newton(disc, np.zeros((n, D)), tol=1e-10, eta=1e-8, m=60)
-    assert np.linalg.norm(to_host(u) - uo) <= 1e-7 * np.linalg.norm(uo)
+    ug = to_host(u)
+    R0 = np.linalg.norm(ores.residual(disc, np.zeros((n, D))))
+    assert np.linalg.norm(ores.residual(disc, ug)) <= 1.01 * tol * R0
+    uo, _ = onw.newton(disc, np.zeros((n, D)), tol=tol, eta=1e-8, m=60)
+    print("solution difference", np.linalg.norm(ug - uo) / np.linalg.norm(uo))
+    assert np.linalg.norm(ug - uo) <= 100 * tol * np.linalg.norm(uo)
 
 
 @pytest.mark.parametrize("p,min_slope", [(1, 2.0), (2, 1.5), (3, 3.5)])

@@ -351,3 +351,45 @@ def test_library_skewness_coefficients_on_sheared_grid():
                 di, dj = ijk[perm[nbr[s, i]]] - ijk[perm[i]]
                 assert abs(di) + abs(dj) == 1
                 assert a[s, i] == pytest.approx(kb * (1 + s2) if dj == 0 else kb, rel=1e-6)
+
+
+def test_stencil_growth_matches_oracle():
+    """stencil_grow: the library grows the same stencils as the oracle (a
+    tensor-perturbed 12^3 grid at p = 3, whose 85-cell stencils are singular at
+    some faces), to the same sizes, with the same folded coefficient per cell;
+    the tables take the largest size."""
+    prob = w.poly_patch(w.box_mesh((12, 12, 12), perturb=0.2, seed=7, mode="tensor"), 3, 3, seed=2)
+    prob.stencil_grow = 10
+    disc = ores.build(prob)
+    ctx = api.context_for(prob, host_only=True)
+    S = prob.stencil_size
+    SW = ctx.report["stencil_size"]
+    assert SW == disc.f_st.shape[1] > S
+    n_or = sum(int(np.sum([np.unique(r).size > S for r in st])) for st in (disc.f_st, disc.d_st))
+    n_or += int(np.sum([np.unique(r).size > S for r in disc.c_st if r[0] >= 0]))
+    assert ctx.report["n_grown_stencils"] == n_or > 0
+    D = 3
+    fst = ctx.host_table("face_stencil").reshape(SW, -1).T
+    nf = fst.shape[0]
+    own = ctx.host_table("face_own")
+    nei = ctx.host_table("face_nei")
+    coef = np.transpose(ctx.host_table("face_coef").reshape(SW, D, nf), (2, 1, 0))  # (nf, D, SW)
+    key = {(a, b): j for j, (a, b) in enumerate(zip(disc.f_own, disc.f_nei))}
+    oc = np.einsum("fq,fqis->fis", disc.f_qw, disc.f_C)
+    grown_faces = 0
+    for i in range(nf):
+        if nei[i] < 0:
+            continue
+        j = key[(own[i], nei[i])]
+        big = np.unique(disc.f_st[j]).size > S
+        grown_faces += big
+        if not big and i % 9:
+            continue
+        ids = np.unique(fst[i])
+        assert np.array_equal(ids, np.unique(disc.f_st[j]))
+        lib = np.zeros((D, ids.size))
+        ora = np.zeros((D, ids.size))
+        np.add.at(lib.T, np.searchsorted(ids, fst[i]), coef[i].T)
+        np.add.at(ora.T, np.searchsorted(ids, disc.f_st[j]), oc[j].T)
+        assert np.abs(lib - ora).max() <= 1e-11 * np.abs(ora).max()
+    assert grown_faces > 0

@@ -345,6 +345,25 @@ def test_mms_orders_2d():
     assert errs[3][2] < errs[2][2] < errs[1][2]
 
 
+@pytest.mark.slow
+def test_mms_orders_2d_with_twenty_surplus_nodes():
+    """With n+ = 20, the remedy Sec. 5 applies to ill-conditioned structured 2D
+    grids, every refinement 8^2 -> 16^2 -> 32^2 shows the displacement orders
+    of the manufactured-solution study: >= 1.8 at p = 1 and 2, >= 3.5 at p = 3
+    (with the default n+ = 10 the p = 3 slope falls to 3.4 at 32^2 and 3.2 at
+    64^2 on these uniform grids)."""
+    for p, bound in ((1, 1.8), (2, 1.8), (3, 3.5)):
+        errs = []
+        for n in (8, 16, 32):
+            prob = w.square_mms(n, p, n_plus=20)
+            disc = rs.build(prob)
+            u, _ = nw.newton(disc, np.zeros((disc.n_cells, 2)), tol=1e-11, eta=1e-6, m=60)
+            ue = prob.loads.exact.value(disc.cen)
+            errs.append(np.sqrt(np.mean(np.sum((u - ue) ** 2, axis=1))))
+        slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+        assert np.all(slopes >= bound), (p, slopes)
+
+
 def _mg_problem(kind):
     if kind == "cube":
         return w.cube_mms(12, 1, perturb=0.2)

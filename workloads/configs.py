@@ -45,6 +45,7 @@ class Problem:
     stencil_quantum: float = 0.0
     n_increments: int = 1
     face_rule: int = 0  # quad faces: 0 tensor Gauss-Legendre, 1 fan triangulation
+    stencil_grow: int = 0  # > 0: grow stencils that fail the pivot test by this many cells at a time
     meta: dict = field(default_factory=dict)
 
     @property
