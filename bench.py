@@ -296,7 +296,7 @@ def parse_seeds(s):
     return out
 
 
-KRYLOV = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0, "side": 0}  # Newton's Krylov options (set from the arguments)
+KRYLOV = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0, "side": 0, "gs_passes": 0}  # Newton's Krylov options (set from the arguments)
 
 
 def forcing_term(rn, rprev, eta_prev, eta_max, tol, r0):
@@ -323,7 +323,8 @@ def newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, max_newton, label)
         rprev = rn
         st = ctx.newton_solve(uu, tol=1e-300, eta=eta, max_newton=1, max_krylov=max_krylov, n_sweeps=2,
                               learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"],
-                              max_line_search=KRYLOV["line_search"], side=KRYLOV["side"])
+                              max_line_search=KRYLOV["line_search"], side=KRYLOV["side"],
+                              gs_passes=KRYLOV["gs_passes"])
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             tot[key] += st[key]
         ctx.residual(uu, R)
@@ -350,7 +351,8 @@ def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None, stepw
         # the predictor spans increments: one library call for all of them
         st = ctx.newton_solve(uu, tol=tol, eta=KRYLOV["eta"], max_krylov=max_krylov, n_sweeps=2, learned=learned,
                               check=False, n_increments=ninc, restart=KRYLOV["restart"],
-                              max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"], predictor=1, side=KRYLOV["side"])
+                              max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"], predictor=1, side=KRYLOV["side"],
+                              gs_passes=KRYLOV["gs_passes"])
         torch.cuda.synchronize()
         out.update({key: st[key] for key in ("newton_iters", "krylov_iters", "fallbacks", "rel_residual")})
         out["converged"] = bool(st["converged"])
@@ -365,7 +367,8 @@ def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None, stepw
         else:
             st = ctx.newton_solve(uu, tol=tol, eta=KRYLOV["eta"], max_krylov=max_krylov, n_sweeps=2,
                                   learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"],
-                                  max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"], side=KRYLOV["side"])
+                                  max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"], side=KRYLOV["side"],
+                              gs_passes=KRYLOV["gs_passes"])
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             out[key] += st[key]
         out["rel_residual"] = st["rel_residual"]
@@ -632,6 +635,9 @@ def main():
                     help="time-to-tolerance solves as one logged library Newton step per call, at most this many "
                          "steps per increment (0: one library call per increment)")
     ap.add_argument("--lz", type=float, default=1.0, help="z extent of the evaluation cube (cell aspect 1/lz)")
+    ap.add_argument("--gs-passes", type=int, default=None,
+                    help="classical Gram-Schmidt passes per Arnoldi step: 1 once (PETSc's default orthogonalisation; "
+                         "the default here), 2 twice (the default for the cantilever's 250-vector cycles)")
     ap.add_argument("--stencil-grow", type=int, default=0,
                     help="grow stencils that fail the pivot test by this many cells at a time (0: such a "
                          "stencil is an error)")
@@ -647,16 +653,17 @@ def main():
     # cycles, full Newton steps, the forcing term and the predictor (its sweeps-only
     # solve does not converge, so it runs the multigrid one)
     defaults = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0,
-                "solvers": "plain,multigrid,learned", "precond_levels": 8}
+                "solvers": "plain,multigrid,learned", "precond_levels": 8, "gs_passes": 1}
     if args.workload == "cantilever":
-        defaults.update(eta=0.5, restart=250, line_search=-1, forcing=1, predictor=1, solvers="multigrid")
+        defaults.update(eta=0.5, restart=250, line_search=-1, forcing=1, predictor=1, solvers="multigrid",
+                        gs_passes=2)
     elif args.workload == "column":  # the mass term keeps each step well conditioned
         defaults.update(eta=0.1, restart=60, line_search=-1, forcing=1, precond_levels=1)
     for key, val in defaults.items():
         if getattr(args, key) is None:
             setattr(args, key, val)
     KRYLOV.update(eta=args.eta, restart=args.restart, line_search=args.line_search, forcing=args.forcing,
-                  predictor=args.predictor, side=args.side)
+                  predictor=args.predictor, side=args.side, gs_passes=args.gs_passes)
     solvers = set(args.solvers.split(","))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built",
@@ -800,7 +807,8 @@ def main():
         solve = {"dynamics": column_steps(args, torch, ctx, prob, cen)}
     elif args.solve:
         solve = {"krylov": {"eta": args.eta, "forcing": args.forcing, "restart": args.restart,
-                            "line_search": args.line_search, "predictor": args.predictor, "side": args.side}}
+                            "line_search": args.line_search, "predictor": args.predictor, "side": args.side,
+                            "gs_passes": 1 if args.gs_passes == 1 else 2}}
         if "plain" in solvers:
             if prob.n_increments == 1:
                 newton(False)  # warm-up (allocates the Krylov workspace)

@@ -289,6 +289,10 @@ typedef struct {
                             prints it: the stopping test and rel_residual are then
                             those of the preconditioned residual M (rhs - J x)
                             against M rhs; not with learned (HOFV_EINVAL) */
+  int32_t gs_passes;     /* classical Gram-Schmidt passes per Arnoldi step: 0 or 2:
+                            twice (default); 1: once, the orthogonalisation PETSc's
+                            GMRES uses unless told otherwise (Sec. 4.1 names PETSc
+                            and no other); others HOFV_EINVAL */
 } hofv_krylov_opts;
 
 typedef struct {

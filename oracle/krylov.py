@@ -1,5 +1,6 @@
 """Right-preconditioned flexible GMRES(m) (Saad 1993) with classical Gram-Schmidt
-applied twice.
+applied twice, or once (passes = 1: the orthogonalisation PETSc's GMRES uses
+unless told otherwise, the library the paper's solver runs on).
 
 Test infrastructure (see package docstring).  The paper solves J du = -R with
 GMRES and a left preconditioner (eq. jfnk); right preconditioning in the
@@ -16,7 +17,7 @@ import numpy as np
 STALL = 0.99  # a cycle that keeps more than this fraction of the residual ends the solve
 
 
-def fgmres(A, b, M=None, x0=None, m=30, rtol=1e-8, maxit=1000, callback=None, stall=STALL):
+def fgmres(A, b, M=None, x0=None, m=30, rtol=1e-8, maxit=1000, callback=None, stall=STALL, passes=2):
     """A, M: callables on flat float64 vectors.  Returns (x, info dict).
 
     The solve also ends (info["stalled"]) when a full cycle reduced the true
@@ -55,9 +56,11 @@ def fgmres(A, b, M=None, x0=None, m=30, rtol=1e-8, maxit=1000, callback=None, st
             w = A(Z[j])
             h = V[: j + 1] @ w
             w = w - V[: j + 1].T @ h
-            h2 = V[: j + 1] @ w
-            w = w - V[: j + 1].T @ h2
-            H[: j + 1, j] = h + h2
+            if passes == 2:
+                h2 = V[: j + 1] @ w
+                w = w - V[: j + 1].T @ h2
+                h = h + h2
+            H[: j + 1, j] = h
             H[j + 1, j] = np.linalg.norm(w)
             if H[j + 1, j] > 0:
                 V[j + 1] = w / H[j + 1, j]
@@ -86,7 +89,7 @@ def fgmres(A, b, M=None, x0=None, m=30, rtol=1e-8, maxit=1000, callback=None, st
         beta = np.linalg.norm(r)
 
 
-def gmres_left(A, b, M, x0=None, m=30, rtol=1e-8, maxit=1000, stall=STALL):
+def gmres_left(A, b, M, x0=None, m=30, rtol=1e-8, maxit=1000, stall=STALL, passes=2):
     """Left-preconditioned GMRES(m) (eq. jfnk as printed): minimises
     ||M (b - A x)|| over x0 + K_k(M A, M r0), classical Gram-Schmidt twice; stops
     when ||M (b - A x)|| <= rtol ||M b|| (recomputed at every restart), after
@@ -114,7 +117,7 @@ def gmres_left(A, b, M, x0=None, m=30, rtol=1e-8, maxit=1000, stall=STALL):
         k = 0
         for j in range(m):
             w = M(A(V[j]))
-            for _ in range(2):
+            for _ in range(passes):
                 h = V[: j + 1] @ w
                 w = w - V[: j + 1].T @ h
                 H[: j + 1, j] += h

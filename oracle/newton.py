@@ -47,7 +47,7 @@ def forcing_term(rn, rprev, eta_prev, eta_max, tol, r0):
 
 def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
            maxit_newton=50, maxit_krylov=2000, n_increments=1, ls_max=10, precond_fn=None,
-           log=None, forcing=0, predictor=0, inertia=None, load_scale=1.0, side=0):
+           log=None, forcing=0, predictor=0, inertia=None, load_scale=1.0, side=0, passes=2):
     n, D = disc.n_cells, disc.dim
     if A is None:
         A = precond.assemble(disc, None if inertia is None else inertia[0])
@@ -93,9 +93,9 @@ def newton(disc, u0, A=None, colours=None, sweeps=2, tol=1e-8, eta=1e-4, m=30,
                 return ((residual(disc, uu + eps * vv, load, inertia) - Ru) / eps).ravel()
 
             if side == 1:
-                du, info = gmres_left(J, -R.ravel(), M, m=m, rtol=eta_k, maxit=maxit_krylov)
+                du, info = gmres_left(J, -R.ravel(), M, m=m, rtol=eta_k, maxit=maxit_krylov, passes=passes)
             else:
-                du, info = fgmres(J, -R.ravel(), M, m=m, rtol=eta_k, maxit=maxit_krylov)
+                du, info = fgmres(J, -R.ravel(), M, m=m, rtol=eta_k, maxit=maxit_krylov, passes=passes)
             stats["krylov"] += info["iters"]
             du = du.reshape(n, D)
             lam = 1.0

@@ -47,27 +47,38 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
 // consumer of the sum (the next kernel) adds the partials of every block in
 // the same fixed order, so all its blocks agree on the total bit for bit.
 
+// Threads per block of the streaming Krylov kernels.  The grid has at most
+// kRedParts blocks (one partial each), so 256-thread blocks would leave two
+// waves per SIMD; 1024-thread blocks keep enough loads in flight where the
+// registers allow (the 32-vector fused pass needs about 210 VGPRs and keeps 256).
+constexpr int kDotT = 1024;
+template <int NV>
+constexpr int gs_threads() { return NV <= 16 ? 1024 : kB; }
+
 // partials of sum_l V_i[l] w[l], i < nv <= NV
 template <int NV>
-__global__ __launch_bounds__(kB) void k_dot(int64_t n, int nv, const double* __restrict__ V, int64_t ld,
-                                            const double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double sred[(kB / 64) * NV], sout[NV];
+__global__ __launch_bounds__(kDotT) void k_dot(int64_t n, int nv, const double* __restrict__ V, int64_t ld,
+                                               const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sred[(kDotT / 64) * NV], sout[NV];
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-  for (int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x; l < n; l += (int64_t)gridDim.x * kB) {
+  for (int64_t l = (int64_t)blockIdx.x * kDotT + threadIdx.x; l < n; l += (int64_t)gridDim.x * kDotT) {
     const double x = w[l];
 #pragma unroll
     for (int i = 0; i < NV; ++i)
       if (i < nv) acc[i] += V[(int64_t)i * ld + l] * x;
   }
-  block_reduce<NV, kB>(acc, sred, sout);
+  block_reduce<NV, kDotT>(acc, sred, sout);
   if ((int)threadIdx.x < nv) part[(int64_t)threadIdx.x * kRedParts + blockIdx.x] = sout[threadIdx.x];
 }
 
-// out[i] = sum over the nb (<= 2 kB) partials of value i, for every thread of the block
-template <int NV>
+// out[i] = sum over the nb (<= kRedParts) partials of value i, for every
+// thread of an NT-thread block (thread t adds partials t, t + NT, ... in
+// that order, then the block reduces in its fixed order)
+template <int NV, int NT>
 __device__ __attribute__((always_inline)) inline void reduce_parts(int nb, int nv, const double* __restrict__ part, double* sred, double* out) {
+  static_assert(NT * 2 >= kRedParts, "at most two partials per thread");
   double a[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
@@ -75,11 +86,11 @@ __device__ __attribute__((always_inline)) inline void reduce_parts(int nb, int n
     if (i < nv) {
       const int t = threadIdx.x;
       if (t < nb) s = part[(int64_t)i * kRedParts + t];
-      if (t + kB < nb) s += part[(int64_t)i * kRedParts + t + kB];
+      if (t + NT < nb) s += part[(int64_t)i * kRedParts + t + NT];
     }
     a[i] = s;
   }
-  block_reduce<NV, kB>(a, sred, out);
+  block_reduce<NV, NT>(a, sred, out);
 }
 
 // out[i] (+)= the total of value i, i < nv (one block)
@@ -87,7 +98,7 @@ template <int NV>
 __global__ __launch_bounds__(kB) void k_dot_final(int nb, int nv, const double* __restrict__ part,
                                                   double* __restrict__ out, int accumulate) {
   __shared__ double sred[(kB / 64) * NV], sout[NV];
-  reduce_parts<NV>(nb, nv, part, sred, sout);
+  reduce_parts<NV, kB>(nb, nv, part, sred, sout);
   if ((int)threadIdx.x < nv) out[threadIdx.x] = accumulate ? out[threadIdx.x] + sout[threadIdx.x] : sout[threadIdx.x];
 }
 
@@ -95,18 +106,18 @@ __global__ __launch_bounds__(kB) void k_dot_final(int nb, int nv, const double* 
 // previous pass's V^T w), w -= V h, and the partials of the new V^T w
 // (NORM = 0) or of w.w (NORM = 1) into part_out.  Block 0 stores h at hout.
 // Each V_i[l] is read once for both products.
-template <int NV, int NORM>
-__global__ __launch_bounds__(kB) void k_gs_pass(int64_t n, int nv, const double* __restrict__ V, int64_t ld, int nb_in,
+template <int NV, int NORM, int NT = gs_threads<NV>()>
+__global__ __launch_bounds__(NT) void k_gs_pass(int64_t n, int nv, const double* __restrict__ V, int64_t ld, int nb_in,
                                                 const double* __restrict__ part_in, double* __restrict__ hout,
                                                 double* __restrict__ w, double* __restrict__ part_out) {
   constexpr int NO = NORM ? 1 : NV;
-  __shared__ double sred[(kB / 64) * NV], h[NV], sout[NO];
-  reduce_parts<NV>(nb_in, nv, part_in, sred, h);
+  __shared__ double sred[(NT / 64) * NV], h[NV], sout[NO];
+  reduce_parts<NV, NT>(nb_in, nv, part_in, sred, h);
   if (blockIdx.x == 0 && (int)threadIdx.x < nv) hout[threadIdx.x] = h[threadIdx.x];
   double acc[NO];
 #pragma unroll
   for (int i = 0; i < NO; ++i) acc[i] = 0.0;
-  for (int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x; l < n; l += (int64_t)gridDim.x * kB) {
+  for (int64_t l = (int64_t)blockIdx.x * NT + threadIdx.x; l < n; l += (int64_t)gridDim.x * NT) {
     double vv[NV];
     double s = 0.0;
 #pragma unroll
@@ -123,7 +134,7 @@ __global__ __launch_bounds__(kB) void k_gs_pass(int64_t n, int nv, const double*
       for (int i = 0; i < NV; ++i) acc[i] += vv[i] * x;
     }
   }
-  block_reduce<NO, kB>(acc, sred, sout);
+  block_reduce<NO, NT>(acc, sred, sout);
   if ((int)threadIdx.x < (NORM ? 1 : nv)) part_out[(int64_t)threadIdx.x * kRedParts + blockIdx.x] = sout[threadIdx.x];
 }
 
@@ -131,16 +142,16 @@ __global__ __launch_bounds__(kB) void k_gs_pass(int64_t n, int nv, const double*
 // w /= ||w|| (0 if ||w|| = 0); block 0 writes Hessenberg column j: h_i =
 // first + second pass (i <= j), h_{j+1} = ||w||, and zz (a learned output's
 // squared norm).
-__global__ __launch_bounds__(kB) void k_gs_scale(int64_t n, int j, int nb, const double* __restrict__ part_norm,
-                                                 double* __restrict__ w, double* __restrict__ hd, int ldh,
-                                                 double* __restrict__ H, double* __restrict__ zz) {
-  __shared__ double sred[kB / 64], sn[1];
-  reduce_parts<1>(nb, 1, part_norm, sred, sn);
+__global__ __launch_bounds__(kDotT) void k_gs_scale(int64_t n, int j, int nb, const double* __restrict__ part_norm,
+                                                    double* __restrict__ w, double* __restrict__ hd, int ldh,
+                                                    double* __restrict__ H, double* __restrict__ zz, int twice) {
+  __shared__ double sred[kDotT / 64], sn[1];
+  reduce_parts<1, kDotT>(nb, 1, part_norm, sred, sn);
   const double nrm = sqrt(sn[0]);
-  for (int64_t l = (int64_t)blockIdx.x * kB + threadIdx.x; l < n; l += (int64_t)gridDim.x * kB)
+  for (int64_t l = (int64_t)blockIdx.x * kDotT + threadIdx.x; l < n; l += (int64_t)gridDim.x * kDotT)
     w[l] = nrm > 0.0 ? w[l] / nrm : 0.0;
   if (blockIdx.x != 0) return;
-  for (int i = threadIdx.x; i <= j; i += kB) H[(int64_t)j * ldh + i] = hd[kHcol + i] + hd[kH2 + i];
+  for (int i = threadIdx.x; i <= j; i += kDotT) H[(int64_t)j * ldh + i] = twice ? hd[kHcol + i] + hd[kH2 + i] : hd[kHcol + i];
   if (threadIdx.x == 0) {
     hd[kHcol + j + 1] = sn[0];
     H[(int64_t)j * ldh + j + 1] = nrm;
@@ -206,7 +217,7 @@ static hofv_status dots(hofv_ctx* c, int64_t n, int nv, const double* V, int64_t
   double* part = c->dev.part;
   for (int c0 = 0; c0 < nv; c0 += kDotChunk) {
     const int nvc = std::min(kDotChunk, nv - c0);
-    HOFV_NV_DISPATCH(nvc, (k_dot<NVT><<<nb, kB, 0, st>>>(n, nvc, V + (int64_t)c0 * ld, ld, x, part),
+    HOFV_NV_DISPATCH(nvc, (k_dot<NVT><<<nb, kDotT, 0, st>>>(n, nvc, V + (int64_t)c0 * ld, ld, x, part),
                            k_dot_final<NVT><<<1, kB, 0, st>>>(nb, nvc, part, out + c0, accumulate)));
   }
   HOFV_HIP(c, hipGetLastError());
@@ -214,30 +225,35 @@ static hofv_status dots(hofv_ctx* c, int64_t n, int nv, const double* V, int64_t
 }
 
 // Arnoldi step j: w (= J z_j) is orthogonalised against V_0..V_j by classical
-// Gram-Schmidt applied twice and normalised; Hessenberg column j goes to
+// Gram-Schmidt applied twice (or once, passes = 1) and normalised; Hessenberg column j goes to
 // H[j ldh ..] (h_i = first + second pass), the Gram-Schmidt scalars to hd.
 // Up to kGsChunk basis vectors the passes are fused (dot; axpy + dot;
 // axpy + norm; scale: four launches, the basis read three times); longer
 // bases take chunked dots and separate axpys.
 static hofv_status cgs2(hofv_ctx* c, int64_t n, int j, const double* V, double* w, double* hd, double* H, int ldh,
-                        double* zz, hipStream_t st) {
+                        double* zz, hipStream_t st, int passes = 2) {
   const int nv = j + 1, nb = red_blocks(n);
   double* pA = c->dev.part;
   double* pB = pA + (size_t)kGsChunk * kRedParts;
   double* pC = pB + (size_t)kGsChunk * kRedParts;
-  if (nv <= kGsChunk) {
-    HOFV_NV_DISPATCH(nv, (k_dot<NVT><<<nb, kB, 0, st>>>(n, nv, V, n, w, pA),
-                          k_gs_pass<NVT, 0><<<nb, kB, 0, st>>>(n, nv, V, n, nb, pA, hd + kHcol, w, pB),
-                          k_gs_pass<NVT, 1><<<nb, kB, 0, st>>>(n, nv, V, n, nb, pB, hd + kH2, w, pC)));
+  if (nv <= kGsChunk && passes == 2) {
+    HOFV_NV_DISPATCH(nv, (k_dot<NVT><<<nb, kDotT, 0, st>>>(n, nv, V, n, w, pA),
+                          k_gs_pass<NVT, 0><<<nb, gs_threads<NVT>(), 0, st>>>(n, nv, V, n, nb, pA, hd + kHcol, w, pB),
+                          k_gs_pass<NVT, 1><<<nb, gs_threads<NVT>(), 0, st>>>(n, nv, V, n, nb, pB, hd + kH2, w, pC)));
+  } else if (nv <= kGsChunk) {  // one pass: dot; axpy + norm
+    HOFV_NV_DISPATCH(nv, (k_dot<NVT><<<nb, kDotT, 0, st>>>(n, nv, V, n, w, pA),
+                          k_gs_pass<NVT, 1><<<nb, gs_threads<NVT>(), 0, st>>>(n, nv, V, n, nb, pA, hd + kHcol, w, pC)));
   } else {
     hofv_status s;
     if ((s = dots(c, n, nv, V, n, w, hd + kHcol, 0, st))) return s;
     k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, nv, V, n, hd + kHcol, -1.0, w);
-    if ((s = dots(c, n, nv, V, n, w, hd + kH2, 0, st))) return s;
-    k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, nv, V, n, hd + kH2, -1.0, w);
-    k_dot<1><<<nb, kB, 0, st>>>(n, 1, w, n, w, pC);
+    if (passes == 2) {
+      if ((s = dots(c, n, nv, V, n, w, hd + kH2, 0, st))) return s;
+      k_multiaxpy<<<nblk(n), kB, 0, st>>>(n, nv, V, n, hd + kH2, -1.0, w);
+    }
+    k_dot<1><<<nb, kDotT, 0, st>>>(n, 1, w, n, w, pC);
   }
-  k_gs_scale<<<nb, kB, 0, st>>>(n, j, nb, pC, w, hd, ldh, H, zz);
+  k_gs_scale<<<nb, kDotT, 0, st>>>(n, j, nb, pC, w, hd, ldh, H, zz, passes == 2);
   HOFV_HIP(c, hipGetLastError());
   return HOFV_OK;
 }
@@ -304,6 +320,8 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
   if (c->nej.k > 0 && (left || o->learned))
     return fail(c, HOFV_EINVAL, "the near-exact Jacobian preconditioner needs right preconditioning, unlearned");
   if (o->side != 0 && o->side != 1) return fail(c, HOFV_EINVAL, "side must be 0 (right) or 1 (left)");
+  if (o->gs_passes < 0 || o->gs_passes > 2) return fail(c, HOFV_EINVAL, "gs_passes must be 0, 1 or 2");
+  const int passes = o->gs_passes == 1 ? 1 : 2;
   if ((s = host_norm(c, n, x, &xnorm, st))) return s;
   if (left) {
     if ((s = precond_dispatch(c, rhs, K.tmp2, sweeps, 0, st))) return s;
@@ -379,7 +397,7 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
         if (learned && (s = dots(c, n, 1, zj, n, zj, hd + kZz, 0, st))) return s;
         if ((s = jvp_impl(c, u, Ru, zj, w, 0.0, st))) return s;
       }
-      if ((s = cgs2(c, n, j, K.V, w, hd, K.Hd, m + 1, K.zz, st))) return s;
+      if ((s = cgs2(c, n, j, K.V, w, hd, K.Hd, m + 1, K.zz, st, passes))) return s;
       ++j;
       if (j - jp < kCheck && j < m && it + (j - jp) < maxit) continue;
       const int nq = j - jp;
@@ -694,6 +712,7 @@ hofv_status harvest_impl(hofv_ctx* c, const double* u, const double* starts, con
   ko.n_sweeps = o->n_sweeps > 0 ? o->n_sweeps : 2;
   ko.learned = 0;
   ko.side = 0;
+  ko.gs_passes = 0;
   hofv_status s = ensure_krylov(c, ko.restart);
   if (s) return s;
   // workspace: R(u), the current v, M v and the Newton state, released on return

@@ -70,6 +70,38 @@ def test_fgmres_parity_linear_system():
     assert np.linalg.norm(to_host(x) - xe) <= 1e-5 * np.linalg.norm(xe)
 
 
+@pytest.mark.parametrize("side", [0, 1])
+def test_one_pass_gram_schmidt_matches_oracle(side):
+    """gs_passes = 1 (classical Gram-Schmidt once, PETSc's default): the linear
+    solve reaches the dense solution, and Newton on the 8^3 p = 2 cube equals
+    the oracle's Newton with one pass (100 tol), right and left preconditioned."""
+    prob = w.cube_mms(8, 2, perturb=0.2)
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    ud = to_dev(np.zeros((n, 3)))
+    Ru = torch.empty_like(ud)
+    ctx.residual(ud, Ru)
+    b = w.random_state(n, 3, seed=7, scale=1.0)
+    x = torch.zeros_like(ud)
+    st = ctx.fgmres_solve(ud, Ru, to_dev(b), x, rtol=1e-7, max_iters=500, n_sweeps=2, side=side, gs_passes=1)
+    assert st["converged"]
+    xe = np.linalg.solve(ojac.jacobian_affine(disc), b.ravel()).reshape(n, 3)
+    assert np.linalg.norm(to_host(x) - xe) <= 1e-5 * np.linalg.norm(xe)
+    tol = 1e-9
+    u = torch.zeros((3, n), device=DEV, dtype=torch.float64)
+    st = ctx.newton_solve(u, tol=tol, eta=1e-6, side=side, gs_passes=1)
+    assert st["converged"]
+    ug = to_host(u)
+    R0 = np.linalg.norm(ores.residual(disc, np.zeros((n, 3))))
+    assert np.linalg.norm(ores.residual(disc, ug)) <= 1.01 * tol * R0
+    uo, _ = onw.newton(disc, np.zeros((n, 3)), tol=tol, eta=1e-6, side=side, passes=1)
+    assert np.linalg.norm(ug - uo) <= 100 * tol * np.linalg.norm(uo)
+    bad = _api().HofvError
+    with pytest.raises(bad):
+        ctx.fgmres_solve(ud, Ru, to_dev(b), x, gs_passes=3)
+
+
 def test_left_gmres_parity_linear_system():
     """side = 1 (eq. jfnk as printed): GMRES on M J x = M b with the FP32 sweeps
     as M; the stopping test is on the preconditioned residual, which the oracle's

@@ -280,14 +280,35 @@ def test_sgs_block_colour_update_equals_sequential_sweep():
     assert np.allclose(pc.sgs(A, col, r, 1), z, rtol=1e-13, atol=1e-15)
 
 
-def test_fgmres_matches_dense_solve():
+@pytest.mark.parametrize("passes", [1, 2])
+def test_fgmres_matches_dense_solve(passes):
     rng = np.random.default_rng(0)
     for n in (5, 40, 120):
         A = rng.standard_normal((n, n)) + n * np.eye(n)
         b = rng.standard_normal(n)
-        x, info = kr.fgmres(lambda v: A @ v, b, m=30, rtol=1e-12, maxit=2000)
+        x, info = kr.fgmres(lambda v: A @ v, b, m=30, rtol=1e-12, maxit=2000, passes=passes)
         assert info["converged"]
         assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-9)
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+def test_fgmres_minimises_over_its_krylov_space(passes):
+    """After k < m iterations of one cycle from x = 0 (M = I), ||b - A x|| is
+    the least-squares minimum over span{b, A b, ..., A^(k-1) b}, with Gram-Schmidt
+    applied once (PETSc's default) or twice; a Hessenberg column missing a
+    pass's projections, or a wrong norm, misses it."""
+    rng = np.random.default_rng(5)
+    n = 60
+    A = rng.standard_normal((n, n)) / np.sqrt(n) + 2.0 * np.eye(n)
+    b = rng.standard_normal(n)
+    for k in (3, 8):
+        x, info = kr.fgmres(lambda v: A @ v, b, m=20, rtol=1e-30, maxit=k, passes=passes)
+        K = np.stack([np.linalg.matrix_power(A, i) @ b for i in range(k)], axis=1)
+        c, *_ = np.linalg.lstsq(A @ K, b, rcond=None)
+        best = np.linalg.norm(b - A @ K @ c)
+        assert np.linalg.norm(b - A @ x) == pytest.approx(best, rel=1e-8)
+    x1, i1 = kr.gmres_left(lambda v: A @ v, b, lambda v: v, m=20, rtol=1e-30, maxit=8, passes=passes)
+    assert i1["rel"] * np.linalg.norm(b) == pytest.approx(best, rel=1e-8)
 
 
 def test_fgmres_exact_preconditioner_one_iteration():
