@@ -333,6 +333,14 @@ def build(problem, active=None) -> Discretisation:
 
 # ----------------------------------------------------------------------------- stresses
 
+def cell_gradient(disc: Discretisation, u: np.ndarray) -> np.ndarray:
+    """Post-processing (Sec. 5's stress errors): grad u at every cell centroid
+    from the cell stencil's least-squares gradient rows, G[i][j] = d u_j / d x_i
+    (cells without a stencil get 0)."""
+    st = np.maximum(disc.c_st, 0)
+    return np.einsum("cis,csj->cij", disc.c_D1, np.asarray(u, float)[st])
+
+
 def stress_linear(G, mu, lam):
     """eq. linearElastic with G[..., i, j] = d u_j / d x_i."""
     D = G.shape[-1]

@@ -369,20 +369,38 @@ def test_mms_orders_2d():
 @pytest.mark.slow
 def test_mms_orders_2d_with_twenty_surplus_nodes():
     """With n+ = 20, the remedy Sec. 5 applies to ill-conditioned structured 2D
-    grids, every refinement 8^2 -> 16^2 -> 32^2 shows the displacement orders
-    of the manufactured-solution study: >= 1.8 at p = 1 and 2, >= 3.5 at p = 3
-    (with the default n+ = 10 the p = 3 slope falls to 3.4 at 32^2 and 3.2 at
-    64^2 on these uniform grids)."""
-    for p, bound in ((1, 1.8), (2, 1.8), (3, 3.5)):
-        errs = []
+    grids, every refinement 8^2 -> 16^2 -> 32^2 shows the orders of the
+    manufactured-solution study: displacement >= 1.8 at p = 1 and 2, >= 3.5 at
+    p = 3 (with the default n+ = 10 the p = 3 slope falls to 3.4 at 32^2 and 3.2
+    at 64^2 on these uniform grids); stress at the centroids, from the cell
+    stencil's gradient, >= 0.9, 1.8, 2.7."""
+    for p, bound, sbound in ((1, 1.8, 0.9), (2, 1.8, 1.8), (3, 3.5, 2.7)):
+        errs, serrs = [], []
         for n in (8, 16, 32):
             prob = w.square_mms(n, p, n_plus=20)
             disc = rs.build(prob)
             u, _ = nw.newton(disc, np.zeros((disc.n_cells, 2)), tol=1e-11, eta=1e-6, m=60)
             ue = prob.loads.exact.value(disc.cen)
             errs.append(np.sqrt(np.mean(np.sum((u - ue) ** 2, axis=1))))
+            sig = rs.stress_linear(rs.cell_gradient(disc, u), disc.mu, disc.lam)
+            sige = rs.stress_linear(prob.loads.exact.grad(disc.cen), disc.mu, disc.lam)
+            serrs.append(np.sqrt(np.mean(np.sum((sig - sige) ** 2, axis=(1, 2)))))
         slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+        sslopes = np.log2(np.array(serrs[:-1]) / np.array(serrs[1:]))
         assert np.all(slopes >= bound), (p, slopes)
+        assert np.all(sslopes >= sbound), (p, sslopes)
+
+
+def test_cell_gradient_reproduces_linear_fields():
+    """The post-processing gradient is exact for fields of degree <= p (here a
+    random quadratic at p = 2 on a perturbed mesh): the same least-squares
+    exactness that pins the residual."""
+    prob = w.poly_patch(w.box_mesh((6, 5), perturb=0.2, seed=3), 2, 2, seed=9)
+    disc = rs.build(prob)
+    u = prob.loads.exact.value(disc.cen)
+    G = rs.cell_gradient(disc, u)
+    Ge = prob.loads.exact.grad(disc.cen)
+    assert np.abs(G - Ge).max() <= 1e-10 * np.abs(Ge).max()
 
 
 def _mg_problem(kind):
