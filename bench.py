@@ -64,14 +64,42 @@ def log(*a):
 _WORKER = {}
 
 
+def _named_problem(spec):
+    """The workloads the oracle is timed on: ("cube", n, p), the perturbed n^3
+    cube of the benchmark; ("square", n, p), the 2D n^2 manufactured problem;
+    ("cantilever", n, p), the 200x20x20 neo-Hookean cantilever."""
+    import workloads as w
+    name, n, p = spec
+    if name == "cube":
+        return w.cube_mms(n, p, perturb=0.2, seed=0)
+    if name == "square":
+        return w.square_mms(n, p)
+    if name == "cantilever":
+        return w.cantilever(p=p)
+    raise ValueError(name)
+
+
+def _oracle_state(prob):
+    """The throughput state: the manufactured field, or the cantilever's bent
+    state u_y = -0.3 x^2 / L; v standard normal (seed 1000)."""
+    from oracle import geometry as geo
+    m = prob.mesh
+    _, cen = geo.cell_volume_centroid(m.verts[m.cells])
+    if prob.loads.exact is not None:
+        u = prob.loads.exact.value(cen)
+    else:
+        u = np.zeros((m.n_cells, prob.dim))
+        u[:, 1] = -0.3 * cen[:, 0] ** 2 / m.lengths[0]
+    v = np.random.default_rng(1000).standard_normal((prob.dim, m.n_cells)).T.copy()
+    return u, v
+
+
 def _oracle_worker_setup(args):
     """Worker process: build the oracle's discretisation for its block of cells."""
     prob_spec, cells, u, v = args
-    import workloads as w
     from oracle import residual as ores
     from oracle import jacobian as ojac
-    name, n, p = prob_spec
-    prob = w.cube_mms(n, p, perturb=0.2, seed=0)
+    prob = _named_problem(prob_spec)
     disc = ores.build(prob, active=cells)
     Ru = ores.residual(disc, u)
     _WORKER.update(disc=disc, u=u, v=v, Ru=Ru, eps=ojac.default_eps(u, v))
@@ -84,6 +112,67 @@ def _oracle_worker_jvp(reps):
     for _ in range(reps):
         ojac.jvp(d["disc"], d["u"], d["v"], d["Ru"], d["eps"])
     return reps
+
+
+def cpu_study(args):
+    """The oracle's residual and J.v throughput on the host, one core and all
+    cores (one process per core on its own block of cells), on bounded samples
+    of each workload: the 2D 32^2 p = 2 square, the 64^3 p = 3 cube,
+    the 200x20x20 p = 2 cantilever and the 128^3 cube at p = 1 and 2 (1000
+    contiguous cells each; the oracle's setup for them is not timed)."""
+    import multiprocessing as mp
+    from oracle import jacobian as ojac
+    from oracle import residual as ores
+    named = {"square32p2": ("square", 32, 2), "cube64p3": ("cube", 64, 3), "cantilever": ("cantilever", 0, 2),
+             "cube128p1": ("cube", 128, 1), "cube128p2": ("cube", 128, 2)}
+    specs = [named[k] for k in args.cpu_workloads.split(",")]
+    nw = min(16, os.cpu_count() or 1)
+    rows = []
+    for spec in specs:
+        log(f"cpu study: {spec} setup")
+        t0 = time.perf_counter()
+        prob = _named_problem(spec)
+        n = prob.mesh.n_cells
+        u, v = _oracle_state(prob)
+        ns = min(1000, n)
+        rng = np.random.default_rng(0)
+        start = int(rng.integers(0, n - ns)) if n > ns else 0
+        cells = np.arange(start, start + ns)
+        disc = ores.build(prob, active=cells)
+        t_setup = time.perf_counter() - t0
+        eps = ojac.default_eps(u, v)
+        reps, t0 = 0, time.perf_counter()
+        while reps < 3 or time.perf_counter() - t0 < 5.0:
+            Ru = ores.residual(disc, u)
+            reps += 1
+        t_res = (time.perf_counter() - t0) / reps
+        reps, t0 = 0, time.perf_counter()
+        while reps < 3 or time.perf_counter() - t0 < 5.0:
+            ojac.jvp(disc, u, v, Ru, eps)
+            reps += 1
+        t_jvp = (time.perf_counter() - t0) / reps
+        row = {"workload": f"{spec[0]} n={spec[1] or '200x20x20'} p={spec[2]}", "n_cells": n, "sample_cells": ns,
+               "setup_seconds": t_setup, "residual_mcells_s_1core": ns / t_res / 1e6,
+               "jvp_mcells_s_1core": ns / t_jvp / 1e6}
+        if n > 1_000_000:
+            # every worker would rebuild the whole mesh's face geometry (6.2 M faces
+            # at 128^3) for its block: one core only
+            row["jvp_mcells_s_all_cores"] = None
+        elif n >= nw * ns:
+            blocks = [np.arange(b0, b0 + ns) for b0 in np.linspace(0, n - ns, nw).astype(np.int64)]
+            log(f"cpu study: {spec} one core done, {nw} worker setups")
+            with mp.get_context("spawn").Pool(nw) as pool:
+                for k, _ in enumerate(pool.imap_unordered(_oracle_worker_setup,
+                                                          [(spec, blk, u, v) for blk in blocks], chunksize=1)):
+                    log(f"cpu study: worker setup {k + 1}/{nw}")
+                t0 = time.perf_counter()
+                pool.map(_oracle_worker_jvp, [reps] * nw, chunksize=1)
+                t_all = time.perf_counter() - t0
+            row["jvp_mcells_s_all_cores"] = nw * ns * reps / t_all / 1e6
+            row["cores"] = nw
+        log(json.dumps(row))
+        rows.append(row)
+    print(json.dumps({"study": "cpu", "kind": "oracle", "host_cores": os.cpu_count(), "rows": rows}), flush=True)
 
 
 def cpu_baseline(prob, n_sample: int, u, v, ctx, torch, label, seed: int = 0, cube=None):
@@ -596,10 +685,12 @@ def main():
     ap.add_argument("--precond-levels", type=int, default=None,
                     help="multigrid levels built for the approximate Jacobian (1: sweeps only); the plain and "
                          "learned solves use the sweeps, a third solve the V-cycle")
-    ap.add_argument("--study", choices=["train", "eval", "nn"], default=None,
+    ap.add_argument("--study", choices=["train", "eval", "nn", "cpu"], default=None,
                     help="learned-preconditioner study instead of the benchmark: train a model on "
                          "--train-seeds (saved to --model), evaluate --model on one mesh, or time the "
                          "learned application alone (nn)")
+    ap.add_argument("--cpu-workloads", default="square32p2,cube64p3,cantilever,cube128p1,cube128p2",
+                    help="workloads of --study cpu")
     ap.add_argument("--train-seeds", default="0-49")
     ap.add_argument("--train-set", choices=["mixed", "cube", "cantilever"], default="cube",
                     help="training meshes of --study train: mixed = 2D squares and neo-Hookean beams (the learned-"
@@ -670,6 +761,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.study == "cpu":
+        cpu_study(args)
+        return
     if args.study:
         study(args)
         return

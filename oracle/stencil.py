@@ -20,10 +20,13 @@ def n_terms(dim: int, p: int) -> int:
 
 
 def nearest(points: np.ndarray, centroids: np.ndarray, size: int, quantum: float,
-            chunk: int = 256) -> np.ndarray:
-    """Stencil (m, size) of cell ids for every reference point (m, D), brute force."""
+            chunk: int | None = None) -> np.ndarray:
+    """Stencil (m, size) of cell ids for every reference point (m, D), brute force
+    (in chunks of points whose distance rows take about 400 MB)."""
     m = points.shape[0]
     n = centroids.shape[0]
+    if chunk is None:
+        chunk = max(1, min(256, 50_000_000 // max(n, 1)))
     if size > n:
         raise ValueError(f"stencil size {size} exceeds the number of cells {n}")
     ids = np.arange(n, dtype=np.int64)

@@ -11,7 +11,9 @@ import numpy as np
 import pytest
 
 import workloads as w
+from oracle import dynamics as ody
 from oracle import jacobian as ojac
+from oracle import nej as onej
 from oracle import newton as onw
 from oracle import precond as opc
 from oracle import residual as ores
@@ -225,3 +227,64 @@ def test_mms_error_falls_on_refined_split_meshes(p, min_slope):
     slope = np.log2(errs[0] / errs[1])
     print(f"split p={p} errors {errs} slope {slope:.2f}")
     assert slope >= min_slope
+
+
+@pytest.mark.parametrize("mk", [lambda: w.poly_patch(_m2(), 2, 2, seed=4),
+                                lambda: w.poly_patch(w.split_block_mesh((3, 3, 3), perturb=0.15, seed=4,
+                                                                        mode="tensor"), 2, 2, seed=4)])
+def test_near_exact_jacobian_on_split_meshes(mk):
+    """The near-exact Jacobian's product (App. C) on face-list meshes against
+    the oracle's assembled operator."""
+    prob = mk()
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n, D = disc.n_cells, disc.dim
+    v = w.random_state(n, D, seed=31, scale=1.0)
+    out = torch.empty((D, n), device=DEV, dtype=torch.float64)
+    ctx.nej_apply(to_dev(v), out)
+    torch.cuda.synchronize()
+    ref = (onej.operator(disc) @ v.ravel()).reshape(n, D)
+    assert np.linalg.norm(to_host(out) - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_symmetry_planes_on_a_split_mesh():
+    """x = 0 symmetry planes on a tensor-perturbed split mesh, a field
+    symmetric about them: R against the oracle and R = 0 for degree p."""
+    prob = w.poly_patch(w.split_block_mesh((4, 3, 3), perturb=0.15, seed=4, mode="tensor"), 2, 2, seed=6,
+                        symmetric=True)
+    disc = ores.build(prob)
+    assert disc.s_own.size > 0
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    for u in (w.random_state(n, 3, seed=3), prob.loads.exact.value(disc.cen)):
+        R = torch.empty((3, n), device=DEV, dtype=torch.float64)
+        ctx.residual(to_dev(u), R)
+        torch.cuda.synchronize()
+        Ro = ores.residual(disc, u)
+        Ff, Fd = ores.face_fluxes(disc, u)
+        scale = max(np.abs(Ff).max(), np.abs(Fd).max())
+        assert np.abs(to_host(R) - Ro).max() <= 1e-10 * scale
+    assert np.abs(to_host(R)).max() <= 1e-10 * scale  # the symmetric quadratic: zero residual
+
+
+def test_bdf2_steps_of_a_split_beam_match_oracle():
+    """A neo-Hookean beam of merged blocks set moving from rest by a sudden end
+    traction: three BDF2 steps on the GPU equal the oracle's."""
+    prob = w.cantilever(shape=(12, 2, 2), p=1, n_plus=10)
+    prob.mesh = w.split_block_mesh((6, 1, 1), lengths=(6.0, 1.0, 1.0))
+    prob.loads = w.fields.cantilever_loads(6.0, (0.0, -0.02, 0.01))
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob)
+    n = disc.n_cells
+    rho, dt = 1.0, 0.5
+    ctx.set_dynamics(rho, dt)
+    zero = torch.zeros((3, n), device=DEV, dtype=torch.float64)
+    ctx.dyn_reset(zero, zero)
+    u = zero.clone()
+    z = np.zeros((n, 3))
+    hist = (z, z, z, z)
+    for k in range(3):
+        st = ctx.dyn_step(u, tol=1e-10, eta=1e-8, max_line_search=-1, restart=96, max_krylov=400)
+        assert st["converged"]
+        uo, hist, _ = ody.step(disc, rho, dt, hist, m=96, maxit_krylov=400, ls_max=-1, tol=1e-10, eta=1e-8)
+        assert np.linalg.norm(to_host(u) - uo) <= 1e-7 * np.linalg.norm(uo)
