@@ -154,8 +154,10 @@ hofv_status hofv_set_mesh_simplices(hofv_ctx* ctx, int64_t n_verts, const double
  * points are (order_p + 2)^dim per simplex (see hofv_volume_qpoints_csr).
  * Cells with more than 2 dim faces give each face its own extrapolation item.
  * HOFV_EINVAL for malformed input (bad indices, a face cell equal on both
- * sides, a cell with fewer than dim + 1 faces or more than 255, non-positive
- * volume).  Called instead of hofv_set_mesh, once. */
+ * sides, a cell with fewer than dim + 1 faces or more than 255, a cell whose
+ * faces do not close, i.e. whose outward vector areas do not sum to zero to
+ * 1e-9 of their sizes: a missing or repeated face or a loop given the wrong
+ * way round; non-positive volume).  Called instead of hofv_set_mesh, once. */
 hofv_status hofv_set_mesh_polyhedra(hofv_ctx* ctx, int64_t n_verts, const double* verts, int64_t n_cells,
                                     int64_t n_faces, const int64_t* face_ptr, const int64_t* face_verts,
                                     const int64_t* face_cells);

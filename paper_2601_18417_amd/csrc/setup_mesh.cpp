@@ -330,7 +330,8 @@ hofv_status build_geometry(hofv_ctx* c) {
     for (int64_t e = 0; e < nc; ++e) c->nqv = std::max<int64_t>(c->nqv, nsimp[e] * npts);
     c->vq_pts.assign((size_t)c->vq_ptr[nc] * D, 0.0);
     c->vq_w.assign((size_t)c->vq_ptr[nc], 0.0);
-#pragma omp parallel for schedule(dynamic, 64) reduction(|| : bad)
+    bool open = false;
+#pragma omp parallel for schedule(dynamic, 64) reduction(|| : bad, open)
     for (int64_t e = 0; e < nc; ++e) {
       std::vector<int64_t> vs;
       for (auto& [f, sd] : side[e])
@@ -378,10 +379,31 @@ hofv_status build_geometry(hofv_ctx* c) {
               c->vq_w[q] = j2w[i] * j1w[j] * gvw[k] * det;
             }
       };
+      // the faces must close: their outward vector areas (1/2 sum (x_k - a) x
+      // (x_k+1 - a) per loop, the rotated edge in 2D) sum to zero for any
+      // polygonal surface, warped or not
+      double Ssum[3] = {0, 0, 0}, Aabs = 0;
       for (auto& [f, sd] : side[e]) {
         const int64_t b0 = c->fv_ptr[f], m = c->fv_ptr[f + 1] - b0;
         std::vector<int64_t> L(m);
         for (int64_t k = 0; k < m; ++k) L[k] = c->fv[sd ? b0 + m - 1 - k : b0 + k];
+        double Sf[3] = {0, 0, 0};
+        if (D == 2) {
+          Sf[0] = c->verts[(size_t)L[1] * 2 + 1] - c->verts[(size_t)L[0] * 2 + 1];
+          Sf[1] = -(c->verts[(size_t)L[1] * 2] - c->verts[(size_t)L[0] * 2]);
+        } else {
+          for (int64_t k = 0; k < m; ++k) {
+            double r0[3], r1[3], cr[3];
+            for (int d = 0; d < 3; ++d) {
+              r0[d] = c->verts[(size_t)L[k] * 3 + d] - apex[d];
+              r1[d] = c->verts[(size_t)L[(k + 1) % m] * 3 + d] - apex[d];
+            }
+            cross3(r0, r1, cr);
+            for (int d = 0; d < 3; ++d) Sf[d] += 0.5 * cr[d];
+          }
+        }
+        for (int d = 0; d < D; ++d) Ssum[d] += Sf[d];
+        Aabs += std::sqrt(Sf[0] * Sf[0] + Sf[1] * Sf[1] + Sf[2] * Sf[2]);
         if (D == 2) {
           const double* X[3] = {apex, &c->verts[(size_t)L[0] * 2], &c->verts[(size_t)L[1] * 2]};
           add_simplex(X);
@@ -399,7 +421,12 @@ hofv_status build_geometry(hofv_ctx* c) {
       c->vol[e] = V;
       for (int d = 0; d < D; ++d) c->cen[(size_t)e * D + d] = mom[d] / V;
       if (!(V > 0)) bad = true;
+      if (!(std::sqrt(Ssum[0] * Ssum[0] + Ssum[1] * Ssum[1] + Ssum[2] * Ssum[2]) <= 1e-9 * Aabs)) open = true;
     }
+    if (open)
+      return fail(c, HOFV_EINVAL,
+                  "the faces of a cell do not close (a missing or repeated face, or a loop whose normal points "
+                  "into its first cell)");
   } else {
   c->nqv = D == 2 ? nv1 * nv1 : nv1 * nv1 * nv1;
   c->vq_ptr.resize(nc + 1);

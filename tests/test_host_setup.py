@@ -393,3 +393,47 @@ def test_stencil_growth_matches_oracle():
         np.add.at(ora.T, np.searchsorted(ids, disc.f_st[j]), oc[j].T)
         assert np.abs(lib - ora).max() <= 1e-11 * np.abs(ora).max()
     assert grown_faces > 0
+
+
+def _poly_ctx(m):
+    mu, lam = w.lame_from_young(1.0, 0.3)
+    return api.Context(m.dim, 1, 10 if m.dim == 2 else 45, 1, 0, mu, lam, stencil_quantum=1e-9, host_only=True)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_face_list_meshes_that_do_not_close_are_refused(dim):
+    """hofv_set_mesh_polyhedra refuses a face list whose cells do not close: a
+    loop given the wrong way round, a missing face, a repeated face; and a face
+    whose two cells are the same."""
+    m = w.split_block_mesh((3, 3) if dim == 2 else (2, 2, 2), perturb=0.1, seed=1)
+
+    def attempt(fp, fv, fc):
+        ctx = _poly_ctx(m)
+        try:
+            ctx.set_mesh_poly(m.verts, fp, fv, fc, m.n_cells)
+        except api.HofvError as e:
+            return str(e)
+        return None
+
+    assert attempt(m.face_ptr, m.face_verts, m.face_cells) is None  # the mesh itself is accepted
+    inner = int(np.nonzero(m.face_cells[:, 1] >= 0)[0][0])
+    fv = m.face_verts.copy()
+    a, b = m.face_ptr[inner], m.face_ptr[inner + 1]
+    fv[a:b] = fv[a:b][::-1].copy()
+    assert "close" in attempt(m.face_ptr, fv, m.face_cells)
+    # a missing face (one of a merged cell's) and a repeated one
+    deg = np.bincount(m.face_cells[m.face_cells >= 0], minlength=m.n_cells)
+    big = int(np.argmax(deg))
+    f = int(np.nonzero((m.face_cells[:, 0] == big) | (m.face_cells[:, 1] == big))[0][0])
+    keep = np.ones(m.face_cells.shape[0], bool)
+    keep[f] = False
+    loops = [m.face_verts[m.face_ptr[i]:m.face_ptr[i + 1]] for i in range(keep.size)]
+    sub = [loops[i] for i in np.nonzero(keep)[0]]
+    fp = np.concatenate([[0], np.cumsum([len(x) for x in sub])])
+    assert "close" in attempt(fp, np.concatenate(sub), m.face_cells[keep])
+    rep = loops + [loops[f]]
+    fp = np.concatenate([[0], np.cumsum([len(x) for x in rep])])
+    assert "close" in attempt(fp, np.concatenate(rep), np.vstack([m.face_cells, m.face_cells[f:f + 1]]))
+    fc = m.face_cells.copy()
+    fc[inner, 1] = fc[inner, 0]
+    assert "bad face cells" in attempt(m.face_ptr, m.face_verts, fc)
