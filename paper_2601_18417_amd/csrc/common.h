@@ -96,6 +96,15 @@ struct DeviceTables {
   int32_t* p_nbr = nullptr;      // [2D][nc] neighbour positions (self where none)
   float* p_a = nullptr;          // [2D][nc] off-diagonal A_PN
   float* p_dinv = nullptr;       // [nc] 1 / A_PP
+  // cells with more than 2 dim face slots (face-list meshes): the kernels that
+  // walk a cell's slots give each of these a group of grp lanes (grp 2 dim
+  // >= ns), which take its slots in turn and add up by shuffles, and one lane
+  // to each other cell, for 2 dim slots; these cells come first
+  int64_t n_big = 0;
+  int grp = 1;
+  int32_t* c_order = nullptr;    // [nc] cells with more than 2 dim faces, then the others (ascending)
+  uint8_t* p_big = nullptr;      // [nc] by colour-major position: more than 2 dim faces
+  std::vector<int64_t> colour_big_end;  // per colour: end of its positions with more than 2 dim faces
   float* p_r = nullptr;          // [D][nc]
   float* p_z = nullptr;          // [D][nc]
   float* p_diag = nullptr;       // [nc] A_PP (multigrid residual)

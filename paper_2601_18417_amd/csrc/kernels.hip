@@ -463,7 +463,12 @@ __global__ __launch_bounds__(kBlock) void k_face_sym_nh(int64_t nfs, int Sh, con
   for (int j = 0; j < 3; ++j) Fs[(int64_t)j * nfs + f] = t[j];
 }
 
-// NST > 0: NST face slots per cell known at compile time; 0: ns at run time
+// NST > 0: NST face slots per cell, thread k takes cell k.  NST = 0 (face-list
+// meshes with ns > 2 D slots, of which a cell uses its first ones): order[]
+// lists the n_big cells with more than 2 D faces first; the
+// first n_big g threads take those, g lanes a cell (lane l: slots l, l + g,
+// ..., added up by shuffles within the group), the others one cell each over
+// its first 2 D slots.
 template <int D, int NST>
 __global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, int ns, const int32_t* __restrict__ cf,
                                                       const double* __restrict__ F, const double* __restrict__ src,
@@ -471,24 +476,55 @@ __global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, int
                                                       const double* __restrict__ eps, const double* __restrict__ ug,
                                                       const double* __restrict__ dm, const double* __restrict__ ds,
                                                       const double* __restrict__ Fs, int64_t nfs,
-                                                      double* __restrict__ R) {
+                                                      double* __restrict__ R, const int32_t* __restrict__ order,
+                                                      int64_t n_big, int g) {
   constexpr int W = D == 3 ? 4 : 2;
-  const int NS = NST > 0 ? NST : ns;
-  const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (P >= nc) return;
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double acc[D];
 #pragma unroll
-  for (int c = 0; c < D; ++c) acc[c] = load * src[(int64_t)c * nc + P];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int32_t k = cf[(int64_t)s * nc + P];
-    if (k == kNoFace) continue;
+  for (int c = 0; c < D; ++c) acc[c] = 0.0;
+  auto take = [&](int32_t f) {
+    if (f == kNoFace) return;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      if (k >= nf) acc[c] += Fs[(int64_t)c * nfs + (k - nf)];  // symmetry face
-      else if (k >= 0) acc[c] += F[(int64_t)c * nf + k];
-      else acc[c] -= F[(int64_t)c * nf + ~k];
+      if (f >= nf) acc[c] += Fs[(int64_t)c * nfs + (f - nf)];  // symmetry face
+      else if (f >= 0) acc[c] += F[(int64_t)c * nf + f];
+      else acc[c] -= F[(int64_t)c * nf + ~f];
     }
+  };
+  int64_t P;
+  const int64_t nbt = NST > 0 ? 0 : n_big * g;  // threads of the many-faced cells
+  if (NST == 0 && k < nbt) {
+    P = order[k / g];
+    const int l = (int)(k % g);
+    // a lane's slot ids are loaded together before the fluxes they point to
+    for (int s0 = l; s0 < ns; s0 += 8 * g) {
+      int32_t f[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) f[j] = s0 + j * g < ns ? cf[(int64_t)(s0 + j * g) * nc + P] : kNoFace;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) take(f[j]);
+    }
+    // groups are aligned within the wavefront (g divides 64 and every lane of
+    // a group is below nbt), so the butterfly stays inside the group
+    for (int o = g / 2; o > 0; o >>= 1)
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
+    if (l != 0) return;
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] += load * src[(int64_t)c * nc + P];
+  } else {
+    const int64_t i = NST > 0 ? k : k - nbt + n_big;
+    if (i >= nc) return;
+    P = NST > 0 ? i : (int64_t)order[i];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] = load * src[(int64_t)c * nc + P];
+    constexpr int S0 = NST > 0 ? NST : 2 * D;
+    int32_t f0[S0];
+#pragma unroll
+    for (int s = 0; s < S0; ++s) f0[s] = cf[(int64_t)s * nc + P];
+#pragma unroll
+    for (int s = 0; s < S0; ++s) take(f0[s]);
   }
 #pragma unroll
   for (int c = 0; c < D; ++c) {
@@ -573,23 +609,88 @@ __global__ __launch_bounds__(kBlock) void k_pc_in(int64_t nc, const int32_t* __r
   }
 }
 
+// acc -= sum over a row's slots of a_s z[nbr_s]: NST slots known at compile
+// time, or (NST = 0) 2 D slots and then slots 2 D .. nsb - 1 when nsb > 0,
+// 8 a step; each step loads its slot entries together before the gathers.
+// Unused slots hold the row itself with a zero coefficient.
+template <int D, int NST>
+__device__ inline void slot_products(float (&acc)[D], int64_t i, int64_t n, int nsb, const int32_t* __restrict__ nbr,
+                                     const float* __restrict__ a, const float* __restrict__ z) {
+  constexpr int S0 = NST > 0 ? NST : 2 * D;
+  int32_t N0[S0];
+  float a0[S0];
+#pragma unroll
+  for (int s = 0; s < S0; ++s) {
+    N0[s] = nbr[(int64_t)s * n + i];
+    a0[s] = a[(int64_t)s * n + i];
+  }
+#pragma unroll
+  for (int s = 0; s < S0; ++s)
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] -= a0[s] * z[(int64_t)c * n + N0[s]];
+  if (NST > 0) return;
+  for (int s0 = S0; s0 < nsb; s0 += 8) {
+    int32_t N[8];
+    float aa[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const bool in = s0 + j < nsb;
+      N[j] = in ? nbr[(int64_t)(s0 + j) * n + i] : (int32_t)i;
+      aa[j] = in ? a[(int64_t)(s0 + j) * n + i] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] -= aa[j] * z[(int64_t)c * n + N[j]];
+  }
+}
+
+// NST > 0: one lane a position, NST slots.  NST = 0 (ns > 2 D slots): the
+// positions begin .. big_end - 1 (cells with more than 2 D faces) take g lanes
+// each (lane l: slots l, l + g, ..., added up by shuffles within the group),
+// the others one lane over their first 2 D slots
 template <int D, int NST>
 __global__ __launch_bounds__(kBlock) void k_pc_sweep(int64_t nc, int64_t begin, int64_t end, int ns,
                                                      const int32_t* __restrict__ nbr, const float* __restrict__ a,
                                                      const float* __restrict__ dinv, const float* __restrict__ r32,
-                                                     float* __restrict__ z32) {
-  const int NS = NST > 0 ? NST : ns;
-  const int64_t i = begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= end) return;
+                                                     float* __restrict__ z32, int64_t big_end, int g) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t nbt = NST > 0 ? 0 : (big_end - begin) * g;
   float acc[D];
+  int64_t i;
+  if (NST == 0 && k < nbt) {
+    i = begin + k / g;
+    const int l = (int)(k % g);
 #pragma unroll
-  for (int c = 0; c < D; ++c) acc[c] = r32[(int64_t)c * nc + i];
+    for (int c = 0; c < D; ++c) acc[c] = 0.0f;
+    for (int s0 = l; s0 < ns; s0 += 8 * g) {
+      int32_t N[8];
+      float aa[8];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int32_t N = nbr[(int64_t)s * nc + i];
-    const float aa = a[(int64_t)s * nc + i];
+      for (int j = 0; j < 8; ++j) {
+        const bool in = s0 + j * g < ns;
+        N[j] = in ? nbr[(int64_t)(s0 + j * g) * nc + i] : (int32_t)i;
+        aa[j] = in ? a[(int64_t)(s0 + j * g) * nc + i] : 0.0f;
+      }
 #pragma unroll
-    for (int c = 0; c < D; ++c) acc[c] -= aa * z32[(int64_t)c * nc + N];
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int c = 0; c < D; ++c) acc[c] -= aa[j] * z32[(int64_t)c * nc + N[j]];
+    }
+    // groups are aligned within the wavefront (g divides 64, all lanes of a
+    // group are below nbt)
+    for (int o = g / 2; o > 0; o >>= 1)
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
+    if (l != 0) return;
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] += r32[(int64_t)c * nc + i];
+  } else {
+    i = begin + (NST > 0 ? k : k - nbt + (big_end - begin));
+    if (i >= end) return;
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] = r32[(int64_t)c * nc + i];
+    slot_products<D, NST>(acc, i, nc, 0, nbr, a, z32);
   }
   const float di = dinv[i];
 #pragma unroll
@@ -608,26 +709,20 @@ __global__ __launch_bounds__(kBlock) void k_pc_out(int64_t nc, const int32_t* __
 
 // ---- multigrid V-cycle on the approximate Jacobian (FP32, D right-hand sides)
 
-// t = r - A z on level 0 (2D-neighbour rows in colour-major order)
+// t = r - A z on level 0 (slot rows in colour-major order); NST = 0 (ns > 2 D
+// slots): rows flagged in big walk all ns slots, the others the first 2 D
 template <int D, int NST>
 __global__ __launch_bounds__(kBlock) void k_mg_res0(int64_t n, int ns, const int32_t* __restrict__ nbr,
                                                     const float* __restrict__ a, const float* __restrict__ diag,
                                                     const float* __restrict__ r, const float* __restrict__ z,
-                                                    float* __restrict__ t) {
-  const int NS = NST > 0 ? NST : ns;
+                                                    float* __restrict__ t, const uint8_t* __restrict__ big) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const float di = diag[i];
   float acc[D];
 #pragma unroll
   for (int c = 0; c < D; ++c) acc[c] = r[(int64_t)c * n + i] - di * z[(int64_t)c * n + i];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int32_t N = nbr[(int64_t)s * n + i];
-    const float aa = a[(int64_t)s * n + i];
-#pragma unroll
-    for (int c = 0; c < D; ++c) acc[c] -= aa * z[(int64_t)c * n + N];
-  }
+  slot_products<D, NST>(acc, i, n, NST > 0 || !big[i] ? 0 : ns, nbr, a, z);
 #pragma unroll
   for (int c = 0; c < D; ++c) t[(int64_t)c * n + i] = acc[c];
 }
@@ -839,11 +934,11 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
   if (t.ns == 2 * D)
     TIMED("k_cell_sum", (k_cell_sum<D, 2 * D><<<blocks_for(nc), kBlock, 0, st>>>(
                             nc, nf, t.ns, t.c_faces, t.flux, t.c_src, c->load, Ru, eps, u, t.dyn_m, t.dyn_s,
-                            t.sym_flux, t.sym_nf, R)));
-  else
-    TIMED("k_cell_sum", (k_cell_sum<D, 0><<<blocks_for(nc), kBlock, 0, st>>>(
+                            t.sym_flux, t.sym_nf, R, nullptr, 0, 1)));
+  else  // face-list meshes with cells of more than 2 dim faces
+    TIMED("k_cell_sum", (k_cell_sum<D, 0><<<blocks_for(nc + t.n_big * (t.grp - 1)), kBlock, 0, st>>>(
                             nc, nf, t.ns, t.c_faces, t.flux, t.c_src, c->load, Ru, eps, u, t.dyn_m, t.dyn_s,
-                            t.sym_flux, t.sym_nf, R)));
+                            t.sym_flux, t.sym_nf, R, t.c_order, t.n_big, t.grp)));
   HOFV_HIP(c, hipGetLastError());
   return HOFV_OK;
 }
@@ -976,10 +1071,11 @@ static void sgs_sweeps(hofv_ctx* c, int sweeps, hipStream_t st) {
         const int64_t b = t.colour_start[col], e = t.colour_start[col + 1];
         if (e > b && t.ns == 2 * D)
           TIMED("k_pc_sweep", (k_pc_sweep<D, 2 * D><<<blocks_for(e - b), kBlock, 0, st>>>(
-                                  nc, b, e, t.ns, t.p_nbr, t.p_a, t.p_dinv, t.p_r, t.p_z)));
-        else if (e > b)
-          TIMED("k_pc_sweep", (k_pc_sweep<D, 0><<<blocks_for(e - b), kBlock, 0, st>>>(nc, b, e, t.ns, t.p_nbr, t.p_a,
-                                                                                       t.p_dinv, t.p_r, t.p_z)));
+                                  nc, b, e, t.ns, t.p_nbr, t.p_a, t.p_dinv, t.p_r, t.p_z, b, 1)));
+        else if (e > b)  // the colour's cells with more than 2 dim faces come first
+          TIMED("k_pc_sweep",
+                (k_pc_sweep<D, 0><<<blocks_for(e - b + (t.colour_big_end[col] - b) * (t.grp - 1)), kBlock, 0, st>>>(
+                    nc, b, e, t.ns, t.p_nbr, t.p_a, t.p_dinv, t.p_r, t.p_z, t.colour_big_end[col], t.grp)));
       }
   }
 }
@@ -1049,9 +1145,9 @@ static void mg_vcycle(hofv_ctx* c, int l, int sweeps, hipStream_t st) {
   if (l > 0) k_fill_f<<<blocks_for((int64_t)D * m.n), kBlock, 0, st>>>((int64_t)D * m.n, 0.0f, z);
   mg_smooth<D>(c, l, sweeps, st);
   if (l == 0 && t.ns == 2 * D)
-    k_mg_res0<D, 2 * D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.ns, t.p_nbr, t.p_a, t.p_diag, r, z, m.t);
+    k_mg_res0<D, 2 * D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.ns, t.p_nbr, t.p_a, t.p_diag, r, z, m.t, nullptr);
   else if (l == 0)
-    k_mg_res0<D, 0><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.ns, t.p_nbr, t.p_a, t.p_diag, r, z, m.t);
+    k_mg_res0<D, 0><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.ns, t.p_nbr, t.p_a, t.p_diag, r, z, m.t, t.p_big);
   else
     mg_res<D>(m.n, m.ptr, m.col, m.val, m.diag, r, z, m.t, m.g_a, st);
   DeviceTables::MgLevel& q = t.mg[l + 1];

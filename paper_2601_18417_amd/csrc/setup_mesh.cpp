@@ -266,7 +266,7 @@ hofv_status build_topology_poly(hofv_ctx* c, int64_t n_faces, const int64_t* fac
   std::sort(inner.begin(), inner.end(), by_owner);
   std::sort(bnd.begin(), bnd.end(), by_owner);
   c->poly = true;
-  c->NS = ns;
+  c->NS = std::max(ns, 2 * D);  // cells with fewer faces leave slots empty, as simplices do
   c->n_internal = (int64_t)inner.size();
   c->faces.clear();
   c->fv_ptr.assign(1, 0);

@@ -469,9 +469,20 @@ hofv_status build_tables(hofv_ctx* c) {
     colour[P] = col;
     ncol = std::max(ncol, col + 1);
   }
+  // cells using slots beyond 2 dim (slots are numbered in the order a cell's
+  // faces come, so these are exactly the cells with more than 2 dim faces):
+  // within a colour they come first, where the sweeps give them lane groups
+  // (the order inside a colour does not change a sweep)
+  std::vector<uint8_t> big(nc, 0);
+  for (const hofv_ctx::Face& F : c->faces) {
+    if (F.sown >= 2 * D) big[F.own] = 1;
+    if (F.nei >= 0 && F.snei >= 2 * D) big[F.nei] = 1;
+  }
   std::vector<int32_t> perm(nc);
   std::iota(perm.begin(), perm.end(), 0);
-  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return colour[a] < colour[b]; });
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+    return colour[a] != colour[b] ? colour[a] < colour[b] : big[a] > big[b];
+  });
   std::vector<int32_t> pos(nc);
   for (int64_t i = 0; i < nc; ++i) pos[perm[i]] = (int32_t)i;
   c->dev.colour_start.assign(ncol + 1, 0);
@@ -671,6 +682,26 @@ hofv_status build_tables(hofv_ctx* c) {
   UP(t.c_src, src);
   UP(t.p_perm, perm);
   UP(t.p_nbr, pnbr);
+  if (NS > 2 * D) {
+    std::vector<int32_t> order;
+    std::vector<uint8_t> pbig(nc, 0);
+    for (int pass = 1; pass >= 0; --pass)
+      for (int64_t P = 0; P < nc; ++P)
+        if (big[P] == pass) order.push_back((int32_t)P);
+    for (int64_t i = 0; i < nc; ++i) pbig[i] = big[perm[i]];
+    t.colour_big_end.assign(ncol, 0);
+    for (int k = 0; k < ncol; ++k) {
+      int64_t e = t.colour_start[k];
+      while (e < t.colour_start[k + 1] && pbig[e]) ++e;
+      t.colour_big_end[k] = e;
+    }
+    t.n_big = 0;
+    for (int64_t P = 0; P < nc; ++P) t.n_big += big[P];
+    t.grp = 1;
+    while (t.grp * 2 * D < NS && t.grp < 64) t.grp *= 2;
+    UP(t.c_order, order);
+    UP(t.p_big, pbig);
+  }
   UP(t.p_a, pa);
   UP(t.p_dinv, pdinv);
   UP(t.p_diag, pdiag);

@@ -288,3 +288,54 @@ def test_bdf2_steps_of_a_split_beam_match_oracle():
         assert st["converged"]
         uo, hist, _ = ody.step(disc, rho, dt, hist, m=96, maxit_krylov=400, ls_max=-1, tol=1e-10, eta=1e-8)
         assert np.linalg.norm(to_host(u) - uo) <= 1e-7 * np.linalg.norm(uo)
+
+
+# face-list copies of ordinary cells: at most 2 dim faces per cell, so the
+# slot-walking kernels take the short-table form (tetrahedra: 4 slots of 6,
+# triangles: 3 of 4) or the fixed 2 dim-slot form (hexahedra, quads)
+FACE_LIST = {
+    "tets_p1": lambda: w.poly_patch(w.face_list_mesh(w.tet_mesh((4, 4, 4), perturb=0.15, seed=2)), 1, 2, seed=3),
+    "tets_p2": lambda: w.poly_patch(w.face_list_mesh(w.tet_mesh((4, 4, 4), perturb=0.15, seed=2)), 2, 3, seed=3),
+    "tris_p3": lambda: w.poly_patch(w.face_list_mesh(w.tri_mesh((12, 11), perturb=0.2, seed=2)), 3, 3, seed=3),
+    "hexes_p2": lambda: w.poly_patch(w.face_list_mesh(w.box_mesh((7, 7, 7), perturb=0.2, seed=7, mode="tensor")),
+                                     2, 3, seed=3),
+    "quads_p2": lambda: w.poly_patch(w.face_list_mesh(w.box_mesh((17, 16), perturb=0.2, seed=7)), 2, 3, seed=3),
+}
+# every mesh has more than 256 cells, so that a V-cycle has a coarse level
+
+
+@pytest.mark.parametrize("name", list(FACE_LIST))
+def test_face_lists_of_ordinary_cells(name):
+    """R, J.v and both preconditioners against the oracle's face-list build."""
+    prob = FACE_LIST[name]()
+    assert prob.mesh.n_cells > 256
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob, precond_levels=8)
+    n, D = disc.n_cells, disc.dim
+    fc = prob.mesh.face_cells
+    assert np.bincount(fc[fc >= 0], minlength=n).max() <= 2 * D
+    u = w.random_state(n, D, seed=11)
+    ud = to_dev(u)
+    R = torch.empty_like(ud)
+    ctx.residual(ud, R)
+    torch.cuda.synchronize()
+    Ro = ores.residual(disc, u)
+    assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro)
+    v = w.random_state(n, D, seed=2, scale=1.0)
+    eps = ojac.default_eps(u, v)
+    Jv = torch.empty_like(ud)
+    ctx.jvp(ud, R, to_dev(v), Jv, eps=eps)
+    torch.cuda.synchronize()
+    Jo = ojac.jvp(disc, u, v, eps=eps)
+    floor = 8 * 2.0 ** -52 * np.linalg.norm(_flux_scale(disc, u)) / eps
+    assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo) + floor
+    A = opc.assemble(disc)
+    col = opc.greedy_colours(A)
+    r = w.random_state(n, D, seed=3, scale=1.0)
+    z = torch.empty((D, n), device=DEV, dtype=torch.float64)
+    for mg in (False, True):
+        ctx.set_multigrid(mg)
+        ctx.precond_apply(to_dev(r), z, n_sweeps=2)
+        torch.cuda.synchronize()
+        z64 = opc.vcycle(opc.hierarchy(A), r, 2) if mg else opc.sgs(A, col, r, 2)
+        assert np.abs(to_host(z) - z64).max() <= (1e-4 if mg else 1e-5) * np.abs(z64).max(), mg

@@ -118,3 +118,20 @@ def test_face_list_mesh_reproduces_the_hex_discretisation():
         u = w.random_state(base.n_cells, 3, seed=8)
         Rh, Rp = rs.residual(dh, u), rs.residual(dp, u)
         assert np.abs(Rh - Rp).max() <= 1e-12 * np.abs(Rh).max()
+
+
+@pytest.mark.parametrize("kind,p", [("tris", 1), ("tris", 2), ("tris", 3), ("tets", 1)])
+def test_face_list_copy_of_simplices_reproduces_the_simplex_discretisation(kind, p):
+    """Triangles and tetrahedra given as face lists match the simplex path to
+    rounding where the face rules coincide: Gauss-Legendre edge rules are
+    symmetric, and at p = 1 a triangle face has one point, its centroid.  (With
+    more points a triangle face's conical-product rule depends on the vertex it
+    starts from, which differs between the two paths: an equally exact rule,
+    but the boundary constraints sit at its points.)"""
+    base = (w.tri_mesh((5, 4), perturb=0.2, seed=2) if kind == "tris"
+            else w.tet_mesh((3, 3, 3), perturb=0.15, seed=2))
+    a = w.poly_patch(base, p, p + 1, seed=3)
+    b = w.poly_patch(w.face_list_mesh(base), p, p + 1, seed=3)
+    u = w.random_state(base.n_cells, base.dim, seed=8)
+    Ra, Rb = rs.residual(rs.build(a), u), rs.residual(rs.build(b), u)
+    assert np.abs(Ra - Rb).max() <= 1e-12 * np.abs(Ra).max()

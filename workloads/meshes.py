@@ -249,3 +249,47 @@ def split_block_mesh(coarse_shape, lengths=None, origin=None, perturb: float = 0
     return PolyMesh(dim, fine.verts, face_ptr, np.ascontiguousarray(face_verts, np.int64),
                     np.ascontiguousarray(np.stack([c0, c1], axis=1), np.int64), nxt, fine.shape,
                     fine.lengths, fine.origin, cell_of)
+
+
+_TRI_EDGES = np.array([[0, 1], [1, 2], [2, 0]])
+_TET_FACES = np.array([[0, 2, 1], [0, 1, 3], [1, 2, 3], [0, 3, 2]])
+
+
+def face_list_mesh(mesh: Mesh) -> PolyMesh:
+    """The same cells (triangles, quads, tetrahedra or hexahedra, cell i stays
+    cell i) given as a face list.  Each face's loop is turned, where needed,
+    so that its right-hand normal points away from its first cell's vertex
+    mean; faces are listed by (first cell, second cell)."""
+    dim, nv = mesh.dim, mesh.cells.shape[1]
+    loops = {(2, 3): _TRI_EDGES, (2, 4): _QUAD_EDGES, (3, 4): _TET_FACES, (3, 8): _HEX_LOOPS}[(dim, nv)]
+    nl = loops.shape[0]
+    flat = mesh.cells[:, loops].reshape(mesh.n_cells * nl, -1).copy()
+    owner = np.repeat(np.arange(mesh.n_cells), nl)
+    X = mesh.verts[flat]
+    if dim == 2:
+        d = X[:, 1] - X[:, 0]
+        normal = np.stack([d[:, 1], -d[:, 0]], axis=1)
+    else:
+        normal = np.cross(X[:, 1] - X[:, 0], X[:, 2] - X[:, 0])
+    away = X.mean(axis=1) - mesh.verts[mesh.cells].mean(axis=1)[owner]
+    turn = np.einsum("fd,fd->f", normal, away) < 0
+    flat[turn] = flat[turn][:, ::-1]
+    keys = np.sort(flat, axis=1)
+    _, inv, counts = np.unique(keys, axis=0, return_inverse=True, return_counts=True)
+    inv = inv.ravel()
+    first = np.full(counts.size, -1, np.int64)
+    second = np.full(counts.size, -1, np.int64)
+    for r in range(flat.shape[0]):
+        if first[inv[r]] < 0:
+            first[inv[r]] = r
+        else:
+            second[inv[r]] = r
+    c0 = owner[first]
+    c1 = np.where(second >= 0, owner[np.maximum(second, 0)], -1)
+    order = np.lexsort((c1, c0))
+    first, c0, c1 = first[order], c0[order], c1[order]
+    nvf = flat.shape[1]
+    return PolyMesh(dim, mesh.verts, np.arange(first.size + 1, dtype=np.int64) * nvf,
+                    np.ascontiguousarray(flat[first].reshape(-1), np.int64),
+                    np.ascontiguousarray(np.stack([c0, c1], axis=1), np.int64), mesh.n_cells, mesh.shape,
+                    mesh.lengths, mesh.origin, np.arange(mesh.n_cells))
