@@ -67,7 +67,7 @@ struct DeviceTables {
   uint16_t* c_local = nullptr;    // [S][nc]
   int32_t* c_cell = nullptr;      // [n_items] cell of each extrapolation item (Morton order)
   int32_t ns = 0;                 // face slots per cell
-  int32_t nsi = 0;                // face slots per extrapolation item: ns, or 1 (one item per cell face)
+  int32_t nsi = 0;                // face slots per extrapolation item: the most faces of a cell, or 1 (one item per cell face)
   int64_t n_items = 0;            // extrapolation items
   // faces
   double* f_coef = nullptr;      // folded: [S][D][nf]; per-point: [S][nq][D][nf]
@@ -82,7 +82,7 @@ struct DeviceTables {
   int32_t* c_faces = nullptr;    // [2D][nc] slot codes
   double* c_src = nullptr;       // [D][nc] constant sources at load 1
   // transient
-  double* ustar = nullptr;       // [2D][D][nc] by extrapolation item
+  double* ustar = nullptr;       // [nsi][D][n_items]
   double* flux = nullptr;        // [D][nf]
   double* w = nullptr;           // [nc][4 | 2] padded gather copy of u (or u + eps v)
   double* scratch = nullptr;     // reduction partials

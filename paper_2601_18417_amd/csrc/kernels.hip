@@ -871,13 +871,18 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
   const bool nh = c->prm.material == HOFV_NEO_HOOKEAN;
   const bool fold = !nh && c->prm.fold_quadrature;
   const int64_t ni = t.n_items;  // u* is indexed by extrapolation item
-  if (t.nsi == 1)
-    TIMED("k_extrap", (k_extrap<D, 1><<<t.ncb, kBlockItems, 0, st>>>(ni, t.S, t.c_blk_item, t.c_blk_cell, t.c_ucell,
-                                                                     t.c_local, t.c_extrap, t.c_cell, u, t.ustar)));
-  else
-    TIMED("k_extrap", (k_extrap<D, 2 * D><<<t.ncb, kBlockItems, 0, st>>>(ni, t.S, t.c_blk_item, t.c_blk_cell,
-                                                                         t.c_ucell, t.c_local, t.c_extrap, t.c_cell, u,
-                                                                         t.ustar)));
+  // one item per face (nsi = 1), or per cell with as many slots as the most
+  // faces of a cell: dim + 1 (simplices) to 2 dim (quads, hexahedra)
+#define EXTRAP(NSI)                                                                                         \
+  TIMED("k_extrap", (k_extrap<D, NSI><<<t.ncb, kBlockItems, 0, st>>>(ni, t.S, t.c_blk_item, t.c_blk_cell, \
+                                                                     t.c_ucell, t.c_local, t.c_extrap, t.c_cell, u, \
+                                                                     t.ustar)))
+  if (t.nsi == 1) EXTRAP(1);
+  else if (t.nsi == D + 1) EXTRAP(D + 1);
+  else if (t.nsi == 2 * D - 1) EXTRAP(2 * D - 1);  // in 3D: cells of at most five faces
+  else if (t.nsi == 2 * D) EXTRAP(2 * D);
+  else return fail(c, HOFV_EINVAL, "unsupported number of face slots per extrapolation item");
+#undef EXTRAP
   if (nf > 0) {
     if (fold) {
       TIMED("k_face_le", (k_face_le<D><<<t.nfb, kBlockItems, 0, st>>>(

@@ -27,10 +27,14 @@ namespace hofv {
 hofv_status build_tables(hofv_ctx* c) {
   auto t0 = std::chrono::steady_clock::now();
   const int D = c->D, p = c->prm.order_p, NS = c->NS;
-  // u* extrapolation items: cells (NSI = NS face slots each), or, when a cell
-  // has more faces than a hexahedron, one item per cell face that needs u*
+  // u* extrapolation items: cells with NSI slots each, as many as the most
+  // faces a cell has (2 dim for quads and hexahedra, dim + 1 for simplices),
+  // or, when a cell has more faces than a hexahedron, one item per cell face
+  // that needs u*
   const bool hf = NS > 2 * D;
-  const int NSI = hf ? 1 : NS;
+  int NSI = 1;
+  if (!hf)
+    for (const hofv_ctx::Face& F : c->faces) NSI = std::max(NSI, std::max(F.sown, F.snei) + 1);
   const int64_t nc = c->nc;
   const int nq = c->nq;
   const bool nh = c->prm.material == HOFV_NEO_HOOKEAN;
@@ -410,7 +414,7 @@ hofv_status build_tables(hofv_ctx* c) {
     for (int r = 0; r < nt; ++r)
       for (int k = 0; k < Sp; ++k) {
         if (hf) cext[cblk.at(item_of[(size_t)slots[r] * nc + P], k, 0, 1, S)] = out[r * Sp + k];
-        else cext[cblk.at(cpos[P], k, slots[r], NS, S)] = out[r * Sp + k];
+        else cext[cblk.at(cpos[P], k, slots[r], NSI, S)] = out[r * Sp + k];
       }
   }
   if (singular) return fail(c, HOFV_ESINGULAR, "rank-deficient least-squares stencil at a cell centroid");

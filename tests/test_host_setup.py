@@ -42,9 +42,10 @@ CASES = [lambda: w.square_mms(8, 2, perturb=0.2), lambda: w.square_mms(7, 3),
 
 def _items(ctx, n):
     """Extrapolation items of the library's u* tables: (NS, NSI, item of
-    (cell, slot)).  Items are cells with NS slots each, or, when a cell has
-    more than 2 dim faces, one item per slot with an internal or displacement
-    face (a cell's items consecutive, in slot order)."""
+    (cell, slot)).  Items are cells with NSI slots each (as many as the most
+    faces of a cell), or, when a cell has more than 2 dim faces, one item per
+    slot with an internal or displacement face (a cell's items consecutive, in
+    slot order)."""
     order = ctx.host_table("cell_order")
     cf = ctx.host_table("cell_faces")
     NS = cf.size // n
@@ -52,7 +53,11 @@ def _items(ctx, n):
     nf = ctx.host_table("face_own").size
     if order.size == n:
         item = np.argsort(order)
-        return NS, NS, lambda P, s: (item[P], s)
+        S = ctx.host_table("cell_stencil").size // n
+        NSI = ctx.host_table("cell_extrap").size // (S * n)
+        used = (cf != np.iinfo(np.int32).min).any(axis=1)
+        assert NSI == np.nonzero(used)[0].max() + 1  # the highest slot in use
+        return NS, NSI, lambda P, s: (item[P], s)
     first = {}
     for r in range(order.size - 1, -1, -1):
         first[order[r]] = r
