@@ -936,7 +936,12 @@ static hofv_status residual_impl(hofv_ctx* c, const double* u, double* R, const 
 #undef SYMNH
     }
   }
-  if (t.ns == 2 * D)
+  // simplices (every face in a cell's first dim + 1 slots) walk those slots only
+  if (t.ns == 2 * D && t.nsi == D + 1)
+    TIMED("k_cell_sum", (k_cell_sum<D, D + 1><<<blocks_for(nc), kBlock, 0, st>>>(
+                            nc, nf, t.ns, t.c_faces, t.flux, t.c_src, c->load, Ru, eps, u, t.dyn_m, t.dyn_s,
+                            t.sym_flux, t.sym_nf, R, nullptr, 0, 1)));
+  else if (t.ns == 2 * D)
     TIMED("k_cell_sum", (k_cell_sum<D, 2 * D><<<blocks_for(nc), kBlock, 0, st>>>(
                             nc, nf, t.ns, t.c_faces, t.flux, t.c_src, c->load, Ru, eps, u, t.dyn_m, t.dyn_s,
                             t.sym_flux, t.sym_nf, R, nullptr, 0, 1)));
@@ -1074,7 +1079,10 @@ static void sgs_sweeps(hofv_ctx* c, int sweeps, hipStream_t st) {
         if (col == last) continue;
         last = col;
         const int64_t b = t.colour_start[col], e = t.colour_start[col + 1];
-        if (e > b && t.ns == 2 * D)
+        if (e > b && t.ns == 2 * D && t.nsi == D + 1)  // simplices: dim + 1 slots
+          TIMED("k_pc_sweep", (k_pc_sweep<D, D + 1><<<blocks_for(e - b), kBlock, 0, st>>>(
+                                  nc, b, e, t.ns, t.p_nbr, t.p_a, t.p_dinv, t.p_r, t.p_z, b, 1)));
+        else if (e > b && t.ns == 2 * D)
           TIMED("k_pc_sweep", (k_pc_sweep<D, 2 * D><<<blocks_for(e - b), kBlock, 0, st>>>(
                                   nc, b, e, t.ns, t.p_nbr, t.p_a, t.p_dinv, t.p_r, t.p_z, b, 1)));
         else if (e > b)  // the colour's cells with more than 2 dim faces come first
@@ -1149,7 +1157,9 @@ static void mg_vcycle(hofv_ctx* c, int l, int sweeps, hipStream_t st) {
   }
   if (l > 0) k_fill_f<<<blocks_for((int64_t)D * m.n), kBlock, 0, st>>>((int64_t)D * m.n, 0.0f, z);
   mg_smooth<D>(c, l, sweeps, st);
-  if (l == 0 && t.ns == 2 * D)
+  if (l == 0 && t.ns == 2 * D && t.nsi == D + 1)  // simplices: dim + 1 slots
+    k_mg_res0<D, D + 1><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.ns, t.p_nbr, t.p_a, t.p_diag, r, z, m.t, nullptr);
+  else if (l == 0 && t.ns == 2 * D)
     k_mg_res0<D, 2 * D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.ns, t.p_nbr, t.p_a, t.p_diag, r, z, m.t, nullptr);
   else if (l == 0)
     k_mg_res0<D, 0><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.ns, t.p_nbr, t.p_a, t.p_diag, r, z, m.t, t.p_big);
