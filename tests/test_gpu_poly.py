@@ -339,3 +339,50 @@ def test_face_lists_of_ordinary_cells(name):
         torch.cuda.synchronize()
         z64 = opc.vcycle(opc.hierarchy(A), r, 2) if mg else opc.sgs(A, col, r, 2)
         assert np.abs(to_host(z) - z64).max() <= (1e-4 if mg else 1e-5) * np.abs(z64).max(), mg
+
+
+MANY = {
+    "cube_54_faces": lambda: w.poly_patch(w.merged_block_mesh(w.box_mesh((7, 7, 7), perturb=0.15, seed=5, mode="tensor"),
+                                                       (2, 2, 2), (5, 5, 5)), 1, 2, seed=3),
+    "square_20_edges": lambda: w.poly_patch(w.merged_block_mesh(w.box_mesh((17, 17), perturb=0.2, seed=5),
+                                                         (6, 6), (11, 11)), 2, 3, seed=3),
+}
+
+
+@pytest.mark.parametrize("name", list(MANY))
+def test_cells_with_many_faces(name):
+    """One cell with 54 faces (3D: 16 lanes of the cell sum and sweeps share
+    it) or 20 edges (2D: 8 lanes) among ordinary cells: R, J.v and both
+    preconditioners against the oracle."""
+    prob = MANY[name]()
+    disc = ores.build(prob)
+    ctx = _api().context_for(prob, precond_levels=8)
+    n, D = disc.n_cells, disc.dim
+    fc = prob.mesh.face_cells
+    assert np.bincount(fc[fc >= 0], minlength=n).max() == (54 if D == 3 else 20)
+    u = w.random_state(n, D, seed=11)
+    ud = to_dev(u)
+    R = torch.empty_like(ud)
+    ctx.residual(ud, R)
+    torch.cuda.synchronize()
+    Ro = ores.residual(disc, u)
+    assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro)
+    assert np.all(np.abs(to_host(R) - Ro) <= 1e-10 * _flux_scale(disc, u))
+    v = w.random_state(n, D, seed=2, scale=1.0)
+    eps = ojac.default_eps(u, v)
+    Jv = torch.empty_like(ud)
+    ctx.jvp(ud, R, to_dev(v), Jv, eps=eps)
+    torch.cuda.synchronize()
+    Jo = ojac.jvp(disc, u, v, eps=eps)
+    floor = 8 * 2.0 ** -52 * np.linalg.norm(_flux_scale(disc, u)) / eps
+    assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo) + floor
+    A = opc.assemble(disc)
+    col = opc.greedy_colours(A)
+    r = w.random_state(n, D, seed=3, scale=1.0)
+    z = torch.empty((D, n), device=DEV, dtype=torch.float64)
+    for mg in (False, True):
+        ctx.set_multigrid(mg)
+        ctx.precond_apply(to_dev(r), z, n_sweeps=2)
+        torch.cuda.synchronize()
+        z64 = opc.vcycle(opc.hierarchy(A), r, 2) if mg else opc.sgs(A, col, r, 2)
+        assert np.abs(to_host(z) - z64).max() <= (1e-4 if mg else 1e-5) * np.abs(z64).max(), mg

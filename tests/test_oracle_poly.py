@@ -135,3 +135,28 @@ def test_face_list_copy_of_simplices_reproduces_the_simplex_discretisation(kind,
     u = w.random_state(base.n_cells, base.dim, seed=8)
     Ra, Rb = rs.residual(rs.build(a), u), rs.residual(rs.build(b), u)
     assert np.abs(Ra - Rb).max() <= 1e-12 * np.abs(Ra).max()
+
+
+@pytest.mark.parametrize("dim,p", [(3, 1), (3, 2), (2, 2), (2, 3)])
+def test_polynomial_fields_give_zero_residual_around_a_cell_of_many_faces(dim, p):
+    """A 3 x 3 x 3 block merged into one cell of 54 faces (tensor-perturbed, so
+    its faces stay planar), or a 5 x 5 block into one of 20 edges: degree <= p
+    fields still give R = 0, and the merged cell's volume is the block's."""
+    if dim == 3:
+        base = w.box_mesh((7, 7, 7), perturb=0.15, seed=5, mode="tensor")
+        m = w.merged_block_mesh(base, (2, 2, 2), (5, 5, 5))
+    else:
+        base = w.box_mesh((9, 9), perturb=0.2, seed=5)
+        m = w.merged_block_mesh(base, (2, 2), (7, 7))
+    fc = m.face_cells
+    nfaces = np.bincount(fc[fc >= 0], minlength=m.n_cells)
+    assert nfaces.max() == (54 if dim == 3 else 20)
+    prob = w.poly_patch(m, p, p, seed=5)
+    disc = rs.build(prob)
+    big = int(np.argmax(nfaces))
+    vb, _ = geo.cell_volume_centroid(base.verts[base.cells])
+    assert abs(disc.vol[big] - vb[m.fine_cell_of == big].sum()) <= 1e-13
+    u = prob.loads.exact.value(disc.cen)
+    R = rs.residual(disc, u)
+    Ff, Fd = rs.face_fluxes(disc, u)
+    assert np.abs(R).max() <= 1e-12 * max(np.abs(Ff).max(), np.abs(Fd).max())

@@ -293,3 +293,29 @@ def face_list_mesh(mesh: Mesh) -> PolyMesh:
                     np.ascontiguousarray(flat[first].reshape(-1), np.int64),
                     np.ascontiguousarray(np.stack([c0, c1], axis=1), np.int64), mesh.n_cells, mesh.shape,
                     mesh.lengths, mesh.origin, np.arange(mesh.n_cells))
+
+
+def merged_block_mesh(mesh: Mesh, lo, hi) -> PolyMesh:
+    """The face list of a structured mesh with the cells whose (i, j[, k]) lie
+    in [lo, hi) merged into one cell (the faces inside the block dropped): a
+    3 x 3 x 3 block gives a cell of 54 faces, a 5 x 5 block one of 20 edges.
+    The merged cell takes the number of the block's first cell."""
+    pm = face_list_mesh(mesh)
+    ijk = cell_ijk(mesh)
+    inside = np.all((ijk >= np.asarray(lo)) & (ijk < np.asarray(hi)), axis=1)
+    first = int(np.nonzero(inside)[0][0])
+    new = np.full(mesh.n_cells, -1, np.int64)
+    nxt = 0
+    for P in range(mesh.n_cells):
+        if inside[P] and P != first:
+            continue
+        new[P] = nxt
+        nxt += 1
+    new[inside] = new[first]
+    fc = np.where(pm.face_cells >= 0, new[np.maximum(pm.face_cells, 0)], -1)
+    keep = fc[:, 0] != fc[:, 1]
+    loops = np.split(pm.face_verts, pm.face_ptr[1:-1])
+    kept = [loops[f] for f in np.nonzero(keep)[0]]
+    ptr = np.concatenate([[0], np.cumsum([v.size for v in kept])]).astype(np.int64)
+    return PolyMesh(mesh.dim, mesh.verts, ptr, np.concatenate(kept).astype(np.int64),
+                    np.ascontiguousarray(fc[keep]), nxt, mesh.shape, mesh.lengths, mesh.origin, new)
