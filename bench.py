@@ -385,7 +385,8 @@ def parse_seeds(s):
     return out
 
 
-KRYLOV = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0, "side": 0, "gs_passes": 0}  # Newton's Krylov options (set from the arguments)
+KRYLOV = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0, "side": 0, "gs_passes": 0,
+          "graphs": 0}  # Newton's Krylov options (set from the arguments)
 
 
 def forcing_term(rn, rprev, eta_prev, eta_max, tol, r0):
@@ -413,7 +414,7 @@ def newton_stepwise(torch, ctx, uu, learned, tol, max_krylov, max_newton, label)
         st = ctx.newton_solve(uu, tol=1e-300, eta=eta, max_newton=1, max_krylov=max_krylov, n_sweeps=2,
                               learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"],
                               max_line_search=KRYLOV["line_search"], side=KRYLOV["side"],
-                              gs_passes=KRYLOV["gs_passes"])
+                              gs_passes=KRYLOV["gs_passes"], graphs=KRYLOV["graphs"])
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             tot[key] += st[key]
         ctx.residual(uu, R)
@@ -441,7 +442,7 @@ def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None, stepw
         st = ctx.newton_solve(uu, tol=tol, eta=KRYLOV["eta"], max_krylov=max_krylov, n_sweeps=2, learned=learned,
                               check=False, n_increments=ninc, restart=KRYLOV["restart"],
                               max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"], predictor=1, side=KRYLOV["side"],
-                              gs_passes=KRYLOV["gs_passes"])
+                              gs_passes=KRYLOV["gs_passes"], graphs=KRYLOV["graphs"])
         torch.cuda.synchronize()
         out.update({key: st[key] for key in ("newton_iters", "krylov_iters", "fallbacks", "rel_residual")})
         out["converged"] = bool(st["converged"])
@@ -457,7 +458,7 @@ def newton_run(torch, ctx, prob, nc, learned, tol, max_krylov, u_out=None, stepw
             st = ctx.newton_solve(uu, tol=tol, eta=KRYLOV["eta"], max_krylov=max_krylov, n_sweeps=2,
                                   learned=learned, check=False, n_increments=0, restart=KRYLOV["restart"],
                                   max_line_search=KRYLOV["line_search"], forcing=KRYLOV["forcing"], side=KRYLOV["side"],
-                              gs_passes=KRYLOV["gs_passes"])
+                              gs_passes=KRYLOV["gs_passes"], graphs=KRYLOV["graphs"])
         for key in ("newton_iters", "krylov_iters", "fallbacks"):
             out[key] += st[key]
         out["rel_residual"] = st["rel_residual"]
@@ -729,6 +730,10 @@ def main():
     ap.add_argument("--gs-passes", type=int, default=None,
                     help="classical Gram-Schmidt passes per Arnoldi step: 1 once (PETSc's default orthogonalisation; "
                          "the default here), 2 twice (the default for the cantilever's 250-vector cycles)")
+    ap.add_argument("--graphs", type=int, default=None,
+                    help="1: replay each Arnoldi step as a HIP graph after its first run (captured in the "
+                         "first solve that reaches it: time a solve after a warm-up on the same state tensor), "
+                         "0: launch one by one (default)")
     ap.add_argument("--stencil-grow", type=int, default=0,
                     help="grow stencils that fail the pivot test by this many cells at a time (0: such a "
                          "stencil is an error)")
@@ -744,7 +749,7 @@ def main():
     # cycles, full Newton steps, the forcing term and the predictor (its sweeps-only
     # solve does not converge, so it runs the multigrid one)
     defaults = {"eta": 1e-4, "restart": 30, "line_search": 10, "forcing": 0, "predictor": 0,
-                "solvers": "plain,multigrid,learned", "precond_levels": 8, "gs_passes": 1}
+                "solvers": "plain,multigrid,learned", "precond_levels": 8, "gs_passes": 1, "graphs": 0}
     if args.workload == "cantilever":
         defaults.update(eta=0.5, restart=250, line_search=-1, forcing=1, predictor=1, solvers="multigrid",
                         gs_passes=2)
@@ -754,7 +759,7 @@ def main():
         if getattr(args, key) is None:
             setattr(args, key, val)
     KRYLOV.update(eta=args.eta, restart=args.restart, line_search=args.line_search, forcing=args.forcing,
-                  predictor=args.predictor, side=args.side, gs_passes=args.gs_passes)
+                  predictor=args.predictor, side=args.side, gs_passes=args.gs_passes, graphs=args.graphs)
     solvers = set(args.solvers.split(","))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built",
@@ -902,7 +907,7 @@ def main():
     elif args.solve:
         solve = {"krylov": {"eta": args.eta, "forcing": args.forcing, "restart": args.restart,
                             "line_search": args.line_search, "predictor": args.predictor, "side": args.side,
-                            "gs_passes": 1 if args.gs_passes == 1 else 2}}
+                            "gs_passes": 1 if args.gs_passes == 1 else 2, "graphs": args.graphs}}
         if "plain" in solvers:
             if prob.n_increments == 1:
                 newton(False)  # warm-up (allocates the Krylov workspace)

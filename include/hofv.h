@@ -295,6 +295,21 @@ typedef struct {
                             twice (default); 1: once, the orthogonalisation PETSc's
                             GMRES uses unless told otherwise (Sec. 4.1 names PETSc
                             and no other); others HOFV_EINVAL */
+  int32_t graphs;        /* 0: every launch of an Arnoldi step made by the host
+                            (default); 1: each step j of a right-preconditioned,
+                            unlearned solve is captured as a HIP graph the
+                            second time it runs and replayed from then on, on a
+                            stream of the context's own for the capture and the
+                            caller's for the replays; the captured steps are
+                            kept across solves while the state and Ru pointers,
+                            sweeps, passes, restart, multigrid and dynamics
+                            settings and load scale stay the same, and rebuilt
+                            otherwise.  Results are bit for bit those of 0.  For
+                            small meshes, where launching rather than the GPU
+                            sets the pace (a few per cent there; nothing on
+                            large ones).  Ignored with learned, side 1, the
+                            near-exact Jacobian or kernel timing on; others
+                            HOFV_EINVAL */
 } hofv_krylov_opts;
 
 typedef struct {

@@ -36,7 +36,8 @@ class SetupReport(C.Structure):
 
 class KrylovOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("rtol", C.c_double),
-                ("n_sweeps", C.c_int32), ("learned", C.c_int32), ("side", C.c_int32), ("gs_passes", C.c_int32)]
+                ("n_sweeps", C.c_int32), ("learned", C.c_int32), ("side", C.c_int32), ("gs_passes", C.c_int32),
+                ("graphs", C.c_int32)]
 
 
 class KrylovStats(C.Structure):

@@ -211,8 +211,9 @@ class Context:
                                                 _stream(stream)))
 
     def fgmres_solve(self, u, Ru, rhs, x, restart=30, max_iters=1000, rtol=1e-6, n_sweeps=2, learned=False,
-                     stream=None, check=True, side=0, gs_passes=0):
-        o = L.KrylovOpts(restart, max_iters, rtol, n_sweeps, int(bool(learned)), int(side), int(gs_passes))
+                     stream=None, check=True, side=0, gs_passes=0, graphs=0):
+        o = L.KrylovOpts(restart, max_iters, rtol, n_sweeps, int(bool(learned)), int(side), int(gs_passes),
+                         int(graphs))
         s = L.KrylovStats()
         st = self.lib.hofv_fgmres_solve(self.h, self._v(u), self._v(Ru), self._v(rhs), self._v(x), C.byref(o),
                                         C.byref(s), _stream(stream))
@@ -222,17 +223,17 @@ class Context:
 
     @staticmethod
     def _newton_opts(tol, eta, max_newton, n_increments, max_line_search, restart, max_krylov, n_sweeps, learned,
-                     forcing, predictor, side=0, gs_passes=0):
+                     forcing, predictor, side=0, gs_passes=0, graphs=0):
         return L.NewtonOpts(tol, eta, max_newton, n_increments, max_line_search,
                             L.KrylovOpts(restart, max_krylov, eta, n_sweeps, int(bool(learned)), int(side),
-                                         int(gs_passes)),
+                                         int(gs_passes), int(graphs)),
                             int(forcing), int(predictor))
 
     def newton_solve(self, u, tol=1e-8, eta=1e-4, max_newton=50, n_increments=1, max_line_search=10,
                      restart=30, max_krylov=2000, n_sweeps=2, learned=False, stream=None, check=True,
-                     forcing=0, predictor=0, side=0, gs_passes=0):
+                     forcing=0, predictor=0, side=0, gs_passes=0, graphs=0):
         o = self._newton_opts(tol, eta, max_newton, n_increments, max_line_search, restart, max_krylov, n_sweeps,
-                              learned, forcing, predictor, side, gs_passes)
+                              learned, forcing, predictor, side, gs_passes, graphs)
         s = L.NewtonStats()
         st = self.lib.hofv_newton_solve(self.h, self._v(u), C.byref(o), C.byref(s), _stream(stream))
         if check or st not in (L.HOFV_OK, -5):

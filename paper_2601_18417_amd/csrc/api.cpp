@@ -108,6 +108,9 @@ hofv_status hofv_destroy(hofv_ctx* c) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
   }
+  for (hipGraphExec_t g : c->kry.step_graph)
+    if (g) hipGraphExecDestroy(g);
+  if (c->kry.cap_stream) hipStreamDestroy(c->kry.cap_stream);
   for (void* p : c->allocations) hipFree(p);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   delete c;

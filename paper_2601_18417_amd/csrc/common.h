@@ -156,6 +156,12 @@ struct Krylov {
   double* hbuf = nullptr;  // pinned host copy
   double* Hd = nullptr;    // device Hessenberg columns of a cycle, column-major [m][m + 1]
   double* zz = nullptr;    // squared norms of learned preconditioner outputs [m]
+  // Arnoldi steps replayed as HIP graphs (hofv_krylov_opts.graphs): step j is
+  // captured, on cap_stream, the second time it runs
+  std::vector<hipGraphExec_t> step_graph;  // [m], null until captured
+  std::vector<uint8_t> step_seen;          // step j has run launched one by one
+  std::vector<uintptr_t> graph_key;        // the host values the captured launches hold
+  hipStream_t cap_stream = nullptr;
 };
 
 // near-exact Jacobian preconditioner (App. C): k right-preconditioned GMRES

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "common.h"
@@ -299,6 +300,47 @@ hofv_status jvp_impl(hofv_ctx* c, const double* u, const double* Ru, const doubl
                      hipStream_t st);
 hofv_status precond_dispatch(hofv_ctx* c, const double* r, double* z, int sweeps, int learned, hipStream_t st);
 
+// Captured Arnoldi steps stay valid while the host values their launches hold
+// (key) do not change; otherwise they are dropped and captured afresh.
+static hofv_status graphs_prepare(hofv_ctx* c, const std::vector<uintptr_t>& key, int m) {
+  Krylov& K = c->kry;
+  if (!K.cap_stream) HOFV_HIP(c, hipStreamCreateWithFlags(&K.cap_stream, hipStreamNonBlocking));
+  if (K.graph_key == key && (int)K.step_graph.size() == m) return HOFV_OK;
+  for (hipGraphExec_t g : K.step_graph)
+    if (g) HOFV_HIP(c, hipGraphExecDestroy(g));
+  K.step_graph.assign(m, nullptr);
+  K.step_seen.assign(m, 0);
+  K.graph_key = key;
+  return HOFV_OK;
+}
+
+// Step j launched one by one the first time, captured on the context's
+// stream and replayed on st from the second time on.
+template <class Step>
+static hofv_status graph_step(hofv_ctx* c, int j, Step&& step, hipStream_t st) {
+  Krylov& K = c->kry;
+  if (!K.step_seen[j]) {
+    K.step_seen[j] = 1;
+    return step(st);
+  }
+  if (!K.step_graph[j]) {
+    HOFV_HIP(c, hipStreamBeginCapture(K.cap_stream, hipStreamCaptureModeThreadLocal));
+    const hofv_status s = step(K.cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(K.cap_stream, &g);
+    if (s) {
+      if (g) hipGraphDestroy(g);
+      return s;
+    }
+    HOFV_HIP(c, e);
+    const hipError_t ei = hipGraphInstantiate(&K.step_graph[j], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HOFV_HIP(c, ei);
+  }
+  HOFV_HIP(c, hipGraphLaunch(K.step_graph[j], st));
+  return HOFV_OK;
+}
+
 hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const double* rhs, double* x,
                         const hofv_krylov_opts* o, hofv_krylov_stats* stats, hipStream_t st) {
   auto t0 = std::chrono::steady_clock::now();
@@ -322,6 +364,17 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
   if (o->side != 0 && o->side != 1) return fail(c, HOFV_EINVAL, "side must be 0 (right) or 1 (left)");
   if (o->gs_passes < 0 || o->gs_passes > 2) return fail(c, HOFV_EINVAL, "gs_passes must be 0, 1 or 2");
   const int passes = o->gs_passes == 1 ? 1 : 2;
+  if (o->graphs < 0 || o->graphs > 1) return fail(c, HOFV_EINVAL, "graphs must be 0 or 1");
+  const bool graphs = o->graphs == 1 && !left && !o->learned && c->nej.k == 0 && !c->timing;
+  if (graphs) {
+    uint64_t load_bits;
+    std::memcpy(&load_bits, &c->load, sizeof load_bits);
+    const std::vector<uintptr_t> key = {(uintptr_t)u, (uintptr_t)Ru, (uintptr_t)K.V, (uintptr_t)K.Z,
+                                        (uintptr_t)K.h, (uintptr_t)K.Hd, (uintptr_t)K.zz, (uintptr_t)m,
+                                        (uintptr_t)sweeps, (uintptr_t)passes, (uintptr_t)c->use_mg,
+                                        (uintptr_t)load_bits, (uintptr_t)c->dev.dyn_m, (uintptr_t)c->dev.dyn_s};
+    if ((s = graphs_prepare(c, key, m))) return s;
+  }
   if ((s = host_norm(c, n, x, &xnorm, st))) return s;
   if (left) {
     if ((s = precond_dispatch(c, rhs, K.tmp2, sweeps, 0, st))) return s;
@@ -384,20 +437,24 @@ hofv_status fgmres_impl(hofv_ctx* c, const double* u, const double* Ru, const do
     bool done = false;
     std::vector<double> hblk((size_t)(m + 1) * kCheck), zzb(kCheck);
     while (!done) {
-      double* vj = K.V + (size_t)j * n;
-      double* zj = K.Z + (size_t)j * n;
-      double* w = K.V + (size_t)(j + 1) * n;
-      if (left) {  // w = M J v_j (z_j holds J v_j)
-        if ((s = jvp_impl(c, u, Ru, vj, zj, 0.0, st))) return s;
-        if ((s = precond_dispatch(c, zj, w, sweeps, 0, st))) return s;
-      } else {  // w = J z_j, z_j = M v_j
-        if ((s = precond_dispatch(c, vj, zj, sweeps, learned, st))) return s;
-        // ||z_j||^2 of a learned output (a NaN z_j would only show up later:
-        // its finite-difference product is defined to be zero)
-        if (learned && (s = dots(c, n, 1, zj, n, zj, hd + kZz, 0, st))) return s;
-        if ((s = jvp_impl(c, u, Ru, zj, w, 0.0, st))) return s;
-      }
-      if ((s = cgs2(c, n, j, K.V, w, hd, K.Hd, m + 1, K.zz, st, passes))) return s;
+      auto step = [&](hipStream_t q) -> hofv_status {
+        double* vj = K.V + (size_t)j * n;
+        double* zj = K.Z + (size_t)j * n;
+        double* w = K.V + (size_t)(j + 1) * n;
+        hofv_status r;
+        if (left) {  // w = M J v_j (z_j holds J v_j)
+          if ((r = jvp_impl(c, u, Ru, vj, zj, 0.0, q))) return r;
+          if ((r = precond_dispatch(c, zj, w, sweeps, 0, q))) return r;
+        } else {  // w = J z_j, z_j = M v_j
+          if ((r = precond_dispatch(c, vj, zj, sweeps, learned, q))) return r;
+          // ||z_j||^2 of a learned output (a NaN z_j would only show up later:
+          // its finite-difference product is defined to be zero)
+          if (learned && (r = dots(c, n, 1, zj, n, zj, hd + kZz, 0, q))) return r;
+          if ((r = jvp_impl(c, u, Ru, zj, w, 0.0, q))) return r;
+        }
+        return cgs2(c, n, j, K.V, w, hd, K.Hd, m + 1, K.zz, q, passes);
+      };
+      if ((s = graphs ? graph_step(c, j, step, st) : step(st))) return s;
       ++j;
       if (j - jp < kCheck && j < m && it + (j - jp) < maxit) continue;
       const int nq = j - jp;

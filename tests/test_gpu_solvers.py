@@ -368,3 +368,58 @@ def test_newton_full_steps_on_a_tip_loaded_beam_match_oracle():
     ug = to_host(u)
     assert np.abs(ug[:, 1]).max() > 0.5
     assert np.linalg.norm(ug - uo) <= 1e-7 * np.linalg.norm(uo)
+
+
+@pytest.mark.parametrize("mg", [False, True])
+def test_graph_replayed_arnoldi_steps_match_launched_ones(mg):
+    """graphs = 1 (each Arnoldi step captured as a HIP graph the second time it
+    runs, replayed after that) gives the results of graphs = 0 bit for bit: two
+    FGMRES solves in a row on the 2D 32^2 problem (the first captures in its
+    later cycles, the second replays every step), with the host's reads of
+    Hessenberg columns and synchronisations between the replays; then Newton
+    over two load increments of a small beam, whose load scale changes between
+    increments, so that the captured steps are dropped and captured again (a
+    step replayed with the old load would put (s_old - s) src / eps into J.v)."""
+    api = _api()
+    prob = w.square_mms(32, 2, perturb=0.2)
+    ctx = api.context_for(prob, precond_levels=8 if mg else 1)
+    ctx.set_multigrid(mg)
+    n = prob.mesh.n_cells
+    u = to_dev(w.random_state(n, 2, seed=3, scale=0.1))
+    Ru = torch.empty_like(u)
+    ctx.residual(u, Ru)
+    b = to_dev(w.random_state(n, 2, seed=7, scale=1.0))
+    runs = {}
+    for graphs in (0, 1):
+        runs[graphs] = []
+        for rep in range(2):
+            x = torch.zeros_like(u)
+            # three full cycles (the tolerance is out of reach on purpose)
+            st = ctx.fgmres_solve(u, Ru, b, x, rtol=1e-14, max_iters=90, restart=30, graphs=graphs, check=False)
+            torch.cuda.synchronize()
+            runs[graphs].append((x.clone(), st))
+            print("graphs", graphs, "solve", rep, {k: st[k] for k in ("iters", "rel_residual", "stalled")})
+    for rep in range(2):
+        (x0, s0), (x1, s1) = runs[0][rep], runs[1][rep]
+        assert torch.equal(x0, x1), rep
+        assert (s0["iters"], s0["rel_residual"], s0["stalled"]) == (s1["iters"], s1["rel_residual"], s1["stalled"])
+    assert runs[1][0][1]["iters"] > 30  # the first solve itself went past one cycle
+
+    beam = w.cantilever(shape=(8, 2, 2), p=1, n_plus=20, n_increments=2)
+    beam.mesh = w.box_mesh((8, 2, 2), lengths=(4.0, 1, 1))
+    beam.loads = w.fields.cantilever_loads(4.0, (0.0, -0.02, 0.0))
+    bctx = api.context_for(beam)
+    kw = dict(tol=1e-10, eta=1e-7, n_increments=2, max_line_search=-1, restart=40, max_krylov=400, max_newton=12)
+    res = {}
+    for graphs in (0, 1):
+        ub = torch.zeros((3, beam.mesh.n_cells), device=DEV, dtype=torch.float64)
+        st = bctx.newton_solve(ub, graphs=graphs, check=False, **kw)
+        torch.cuda.synchronize()
+        res[graphs] = (ub.clone(), st)
+        print("graphs", graphs, "newton", st)
+    assert res[0][1]["converged"]
+    assert torch.equal(res[0][0], res[1][0])
+    for k in ("newton_iters", "krylov_iters", "rel_residual"):
+        assert res[0][1][k] == res[1][1][k], k
+    with pytest.raises(api.HofvError):
+        ctx.fgmres_solve(u, Ru, b, torch.zeros_like(u), graphs=2)
