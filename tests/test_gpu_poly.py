@@ -342,24 +342,33 @@ def test_face_lists_of_ordinary_cells(name):
 
 
 MANY = {
-    "cube_54_faces": lambda: w.poly_patch(w.merged_block_mesh(w.box_mesh((7, 7, 7), perturb=0.15, seed=5, mode="tensor"),
-                                                       (2, 2, 2), (5, 5, 5)), 1, 2, seed=3),
+    "cube_54_faces": lambda: w.poly_patch(w.merged_block_mesh(w.box_mesh((7, 7, 7), perturb=0.15, seed=5,
+                                                                         mode="tensor"), (2, 2, 2), (5, 5, 5)),
+                                          1, 2, seed=3),
     "square_20_edges": lambda: w.poly_patch(w.merged_block_mesh(w.box_mesh((17, 17), perturb=0.2, seed=5),
-                                                         (6, 6), (11, 11)), 2, 3, seed=3),
+                                                                (6, 6), (11, 11)), 2, 3, seed=3),
+    # the largest cells accepted: groups of 64 lanes, the whole wavefront
+    "cube_216_faces": lambda: w.poly_patch(w.merged_block_mesh(w.box_mesh((8, 8, 8), perturb=0.15, seed=5,
+                                                                          mode="tensor"), (1, 1, 1), (7, 7, 7)),
+                                           1, 2, seed=3),
+    "square_252_edges": lambda: w.poly_patch(w.merged_block_mesh(w.box_mesh((65, 65), perturb=0.2, seed=5),
+                                                                 (1, 1), (64, 64)), 1, 2, seed=3),
 }
+NFACES = {"cube_54_faces": 54, "square_20_edges": 20, "cube_216_faces": 216, "square_252_edges": 252}
 
 
 @pytest.mark.parametrize("name", list(MANY))
 def test_cells_with_many_faces(name):
     """One cell with 54 faces (3D: 16 lanes of the cell sum and sweeps share
-    it) or 20 edges (2D: 8 lanes) among ordinary cells: R, J.v and both
+    it), 20 edges (2D: 8 lanes), or the most a cell may have short of 255
+    (216 faces, 252 edges: 64 lanes) among ordinary cells: R, J.v and both
     preconditioners against the oracle."""
     prob = MANY[name]()
     disc = ores.build(prob)
     ctx = _api().context_for(prob, precond_levels=8)
     n, D = disc.n_cells, disc.dim
     fc = prob.mesh.face_cells
-    assert np.bincount(fc[fc >= 0], minlength=n).max() == (54 if D == 3 else 20)
+    assert np.bincount(fc[fc >= 0], minlength=n).max() == NFACES[name]
     u = w.random_state(n, D, seed=11)
     ud = to_dev(u)
     R = torch.empty_like(ud)

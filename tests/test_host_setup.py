@@ -442,3 +442,26 @@ def test_face_list_meshes_that_do_not_close_are_refused(dim):
     fc = m.face_cells.copy()
     fc[inner, 1] = fc[inner, 0]
     assert "bad face cells" in attempt(m.face_ptr, m.face_verts, fc)
+
+
+def test_limits_of_255_are_enforced():
+    """A cell of 294 faces (a merged 7 x 7 x 7 block), a stencil of more than
+    255 cells and stencil growth above 255 are refused with HOFV_EINVAL; the
+    largest accepted cells (216 faces, 252 edges) set up."""
+    m = w.merged_block_mesh(w.box_mesh((9, 9, 9)), (1, 1, 1), (8, 8, 8))
+    fc = m.face_cells
+    assert np.bincount(fc[fc >= 0]).max() == 294
+    with pytest.raises(api.HofvError, match="more than 255 faces"):
+        api.context_for(w.poly_patch(m, 1, 1, seed=1), host_only=True)
+    for mk in (lambda: w.merged_block_mesh(w.box_mesh((8, 8, 8), perturb=0.15, seed=5, mode="tensor"),
+                                           (1, 1, 1), (7, 7, 7)),
+               lambda: w.merged_block_mesh(w.box_mesh((65, 65), perturb=0.2, seed=5), (1, 1), (64, 64))):
+        api.context_for(w.poly_patch(mk(), 1, 2, seed=3), host_only=True).close()
+    prob = w.cube_mms(8, 2, perturb=0.2)
+    prob.n_plus = 250  # |S| = 10 + 250
+    with pytest.raises(api.HofvError, match="above 255"):
+        api.context_for(prob, host_only=True)
+    prob = w.cube_mms(8, 2, perturb=0.2)
+    prob.stencil_grow = 256
+    with pytest.raises(api.HofvError):
+        api.context_for(prob, host_only=True)
