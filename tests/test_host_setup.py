@@ -280,6 +280,16 @@ def test_bench_and_entry_points_compile(repo_root):
         py_compile.compile(os.path.join(repo_root, f), doraise=True)
 
 
+def test_bench_refuses_more_than_one_gpu(repo_root):
+    """bench.py measures one GPU; --gpus 2 ends with status 2 and says so,
+    before anything touches a GPU."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(repo_root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=repo_root)
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
+
+
 def test_symmetry_faces_get_their_own_flux_codes():
     """Cells on a symmetry plane point one face slot at the symmetry fluxes
     (codes >= the number of internal and displacement faces)."""
