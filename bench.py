@@ -660,7 +660,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cube",
-                    choices=["cube", "cantilever", "square", "column", "symmetric", "tets", "poly"],
+                    choices=["cube", "cantilever", "square", "plane", "column", "symmetric", "tets", "poly"],
                     help="cube: 3D LE manufactured solution on a perturbed n^3 mesh (default); cantilever: "
                          "3D neo-Hookean 200x20x20 beam, 10 load increments; square: 2D 32x32 LE, p=2; "
                          "column: the vibrating neo-Hookean column, BDF2 time steps; symmetric: a polynomial "
@@ -799,6 +799,8 @@ def main():
     elif args.workload == "symmetric":
         prob = w.poly_patch(w.box_mesh((args.n,) * 3, perturb=0.2, seed=0, mode="tensor"), args.p, args.p, seed=1,
                             symmetric=True)
+    elif args.workload == "plane":  # the square's problem at n^2 perturbed cells
+        prob = w.square_mms(args.n, args.p, perturb=0.2, seed=0)
     else:
         prob = w.square_mms(32, args.p)
     prob.stencil_grow = args.stencil_grow
@@ -988,7 +990,8 @@ def main():
     cpu = None
     if args.cpu_sample > 0:
         label = {"cube": f"{args.n}^3 p={args.p}", "cantilever": f"cantilever p={args.p}",
-                 "square": f"32^2 p={args.p}"}.get(args.workload, f"{args.workload} p={args.p}")
+                 "square": f"32^2 p={args.p}", "plane": f"{args.n}^2 p={args.p}"}.get(
+                     args.workload, f"{args.workload} p={args.p}")
         cpu = cpu_baseline(prob, min(args.cpu_sample, nc // 2), u.cpu().numpy().T.copy(),
                            v.cpu().numpy().T.copy(), ctx, torch, label,
                            cube=("cube", args.n, args.p) if args.workload == "cube" else None)
@@ -1018,6 +1021,8 @@ def main():
                                               f"|S|={ctx.report['stencil_size']}, 10 load increments",
                                 "square": f"2D plane-strain LE MMS, 32x32 quads, p={args.p}, "
                                           f"|S|={ctx.report['stencil_size']}",
+                                "plane": f"2D plane-strain LE MMS, unit square {args.n}^2 quads perturbed +-20% "
+                                         f"(seed 0), p={args.p}, |S|={ctx.report['stencil_size']}",
                                 "column": f"3D neo-Hookean vibrating column 6 x 0.2 x 0.2 m, {args.column_cells} hex, "
                                           f"p={args.p}, |S|={ctx.report['stencil_size']}, BDF2 dt = 1 ms",
                                 "tets": f"3D linear elastic MMS, unit cube, {args.n}^3 hex perturbed +-20% (seed 0) "
