@@ -133,3 +133,57 @@ def test_mms_error_falls_on_refined_simplices(kind, p, sizes):
     slope = np.log(errs[0] / errs[1]) / np.log(2.0)
     print(f"{kind} p={p} errors {errs} slope {slope:.2f}")
     assert slope >= 1.0
+
+
+def _flux_scale(disc, u):
+    Ff, Fd = ores.face_fluxes(disc, u)
+    s = np.zeros((disc.n_cells, disc.dim))
+    np.add.at(s, disc.f_own, np.abs(Ff))
+    np.add.at(s, disc.f_nei, np.abs(Ff))
+    np.add.at(s, disc.d_own, np.abs(Fd))
+    return s + np.abs(disc.b_body + disc.b_trac)
+
+
+SYM = {
+    "tets_p1": lambda: w.poly_patch(w.tet_mesh((4, 4, 4), perturb=0.15, seed=3), 1, 1, seed=6, symmetric=True),
+    "tets_p2": lambda: w.poly_patch(w.tet_mesh((4, 4, 4), perturb=0.15, seed=3), 2, 2, seed=6, symmetric=True),
+    "tris_p2": lambda: w.poly_patch(w.tri_mesh((8, 7), perturb=0.15, seed=4), 2, 2, seed=6, symmetric=True),
+    "tris_p3": lambda: w.poly_patch(w.tri_mesh((9, 8), perturb=0.15, seed=4), 3, 3, seed=7, symmetric=True),
+}
+
+
+@pytest.mark.parametrize("name", list(SYM))
+def test_symmetry_planes_on_simplices(name):
+    """Symmetry planes (Sec. 3.5) on the x = 0 triangles of a tetrahedral mesh
+    or edges of a triangular one, with fields symmetric about them: R against
+    the oracle cell by cell (random states), zero for the symmetric degree-p
+    field, and J.v."""
+    prob = SYM[name]()
+    disc = ores.build(prob)
+    assert len(disc.s_own) > 0
+    ctx = _api().context_for(prob)
+    n, D = disc.n_cells, disc.dim
+    for seed in (11, 12):
+        u = w.random_state(n, D, seed=seed)
+        R = torch.empty((D, n), device=DEV, dtype=torch.float64)
+        ctx.residual(to_dev(u), R)
+        torch.cuda.synchronize()
+        Ro = ores.residual(disc, u)
+        assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro), seed
+        assert np.all(np.abs(to_host(R) - Ro) <= 1e-10 * _flux_scale(disc, u)), seed
+    ue = prob.loads.exact.value(disc.cen)
+    R = torch.empty((D, n), device=DEV, dtype=torch.float64)
+    ctx.residual(to_dev(ue), R)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(to_host(R)) <= 1e-10 * _flux_scale(disc, ue))
+    u = w.random_state(n, D, seed=1)
+    v = w.random_state(n, D, seed=2, scale=1.0)
+    ud = to_dev(u)
+    Ru = torch.empty_like(ud)
+    ctx.residual(ud, Ru)
+    eps = ojac.default_eps(u, v)
+    Jv = torch.empty_like(ud)
+    ctx.jvp(ud, Ru, to_dev(v), Jv, eps=eps)
+    torch.cuda.synchronize()
+    Jo = ojac.jvp(disc, u, v, eps=eps)
+    assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
