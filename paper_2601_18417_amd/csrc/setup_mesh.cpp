@@ -439,18 +439,23 @@ hofv_status build_geometry(hofv_ctx* c) {
     for (int a = 0; a < ncv; ++a)
       for (int d = 0; d < D; ++d) X[D * a + d] = c->verts[(size_t)c->cells[(size_t)e * ncv + a] * D + d];
     if (D == 2) {
-      // polygon (shoelace) area and centroid of the straight-edged quad or triangle
+      // polygon (shoelace) area and centroid of the straight-edged quad or
+      // triangle, in coordinates relative to its first vertex: with absolute
+      // ones the cross products, of size |x|^2, cancel down to the area, of
+      // size h^2, and the centroid loses (|x| / h)^2 of its precision
       double A2 = 0, cx = 0, cy = 0;
       for (int a = 0; a < ncv; ++a) {
-        int b = (a + 1) % ncv;
-        double cr = X[2 * a] * X[2 * b + 1] - X[2 * b] * X[2 * a + 1];
+        const int b = (a + 1) % ncv;
+        const double xa = X[2 * a] - X[0], ya = X[2 * a + 1] - X[1];
+        const double xb = X[2 * b] - X[0], yb = X[2 * b + 1] - X[1];
+        const double cr = xa * yb - xb * ya;
         A2 += cr;
-        cx += (X[2 * a] + X[2 * b]) * cr;
-        cy += (X[2 * a + 1] + X[2 * b + 1]) * cr;
+        cx += (xa + xb) * cr;
+        cy += (ya + yb) * cr;
       }
       c->vol[e] = 0.5 * A2;
-      c->cen[2 * e] = cx / (3.0 * A2);
-      c->cen[2 * e + 1] = cy / (3.0 * A2);
+      c->cen[2 * e] = X[0] + cx / (3.0 * A2);
+      c->cen[2 * e + 1] = X[1] + cy / (3.0 * A2);
       int q = 0;
       for (int i = 0; i < nv1; ++i)
         for (int j = 0; j < nv1; ++j, ++q) {

@@ -148,3 +148,43 @@ def test_fullsize_128_cube_sampled(p):
     ue = prob.loads.exact.value(ctx.cell_centroids())
     _check_sampled(prob, ctx, disc, sample, ue, v, near_solution=True)
     ctx.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("p", [2, 3])
+def test_fullsize_512_square_sampled(p):
+    """The 2D problem on 512^2 perturbed quadrilaterals (262,144 cells, the
+    bench's plane workload), p = 2, 3: the 2D kernels at full size, random
+    state and manufactured field."""
+    from paper_2601_18417_amd import api
+    prob = w.square_mms(512, p, perturb=0.2, seed=0)
+    ctx = api.context_for(prob)
+    n = prob.mesh.n_cells
+    sample = _sample(prob, np.random.default_rng(30 + p))
+    disc = ores.build(prob, active=sample)
+    u = w.random_state(n, 2, seed=24)
+    v = np.random.default_rng(1003).standard_normal((n, 2))
+    _check_sampled(prob, ctx, disc, sample, u, v)
+    ue = prob.loads.exact.value(ctx.cell_centroids())
+    _check_sampled(prob, ctx, disc, sample, ue, v, near_solution=True)
+    ctx.close()
+
+
+@pytest.mark.timeout(600)
+def test_fullsize_tetrahedra_sampled():
+    """663,552 tetrahedra (48^3 perturbed hexes split in six, the bench's tets
+    workload) at p = 2: 4-slot extrapolation items and cell walks at full
+    size, against the oracle on sampled cells."""
+    from paper_2601_18417_amd import api
+    prob = w.tet_mms(48, 2, perturb=0.2, seed=0)
+    ctx = api.context_for(prob)
+    n = prob.mesh.n_cells
+    rng = np.random.default_rng(40)
+    sample = np.unique(np.concatenate([rng.choice(n, 40, replace=False), np.arange(6), np.arange(n - 6, n)]))
+    disc = ores.build(prob, active=sample)
+    u = w.random_state(n, 3, seed=25)
+    v = np.random.default_rng(1004).standard_normal((n, 3))
+    _check_sampled(prob, ctx, disc, sample, u, v)
+    ue = prob.loads.exact.value(ctx.cell_centroids())
+    _check_sampled(prob, ctx, disc, sample, ue, v, near_solution=True)
+    ctx.close()
