@@ -478,15 +478,19 @@ def test_limits_of_255_are_enforced():
         api.context_for(prob, host_only=True)
 
 
-@pytest.mark.parametrize("kind", ["quads", "tris"])
-def test_2d_geometry_is_translation_stable(kind):
-    """Areas and centroids of 2D cells far from the origin (|x| / h ~ 10^4,
-    where a shoelace formula in absolute coordinates would lose about
-    (|x| / h)^2 of its precision) agree with the oracle's to 1e-10 of the
-    cell size."""
-    mk = w.box_mesh if kind == "quads" else w.tri_mesh
-    mesh = mk((64, 48), lengths=(1.0, 0.75), origin=(100.0, -50.0), perturb=0.2, seed=3)
-    ctx = api.context_for(w.poly_patch(mesh, 2, 2, seed=1), host_only=True)
+@pytest.mark.parametrize("kind", ["quads", "tris", "hexes", "tets"])
+def test_geometry_is_translation_stable(kind):
+    """Centroids of cells far from the origin (|x| / h ~ 10^3 to 10^4, where a
+    2D shoelace formula in absolute coordinates would lose about (|x| / h)^2
+    of its precision) agree with the oracle's to 1e-10 of the cell size."""
+    if kind in ("quads", "tris"):
+        mk = w.box_mesh if kind == "quads" else w.tri_mesh
+        mesh = mk((64, 48), lengths=(1.0, 0.75), origin=(100.0, -50.0), perturb=0.2, seed=3)
+        h = 1.0 / 64
+    else:
+        mk = w.box_mesh if kind == "hexes" else w.tet_mesh
+        mesh = mk((24, 20, 16), lengths=(1.0, 0.8, 0.64), origin=(100.0, -50.0, 30.0), perturb=0.2, seed=3)
+        h = 1.0 / 24
+    ctx = api.context_for(w.poly_patch(mesh, 1, 1, seed=1), host_only=True)
     vol, cen = geo.cell_volume_centroid(mesh.verts[mesh.cells])
-    h = 1.0 / 64
     assert np.abs(ctx.cell_centroids() - cen).max() <= 1e-10 * h
