@@ -63,6 +63,12 @@ CASES = {
                                             seed=6, symmetric=True),
     "box_p3_symmetry": lambda: w.poly_patch(w.box_mesh((7, 6, 6), perturb=0.2, seed=4, mode="tensor"), 3, 3,
                                             seed=7, symmetric=True),
+    # far from the origin (|x| / h ~ 10^3): geometry, stencils and least squares
+    # start from absolute coordinates
+    "square_far_p2": lambda: w.poly_patch(w.box_mesh((12, 10), lengths=(1.0, 0.8), origin=(100.0, -50.0),
+                                                     perturb=0.2, seed=2), 2, 2, seed=4),
+    "cube_far_p2": lambda: w.poly_patch(w.box_mesh((7, 6, 6), lengths=(1.0, 0.9, 0.8), origin=(40.0, -20.0, 10.0),
+                                                   perturb=0.2, seed=3), 2, 2, seed=5),
 }
 
 
