@@ -69,6 +69,10 @@ CASES = {
                                                      perturb=0.2, seed=2), 2, 2, seed=4),
     "cube_far_p2": lambda: w.poly_patch(w.box_mesh((7, 6, 6), lengths=(1.0, 0.9, 0.8), origin=(40.0, -20.0, 10.0),
                                                    perturb=0.2, seed=3), 2, 2, seed=5),
+    # very small and very large domains: nothing in the setup may assume unit size
+    "cube_mm_p2": lambda: w.poly_patch(w.box_mesh((6, 6, 5), lengths=(1e-3, 1e-3, 8e-4), perturb=0.2, seed=3), 2, 2,
+                                       seed=5),
+    "square_km_p3": lambda: w.poly_patch(w.box_mesh((10, 9), lengths=(1e3, 9e2), perturb=0.2, seed=2), 3, 3, seed=4),
 }
 
 
