@@ -266,3 +266,36 @@ def test_residual_and_jvp_parity_with_the_fan_face_rule(case):
     assert np.linalg.norm(to_host(R) - Ro) <= 1e-10 * np.linalg.norm(Ro)
     Jo = ojac.jvp(disc, u, v, eps=eps)
     assert np.linalg.norm(to_host(Jv) - Jo) <= 1e-6 * np.linalg.norm(Jo)
+
+
+@pytest.mark.parametrize("name", ["cube8_p2_pert", "square9_p1", "tri8_p3"])
+def test_caller_cell_numbering_is_kept(name):
+    """The library orders cells and faces internally (Morton order, item
+    blocks) but reads and writes vectors in the caller's cell numbering:
+    renumbering the cells permutes R and J.v the same way (to rounding, as
+    the sums' order changes), on perturbed meshes where no stencil ties."""
+    import copy
+    if name == "tri8_p3":
+        prob = w.tri_mms(8, 3, perturb=0.2)
+    else:
+        prob = CASES[name]()
+    n, D = prob.mesh.n_cells, prob.dim
+    perm = np.random.default_rng(5).permutation(n)
+    prob2 = copy.deepcopy(prob)
+    prob2.mesh.cells = prob.mesh.cells[perm]  # cell i of prob2 is cell perm[i] of prob
+    api = _api()
+    c1, c2 = api.context_for(prob), api.context_for(prob2)
+    u = w.random_state(n, D, seed=31)
+    v = w.random_state(n, D, seed=32, scale=1.0)
+    out = []
+    for ctx, uu, vv in ((c1, u, v), (c2, u[perm], v[perm])):
+        ud, vd = to_dev(uu), to_dev(vv)
+        R = torch.empty_like(ud)
+        Jv = torch.empty_like(ud)
+        ctx.residual(ud, R)
+        ctx.jvp(ud, R, vd, Jv, eps=1e-7)
+        torch.cuda.synchronize()
+        out.append((to_host(R), to_host(Jv)))
+    (R1, J1), (R2, J2) = out
+    assert np.abs(R2 - R1[perm]).max() <= 1e-12 * np.abs(R1).max()
+    assert np.abs(J2 - J1[perm]).max() <= 1e-7 * np.abs(J1).max()
