@@ -73,6 +73,9 @@ CASES = {
     "cube_mm_p2": lambda: w.poly_patch(w.box_mesh((6, 6, 5), lengths=(1e-3, 1e-3, 8e-4), perturb=0.2, seed=3), 2, 2,
                                        seed=5),
     "square_km_p3": lambda: w.poly_patch(w.box_mesh((10, 9), lengths=(1e3, 9e2), perturb=0.2, seed=2), 3, 3, seed=4),
+    # flat cells (aspect 10 and 30): the least squares are worse conditioned
+    "box_aspect10_p3": lambda: w.cube_mms((9, 9, 9), 3, perturb=0.2, seed=4, lengths=(1.0, 1.0, 0.1)),
+    "box_aspect30_p2": lambda: w.cube_mms((9, 9, 8), 2, perturb=0.2, seed=4, lengths=(1.0, 1.0, 1.0 / 30 * 8 / 9)),
 }
 
 
