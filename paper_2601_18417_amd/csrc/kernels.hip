@@ -44,13 +44,19 @@ constexpr int kFaceChunk = HOFV_FACE_CHUNK, kExtrapChunk = HOFV_EXTRAP_CHUNK, kF
 inline unsigned blocks_for(int64_t n, int per = kBlock) { return (unsigned)((n + per - 1) / per); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2.  Remap so that XCD x runs one contiguous range of logical blocks:
-// neighbouring item blocks, whose stencil unions overlap, share one L2.
-// Bijective for any grid.
+// L2.  Remap so that XCD x takes runs of G consecutive logical blocks in turn
+// (blocks 8 G k + x G .. 8 G k + x G + G - 1): neighbouring item blocks, whose
+// stencil unions overlap, share an L2 in runs of G, while every XCD works
+// through the whole mesh, boundary-face blocks included, at the same pace
+// (one contiguous range per XCD was slower: the face and extrapolation
+// kernels gain 2 and 9 % with G = 8 and 2).  The last nb mod 8 G blocks keep
+// their index; bijective for any grid.
+template <int G>
 __device__ inline int64_t xcd_block() {
-  const int64_t nb = gridDim.x, b = blockIdx.x;
-  const int64_t x = b % 8, local = b / 8, base = nb / 8, r = nb % 8;
-  return x * base + (x < r ? x : r) + local;
+  const int64_t nb = gridDim.x, b = blockIdx.x, M = nb / (8 * G) * (8 * G);
+  if (b >= M) return b;
+  const int64_t x = b % 8, k = b / 8;
+  return (k / G) * (8 * G) + x * G + k % G;
 }
 
 // displacement of cell n from the padded gather copy (4 doubles per cell in
@@ -186,7 +192,7 @@ __global__ __launch_bounds__(kBlockItems) void k_extrap(int64_t nc, int S, const
                                                     const int32_t* __restrict__ cell, const double* __restrict__ ug,
                                                     double* __restrict__ ustar) {
   __shared__ double lds[D][kLdsCellCells];
-  const int64_t b = xcd_block();
+  const int64_t b = xcd_block<2>();
   stage_union<D, kLdsCellCells>(b, blk_cell, ucell, ug, lds);
   const int64_t i0 = blk_item[b], nb = blk_item[b + 1] - i0, ti = threadIdx.x;
   if (ti >= nb) return;
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(kBlockItems) void k_face_le(int64_t nf, int64_t nfi
                                                      double mu, double lam, const double* __restrict__ ug,
                                                      const double* __restrict__ ustar, double* __restrict__ F) {
   __shared__ double lds[D][kLdsFaceCells];
-  const int64_t b = xcd_block();
+  const int64_t b = xcd_block<8>();
   stage_union<D, kLdsFaceCells>(b, blk_cell, ucell, ug, lds);
   const int64_t i0 = blk_item[b], nb = blk_item[b + 1] - i0, ti = threadIdx.x;
   if (ti >= nb) return;
@@ -347,7 +353,7 @@ __global__ __launch_bounds__(kBlockItems) void k_face_q(int64_t nf, int64_t nfi,
                                                     const double* __restrict__ ustar, double* __restrict__ F,
                                                     int32_t* __restrict__ flag) {
   __shared__ double lds[D][kLdsFaceCells];
-  const int64_t b = xcd_block();
+  const int64_t b = xcd_block<8>();
   stage_union<D, kLdsFaceCells>(b, blk_cell, ucell, ug, lds);
   const int64_t i0 = blk_item[b], nb = blk_item[b + 1] - i0, ti = threadIdx.x;
   if (ti >= nb) return;
