@@ -499,6 +499,13 @@ __global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, int
     }
   };
   int64_t P;
+  // R(u)'s entries of the cell are loaded as soon as P is known, alongside the fluxes
+  double ru[D], e = 0.0;
+  auto own = [&]() {
+#pragma unroll
+    for (int c = 0; c < D; ++c) ru[c] = Ru ? Ru[(int64_t)c * nc + P] : 0.0;
+    if (Ru) e = eps[0];
+  };
   const int64_t nbt = NST > 0 ? 0 : n_big * g;  // threads of the many-faced cells
   if (NST == 0 && k < nbt) {
     P = order[k / g];
@@ -517,30 +524,48 @@ __global__ __launch_bounds__(kBlock) void k_cell_sum(int64_t nc, int64_t nf, int
 #pragma unroll
       for (int c = 0; c < D; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
     if (l != 0) return;
+    own();
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[c] += load * src[(int64_t)c * nc + P];
   } else {
     const int64_t i = NST > 0 ? k : k - nbt + n_big;
     if (i >= nc) return;
     P = NST > 0 ? i : (int64_t)order[i];
+    own();
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[c] = load * src[(int64_t)c * nc + P];
     constexpr int S0 = NST > 0 ? NST : 2 * D;
     int32_t f0[S0];
 #pragma unroll
     for (int s = 0; s < S0; ++s) f0[s] = cf[(int64_t)s * nc + P];
+    if (nfs == 0 && nf > 0) {
+      // no symmetry faces: the row is selected rather than branched on, so
+      // that the loads of all slots are in flight together (an empty slot
+      // reads row 0 and adds nothing)
+      double v[S0][D];
 #pragma unroll
-    for (int s = 0; s < S0; ++s) take(f0[s]);
+      for (int s = 0; s < S0; ++s) {
+        const int32_t f = f0[s];
+        const int64_t i = f == kNoFace ? 0 : f < 0 ? (int64_t)~f : (int64_t)f;
+#pragma unroll
+        for (int c = 0; c < D; ++c) v[s][c] = F[(int64_t)c * nf + i];
+      }
+#pragma unroll
+      for (int s = 0; s < S0; ++s)
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+          acc[c] = f0[s] == kNoFace ? acc[c] : f0[s] < 0 ? acc[c] - v[s][c] : acc[c] + v[s][c];
+    } else {
+#pragma unroll
+      for (int s = 0; s < S0; ++s) take(f0[s]);
+    }
   }
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     double a = acc[c];
     // BDF2 inertia at the centroid: s_P - m_P u_P (u from the gather copy)
     if (dm) a += ds[(int64_t)c * nc + P] - dm[P] * ug[(int64_t)W * P + c];
-    if (Ru) {
-      const double e = eps[0];
-      a = e > 0.0 ? (a - Ru[(int64_t)c * nc + P]) / e : 0.0;
-    }
+    if (Ru) a = e > 0.0 ? (a - ru[c]) / e : 0.0;
     R[(int64_t)c * nc + P] = a;
   }
 }
@@ -552,10 +577,23 @@ __global__ __launch_bounds__(kBlock) void k_sumsq2(int64_t n, const double* __re
                                                    const double* __restrict__ b, double* __restrict__ part) {
   __shared__ double sred[(kBlock / 64) * 2], sout[2];
   double acc[2] = {0.0, 0.0};
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-    const double x = a[i], y = b[i];
-    acc[0] += x * x;
-    acc[1] += y * y;
+  // a thread's strided entries are loaded 8 at a time and added in index
+  // order (an entry past n loads as 0 and adds nothing to the sums of squares)
+  constexpr int U = 8;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += U * stride) {
+    double x[U], y[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int64_t i = i0 + j * stride;
+      x[j] = i < n ? a[i] : 0.0;
+      y[j] = i < n ? b[i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      acc[0] += x[j] * x[j];
+      acc[1] += y[j] * y[j];
+    }
   }
   block_reduce<2, kBlock>(acc, sred, sout);
   if (threadIdx.x < 2) part[threadIdx.x * kRedParts + blockIdx.x] = sout[threadIdx.x];
@@ -571,6 +609,15 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t nc, const double* __res
                                                  const double* __restrict__ part, double* __restrict__ eps_out,
                                                  double* __restrict__ ug) {
   constexpr int W = D == 3 ? 4 : 2;
+  const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool live = P < nc;
+  // the cell's u and v are loaded before the partials are added up
+  double uu[D], vv[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    uu[c] = live ? u[(int64_t)c * nc + P] : 0.0;
+    vv[c] = v && live ? v[(int64_t)c * nc + P] : 0.0;
+  }
   double e = eps_host;
   if (v && nb > 0) {
     __shared__ double sred[(kBlock / 64) * 2], sn[2];
@@ -587,13 +634,12 @@ __global__ __launch_bounds__(kBlock) void k_pack(int64_t nc, const double* __res
     e = nv > 0.0 ? sqrt((1.0 + nu) * DBL_EPSILON) / nv : 0.0;
   }
   if (v && blockIdx.x == 0 && threadIdx.x == 0) eps_out[0] = e;
-  const int64_t P = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (P >= nc) return;
+  if (!live) return;
   double x[W];
 #pragma unroll
   for (int c = 0; c < W; ++c) x[c] = 0.0;
 #pragma unroll
-  for (int c = 0; c < D; ++c) x[c] = v ? u[(int64_t)c * nc + P] + e * v[(int64_t)c * nc + P] : u[(int64_t)c * nc + P];
+  for (int c = 0; c < D; ++c) x[c] = v ? uu[c] + e * vv[c] : uu[c];
   double2* o = reinterpret_cast<double2*>(ug + (int64_t)W * P);
   o[0] = make_double2(x[0], x[1]);
   if constexpr (W == 4) o[1] = make_double2(x[2], x[3]);
