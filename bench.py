@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # passes (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, factors from a plain 512 MiB
 # elementwise copy), valid only for the kernel and table-layout sources whose
 # combined sha256 has this prefix.
-MEASURED_TRAFFIC = {"kernel": "k_face_le", "n": 64, "p": 3, "bytes": 1934190115.0,
-                    "kernels_sha256": "2e06a0c2b947717b"}
+MEASURED_TRAFFIC = {"kernel": "k_face_le", "n": 64, "p": 3, "bytes": 1934204633.0,
+                    "kernels_sha256": "b021e324ca743f5b"}
 TRAFFIC_SOURCES = ("kernels.hip", "common.h", "setup_blocks.cpp", "setup_tables.cpp")
 
 

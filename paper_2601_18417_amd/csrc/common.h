@@ -135,6 +135,7 @@ struct DeviceTables {
     int32_t *p_ptr = nullptr, *p_col = nullptr, *r_ptr = nullptr, *r_col = nullptr;
     float *p_val = nullptr, *r_val = nullptr;  // P (rows: this level) and P^T
     float *r = nullptr, *z = nullptr, *t = nullptr;  // [D][n]
+    float* z2 = nullptr;  // [D][n] the other iterate of the Jacobi steps (levels 1 .. L-2)
     float* cinv = nullptr;  // coarsest level: dense inverse, column-major
     int g_a = 1, g_p = 1, g_r = 1;  // lanes per CSR row of A, P, P^T
   };

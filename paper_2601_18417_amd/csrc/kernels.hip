@@ -844,15 +844,49 @@ __global__ __launch_bounds__(kBlock) void k_mg_spmv(int64_t ny, const int32_t* _
   for (int c = 0; c < D; ++c) y[(int64_t)c * ny + i] = (add ? y[(int64_t)c * ny + i] : 0.0f) + acc[c];
 }
 
-// damped Jacobi update z += w_i t_i (t = r - A z)
+// first damped Jacobi step from z = 0: z = w_i r_i
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_mg_jacobi(int64_t n, const float* __restrict__ wdinv,
-                                                      const float* __restrict__ t, float* __restrict__ z) {
+__global__ __launch_bounds__(kBlock) void k_mg_jinit(int64_t n, const float* __restrict__ wdinv,
+                                                     const float* __restrict__ r, float* __restrict__ z) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const float w = wdinv[i];
 #pragma unroll
-  for (int c = 0; c < D; ++c) z[(int64_t)c * n + i] += w * t[(int64_t)c * n + i];
+  for (int c = 0; c < D; ++c) z[(int64_t)c * n + i] = w * r[(int64_t)c * n + i];
+}
+
+// one damped Jacobi step into the other iterate: zo = z + w_i (r - A z)_i,
+// the residual formed as in k_mg_res
+template <int D, int G>
+__global__ __launch_bounds__(kBlock) void k_mg_jstep(int64_t n, const int32_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ col, const float* __restrict__ val,
+                                                     const float* __restrict__ diag, const float* __restrict__ wdinv,
+                                                     const float* __restrict__ r, const float* __restrict__ z,
+                                                     float* __restrict__ zo) {
+  const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  const bool live = g < n;
+  const int64_t i = live ? g : n - 1;
+  float acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = 0.0f;
+  if (live)
+    for (int32_t u = ptr[i] + lane; u < ptr[i + 1]; u += G) {
+      const int32_t j = col[u];
+      const float v = val[u];
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] += v * z[(int64_t)c * n + j];
+    }
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = group_sum<G>(acc[c]);
+  if (!live || lane != 0) return;
+  const float di = diag[i], w = wdinv[i];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const float zi = z[(int64_t)c * n + i];
+    const float t = r[(int64_t)c * n + i] - di * zi - acc[c];
+    zo[(int64_t)c * n + i] = zi + w * t;
+  }
 }
 
 // z = C r with the coarsest level's dense inverse C (column-major)
@@ -871,11 +905,6 @@ __global__ __launch_bounds__(kBlock) void k_mg_dense(int64_t n, const float* __r
   }
 #pragma unroll
   for (int c = 0; c < D; ++c) z[(int64_t)c * n + i] = acc[c];
-}
-
-__global__ __launch_bounds__(kBlock) void k_fill_f(int64_t n, float v, float* __restrict__ x) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) x[i] = v;
 }
 
 }  // namespace
@@ -1179,23 +1208,34 @@ static void mg_spmv(int64_t ny, const int32_t* ptr, const int32_t* col, const fl
 #undef SPMV
 }
 
-// smoothing on level l: level 0 Gauss-Seidel sweeps, coarser levels damped
-// Jacobi steps (t = r - A z; z += w t)
+// steps damped Jacobi steps zo = z + w (r - A z) on a coarse level, each into
+// the other of its two iterates; returns the one holding the result
 template <int D>
-static void mg_smooth(hofv_ctx* c, int l, int sweeps, hipStream_t st) {
-  DeviceTables& t = c->dev;
-  DeviceTables::MgLevel& m = t.mg[l];
-  if (l == 0) {
-    sgs_sweeps<D>(c, sweeps, st);
-    return;
+static float* mg_jacobi_steps(DeviceTables::MgLevel& m, float* z, int steps, hipStream_t st) {
+  const unsigned nb = blocks_for(m.n * m.g_a);
+  for (int s = 0; s < steps; ++s) {
+    float* zo = z == m.z ? m.z2 : m.z;
+#define JSTEP(G) k_mg_jstep<D, G><<<nb, kBlock, 0, st>>>(m.n, m.ptr, m.col, m.val, m.diag, m.wdinv, m.r, z, zo)
+    switch (m.g_a) {
+      case 1: JSTEP(1); break;
+      case 2: JSTEP(2); break;
+      case 4: JSTEP(4); break;
+      case 8: JSTEP(8); break;
+      case 16: JSTEP(16); break;
+      case 32: JSTEP(32); break;
+      default: JSTEP(64); break;
+    }
+#undef JSTEP
+    z = zo;
   }
-  for (int s = 0; s < sweeps; ++s) {
-    mg_res<D>(m.n, m.ptr, m.col, m.val, m.diag, m.r, m.z, m.t, m.g_a, st);
-    k_mg_jacobi<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.wdinv, m.t, m.z);
-  }
+  return z;
 }
 
-// V-cycle on level l for r_l (level 0: p_r), result in z_l (level 0: p_z, zero on entry)
+// V-cycle on level l for r_l (level 0: p_r), result in z_l (level 0: p_z, zero on
+// entry).  Level 0 is smoothed by Gauss-Seidel sweeps, coarser levels by damped
+// Jacobi steps: the first from z = 0 (z = w r), the others each forming the
+// residual and the update in one launch, alternating between z and z2 so that
+// the 2 sweeps - 1 of them end in z.
 template <int D>
 static void mg_vcycle(hofv_ctx* c, int l, int sweeps, hipStream_t st) {
   DeviceTables& t = c->dev;
@@ -1207,8 +1247,12 @@ static void mg_vcycle(hofv_ctx* c, int l, int sweeps, hipStream_t st) {
     k_mg_dense<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.cinv, r, z);
     return;
   }
-  if (l > 0) k_fill_f<<<blocks_for((int64_t)D * m.n), kBlock, 0, st>>>((int64_t)D * m.n, 0.0f, z);
-  mg_smooth<D>(c, l, sweeps, st);
+  if (l == 0) {
+    sgs_sweeps<D>(c, sweeps, st);
+  } else {
+    k_mg_jinit<D><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, m.wdinv, r, m.z2);
+    z = mg_jacobi_steps<D>(m, m.z2, sweeps - 1, st);
+  }
   if (l == 0 && t.ns == 2 * D && t.nsi == D + 1)  // simplices: dim + 1 slots
     k_mg_res0<D, D + 1><<<blocks_for(m.n), kBlock, 0, st>>>(m.n, t.ns, t.p_nbr, t.p_a, t.p_diag, r, z, m.t, nullptr);
   else if (l == 0 && t.ns == 2 * D)
@@ -1221,13 +1265,15 @@ static void mg_vcycle(hofv_ctx* c, int l, int sweeps, hipStream_t st) {
   mg_spmv<D>(q.n, m.r_ptr, m.r_col, m.r_val, m.t, m.n, q.r, 0, m.g_r, st);
   mg_vcycle<D>(c, l + 1, sweeps, st);
   mg_spmv<D>(m.n, m.p_ptr, m.p_col, m.p_val, q.z, q.n, z, 1, m.g_p, st);
-  mg_smooth<D>(c, l, sweeps, st);
+  if (l == 0) sgs_sweeps<D>(c, sweeps, st);
+  else mg_jacobi_steps<D>(m, z, sweeps, st);  // ends in m.z
 }
 
 template <int D>
 static hofv_status precond_impl(hofv_ctx* c, const double* r, double* z, int sweeps, hipStream_t st) {
   DeviceTables& t = c->dev;
   const int64_t nc = c->nc;
+  if (sweeps < 1) return fail(c, HOFV_EINVAL, "the preconditioner needs at least one sweep");
   k_pc_in<D><<<blocks_for(nc), kBlock, 0, st>>>(nc, t.p_perm, r, t.p_r, t.p_z);
   if (c->use_mg && t.mg.size() > 1) mg_vcycle<D>(c, 0, sweeps, st);
   else sgs_sweeps<D>(c, sweeps, st);

@@ -280,6 +280,7 @@ hofv_status build_multigrid(hofv_ctx* c, const std::vector<int64_t>& ptr, const 
       UPV(m.wdinv, wd);
       if ((s = dev_alloc(c, &m.r, (size_t)D * L.n))) return s;
       if ((s = dev_alloc(c, &m.z, (size_t)D * L.n))) return s;
+      if (l < nl - 1 && (s = dev_alloc(c, &m.z2, (size_t)D * L.n))) return s;
     }
     if ((s = dev_alloc(c, &m.t, (size_t)D * L.n))) return s;
     if (l < nl - 1) {  // P with rows in this level's vector order (level 0: colour-major)
